@@ -1,0 +1,340 @@
+"""Oracle model of the urgency-ordered launch gate, one decision instant at a time.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+This is the paper's GPU prioritisation (Sec. 4.4) written as a state machine
+over *decision instants*.  At an instant ``t`` the gate receives inputs (frame
+arrivals and observed completions of events it recorded), updates the urgency
+of every active chain instance (Eq. (2), Sec. 4.2) and decides, in order of
+decreasing urgency, which kernels to launch, on which stream, and which to
+hold back:
+
+* task-level stream binding with a reserved top level (Sec. 4.4.3);
+* delayed launching while a more urgent, truly urgent kernel of another chain
+  is active (Sec. 4.4.4), with the low-utilisation exemption;
+* batched launching with batch overlap (Sec. 4.4.5): an event marks the start
+  of each batch; once a batch is closed the task waits until the *previous*
+  batch has finished before it launches more, and each such observation
+  advances the executing-kernel index used by Eq. (2);
+* the Active Kernel Buffer (Sec. 4.4.2) as the per-instance range of launched
+  kernels not yet confirmed complete.
+
+Readings where the paper is silent (each listed in the design notes):
+executing-kernel index = kernels confirmed complete by an observed event;
+exact rational comparison of urgencies with ties to the lower (chain, frame);
+a task binds when its first kernel is actually released; the delay rule holds
+a kernel only for a *more urgent* truly urgent instance of another chain;
+frames of one chain run each task in arrival order, one frame per task at a
+time; a CPU segment is a host-side delay before the task's kernels.
+
+Decision records (tuples):
+    ("COMPLETE", c, f, t_done)
+    ("TSTART",   c, f, j)
+    ("BIND",     c, f, j, level, lane)
+    ("HOLD",     c, f, g)
+    ("EVREC",    c, f, j, kind, seq)      kind 0 = batch start, 1 = task end
+    ("LAUNCH",   c, f, g, level, lane)
+where c = chain, f = frame index within the chain, j = task, g = kernel index
+within the chain (kernels of all tasks numbered in order).  For a batch-start
+event ``seq`` is the batch index; for the end event it is the number of
+batches of the task.
+"""
+
+from collections import deque
+
+import numpy as np
+
+from . import policy as P
+
+START = 0
+END = 1
+
+
+class ChainSpec:
+    """A chain: deadline and ordered tasks, each a CPU segment then kernels."""
+
+    def __init__(self, spec):
+        self.deadline = int(spec["deadline_ns"])
+        self.task_first = []      # first global kernel index of each task
+        self.task_end = []        # one past the last global kernel index
+        self.cpu = []             # CPU-segment estimate of each task (ns)
+        self.est = []             # estimated time of each kernel (ns)
+        self.util = []            # utilisation of each kernel (float32)
+        for task in spec["tasks"]:
+            self.task_first.append(len(self.est))
+            self.est.extend(int(e) for e in task["est_ns"])
+            self.util.extend(np.float32(u) for u in task["util"])
+            self.task_end.append(len(self.est))
+            self.cpu.append(int(task.get("cpu_ns", 0)))
+            assert self.task_end[-1] > self.task_first[-1], "a task needs kernels"
+        self.n_tasks = len(self.task_first)
+        n = len(self.est)
+        # Remaining-work sums of Eq. (2): gpu_rem[g] = sum_{k >= g} E_k,
+        # cpu_rem[j] = sum_{j' >= j} E^cpu_j'.
+        self.gpu_rem = [0] * (n + 1)
+        for g in range(n - 1, -1, -1):
+            self.gpu_rem[g] = self.gpu_rem[g + 1] + self.est[g]
+        self.cpu_rem = [0] * (self.n_tasks + 1)
+        for j in range(self.n_tasks - 1, -1, -1):
+            self.cpu_rem[j] = self.cpu_rem[j + 1] + self.cpu[j]
+
+
+class Instance:
+    """One chain instance (one data frame travelling through the chain)."""
+
+    def __init__(self, c, f, t_arr, chain):
+        self.c, self.f, self.t_arr = c, f, t_arr
+        self.chain = chain
+        self.phase = "wait"       # wait | cpu | launch | done
+        self.task = -1
+        self.cpu_ready = None
+        self.i_gpu = 0            # kernels confirmed complete (executing index)
+        self.i_cpu = 0            # index of the first unfinished CPU segment
+        self.g_next = 0           # next kernel to release
+        self.released_hi = 0      # one past the last released kernel
+        self.batch = 0            # index of the open (or next) batch
+        self.batch_open = False
+        self.batch_sum = 0
+        self.batch_first = []     # first kernel of each batch of the task
+        self.waits = deque()      # events to observe, in order: (kind, seq)
+        self.bound = False
+        self.level = None
+        self.lane = None
+        self.wake = None          # re-check time of a held launch (sleep loop)
+
+    @property
+    def key(self):
+        return (self.c, self.f)
+
+    def in_flight(self):
+        """Has Active-Kernel-Buffer entries: launched, not yet confirmed complete."""
+        return self.released_hi > self.i_gpu
+
+
+DEFAULT_CFG = {
+    "policy": "urgency",        # "urgency" or "fifo"
+    "bind": True,
+    "delay": True,
+    "batch": True,
+    "delta_eval_ns": 500_000,   # Delta_eval = 0.5 ms (Sec. 4.4.5)
+    "delay_poll_ns": 1_000_000, # 1 ms sleep loop (Sec. 4.4.4); 0 = re-check every instant
+    "util_exempt": 0.1,         # kernels below this utilisation are never delayed
+    "th_slack_ns": 0,           # TH_urgent as a slack; <= 0 means +infinity
+    "lanes": [1, 2, 1],         # streams per level; len = number of levels
+    "calibrate": False,
+}
+
+
+class GateModel:
+    def __init__(self, chains, cfg=None):
+        self.cfg = dict(DEFAULT_CFG)
+        if cfg:
+            self.cfg.update(cfg)
+        self.chains = [c if isinstance(c, ChainSpec) else ChainSpec(c) for c in chains]
+        self.urgency_policy = self.cfg["policy"] == "urgency"
+        self.u_exempt = np.float32(self.cfg["util_exempt"])
+        self.lanes = list(self.cfg["lanes"])
+        self.n_levels = len(self.lanes)
+        # FIFO launch: one stream per task of every chain.
+        self.fifo_lane = []
+        k = 0
+        for ch in self.chains:
+            self.fifo_lane.append(list(range(k, k + ch.n_tasks)))
+            k += ch.n_tasks
+        self.inst = {}                                 # (c, f) -> Instance
+        self.slot = {}                                 # (c, j) -> frame running task j
+        self.queue = {}                                # (c, j) -> frames waiting for task j
+        for c, ch in enumerate(self.chains):
+            for j in range(ch.n_tasks):
+                self.slot[(c, j)] = None
+                self.queue[(c, j)] = deque()
+        self.lane_load = {(lv, ln): 0 for lv in range(self.n_levels)
+                          for ln in range(self.lanes[lv])}
+        self.samples = []                              # slacks for TH_urgent
+        self.completed = []                            # (c, f, t_arr, t_done)
+        self.last_snapshot = {}
+
+    # ------------------------------------------------------------------
+    def slack(self, inst, t):
+        ch = inst.chain
+        return P.slack_ns(t, inst.t_arr, ch.deadline, ch.gpu_rem[inst.i_gpu],
+                          ch.cpu_rem[inst.i_cpu])
+
+    def _start_task(self, inst, j, t, out):
+        ch = inst.chain
+        inst.task = j
+        inst.phase = "cpu"
+        inst.cpu_ready = t + ch.cpu[j]
+        inst.g_next = ch.task_first[j]
+        inst.released_hi = ch.task_first[j]
+        inst.batch = 0
+        inst.batch_open = False
+        inst.batch_sum = 0
+        inst.batch_first = []
+        inst.waits = deque()
+        inst.bound = False
+        inst.level = inst.lane = None
+        inst.wake = None
+        self.slot[(inst.c, j)] = inst.f
+        out.append(("TSTART", inst.c, inst.f, j))
+
+    # ------------------------------------------------------------------
+    def instant(self, t, arrivals=(), evdones=()):
+        """Process one decision instant.  Returns the list of decisions.
+
+        ``arrivals``: (c, f, t_arr) of frames first seen at this instant.
+        ``evdones``: (c, f, j, kind, seq) of events observed complete.
+        """
+        out = []
+        finished = []
+        # 1. inputs, in canonical order
+        for c, f, t_arr in sorted(arrivals):
+            assert (c, f) not in self.inst, "frame arrives twice"
+            inst = Instance(c, f, t_arr, self.chains[c])
+            self.inst[(c, f)] = inst
+            self.queue[(c, 0)].append(f)
+        for c, f, j, kind, seq in sorted(evdones, key=lambda e: (e[0], e[1], e[2], e[4], e[3])):
+            inst = self.inst[(c, f)]
+            assert inst.task == j and inst.waits and inst.waits[0] == (kind, seq), \
+                ("unexpected event", (c, f, j, kind, seq), list(inst.waits))
+            inst.waits.popleft()
+            ch = inst.chain
+            if kind == START:
+                # Batch `seq` has begun, so every earlier batch of the task is
+                # done: the executing kernel is the first kernel of `seq`.
+                inst.i_gpu = inst.batch_first[seq]
+            else:
+                inst.i_gpu = ch.task_end[j]
+                if inst.bound and self.urgency_policy:
+                    self.lane_load[(inst.level, inst.lane)] -= 1
+                self.slot[(c, j)] = None
+                if j == ch.n_tasks - 1:
+                    inst.phase = "done"
+                    finished.append(inst)
+                else:
+                    inst.phase = "wait"
+                    self.queue[(c, j + 1)].append(f)
+        for inst in sorted(finished, key=lambda i: i.key):
+            out.append(("COMPLETE", inst.c, inst.f, t))
+            self.completed.append((inst.c, inst.f, inst.t_arr, t))
+        # 2. tasks whose predecessor (in the chain and in the frame order) is done
+        for c, ch in enumerate(self.chains):
+            for j in range(ch.n_tasks):
+                if self.slot[(c, j)] is None and self.queue[(c, j)]:
+                    f = self.queue[(c, j)].popleft()
+                    self._start_task(self.inst[(c, f)], j, t, out)
+        # 3. CPU segments that have finished
+        active = sorted((i for i in self.inst.values() if i.phase != "done"),
+                        key=lambda i: i.key)
+        for inst in active:
+            if inst.phase == "cpu" and inst.cpu_ready <= t:
+                inst.phase = "launch"
+                inst.i_cpu = inst.task + 1
+        # 4. one urgency snapshot for the whole instant (Eq. (2))
+        slack = {inst.key: self.slack(inst, t) for inst in active}
+        self.last_snapshot = dict(slack)
+        # 5. sample the highest urgency among active kernels (Sec. 4.4.3)
+        if self.cfg["calibrate"]:
+            fl = [(slack[i.key], i.key, None) for i in active if i.in_flight()]
+            if fl:
+                self.samples.append(P.rank_sort(fl)[0][0])
+        # 6. launch requests, most urgent first
+        ready = [i for i in active
+                 if i.phase == "launch" and i.g_next < i.chain.task_end[i.task]
+                 and not i.waits and (i.wake is None or i.wake <= t)]
+        if self.urgency_policy:
+            ready = [r[2] for r in P.rank_sort([(slack[i.key], i.key, i) for i in ready])]
+        for inst in ready:
+            self._release(inst, t, slack, active, out)
+        return out
+
+    # ------------------------------------------------------------------
+    def _urgent(self, s):
+        return P.is_truly_urgent(s, self.cfg["th_slack_ns"])
+
+    def _blocked(self, inst, slack, active):
+        """Sec. 4.4.4: another chain's truly urgent, more urgent instance is active."""
+        si = slack[inst.key]
+        for o in active:
+            if o.c == inst.c or not o.in_flight():
+                continue
+            so = slack[o.key]
+            if self._urgent(so) and P.more_urgent(so, o.key, si, inst.key):
+                return True
+        return False
+
+    def _bind(self, inst, slack, active, out):
+        """Sec. 4.4.3: choose the stream of the whole task at its first launch."""
+        if not self.urgency_policy:
+            inst.level, inst.lane = 0, self.fifo_lane[inst.c][inst.task]
+        else:
+            si = slack[inst.key]
+            if not self.cfg["bind"]:
+                # binding switched off: every task shares the first unreserved level
+                level = min(1, self.n_levels - 1)
+            elif self.n_levels <= 1:
+                level = 0
+            elif self._urgent(si):
+                level = 0
+            else:
+                group = [(slack[o.key], o.key, o) for o in active
+                         if o is not inst and o.in_flight() and not self._urgent(slack[o.key])]
+                group.append((si, inst.key, inst))
+                order = [g[2] for g in P.rank_sort(group)]
+                rank = order.index(inst) + 1
+                level = P.binding_level(rank, len(order), self.n_levels)
+            loads = [(self.lane_load[(level, ln)], ln) for ln in range(self.lanes[level])]
+            lane = min(loads)[1]
+            self.lane_load[(level, lane)] += 1
+            inst.level, inst.lane = level, lane
+        inst.bound = True
+        out.append(("BIND", inst.c, inst.f, inst.task, inst.level, inst.lane))
+
+    def _release(self, inst, t, slack, active, out):
+        ch = inst.chain
+        end = ch.task_end[inst.task]
+        delta = self.cfg["delta_eval_ns"] if (self.urgency_policy and self.cfg["batch"]) else None
+        while inst.g_next < end and not inst.waits:
+            g = inst.g_next
+            if (self.urgency_policy and self.cfg["delay"]
+                    and ch.util[g] >= self.u_exempt and self._blocked(inst, slack, active)):
+                out.append(("HOLD", inst.c, inst.f, g))
+                poll = self.cfg["delay_poll_ns"]
+                inst.wake = t + poll if poll > 0 else None
+                return
+            inst.wake = None
+            if not inst.bound:
+                self._bind(inst, slack, active, out)
+            if not inst.batch_open:
+                inst.batch_open = True
+                inst.batch_first.append(g)
+                out.append(("EVREC", inst.c, inst.f, inst.task, START, inst.batch))
+            out.append(("LAUNCH", inst.c, inst.f, g, inst.level, inst.lane))
+            inst.released_hi = g + 1
+            inst.g_next = g + 1
+            inst.batch_sum += ch.est[g]
+            last = g == end - 1
+            if last or (delta is not None and inst.batch_sum > delta):
+                inst.waits.append((START, inst.batch))
+                if last:
+                    out.append(("EVREC", inst.c, inst.f, inst.task, END, inst.batch + 1))
+                    inst.waits.append((END, inst.batch + 1))
+                inst.batch += 1
+                inst.batch_open = False
+                inst.batch_sum = 0
+
+    # ------------------------------------------------------------------
+    def timers(self):
+        """Earliest future time at which the gate must run without an input."""
+        ts = []
+        for inst in self.inst.values():
+            if inst.phase == "cpu":
+                ts.append(inst.cpu_ready)
+            if inst.phase == "launch" and inst.wake is not None:
+                ts.append(inst.wake)
+        return min(ts) if ts else None
+
+    def due(self, t):
+        """True if some timer has expired by ``t`` (a timer-only instant)."""
+        nt = self.timers()
+        return nt is not None and nt <= t

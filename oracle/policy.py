@@ -1,0 +1,187 @@
+"""Oracle policy primitives: urgency, comparison, binding level, batches, threshold, metrics.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+All times are integer nanoseconds (Python ints, exact).  Urgency levels are
+compared exactly as rationals; floats appear only in reporting helpers.
+"""
+
+from fractions import Fraction
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------
+# Eq. (2): urgency level of a chain instance
+# --------------------------------------------------------------------------
+def slack_ns(t, t_arr, deadline, gpu_remaining, cpu_remaining):
+    """Denominator of Eq. (2): t_arr + D - sum(remaining GPU est) - sum(remaining CPU est) - t.
+
+    ``gpu_remaining`` is the sum of the estimated kernel times from the
+    currently executing kernel index to the end of the chain, and
+    ``cpu_remaining`` the same over CPU segments (Sec. 4.2).
+    """
+    return t_arr + deadline - gpu_remaining - cpu_remaining - t
+
+
+def urgency(slack):
+    """UL = 1 / slack as an exact extended rational: None stands for +infinity.
+
+    A zero slack (no time left at all) is infinitely urgent; a negative slack
+    (the deadline is already lost) gives a negative urgency, below every
+    positive one (Sec. 4.2, Eq. (2) taken literally).
+    """
+    if slack == 0:
+        return None
+    return Fraction(1, slack)
+
+
+def ul_greater(s1, s2):
+    """True iff UL(s1) > UL(s2), exactly (Eq. (2))."""
+    u1, u2 = urgency(s1), urgency(s2)
+    if u1 is None:
+        return u2 is not None
+    if u2 is None:
+        return False
+    return u1 > u2
+
+
+def more_urgent(s1, key1, s2, key2):
+    """Strict total order used for every ranking: higher UL first, then the
+    lower (chain id, frame index)."""
+    if ul_greater(s1, s2):
+        return True
+    if ul_greater(s2, s1):
+        return False
+    return key1 < key2
+
+
+def rank_sort(items):
+    """Sort (slack, key, payload) triples from most to least urgent."""
+    from functools import cmp_to_key
+
+    def cmp(a, b):
+        if more_urgent(a[0], a[1], b[0], b[1]):
+            return -1
+        if more_urgent(b[0], b[1], a[0], a[1]):
+            return 1
+        return 0
+    return sorted(items, key=cmp_to_key(cmp))
+
+
+def is_truly_urgent(slack, th_slack):
+    """UL > TH_urgent (Sec. 4.4.3).
+
+    The threshold is carried as a slack: TH_urgent = 1 / th_slack for
+    th_slack > 0; th_slack <= 0 stands for TH_urgent = +infinity, which no
+    urgency exceeds.
+    """
+    if th_slack <= 0:
+        return False
+    return ul_greater(slack, th_slack)
+
+
+def ul_per_ms(slack_ns_value):
+    """UL in 1/ms as a float, for reporting only."""
+    if slack_ns_value == 0:
+        return float("inf")
+    return 1e6 / slack_ns_value
+
+
+# --------------------------------------------------------------------------
+# Sec. 4.4.3: stream level from the urgency rank
+# --------------------------------------------------------------------------
+def binding_level(rank, n, n_levels):
+    """Level of a task that is not truly urgent.
+
+    The top level (0) is reserved for truly urgent tasks; the others rank the
+    urgency of the active tasks and spread the ranks evenly over levels
+    1 .. n_levels-1 (rank 1 = most urgent = level 1).  With a single level
+    there is nothing to reserve and every task gets level 0.
+    """
+    assert 1 <= rank <= n
+    if n_levels <= 1:
+        return 0
+    return 1 + ((rank - 1) * (n_levels - 1)) // n
+
+
+# --------------------------------------------------------------------------
+# Sec. 4.4.5: batch partition of a task's kernels
+# --------------------------------------------------------------------------
+def batch_partition(est, delta):
+    """Split a task's kernels (estimated times ``est``) into launch batches.
+
+    Kernels are added to the current batch while the summed estimate stays
+    within Delta_eval; the kernel whose estimate makes the sum exceed
+    Delta_eval still belongs to the batch and closes it.  The task's last
+    kernel always closes the last batch.  ``delta=None`` disables batching
+    (one batch).  Returns a list of lists of kernel indices.
+    """
+    batches = []
+    cur = []
+    acc = 0
+    for k, e in enumerate(est):
+        cur.append(k)
+        acc += e
+        if k == len(est) - 1 or (delta is not None and acc > delta):
+            batches.append(cur)
+            cur = []
+            acc = 0
+    return batches
+
+
+# --------------------------------------------------------------------------
+# Sec. 4.4.3: TH_urgent from the recorded highest urgencies
+# --------------------------------------------------------------------------
+def threshold_from_samples(samples, pct=95):
+    """TH_urgent as the nearest-rank ``pct``-th percentile of the sampled
+    highest urgencies, returned as a slack (see ``is_truly_urgent``).
+
+    ``samples`` are slacks of the most urgent active instance recorded at each
+    sampling instant.  They are ordered by urgency (ascending UL) and the
+    element at index ceil(pct/100 * n) - 1 is taken.  A percentile at zero or
+    negative slack leaves no urgency above it, so no task is truly urgent
+    (th_slack = 0).
+    """
+    if not samples:
+        return 0
+    order = rank_sort([(s, (i,), None) for i, s in enumerate(samples)])
+    ascending = [s for s, _, _ in reversed(order)]
+    n = len(ascending)
+    idx = (pct * n + 99) // 100 - 1
+    s = ascending[idx]
+    return s if s > 0 else 0
+
+
+# --------------------------------------------------------------------------
+# Eq. (3) and latency percentiles
+# --------------------------------------------------------------------------
+def overall_miss_ratio(per_chain):
+    """Eq. (3): mean over chains of (missed instances / total instances).
+
+    ``per_chain`` maps chain -> (missed, total); chains with no instances are
+    left out.
+    """
+    ratios = [Fraction(m, n) for m, n in per_chain.values() if n > 0]
+    if not ratios:
+        return Fraction(0)
+    return sum(ratios) / len(ratios)
+
+
+def is_miss(latency, deadline):
+    """A chain instance misses its deadline when its latency exceeds D."""
+    return latency > deadline
+
+
+def percentile_nearest_rank(values, pct):
+    """Nearest-rank percentile: the ceil(pct/100 * n)-th smallest value."""
+    v = sorted(values)
+    if not v:
+        return None
+    idx = max(0, -(-pct * len(v) // 100) - 1)
+    return v[idx]
+
+
+def percentile_numpy_inverted_cdf(values, pct):
+    """The same percentile through numpy's 'inverted_cdf' method (cross-check)."""
+    return np.percentile(np.asarray(values), pct, method="inverted_cdf")

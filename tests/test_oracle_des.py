@@ -1,0 +1,308 @@
+"""Pins of the oracle gate model and its discrete-event drivers.
+
+Hand timelines (closed forms), brute force over every execution order on
+tiny instances, the Jackson special case, a pinned counterexample that keeps
+the policy least-laxity rather than earliest-deadline, and invariants on
+randomised runs.
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import brute, des
+from oracle import policy as P
+from oracle.gate import END, START, GateModel
+
+MS = 1_000_000
+US = 1_000
+
+
+def chain(deadline, tasks):
+    """tasks: list of (cpu_ns, [(est_ns, util), ...])."""
+    return {"deadline_ns": deadline,
+            "tasks": [{"cpu_ns": cpu, "est_ns": [e for e, _ in ks], "util": [u for _, u in ks]}
+                      for cpu, ks in tasks]}
+
+
+def by_est(chains):
+    """Device durations equal to the estimates."""
+    def d(c, f, g):
+        est = [e for t in chains[c]["tasks"] for e in t["est_ns"]]
+        return est[g]
+    return d
+
+
+# ------------------------------------------------------------------ T1
+def test_T1_slack_after_first_batch_is_confirmed():
+    ch = [chain(10 * MS, [(0, [(2 * MS, 1.0), (3 * MS, 1.0), (1 * MS, 1.0)])])]
+    actual = [int(2.5 * MS), 3 * MS, 1 * MS]
+    cfg = {"policy": "urgency", "delta_eval_ns": 500 * US}
+    res = des.simulate(ch, cfg, [(0, 0, 0)], lambda c, f, g: actual[g])
+    # instant at 2.5 ms observes the start of batch 1 (kernel 1): kernel 0 is done
+    snaps = {}
+    model = GateModel(ch, cfg)
+    for t, arr, evs, dec in res["instants"]:
+        model.instant(t, arr, evs)
+        snaps[t] = model.last_snapshot.get((0, 0))
+    assert snaps[0] == 4 * MS
+    assert snaps[int(2.5 * MS)] == int(3.5 * MS)
+    # frame completes when the last kernel does: 2.5 + 3 + 1 ms
+    assert res["completed"] == [(0, 0, 0, int(6.5 * MS))]
+
+
+# ------------------------------------------------------------------ T2 on the gate
+def test_T2_batches_and_overlap_on_gate():
+    est = [200 * US, 200 * US, 200 * US, 100 * US, 600 * US, 50 * US]
+    ch = [chain(100 * MS, [(0, [(e, 1.0) for e in est])])]
+    cfg = {"policy": "urgency", "delta_eval_ns": 500 * US}
+    res = des.simulate(ch, cfg, [(0, 0, 0)], by_est(ch))
+    dec = [d for _, _, _, ds in res["instants"] for d in ds]
+    seq = [(d[0], d[5] if d[0] == "EVREC" else d[3]) for d in dec if d[0] in ("EVREC", "LAUNCH")]
+    assert seq == [("EVREC", 0), ("LAUNCH", 0), ("LAUNCH", 1), ("LAUNCH", 2),
+                   ("EVREC", 1), ("LAUNCH", 3), ("LAUNCH", 4),
+                   ("EVREC", 2), ("LAUNCH", 5), ("EVREC", 3)]
+    # batch 2 is launched when batch 0 is done (start event of batch 1 observed)
+    t_b2 = [t for t, _, _, ds in res["instants"] if any(d[0] == "LAUNCH" and d[3] == 5 for d in ds)]
+    assert t_b2 == [600 * US]
+    des.check_log(ch, cfg, res["instants"])
+
+
+# ------------------------------------------------------------------ delay timelines
+def _delay_case(poll, deadline_a=3 * MS):
+    # A: truly urgent (slack 1.5 ms < TH 2 ms at t = 0, 0.5 ms at 1 ms);
+    # B: lax, high utilisation
+    ch = [chain(deadline_a, [(0, [(int(1.5 * MS), 1.0)])]),
+          chain(100 * MS, [(0, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "th_slack_ns": 2 * MS, "delay_poll_ns": poll}
+    return ch, cfg, des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 0)], by_est(ch))
+
+
+def test_delay_sleep_loop_timeline():
+    ch, cfg, res = _delay_case(1 * MS)
+    holds = [t for t, _, _, ds in res["instants"] for d in ds if d[0] == "HOLD"]
+    rel = [t for t, _, _, ds in res["instants"] for d in ds if d[0] == "LAUNCH" and d[1] == 1]
+    # held at 0 and again at the 1 ms wake (A still active until 1.5 ms);
+    # released at the next wake, 2 ms, not when A retires
+    assert holds == [0, 1 * MS]
+    assert rel == [2 * MS]
+    assert sorted(res["completed"]) == [(0, 0, 0, int(1.5 * MS)), (1, 0, 0, 3 * MS)]
+    binds = [d for _, _, _, ds in res["instants"] for d in ds if d[0] == "BIND"]
+    assert binds[0][4] == 0            # A bound to the reserved level
+    des.check_log(ch, cfg, res["instants"])
+
+
+def test_delay_event_driven_timeline():
+    ch, cfg, res = _delay_case(0)
+    rel = [t for t, _, _, ds in res["instants"] for d in ds if d[0] == "LAUNCH" and d[1] == 1]
+    assert rel == [int(1.5 * MS)]      # released as soon as A's completion is observed
+
+
+def test_lost_deadline_is_no_longer_urgent():
+    """With D_A = 2 ms, A's slack is 0.5 ms at t = 0 but -0.5 ms at the 1 ms
+    wake (its estimate says the deadline is lost), so A stops blocking and B
+    is released at that wake although A is still running."""
+    ch, cfg, res = _delay_case(1 * MS, deadline_a=2 * MS)
+    holds = [t for t, _, _, ds in res["instants"] for d in ds if d[0] == "HOLD"]
+    rel = [t for t, _, _, ds in res["instants"] for d in ds if d[0] == "LAUNCH" and d[1] == 1]
+    assert holds == [0] and rel == [1 * MS]
+
+
+def test_low_utilisation_kernels_are_exempt():
+    ch = [chain(3 * MS, [(0, [(int(1.5 * MS), 1.0)])]),
+          chain(100 * MS, [(0, [(1 * MS, 0.09)])])]
+    cfg = {"policy": "urgency", "th_slack_ns": 2 * MS}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 0)], by_est(ch))
+    assert not any(d[0] == "HOLD" for _, _, _, ds in res["instants"] for d in ds)
+
+
+def test_same_chain_never_blocks_itself():
+    # two frames of one chain, pipelined over two tasks; the urgent older
+    # frame must not hold the newer one back
+    ch = [chain(2 * MS, [(0, [(1 * MS, 1.0)]), (0, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "th_slack_ns": 5 * MS}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (0, 1, 500 * US)], by_est(ch))
+    assert not any(d[0] == "HOLD" for _, _, _, ds in res["instants"] for d in ds)
+
+
+# ------------------------------------------------------------------ CPU segments
+def test_cpu_segment_delays_and_counts_in_slack():
+    ch = [chain(20 * MS, [(3 * MS, [(1 * MS, 1.0)]), (2 * MS, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency"}
+    res = des.simulate(ch, cfg, [(0, 0, 0)], by_est(ch))
+    launches = [(t, d[3]) for t, _, _, ds in res["instants"] for d in ds if d[0] == "LAUNCH"]
+    assert launches == [(3 * MS, 0), (6 * MS, 1)]
+    assert res["completed"] == [(0, 0, 0, 7 * MS)]
+    model = GateModel(ch, cfg)
+    model.instant(0, [(0, 0, 0)], [])
+    assert model.last_snapshot[(0, 0)] == 20 * MS - 2 * MS - 5 * MS
+
+
+# ------------------------------------------------------------------ FIFO
+def test_fifo_launches_everything_on_task_streams():
+    ch = [chain(50 * MS, [(0, [(1 * MS, 1.0)] * 3)]),
+          chain(50 * MS, [(0, [(1 * MS, 1.0)] * 2), (0, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "fifo"}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 0)], by_est(ch))
+    first = res["instants"][0][3]
+    kinds = [d[0] for d in first]
+    assert kinds.count("LAUNCH") == 5 and "HOLD" not in kinds
+    lanes = {(d[1], d[3]): d[5] for d in first if d[0] == "BIND"}
+    assert lanes == {(0, 0): 0, (1, 0): 1}
+    t_task1 = [t for t, _, _, ds in res["instants"] if ("TSTART", 1, 0, 1) in ds]
+    assert lanes and t_task1 == [5 * MS]    # served in launch order: 3 + 2 ms
+
+
+# ------------------------------------------------------------------ brute force
+def _random_tiny(r, n_chains, max_kernels=6, unit=US):
+    chains, arrivals = [], []
+    budget = max_kernels
+    for c in range(n_chains):
+        k_left = budget - (n_chains - c - 1)
+        n_k = int(r.integers(1, min(3, k_left) + 1))
+        budget -= n_k
+        split = int(r.integers(0, n_k)) if n_k > 1 else 0
+        ks = [(int(r.integers(1, 8)) * 100 * unit, 1.0) for _ in range(n_k)]
+        tasks = [(0, ks)] if split == 0 else [(0, ks[:split]), (int(r.integers(0, 3)) * 100 * unit, ks[split:])]
+        chains.append(chain(int(r.integers(3, 25)) * 100 * unit, tasks))
+        arrivals.append((c, 0, int(r.integers(0, 6)) * 100 * unit))
+    return chains, arrivals
+
+
+def _exec_order(trace):
+    return [(c, g) for _, _, c, _, g in sorted(trace)]
+
+
+def test_bruteforce_accounting_identity_and_optimality():
+    r = np.random.default_rng(0)
+    for it in range(150):
+        chains, arrivals = _random_tiny(r, int(r.integers(2, 4)))
+        dur = by_est(chains)
+        cfg = {"policy": "urgency", "delay": False, "th_slack_ns": 0,
+               "delta_eval_ns": int(r.integers(1, 10)) * 100 * US}
+        res = des.simulate(chains, cfg, arrivals, dur)
+        done = {c: td for c, f, ta, td in res["completed"]}
+        forced = brute.forced_order(chains, arrivals, dur, _exec_order(res["trace"]))
+        assert done == forced, it
+        m, lmax, _ = brute.objectives(chains, arrivals, done)
+        bm, bl, _ = brute.best(chains, arrivals, dur)
+        assert m >= bm and lmax >= bl
+        des.check_log(chains, cfg, res["instants"])
+
+
+def test_jackson_subclass_is_optimal_for_lateness():
+    """Common arrival, one kernel per chain, equal durations, no deadline
+    already lost (D >= e, so every slack at t = 0 is >= 0): slack order is
+    deadline order (Jackson's rule), which minimises the maximum lateness and
+    so meets every deadline whenever some order does.  (A chain whose slack is
+    negative would rank last under Eq. (2), which is not EDF.)"""
+    r = np.random.default_rng(1)
+    for it in range(60):
+        n = int(r.integers(2, 7))
+        e = 300 * US
+        chains = [chain(int(r.integers(2, 13)) * 150 * US, [(0, [(e, 1.0)])]) for _ in range(n)]
+        arrivals = [(c, 0, 0) for c in range(n)]
+        cfg = {"policy": "urgency", "delay": False}
+        res = des.simulate(chains, cfg, arrivals, by_est(chains))
+        done = {c: td for c, f, ta, td in res["completed"]}
+        m, lmax, _ = brute.objectives(chains, arrivals, done)
+        bm, bl, _ = brute.best(chains, arrivals, by_est(chains))
+        assert lmax == bl, it
+        assert (m == 0) == (bm == 0)
+
+
+def test_T3_least_laxity_is_not_edf():
+    """A (e = 5, D = 6) and B (e = 1, D = 3) at t = 0 with no truly urgent
+    level: A has the smaller slack (1 < 2) and runs first, so B misses, while
+    running B first meets both deadlines: regret 1."""
+    chains = [chain(6 * MS, [(0, [(5 * MS, 1.0)])]), chain(3 * MS, [(0, [(1 * MS, 1.0)])])]
+    arrivals = [(0, 0, 0), (1, 0, 0)]
+    cfg = {"policy": "urgency", "th_slack_ns": 0}
+    res = des.simulate(chains, cfg, arrivals, by_est(chains))
+    done = {c: td for c, f, ta, td in res["completed"]}
+    assert done == {0: 5 * MS, 1: 6 * MS}
+    m, _, _ = brute.objectives(chains, arrivals, done)
+    bm, _, _ = brute.best(chains, arrivals, by_est(chains))
+    assert (m, bm) == (1, 0)
+
+
+def test_brute_force_enumerates_every_interleaving():
+    chains = [chain(MS, [(0, [(1, 1.0)] * 2)]), chain(MS, [(0, [(1, 1.0)] * 2)]),
+              chain(MS, [(0, [(1, 1.0)] * 1)])]
+    orders = list(brute.all_orders(chains))
+    assert len(orders) == 30                  # 5! / (2! 2! 1!)
+    assert len(set(map(tuple, orders))) == 30
+
+
+# ------------------------------------------------------------------ randomised invariants
+def _random_workload(r, n_chains=4, n_frames=4):
+    chains, arrivals = [], []
+    for c in range(n_chains):
+        tasks = []
+        for j in range(int(r.integers(1, 4))):
+            ks = [(int(r.integers(20, 400)) * US, float(r.choice([0.05, 0.5, 1.0])))
+                  for _ in range(int(r.integers(1, 8)))]
+            tasks.append((int(r.integers(0, 3)) * 200 * US, ks))
+        period = int(r.integers(4, 12)) * MS
+        chains.append(chain(int(period * r.choice([0.5, 1.0])), tasks))
+        phase = int(r.integers(0, period))
+        for f in range(n_frames):
+            arrivals.append((c, f, phase + f * period + int(r.integers(0, 300)) * US))
+    return chains, arrivals
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_runs_satisfy_invariants_and_replay(seed):
+    r = np.random.default_rng(100 + seed)
+    chains, arrivals = _random_workload(r)
+    noise = {}
+
+    def dur(c, f, g):
+        key = (c, f, g)
+        if key not in noise:
+            est = [e for t in chains[c]["tasks"] for e in t["est_ns"]]
+            noise[key] = max(1, int(est[g] * r.uniform(0.7, 1.4)))
+        return noise[key]
+
+    for cfg in ({"policy": "urgency", "th_slack_ns": 3 * MS},
+                {"policy": "urgency", "th_slack_ns": 3 * MS, "delay_poll_ns": 0},
+                {"policy": "urgency", "th_slack_ns": 0, "lanes": [1, 1]},
+                {"policy": "urgency", "batch": False, "bind": False, "th_slack_ns": 2 * MS}):
+        res = des.simulate(chains, cfg, arrivals, dur)
+        assert len(res["completed"]) == len(arrivals)
+        des.check_log(chains, cfg, res["instants"])
+        assert des.replay(chains, cfg, res["instants"]) is None
+    res = des.simulate(chains, {"policy": "fifo"}, arrivals, dur)
+    assert len(res["completed"]) == len(arrivals)
+
+
+def test_replay_detects_a_changed_decision():
+    r = np.random.default_rng(7)
+    chains, arrivals = _random_workload(r, 3, 3)
+    cfg = {"policy": "urgency", "th_slack_ns": 2 * MS}
+    res = des.simulate(chains, cfg, arrivals, by_est(chains))
+    inst = list(res["instants"])
+    k = next(i for i, x in enumerate(inst) if any(d[0] == "LAUNCH" for d in x[3]))
+    t, a, e, d = inst[k]
+    d = list(d)
+    li = next(i for i, x in enumerate(d) if x[0] == "LAUNCH")
+    d[li] = d[li][:5] + (d[li][5] + 1,)
+    inst[k] = (t, a, e, d)
+    assert des.replay(chains, cfg, inst)[0] == k
+
+
+def test_calibration_samples_and_threshold():
+    r = np.random.default_rng(3)
+    chains, arrivals = _random_workload(r, 4, 6)
+    cfg = {"policy": "urgency", "delay": False, "th_slack_ns": 0, "calibrate": True}
+    res = des.simulate(chains, cfg, arrivals, by_est(chains))
+    s = res["gate"].samples
+    assert len(s) > 10
+    th = P.threshold_from_samples(s)
+    pos = sorted(v for v in s if v > 0)
+    assert th == 0 or th in s
+    if th > 0:
+        # at most 5 % of the samples are more urgent than the threshold
+        more = sum(1 for v in s if P.ul_greater(v, th))
+        assert more <= 0.05 * len(s) + 1

@@ -1,0 +1,240 @@
+"""Pins of the oracle kernels against facts other than the oracle itself.
+
+Each test fixes a result by something independent of ``oracle.kernels``:
+integer arithmetic (exact in any order), hand-computed special cases, brute
+force over explicit loops, library routines (torch on the CPU), and closed
+forms.  Transposed operands, a flipped convolution window, a wrong padding, a
+mis-signed bias, a wrong axis or a transposed voxel index each fail at least
+one of them.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import kernels as K
+
+
+def rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# --------------------------------------------------------------------- GEMM
+def test_gemm_integer_inputs_exact():
+    r = rng(1)
+    A = r.integers(-2, 3, size=(37, 53)).astype(np.float32)
+    B = r.integers(-2, 3, size=(53, 29)).astype(np.float32)
+    exact = A.astype(np.int64) @ B.astype(np.int64)           # integer matmul
+    got = K.gemm_f64(A, B)
+    assert got.shape == (37, 29)
+    assert np.array_equal(got, exact.astype(np.float64))
+
+
+def test_gemm_hand_example():
+    A = np.array([[1, 2, 3], [4, 5, 6]], np.float32)
+    B = np.array([[7, 8], [9, 10], [11, 12]], np.float32)
+    assert K.gemm_f64(A, B).tolist() == [[58.0, 64.0], [139.0, 154.0]]
+    v, s = K.gemm_entry_f64(A, B, 1, 0)
+    assert v == 139.0 and s == 139.0
+
+
+def test_gemm_abs_scale_bounds_error():
+    r = rng(2)
+    A = r.uniform(-1, 1, (64, 256)).astype(np.float32)
+    B = r.uniform(-1, 1, (256, 48)).astype(np.float32)
+    c32 = (torch.from_numpy(A) @ torch.from_numpy(B)).numpy()
+    c64 = K.gemm_f64(A, B)
+    scale = K.gemm_abs_f64(A, B)
+    # gamma_K bound of float32 summation: K u / (1 - K u)
+    u = 2.0 ** -24
+    gam = 256 * u / (1 - 256 * u)
+    assert np.all(np.abs(c32 - c64) <= gam * scale + 1e-30)
+
+
+# --------------------------------------------------------------- bias+ReLU
+def test_bias_relu_special_values():
+    X = np.array([[-0.0, np.nan, 1.5, -3.0],
+                  [2.0, 0.25, -0.25, np.inf]], np.float32)
+    b = np.array([0.0, 1.0, -1.5, 1.0], np.float32)        # per column
+    y = K.bias_relu_f32(X, b, axis=0)
+    want = np.array([[0.0, 0.0, 0.0, 0.0],
+                     [2.0, 1.25, 0.0, np.inf]], np.float32)
+    assert np.array_equal(y, want)
+    assert not np.any(np.signbit(y))                        # -0 maps to +0
+
+
+def test_bias_relu_single_rounding():
+    # 1 + 2^-24 is a tie in float32 and rounds to even (1.0); a two-step or
+    # float64 sum would give a different bit pattern.
+    X = np.array([[1.0, 1.0]], np.float32)
+    b = np.array([2.0 ** -24, 3 * 2.0 ** -24], np.float32)
+    y = K.bias_relu_f32(X, b, axis=0)
+    assert y[0, 0] == np.float32(1.0)
+    assert y[0, 1] == np.float32(1.0 + 2.0 ** -22)
+
+
+def test_bias_relu_axis_orientation():
+    X = np.zeros((2, 3), np.float32)
+    yc = K.bias_relu_f32(X, np.array([1, 2, 3], np.float32), axis=0)
+    yr = K.bias_relu_f32(X, np.array([5, 7], np.float32), axis=1)
+    assert yc.tolist() == [[1, 2, 3], [1, 2, 3]]
+    assert yr.tolist() == [[5, 5, 5], [7, 7, 7]]
+
+
+# ------------------------------------------------------------------- conv
+def conv_loops(X, W):
+    """Six nested loops over the definition, Python ints/floats."""
+    n, c, h, w = X.shape
+    o = W.shape[0]
+    Y = np.zeros((n, o, h, w))
+    for b in range(n):
+        for oc in range(o):
+            for y in range(h):
+                for x in range(w):
+                    acc = 0.0
+                    for ic in range(c):
+                        for dy in range(3):
+                            for dx in range(3):
+                                yy, xx = y + dy - 1, x + dx - 1
+                                if 0 <= yy < h and 0 <= xx < w:
+                                    acc += float(W[oc, ic, dy, dx]) * float(X[b, ic, yy, xx])
+                    Y[b, oc, y, x] = acc
+    return Y
+
+
+def test_conv_integer_bruteforce():
+    r = rng(3)
+    X = r.integers(-2, 3, (1, 3, 5, 6)).astype(np.float32)
+    W = r.integers(-2, 3, (3, 3, 3, 3)).astype(np.float32)
+    assert np.array_equal(K.conv3x3_f64(X, W), conv_loops(X, W))
+
+
+def test_conv_identity_and_shift():
+    r = rng(4)
+    X = r.uniform(-1, 1, (1, 2, 4, 5)).astype(np.float32)
+    W = np.zeros((2, 2, 3, 3), np.float32)
+    W[0, 0, 1, 1] = 1.0
+    W[1, 1, 1, 1] = 1.0
+    assert np.array_equal(K.conv3x3_f64(X, W), X.astype(np.float64))
+    # tap (dy, dx) = (0, 0) reads X[y-1, x-1] (cross-correlation, zero pad)
+    W = np.zeros((2, 2, 3, 3), np.float32)
+    W[0, 0, 0, 0] = 1.0
+    W[1, 1, 0, 0] = 1.0
+    Y = K.conv3x3_f64(X, W)
+    assert np.all(Y[:, :, 0, :] == 0) and np.all(Y[:, :, :, 0] == 0)
+    assert np.array_equal(Y[:, :, 1:, 1:], X[:, :, :-1, :-1].astype(np.float64))
+
+
+def test_conv_matches_torch_cpu_f64():
+    r = rng(5)
+    X = r.uniform(-1, 1, (2, 5, 9, 7)).astype(np.float32)
+    W = r.uniform(-1, 1, (5, 5, 3, 3)).astype(np.float32)
+    ref = torch.nn.functional.conv2d(torch.from_numpy(X).double(),
+                                     torch.from_numpy(W).double(), padding=1).numpy()
+    np.testing.assert_allclose(K.conv3x3_f64(X, W), ref, rtol=1e-13, atol=1e-13)
+    v, s = K.conv3x3_entry_f64(X, W, 1, 3, 0, 6)
+    assert abs(v - ref[1, 3, 0, 6]) < 1e-12
+    assert abs(s - K.conv3x3_abs_f64(X, W)[1, 3, 0, 6]) < 1e-12
+
+
+# ----------------------------------------------------------------- rowsum
+def test_rowsum_integer_exact_and_closed_form():
+    r = rng(6)
+    Z = r.integers(-2, 3, (17, 301)).astype(np.float32)
+    s, a = K.rowsum_f64(Z)
+    assert np.array_equal(s, Z.astype(np.int64).sum(axis=1).astype(np.float64))
+    assert np.array_equal(a, np.abs(Z).astype(np.int64).sum(axis=1).astype(np.float64))
+    ones = np.ones((3, 1000), np.float32)
+    assert K.rowsum_f64(ones)[0].tolist() == [1000.0] * 3
+
+
+# ---------------------------------------------------------------- softmax
+def test_softmax_closed_forms():
+    y = K.softmax_f64(np.array([[0.0, math.log(3.0)]]))
+    np.testing.assert_allclose(y, [[0.25, 0.75]], rtol=1e-15)
+    c = K.softmax_f64(np.full((2, 7), 3.25, np.float32))
+    assert np.all(c == 1.0 / 7.0)
+
+
+def test_softmax_sums_and_shift_invariance():
+    r = rng(7)
+    X = r.uniform(-30, 30, (9, 513))
+    y = K.softmax_f64(X)
+    np.testing.assert_allclose(y.sum(axis=1), 1.0, rtol=1e-14)
+    np.testing.assert_allclose(K.softmax_f64(X + 17.0), y, rtol=1e-12)
+    assert np.argmax(y[0]) == np.argmax(X[0])
+    ref = torch.softmax(torch.from_numpy(X), dim=1).numpy()
+    np.testing.assert_allclose(y, ref, rtol=1e-12)
+
+
+# ----------------------------------------------------------------- voxels
+def test_voxel_cell_centres_and_orientation():
+    # nx != ny so a transposed index is caught; points at cell centres are
+    # unambiguous whatever the rounding.
+    nx, ny = 7, 5
+    xmin, ymin, scale = np.float32(-1.4), np.float32(-1.0), np.float32(5.0)
+    pts = []
+    want = []
+    for iy in range(ny):
+        for ix in range(nx):
+            pts.append([-1.4 + (ix + 0.5) * 0.2, -1.0 + (iy + 0.5) * 0.2, 0.0, 0.0])
+            want.append(iy * nx + ix)
+    got = K.voxel_cell_f32(np.array(pts, np.float32), nx, ny, xmin, ymin, scale)
+    assert got.tolist() == want
+
+
+def test_voxel_boundaries():
+    P = np.array([
+        [-51.2, 0.1, 0, 0],          # left edge is inside: ix = 0
+        [51.2, 0.1, 0, 0],           # right edge is outside (half open)
+        [-51.2001, 0.1, 0, 0],       # just left of the grid
+        [51.19, 51.19, 0, 0],        # last cell
+        [0.1, -51.2, 0, 0],          # bottom edge inside
+        [0.1, 51.2, 0, 0],           # top edge outside
+        [np.nan, 0.0, 0, 0],
+        [np.inf, 0.0, 0, 0],
+        [0.0, -np.inf, 0, 0],
+    ], np.float32)
+    v = K.voxel_cell_f32(P)
+    assert v[0] == 256 * 512 + 0
+    assert v[1] == -1 and v[2] == -1
+    assert v[3] == 511 * 512 + 511
+    assert v[4] == 0 * 512 + 256
+    assert v[5] == -1 and v[6] == -1 and v[7] == -1 and v[8] == -1
+
+
+def test_voxel_reductions_bruteforce():
+    r = rng(8)
+    n = 3000
+    pts = np.stack([r.normal(0, 0.3, n), r.normal(0, 0.3, n),
+                    r.normal(0, 1, n), r.uniform(0, 1, n)], axis=1).astype(np.float32)
+    pts[::97, 0] = 60.0                                  # some points outside
+    nx, ny = 8, 6
+    xmin, ymin, scale = np.float32(-0.8), np.float32(-0.6), np.float32(5.0)
+    vidx, count, zmax, first = K.voxel_scatter(pts, nx, ny, xmin, ymin, scale)
+    cells = {}
+    for p in range(n):
+        v = int(vidx[p])
+        if v < 0:
+            continue
+        cells.setdefault(v, []).append(p)
+    for v in range(nx * ny):
+        members = cells.get(v, [])
+        assert count[v] == len(members)
+        if members:
+            assert zmax[v] == max(pts[p, 2] for p in members)
+            assert first[v] == min(members)
+        else:
+            assert zmax[v] == -np.inf and first[v] == -1
+    assert count.sum() == int((vidx >= 0).sum())
+
+
+def test_voxel_signed_zero_max():
+    pts = np.array([[0.1, 0.1, -0.0, 0], [0.1, 0.1, 0.0, 0], [0.3, 0.1, -0.0, 0]], np.float32)
+    _, _, zmax, _ = K.voxel_scatter(pts)
+    v0 = K.voxel_cell_f32(pts[:1])[0]
+    v2 = K.voxel_cell_f32(pts[2:])[0]
+    assert zmax[v0] == 0 and not np.signbit(zmax[v0])
+    assert zmax[v2] == 0 and np.signbit(zmax[v2])
