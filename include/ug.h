@@ -1,0 +1,344 @@
+/*
+ * ug.h -- C-ABI of libug: an urgency-gated launcher for deadline-bound task
+ * chains of GPU kernels on one MI355X (gfx950), after UrgenGo
+ * (arXiv 2509.12207).
+ *
+ * Problem statement (Sec. 1, Sec. 2 "Urgency Level", Sec. 4.2): a set of
+ * periodic task chains shares one GPU.  Each chain has an end-to-end deadline
+ * D and an ordered list of tasks; each task is a CPU segment followed by a
+ * sequence of GPU kernels that run on one stream.  Every arriving data frame
+ * starts an instance of its chain.  The library launches the kernels of all
+ * instances itself, ordered by the urgency of Eq. (2), with task-level stream
+ * binding (Sec. 4.4.3), delayed launching (Sec. 4.4.4) and batched launch
+ * synchronisation with batch overlap (Sec. 4.4.5), and reports each frame's
+ * latency and deadline miss (Sec. 6.2).
+ *
+ * Conventions
+ *   - Every function is extern "C" and never throws.  Functions returning
+ *     ug_status return UG_OK (0) or a negative UG_E* code; the message of the
+ *     last failure on a context is available from ug_last_error().
+ *   - Times are int64 nanoseconds on CLOCK_MONOTONIC (ug_now_ns()).
+ *   - Buffers are device pointers (hipMalloc or torch allocations on the
+ *     context's device).  The library never allocates or frees them.
+ *   - A device error (a failed HIP call) is sticky: once reported, every later
+ *     call on the context returns UG_EDEVICE.
+ *
+ * Threading: one caller thread may call ug_frame_submit / ug_poll_complete /
+ * ug_drain while the context's internal gate thread runs.  Other calls must
+ * not overlap with them.
+ */
+#ifndef UG_H
+#define UG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UG_ABI_VERSION 1u
+
+typedef int32_t ug_status;
+enum {
+  UG_OK = 0,
+  UG_EINVAL = -1,    /* invalid argument (shape, slot, id, size, null)       */
+  UG_ENOMEM = -2,    /* host allocation failed                               */
+  UG_EDEVICE = -3,   /* a HIP call failed; sticky for the context            */
+  UG_EAGAIN = -4,    /* submission queue full; retry after polling           */
+  UG_ETIMEDOUT = -5, /* ug_drain timed out                                   */
+  UG_ESTATE = -6,    /* call not allowed in the context's current state      */
+  UG_ENODEV = -7     /* the context has no device (created with device < 0) */
+};
+
+/* Launch policy. */
+enum {
+  UG_POLICY_FIFO = 0,    /* plain launch: every kernel of a ready task at once,
+                            on that task's own stream, one end event per task
+                            (the "vanilla" baseline of Sec. 6.3)             */
+  UG_POLICY_URGENCY = 1  /* urgency-ordered gate of Sec. 4.4                  */
+};
+
+/* Switches of the urgency policy (ug_config.flags). */
+enum {
+  UG_F_BIND = 1u,      /* task-level stream binding with reservation (4.4.3) */
+  UG_F_DELAY = 2u,     /* delayed launching (4.4.4)                          */
+  UG_F_BATCH = 4u,     /* batched launching with batch overlap (4.4.5)       */
+  UG_F_CALIBRATE = 8u  /* record highest-urgency samples for TH_urgent (4.4.3) */
+};
+
+/* Operations.  Shapes and slot meaning per op; all float buffers are fp32,
+ * row-major / NCHW, densely packed.  "in"/"out" hold buffer-slot indices
+ * into the pointer array passed with each frame (-1 = unused).
+ *
+ *  UG_OP_GEMM_F32       C = A B.  shape {M, N, K}; in {A[M,K], B[K,N]};
+ *                       out {C[M,N]}.  FP32 MFMA, FP32 accumulation.
+ *  UG_OP_BIAS_RELU_F32  y = max(x + b, +0).  shape {R, C, axis}; in {X[R,C],
+ *                       b}; out {Y[R,C]} (Y may alias X).  axis 0: b[C] per
+ *                       column; axis 1: b[R] per row (NCHW channel bias).
+ *  UG_OP_CONV3X3_F32    3x3 cross-correlation, stride 1, zero pad 1, as many
+ *                       output as input channels.  shape {N, C, H, W};
+ *                       in {X[N,C,H,W], W[C,C,3,3]}; out {Y[N,C,H,W]}.
+ *  UG_OP_ROWSUM_F32     r_i = sum_j Z_ij.  shape {R, C}; in {Z[R,C]}; out {r[R]}.
+ *  UG_OP_SOFTMAX_F32    row softmax.  shape {R, L}; in {X[R,L]}; out {Y[R,L]}
+ *                       (Y may alias X).
+ *  UG_OP_VOXEL_F32      bird's-eye-view pillar binning.  shape {N, nx, ny};
+ *                       fparam {xmin, ymin, scale}; in {pts[N,4] (x,y,z,i)};
+ *                       out {vidx[N] int32, count[nx*ny] int32,
+ *                       zmax[nx*ny] fp32, first[nx*ny] int32}.  Cell of a
+ *                       point: ix = floor(fl32(fl32(x - xmin) * scale)), iy
+ *                       likewise, inside iff 0 <= ix < nx and 0 <= iy < ny;
+ *                       vidx = iy*nx + ix or -1.  Empty cells: count 0,
+ *                       zmax -inf, first -1.  z must not be NaN.
+ */
+enum {
+  UG_OP_GEMM_F32 = 1,
+  UG_OP_BIAS_RELU_F32 = 2,
+  UG_OP_CONV3X3_F32 = 3,
+  UG_OP_ROWSUM_F32 = 4,
+  UG_OP_SOFTMAX_F32 = 5,
+  UG_OP_VOXEL_F32 = 6
+};
+
+/* One kernel of a task (a row of the paper's lookup table, Tab. "Example
+ * lookup table", plus its buffer bindings). */
+typedef struct {
+  int32_t op;          /* UG_OP_*                                             */
+  int32_t in[3];       /* input buffer slots, -1 = unused                     */
+  int32_t out[4];      /* output buffer slots, -1 = unused                    */
+  int64_t shape[4];    /* op-specific, see above                              */
+  float fparam[4];     /* op-specific float parameters                        */
+  int64_t est_ns;      /* estimated execution time E_k; 0 = not yet profiled  */
+  float util;          /* utilisation U_k in [0,1]; < 0 = derive from launch  */
+  int32_t pad1;
+} ug_kernel;
+
+/* One task: a CPU segment (host-side time before the kernels may launch,
+ * Sec. 4.2) followed by kernels that run in order on one stream. */
+typedef struct {
+  const ug_kernel* kernels;
+  uint32_t n_kernels;
+  uint32_t pad0;
+  int64_t cpu_ns;      /* CPU-segment time; also its estimate in Eq. (2)     */
+} ug_task;
+
+typedef struct {
+  uint32_t abi_version;    /* must be UG_ABI_VERSION                         */
+  int32_t policy;          /* UG_POLICY_*                                    */
+  uint32_t flags;          /* UG_F_* (urgency policy only)                   */
+  int32_t device;          /* HIP device ordinal; < 0 = no device: the
+                              context only registers chains and replays
+                              decision instants (ug_replay_instant)          */
+  int64_t delta_eval_ns;   /* Delta_eval of batched launching (0.5 ms)       */
+  int64_t delay_poll_ns;   /* sleep step of delayed launching (1 ms);
+                              0 = re-check a held launch at every instant    */
+  float util_exempt;       /* kernels with U below this are never held (0.1) */
+  int32_t n_levels;        /* stream levels, 1..8; level 0 is reserved for
+                              truly urgent tasks when n_levels > 1          */
+  int32_t lanes[8];        /* streams per level                             */
+  int64_t th_slack_ns;     /* TH_urgent carried as a slack: truly urgent iff
+                              0 <= slack < th_slack_ns; <= 0 = nobody        */
+  int64_t idle_sleep_ns;   /* gate thread sleep when idle; 0 = spin         */
+  uint32_t queue_capacity; /* max frames submitted and not yet completed    */
+  uint32_t trace_capacity; /* decision-log records kept; 0 = no log         */
+} ug_config;
+
+/* Completion of one frame (Sec. 6.2: latency, miss). */
+typedef struct {
+  uint32_t chain;
+  uint32_t pad0;
+  uint64_t frame;          /* frame index within its chain (0, 1, ...)      */
+  int64_t t_arr_ns;
+  int64_t t_done_ns;       /* when the gate observed the last kernel done   */
+  int64_t latency_ns;      /* t_done - t_arr                                */
+  int32_t missed;          /* latency > deadline                            */
+  int32_t n_holds;         /* launches of this frame that were held         */
+  int32_t n_batches;       /* launch batches of this frame                  */
+  int32_t pad1;
+} ug_completion;
+
+/* Decision-log record.  The log is a sequence of instants; each INSTANT
+ * record is followed by its inputs (ARRIVE, EVDONE) and then the decisions
+ * taken at that instant (COMPLETE, TSTART, BIND, HOLD, EVREC, LAUNCH).
+ *   INSTANT  t = instant time, a = #arrivals, b = #observed events
+ *   ARRIVE   chain, frame, t = t_arr
+ *   EVDONE   chain, frame, task, a = kind (0 batch start, 1 task end), b = seq
+ *   COMPLETE chain, frame, t = t_done
+ *   TSTART   chain, frame, task
+ *   BIND     chain, frame, task, a = level, b = lane
+ *   HOLD     chain, frame, kernel
+ *   EVREC    chain, frame, task, a = kind, b = seq (batch index, or the
+ *            number of batches for the end event)
+ *   LAUNCH   chain, frame, kernel, a = level, b = lane
+ * kernel = index within the chain (all tasks' kernels numbered in order). */
+enum {
+  UG_REC_INSTANT = 1, UG_REC_ARRIVE = 2, UG_REC_EVDONE = 3, UG_REC_COMPLETE = 4,
+  UG_REC_TSTART = 5, UG_REC_BIND = 6, UG_REC_HOLD = 7, UG_REC_EVREC = 8,
+  UG_REC_LAUNCH = 9
+};
+typedef struct {
+  int32_t type;
+  int32_t chain;
+  int64_t frame;
+  int32_t task;
+  int32_t kernel;
+  int32_t a;
+  int32_t b;
+  int64_t t;
+} ug_record;
+
+typedef struct {
+  uint64_t frames_submitted;
+  uint64_t frames_completed;
+  uint64_t frames_missed;
+  uint64_t launches;
+  uint64_t holds;
+  uint64_t batches;
+  uint64_t instants;
+  uint64_t collisions;     /* truly urgent launches made while another
+                              chain's kernels were active (Sec. 6.4)        */
+  int64_t decide_ns;       /* time spent deciding (policy only)             */
+  int64_t launch_ns;       /* time spent in HIP launch/record calls         */
+  uint64_t trace_records;  /* records currently in the log                  */
+  uint64_t trace_dropped;  /* records lost because the log was full         */
+} ug_stats;
+
+/* ------------------------------------------------------------------------ */
+
+/* Fills *cfg with the paper's defaults: URGENCY with BIND|DELAY|BATCH,
+ * Delta_eval 0.5 ms, 1 ms sleep step, U exemption 0.1, device 0, 3 levels
+ * with lanes {1, 2, 1}, no truly-urgent threshold, spinning gate thread. */
+void ug_config_default(ug_config* cfg);
+
+/* CLOCK_MONOTONIC in ns: the clock of every time argument. */
+int64_t ug_now_ns(void);
+
+/* Static text of a status code. */
+const char* ug_status_str(ug_status s);
+
+/* Creates a context.  With cfg->device >= 0 it creates its streams (all at
+ * the default priority) and events on that device.  *out is owned by the
+ * caller and released with ug_destroy.  Errors: UG_EINVAL, UG_ENOMEM,
+ * UG_EDEVICE. */
+ug_status ug_create(const ug_config* cfg, void** out);
+
+/* Stops the gate thread (without waiting for in-flight frames), releases
+ * streams and events.  Buffers of unfinished frames are left untouched. */
+void ug_destroy(void* ctx);
+
+/* Message of the last error on ctx (static storage of the context). */
+const char* ug_last_error(void* ctx);
+
+/* Registers a chain: a period (informational), an end-to-end deadline and
+ * an ordered task list (Sec. 4.1).  n_buffers is the number of buffer slots
+ * each frame supplies.  Descriptors are deep-copied.  Only before ug_start.
+ * Errors: UG_EINVAL (bad op/shape/slot), UG_ESTATE (already started). */
+ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
+                            const ug_task* tasks, uint32_t n_tasks,
+                            uint32_t n_buffers, uint32_t* chain_id);
+
+/* Sets / reads the estimate E_k and utilisation U_k of kernel `kernel` of a
+ * chain (offline profile, Sec. 4.1 and Tab. "Example lookup table").  Set
+ * only before ug_start.  util < 0 keeps the current value. */
+ug_status ug_kernel_set_estimate(void* ctx, uint32_t chain, uint32_t kernel,
+                                 int64_t est_ns, float util);
+ug_status ug_kernel_get_estimate(void* ctx, uint32_t chain, uint32_t kernel,
+                                 int64_t* est_ns, float* util);
+
+/* Offline profiling stage (Sec. 4.1): runs every kernel of the chain in
+ * isolation on the given frame buffers (warmup, then reps timed with HIP
+ * events; the median is E_k) and stores the estimates.  Kernels with the
+ * same (op, shape) share one measurement.  Overwrites the buffers' contents.
+ * Only before ug_start.  Errors: UG_ENODEV, UG_EINVAL, UG_EDEVICE. */
+ug_status ug_profile(void* ctx, uint32_t chain, void* const* buffers,
+                     uint32_t n_buffers, uint32_t warmup, uint32_t reps);
+
+/* Changes TH_urgent (as a slack) or turns calibration sampling on/off.
+ * Only while not started. */
+ug_status ug_set_threshold(void* ctx, int64_t th_slack_ns);
+ug_status ug_set_flags(void* ctx, int32_t policy, uint32_t flags);
+
+/* Starts the gate thread.  Registration is closed from here on. */
+ug_status ug_start(void* ctx);
+
+/* Submits one frame of `chain` arriving at t_arr_ns (< 0: now; a future time
+ * is honoured: the frame arrives when the clock reaches it).  buffers[i] is
+ * the device pointer of slot i; the caller keeps them alive and unmodified
+ * until the frame is returned by ug_poll_complete (borrowed).  *frame gets
+ * the frame index within the chain.  Errors: UG_EINVAL, UG_ESTATE (not
+ * started), UG_EAGAIN (queue_capacity frames outstanding), UG_EDEVICE. */
+ug_status ug_frame_submit(void* ctx, uint32_t chain, int64_t t_arr_ns,
+                          void* const* buffers, uint32_t n_buffers,
+                          uint64_t* frame);
+
+/* Non-blocking: copies up to cap completions into out.  Returns how many
+ * (>= 0), or UG_EDEVICE. */
+int32_t ug_poll_complete(void* ctx, ug_completion* out, uint32_t cap);
+
+/* Waits until every submitted frame has completed (completions stay
+ * queued for ug_poll_complete).  Errors: UG_ETIMEDOUT, UG_EDEVICE. */
+ug_status ug_drain(void* ctx, int64_t timeout_ns);
+
+/* Stops the gate thread after ug_drain; registration stays closed.  The
+ * context can be restarted with ug_start (e.g. after ug_set_threshold). */
+ug_status ug_stop(void* ctx);
+
+ug_status ug_get_stats(void* ctx, ug_stats* out);
+
+/* Copies up to cap records of the decision log into out and removes them
+ * from the log.  Returns how many (>= 0). */
+int32_t ug_trace_read(void* ctx, ug_record* out, uint32_t cap);
+
+/* Copies the calibration samples (slack of the most urgent active
+ * instance at each instant, ns) recorded under UG_F_CALIBRATE; returns the
+ * number copied. */
+int32_t ug_calibration_read(void* ctx, int64_t* out, uint32_t cap);
+
+/* TH_urgent from the recorded samples (Sec. 4.4.3): the samples are ordered
+ * by urgency (ascending UL = 1/slack) and the nearest-rank pct-th percentile
+ * is taken (index ceil(pct/100 * n) - 1).  *th_slack_ns gets its slack, or 0
+ * (no task is truly urgent) if that slack is <= 0 or there is no sample.
+ * Only while not started. */
+ug_status ug_calibration_threshold(void* ctx, int32_t pct, int64_t* th_slack_ns);
+
+/* Deadline metrics over the frames completed since ug_start (Sec. 6.2):
+ * Eq. (3) overall miss ratio (mean over chains with completions of
+ * missed / completed), and pooled nearest-rank latency percentiles. */
+typedef struct {
+  uint64_t frames;
+  uint64_t missed;
+  double miss_ratio;       /* Eq. (3), in [0, 1]                             */
+  int64_t p50_ns;
+  int64_t p99_ns;
+  int64_t max_ns;
+  double mean_ns;
+  uint32_t n_chains;       /* chains with at least one completed frame       */
+  uint32_t pad0;
+} ug_metrics;
+ug_status ug_get_metrics(void* ctx, ug_metrics* out);
+
+/* Offline replay of one decision instant on a context created with
+ * device < 0: applies `inputs` (ARRIVE and EVDONE records) at time t,
+ * decides, and writes the decisions to out (COMPLETE..LAUNCH records).
+ * *n_out receives their number.  Errors: UG_ESTATE (context has a device),
+ * UG_EINVAL (an input the state does not expect), UG_ENOMEM (cap too small). */
+ug_status ug_replay_instant(void* ctx, int64_t t, const ug_record* inputs,
+                            uint32_t n_inputs, ug_record* out, uint32_t cap,
+                            uint32_t* n_out);
+
+/* Launches one kernel directly on a HIP stream (NULL = default stream) with
+ * the given buffer pointers, outside any context.  Used by the profiling
+ * stage and for testing each kernel alone.  Asynchronous.  Errors:
+ * UG_EINVAL (bad descriptor or missing buffer), UG_EDEVICE. */
+ug_status ug_kernel_launch(const ug_kernel* k, void* const* buffers,
+                           uint32_t n_buffers, void* hip_stream);
+
+/* Static utilisation of a kernel's launch on `device`: the fraction of the
+ * device's workgroup slots its grid occupies, min(1, WGs / (CUs x resident
+ * WGs per CU)). */
+ug_status ug_kernel_util(const ug_kernel* k, int32_t device, float* util);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UG_H */

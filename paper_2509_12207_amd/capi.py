@@ -1,0 +1,379 @@
+"""ctypes binding of libug (include/ug.h): argument marshalling only.
+
+Every computation happens in the library (gate thread, policy, gfx950
+kernels).  The library is built in-tree by ``paper_2509_12207_amd.build``;
+loading fails loudly if it is missing.
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libug.so")
+
+ABI_VERSION = 1
+
+OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
+POLICY_FIFO, POLICY_URGENCY = 0, 1
+F_BIND, F_DELAY, F_BATCH, F_CALIBRATE = 1, 2, 4, 8
+
+OP_GEMM_F32 = 1
+OP_BIAS_RELU_F32 = 2
+OP_CONV3X3_F32 = 3
+OP_ROWSUM_F32 = 4
+OP_SOFTMAX_F32 = 5
+OP_VOXEL_F32 = 6
+OP_NAMES = {OP_GEMM_F32: "gemm", OP_BIAS_RELU_F32: "bias_relu", OP_CONV3X3_F32: "conv3x3",
+            OP_ROWSUM_F32: "rowsum", OP_SOFTMAX_F32: "softmax", OP_VOXEL_F32: "voxel"}
+OP_IDS = {v: k for k, v in OP_NAMES.items()}
+
+REC_INSTANT, REC_ARRIVE, REC_EVDONE, REC_COMPLETE = 1, 2, 3, 4
+REC_TSTART, REC_BIND, REC_HOLD, REC_EVREC, REC_LAUNCH = 5, 6, 7, 8, 9
+
+EXPORTED = [
+    "ug_config_default", "ug_now_ns", "ug_status_str", "ug_create", "ug_destroy",
+    "ug_last_error", "ug_chain_register", "ug_kernel_set_estimate", "ug_kernel_get_estimate",
+    "ug_profile", "ug_set_threshold", "ug_set_flags", "ug_start", "ug_frame_submit",
+    "ug_poll_complete", "ug_drain", "ug_stop", "ug_get_stats", "ug_trace_read",
+    "ug_calibration_read", "ug_calibration_threshold", "ug_get_metrics", "ug_replay_instant",
+    "ug_kernel_launch", "ug_kernel_util",
+]
+
+
+class Kernel(C.Structure):
+    _fields_ = [("op", C.c_int32), ("in_", C.c_int32 * 3), ("out", C.c_int32 * 4),
+                ("shape", C.c_int64 * 4), ("fparam", C.c_float * 4), ("est_ns", C.c_int64),
+                ("util", C.c_float), ("pad1", C.c_int32)]
+
+
+class Task(C.Structure):
+    _fields_ = [("kernels", C.POINTER(Kernel)), ("n_kernels", C.c_uint32),
+                ("pad0", C.c_uint32), ("cpu_ns", C.c_int64)]
+
+
+class Config(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("policy", C.c_int32), ("flags", C.c_uint32),
+                ("device", C.c_int32), ("delta_eval_ns", C.c_int64),
+                ("delay_poll_ns", C.c_int64), ("util_exempt", C.c_float),
+                ("n_levels", C.c_int32), ("lanes", C.c_int32 * 8), ("th_slack_ns", C.c_int64),
+                ("idle_sleep_ns", C.c_int64), ("queue_capacity", C.c_uint32),
+                ("trace_capacity", C.c_uint32)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("chain", C.c_uint32), ("pad0", C.c_uint32), ("frame", C.c_uint64),
+                ("t_arr_ns", C.c_int64), ("t_done_ns", C.c_int64), ("latency_ns", C.c_int64),
+                ("missed", C.c_int32), ("n_holds", C.c_int32), ("n_batches", C.c_int32),
+                ("pad1", C.c_int32)]
+
+
+class Record(C.Structure):
+    _fields_ = [("type", C.c_int32), ("chain", C.c_int32), ("frame", C.c_int64),
+                ("task", C.c_int32), ("kernel", C.c_int32), ("a", C.c_int32), ("b", C.c_int32),
+                ("t", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("frames_submitted", C.c_uint64), ("frames_completed", C.c_uint64),
+                ("frames_missed", C.c_uint64), ("launches", C.c_uint64), ("holds", C.c_uint64),
+                ("batches", C.c_uint64), ("instants", C.c_uint64), ("collisions", C.c_uint64),
+                ("decide_ns", C.c_int64), ("launch_ns", C.c_int64),
+                ("trace_records", C.c_uint64), ("trace_dropped", C.c_uint64)]
+
+
+class Metrics(C.Structure):
+    _fields_ = [("frames", C.c_uint64), ("missed", C.c_uint64), ("miss_ratio", C.c_double),
+                ("p50_ns", C.c_int64), ("p99_ns", C.c_int64), ("max_ns", C.c_int64),
+                ("mean_ns", C.c_double), ("n_chains", C.c_uint32), ("pad0", C.c_uint32)]
+
+
+RECORD_DTYPE = np.dtype([("type", np.int32), ("chain", np.int32), ("frame", np.int64),
+                         ("task", np.int32), ("kernel", np.int32), ("a", np.int32),
+                         ("b", np.int32), ("t", np.int64)])
+COMPLETION_DTYPE = np.dtype([("chain", np.uint32), ("pad0", np.uint32), ("frame", np.uint64),
+                             ("t_arr_ns", np.int64), ("t_done_ns", np.int64),
+                             ("latency_ns", np.int64), ("missed", np.int32),
+                             ("n_holds", np.int32), ("n_batches", np.int32), ("pad1", np.int32)])
+
+_lib = None
+
+
+class UgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libug error {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "__graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.ug_config_default.argtypes = [C.POINTER(Config)]
+        L.ug_config_default.restype = None
+        L.ug_now_ns.restype = C.c_int64
+        L.ug_status_str.argtypes = [C.c_int32]
+        L.ug_status_str.restype = C.c_char_p
+        L.ug_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+        L.ug_destroy.argtypes = [vp]
+        L.ug_destroy.restype = None
+        L.ug_last_error.argtypes = [vp]
+        L.ug_last_error.restype = C.c_char_p
+        L.ug_chain_register.argtypes = [vp, C.c_int64, C.c_int64, C.POINTER(Task), C.c_uint32,
+                                        C.c_uint32, C.POINTER(C.c_uint32)]
+        L.ug_kernel_set_estimate.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int64, C.c_float]
+        L.ug_kernel_get_estimate.argtypes = [vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_int64),
+                                             C.POINTER(C.c_float)]
+        L.ug_profile.argtypes = [vp, C.c_uint32, C.POINTER(vp), C.c_uint32, C.c_uint32, C.c_uint32]
+        L.ug_set_threshold.argtypes = [vp, C.c_int64]
+        L.ug_set_flags.argtypes = [vp, C.c_int32, C.c_uint32]
+        L.ug_start.argtypes = [vp]
+        L.ug_frame_submit.argtypes = [vp, C.c_uint32, C.c_int64, C.POINTER(vp), C.c_uint32,
+                                      C.POINTER(C.c_uint64)]
+        L.ug_poll_complete.argtypes = [vp, C.POINTER(Completion), C.c_uint32]
+        L.ug_drain.argtypes = [vp, C.c_int64]
+        L.ug_stop.argtypes = [vp]
+        L.ug_get_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.ug_trace_read.argtypes = [vp, C.POINTER(Record), C.c_uint32]
+        L.ug_calibration_read.argtypes = [vp, C.POINTER(C.c_int64), C.c_uint32]
+        L.ug_calibration_threshold.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
+        L.ug_get_metrics.argtypes = [vp, C.POINTER(Metrics)]
+        L.ug_replay_instant.argtypes = [vp, C.c_int64, C.POINTER(Record), C.c_uint32,
+                                        C.POINTER(Record), C.c_uint32, C.POINTER(C.c_uint32)]
+        L.ug_kernel_launch.argtypes = [C.POINTER(Kernel), C.POINTER(vp), C.c_uint32, vp]
+        L.ug_kernel_util.argtypes = [C.POINTER(Kernel), C.c_int32, C.POINTER(C.c_float)]
+        for name in ("ug_create", "ug_chain_register", "ug_kernel_set_estimate",
+                     "ug_kernel_get_estimate", "ug_profile", "ug_set_threshold", "ug_set_flags",
+                     "ug_start", "ug_frame_submit", "ug_poll_complete", "ug_drain", "ug_stop",
+                     "ug_get_stats", "ug_trace_read", "ug_calibration_read",
+                     "ug_calibration_threshold", "ug_get_metrics", "ug_replay_instant",
+                     "ug_kernel_launch", "ug_kernel_util"):
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def status_str(s):
+    return lib().ug_status_str(s).decode()
+
+
+# --------------------------------------------------------------------------
+# descriptors
+# --------------------------------------------------------------------------
+def kernel_struct(k):
+    """Kernel descriptor dict -> ug_kernel.
+
+    dict keys: op (name or id), shape (<= 4 ints), in (<= 3 slots), out (<= 4
+    slots), fparam (<= 4 floats), est_ns (int, default 0), util (float,
+    default -1 = derive from the launch shape).
+    """
+    s = Kernel()
+    op = k["op"]
+    s.op = OP_IDS[op] if isinstance(op, str) else int(op)
+    for i in range(3):
+        s.in_[i] = -1
+    for i in range(4):
+        s.out[i] = -1
+    for i, v in enumerate(k.get("in", ())):
+        s.in_[i] = int(v)
+    for i, v in enumerate(k.get("out", ())):
+        s.out[i] = int(v)
+    for i, v in enumerate(k.get("shape", ())):
+        s.shape[i] = int(v)
+    for i, v in enumerate(k.get("fparam", ())):
+        s.fparam[i] = float(v)
+    s.est_ns = int(k.get("est_ns", 0))
+    s.util = float(k.get("util", -1.0))
+    return s
+
+
+def pointer_array(ptrs):
+    arr = (C.c_void_p * max(1, len(ptrs)))()
+    for i, p in enumerate(ptrs):
+        arr[i] = int(p)
+    return arr
+
+
+def kernel_launch(k, ptrs, stream=None):
+    """Launch one kernel on a HIP stream (an int handle, or None for the default)."""
+    ks = kernel_struct(k)
+    arr = pointer_array(ptrs)
+    st = lib().ug_kernel_launch(C.byref(ks), arr, len(ptrs), C.c_void_p(stream or 0))
+    if st != OK:
+        raise UgError(st, f"ug_kernel_launch({OP_NAMES.get(ks.op, ks.op)})")
+
+
+def kernel_util(k, device=0):
+    u = C.c_float()
+    st = lib().ug_kernel_util(C.byref(kernel_struct(k)), device, C.byref(u))
+    if st != OK:
+        raise UgError(st, "ug_kernel_util")
+    return float(u.value)
+
+
+def now_ns():
+    return int(lib().ug_now_ns())
+
+
+# --------------------------------------------------------------------------
+# context
+# --------------------------------------------------------------------------
+class Gate:
+    """One libug context.
+
+    ``policy``: "urgency" or "fifo".  Keyword arguments override the fields
+    of ug_config (``lanes`` takes a list, one entry per level).
+    """
+
+    def __init__(self, policy="urgency", device=0, **kw):
+        L = lib()
+        cfg = Config()
+        L.ug_config_default(C.byref(cfg))
+        cfg.policy = POLICY_URGENCY if policy == "urgency" else POLICY_FIFO
+        cfg.device = device
+        lanes = kw.pop("lanes", None)
+        if lanes is not None:
+            cfg.n_levels = len(lanes)
+            for i in range(8):
+                cfg.lanes[i] = lanes[i] if i < len(lanes) else 0
+        for key, v in kw.items():
+            setattr(cfg, key, v)
+        self.cfg = cfg
+        h = C.c_void_p()
+        st = L.ug_create(C.byref(cfg), C.byref(h))
+        if st != OK:
+            raise UgError(st, "ug_create")
+        self.h = h
+        self._keep = []
+
+    def _check(self, st, what):
+        if st != OK:
+            msg = lib().ug_last_error(self.h).decode() if self.h else ""
+            raise UgError(st, f"{what}: {msg}")
+
+    def close(self):
+        if self.h:
+            lib().ug_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def register_chain(self, period_ns, deadline_ns, tasks, n_buffers):
+        """tasks: list of {"cpu_ns": int, "kernels": [kernel dicts]}."""
+        arrays = []
+        tarr = (Task * len(tasks))()
+        for j, t in enumerate(tasks):
+            ks = (Kernel * len(t["kernels"]))(*[kernel_struct(k) for k in t["kernels"]])
+            arrays.append(ks)
+            tarr[j].kernels = C.cast(ks, C.POINTER(Kernel))
+            tarr[j].n_kernels = len(t["kernels"])
+            tarr[j].cpu_ns = int(t.get("cpu_ns", 0))
+        cid = C.c_uint32()
+        st = lib().ug_chain_register(self.h, int(period_ns), int(deadline_ns), tarr, len(tasks),
+                                     int(n_buffers), C.byref(cid))
+        self._check(st, "ug_chain_register")
+        return int(cid.value)
+
+    def set_estimate(self, chain, kernel, est_ns, util=-1.0):
+        self._check(lib().ug_kernel_set_estimate(self.h, chain, kernel, int(est_ns), float(util)),
+                    "ug_kernel_set_estimate")
+
+    def get_estimate(self, chain, kernel):
+        e, u = C.c_int64(), C.c_float()
+        self._check(lib().ug_kernel_get_estimate(self.h, chain, kernel, C.byref(e), C.byref(u)),
+                    "ug_kernel_get_estimate")
+        return int(e.value), float(u.value)
+
+    def profile(self, chain, ptrs, warmup=3, reps=10):
+        arr = pointer_array(ptrs)
+        self._check(lib().ug_profile(self.h, chain, arr, len(ptrs), warmup, reps), "ug_profile")
+
+    def set_threshold(self, th_slack_ns):
+        self._check(lib().ug_set_threshold(self.h, int(th_slack_ns)), "ug_set_threshold")
+
+    def set_flags(self, flags):
+        self._check(lib().ug_set_flags(self.h, self.cfg.policy, int(flags)), "ug_set_flags")
+        self.cfg.flags = flags
+
+    def start(self):
+        self._check(lib().ug_start(self.h), "ug_start")
+
+    def stop(self):
+        self._check(lib().ug_stop(self.h), "ug_stop")
+
+    def submit(self, chain, t_arr_ns, ptrs):
+        arr = pointer_array(ptrs)
+        f = C.c_uint64()
+        st = lib().ug_frame_submit(self.h, chain, int(t_arr_ns), arr, len(ptrs), C.byref(f))
+        if st == EAGAIN:
+            return None
+        self._check(st, "ug_frame_submit")
+        return int(f.value)
+
+    def poll(self, cap=4096):
+        buf = (Completion * cap)()
+        n = lib().ug_poll_complete(self.h, buf, cap)
+        if n < 0:
+            self._check(n, "ug_poll_complete")
+        out = np.frombuffer(bytes(buf)[: n * C.sizeof(Completion)], dtype=COMPLETION_DTYPE)
+        return out.copy()
+
+    def drain(self, timeout_s=60.0):
+        self._check(lib().ug_drain(self.h, int(timeout_s * 1e9)), "ug_drain")
+
+    def stats(self):
+        s = Stats()
+        self._check(lib().ug_get_stats(self.h, C.byref(s)), "ug_get_stats")
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def trace(self, cap=1 << 20):
+        chunks = []
+        while True:
+            buf = (Record * cap)()
+            n = lib().ug_trace_read(self.h, buf, cap)
+            if n < 0:
+                self._check(n, "ug_trace_read")
+            chunks.append(np.frombuffer(bytes(buf)[: n * C.sizeof(Record)], dtype=RECORD_DTYPE).copy())
+            if n < cap:
+                break
+        return np.concatenate(chunks) if chunks else np.zeros(0, RECORD_DTYPE)
+
+    def calibration_samples(self, cap=1 << 22):
+        buf = (C.c_int64 * cap)()
+        n = lib().ug_calibration_read(self.h, buf, cap)
+        if n < 0:
+            self._check(n, "ug_calibration_read")
+        return [int(buf[i]) for i in range(n)]
+
+    def calibration_threshold(self, pct=95):
+        th = C.c_int64()
+        self._check(lib().ug_calibration_threshold(self.h, int(pct), C.byref(th)),
+                    "ug_calibration_threshold")
+        return int(th.value)
+
+    def metrics(self):
+        m = Metrics()
+        self._check(lib().ug_get_metrics(self.h, C.byref(m)), "ug_get_metrics")
+        return {f: getattr(m, f) for f, _ in Metrics._fields_ if f != "pad0"}
+
+    def replay_instant(self, t, inputs, cap=1 << 16):
+        """inputs: numpy RECORD_DTYPE array (ARRIVE / EVDONE records)."""
+        n_in = len(inputs)
+        inp = (Record * max(1, n_in))()
+        if n_in:
+            C.memmove(inp, np.ascontiguousarray(inputs, dtype=RECORD_DTYPE).ctypes.data,
+                      n_in * C.sizeof(Record))
+        out = (Record * cap)()
+        n_out = C.c_uint32()
+        self._check(lib().ug_replay_instant(self.h, int(t), inp, n_in, out, cap, C.byref(n_out)),
+                    "ug_replay_instant")
+        return np.frombuffer(bytes(out)[: n_out.value * C.sizeof(Record)], dtype=RECORD_DTYPE).copy()

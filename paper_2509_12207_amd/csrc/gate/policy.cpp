@@ -1,0 +1,349 @@
+// Urgency-ordered launch policy: see policy.hpp for the per-instant order.
+#include "policy.hpp"
+
+#include <algorithm>
+
+namespace ug {
+
+// ---------------------------------------------------------------- Eq. (2)
+bool ul_greater(int64_t s1, int64_t s2) {
+  // 1/0 is +infinity: above every finite level, not above itself.
+  if (s1 == 0) return s2 != 0;
+  if (s2 == 0) return false;
+  // 1/s1 - 1/s2 = (s2 - s1) / (s1 s2): positive iff the numerator and the
+  // product have the same sign.  The numerator is formed in 128 bits.
+  __int128 num = static_cast<__int128>(s2) - static_cast<__int128>(s1);
+  if (num == 0) return false;
+  bool prod_pos = (s1 > 0) == (s2 > 0);
+  return (num > 0) == prod_pos;
+}
+
+bool more_urgent(int64_t s1, const Key& k1, int64_t s2, const Key& k2) {
+  if (ul_greater(s1, s2)) return true;
+  if (ul_greater(s2, s1)) return false;
+  return k1 < k2;
+}
+
+// ---------------------------------------------------------------- chains
+void ChainSpec::finalize() {
+  const size_t n = est.size();
+  gpu_rem.assign(n + 1, 0);
+  for (size_t g = n; g-- > 0;) gpu_rem[g] = gpu_rem[g + 1] + est[g];
+  const size_t m = cpu.size();
+  cpu_rem.assign(m + 1, 0);
+  for (size_t j = m; j-- > 0;) cpu_rem[j] = cpu_rem[j + 1] + cpu[j];
+}
+
+uint32_t Policy::add_chain(ChainSpec&& spec) {
+  spec.finalize();
+  const int32_t c = static_cast<int32_t>(chains_.size());
+  fifo_base_.push_back(fifo_total_);
+  fifo_total_ += static_cast<int32_t>(spec.task_first.size());
+  for (int32_t j = 0; j < static_cast<int32_t>(spec.task_first.size()); ++j) {
+    slot_[{c, j}] = -1;
+    queue_[{c, j}];
+  }
+  chains_.push_back(std::move(spec));
+  return static_cast<uint32_t>(c);
+}
+
+void Policy::finalize() {
+  for (auto& ch : chains_) ch.finalize();
+  lane_load_.clear();
+  for (int32_t lv = 0; lv < static_cast<int32_t>(cfg_.lanes.size()); ++lv)
+    for (int32_t ln = 0; ln < cfg_.lanes[lv]; ++ln) lane_load_[{lv, ln}] = 0;
+}
+
+void Policy::reset() {
+  inst_.clear();
+  for (auto& s : slot_) s.second = -1;
+  for (auto& q : queue_) q.second.clear();
+  finished_.clear();
+  samples_.clear();
+  collisions_ = 0;
+  finalize();
+}
+
+bool Policy::urgent(int64_t slack) const {
+  // UL > TH_urgent with TH = 1/th_slack; th_slack <= 0 is TH = +infinity.
+  if (cfg_.th_slack_ns <= 0) return false;
+  return ul_greater(slack, cfg_.th_slack_ns);
+}
+
+static ug_record rec(int32_t type, int32_t c, int64_t f, int32_t task,
+                     int32_t kernel, int32_t a, int32_t b, int64_t t) {
+  ug_record r;
+  r.type = type;
+  r.chain = c;
+  r.frame = f;
+  r.task = task;
+  r.kernel = kernel;
+  r.a = a;
+  r.b = b;
+  r.t = t;
+  return r;
+}
+
+void Policy::start_task(Instance& in, int32_t j, int64_t t, std::vector<ug_record>& out) {
+  const ChainSpec& ch = chains_[in.c];
+  in.task = j;
+  in.phase = kCpu;
+  in.cpu_ready = t + ch.cpu[j];
+  in.g_next = ch.task_first[j];
+  in.released_hi = ch.task_first[j];
+  in.batch = 0;
+  in.batch_open = false;
+  in.batch_sum = 0;
+  in.batch_first.clear();
+  in.waits.clear();
+  in.bound = false;
+  in.level = in.lane = -1;
+  in.has_wake = false;
+  slot_[{in.c, j}] = in.f;
+  out.push_back(rec(UG_REC_TSTART, in.c, in.f, j, 0, 0, 0, 0));
+}
+
+// ------------------------------------------------------------ one instant
+bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
+                     std::vector<EvDone>& evdones, std::vector<ug_record>& out,
+                     const char** err) {
+  // 1. inputs in canonical order
+  std::sort(arrivals.begin(), arrivals.end(), [](const Arrival& a, const Arrival& b) {
+    return a.c != b.c ? a.c < b.c : a.f < b.f;
+  });
+  for (const Arrival& a : arrivals) {
+    if (a.c < 0 || a.c >= static_cast<int32_t>(chains_.size()) || inst_.count({a.c, a.f})) {
+      *err = "arrival of an unknown chain or a frame seen before";
+      return false;
+    }
+    Instance in;
+    in.c = a.c;
+    in.f = a.f;
+    in.t_arr = a.t_arr;
+    inst_.emplace(Key{a.c, a.f}, std::move(in));
+    queue_[{a.c, 0}].push_back(a.f);
+  }
+  std::sort(evdones.begin(), evdones.end(), [](const EvDone& a, const EvDone& b) {
+    if (a.c != b.c) return a.c < b.c;
+    if (a.f != b.f) return a.f < b.f;
+    if (a.task != b.task) return a.task < b.task;
+    if (a.seq != b.seq) return a.seq < b.seq;
+    return a.kind < b.kind;
+  });
+  std::vector<Key> completed;
+  for (const EvDone& e : evdones) {
+    auto it = inst_.find({e.c, e.f});
+    if (it == inst_.end()) {
+      *err = "event of an unknown frame";
+      return false;
+    }
+    Instance& in = it->second;
+    if (in.task != e.task || in.waits.empty() || !(in.waits.front() == Wait{e.kind, e.seq})) {
+      *err = "event the instance is not waiting for";
+      return false;
+    }
+    in.waits.pop_front();
+    const ChainSpec& ch = chains_[e.c];
+    if (e.kind == 0) {
+      // batch e.seq has started on the device: all earlier batches are done
+      in.i_gpu = in.batch_first[e.seq];
+    } else {
+      in.i_gpu = ch.task_end[e.task];
+      if (in.bound && cfg_.policy == UG_POLICY_URGENCY) lane_load_[{in.level, in.lane}] -= 1;
+      slot_[{e.c, e.task}] = -1;
+      if (e.task + 1 == static_cast<int32_t>(ch.task_first.size())) {
+        in.phase = kDone;
+        completed.push_back({e.c, e.f});
+      } else {
+        in.phase = kWait;
+        queue_[{e.c, e.task + 1}].push_back(e.f);
+      }
+    }
+  }
+  for (const Key& k : completed) {  // already in (chain, frame) order
+    Instance& in = inst_.at(k);
+    out.push_back(rec(UG_REC_COMPLETE, in.c, in.f, 0, 0, 0, 0, t));
+    finished_.push_back({in.c, in.f, in.t_arr, t, in.n_holds, in.n_batches});
+    inst_.erase(k);
+  }
+  // 2. task starts, in (chain, task) order
+  for (int32_t c = 0; c < static_cast<int32_t>(chains_.size()); ++c) {
+    const int32_t nt = static_cast<int32_t>(chains_[c].task_first.size());
+    for (int32_t j = 0; j < nt; ++j) {
+      auto& q = queue_[{c, j}];
+      if (slot_[{c, j}] < 0 && !q.empty()) {
+        int64_t f = q.front();
+        q.pop_front();
+        start_task(inst_.at({c, f}), j, t, out);
+      }
+    }
+  }
+  // 3. finished CPU segments
+  std::vector<Instance*> active;
+  active.reserve(inst_.size());
+  for (auto& kv : inst_) {
+    Instance& in = kv.second;
+    if (in.phase == kCpu && in.cpu_ready <= t) {
+      in.phase = kLaunch;
+      in.i_cpu = in.task + 1;
+    }
+    active.push_back(&in);
+  }
+  // 4. urgency snapshot: slack = t_arr + D - sum E^gpu - sum E^cpu - t
+  std::map<Key, int64_t> slack;
+  for (Instance* in : active) {
+    const ChainSpec& ch = chains_[in->c];
+    slack[{in->c, in->f}] =
+        in->t_arr + ch.deadline_ns - ch.gpu_rem[in->i_gpu] - ch.cpu_rem[in->i_cpu] - t;
+  }
+  // 5. highest urgency among active kernels, for TH_urgent calibration
+  if (cfg_.calibrate) {
+    const Instance* top = nullptr;
+    for (Instance* in : active) {
+      if (!in->in_flight()) continue;
+      if (!top || more_urgent(slack[{in->c, in->f}], {in->c, in->f},
+                              slack[{top->c, top->f}], {top->c, top->f}))
+        top = in;
+    }
+    if (top) samples_.push_back(slack[{top->c, top->f}]);
+  }
+  // 6. launch requests, most urgent first
+  std::vector<Instance*> ready;
+  for (Instance* in : active) {
+    if (in->phase != kLaunch) continue;
+    if (in->g_next >= chains_[in->c].task_end[in->task]) continue;
+    if (!in->waits.empty()) continue;
+    if (in->has_wake && in->wake > t) continue;
+    ready.push_back(in);
+  }
+  if (cfg_.policy == UG_POLICY_URGENCY) {
+    std::sort(ready.begin(), ready.end(), [&](const Instance* a, const Instance* b) {
+      return more_urgent(slack[{a->c, a->f}], {a->c, a->f}, slack[{b->c, b->f}], {b->c, b->f});
+    });
+  }
+  for (Instance* in : ready) release(*in, t, active, slack, out);
+  return true;
+}
+
+bool Policy::blocked(const Instance& me, const std::vector<Instance*>& active,
+                     const std::map<Key, int64_t>& slack) const {
+  // Delayed launching: another chain has an active kernel that is truly
+  // urgent and more urgent than this one.
+  const int64_t sm = slack.at({me.c, me.f});
+  for (const Instance* o : active) {
+    if (o->c == me.c || !o->in_flight()) continue;
+    const int64_t so = slack.at({o->c, o->f});
+    if (urgent(so) && more_urgent(so, {o->c, o->f}, sm, {me.c, me.f})) return true;
+  }
+  return false;
+}
+
+void Policy::bind(Instance& me, const std::vector<Instance*>& active,
+                  const std::map<Key, int64_t>& slack, std::vector<ug_record>& out) {
+  if (cfg_.policy != UG_POLICY_URGENCY) {
+    me.level = 0;
+    me.lane = fifo_lane(me.c, me.task);
+  } else {
+    const int32_t n_levels = static_cast<int32_t>(cfg_.lanes.size());
+    const int64_t sm = slack.at({me.c, me.f});
+    int32_t level;
+    if (!cfg_.bind) {
+      level = std::min<int32_t>(1, n_levels - 1);
+    } else if (n_levels <= 1) {
+      level = 0;
+    } else if (urgent(sm)) {
+      level = 0;  // reserved for truly urgent tasks
+    } else {
+      // rank among active, not truly urgent instances (and this one)
+      int32_t rank = 1, n = 1;
+      for (const Instance* o : active) {
+        if (o == &me || !o->in_flight()) continue;
+        const int64_t so = slack.at({o->c, o->f});
+        if (urgent(so)) continue;
+        ++n;
+        if (more_urgent(so, {o->c, o->f}, sm, {me.c, me.f})) ++rank;
+      }
+      level = 1 + static_cast<int32_t>((static_cast<int64_t>(rank - 1) * (n_levels - 1)) / n);
+    }
+    int32_t best = 0;
+    for (int32_t ln = 1; ln < cfg_.lanes[level]; ++ln)
+      if (lane_load_[{level, ln}] < lane_load_[{level, best}]) best = ln;
+    lane_load_[{level, best}] += 1;
+    me.level = level;
+    me.lane = best;
+  }
+  me.bound = true;
+  out.push_back(rec(UG_REC_BIND, me.c, me.f, me.task, 0, me.level, me.lane, 0));
+}
+
+void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& active,
+                     const std::map<Key, int64_t>& slack, std::vector<ug_record>& out) {
+  const ChainSpec& ch = chains_[me.c];
+  const int32_t end = ch.task_end[me.task];
+  const bool gated = cfg_.policy == UG_POLICY_URGENCY;
+  const bool batching = gated && cfg_.batch;
+  while (me.g_next < end && me.waits.empty()) {
+    const int32_t g = me.g_next;
+    if (gated && cfg_.delay && ch.util[g] >= cfg_.util_exempt && blocked(me, active, slack)) {
+      out.push_back(rec(UG_REC_HOLD, me.c, me.f, me.task, g, 0, 0, 0));
+      me.n_holds += 1;
+      if (cfg_.delay_poll_ns > 0) {
+        me.has_wake = true;
+        me.wake = t + cfg_.delay_poll_ns;
+      } else {
+        me.has_wake = false;
+      }
+      return;
+    }
+    me.has_wake = false;
+    if (!me.bound) bind(me, active, slack, out);
+    if (!me.batch_open) {
+      me.batch_open = true;
+      me.batch_first.push_back(g);
+      me.n_batches += 1;
+      out.push_back(rec(UG_REC_EVREC, me.c, me.f, me.task, 0, 0, me.batch, 0));
+    }
+    if (gated && urgent(slack.at({me.c, me.f}))) {
+      for (const Instance* o : active)
+        if (o->c != me.c && o->in_flight()) {
+          ++collisions_;
+          break;
+        }
+    }
+    out.push_back(rec(UG_REC_LAUNCH, me.c, me.f, me.task, g, me.level, me.lane, 0));
+    me.released_hi = g + 1;
+    me.g_next = g + 1;
+    me.batch_sum += ch.est[g];
+    const bool last = g == end - 1;
+    if (last || (batching && me.batch_sum > cfg_.delta_eval_ns)) {
+      me.waits.push_back({0, me.batch});
+      if (last) {
+        out.push_back(rec(UG_REC_EVREC, me.c, me.f, me.task, 0, 1, me.batch + 1, 0));
+        me.waits.push_back({1, me.batch + 1});
+      }
+      me.batch += 1;
+      me.batch_open = false;
+      me.batch_sum = 0;
+    }
+  }
+}
+
+bool Policy::next_timer(int64_t* t) const {
+  bool any = false;
+  int64_t best = 0;
+  for (const auto& kv : inst_) {
+    const Instance& in = kv.second;
+    if (in.phase == kCpu && (!any || in.cpu_ready < best)) {
+      best = in.cpu_ready;
+      any = true;
+    }
+    if (in.phase == kLaunch && in.has_wake && (!any || in.wake < best)) {
+      best = in.wake;
+      any = true;
+    }
+  }
+  if (any) *t = best;
+  return any;
+}
+
+}  // namespace ug

@@ -1,0 +1,161 @@
+// Urgency-ordered launch policy (UrgenGo, arXiv 2509.12207, Sec. 4.2-4.4),
+// as a pure state machine over decision instants.  No clock, no HIP: the
+// gate thread (runtime.cpp) feeds it the inputs it observed at an instant and
+// executes the decisions it returns; ug_replay_instant feeds it a recorded
+// instant offline.
+//
+// Per instant t:
+//   1. apply inputs in canonical order: arrivals by (chain, frame), then
+//      observed events by (chain, frame, task, seq).  A batch-start event
+//      moves the chain instance's executing-kernel index to the first kernel
+//      of that batch (every earlier batch is done); a task-end event finishes
+//      the task, frees its per-chain task slot and queues the frame for its
+//      next task (or completes the frame).
+//   2. start tasks: for each (chain, task) whose slot is free, the oldest
+//      waiting frame starts the task's CPU segment.
+//   3. CPU segments whose time has elapsed finish; the task may launch.
+//   4. one urgency snapshot (Eq. 2) for every active instance.
+//   5. launch requests are served from the most to the least urgent; each
+//      releases kernels until its batch closes, its task ends, or delayed
+//      launching holds it.
+#pragma once
+
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <utility>
+#include <vector>
+
+#include "ug.h"
+
+namespace ug {
+
+struct PolicyConfig {
+  int policy = UG_POLICY_URGENCY;
+  bool bind = true, delay = true, batch = true, calibrate = false;
+  int64_t delta_eval_ns = 500000;
+  int64_t delay_poll_ns = 1000000;
+  float util_exempt = 0.1f;
+  int64_t th_slack_ns = 0;
+  std::vector<int32_t> lanes{1, 2, 1};
+};
+
+struct ChainSpec {
+  int64_t period_ns = 0, deadline_ns = 0;
+  uint32_t n_buffers = 0;
+  std::vector<ug_kernel> kernels;     // all tasks, in order
+  std::vector<int64_t> est;           // E_k
+  std::vector<float> util;            // U_k
+  std::vector<int32_t> task_first, task_end;
+  std::vector<int64_t> cpu;           // CPU segment of each task
+  std::vector<int64_t> gpu_rem;       // sum_{k >= g} E_k, size N + 1
+  std::vector<int64_t> cpu_rem;       // sum_{j' >= j} E^cpu_j', size M + 1
+  void finalize();
+};
+
+struct Wait {
+  int32_t kind;  // 0 batch start, 1 task end
+  int32_t seq;
+  bool operator==(const Wait& o) const { return kind == o.kind && seq == o.seq; }
+};
+
+enum Phase { kWait = 0, kCpu = 1, kLaunch = 2, kDone = 3 };
+
+struct Instance {
+  int32_t c = 0;
+  int64_t f = 0;
+  int64_t t_arr = 0;
+  int phase = kWait;
+  int32_t task = -1;
+  int64_t cpu_ready = 0;
+  int32_t i_gpu = 0, i_cpu = 0;        // executing-kernel / CPU-segment index
+  int32_t g_next = 0, released_hi = 0;
+  int32_t batch = 0;
+  bool batch_open = false;
+  int64_t batch_sum = 0;
+  std::vector<int32_t> batch_first;
+  std::deque<Wait> waits;
+  bool bound = false;
+  int32_t level = -1, lane = -1;
+  bool has_wake = false;
+  int64_t wake = 0;
+  int32_t n_holds = 0, n_batches = 0;
+  bool in_flight() const { return released_hi > i_gpu; }
+};
+
+struct Arrival {
+  int32_t c;
+  int64_t f;
+  int64_t t_arr;
+};
+struct EvDone {
+  int32_t c;
+  int64_t f;
+  int32_t task, kind, seq;
+};
+struct Finished {
+  int32_t c;
+  int64_t f, t_arr, t_done;
+  int32_t n_holds, n_batches;
+};
+
+using Key = std::pair<int32_t, int64_t>;  // (chain, frame)
+
+class Policy {
+ public:
+  explicit Policy(const PolicyConfig& cfg) : cfg_(cfg) {}
+
+  uint32_t add_chain(ChainSpec&& spec);
+  void finalize();                       // recompute remaining-work sums
+  void reset();                          // drop every instance and sample
+  const PolicyConfig& config() const { return cfg_; }
+  PolicyConfig& mutable_config() { return cfg_; }
+  std::vector<ChainSpec>& chains() { return chains_; }
+  const std::vector<ChainSpec>& chains() const { return chains_; }
+
+  // Process one instant; decisions are appended to `out`.  Returns false
+  // (and leaves `err`) if an input does not match the state.
+  bool instant(int64_t t, std::vector<Arrival>& arrivals,
+               std::vector<EvDone>& evdones, std::vector<ug_record>& out,
+               const char** err);
+
+  // Earliest pending timer (CPU segment end, sleep-loop wake); false if none.
+  bool next_timer(int64_t* t) const;
+
+  const std::map<Key, Instance>& instances() const { return inst_; }
+  std::vector<Finished>& finished() { return finished_; }
+  std::vector<int64_t>& samples() { return samples_; }
+  uint64_t collisions() const { return collisions_; }
+  int32_t fifo_lane(int32_t c, int32_t task) const { return fifo_base_[c] + task; }
+  int32_t fifo_lanes() const { return fifo_total_; }
+
+ private:
+  bool urgent(int64_t slack) const;
+  bool blocked(const Instance& me, const std::vector<Instance*>& active,
+               const std::map<Key, int64_t>& slack) const;
+  void bind(Instance& me, const std::vector<Instance*>& active,
+            const std::map<Key, int64_t>& slack, std::vector<ug_record>& out);
+  void release(Instance& me, int64_t t, const std::vector<Instance*>& active,
+               const std::map<Key, int64_t>& slack, std::vector<ug_record>& out);
+  void start_task(Instance& in, int32_t j, int64_t t, std::vector<ug_record>& out);
+
+  PolicyConfig cfg_;
+  std::vector<ChainSpec> chains_;
+  std::vector<int32_t> fifo_base_;
+  int32_t fifo_total_ = 0;
+  std::map<Key, Instance> inst_;
+  std::map<std::pair<int32_t, int32_t>, int64_t> slot_;      // -1 = free
+  std::map<std::pair<int32_t, int32_t>, std::deque<int64_t>> queue_;
+  std::map<std::pair<int32_t, int32_t>, int32_t> lane_load_;
+  std::vector<Finished> finished_;
+  std::vector<int64_t> samples_;
+  uint64_t collisions_ = 0;
+};
+
+// Exact comparison of urgency levels UL = 1/slack (Eq. 2): true iff
+// 1/s1 > 1/s2, with 1/0 = +infinity.
+bool ul_greater(int64_t s1, int64_t s2);
+// Strict total order: higher UL first, then lower (chain, frame).
+bool more_urgent(int64_t s1, const Key& k1, int64_t s2, const Key& k2);
+
+}  // namespace ug

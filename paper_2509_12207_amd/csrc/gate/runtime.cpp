@@ -1,0 +1,859 @@
+// libug runtime: context, gate thread, streams, events and the C-ABI.
+//
+// One gate thread per context owns the policy (policy.hpp), every stream and
+// every event.  Each loop iteration it
+//   1. polls, for every active chain instance, the events at the head of its
+//      wait list (hipEventQuery; completed prefix only),
+//   2. reads the clock (t), takes the frames whose arrival time has come,
+//   3. if anything was observed or a timer expired, runs one decision instant
+//      at t and executes the decisions: event records and kernel launches on
+//      the bound stream, completions to the caller's queue,
+//   4. logs the instant (inputs and decisions) for offline replay.
+// Callers talk to the gate only through two mutex-protected queues
+// (submissions in, completions out).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <ctime>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "../kernels/ops.hpp"
+#include "policy.hpp"
+#include "ug.h"
+
+namespace {
+
+int64_t mono_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return static_cast<int64_t>(ts.tv_sec) * 1000000000LL + ts.tv_nsec;
+}
+
+struct Frame {
+  uint32_t chain = 0;
+  int64_t f = 0;
+  int64_t t_arr = 0;
+  std::vector<void*> buffers;
+};
+
+using EvKey = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t>;  // c, f, task, kind, seq
+
+struct Ctx {
+  ug_config cfg{};
+  ug::Policy policy{ug::PolicyConfig{}};
+  bool has_device = false;
+  bool started = false;
+  bool finalized = false;
+
+  std::vector<std::vector<hipStream_t>> level_streams;  // [level][lane]
+  std::vector<hipStream_t> fifo_streams;                // one per task of every chain
+  std::vector<hipEvent_t> event_pool;
+  std::vector<hipEvent_t> all_events;
+  std::map<EvKey, hipEvent_t> live_events;
+  std::map<ug::Key, hipStream_t> bound;
+  std::map<ug::Key, Frame> frames;                      // arrived, not completed
+  std::vector<Frame> pending;                           // submitted, not arrived
+
+  std::mutex mu;  // inbox, outbox, counters, next_frame
+  std::condition_variable cv_done;
+  std::deque<Frame> inbox;
+  std::deque<ug_completion> outbox;
+  std::vector<int64_t> next_frame;
+  uint64_t outstanding = 0;
+
+  // completed-frame latencies and per-chain counts since start (under mu)
+  std::vector<int64_t> latencies;
+  std::vector<uint64_t> chain_done, chain_missed;
+
+  std::mutex trace_mu;
+  std::vector<ug_record> trace;
+  uint64_t trace_dropped = 0;
+
+  std::thread thr;
+  std::atomic<bool> stop{false};
+  std::atomic<int> device_error{0};
+  std::string last_error;
+  std::string device_msg;
+
+  // statistics (written by the gate thread; read racily by ug_get_stats
+  // through atomics)
+  std::atomic<uint64_t> st_submitted{0}, st_completed{0}, st_missed{0}, st_launches{0},
+      st_holds{0}, st_batches{0}, st_instants{0};
+  std::atomic<int64_t> st_decide_ns{0}, st_launch_ns{0};
+};
+
+ug_status fail(Ctx* c, ug_status s, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+ug_status hip_fail(Ctx* c, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (c) {
+    c->device_error.store(1);
+    c->device_msg = m;
+    c->last_error = m;
+  }
+  return UG_EDEVICE;
+}
+
+bool sticky(Ctx* c) { return c->device_error.load() != 0; }
+
+ug::PolicyConfig policy_config(const ug_config& cfg) {
+  ug::PolicyConfig p;
+  p.policy = cfg.policy;
+  p.bind = (cfg.flags & UG_F_BIND) != 0;
+  p.delay = (cfg.flags & UG_F_DELAY) != 0;
+  p.batch = (cfg.flags & UG_F_BATCH) != 0;
+  p.calibrate = (cfg.flags & UG_F_CALIBRATE) != 0;
+  p.delta_eval_ns = cfg.delta_eval_ns;
+  p.delay_poll_ns = cfg.delay_poll_ns;
+  p.util_exempt = cfg.util_exempt;
+  p.th_slack_ns = cfg.th_slack_ns;
+  p.lanes.assign(cfg.lanes, cfg.lanes + cfg.n_levels);
+  return p;
+}
+
+void push_trace(Ctx* c, const ug_record& r) {
+  if (c->cfg.trace_capacity == 0) return;
+  if (c->trace.size() >= c->cfg.trace_capacity) {
+    ++c->trace_dropped;
+    return;
+  }
+  c->trace.push_back(r);
+}
+
+ug_record make_rec(int32_t type, int32_t chain, int64_t frame, int32_t task, int32_t kernel,
+                   int32_t a, int32_t b, int64_t t) {
+  ug_record r;
+  r.type = type;
+  r.chain = chain;
+  r.frame = frame;
+  r.task = task;
+  r.kernel = kernel;
+  r.a = a;
+  r.b = b;
+  r.t = t;
+  return r;
+}
+
+hipEvent_t take_event(Ctx* c) {
+  if (c->event_pool.empty()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    c->all_events.push_back(e);
+    return e;
+  }
+  hipEvent_t e = c->event_pool.back();
+  c->event_pool.pop_back();
+  return e;
+}
+
+// Executes the decisions of one instant.  Returns false on a device error.
+bool execute(Ctx* c, const std::vector<ug_record>& dec) {
+  for (const ug_record& d : dec) {
+    const ug::Key key{d.chain, d.frame};
+    switch (d.type) {
+      case UG_REC_BIND: {
+        hipStream_t s = c->cfg.policy == UG_POLICY_FIFO ? c->fifo_streams[d.b]
+                                                        : c->level_streams[d.a][d.b];
+        c->bound[key] = s;
+        break;
+      }
+      case UG_REC_EVREC: {
+        hipEvent_t e = take_event(c);
+        if (!e) {
+          hip_fail(c, hipErrorOutOfMemory, "hipEventCreateWithFlags");
+          return false;
+        }
+        const int64_t t0 = mono_ns();
+        hipError_t err = hipEventRecord(e, c->bound.at(key));
+        c->st_launch_ns += mono_ns() - t0;
+        if (err != hipSuccess) {
+          hip_fail(c, err, "hipEventRecord");
+          return false;
+        }
+        c->live_events[EvKey{d.chain, d.frame, d.task, d.a, d.b}] = e;
+        if (d.a == 0) c->st_batches++;
+        break;
+      }
+      case UG_REC_LAUNCH: {
+        const ug::ChainSpec& ch = c->policy.chains()[d.chain];
+        const Frame& fr = c->frames.at(key);
+        const int64_t t0 = mono_ns();
+        hipError_t err = ug::launch_kernel(ch.kernels[d.kernel], fr.buffers.data(), c->bound.at(key));
+        c->st_launch_ns += mono_ns() - t0;
+        if (err != hipSuccess) {
+          hip_fail(c, err, "kernel launch");
+          return false;
+        }
+        c->st_launches++;
+        break;
+      }
+      case UG_REC_HOLD:
+        c->st_holds++;
+        break;
+      default:
+        break;
+    }
+  }
+  return true;
+}
+
+void deliver_completions(Ctx* c) {
+  auto& fin = c->policy.finished();
+  if (fin.empty()) return;
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (const ug::Finished& f : fin) {
+    const ug::ChainSpec& ch = c->policy.chains()[f.c];
+    ug_completion out{};
+    out.chain = static_cast<uint32_t>(f.c);
+    out.frame = static_cast<uint64_t>(f.f);
+    out.t_arr_ns = f.t_arr;
+    out.t_done_ns = f.t_done;
+    out.latency_ns = f.t_done - f.t_arr;
+    out.missed = out.latency_ns > ch.deadline_ns ? 1 : 0;
+    out.n_holds = f.n_holds;
+    out.n_batches = f.n_batches;
+    c->outbox.push_back(out);
+    c->latencies.push_back(out.latency_ns);
+    c->chain_done[f.c] += 1;
+    c->chain_missed[f.c] += out.missed;
+    c->frames.erase({f.c, f.f});
+    c->bound.erase({f.c, f.f});
+    c->st_completed++;
+    if (out.missed) c->st_missed++;
+    if (c->outstanding > 0) --c->outstanding;
+  }
+  fin.clear();
+  c->cv_done.notify_all();
+}
+
+void gate_main(Ctx* c) {
+  (void)hipSetDevice(c->cfg.device);
+  std::vector<ug::Arrival> arr;
+  std::vector<ug::EvDone> evs;
+  std::vector<ug_record> dec;
+  std::vector<Frame> incoming;
+  while (!c->stop.load(std::memory_order_relaxed)) {
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      while (!c->inbox.empty()) {
+        incoming.push_back(std::move(c->inbox.front()));
+        c->inbox.pop_front();
+      }
+    }
+    for (Frame& f : incoming) c->pending.push_back(std::move(f));
+    incoming.clear();
+
+    // 1. observe events: completed prefix of each instance's wait list
+    evs.clear();
+    bool dev_err = false;
+    for (const auto& kv : c->policy.instances()) {
+      const ug::Instance& in = kv.second;
+      for (const ug::Wait& w : in.waits) {
+        auto it = c->live_events.find(EvKey{in.c, in.f, in.task, w.kind, w.seq});
+        if (it == c->live_events.end()) break;
+        hipError_t q = hipEventQuery(it->second);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) {
+          hip_fail(c, q, "hipEventQuery");
+          dev_err = true;
+          break;
+        }
+        evs.push_back({in.c, in.f, in.task, w.kind, w.seq});
+      }
+      if (dev_err) break;
+    }
+    if (dev_err) break;
+
+    // 2. clock, arrivals, timers
+    const int64_t now = mono_ns();
+    arr.clear();
+    for (size_t i = 0; i < c->pending.size();) {
+      if (c->pending[i].t_arr <= now) {
+        Frame& f = c->pending[i];
+        arr.push_back({static_cast<int32_t>(f.chain), f.f, f.t_arr});
+        c->frames[{static_cast<int32_t>(f.chain), f.f}] = std::move(f);
+        if (i + 1 != c->pending.size()) c->pending[i] = std::move(c->pending.back());
+        c->pending.pop_back();
+      } else {
+        ++i;
+      }
+    }
+    int64_t tt = 0;
+    const bool timer = c->policy.next_timer(&tt) && tt <= now;
+    if (arr.empty() && evs.empty() && !timer) {
+      if (c->cfg.idle_sleep_ns > 0)
+        std::this_thread::sleep_for(std::chrono::nanoseconds(c->cfg.idle_sleep_ns));
+      else
+        std::this_thread::yield();
+      continue;
+    }
+
+    // 3. decide
+    dec.clear();
+    const char* err = nullptr;
+    const int64_t t0 = mono_ns();
+    const bool ok = c->policy.instant(now, arr, evs, dec, &err);
+    c->st_decide_ns += mono_ns() - t0;
+    c->st_instants++;
+    if (!ok) {
+      c->last_error = err ? err : "policy error";
+      c->device_error.store(1);
+      c->device_msg = c->last_error;
+      break;
+    }
+    {
+      std::lock_guard<std::mutex> lk(c->trace_mu);
+      push_trace(c, make_rec(UG_REC_INSTANT, 0, 0, 0, 0, (int32_t)arr.size(), (int32_t)evs.size(), now));
+      for (const auto& a : arr) push_trace(c, make_rec(UG_REC_ARRIVE, a.c, a.f, 0, 0, 0, 0, a.t_arr));
+      for (const auto& e : evs)
+        push_trace(c, make_rec(UG_REC_EVDONE, e.c, e.f, e.task, 0, e.kind, e.seq, 0));
+      for (const auto& d : dec) push_trace(c, d);
+    }
+    for (const auto& e : evs) {
+      auto it = c->live_events.find(EvKey{e.c, e.f, e.task, e.kind, e.seq});
+      c->event_pool.push_back(it->second);
+      c->live_events.erase(it);
+    }
+    if (!execute(c, dec)) break;
+    deliver_completions(c);
+  }
+  c->cv_done.notify_all();
+}
+
+void stop_thread(Ctx* c) {
+  if (c->thr.joinable()) {
+    c->stop.store(true);
+    c->thr.join();
+  }
+  c->stop.store(false);
+}
+
+}  // namespace
+
+// ========================================================================
+extern "C" {
+
+void ug_config_default(ug_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->abi_version = UG_ABI_VERSION;
+  cfg->policy = UG_POLICY_URGENCY;
+  cfg->flags = UG_F_BIND | UG_F_DELAY | UG_F_BATCH;
+  cfg->device = 0;
+  cfg->delta_eval_ns = 500000;
+  cfg->delay_poll_ns = 1000000;
+  cfg->util_exempt = 0.1f;
+  cfg->n_levels = 3;
+  cfg->lanes[0] = 1;
+  cfg->lanes[1] = 2;
+  cfg->lanes[2] = 1;
+  cfg->th_slack_ns = 0;
+  cfg->idle_sleep_ns = 0;
+  cfg->queue_capacity = 4096;
+  cfg->trace_capacity = 0;
+}
+
+int64_t ug_now_ns(void) { return mono_ns(); }
+
+const char* ug_status_str(ug_status s) {
+  switch (s) {
+    case UG_OK: return "ok";
+    case UG_EINVAL: return "invalid argument";
+    case UG_ENOMEM: return "out of memory";
+    case UG_EDEVICE: return "device error";
+    case UG_EAGAIN: return "queue full";
+    case UG_ETIMEDOUT: return "timed out";
+    case UG_ESTATE: return "invalid state";
+    case UG_ENODEV: return "no device";
+    default: return "unknown status";
+  }
+}
+
+ug_status ug_create(const ug_config* cfg, void** out) {
+  if (!cfg || !out) return UG_EINVAL;
+  *out = nullptr;
+  if (cfg->abi_version != UG_ABI_VERSION) return UG_EINVAL;
+  if (cfg->policy != UG_POLICY_FIFO && cfg->policy != UG_POLICY_URGENCY) return UG_EINVAL;
+  if (cfg->n_levels < 1 || cfg->n_levels > 8) return UG_EINVAL;
+  for (int i = 0; i < cfg->n_levels; ++i)
+    if (cfg->lanes[i] < 1 || cfg->lanes[i] > 64) return UG_EINVAL;
+  if (cfg->delta_eval_ns < 0 || cfg->delay_poll_ns < 0 || cfg->queue_capacity == 0)
+    return UG_EINVAL;
+  std::unique_ptr<Ctx> c(new (std::nothrow) Ctx());
+  if (!c) return UG_ENOMEM;
+  c->cfg = *cfg;
+  c->policy = ug::Policy(policy_config(*cfg));
+  c->has_device = cfg->device >= 0;
+  if (c->has_device) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || cfg->device >= n) {
+      return e != hipSuccess ? hip_fail(nullptr, e, "hipGetDeviceCount") : UG_EINVAL;
+    }
+    if ((e = hipSetDevice(cfg->device)) != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+    if (cfg->policy == UG_POLICY_URGENCY) {
+      c->level_streams.resize(cfg->n_levels);
+      for (int lv = 0; lv < cfg->n_levels; ++lv)
+        for (int ln = 0; ln < cfg->lanes[lv]; ++ln) {
+          hipStream_t s = nullptr;
+          if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(nullptr, e, "hipStreamCreateWithFlags");
+          c->level_streams[lv].push_back(s);
+        }
+    }
+    for (int i = 0; i < 1024; ++i) {
+      hipEvent_t ev = nullptr;
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(nullptr, e, "hipEventCreateWithFlags");
+      c->event_pool.push_back(ev);
+      c->all_events.push_back(ev);
+    }
+  }
+  c->trace.reserve(std::min<uint32_t>(cfg->trace_capacity, 1u << 22));
+  *out = c.release();
+  return UG_OK;
+}
+
+void ug_destroy(void* ctx) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return;
+  stop_thread(c);
+  if (c->has_device) {
+    (void)hipSetDevice(c->cfg.device);
+    for (auto& lv : c->level_streams)
+      for (hipStream_t s : lv) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+      }
+    for (hipStream_t s : c->fifo_streams) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+    for (hipEvent_t e : c->all_events) (void)hipEventDestroy(e);
+  }
+  delete c;
+}
+
+const char* ug_last_error(void* ctx) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  return c ? c->last_error.c_str() : "null context";
+}
+
+ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
+                            const ug_task* tasks, uint32_t n_tasks, uint32_t n_buffers,
+                            uint32_t* chain_id) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (sticky(c)) return UG_EDEVICE;
+  if (c->started || c->finalized) return fail(c, UG_ESTATE, "chains are registered before start");
+  if (!tasks || n_tasks == 0 || deadline_ns <= 0 || period_ns < 0)
+    return fail(c, UG_EINVAL, "chain needs tasks and a positive deadline");
+  ug::ChainSpec spec;
+  spec.period_ns = period_ns;
+  spec.deadline_ns = deadline_ns;
+  spec.n_buffers = n_buffers;
+    for (uint32_t j = 0; j < n_tasks; ++j) {
+    const ug_task& t = tasks[j];
+    if (!t.kernels || t.n_kernels == 0 || t.cpu_ns < 0)
+      return fail(c, UG_EINVAL, "every task needs at least one kernel and cpu_ns >= 0");
+    spec.task_first.push_back(static_cast<int32_t>(spec.kernels.size()));
+    for (uint32_t k = 0; k < t.n_kernels; ++k) {
+      const ug_kernel& kd = t.kernels[k];
+      if (const char* why = ug::validate_kernel(kd, n_buffers)) return fail(c, UG_EINVAL, why);
+      if (kd.est_ns < 0) return fail(c, UG_EINVAL, "est_ns must be >= 0");
+      float u = kd.util;
+      if (u < 0.f) {
+        if (c->has_device) {
+          if (ug_kernel_util(&kd, c->cfg.device, &u) != UG_OK) u = 1.0f;
+        } else {
+          u = 1.0f;
+        }
+      }
+      spec.kernels.push_back(kd);
+      spec.est.push_back(kd.est_ns);
+      spec.util.push_back(u);
+    }
+    spec.task_end.push_back(static_cast<int32_t>(spec.kernels.size()));
+    spec.cpu.push_back(t.cpu_ns);
+  }
+  const uint32_t id = c->policy.add_chain(std::move(spec));
+  c->next_frame.push_back(0);
+  if (chain_id) *chain_id = id;
+  return UG_OK;
+}
+
+ug_status ug_kernel_set_estimate(void* ctx, uint32_t chain, uint32_t kernel, int64_t est_ns,
+                                 float util) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (c->started) return fail(c, UG_ESTATE, "estimates are set before start");
+  auto& chs = c->policy.chains();
+  if (chain >= chs.size() || kernel >= chs[chain].est.size() || est_ns < 0)
+    return fail(c, UG_EINVAL, "no such kernel");
+  chs[chain].est[kernel] = est_ns;
+  if (util >= 0.f) chs[chain].util[kernel] = util;
+  chs[chain].finalize();
+  return UG_OK;
+}
+
+ug_status ug_kernel_get_estimate(void* ctx, uint32_t chain, uint32_t kernel, int64_t* est_ns,
+                                 float* util) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  const auto& chs = c->policy.chains();
+  if (chain >= chs.size() || kernel >= chs[chain].est.size())
+    return fail(c, UG_EINVAL, "no such kernel");
+  if (est_ns) *est_ns = chs[chain].est[kernel];
+  if (util) *util = chs[chain].util[kernel];
+  return UG_OK;
+}
+
+ug_status ug_profile(void* ctx, uint32_t chain, void* const* buffers, uint32_t n_buffers,
+                     uint32_t warmup, uint32_t reps) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (sticky(c)) return UG_EDEVICE;
+  if (!c->has_device) return fail(c, UG_ENODEV, "profiling needs a device");
+  if (c->started) return fail(c, UG_ESTATE, "profile before start");
+  auto& chs = c->policy.chains();
+  if (chain >= chs.size() || !buffers || n_buffers != chs[chain].n_buffers || reps == 0)
+    return fail(c, UG_EINVAL, "profile: bad chain, buffers or reps");
+  for (uint32_t i = 0; i < n_buffers; ++i)
+    if (!buffers[i]) return fail(c, UG_EINVAL, "profile: null buffer");
+  (void)hipSetDevice(c->cfg.device);
+  hipStream_t s = nullptr;
+  hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+    return hip_fail(c, e, "hipStreamCreateWithFlags");
+  std::vector<hipEvent_t> ev(2 * reps);
+  for (auto& x : ev) (void)hipEventCreate(&x);
+  std::map<std::vector<int64_t>, int64_t> measured;
+  ug::ChainSpec& ch = chs[chain];
+  ug_status st = UG_OK;
+  for (size_t k = 0; k < ch.kernels.size() && st == UG_OK; ++k) {
+    const ug_kernel& kd = ch.kernels[k];
+    std::vector<int64_t> key{kd.op, kd.shape[0], kd.shape[1], kd.shape[2], kd.shape[3]};
+    auto it = measured.find(key);
+    if (it != measured.end()) {
+      ch.est[k] = it->second;
+      continue;
+    }
+    for (uint32_t w = 0; w < warmup; ++w)
+      if ((e = ug::launch_kernel(kd, buffers, s)) != hipSuccess) st = hip_fail(c, e, "profile launch");
+    std::vector<float> ms(reps);
+    for (uint32_t r = 0; r < reps && st == UG_OK; ++r) {
+      (void)hipEventRecord(ev[2 * r], s);
+      if ((e = ug::launch_kernel(kd, buffers, s)) != hipSuccess) st = hip_fail(c, e, "profile launch");
+      (void)hipEventRecord(ev[2 * r + 1], s);
+    }
+    if (st != UG_OK) break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+      st = hip_fail(c, e, "hipStreamSynchronize");
+      break;
+    }
+    for (uint32_t r = 0; r < reps; ++r) (void)hipEventElapsedTime(&ms[r], ev[2 * r], ev[2 * r + 1]);
+    std::sort(ms.begin(), ms.end());
+    const int64_t est = static_cast<int64_t>(ms[reps / 2] * 1.0e6);
+    measured[key] = est;
+    ch.est[k] = est;
+  }
+  ch.finalize();
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  (void)hipStreamDestroy(s);
+  return st;
+}
+
+ug_status ug_set_threshold(void* ctx, int64_t th_slack_ns) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (c->started) return fail(c, UG_ESTATE, "stop before changing the threshold");
+  c->cfg.th_slack_ns = th_slack_ns;
+  c->policy.mutable_config().th_slack_ns = th_slack_ns;
+  return UG_OK;
+}
+
+ug_status ug_set_flags(void* ctx, int32_t policy, uint32_t flags) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (c->started) return fail(c, UG_ESTATE, "stop before changing flags");
+  if (policy != c->cfg.policy) return fail(c, UG_EINVAL, "the policy is fixed at creation");
+  c->cfg.flags = flags;
+  ug::PolicyConfig& p = c->policy.mutable_config();
+  p.bind = (flags & UG_F_BIND) != 0;
+  p.delay = (flags & UG_F_DELAY) != 0;
+  p.batch = (flags & UG_F_BATCH) != 0;
+  p.calibrate = (flags & UG_F_CALIBRATE) != 0;
+  return UG_OK;
+}
+
+ug_status ug_start(void* ctx) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (sticky(c)) return UG_EDEVICE;
+  if (!c->has_device) return fail(c, UG_ENODEV, "no device");
+  if (c->started) return fail(c, UG_ESTATE, "already started");
+  (void)hipSetDevice(c->cfg.device);
+  if (c->cfg.policy == UG_POLICY_FIFO &&
+      static_cast<int32_t>(c->fifo_streams.size()) < c->policy.fifo_lanes()) {
+    for (int32_t i = static_cast<int32_t>(c->fifo_streams.size()); i < c->policy.fifo_lanes(); ++i) {
+      hipStream_t s = nullptr;
+      hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreateWithFlags");
+      c->fifo_streams.push_back(s);
+    }
+  }
+  c->policy.reset();
+  c->finalized = true;
+  c->live_events.clear();
+  c->event_pool = c->all_events;
+  c->bound.clear();
+  c->frames.clear();
+  c->pending.clear();
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->latencies.clear();
+    c->chain_done.assign(c->policy.chains().size(), 0);
+    c->chain_missed.assign(c->policy.chains().size(), 0);
+  }
+  c->stop.store(false);
+  c->started = true;
+  c->thr = std::thread(gate_main, c);
+  return UG_OK;
+}
+
+ug_status ug_frame_submit(void* ctx, uint32_t chain, int64_t t_arr_ns, void* const* buffers,
+                          uint32_t n_buffers, uint64_t* frame) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (sticky(c)) return UG_EDEVICE;
+  if (!c->started) return fail(c, UG_ESTATE, "not started");
+  const auto& chs = c->policy.chains();
+  if (chain >= chs.size() || !buffers || n_buffers != chs[chain].n_buffers)
+    return fail(c, UG_EINVAL, "submit: bad chain or buffer count");
+  for (uint32_t i = 0; i < n_buffers; ++i)
+    if (!buffers[i]) return fail(c, UG_EINVAL, "submit: null buffer");
+  Frame f;
+  f.chain = chain;
+  f.t_arr = t_arr_ns < 0 ? mono_ns() : t_arr_ns;
+  f.buffers.assign(buffers, buffers + n_buffers);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->outstanding >= c->cfg.queue_capacity) return UG_EAGAIN;
+  f.f = c->next_frame[chain]++;
+  if (frame) *frame = static_cast<uint64_t>(f.f);
+  c->inbox.push_back(std::move(f));
+  ++c->outstanding;
+  c->st_submitted++;
+  return UG_OK;
+}
+
+int32_t ug_poll_complete(void* ctx, ug_completion* out, uint32_t cap) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c || (!out && cap)) return UG_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  uint32_t n = 0;
+  while (n < cap && !c->outbox.empty()) {
+    out[n++] = c->outbox.front();
+    c->outbox.pop_front();
+  }
+  if (n == 0 && sticky(c)) return UG_EDEVICE;
+  return static_cast<int32_t>(n);
+}
+
+ug_status ug_drain(void* ctx, int64_t timeout_ns) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (!c->started) return UG_OK;
+  std::unique_lock<std::mutex> lk(c->mu);
+  const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(timeout_ns);
+  while (c->outstanding > 0) {
+    if (sticky(c)) return UG_EDEVICE;
+    if (c->cv_done.wait_until(lk, deadline) == std::cv_status::timeout && c->outstanding > 0)
+      return fail(c, UG_ETIMEDOUT, "drain timed out");
+  }
+  return sticky(c) ? UG_EDEVICE : UG_OK;
+}
+
+ug_status ug_stop(void* ctx) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (!c->started) return UG_OK;
+  stop_thread(c);
+  c->started = false;
+  if (c->has_device) {
+    (void)hipSetDevice(c->cfg.device);
+    for (auto& lv : c->level_streams)
+      for (hipStream_t s : lv) (void)hipStreamSynchronize(s);
+    for (hipStream_t s : c->fifo_streams) (void)hipStreamSynchronize(s);
+  }
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->inbox.clear();
+    c->outstanding = 0;
+    for (auto& n : c->next_frame) n = 0;
+  }
+  return sticky(c) ? UG_EDEVICE : UG_OK;
+}
+
+ug_status ug_get_stats(void* ctx, ug_stats* out) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c || !out) return UG_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->frames_submitted = c->st_submitted.load();
+  out->frames_completed = c->st_completed.load();
+  out->frames_missed = c->st_missed.load();
+  out->launches = c->st_launches.load();
+  out->holds = c->st_holds.load();
+  out->batches = c->st_batches.load();
+  out->instants = c->st_instants.load();
+  out->collisions = c->started ? 0 : c->policy.collisions();
+  out->decide_ns = c->st_decide_ns.load();
+  out->launch_ns = c->st_launch_ns.load();
+  std::lock_guard<std::mutex> lk(c->trace_mu);
+  out->trace_records = c->trace.size();
+  out->trace_dropped = c->trace_dropped;
+  return UG_OK;
+}
+
+int32_t ug_trace_read(void* ctx, ug_record* out, uint32_t cap) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c || (!out && cap)) return UG_EINVAL;
+  std::lock_guard<std::mutex> lk(c->trace_mu);
+  const uint32_t n = static_cast<uint32_t>(std::min<size_t>(cap, c->trace.size()));
+  std::copy(c->trace.begin(), c->trace.begin() + n, out);
+  c->trace.erase(c->trace.begin(), c->trace.begin() + n);
+  return static_cast<int32_t>(n);
+}
+
+int32_t ug_calibration_read(void* ctx, int64_t* out, uint32_t cap) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c || (!out && cap)) return UG_EINVAL;
+  if (c->started) return fail(c, UG_ESTATE, "stop before reading samples");
+  const auto& s = c->policy.samples();
+  const uint32_t n = static_cast<uint32_t>(std::min<size_t>(cap, s.size()));
+  std::copy(s.begin(), s.begin() + n, out);
+  return static_cast<int32_t>(n);
+}
+
+ug_status ug_calibration_threshold(void* ctx, int32_t pct, int64_t* th_slack_ns) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c || !th_slack_ns || pct < 1 || pct > 100) return UG_EINVAL;
+  if (c->started) return fail(c, UG_ESTATE, "stop before computing the threshold");
+  std::vector<int64_t> s = c->policy.samples();
+  *th_slack_ns = 0;
+  if (s.empty()) return UG_OK;
+  // ascending urgency: a before b iff UL(b) > UL(a)
+  std::sort(s.begin(), s.end(), [](int64_t a, int64_t b) { return ug::ul_greater(b, a); });
+  const size_t n = s.size();
+  const size_t idx = (static_cast<size_t>(pct) * n + 99) / 100 - 1;
+  *th_slack_ns = s[idx] > 0 ? s[idx] : 0;
+  return UG_OK;
+}
+
+ug_status ug_get_metrics(void* ctx, ug_metrics* out) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c || !out) return UG_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  std::vector<int64_t> lat;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    lat = c->latencies;
+    double ratio_sum = 0.0;
+    for (size_t i = 0; i < c->chain_done.size(); ++i) {
+      if (c->chain_done[i] == 0) continue;
+      out->n_chains += 1;
+      out->missed += c->chain_missed[i];
+      ratio_sum += static_cast<double>(c->chain_missed[i]) / static_cast<double>(c->chain_done[i]);
+    }
+    out->miss_ratio = out->n_chains ? ratio_sum / out->n_chains : 0.0;
+  }
+  out->frames = lat.size();
+  if (lat.empty()) return UG_OK;
+  std::sort(lat.begin(), lat.end());
+  const size_t n = lat.size();
+  out->p50_ns = lat[(50 * n + 99) / 100 - 1];
+  out->p99_ns = lat[(99 * n + 99) / 100 - 1];
+  out->max_ns = lat.back();
+  double sum = 0.0;
+  for (int64_t v : lat) sum += static_cast<double>(v);
+  out->mean_ns = sum / static_cast<double>(n);
+  return UG_OK;
+}
+
+ug_status ug_replay_instant(void* ctx, int64_t t, const ug_record* inputs, uint32_t n_inputs,
+                            ug_record* out, uint32_t cap, uint32_t* n_out) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c || (!inputs && n_inputs) || !n_out) return UG_EINVAL;
+  if (c->has_device) return fail(c, UG_ESTATE, "replay runs on a context without a device");
+  if (!c->finalized) {
+    c->policy.reset();
+    c->finalized = true;
+  }
+  std::vector<ug::Arrival> arr;
+  std::vector<ug::EvDone> evs;
+  for (uint32_t i = 0; i < n_inputs; ++i) {
+    const ug_record& r = inputs[i];
+    if (r.type == UG_REC_ARRIVE)
+      arr.push_back({r.chain, r.frame, r.t});
+    else if (r.type == UG_REC_EVDONE)
+      evs.push_back({r.chain, r.frame, r.task, r.a, r.b});
+    else
+      return fail(c, UG_EINVAL, "replay inputs are ARRIVE and EVDONE records");
+  }
+  std::vector<ug_record> dec;
+  const char* err = nullptr;
+  if (!c->policy.instant(t, arr, evs, dec, &err)) return fail(c, UG_EINVAL, err ? err : "replay");
+  c->policy.finished().clear();
+  *n_out = static_cast<uint32_t>(dec.size());
+  if (dec.size() > cap) return fail(c, UG_ENOMEM, "replay: output buffer too small");
+  std::copy(dec.begin(), dec.end(), out);
+  return UG_OK;
+}
+
+ug_status ug_kernel_launch(const ug_kernel* k, void* const* buffers, uint32_t n_buffers,
+                           void* hip_stream) {
+  if (!k || !buffers) return UG_EINVAL;
+  if (ug::validate_kernel(*k, n_buffers)) return UG_EINVAL;
+  const int32_t* slots[2] = {k->in, k->out};
+  const int counts[2] = {3, 4};
+  for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < counts[a]; ++i) {
+      const int32_t s = slots[a][i];
+      if (s >= 0 && (static_cast<uint32_t>(s) >= n_buffers || !buffers[s])) return UG_EINVAL;
+    }
+  hipError_t e = ug::launch_kernel(*k, buffers, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? UG_OK : UG_EDEVICE;
+}
+
+ug_status ug_kernel_util(const ug_kernel* k, int32_t device, float* util) {
+  if (!k || !util) return UG_EINVAL;
+  if (ug::validate_kernel(*k, 16)) return UG_EINVAL;
+  ug::OpPlan p = ug::plan_kernel(*k);
+  if (!p.func) return UG_EINVAL;
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return UG_EDEVICE;
+  const int threads = static_cast<int>(p.block.x * p.block.y * p.block.z);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p.func, threads, p.lds) != hipSuccess ||
+      per_cu <= 0)
+    return UG_EDEVICE;
+  const double wgs = static_cast<double>(p.grid.x) * p.grid.y * p.grid.z;
+  const double slots = static_cast<double>(cus) * per_cu;
+  *util = static_cast<float>(std::min(1.0, wgs / slots));
+  return UG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Operation-level validation and dispatch to the gfx950 kernels.
+#include "ops.hpp"
+
+namespace ug {
+
+namespace {
+constexpr int64_t kMaxDim = int64_t(1) << 31;
+
+bool slot_ok(int32_t s, uint32_t n) { return s >= 0 && static_cast<uint32_t>(s) < n; }
+bool pos(int64_t v) { return v > 0 && v < kMaxDim; }
+}  // namespace
+
+const char* validate_kernel(const ug_kernel& k, uint32_t nb) {
+  const int64_t* s = k.shape;
+  switch (k.op) {
+    case UG_OP_GEMM_F32:
+      if (!pos(s[0]) || !pos(s[1]) || !pos(s[2])) return "gemm: M, N, K must be in [1, 2^31)";
+      if (s[0] * s[2] >= kMaxDim * 8 || s[2] * s[1] >= kMaxDim * 8 || s[0] * s[1] >= kMaxDim * 8)
+        return "gemm: operand too large";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
+        return "gemm: needs in {A, B}, out {C}";
+      return nullptr;
+    case UG_OP_BIAS_RELU_F32:
+      if (!pos(s[0]) || !pos(s[1]) || (s[2] != 0 && s[2] != 1))
+        return "bias_relu: shape {R, C, axis in {0,1}}";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
+        return "bias_relu: needs in {X, b}, out {Y}";
+      return nullptr;
+    case UG_OP_CONV3X3_F32:
+      if (!pos(s[0]) || !pos(s[1]) || !pos(s[2]) || !pos(s[3]))
+        return "conv3x3: shape {N, C, H, W} must be positive";
+      if (s[2] * s[3] >= kMaxDim || s[1] * s[1] * 9 >= kMaxDim * 4)
+        return "conv3x3: plane or weights too large";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
+        return "conv3x3: needs in {X, W}, out {Y}";
+      return nullptr;
+    case UG_OP_ROWSUM_F32:
+      if (!pos(s[0]) || !pos(s[1])) return "rowsum: shape {R, C} must be positive";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.out[0], nb)) return "rowsum: needs in {Z}, out {r}";
+      return nullptr;
+    case UG_OP_SOFTMAX_F32:
+      if (!pos(s[0]) || !pos(s[1])) return "softmax: shape {R, L} must be positive";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.out[0], nb)) return "softmax: needs in {X}, out {Y}";
+      return nullptr;
+    case UG_OP_VOXEL_F32:
+      if (s[0] < 0 || s[0] >= kMaxDim) return "voxel: N must be in [0, 2^31)";
+      if (!pos(s[1]) || !pos(s[2]) || s[1] * s[2] >= kMaxDim) return "voxel: bad grid nx, ny";
+      if (!(k.fparam[2] > 0.0f)) return "voxel: scale must be positive";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.out[0], nb) || !slot_ok(k.out[1], nb) ||
+          !slot_ok(k.out[2], nb) || !slot_ok(k.out[3], nb))
+        return "voxel: needs in {pts}, out {vidx, count, zmax, first}";
+      return nullptr;
+    default:
+      return "unknown op";
+  }
+}
+
+hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st) {
+  const int64_t* s = k.shape;
+  auto F = [&](int32_t slot) { return static_cast<float*>(b[slot]); };
+  auto I = [&](int32_t slot) { return static_cast<int*>(b[slot]); };
+  switch (k.op) {
+    case UG_OP_GEMM_F32:
+      return gemm_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], s[2], st);
+    case UG_OP_BIAS_RELU_F32:
+      return bias_relu_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], (int)s[2], st);
+    case UG_OP_CONV3X3_F32:
+      return conv3x3_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], s[2], s[3], st);
+    case UG_OP_ROWSUM_F32:
+      return rowsum_f32_launch(F(k.in[0]), F(k.out[0]), s[0], s[1], st);
+    case UG_OP_SOFTMAX_F32:
+      return softmax_f32_launch(F(k.in[0]), F(k.out[0]), s[0], s[1], st);
+    case UG_OP_VOXEL_F32:
+      return voxel_f32_launch(F(k.in[0]), I(k.out[0]), I(k.out[1]), F(k.out[2]), I(k.out[3]),
+                              s[0], (int)s[1], (int)s[2], k.fparam[0], k.fparam[1], k.fparam[2],
+                              st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+OpPlan plan_kernel(const ug_kernel& k) {
+  const int64_t* s = k.shape;
+  switch (k.op) {
+    case UG_OP_GEMM_F32:
+      return gemm_f32_plan(s[0], s[1], s[2], (s[2] % 4 == 0) && (s[1] % 4 == 0));
+    case UG_OP_BIAS_RELU_F32:
+      return bias_relu_f32_plan(s[0], s[1], (int)s[2], s[1] % 4 == 0);
+    case UG_OP_CONV3X3_F32:
+      return conv3x3_f32_plan(s[0], s[1], s[2], s[3]);
+    case UG_OP_ROWSUM_F32:
+      return rowsum_f32_plan(s[0], s[1]);
+    case UG_OP_SOFTMAX_F32:
+      return softmax_f32_plan(s[0], s[1], s[1] % 4 == 0);
+    case UG_OP_VOXEL_F32:
+      return voxel_f32_plan(s[0]);
+    default:
+      return OpPlan{};
+  }
+}
+
+}  // namespace ug

@@ -1,0 +1,54 @@
+// Host-side entry points of the gfx950 kernels (one per operation), and the
+// operation-level validation and dispatch used by the gate and the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ug.h"
+
+namespace ug {
+
+// Launch shape of an operation's main kernel (for the utilisation estimate).
+struct OpPlan {
+  const void* func = nullptr;
+  dim3 grid{1, 1, 1};
+  dim3 block{1, 1, 1};
+  size_t lds = 0;
+};
+
+OpPlan gemm_f32_plan(int64_t M, int64_t N, int64_t K, bool vec);
+hipError_t gemm_f32_launch(const float* A, const float* B, float* C, int64_t M, int64_t N,
+                           int64_t K, hipStream_t s);
+
+OpPlan conv3x3_f32_plan(int64_t N, int64_t C, int64_t H, int64_t W);
+hipError_t conv3x3_f32_launch(const float* X, const float* Wt, float* Y, int64_t N, int64_t C,
+                              int64_t H, int64_t W, hipStream_t s);
+
+OpPlan bias_relu_f32_plan(int64_t R, int64_t C, int axis, bool vec);
+hipError_t bias_relu_f32_launch(const float* X, const float* b, float* Y, int64_t R, int64_t C,
+                                int axis, hipStream_t s);
+
+OpPlan rowsum_f32_plan(int64_t R, int64_t C);
+hipError_t rowsum_f32_launch(const float* Z, float* r, int64_t R, int64_t C, hipStream_t s);
+
+OpPlan softmax_f32_plan(int64_t R, int64_t L, bool vec);
+hipError_t softmax_f32_launch(const float* X, float* Y, int64_t R, int64_t L, hipStream_t s);
+
+OpPlan voxel_f32_plan(int64_t N);
+hipError_t voxel_f32_launch(const float* pts, int* vidx, int* count, float* zmax, int* first,
+                            int64_t N, int nx, int ny, float xmin, float ymin, float scale,
+                            hipStream_t s);
+
+// Checks a descriptor against n_buffers slots.  Returns nullptr if valid,
+// else a static message.
+const char* validate_kernel(const ug_kernel& k, uint32_t n_buffers);
+
+// Launches the operation with buffers[slot] pointers.  Asynchronous.
+hipError_t launch_kernel(const ug_kernel& k, void* const* buffers, hipStream_t s);
+
+// Main-kernel launch shape of an operation.
+OpPlan plan_kernel(const ug_kernel& k);
+
+}  // namespace ug

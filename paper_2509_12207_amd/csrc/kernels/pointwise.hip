@@ -1,0 +1,313 @@
+// HBM-bound kernels: bias + ReLU, row sum, row softmax (FP32).
+//
+// All three stream their input once and write their output once.  Accesses
+// are float4 per lane where rows allow it, consecutive lanes touching
+// consecutive 16-byte words; reductions are wavefront shuffles (plus one LDS
+// exchange across the waves of a workgroup), in a fixed order, so results are
+// reproducible run to run.
+#include "ops.hpp"
+
+namespace ug {
+namespace {
+
+// ---------------------------------------------------------------- bias+ReLU
+// y = s > 0 ? s : +0 with s = x + b (one FP32 add; -0 and NaN give +0).
+__device__ __forceinline__ float relu_add(float x, float b) {
+  const float s = x + b;
+  return s > 0.0f ? s : 0.0f;
+}
+
+// axis 0: b[C] per column; axis 1: b[R] per row.  Vector path: C % 4 == 0.
+template <int AXIS>
+__global__ __launch_bounds__(256) void bias_relu_vec(const float4* __restrict__ X,
+                                                     const float* __restrict__ b,
+                                                     float4* __restrict__ Y, int64_t R,
+                                                     int64_t C4) {
+  const int64_t n = R * C4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float4 x = X[i];
+    float4 y;
+    if (AXIS == 0) {
+      const float4 bb = reinterpret_cast<const float4*>(b)[i % C4];
+      y = make_float4(relu_add(x.x, bb.x), relu_add(x.y, bb.y), relu_add(x.z, bb.z),
+                      relu_add(x.w, bb.w));
+    } else {
+      const float bb = b[i / C4];
+      y = make_float4(relu_add(x.x, bb), relu_add(x.y, bb), relu_add(x.z, bb), relu_add(x.w, bb));
+    }
+    Y[i] = y;
+  }
+}
+
+template <int AXIS>
+__global__ __launch_bounds__(256) void bias_relu_scalar(const float* __restrict__ X,
+                                                        const float* __restrict__ b,
+                                                        float* __restrict__ Y, int64_t R,
+                                                        int64_t C) {
+  const int64_t n = R * C;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    Y[i] = relu_add(X[i], AXIS == 0 ? b[i % C] : b[i / C]);
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// One wave per row (4 rows per workgroup): rows of up to a few thousand.
+__global__ __launch_bounds__(256) void rowsum_wave(const float* __restrict__ Z,
+                                                   float* __restrict__ r, int64_t R, int64_t C) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= R) return;
+  const float* z = Z + row * C;
+  float s = 0.f;
+  if ((C & 3) == 0 && ((reinterpret_cast<uintptr_t>(z) & 15) == 0)) {
+    const float4* z4 = reinterpret_cast<const float4*>(z);
+    for (int64_t j = lane; j < C / 4; j += 64) {
+      const float4 v = z4[j];
+      s += (v.x + v.y) + (v.z + v.w);
+    }
+  } else {
+    for (int64_t j = lane; j < C; j += 64) s += z[j];
+  }
+  s = wave_sum(s);
+  if (lane == 0) r[row] = s;
+}
+
+// One workgroup (4 waves) per row: long rows.
+__global__ __launch_bounds__(256) void rowsum_block(const float* __restrict__ Z,
+                                                    float* __restrict__ r, int64_t R, int64_t C) {
+  __shared__ float part[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t row = blockIdx.x;
+  const float* z = Z + row * C;
+  float s = 0.f;
+  if ((C & 3) == 0 && ((reinterpret_cast<uintptr_t>(z) & 15) == 0)) {
+    const float4* z4 = reinterpret_cast<const float4*>(z);
+    for (int64_t j = threadIdx.x; j < C / 4; j += 256) {
+      const float4 v = z4[j];
+      s += (v.x + v.y) + (v.z + v.w);
+    }
+  } else {
+    for (int64_t j = threadIdx.x; j < C; j += 256) s += z[j];
+  }
+  s = wave_sum(s);
+  if (lane == 0) part[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) r[row] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+// ---------------------------------------------------------------- softmax
+// Row held in registers: NV float4 per lane, WAVES waves per row.
+template <int WAVES, int NV>
+__global__ __launch_bounds__(256) void softmax_reg(const float* __restrict__ X,
+                                                   float* __restrict__ Y, int64_t R, int64_t L) {
+  constexpr int T = WAVES * 64;               // lanes per row
+  constexpr int ROWS = 256 / T;               // rows per workgroup
+  __shared__ float red[4];
+  const int t = threadIdx.x % T;
+  const int sub = threadIdx.x / T;
+  const int lane = threadIdx.x & 63;
+  const int wbase = sub * WAVES;              // first wave of this row
+  const int64_t row = (int64_t)blockIdx.x * ROWS + sub;
+  const bool live = row < R;
+  const float* x = X + row * L;
+  float* y = Y + row * L;
+  float4 v[NV];
+  const int64_t L4 = L / 4;
+  float m = -INFINITY;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int64_t j = t + (int64_t)i * T;
+    if (live && j < L4) {
+      v[i] = reinterpret_cast<const float4*>(x)[j];
+      m = fmaxf(m, fmaxf(fmaxf(v[i].x, v[i].y), fmaxf(v[i].z, v[i].w)));
+    } else {
+      v[i] = make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+    }
+  }
+  m = wave_max(m);
+  if (WAVES > 1) {
+    if (lane == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = red[wbase];
+#pragma unroll
+    for (int w = 1; w < WAVES; ++w) m = fmaxf(m, red[wbase + w]);
+    __syncthreads();
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    v[i].x = expf(v[i].x - m);
+    v[i].y = expf(v[i].y - m);
+    v[i].z = expf(v[i].z - m);
+    v[i].w = expf(v[i].w - m);
+    s += (v[i].x + v[i].y) + (v[i].z + v[i].w);
+  }
+  s = wave_sum(s);
+  if (WAVES > 1) {
+    if (lane == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    s = red[wbase];
+#pragma unroll
+    for (int w = 1; w < WAVES; ++w) s += red[wbase + w];
+  }
+  const float inv = 1.0f / s;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int64_t j = t + (int64_t)i * T;
+    if (live && j < L4)
+      reinterpret_cast<float4*>(y)[j] =
+          make_float4(v[i].x * inv, v[i].y * inv, v[i].z * inv, v[i].w * inv);
+  }
+}
+
+// Any row length: one workgroup per row, three passes over the row.
+__global__ __launch_bounds__(256) void softmax_any(const float* __restrict__ X,
+                                                   float* __restrict__ Y, int64_t R, int64_t L) {
+  __shared__ float red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float* x = X + (int64_t)blockIdx.x * L;
+  float* y = Y + (int64_t)blockIdx.x * L;
+  float m = -INFINITY;
+  for (int64_t j = threadIdx.x; j < L; j += 256) m = fmaxf(m, x[j]);
+  m = wave_max(m);
+  if (lane == 0) red[wave] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  __syncthreads();
+  float s = 0.f;
+  for (int64_t j = threadIdx.x; j < L; j += 256) s += expf(x[j] - m);
+  s = wave_sum(s);
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  s = (red[0] + red[1]) + (red[2] + red[3]);
+  const float inv = 1.0f / s;
+  for (int64_t j = threadIdx.x; j < L; j += 256) y[j] = expf(x[j] - m) * inv;
+}
+
+unsigned grid_for(int64_t work, int64_t per_block, int64_t cap) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Grid-stride kernels: 8 waves of work per CU slot on 256 CUs is plenty.
+static constexpr int64_t kStreamGridCap = 256 * 32;
+
+OpPlan bias_relu_f32_plan(int64_t R, int64_t C, int axis, bool vec) {
+  OpPlan p;
+  if (vec)
+    p.func = axis == 0 ? reinterpret_cast<const void*>(&bias_relu_vec<0>)
+                       : reinterpret_cast<const void*>(&bias_relu_vec<1>);
+  else
+    p.func = axis == 0 ? reinterpret_cast<const void*>(&bias_relu_scalar<0>)
+                       : reinterpret_cast<const void*>(&bias_relu_scalar<1>);
+  const int64_t work = vec ? R * (C / 4) : R * C;
+  p.grid = dim3(grid_for(work, 256, kStreamGridCap));
+  p.block = dim3(256);
+  return p;
+}
+
+hipError_t bias_relu_f32_launch(const float* X, const float* b, float* Y, int64_t R, int64_t C,
+                                int axis, hipStream_t s) {
+  const bool vec = (C % 4 == 0) && aligned16(X) && aligned16(Y) && (axis == 1 || aligned16(b));
+  OpPlan p = bias_relu_f32_plan(R, C, axis, vec);
+  if (vec) {
+    if (axis == 0)
+      hipLaunchKernelGGL(bias_relu_vec<0>, p.grid, p.block, 0, s,
+                         reinterpret_cast<const float4*>(X), b, reinterpret_cast<float4*>(Y), R,
+                         C / 4);
+    else
+      hipLaunchKernelGGL(bias_relu_vec<1>, p.grid, p.block, 0, s,
+                         reinterpret_cast<const float4*>(X), b, reinterpret_cast<float4*>(Y), R,
+                         C / 4);
+  } else {
+    if (axis == 0)
+      hipLaunchKernelGGL(bias_relu_scalar<0>, p.grid, p.block, 0, s, X, b, Y, R, C);
+    else
+      hipLaunchKernelGGL(bias_relu_scalar<1>, p.grid, p.block, 0, s, X, b, Y, R, C);
+  }
+  return hipGetLastError();
+}
+
+OpPlan rowsum_f32_plan(int64_t R, int64_t C) {
+  OpPlan p;
+  p.block = dim3(256);
+  if (C <= 2048) {
+    p.func = reinterpret_cast<const void*>(&rowsum_wave);
+    p.grid = dim3((unsigned)((R + 3) / 4));
+  } else {
+    p.func = reinterpret_cast<const void*>(&rowsum_block);
+    p.grid = dim3((unsigned)R);
+  }
+  return p;
+}
+
+hipError_t rowsum_f32_launch(const float* Z, float* r, int64_t R, int64_t C, hipStream_t s) {
+  OpPlan p = rowsum_f32_plan(R, C);
+  if (C <= 2048)
+    hipLaunchKernelGGL(rowsum_wave, p.grid, p.block, 0, s, Z, r, R, C);
+  else
+    hipLaunchKernelGGL(rowsum_block, p.grid, p.block, 0, s, Z, r, R, C);
+  return hipGetLastError();
+}
+
+// Register-resident variants by row length (L % 4 == 0):
+//   L <= 256: one wave per row, 1 float4 per lane; <= 1024: one wave, 4;
+//   <= 2048: two waves, 4; <= 4096: four waves, 4.
+OpPlan softmax_f32_plan(int64_t R, int64_t L, bool vec) {
+  OpPlan p;
+  p.block = dim3(256);
+  if (!vec || L > 4096) {
+    p.func = reinterpret_cast<const void*>(&softmax_any);
+    p.grid = dim3((unsigned)R);
+  } else if (L <= 256) {
+    p.func = reinterpret_cast<const void*>(&softmax_reg<1, 1>);
+    p.grid = dim3((unsigned)((R + 3) / 4));
+  } else if (L <= 1024) {
+    p.func = reinterpret_cast<const void*>(&softmax_reg<1, 4>);
+    p.grid = dim3((unsigned)((R + 3) / 4));
+  } else if (L <= 2048) {
+    p.func = reinterpret_cast<const void*>(&softmax_reg<2, 4>);
+    p.grid = dim3((unsigned)((R + 1) / 2));
+  } else {
+    p.func = reinterpret_cast<const void*>(&softmax_reg<4, 4>);
+    p.grid = dim3((unsigned)R);
+  }
+  return p;
+}
+
+hipError_t softmax_f32_launch(const float* X, float* Y, int64_t R, int64_t L, hipStream_t s) {
+  const bool vec = (L % 4 == 0) && aligned16(X) && aligned16(Y);
+  OpPlan p = softmax_f32_plan(R, L, vec);
+  if (!vec || L > 4096)
+    hipLaunchKernelGGL(softmax_any, p.grid, p.block, 0, s, X, Y, R, L);
+  else if (L <= 256)
+    hipLaunchKernelGGL((softmax_reg<1, 1>), p.grid, p.block, 0, s, X, Y, R, L);
+  else if (L <= 1024)
+    hipLaunchKernelGGL((softmax_reg<1, 4>), p.grid, p.block, 0, s, X, Y, R, L);
+  else if (L <= 2048)
+    hipLaunchKernelGGL((softmax_reg<2, 4>), p.grid, p.block, 0, s, X, Y, R, L);
+  else
+    hipLaunchKernelGGL((softmax_reg<4, 4>), p.grid, p.block, 0, s, X, Y, R, L);
+  return hipGetLastError();
+}
+
+}  // namespace ug

@@ -1,0 +1,118 @@
+"""Drive a synthetic workload through libug on torch-allocated device memory.
+
+Torch provides device memory only; every kernel and every scheduling
+decision runs in libug.  Read-only inputs are uploaded once per chain;
+outputs come in ``n_sets`` copies and frame f of a chain writes copy
+f % n_sets.
+"""
+
+import time
+
+import numpy as np
+
+from . import capi, synth
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the HIP path cannot run")
+    return torch
+
+
+class DeviceWorkload:
+    def __init__(self, wl, device="cuda:0", n_sets=2):
+        torch = _torch()
+        self.wl = wl
+        self.device = torch.device(device)
+        self.n_sets = n_sets
+        self.inputs = []          # per chain: {slot: tensor}
+        self.outputs = []         # per chain: [ {slot: tensor} per set ]
+        self.ptrs = []            # per chain: [ [ptr per slot] per set ]
+        for c, ch in enumerate(wl.chains):
+            ins = {}
+            for s, b in enumerate(ch.buffers):
+                if b.role == "in":
+                    host = synth.input_array(wl.seed, c, s, b)
+                    ins[s] = torch.from_numpy(host).to(self.device)
+            sets = []
+            for _ in range(n_sets):
+                outs = {}
+                for s, b in enumerate(ch.buffers):
+                    if b.role == "out":
+                        dt = torch.float32 if b.kind == "f32" else torch.int32
+                        outs[s] = torch.zeros(b.n, dtype=dt, device=self.device)
+                sets.append(outs)
+            self.inputs.append(ins)
+            self.outputs.append(sets)
+            self.ptrs.append([[int((ins.get(s) if s in ins else sets[k][s]).data_ptr())
+                               for s in range(len(ch.buffers))] for k in range(n_sets)])
+        torch.cuda.synchronize(self.device)
+
+    def host_input(self, c, slot):
+        return synth.input_array(self.wl.seed, c, slot, self.wl.chains[c].buffers[slot])
+
+    def output(self, c, slot, k=0):
+        return self.outputs[c][k][slot].cpu().numpy()
+
+    def nbytes(self):
+        tot = 0
+        for ins, sets in zip(self.inputs, self.outputs):
+            tot += sum(t.numel() * 4 for t in ins.values())
+            tot += sum(t.numel() * 4 for s in sets for t in s.values())
+        return tot
+
+
+def make_gate(wl, policy="urgency", device=0, **cfg):
+    g = capi.Gate(policy=policy, device=device, **cfg)
+    for ch in wl.chains:
+        g.register_chain(ch.period_ns, ch.deadline_ns, ch.tasks, len(ch.buffers))
+    return g
+
+
+def profile(g, dw, warmup=3, reps=10):
+    for c in range(len(dw.wl.chains)):
+        g.profile(c, dw.ptrs[c][0], warmup=warmup, reps=reps)
+
+
+def copy_estimates(src, dst, wl):
+    """Give ``dst`` the estimates profiled on ``src`` (same chains)."""
+    for c, ch in enumerate(wl.chains):
+        n = sum(len(t["kernels"]) for t in ch.tasks)
+        for k in range(n):
+            e, u = src.get_estimate(c, k)
+            dst.set_estimate(c, k, e, u)
+
+
+def estimates(g, wl):
+    out = {}
+    for c, ch in enumerate(wl.chains):
+        n = sum(len(t["kernels"]) for t in ch.tasks)
+        for k in range(n):
+            out[(c, k)] = g.get_estimate(c, k)
+    return out
+
+
+def run(g, dw, arrivals, lead_ns=20_000_000, timeout_s=120.0, progress=None):
+    """Submit every arrival (offsets relative to a start time ``lead_ns``
+    from now), wait for all completions and return them.  The gate must be
+    started; it is left running."""
+    t0 = capi.now_ns() + lead_ns
+    for c, f, t in arrivals:
+        fid = g.submit(c, t0 + t, dw.ptrs[c][f % dw.n_sets])
+        if fid is None:
+            raise RuntimeError("submission queue full")
+    done = []
+    n_done = 0
+    deadline = time.time() + timeout_s + (max(t for _, _, t in arrivals) / 1e9 if arrivals else 0)
+    while n_done < len(arrivals):
+        got = g.poll()
+        if len(got):
+            done.append(got)
+            n_done += len(got)
+        elif time.time() > deadline:
+            raise TimeoutError(f"{n_done} of {len(arrivals)} frames completed")
+        else:
+            time.sleep(0.002)
+    out = np.concatenate(done) if done else np.zeros(0, capi.COMPLETION_DTYPE)
+    return out, t0

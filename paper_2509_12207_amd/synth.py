@@ -1,0 +1,439 @@
+"""Seeded synthetic workloads: chain structure, arrival times and input data.
+
+This module holds none of the method's arithmetic; it only describes what to
+run and with which inputs.  Tests (for the oracle and the HIP path alike) and
+``bench.py`` draw from it.
+
+The paper's chains are closed-source perception, localisation, calibration
+and language pipelines (Sec. 5, Tab. "Characteristics of an example
+workflow" and Tab. "GPU task profiling results"); they are replaced by chains
+of the six synthetic operations with the same structure: 11 chains of 2-6
+tasks, 50-300 kernels per task, modality-specific operation mixes, per-chain
+GPU work proportional to the paper's E_gpu column, periods of 33-500 ms,
+40 % of chains with halved deadlines (f_tight, Sec. 6.2) and 15 ms arrival
+jitter (Sec. 5).
+"""
+
+import dataclasses
+import math
+
+import numpy as np
+
+MS = 1_000_000
+US = 1_000
+
+# name, modality, period (ms), E_gpu of the matching chain in the paper (ms)
+CHAINS_CFG1 = [
+    ("c0_lidar_det", "lidar_det", 100, 28.4),
+    ("c1_lidar_det", "lidar_det", 100, 28.4),
+    ("c2_cam_det", "camera", 67, 27.0),
+    ("c3_cam_det", "camera", 33, 30.2),
+    ("c4_cam_face", "camera", 67, 19.5),
+    ("c5_cam_det", "camera", 33, 30.2),
+    ("c6_cam_sign", "camera", 67, 19.5),
+    ("c7_cam_seg", "camera", 67, 27.0),
+    ("c8_lidar_loc", "lidar_loc", 200, 19.7),
+    ("c9_calib", "calib", 500, 46.1),
+    ("c10_text", "text", 500, 6.7),
+]
+
+VOXEL_GRID = (512, 512)
+VOXEL_FPARAM = (-51.2, -51.2, 5.0)
+
+
+@dataclasses.dataclass
+class Buffer:
+    name: str
+    kind: str        # "f32" or "i32"
+    n: int           # elements
+    role: str        # "in" (read-only, shared by every frame) or "out"
+    init: tuple = ("uniform", -1.0, 1.0)   # for inputs: ("uniform", lo, hi) | ("points", sigma)
+
+    @property
+    def nbytes(self):
+        return 4 * self.n
+
+
+@dataclasses.dataclass
+class Block:
+    """One producer (a contraction or a voxel scatter) and its epilogue kernels."""
+    kind: str                 # "dense", "conv", "voxel"
+    task: int
+    kernels: list             # indices into the task's kernel list
+    shape: tuple
+    outputs: dict             # role -> slot name written by this block
+
+
+@dataclasses.dataclass
+class ChainDef:
+    name: str
+    period_ns: int
+    deadline_ns: int
+    tasks: list               # [{"cpu_ns": int, "kernels": [kernel dict]}]
+    buffers: list             # [Buffer]; slot index = position
+    blocks: list              # [Block]
+
+    def slot(self, name):
+        for i, b in enumerate(self.buffers):
+            if b.name == name:
+                return i
+        raise KeyError(name)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    chains: list
+    arrivals: list            # (chain, frame, t_offset_ns), sorted by time
+    seed: int
+    meta: dict
+
+
+# ----------------------------------------------------------------------------
+# input data
+# ----------------------------------------------------------------------------
+def input_array(seed, chain, slot, buf):
+    """Deterministic host data of an input buffer (float32 or int32)."""
+    rng = np.random.default_rng([seed, chain, slot, 7])
+    kind = buf.init[0]
+    if kind == "uniform":
+        lo, hi = buf.init[1], buf.init[2]
+        return rng.uniform(lo, hi, buf.n).astype(np.float32)
+    if kind == "points":
+        sigma = buf.init[1]
+        n = buf.n // 4
+        xyz = rng.normal(0.0, sigma, (n, 3))
+        inten = rng.uniform(0.0, 1.0, (n, 1))
+        return np.concatenate([xyz, inten], axis=1).astype(np.float32).reshape(-1)
+    raise ValueError(kind)
+
+
+# ----------------------------------------------------------------------------
+# kernel descriptors
+# ----------------------------------------------------------------------------
+def k_gemm(M, N, K, a, b, c):
+    return {"op": "gemm", "shape": (M, N, K), "in": (a, b), "out": (c,)}
+
+
+def k_bias_relu(R, Cn, axis, x, bias, y):
+    return {"op": "bias_relu", "shape": (R, Cn, axis), "in": (x, bias), "out": (y,)}
+
+
+def k_conv(N, Cc, H, W, x, w, y):
+    return {"op": "conv3x3", "shape": (N, Cc, H, W), "in": (x, w), "out": (y,)}
+
+
+def k_rowsum(R, Cn, z, r):
+    return {"op": "rowsum", "shape": (R, Cn), "in": (z,), "out": (r,)}
+
+
+def k_softmax(R, L, x, y):
+    return {"op": "softmax", "shape": (R, L), "in": (x,), "out": (y,)}
+
+
+def k_voxel(N, pts, vi, vc, vz, vf, grid=VOXEL_GRID, fparam=VOXEL_FPARAM):
+    return {"op": "voxel", "shape": (N, grid[0], grid[1]), "in": (pts,), "out": (vi, vc, vz, vf),
+            "fparam": fparam}
+
+
+# ----------------------------------------------------------------------------
+# configuration 0: 2 chains x 3 tasks x (GEMM, bias+ReLU, conv, row sum)
+# ----------------------------------------------------------------------------
+def config0(seed=0, frames=10):
+    """Two chains (periods 100 and 200 ms, deadline = period), three tasks
+    each; a task is GEMM 128^3 -> bias+ReLU -> 3x3 conv on 1x16x64x64 -> row
+    sum of the conv output viewed as [1024, 64].  Ten frames per chain at
+    k * period, inputs U(-1, 1)."""
+    chains = []
+    for ci, period in enumerate((100, 200)):
+        buffers, tasks, blocks = [], [], []
+        for j in range(3):
+            base = len(buffers)
+            names = ["A", "B", "C", "bias", "X", "W", "Z", "r"]
+            sizes = [128 * 128, 128 * 128, 128 * 128, 128, 16 * 64 * 64, 16 * 16 * 9,
+                     16 * 64 * 64, 1024]
+            roles = ["in", "in", "out", "in", "in", "in", "out", "out"]
+            for nm, n, rl in zip(names, sizes, roles):
+                buffers.append(Buffer(f"t{j}.{nm}", "f32", n, rl))
+            A, B, Cb, bias, X, W, Z, r = range(base, base + 8)
+            ks = [k_gemm(128, 128, 128, A, B, Cb), k_bias_relu(128, 128, 0, Cb, bias, Cb),
+                  k_conv(1, 16, 64, 64, X, W, Z), k_rowsum(1024, 64, Z, r)]
+            tasks.append({"cpu_ns": 0, "kernels": ks})
+            blocks.append(Block("dense", j, [0, 1], (128, 128, 128), {"C": f"t{j}.C"}))
+            blocks.append(Block("conv", j, [2], (1, 16, 64, 64), {"Y": f"t{j}.Z"}))
+            blocks.append(Block("rowsum", j, [3], (1024, 64), {"r": f"t{j}.r"}))
+        chains.append(ChainDef(f"c{ci}", period * MS, period * MS, tasks, buffers, blocks))
+    arrivals = sorted(((c, f, f * chains[c].period_ns) for c in range(2) for f in range(frames)),
+                      key=lambda a: (a[2], a[0], a[1]))
+    return Workload("cfg0", chains, arrivals, seed, {"frames": frames})
+
+
+# ----------------------------------------------------------------------------
+# configuration 1: 11 chains, 2-6 tasks, 50-300 kernels per task
+# ----------------------------------------------------------------------------
+def _model_ns(op, shape):
+    """Rough time model used only to size the synthetic tasks."""
+    floor = 6 * US
+    if op == "gemm":
+        M, N, K = shape
+        return floor + max(2 * M * N * K / 80e12, 4 * (M * K + K * N + M * N) / 4e12) * 1e9
+    if op == "conv3x3":
+        _, Cc, H, W = shape
+        return floor + max(18 * Cc * Cc * H * W / 70e12, 8 * Cc * H * W / 4e12) * 1e9
+    if op in ("bias_relu", "softmax"):
+        R, Cn = shape[0], shape[1]
+        return floor + 8 * R * Cn / 4e12 * 1e9
+    if op == "rowsum":
+        R, Cn = shape
+        return floor + 4 * R * Cn / 4e12 * 1e9
+    if op == "voxel":
+        return 3 * floor + 20 * shape[0] / 1e12 * 1e9
+    raise ValueError(op)
+
+
+def _pow2_pick(lo, hi, q, s, step=1):
+    """Value in [lo, hi] (powers of two apart) at quantile q scaled by s."""
+    n = int(round(math.log2(hi / lo)))
+    i = min(n, int(math.floor(q * s * (n + 1))))
+    return lo * (2 ** i)
+
+
+def _gemm_shape(q, s):
+    dims = []
+    for qi in q:
+        # multiples of 256 in [256, 4096], log-spaced
+        v = 256 * (2 ** (qi * s * 4.0))
+        dims.append(int(min(4096, max(256, 256 * round(v / 256)))))
+    return tuple(dims)
+
+
+def _draw_task(rng, modality, task_idx, n_tasks, budget_ns):
+    """Draw a task's block list (kind and size quantiles) with 50-300 kernels."""
+    target = int(round(math.exp(rng.uniform(math.log(50), math.log(300)))))
+    blocks = []
+    count = 0
+    first = True
+    while count < target:
+        if first and task_idx == 0 and modality in ("lidar_det", "lidar_loc", "calib"):
+            kind = "voxel"
+        elif modality in ("lidar_det", "calib"):
+            kind = "conv" if rng.uniform() < 0.65 else "dense"
+        elif modality == "camera":
+            kind = "conv" if rng.uniform() < 0.8 else "dense"
+        elif modality == "lidar_loc":
+            kind = "dense"
+        else:                                  # text
+            kind = "dense"
+        first = False
+        b = {"kind": kind, "q": rng.uniform(0, 1, 3).tolist()}
+        if kind == "voxel":
+            b["n_points"] = int(rng.integers(30_000, 120_001))
+            count += 1
+        elif kind == "dense":
+            b["softmax"] = bool(rng.uniform() < (0.5 if modality == "text" else 0.2))
+            b["rowsum"] = bool(rng.uniform() < 0.15)
+            count += 2 + b["softmax"] + b["rowsum"]
+        else:
+            b["rowsum"] = bool(rng.uniform() < 0.15)
+            count += 2 + b["rowsum"]
+        blocks.append(b)
+    return blocks
+
+
+def _shapes(b, s):
+    if b["kind"] == "dense":
+        return _gemm_shape(b["q"], s)
+    if b["kind"] == "conv":
+        Cc = _pow2_pick(32, 256, b["q"][0], s)
+        H = _pow2_pick(32, 256, b["q"][1], s)
+        return (1, Cc, H, H)
+    return (b["n_points"],)
+
+
+def _block_time(b, s):
+    shp = _shapes(b, s)
+    if b["kind"] == "dense":
+        M, N, K = shp
+        t = _model_ns("gemm", shp) + _model_ns("bias_relu", (M, N))
+        if b["softmax"]:
+            t += _model_ns("softmax", (M, N))
+        if b["rowsum"]:
+            t += _model_ns("rowsum", (M, N))
+        return t
+    if b["kind"] == "conv":
+        _, Cc, H, W = shp
+        t = _model_ns("conv3x3", shp) + _model_ns("bias_relu", (Cc, H * W))
+        if b["rowsum"]:
+            t += _model_ns("rowsum", (Cc, H * W))
+        return t
+    return _model_ns("voxel", shp)
+
+
+def _fit_scale(blocks, budget_ns):
+    lo, hi = 0.0, 1.0
+    if sum(_block_time(b, hi) for b in blocks) <= budget_ns:
+        return hi
+    if sum(_block_time(b, lo) for b in blocks) >= budget_ns:
+        return lo
+    for _ in range(30):
+        mid = 0.5 * (lo + hi)
+        if sum(_block_time(b, mid) for b in blocks) > budget_ns:
+            hi = mid
+        else:
+            lo = mid
+    return lo
+
+
+def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales):
+    buffers, tasks, blocks = [], [], []
+    for j, (tb, s) in enumerate(zip(task_blocks, scales)):
+        shapes = [_shapes(b, s) for b in tb]
+        need = {}
+
+        def want(nm, n, role, init=("uniform", -1.0, 1.0), kind="f32"):
+            key = f"t{j}.{nm}"
+            cur = need.get(key)
+            need[key] = (max(n, cur[0]) if cur else n, role, init, kind)
+
+        for b, shp in zip(tb, shapes):
+            if b["kind"] == "dense":
+                M, N, K = shp
+                want("in_a", M * K, "in")
+                want("in_b", K * N, "in")
+                want("bias_col", N, "in")
+                want("D0", M * N, "out")
+                want("D1", M * N, "out")
+                if b["softmax"]:
+                    want("SM", M * N, "out")
+                if b["rowsum"]:
+                    want("RS", M, "out")
+            elif b["kind"] == "conv":
+                _, Cc, H, W = shp
+                want("in_x", Cc * H * W, "in")
+                want("in_w", Cc * Cc * 9, "in")
+                want("bias_row", Cc, "in")
+                want("C0", Cc * H * W, "out")
+                want("C1", Cc * H * W, "out")
+                if b["rowsum"]:
+                    want("RS", Cc, "out")
+            else:
+                n = shp[0]
+                G = VOXEL_GRID[0] * VOXEL_GRID[1]
+                want("pts", 4 * n, "in", ("points", 20.0))
+                want("VI", n, "out", kind="i32")
+                want("VC", G, "out", kind="i32")
+                want("VZ", G, "out")
+                want("VF", G, "out", kind="i32")
+        base = len(buffers)
+        for key, (n, role, init, kind) in need.items():
+            buffers.append(Buffer(key, kind, n, role, init))
+        slot = {b.name: i for i, b in enumerate(buffers)}
+        ks = []
+        dn = cn = 0
+        for b, shp in zip(tb, shapes):
+            first = len(ks)
+            if b["kind"] == "dense":
+                M, N, K = shp
+                out = slot[f"t{j}.D{dn % 2}"]
+                outs = {"C": f"t{j}.D{dn % 2}"}
+                dn += 1
+                ks.append(k_gemm(M, N, K, slot[f"t{j}.in_a"], slot[f"t{j}.in_b"], out))
+                ks.append(k_bias_relu(M, N, 0, out, slot[f"t{j}.bias_col"], out))
+                if b["softmax"]:
+                    ks.append(k_softmax(M, N, out, slot[f"t{j}.SM"]))
+                    outs["SM"] = f"t{j}.SM"
+                if b["rowsum"]:
+                    ks.append(k_rowsum(M, N, out, slot[f"t{j}.RS"]))
+                    outs["RS"] = f"t{j}.RS"
+            elif b["kind"] == "conv":
+                _, Cc, H, W = shp
+                out = slot[f"t{j}.C{cn % 2}"]
+                outs = {"Y": f"t{j}.C{cn % 2}"}
+                cn += 1
+                ks.append(k_conv(1, Cc, H, W, slot[f"t{j}.in_x"], slot[f"t{j}.in_w"], out))
+                ks.append(k_bias_relu(Cc, H * W, 1, out, slot[f"t{j}.bias_row"], out))
+                if b["rowsum"]:
+                    ks.append(k_rowsum(Cc, H * W, out, slot[f"t{j}.RS"]))
+                    outs["RS"] = f"t{j}.RS"
+            else:
+                n = shp[0]
+                ks.append(k_voxel(n, slot[f"t{j}.pts"], slot[f"t{j}.VI"], slot[f"t{j}.VC"],
+                                  slot[f"t{j}.VZ"], slot[f"t{j}.VF"]))
+                outs = {"VI": f"t{j}.VI", "VC": f"t{j}.VC", "VZ": f"t{j}.VZ", "VF": f"t{j}.VF"}
+            blocks.append(Block(b["kind"], j, list(range(first, len(ks))), shp, outs))
+        tasks.append({"cpu_ns": 0, "kernels": ks})
+        del base
+    return ChainDef(name, period_ns, deadline_ns, tasks, buffers, blocks)
+
+
+def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=0.85, window_s=10.0,
+            jitter_ms=15.0, chains_subset=None):
+    """Eleven chains of 2-6 tasks with 50-300 FP32 kernels per task.
+
+    Per-chain GPU work per frame is proportional to the paper's E_gpu of the
+    matching chain, scaled so that sum_c E_c / P_c = u_target under the
+    generator's own time model at f_a = 1 (the measured utilisation is
+    reported by the benchmark).  ``f_tight`` of the chains (chosen by the
+    seed) get half-period deadlines, the rest a deadline equal to the period;
+    all deadlines are scaled by f_d.  Arrivals: per-chain phase U[0, P'),
+    nominal k * P' with P' = P / f_a, plus uniform jitter of +-jitter_ms/2.
+    """
+    rng = np.random.default_rng([seed, 1])
+    rows = CHAINS_CFG1 if chains_subset is None else [CHAINS_CFG1[i] for i in chains_subset]
+    lam = u_target / sum(e / p for _, _, p, e in rows)
+    n = len(rows)
+    n_tight = int(round(f_tight * n))
+    tight = set(rng.permutation(n)[:n_tight].tolist())
+    chains = []
+    for ci, (name, modality, period_ms, egpu) in enumerate(rows):
+        crng = np.random.default_rng([seed, 2, ci])
+        e_chain = lam * egpu * MS
+        n_tasks = int(crng.integers(2, 7))
+        split = crng.dirichlet(np.full(n_tasks, 2.0))
+        task_blocks, scales = [], []
+        for j in range(n_tasks):
+            budget = e_chain * split[j]
+            tb = _draw_task(crng, modality, j, n_tasks, budget)
+            task_blocks.append(tb)
+            scales.append(_fit_scale(tb, budget))
+        period = period_ms * MS
+        deadline = int(period * (0.5 if ci in tight else 1.0) * f_d)
+        chains.append(_build_chain(name, modality, period, deadline, task_blocks, scales))
+    arr = []
+    arng = np.random.default_rng([seed, 3])
+    window = int(window_s * 1e9)
+    half_j = jitter_ms * MS / 2
+    for ci, ch in enumerate(chains):
+        p = ch.period_ns / f_a
+        phase = arng.uniform(0, p)
+        k, last = 0, -1
+        while True:
+            t = phase + k * p + arng.uniform(-half_j, half_j)
+            t = int(max(t, last + 1, 0))
+            if t >= window:
+                break
+            arr.append((ci, k, t))
+            last = t
+            k += 1
+    arr.sort(key=lambda a: (a[2], a[0], a[1]))
+    meta = {"f_a": f_a, "f_d": f_d, "f_tight": f_tight, "u_target": u_target,
+            "tight": sorted(tight), "window_s": window_s}
+    return Workload("cfg1", chains, arr, seed, meta)
+
+
+def model_utilisation(wl, f_a=1.0):
+    """sum_c (model GPU time per frame) / P'_c under the generator's model."""
+    u = 0.0
+    for ch in wl.chains:
+        t = 0.0
+        for task in ch.tasks:
+            for k in task["kernels"]:
+                t += _model_ns(k["op"], tuple(k["shape"][:4 if k["op"] == "conv3x3" else
+                                                         (3 if k["op"] == "gemm" else
+                                                          (1 if k["op"] == "voxel" else 2))]))
+        u += t / (ch.period_ns / f_a)
+    return u
+
+
+def kernel_counts(wl):
+    return [[len(t["kernels"]) for t in ch.tasks] for ch in wl.chains]

@@ -1,0 +1,82 @@
+"""Conversion between libug decision-log records and the oracle's tuples."""
+
+import numpy as np
+
+from paper_2509_12207_amd import capi
+
+NAMES = {capi.REC_COMPLETE: "COMPLETE", capi.REC_TSTART: "TSTART", capi.REC_BIND: "BIND",
+         capi.REC_HOLD: "HOLD", capi.REC_EVREC: "EVREC", capi.REC_LAUNCH: "LAUNCH"}
+
+
+def record_to_tuple(r):
+    t = int(r["type"])
+    c, f = int(r["chain"]), int(r["frame"])
+    if t == capi.REC_COMPLETE:
+        return ("COMPLETE", c, f, int(r["t"]))
+    if t == capi.REC_TSTART:
+        return ("TSTART", c, f, int(r["task"]))
+    if t == capi.REC_BIND:
+        return ("BIND", c, f, int(r["task"]), int(r["a"]), int(r["b"]))
+    if t == capi.REC_HOLD:
+        return ("HOLD", c, f, int(r["kernel"]))
+    if t == capi.REC_EVREC:
+        return ("EVREC", c, f, int(r["task"]), int(r["a"]), int(r["b"]))
+    if t == capi.REC_LAUNCH:
+        return ("LAUNCH", c, f, int(r["kernel"]), int(r["a"]), int(r["b"]))
+    raise ValueError(t)
+
+
+def inputs_to_records(arrivals, evdones):
+    recs = np.zeros(len(arrivals) + len(evdones), capi.RECORD_DTYPE)
+    i = 0
+    for c, f, t_arr in arrivals:
+        recs[i]["type"], recs[i]["chain"], recs[i]["frame"], recs[i]["t"] = capi.REC_ARRIVE, c, f, t_arr
+        i += 1
+    for c, f, j, kind, seq in evdones:
+        r = recs[i]
+        r["type"], r["chain"], r["frame"], r["task"], r["a"], r["b"] = capi.REC_EVDONE, c, f, j, kind, seq
+        i += 1
+    return recs
+
+
+def instants_from_trace(recs):
+    """Split a gate log into (t, arrivals, evdones, decisions) instants."""
+    out = []
+    cur = None
+    for r in recs:
+        t = int(r["type"])
+        if t == capi.REC_INSTANT:
+            if cur is not None:
+                out.append(cur)
+            cur = (int(r["t"]), [], [], [])
+        elif t == capi.REC_ARRIVE:
+            cur[1].append((int(r["chain"]), int(r["frame"]), int(r["t"])))
+        elif t == capi.REC_EVDONE:
+            cur[2].append((int(r["chain"]), int(r["frame"]), int(r["task"]), int(r["a"]), int(r["b"])))
+        else:
+            cur[3].append(record_to_tuple(r))
+    if cur is not None:
+        out.append(cur)
+    return out
+
+
+def oracle_chains(wl_or_chains, estimates=None):
+    """Plain-data chain descriptions for the oracle from synth ChainDefs.
+
+    ``estimates``: optional {(chain, kernel): (est_ns, util)} as read back
+    from the library (the policy sees the same numbers on both sides)."""
+    chains = wl_or_chains.chains if hasattr(wl_or_chains, "chains") else wl_or_chains
+    out = []
+    for c, ch in enumerate(chains):
+        tasks = []
+        g = 0
+        for task in ch.tasks:
+            est, util = [], []
+            for k in task["kernels"]:
+                e, u = estimates[(c, g)] if estimates else (k.get("est_ns", 0), k.get("util", 1.0))
+                est.append(e)
+                util.append(u)
+                g += 1
+            tasks.append({"cpu_ns": task.get("cpu_ns", 0), "est_ns": est, "util": util})
+        out.append({"deadline_ns": ch.deadline_ns, "tasks": tasks})
+    return out

@@ -1,0 +1,199 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* the library loads and exports every function include/ug.h declares;
+* the ctypes structures have the C layout (a gcc-compiled probe of ug.h);
+* the C++ policy core, replayed offline instant by instant, takes exactly
+  the oracle's decisions on randomised workloads (the oracle's DES produces
+  the inputs: arrivals and observed event completions);
+* the C++ TH_urgent percentile matches the oracle's.
+"""
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import des
+from oracle import policy as OP
+from paper_2509_12207_amd import capi
+
+from _trace import inputs_to_records, record_to_tuple
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ug.h")
+MS = 1_000_000
+US = 1_000
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ug_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = capi.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert missing == []
+    assert sorted(capi.EXPORTED) == names
+    out = subprocess.run(["nm", "-D", "--defined-only", capi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (ug_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_c(tmp_path):
+    probe = tmp_path / "probe.c"
+    structs = {"ug_kernel": capi.Kernel, "ug_task": capi.Task, "ug_config": capi.Config,
+               "ug_completion": capi.Completion, "ug_record": capi.Record,
+               "ug_stats": capi.Stats, "ug_metrics": capi.Metrics}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ug.h"', 'int main(void){']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            cf = "in" if f == "in_" else f
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {cf}));')
+    lines.append("return 0;}")
+    probe.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(probe), "-o",
+                    str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+    assert capi.RECORD_DTYPE.itemsize == C.sizeof(capi.Record)
+    assert capi.COMPLETION_DTYPE.itemsize == C.sizeof(capi.Completion)
+
+
+def test_config_defaults_and_errors():
+    L = capi.lib()
+    cfg = capi.Config()
+    L.ug_config_default(C.byref(cfg))
+    assert cfg.abi_version == capi.ABI_VERSION
+    assert cfg.delta_eval_ns == 500_000 and cfg.delay_poll_ns == 1_000_000
+    assert abs(cfg.util_exempt - 0.1) < 1e-7
+    assert cfg.flags == capi.F_BIND | capi.F_DELAY | capi.F_BATCH
+    bad = capi.Config()
+    L.ug_config_default(C.byref(bad))
+    bad.abi_version = 99
+    h = C.c_void_p()
+    assert L.ug_create(C.byref(bad), C.byref(h)) == capi.EINVAL
+    g = capi.Gate(device=-1)
+    with pytest.raises(capi.UgError) as e:
+        g.register_chain(1, 10, [{"kernels": [{"op": "gemm", "shape": (0, 4, 4), "in": (0, 1),
+                                               "out": (2,)}]}], 3)
+    assert e.value.status == capi.EINVAL
+    with pytest.raises(capi.UgError) as e:
+        g.register_chain(1, 10, [{"kernels": [{"op": "gemm", "shape": (4, 4, 4), "in": (0, 5),
+                                               "out": (2,)}]}], 3)
+    assert e.value.status == capi.EINVAL
+    with pytest.raises(capi.UgError) as e:
+        g.start()
+    assert e.value.status == capi.ENODEV
+    with pytest.raises(capi.UgError) as e:
+        g.submit(0, 0, [1, 2, 3])
+    assert e.value.status in (capi.ESTATE, capi.EINVAL)
+    g.close()
+
+
+# ----------------------------------------------------------------------------
+# C++ policy core == oracle gate model, instant by instant
+# ----------------------------------------------------------------------------
+def _random_workload(r, n_chains, n_frames):
+    chains, arrivals = [], []
+    for c in range(n_chains):
+        tasks = []
+        for j in range(int(r.integers(1, 4))):
+            ks = [(int(r.integers(20, 400)) * US, float(r.choice([0.05, 0.09, 0.1, 0.5, 1.0])))
+                  for _ in range(int(r.integers(1, 9)))]
+            tasks.append({"cpu_ns": int(r.integers(0, 3)) * 150 * US,
+                          "est_ns": [e for e, _ in ks], "util": [u for _, u in ks]})
+        period = int(r.integers(3, 12)) * MS
+        chains.append({"deadline_ns": int(period * r.choice([0.5, 1.0])), "tasks": tasks,
+                       "period_ns": period})
+        phase = int(r.integers(0, period))
+        for f in range(n_frames):
+            arrivals.append((c, f, phase + f * period + int(r.integers(0, 500)) * US))
+    return chains, arrivals
+
+
+def _register(g, chains):
+    for ch in chains:
+        tasks = []
+        for t in ch["tasks"]:
+            ks = [{"op": "rowsum", "shape": (4, 4), "in": (0,), "out": (1,), "est_ns": e,
+                   "util": u} for e, u in zip(t["est_ns"], t["util"])]
+            tasks.append({"cpu_ns": t["cpu_ns"], "kernels": ks})
+        g.register_chain(ch.get("period_ns", 0), ch["deadline_ns"], tasks, 2)
+
+
+def _flags(cfg):
+    return ((capi.F_BIND if cfg.get("bind", True) else 0) | (capi.F_DELAY if cfg.get("delay", True) else 0)
+            | (capi.F_BATCH if cfg.get("batch", True) else 0)
+            | (capi.F_CALIBRATE if cfg.get("calibrate", False) else 0))
+
+
+def _gate_for(cfg):
+    lanes = cfg.get("lanes", [1, 2, 1])
+    return capi.Gate(policy=cfg.get("policy", "urgency"), device=-1, lanes=lanes,
+                     flags=_flags(cfg), delta_eval_ns=cfg.get("delta_eval_ns", 500_000),
+                     delay_poll_ns=cfg.get("delay_poll_ns", 1_000_000),
+                     th_slack_ns=cfg.get("th_slack_ns", 0))
+
+
+CFGS = [
+    {"policy": "urgency", "th_slack_ns": 3 * MS},
+    {"policy": "urgency", "th_slack_ns": 3 * MS, "delay_poll_ns": 0},
+    {"policy": "urgency", "th_slack_ns": 0, "lanes": [1, 1]},
+    {"policy": "urgency", "th_slack_ns": 2 * MS, "lanes": [2, 3, 1, 2]},
+    {"policy": "urgency", "batch": False, "bind": False, "th_slack_ns": 2 * MS},
+    {"policy": "urgency", "delay": False, "th_slack_ns": 0, "calibrate": True},
+    {"policy": "urgency", "th_slack_ns": 4 * MS, "lanes": [1]},
+    {"policy": "fifo"},
+]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_cpp_policy_replays_oracle_decisions(seed):
+    r = np.random.default_rng(500 + seed)
+    chains, arrivals = _random_workload(r, int(r.integers(2, 6)), int(r.integers(2, 6)))
+    noise = {}
+
+    def dur(c, f, g):
+        if (c, f, g) not in noise:
+            est = [e for t in chains[c]["tasks"] for e in t["est_ns"]]
+            noise[(c, f, g)] = max(1, int(est[g] * r.uniform(0.5, 1.6)))
+        return noise[(c, f, g)]
+
+    for cfg in CFGS:
+        res = des.simulate(chains, cfg, arrivals, dur)
+        g = _gate_for(cfg)
+        _register(g, chains)
+        n_dec = 0
+        for idx, (t, arr, evs, dec) in enumerate(res["instants"]):
+            got = [record_to_tuple(x) for x in g.replay_instant(t, inputs_to_records(arr, evs))]
+            assert got == list(dec), (cfg, idx, t)
+            n_dec += len(dec)
+        assert n_dec > 0
+        if cfg.get("calibrate"):
+            samples = g.calibration_samples()
+            assert samples == res["gate"].samples
+            assert g.calibration_threshold(95) == OP.threshold_from_samples(samples)
+        g.close()
+
+
+def test_cpp_replay_rejects_unexpected_event():
+    g = _gate_for({"policy": "urgency"})
+    _register(g, [{"deadline_ns": 10 * MS, "tasks": [{"cpu_ns": 0, "est_ns": [MS], "util": [1.0]}]}])
+    g.replay_instant(0, inputs_to_records([(0, 0, 0)], []))
+    with pytest.raises(capi.UgError):
+        g.replay_instant(1, inputs_to_records([], [(0, 0, 0, 1, 5)]))
+    g.close()

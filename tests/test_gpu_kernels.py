@@ -1,0 +1,247 @@
+"""Parity of each gfx950 kernel with the oracle, called through the C-ABI
+(ug_kernel_launch) on torch-allocated device memory.
+
+Tolerances: bias+ReLU and the voxel scatter are bit-exact; GEMM, conv and row
+sum are componentwise within 1e-5 of the absolute-value computation
+(|A||B|, |W|*|X|, sum |Z|); softmax within 1e-5 relative per element.
+Integer-valued inputs make every partial sum exact, so there the contractions
+must match bit for bit.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import kernels as OK
+from paper_2509_12207_amd import capi
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = 1e-5
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def launch(desc, tensors):
+    capi.kernel_launch(desc, [int(t.data_ptr()) for t in tensors])
+    torch.cuda.synchronize()
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+# --------------------------------------------------------------------- GEMM
+def run_gemm(A, B):
+    M, K = A.shape
+    N = B.shape[1]
+    a, b = dev(A), dev(B)
+    c = torch.full((M, N), float("nan"), device=DEV)
+    launch({"op": "gemm", "shape": (M, N, K), "in": (0, 1), "out": (2,)}, [a, b, c])
+    return c.cpu().numpy()
+
+
+# tile variants: small 32x32 with a 4-way K split (most), mid 64x64
+# (1024 x 1024, 2048 x 1024), big 128x128 (the full-size test below)
+@pytest.mark.parametrize("M,N,K", [(128, 128, 128), (256, 512, 384), (130, 70, 37),
+                                   (257, 132, 64), (1, 1, 1), (33, 1000, 19), (512, 256, 4096),
+                                   (1024, 1024, 300), (2048, 1024, 64), (1000, 1030, 17)])
+def test_gemm_parity(M, N, K):
+    r = rng(M * 7 + N * 3 + K)
+    A = r.uniform(-1, 1, (M, K)).astype(np.float32)
+    B = r.uniform(-1, 1, (K, N)).astype(np.float32)
+    C = run_gemm(A, B)
+    ref = OK.gemm_f64(A, B)
+    scale = OK.gemm_abs_f64(A, B)
+    assert np.all(np.abs(C - ref) <= TOL * scale), np.max(np.abs(C - ref) / scale)
+
+
+@pytest.mark.parametrize("M,N,K", [(128, 128, 128), (300, 200, 100), (64, 96, 2048)])
+def test_gemm_integer_inputs_bit_exact(M, N, K):
+    r = rng(11 + M)
+    A = r.integers(-2, 3, (M, K)).astype(np.float32)
+    B = r.integers(-2, 3, (K, N)).astype(np.float32)
+    C = run_gemm(A, B)
+    assert np.array_equal(C, (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32))
+
+
+def test_gemm_full_size_sampled():
+    """4096^3 (the largest configuration shape), checked on sampled entries."""
+    M = N = K = 4096
+    g = torch.Generator(device="cpu").manual_seed(5)
+    A = (torch.rand(M, K, generator=g) * 2 - 1).numpy()
+    B = (torch.rand(K, N, generator=g) * 2 - 1).numpy()
+    C = run_gemm(A, B)
+    r = rng(6)
+    for m, n in zip(r.integers(0, M, 64), r.integers(0, N, 64)):
+        v, s = OK.gemm_entry_f64(A, B, m, n)
+        assert abs(C[m, n] - v) <= TOL * s
+    assert np.isfinite(C).all()
+
+
+# ---------------------------------------------------------------- bias+ReLU
+@pytest.mark.parametrize("R,Cn,axis", [(128, 128, 0), (16, 4096, 1), (37, 53, 0), (5, 7, 1),
+                                       (1024, 1024, 0)])
+def test_bias_relu_bit_exact(R, Cn, axis):
+    r = rng(R + Cn + axis)
+    X = r.uniform(-1, 1, (R, Cn)).astype(np.float32)
+    X.flat[::17] = -0.0
+    X.flat[::23] = np.nan
+    b = r.uniform(-0.5, 0.5, Cn if axis == 0 else R).astype(np.float32)
+    x, bb = dev(X), dev(b)
+    y = torch.empty_like(x)
+    launch({"op": "bias_relu", "shape": (R, Cn, axis), "in": (0, 1), "out": (2,)}, [x, bb, y])
+    want = OK.bias_relu_f32(X, b, axis)
+    got = y.cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    # in place
+    launch({"op": "bias_relu", "shape": (R, Cn, axis), "in": (0, 1), "out": (0,)}, [x, bb])
+    assert np.array_equal(x.cpu().numpy().view(np.uint32), want.view(np.uint32))
+
+
+# --------------------------------------------------------------------- conv
+def run_conv(X, W):
+    n, c, h, w = X.shape
+    x, wt = dev(X), dev(W)
+    y = torch.full((n, c, h, w), float("nan"), device=DEV)
+    launch({"op": "conv3x3", "shape": (n, c, h, w), "in": (0, 1), "out": (2,)}, [x, wt, y])
+    return y.cpu().numpy()
+
+
+# tile variants: (1, 64, 128, 128) -> 64 ch x 2x16 px with a K split,
+# (1, 32, 256, 256) -> 32 ch x 8x16 px, the rest -> 32 ch x 2x16 px with a K
+# split; 64 ch x 8x16 px and 128 ch x 8x16 px in the sampled tests below
+@pytest.mark.parametrize("n,c,h,w", [(1, 16, 64, 64), (1, 32, 32, 32), (1, 64, 32, 48),
+                                     (1, 130, 20, 20), (2, 3, 13, 21), (1, 1, 1, 1),
+                                     (1, 256, 16, 16), (1, 64, 128, 128), (1, 32, 256, 256),
+                                     (1, 100, 33, 47)])
+def test_conv_parity(n, c, h, w):
+    r = rng(n + 5 * c + 7 * h + w)
+    X = r.uniform(-1, 1, (n, c, h, w)).astype(np.float32)
+    W = r.uniform(-1, 1, (c, c, 3, 3)).astype(np.float32)
+    Y = run_conv(X, W)
+    ref = OK.conv3x3_f64(X, W)
+    scale = OK.conv3x3_abs_f64(X, W)
+    assert np.all(np.abs(Y - ref) <= TOL * scale + 1e-30), np.nanmax(np.abs(Y - ref) / (scale + 1e-30))
+
+
+def test_conv_integer_inputs_bit_exact():
+    r = rng(77)
+    X = r.integers(-2, 3, (1, 48, 24, 40)).astype(np.float32)
+    W = r.integers(-2, 3, (48, 48, 3, 3)).astype(np.float32)
+    assert np.array_equal(run_conv(X, W), OK.conv3x3_f64(X, W).astype(np.float32))
+
+
+@pytest.mark.parametrize("c", [256, 64])
+def test_conv_full_size_sampled(c):
+    """C = 256, H = W = 256 (the largest configuration shape; 128-channel
+    tiles) and C = 64 (64-channel tiles), sampled entries."""
+    r = rng(78 + c)
+    X = r.uniform(-1, 1, (1, c, 256, 256)).astype(np.float32)
+    W = r.uniform(-1, 1, (c, c, 3, 3)).astype(np.float32)
+    Y = run_conv(X, W)
+    pts = list(zip(r.integers(0, c, 48), r.integers(0, 256, 48), r.integers(0, 256, 48)))
+    pts += [(0, 0, 0), (c - 1, 255, 255), (17, 0, 255), (3, 255, 0)]
+    for o, y, x in pts:
+        v, s = OK.conv3x3_entry_f64(X, W, 0, o, y, x)
+        assert abs(Y[0, o, y, x] - v) <= TOL * s
+
+
+# ------------------------------------------------------------------- rowsum
+@pytest.mark.parametrize("R,Cn", [(1024, 64), (7, 5), (3, 5000), (300, 2048), (2, 16384),
+                                  (4096, 1)])
+def test_rowsum_parity(R, Cn):
+    r = rng(R * 3 + Cn)
+    Z = r.uniform(-1, 1, (R, Cn)).astype(np.float32)
+    z = dev(Z)
+    out = torch.full((R,), float("nan"), device=DEV)
+    launch({"op": "rowsum", "shape": (R, Cn), "in": (0,), "out": (1,)}, [z, out])
+    s, a = OK.rowsum_f64(Z)
+    assert np.all(np.abs(out.cpu().numpy() - s) <= TOL * a)
+
+
+def test_rowsum_integer_exact():
+    r = rng(9)
+    Z = r.integers(-2, 3, (100, 3000)).astype(np.float32)
+    z = dev(Z)
+    out = torch.empty(100, device=DEV)
+    launch({"op": "rowsum", "shape": (100, 3000), "in": (0,), "out": (1,)}, [z, out])
+    assert np.array_equal(out.cpu().numpy(), Z.astype(np.int64).sum(1).astype(np.float32))
+
+
+# ------------------------------------------------------------------ softmax
+@pytest.mark.parametrize("R,L", [(256, 128), (5, 3), (64, 256), (33, 1000), (16, 1024),
+                                 (9, 2048), (8, 4096), (3, 5000), (7, 1)])
+def test_softmax_parity(R, L):
+    r = rng(R + L)
+    X = r.uniform(-8, 8, (R, L)).astype(np.float32)
+    x = dev(X)
+    y = torch.full_like(x, float("nan"))
+    launch({"op": "softmax", "shape": (R, L), "in": (0,), "out": (1,)}, [x, y])
+    ref = OK.softmax_f64(X)
+    got = y.cpu().numpy()
+    big = ref >= 1e-30
+    assert np.all(np.abs(got[big] - ref[big]) <= TOL * ref[big])
+    assert np.all(np.abs(got[~big]) <= 1e-37)
+
+
+# -------------------------------------------------------------------- voxel
+def run_voxel(P, nx=512, ny=512, fp=(-51.2, -51.2, 5.0)):
+    n = len(P)
+    p = dev(P.reshape(-1)) if n else torch.zeros(4, device=DEV)
+    G = nx * ny
+    vi = torch.full((max(n, 1),), 7, dtype=torch.int32, device=DEV)
+    vc = torch.full((G,), 7, dtype=torch.int32, device=DEV)
+    vz = torch.full((G,), 7.0, device=DEV)
+    vf = torch.full((G,), 7, dtype=torch.int32, device=DEV)
+    launch({"op": "voxel", "shape": (n, nx, ny), "in": (0,), "out": (1, 2, 3, 4), "fparam": fp},
+           [p, vi, vc, vz, vf])
+    return vi.cpu().numpy()[:n], vc.cpu().numpy(), vz.cpu().numpy(), vf.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [1000, 120_000, 1])
+def test_voxel_bit_exact(n):
+    r = rng(n)
+    P = np.concatenate([r.normal(0, 20, (n, 3)), r.uniform(0, 1, (n, 1))], axis=1).astype(np.float32)
+    got = run_voxel(P)
+    want = OK.voxel_scatter(P)
+    for g, w in zip(got, want):
+        assert np.array_equal(np.asarray(g).view(np.uint32), np.asarray(w).view(np.uint32))
+
+
+def test_voxel_boundaries_and_empty():
+    P = np.array([[-51.2, 0.1, 1.0, 0], [51.2, 0.1, 2.0, 0], [-51.2001, 0.1, 3, 0],
+                  [51.19, 51.19, -4.0, 0], [np.nan, 0, 0, 0], [0.1, 0.1, -0.0, 0],
+                  [0.1, 0.1, 0.0, 0], [0.1, 0.15, -7.0, 0], [np.inf, 1, 1, 0]], np.float32)
+    got = run_voxel(P)
+    want = OK.voxel_scatter(P)
+    for g, w in zip(got, want):
+        assert np.array_equal(np.asarray(g).view(np.uint32), np.asarray(w).view(np.uint32))
+    vi, vc, vz, vf = run_voxel(np.zeros((0, 4), np.float32))
+    assert vc.sum() == 0 and np.all(vf == -1) and np.all(np.isneginf(vz))
+
+
+def test_voxel_small_grid_ragged():
+    r = rng(3)
+    P = np.concatenate([r.normal(0, 1, (5000, 3)), r.uniform(0, 1, (5000, 1))], 1).astype(np.float32)
+    fp = (-1.4, -1.0, 5.0)
+    got = run_voxel(P, 7, 5, fp)
+    want = OK.voxel_scatter(P, 7, 5, np.float32(fp[0]), np.float32(fp[1]), np.float32(fp[2]))
+    for g, w in zip(got, want):
+        assert np.array_equal(np.asarray(g).view(np.uint32), np.asarray(w).view(np.uint32))
+
+
+def test_kernel_launch_rejects_bad_descriptors():
+    a = torch.zeros(16, device=DEV)
+    with pytest.raises(capi.UgError):
+        capi.kernel_launch({"op": "gemm", "shape": (4, 4, 0), "in": (0, 0), "out": (0,)},
+                           [a.data_ptr()])
+    with pytest.raises(capi.UgError):
+        capi.kernel_launch({"op": "rowsum", "shape": (4, 4), "in": (0,), "out": (3,)},
+                           [a.data_ptr()])
+    u = capi.kernel_util({"op": "gemm", "shape": (4096, 4096, 4096), "in": (0, 1), "out": (2,)})
+    assert u == 1.0
+    u = capi.kernel_util({"op": "rowsum", "shape": (8, 64), "in": (0,), "out": (1,)})
+    assert 0 < u < 0.1
