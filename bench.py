@@ -1,0 +1,402 @@
+"""Benchmark: deadline-miss ratio and p99 chain latency of urgency-gated
+launching vs plain FIFO launching on one MI355X, plus the roofline fraction
+of the dominant kernel and the CPU oracle baseline.
+
+Workload: 11 synthetic chains (2-6 tasks, 50-300 FP32 kernels per task:
+GEMM, 3x3 conv, bias+ReLU, row softmax, row sum, voxel scatter), periods
+33-500 ms, 40 % of chains with half-period deadlines, 15 ms arrival jitter.
+One step = one second of frame arrivals, processed end to end (urgency
+estimation, binding, delayed and batched launching, kernels, completion).
+The same arrival sequence is run once under the urgency gate and once under
+FIFO launch.  Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MS = 1_000_000
+PEAK_FP32_MFMA = 157.3e12
+PEAK_HBM = 8.0e12
+METRIC = "deadline-miss ratio & p99 chain latency vs FIFO launch; kernel % of roofline"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed one-second windows per policy")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed one-second windows")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--f-a", type=float, default=1.0, help="arrival-rate factor")
+    ap.add_argument("--f-d", type=float, default=1.0, help="deadline factor")
+    ap.add_argument("--roofline-reps", type=int, default=20)
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fifo", action="store_true")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the per-kernel roofline leg (plus a 1 GiB device copy of known "
+                         "size, the scale for HBM byte counters)")
+    return ap.parse_args()
+
+
+# ----------------------------------------------------------------------------
+def run_policy(g, dw, arrivals, torch):
+    from paper_2509_12207_amd import runner
+    g.start()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    comps, _ = runner.run(g, dw, arrivals, timeout_s=120.0)
+    g.drain(120.0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    m = g.metrics()
+    st = g.stats()
+    g.stop()
+    return comps, m, st, t1 - t0
+
+
+def summarise(m, st, wall, n_frames):
+    return {
+        "miss_ratio_pct": round(100.0 * m["miss_ratio"], 3),
+        "p50_ms": round(m["p50_ns"] / 1e6, 3),
+        "p99_ms": round(m["p99_ns"] / 1e6, 3),
+        "max_ms": round(m["max_ns"] / 1e6, 3),
+        "mean_ms": round(m["mean_ns"] / 1e6, 3),
+        "frames": int(m["frames"]),
+        "missed": int(m["missed"]),
+        "frames_per_s": round(n_frames / wall, 2),
+        "launches": int(st["launches"]),
+        "holds": int(st["holds"]),
+        "batches": int(st["batches"]),
+        "instants": int(st["instants"]),
+        "gate_decide_us_per_instant": round(st["decide_ns"] / max(1, st["instants"]) / 1e3, 3),
+        "launch_us_per_launch": round(st["launch_ns"] / max(1, st["launches"]) / 1e3, 3),
+    }
+
+
+# ----------------------------------------------------------------------------
+ROOF_SHAPES = {
+    # op: (shape, algorithmic flops, algorithmic bytes, bound)
+    "gemm": ((4096, 4096, 4096), 2 * 4096 ** 3, 4 * 3 * 4096 ** 2, "mfma"),
+    "conv3x3": ((1, 256, 256, 256), 18 * 256 ** 2 * 256 ** 2, 4 * (2 * 256 ** 3 + 9 * 256 ** 2), "mfma"),
+    "bias_relu": ((16384, 16384, 0), 2 * 16384 ** 2, 8 * 16384 ** 2 + 4 * 16384, "hbm"),
+    "rowsum": ((16384, 16384), 16384 ** 2, 4 * 16384 ** 2 + 4 * 16384, "hbm"),
+    "softmax": ((65536, 4096), 5 * 65536 * 4096, 8 * 65536 * 4096, "hbm"),
+    "voxel": ((64 << 20, 512, 512), 0, 20 * (64 << 20) + 12 * 512 * 512, "hbm"),
+}
+
+
+def measured_traffic(op):
+    """HBM bytes per launch of ``op`` at its roofline shape, from the committed
+    rocprofv3 counter summary, if the kernel source has not changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))["kernels"][op]
+        cur = hashlib.sha256(open(os.path.join(ROOT, rec["source_file"]), "rb").read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["traffic_bytes"] if cur == rec["source_sha256"] else None
+
+
+def roofline_op(op, reps, torch):
+    """Time one kernel at its roofline shape with HIP events recorded on the
+    stream the kernel is launched on; return the roofline record."""
+    from paper_2509_12207_amd import capi
+    shape, flops, nbytes, bound = ROOF_SHAPES[op]
+    dev = "cuda:0"
+    if op == "gemm":
+        M, N, K = shape
+        t = [torch.rand(M * K, device=dev), torch.rand(K * N, device=dev), torch.empty(M * N, device=dev)]
+        desc = {"op": op, "shape": shape, "in": (0, 1), "out": (2,)}
+    elif op == "conv3x3":
+        _, C, H, W = shape
+        t = [torch.rand(C * H * W, device=dev), torch.rand(C * C * 9, device=dev),
+             torch.empty(C * H * W, device=dev)]
+        desc = {"op": op, "shape": shape, "in": (0, 1), "out": (2,)}
+    elif op == "bias_relu":
+        R, C, _ = shape
+        t = [torch.rand(R * C, device=dev) - 0.5, torch.rand(C, device=dev), torch.empty(R * C, device=dev)]
+        desc = {"op": op, "shape": shape, "in": (0, 1), "out": (2,)}
+    elif op == "rowsum":
+        R, C = shape
+        t = [torch.rand(R * C, device=dev), torch.empty(R, device=dev)]
+        desc = {"op": op, "shape": shape, "in": (0,), "out": (1,)}
+    elif op == "softmax":
+        R, L = shape
+        t = [torch.rand(R * L, device=dev), torch.empty(R * L, device=dev)]
+        desc = {"op": op, "shape": shape, "in": (0,), "out": (1,)}
+    else:
+        N = shape[0]
+        G = shape[1] * shape[2]
+        t = [torch.randn(N * 4, device=dev) * 20, torch.empty(N, dtype=torch.int32, device=dev),
+             torch.empty(G, dtype=torch.int32, device=dev), torch.empty(G, device=dev),
+             torch.empty(G, dtype=torch.int32, device=dev)]
+        desc = {"op": op, "shape": shape, "in": (0,), "out": (1, 2, 3, 4),
+                "fparam": (-51.2, -51.2, 5.0)}
+    ptrs = [int(x.data_ptr()) for x in t]
+    stream = torch.cuda.Stream()
+    # a buffer larger than the 256 MB Infinity Cache, rewritten between
+    # launches of HBM-bound kernels so every launch streams from HBM
+    flush = torch.empty(512 << 20 >> 2, device=dev) if bound == "hbm" else None
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            capi.kernel_launch(desc, ptrs, stream.cuda_stream)
+        ms = []
+        for _ in range(reps):
+            if flush is not None:
+                flush.fill_(1.0)
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record(stream)
+            capi.kernel_launch(desc, ptrs, stream.cuda_stream)
+            e.record(stream)
+            ms.append((s, e))
+    torch.cuda.synchronize()
+    dur = sorted(s.elapsed_time(e) * 1e-3 for s, e in ms)
+    avg = sum(dur) / len(dur)
+    if bound == "mfma":
+        achieved, peak, unit = flops / avg / 1e12, PEAK_FP32_MFMA / 1e12, "TFLOP/s"
+    else:
+        achieved, peak, unit = nbytes / avg / 1e9, PEAK_HBM / 1e9, "GB/s"
+    del t, flush
+    torch.cuda.empty_cache()
+    return {"kernel": op, "shape": list(shape), "bound": bound, "achieved": round(achieved, 2),
+            "peak": peak, "unit": unit, "frac": round(achieved / peak, 4),
+            "avg_us": round(avg * 1e6, 2), "median_us": round(dur[len(dur) // 2] * 1e6, 2),
+            "reps": reps, "traffic": measured_traffic(op)}
+
+
+# ----------------------------------------------------------------------------
+def cpu_baseline(wl, budget_s):
+    """The oracle (numpy, as written) executing frame 0 of every chain, in
+    chain order, each for at most its deadline (or until the frame is done):
+    a frame not done within its deadline is a miss."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    from oracle import kernels as OK
+    from paper_2509_12207_amd import synth
+
+    per_chain = {}
+    kernels_done = 0
+    kernels_total = 0
+    spent = 0.0
+    for c, ch in enumerate(wl.chains):
+        bufs = {}
+        for s, b in enumerate(ch.buffers):
+            if b.role == "in":
+                bufs[s] = synth.input_array(wl.seed, c, s, b)
+            else:
+                bufs[s] = np.zeros(b.n, np.float32 if b.kind == "f32" else np.int32)
+        limit = min(ch.deadline_ns / 1e9, max(0.0, budget_s - spent))
+        t0 = time.perf_counter()
+        done = True
+        n_k = sum(len(t["kernels"]) for t in ch.tasks)
+        kernels_total += n_k
+        for task in ch.tasks:
+            for k in task["kernels"]:
+                if time.perf_counter() - t0 > limit:
+                    done = False
+                    break
+                _oracle_exec(OK, k, bufs)
+                kernels_done += 1
+            if not done:
+                break
+        el = time.perf_counter() - t0
+        spent += el
+        per_chain[c] = (0 if done and el * 1e9 <= ch.deadline_ns else 1, 1)
+    miss = sum(m for m, _ in per_chain.values()) / len(per_chain)
+    return {"value": round(100.0 * miss, 3), "unit": "% frames missed (Eq. 3)", "cores": threads,
+            "kind": "oracle",
+            "sample": (f"frame 0 of each of the {len(wl.chains)} chains, each run for at most its "
+                       f"deadline; {kernels_done} of {kernels_total} kernels executed in "
+                       f"{spent:.1f} s of CPU time"),
+            "kernels_per_s": round(kernels_done / max(spent, 1e-9), 2)}
+
+
+def _oracle_exec(OK, k, bufs):
+    import numpy as np
+    op, s = k["op"], k["shape"]
+    i, o = k["in"], k["out"]
+    if op == "gemm":
+        M, N, K = s
+        bufs[o[0]][: M * N] = OK.gemm_f64(bufs[i[0]][: M * K].reshape(M, K),
+                                         bufs[i[1]][: K * N].reshape(K, N)).astype(np.float32).ravel()
+    elif op == "bias_relu":
+        R, C, ax = s
+        y = OK.bias_relu_f32(bufs[i[0]][: R * C].reshape(R, C), bufs[i[1]][: (C if ax == 0 else R)], ax)
+        bufs[o[0]][: R * C] = y.ravel()
+    elif op == "conv3x3":
+        n, C, H, W = s
+        y = OK.conv3x3_f64(bufs[i[0]][: n * C * H * W].reshape(n, C, H, W),
+                           bufs[i[1]][: C * C * 9].reshape(C, C, 3, 3))
+        bufs[o[0]][: n * C * H * W] = y.astype(np.float32).ravel()
+    elif op == "rowsum":
+        R, C = s
+        bufs[o[0]][:R] = OK.rowsum_f64(bufs[i[0]][: R * C].reshape(R, C))[0].astype(np.float32)
+    elif op == "softmax":
+        R, L = s
+        bufs[o[0]][: R * L] = OK.softmax_f64(bufs[i[0]][: R * L].reshape(R, L)).astype(np.float32).ravel()
+    elif op == "voxel":
+        N, nx, ny = s[:3]
+        fp = k["fparam"]
+        vi, vc, vz, vf = OK.voxel_scatter(bufs[i[0]][: 4 * N].reshape(N, 4), nx, ny,
+                                          np.float32(fp[0]), np.float32(fp[1]), np.float32(fp[2]))
+        bufs[o[0]][:N] = vi
+        bufs[o[1]][: nx * ny] = vc
+        bufs[o[2]][: nx * ny] = vz
+        bufs[o[3]][: nx * ny] = vf
+
+
+# ----------------------------------------------------------------------------
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by chain "
+              "with one gate per GPU, which this build does not launch", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2509_12207_amd import capi, runner, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    capi.lib()
+    if args.roofline_only:
+        kernels = [roofline_op(op, args.roofline_reps if op != "voxel" else 5, torch)
+                   for op in ROOF_SHAPES]
+        a = torch.empty(1 << 28, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernels": kernels, "copy_bytes_each_way": a.numel() * 4}), flush=True)
+        return
+    W, K = args.warmup, args.steps
+    wl = synth.config1(seed=args.seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + K))
+    warm = [(c, f, t) for c, f, t in wl.arrivals if t < W * 1e9]
+    timed = [(c, f, t - W * 10 ** 9) for c, f, t in wl.arrivals if t >= W * 1e9]
+    n_kernels = sum(len(t["kernels"]) for ch in wl.chains for t in ch.tasks)
+    log(f"cfg1: {len(wl.chains)} chains, {n_kernels} kernels per hyper-frame set, "
+        f"{len(warm)} warm-up + {len(timed)} timed frames")
+    t = time.time()
+    dw = runner.DeviceWorkload(wl, n_sets=4)
+    log(f"device buffers {dw.nbytes() / 2**30:.2f} GiB in {time.time() - t:.1f} s")
+
+    # a1: offline profiling stage (isolated kernel times, utilisation)
+    urg = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16)
+    t = time.time()
+    runner.profile(urg, dw, warmup=2, reps=7)
+    est = runner.estimates(urg, wl)
+    log(f"profiled in {time.time() - t:.1f} s")
+    util = 0.0
+    by_op = {}
+    for c, ch in enumerate(wl.chains):
+        e_frame = 0
+        g = 0
+        for task in ch.tasks:
+            for k in task["kernels"]:
+                e = est[(c, g)][0]
+                e_frame += e
+                by_op[k["op"]] = by_op.get(k["op"], 0) + e * 1e9 / ch.period_ns
+                g += 1
+        util += e_frame / (ch.period_ns / args.f_a)
+    dominant = max(by_op, key=by_op.get)
+    log(f"isolated-kernel utilisation {util:.3f}; GPU time share by op "
+        + ", ".join(f"{k} {v / sum(by_op.values()):.2f}" for k, v in sorted(by_op.items(), key=lambda x: -x[1])))
+
+    # TH_urgent: run the warm-up windows with delayed launching off and
+    # calibration sampling on, take the 95th percentile (Sec. 4.4.3)
+    urg.set_flags(capi.F_BIND | capi.F_BATCH | capi.F_CALIBRATE)
+    urg.set_threshold(0)
+    run_policy(urg, dw, warm, torch)
+    th = urg.calibration_threshold(95)
+    urg.set_threshold(th)
+    urg.set_flags(capi.F_BIND | capi.F_DELAY | capi.F_BATCH)
+    log(f"TH_urgent calibrated: slack {th / 1e6:.3f} ms")
+
+    # timed: urgency gate
+    comps_u, m_u, st_u, wall_u = run_policy(urg, dw, timed, torch)
+    urg_sum = summarise(m_u, st_u, wall_u, len(timed))
+    log("urgency:", json.dumps(urg_sum))
+    collisions = urg.stats()["collisions"]
+    urg_sum["collisions"] = int(collisions)
+
+    fifo_sum = None
+    if not args.no_fifo:
+        fifo = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16)
+        for (c, k), (e, u) in est.items():
+            fifo.set_estimate(c, k, e, u)
+        run_policy(fifo, dw, warm[: len(warm) // 2], torch)     # warm the FIFO streams
+        comps_f, m_f, st_f, wall_f = run_policy(fifo, dw, timed, torch)
+        fifo_sum = summarise(m_f, st_f, wall_f, len(timed))
+        log("fifo:", json.dumps(fifo_sum))
+        fifo.close()
+    urg.close()
+    del dw
+    torch.cuda.empty_cache()
+
+    # roofline of every kernel at its saturating shape; the dominant one is
+    # reported as `roofline`
+    kernels = []
+    for op in ROOF_SHAPES:
+        r = roofline_op(op, args.roofline_reps if op != "voxel" else 5, torch)
+        kernels.append(r)
+        log("roofline:", json.dumps(r))
+    roof = next(r for r in kernels if r["kernel"] == dominant)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t = time.time()
+        cpu = cpu_baseline(wl, args.cpu_budget_s)
+        log(f"cpu baseline in {time.time() - t:.1f} s: {cpu}")
+
+    value = urg_sum["miss_ratio_pct"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "% frames missed (Eq. 3), urgency gate",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(wall_u * 1000.0 / K, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "11 chains x 2-6 tasks x 50-300 fp32 kernels (GEMM M,N,K 256..4096, "
+                               "conv3x3 C 32..256 H=W 32..256, softmax, row sum, voxel scatter "
+                               "30k-120k pts), periods 33-500 ms, deadlines 0.5-1.0 x period, "
+                               "urgency gate vs FIFO",
+                   "seed": args.seed, "f_a": args.f_a, "f_d": args.f_d, "window_s": K,
+                   "frames": len(timed), "kernels_per_round": n_kernels,
+                   "isolated_utilisation": round(util, 3), "th_urgent_slack_ms": round(th / 1e6, 3)},
+        "urgency": urg_sum,
+        "fifo": fifo_sum,
+        "miss_ratio_fifo_pct": fifo_sum["miss_ratio_pct"] if fifo_sum else None,
+        "p99_ms": {"urgency": urg_sum["p99_ms"], "fifo": fifo_sum["p99_ms"] if fifo_sum else None},
+        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
+        | {"kernel": roof["kernel"], "shape": roof["shape"], "avg_us": roof["avg_us"]},
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,99 @@
+"""Summarise a rocprofv3 CSV output directory into a short markdown report.
+
+    python -m paper_2509_12207_amd.profsum <rocprof dir> --kernel <regex> \
+        --last N [--skip S] [--title T] [--command C] [--pmc] > summary.md
+
+Reports the top kernels by total time (the --stats view: calls, total, mean)
+and, for the kernel matching --kernel, the mean duration of its last N
+dispatches excluding the final S ... i.e. the dispatches of a timed leg that
+runs after everything else (e.g. the roofline leg of bench.py).  With --pmc
+the counter columns (FETCH_SIZE, WRITE_SIZE, ...) of those same dispatches
+are averaged too.
+"""
+
+import argparse
+import csv
+import glob
+import os
+import re
+import sys
+
+
+def _rows(d, pattern):
+    out = []
+    for path in sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True)):
+        with open(path, newline="") as fh:
+            out.extend(csv.DictReader(fh))
+    return out
+
+
+def _dur(r):
+    return int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("dir")
+    ap.add_argument("--kernel", required=True, help="regex selecting the timed kernel")
+    ap.add_argument("--last", type=int, default=20)
+    ap.add_argument("--skip", type=int, default=0, help="dispatches to drop from the end")
+    ap.add_argument("--title", default="rocprofv3 summary")
+    ap.add_argument("--command", default="")
+    ap.add_argument("--top", type=int, default=12)
+    ap.add_argument("--pmc", action="store_true", help="counter collection output")
+    a = ap.parse_args(argv)
+
+    pat = re.compile(a.kernel)
+    if a.pmc:
+        rows = _rows(a.dir, "*counter_collection.csv")
+        sel = [r for r in rows if pat.search(r.get("Kernel_Name", ""))]
+        by_disp = {}
+        for r in sel:
+            by_disp.setdefault(r["Dispatch_Id"], {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        disp = [by_disp[k] for k in sorted(by_disp, key=int)]
+        tail = disp[len(disp) - a.last - a.skip: len(disp) - a.skip] if a.skip else disp[-a.last:]
+        print(f"# {a.title}\n")
+        if a.command:
+            print(f"Command:\n\n```\n{a.command}\n```\n")
+        print(f"Kernel regex `{a.kernel}`: {len(disp)} dispatches with counters; "
+              f"mean over the last {len(tail)} (skipping {a.skip} at the end):\n")
+        names = sorted({n for d in tail for n in d})
+        print("| counter | mean per dispatch |\n|---|---|")
+        for n in names:
+            vals = [d[n] for d in tail if n in d]
+            print(f"| {n} | {sum(vals) / len(vals):.1f} |")
+        return 0
+
+    rows = _rows(a.dir, "*kernel_trace.csv")
+    if not rows:
+        print(f"no kernel_trace.csv under {a.dir}", file=sys.stderr)
+        return 1
+    tot = {}
+    for r in rows:
+        k = r["Kernel_Name"]
+        n, s = tot.get(k, (0, 0))
+        tot[k] = (n + 1, s + _dur(r))
+    grand = sum(s for _, s in tot.values())
+    print(f"# {a.title}\n")
+    if a.command:
+        print(f"Command:\n\n```\n{a.command}\n```\n")
+    print(f"{len(rows)} dispatches, {grand / 1e6:.1f} ms of kernel time.\n")
+    print("| kernel | calls | total ms | mean us | share |\n|---|---|---|---|---|")
+    for k, (n, s) in sorted(tot.items(), key=lambda kv: -kv[1][1])[: a.top]:
+        short = k if len(k) < 110 else k[:107] + "..."
+        print(f"| `{short}` | {n} | {s / 1e6:.2f} | {s / n / 1e3:.2f} | {s / grand:.3f} |")
+    sel = sorted((r for r in rows if pat.search(r["Kernel_Name"])), key=lambda r: int(r["Start_Timestamp"]))
+    tail = sel[len(sel) - a.last - a.skip: len(sel) - a.skip] if a.skip else sel[-a.last:]
+    if tail:
+        d = [_dur(r) for r in tail]
+        g = tail[-1]
+        grid = "x".join(g.get(f"Grid_Size_{c}", "?") for c in "XYZ")
+        wg = "x".join(g.get(f"Workgroup_Size_{c}", "?") for c in "XYZ")
+        print(f"\nTimed leg: kernel regex `{a.kernel}`, last {len(tail)} dispatches "
+              f"(grid {grid}, workgroup {wg}): mean {sum(d) / len(d) / 1e3:.2f} us, "
+              f"min {min(d) / 1e3:.2f} us, max {max(d) / 1e3:.2f} us.")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
