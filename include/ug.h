@@ -225,7 +225,8 @@ ug_status ug_create(const ug_config* cfg, void** out);
  * streams and events.  Buffers of unfinished frames are left untouched. */
 void ug_destroy(void* ctx);
 
-/* Message of the last error on ctx (static storage of the context). */
+/* Message of the last error on ctx (storage of the context); with ctx NULL,
+ * the message of the last failed ug_create in the process. */
 const char* ug_last_error(void* ctx);
 
 /* Registers a chain: a period (informational), an end-to-end deadline and

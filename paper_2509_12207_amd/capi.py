@@ -247,7 +247,7 @@ class Gate:
         h = C.c_void_p()
         st = L.ug_create(C.byref(cfg), C.byref(h))
         if st != OK:
-            raise UgError(st, "ug_create")
+            raise UgError(st, "ug_create: " + L.ug_last_error(None).decode())
         self.h = h
         self._keep = []
 

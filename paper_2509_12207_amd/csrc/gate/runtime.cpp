@@ -98,8 +98,16 @@ ug_status fail(Ctx* c, ug_status s, const std::string& msg) {
   return s;
 }
 
+// Message of the last failure of a call that has no context yet (ug_create).
+std::mutex g_create_mu;
+std::string g_create_error;
+
 ug_status hip_fail(Ctx* c, hipError_t e, const char* what) {
   std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (!c) {
+    std::lock_guard<std::mutex> lk(g_create_mu);
+    g_create_error = m;
+  }
   if (c) {
     c->device_error.store(1);
     c->device_msg = m;
@@ -450,7 +458,9 @@ void ug_destroy(void* ctx) {
 
 const char* ug_last_error(void* ctx) {
   Ctx* c = static_cast<Ctx*>(ctx);
-  return c ? c->last_error.c_str() : "null context";
+  if (c) return c->last_error.c_str();
+  std::lock_guard<std::mutex> lk(g_create_mu);
+  return g_create_error.c_str();
 }
 
 ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,

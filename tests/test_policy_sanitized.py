@@ -1,0 +1,113 @@
+"""The C++ policy core built for the host with AddressSanitizer and
+UndefinedBehaviorSanitizer (g++, no HIP), driven through recorded instants of
+the oracle's simulations: no sanitizer report, and every decision equal to
+the oracle's."""
+
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import des
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2509_12207_amd", "csrc")
+MS, US = 1_000_000, 1_000
+NAMES = {4: "COMPLETE", 5: "TSTART", 6: "BIND", 7: "HOLD", 8: "EVREC", 9: "LAUNCH"}
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    d = tmp_path_factory.mktemp("san")
+    exe = d / "policy_replay"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(ROOT, "tests", "native", "policy_replay_main.cpp"),
+           os.path.join(CSRC, "gate", "policy.cpp"), "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return exe
+
+
+def _tuple(line):
+    f = line.split()
+    ty, c, fr, task, k, a, b, t = (int(x) for x in f)
+    n = NAMES[ty]
+    if n == "COMPLETE":
+        return (n, c, fr, t)
+    if n == "TSTART":
+        return (n, c, fr, task)
+    if n == "HOLD":
+        return (n, c, fr, k)
+    if n in ("BIND", "EVREC"):
+        return (n, c, fr, task, a, b)
+    return (n, c, fr, k, a, b)
+
+
+def _encode(chains, cfg, instants):
+    c = {"policy": "urgency", "bind": True, "delay": True, "batch": True, "calibrate": False,
+         "delta_eval_ns": 500_000, "delay_poll_ns": 1_000_000, "th_slack_ns": 0,
+         "util_exempt": 0.1, "lanes": [1, 2, 1]}
+    c.update(cfg)
+    lines = [" ".join(str(x) for x in ["cfg", 1 if c["policy"] == "urgency" else 0, int(c["bind"]),
+                                       int(c["delay"]), int(c["batch"]), int(c["calibrate"]),
+                                       c["delta_eval_ns"], c["delay_poll_ns"], c["th_slack_ns"],
+                                       c["util_exempt"], len(c["lanes"]), *c["lanes"]])]
+    for ch in chains:
+        lines.append(f"chain {ch['deadline_ns']} {len(ch['tasks'])}")
+        for t in ch["tasks"]:
+            ks = " ".join(f"{e} {u!r}" for e, u in zip(t["est_ns"], t["util"]))
+            lines.append(f"task {t['cpu_ns']} {len(t['est_ns'])} {ks}")
+    for t, arr, evs, _ in instants:
+        lines.append(f"instant {t} {len(arr)} {len(evs)}")
+        lines += [f"a {a} {b} {c_}" for a, b, c_ in arr]
+        lines += [f"e {a} {b} {j} {k} {s}" for a, b, j, k, s in evs]
+    return "\n".join(lines) + "\n"
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_sanitized_policy_matches_oracle(driver, seed):
+    r = np.random.default_rng(900 + seed)
+    chains, arrivals = [], []
+    for ci in range(int(r.integers(2, 6))):
+        tasks = []
+        for _ in range(int(r.integers(1, 4))):
+            n = int(r.integers(1, 9))
+            tasks.append({"cpu_ns": int(r.integers(0, 3)) * 150 * US,
+                          "est_ns": [int(r.integers(20, 400)) * US for _ in range(n)],
+                          "util": [float(r.choice([0.05, 0.1, 0.5, 1.0])) for _ in range(n)]})
+        period = int(r.integers(3, 12)) * MS
+        chains.append({"deadline_ns": int(period * r.choice([0.5, 1.0])), "tasks": tasks})
+        phase = int(r.integers(0, period))
+        for f in range(int(r.integers(2, 6))):
+            arrivals.append((ci, f, phase + f * period + int(r.integers(0, 500)) * US))
+    noise = {}
+
+    def dur(c, f, g):
+        if (c, f, g) not in noise:
+            est = [e for t in chains[c]["tasks"] for e in t["est_ns"]]
+            noise[(c, f, g)] = max(1, int(est[g] * r.uniform(0.5, 1.6)))
+        return noise[(c, f, g)]
+
+    for cfg in ({"th_slack_ns": 3 * MS}, {"th_slack_ns": 3 * MS, "delay_poll_ns": 0},
+                {"th_slack_ns": 0, "lanes": [2, 8, 8], "calibrate": True, "delay": False},
+                {"policy": "fifo"}):
+        res = des.simulate(chains, cfg, arrivals, dur)
+        text = _encode(chains, cfg, res["instants"])
+        p = subprocess.run([str(driver)], input=text, capture_output=True, text=True)
+        assert p.returncode == 0, p.stdout[-2000:] + p.stderr[-4000:]
+        assert "ERROR: AddressSanitizer" not in p.stderr and "runtime error" not in p.stderr
+        lines = p.stdout.splitlines()
+        i = 0
+        for t, _, _, dec in res["instants"]:
+            head = lines[i].split()
+            assert head[0] == "instant" and int(head[1]) == t
+            n = int(head[2])
+            got = [_tuple(l) for l in lines[i + 1: i + 1 + n]]
+            assert got == list(dec), (cfg, t)
+            i += 1 + n
+        if cfg.get("calibrate"):
+            assert lines[i] == f"samples {len(res['gate'].samples)}"
