@@ -204,9 +204,11 @@ typedef struct {
 
 /* ------------------------------------------------------------------------ */
 
-/* Fills *cfg with the paper's defaults: URGENCY with BIND|DELAY|BATCH,
- * Delta_eval 0.5 ms, 1 ms sleep step, U exemption 0.1, device 0, 3 levels
- * with lanes {1, 2, 1}, no truly-urgent threshold, spinning gate thread. */
+/* Fills *cfg with the defaults: URGENCY with BIND|DELAY|BATCH, Delta_eval
+ * 0.5 ms, 1 ms sleep step, U exemption 0.1 (the paper's values), device 0,
+ * 2 levels with lanes {2, 6} (the reserved level and one shared level: all
+ * streams have the same hardware priority, so further levels only split
+ * lanes), no truly-urgent threshold, spinning gate thread. */
 void ug_config_default(ug_config* cfg);
 
 /* CLOCK_MONOTONIC in ns: the clock of every time argument. */
@@ -333,9 +335,9 @@ ug_status ug_replay_instant(void* ctx, int64_t t, const ug_record* inputs,
 ug_status ug_kernel_launch(const ug_kernel* k, void* const* buffers,
                            uint32_t n_buffers, void* hip_stream);
 
-/* Static utilisation of a kernel's launch on `device`: the fraction of the
- * device's workgroup slots its grid occupies, min(1, WGs / (CUs x resident
- * WGs per CU)). */
+/* Static utilisation of a kernel's launch on `device` (U_k of Sec. 4.1): the
+ * fraction of the device's compute units its grid occupies,
+ * min(1, workgroups / CUs). */
 ug_status ug_kernel_util(const ug_kernel* k, int32_t device, float* util);
 
 #ifdef __cplusplus

@@ -120,7 +120,7 @@ DEFAULT_CFG = {
     "delay_poll_ns": 1_000_000, # 1 ms sleep loop (Sec. 4.4.4); 0 = re-check every instant
     "util_exempt": 0.1,         # kernels below this utilisation are never delayed
     "th_slack_ns": 0,           # TH_urgent as a slack; <= 0 means +infinity
-    "lanes": [1, 2, 1],         # streams per level; len = number of levels
+    "lanes": [2, 6],            # streams per level; len = number of levels
     "calibrate": False,
 }
 

@@ -37,7 +37,7 @@ struct PolicyConfig {
   int64_t delay_poll_ns = 1000000;
   float util_exempt = 0.1f;
   int64_t th_slack_ns = 0;
-  std::vector<int32_t> lanes{1, 2, 1};
+  std::vector<int32_t> lanes{2, 6};
 };
 
 struct ChainSpec {

@@ -365,10 +365,9 @@ void ug_config_default(ug_config* cfg) {
   cfg->delta_eval_ns = 500000;
   cfg->delay_poll_ns = 1000000;
   cfg->util_exempt = 0.1f;
-  cfg->n_levels = 3;
-  cfg->lanes[0] = 1;
-  cfg->lanes[1] = 2;
-  cfg->lanes[2] = 1;
+  cfg->n_levels = 2;
+  cfg->lanes[0] = 2;
+  cfg->lanes[1] = 6;
   cfg->th_slack_ns = 0;
   cfg->idle_sleep_ns = 0;
   cfg->queue_capacity = 4096;
@@ -853,16 +852,13 @@ ug_status ug_kernel_util(const ug_kernel* k, int32_t device, float* util) {
   if (ug::validate_kernel(*k, 16)) return UG_EINVAL;
   ug::OpPlan p = ug::plan_kernel(*k);
   if (!p.func) return UG_EINVAL;
-  int cus = 0, per_cu = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      cus <= 0)
     return UG_EDEVICE;
-  const int threads = static_cast<int>(p.block.x * p.block.y * p.block.z);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p.func, threads, p.lds) != hipSuccess ||
-      per_cu <= 0)
-    return UG_EDEVICE;
+  // fraction of the device's compute units the launch occupies
   const double wgs = static_cast<double>(p.grid.x) * p.grid.y * p.grid.z;
-  const double slots = static_cast<double>(cus) * per_cu;
-  *util = static_cast<float>(std::min(1.0, wgs / slots));
+  *util = static_cast<float>(std::min(1.0, wgs / static_cast<double>(cus)));
   return UG_OK;
 }
 

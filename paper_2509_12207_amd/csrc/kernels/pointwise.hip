@@ -18,25 +18,41 @@ __device__ __forceinline__ float relu_add(float x, float b) {
 }
 
 // axis 0: b[C] per column; axis 1: b[R] per row.  Vector path: C % 4 == 0.
-template <int AXIS>
+// Each thread keeps UNROLL independent float4 loads in flight (consecutive
+// lanes on consecutive 16-byte words); the row/column of a float4 comes from
+// a 32-bit division when the tensor has fewer than 2^32 float4 (always in
+// practice), avoiding 64-bit division in the stream.
+constexpr int UNROLL = 4;
+
+template <int AXIS, typename I>
+__device__ __forceinline__ float4 bias_relu4(const float4 x, const float* __restrict__ b, I i,
+                                             I c4) {
+  if (AXIS == 0) {
+    const float4 bb = reinterpret_cast<const float4*>(b)[i % c4];
+    return make_float4(relu_add(x.x, bb.x), relu_add(x.y, bb.y), relu_add(x.z, bb.z),
+                       relu_add(x.w, bb.w));
+  }
+  const float bb = b[i / c4];
+  return make_float4(relu_add(x.x, bb), relu_add(x.y, bb), relu_add(x.z, bb), relu_add(x.w, bb));
+}
+
+template <int AXIS, typename I>
 __global__ __launch_bounds__(256) void bias_relu_vec(const float4* __restrict__ X,
                                                      const float* __restrict__ b,
-                                                     float4* __restrict__ Y, int64_t R,
-                                                     int64_t C4) {
-  const int64_t n = R * C4;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float4 x = X[i];
-    float4 y;
-    if (AXIS == 0) {
-      const float4 bb = reinterpret_cast<const float4*>(b)[i % C4];
-      y = make_float4(relu_add(x.x, bb.x), relu_add(x.y, bb.y), relu_add(x.z, bb.z),
-                      relu_add(x.w, bb.w));
-    } else {
-      const float bb = b[i / C4];
-      y = make_float4(relu_add(x.x, bb), relu_add(x.y, bb), relu_add(x.z, bb), relu_add(x.w, bb));
+                                                     float4* __restrict__ Y, I n, I c4) {
+  const I stride = (I)gridDim.x * 256 * UNROLL;
+  for (I base = (I)blockIdx.x * 256 * UNROLL + threadIdx.x; base < n; base += stride) {
+    float4 x[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const I i = base + (I)u * 256;
+      if (i < n) x[u] = X[i];
     }
-    Y[i] = y;
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const I i = base + (I)u * 256;
+      if (i < n) Y[i] = bias_relu4<AXIS>(x[u], b, i, c4);
+    }
   }
 }
 
@@ -93,11 +109,23 @@ __global__ __launch_bounds__(256) void rowsum_block(const float* __restrict__ Z,
   const float* z = Z + row * C;
   float s = 0.f;
   if ((C & 3) == 0 && ((reinterpret_cast<uintptr_t>(z) & 15) == 0)) {
+    // four independent loads in flight per lane, summed in a fixed order
     const float4* z4 = reinterpret_cast<const float4*>(z);
-    for (int64_t j = threadIdx.x; j < C / 4; j += 256) {
-      const float4 v = z4[j];
-      s += (v.x + v.y) + (v.z + v.w);
+    const int64_t c4 = C / 4;
+    float a[4] = {0.f, 0.f, 0.f, 0.f};
+    int64_t j = threadIdx.x;
+    for (; j + 768 < c4; j += 1024) {
+      float4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = z4[j + 256 * u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] += (v[u].x + v[u].y) + (v[u].z + v[u].w);
     }
+    for (; j < c4; j += 256) {
+      const float4 v = z4[j];
+      a[0] += (v.x + v.y) + (v.z + v.w);
+    }
+    s = (a[0] + a[1]) + (a[2] + a[3]);
   } else {
     for (int64_t j = threadIdx.x; j < C; j += 256) s += z[j];
   }
@@ -213,14 +241,18 @@ static constexpr int64_t kStreamGridCap = 256 * 32;
 
 OpPlan bias_relu_f32_plan(int64_t R, int64_t C, int axis, bool vec) {
   OpPlan p;
-  if (vec)
-    p.func = axis == 0 ? reinterpret_cast<const void*>(&bias_relu_vec<0>)
-                       : reinterpret_cast<const void*>(&bias_relu_vec<1>);
+  const bool narrow = vec && R * (C / 4) < (int64_t(1) << 32);
+  if (vec && narrow)
+    p.func = axis == 0 ? reinterpret_cast<const void*>(&bias_relu_vec<0, uint32_t>)
+                       : reinterpret_cast<const void*>(&bias_relu_vec<1, uint32_t>);
+  else if (vec)
+    p.func = axis == 0 ? reinterpret_cast<const void*>(&bias_relu_vec<0, int64_t>)
+                       : reinterpret_cast<const void*>(&bias_relu_vec<1, int64_t>);
   else
     p.func = axis == 0 ? reinterpret_cast<const void*>(&bias_relu_scalar<0>)
                        : reinterpret_cast<const void*>(&bias_relu_scalar<1>);
   const int64_t work = vec ? R * (C / 4) : R * C;
-  p.grid = dim3(grid_for(work, 256, kStreamGridCap));
+  p.grid = dim3(grid_for(work, vec ? 256 * UNROLL : 256, kStreamGridCap));
   p.block = dim3(256);
   return p;
 }
@@ -229,15 +261,20 @@ hipError_t bias_relu_f32_launch(const float* X, const float* b, float* Y, int64_
                                 int axis, hipStream_t s) {
   const bool vec = (C % 4 == 0) && aligned16(X) && aligned16(Y) && (axis == 1 || aligned16(b));
   OpPlan p = bias_relu_f32_plan(R, C, axis, vec);
-  if (vec) {
+  const int64_t n4 = R * (C / 4), c4 = C / 4;
+  const float4* x4 = reinterpret_cast<const float4*>(X);
+  float4* y4 = reinterpret_cast<float4*>(Y);
+  if (vec && n4 < (int64_t(1) << 32)) {
+    const uint32_t n = (uint32_t)n4, c = (uint32_t)c4;
     if (axis == 0)
-      hipLaunchKernelGGL(bias_relu_vec<0>, p.grid, p.block, 0, s,
-                         reinterpret_cast<const float4*>(X), b, reinterpret_cast<float4*>(Y), R,
-                         C / 4);
+      hipLaunchKernelGGL((bias_relu_vec<0, uint32_t>), p.grid, p.block, 0, s, x4, b, y4, n, c);
     else
-      hipLaunchKernelGGL(bias_relu_vec<1>, p.grid, p.block, 0, s,
-                         reinterpret_cast<const float4*>(X), b, reinterpret_cast<float4*>(Y), R,
-                         C / 4);
+      hipLaunchKernelGGL((bias_relu_vec<1, uint32_t>), p.grid, p.block, 0, s, x4, b, y4, n, c);
+  } else if (vec) {
+    if (axis == 0)
+      hipLaunchKernelGGL((bias_relu_vec<0, int64_t>), p.grid, p.block, 0, s, x4, b, y4, n4, c4);
+    else
+      hipLaunchKernelGGL((bias_relu_vec<1, int64_t>), p.grid, p.block, 0, s, x4, b, y4, n4, c4);
   } else {
     if (axis == 0)
       hipLaunchKernelGGL(bias_relu_scalar<0>, p.grid, p.block, 0, s, X, b, Y, R, C);

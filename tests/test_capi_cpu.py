@@ -142,7 +142,7 @@ def _flags(cfg):
 
 
 def _gate_for(cfg):
-    lanes = cfg.get("lanes", [1, 2, 1])
+    lanes = cfg.get("lanes", [2, 6])
     return capi.Gate(policy=cfg.get("policy", "urgency"), device=-1, lanes=lanes,
                      flags=_flags(cfg), delta_eval_ns=cfg.get("delta_eval_ns", 500_000),
                      delay_poll_ns=cfg.get("delay_poll_ns", 1_000_000),

@@ -244,4 +244,6 @@ def test_kernel_launch_rejects_bad_descriptors():
     u = capi.kernel_util({"op": "gemm", "shape": (4096, 4096, 4096), "in": (0, 1), "out": (2,)})
     assert u == 1.0
     u = capi.kernel_util({"op": "rowsum", "shape": (8, 64), "in": (0,), "out": (1,)})
-    assert 0 < u < 0.1
+    assert u == 2 / 256          # 2 workgroups of 256 CUs
+    u = capi.kernel_util({"op": "gemm", "shape": (256, 256, 256), "in": (0, 1), "out": (2,)})
+    assert u == 64 / 256         # 32 x 32 tiles

@@ -50,7 +50,7 @@ def _tuple(line):
 def _encode(chains, cfg, instants):
     c = {"policy": "urgency", "bind": True, "delay": True, "batch": True, "calibrate": False,
          "delta_eval_ns": 500_000, "delay_poll_ns": 1_000_000, "th_slack_ns": 0,
-         "util_exempt": 0.1, "lanes": [1, 2, 1]}
+         "util_exempt": 0.1, "lanes": [2, 6]}
     c.update(cfg)
     lines = [" ".join(str(x) for x in ["cfg", 1 if c["policy"] == "urgency" else 0, int(c["bind"]),
                                        int(c["delay"]), int(c["batch"]), int(c["calibrate"]),
