@@ -172,7 +172,7 @@ def roofline_op(op, reps, torch):
     return {"kernel": op, "shape": list(shape), "bound": bound, "achieved": round(achieved, 2),
             "peak": peak, "unit": unit, "frac": round(achieved / peak, 4),
             "avg_us": round(avg * 1e6, 2), "median_us": round(dur[len(dur) // 2] * 1e6, 2),
-            "reps": reps, "traffic": measured_traffic(op)}
+            "reps": reps, "flops": flops, "bytes": nbytes, "traffic": measured_traffic(op)}
 
 
 # ----------------------------------------------------------------------------

@@ -9,6 +9,15 @@ dispatches excluding the final S ... i.e. the dispatches of a timed leg that
 runs after everything else (e.g. the roofline leg of bench.py).  With --pmc
 the counter columns (FETCH_SIZE, WRITE_SIZE, ...) of those same dispatches
 are averaged too.
+
+    python -m paper_2509_12207_amd.profsum --traffic <FETCH_SIZE dir> \
+        <WRITE_SIZE dir> <roofline-only json> > profiles/traffic.json
+
+builds the per-kernel HBM traffic table that bench.py reports: for every
+kernel of the roofline leg, FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of
+its timed launches, each scaled to bytes by what the same counter reads for
+the leg's 1 GiB device-to-device copy, next to the kernel's algorithmic bytes
+and the hash of its source file (a changed source invalidates the entry).
 """
 
 import argparse
@@ -31,7 +40,75 @@ def _dur(r):
     return int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
 
 
+# roofline-leg op -> (kernel-name regex, dispatches per launch, source file)
+TRAFFIC_KERNELS = {
+    "gemm": (r"gemm_f32_kernel<2, 2, 2, 2, 1, true>", 1,
+             "paper_2509_12207_amd/csrc/kernels/gemm_f32.hip"),
+    "conv3x3": (r"conv3x3_f32_kernel<2, 2, 2, 2, 1, 8, 16>", 1,
+                "paper_2509_12207_amd/csrc/kernels/conv3x3_f32.hip"),
+    "bias_relu": (r"bias_relu_vec<0", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
+    "rowsum": (r"rowsum_block", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
+    "softmax": (r"softmax_reg<4, 4>", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
+    "voxel": (r"voxel_(init|scatter|finalize)", 3, "paper_2509_12207_amd/csrc/kernels/voxel.hip"),
+}
+
+
+def _counter_per_dispatch(d, name):
+    """[(kernel name, value)] in dispatch order for counter ``name``."""
+    rows = _rows(d, "*counter_collection.csv")
+    by = {}
+    for r in rows:
+        if r["Counter_Name"] == name:
+            k = int(r["Dispatch_Id"])
+            nm, v = by.get(k, (r["Kernel_Name"], 0.0))
+            by[k] = (nm, v + float(r["Counter_Value"]))
+    return [by[k] for k in sorted(by)]
+
+
+def traffic(fetch_dir, write_dir, roof_json, root):
+    import hashlib
+    import json
+    roof = None
+    for line in open(roof_json):
+        if line.startswith("{"):
+            roof = json.loads(line)
+    recs = {r["kernel"]: r for r in roof["kernels"]}
+    fetch = _counter_per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = _counter_per_dispatch(write_dir, "WRITE_SIZE")
+    copy_kib = roof["copy_bytes_each_way"] / 1024.0
+    copies_f = [v for n, v in fetch if "copyBuffer" in n]
+    copies_w = [v for n, v in write if "copyBuffer" in n]
+    fs = copy_kib / (sum(copies_f[-3:]) / len(copies_f[-3:]))
+    ws = copy_kib / (sum(copies_w[-3:]) / len(copies_w[-3:]))
+    out = {"source": "rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, of `python3 bench.py "
+                     "--roofline-only` (the timed launches of each kernel at its roofline "
+                     "shape); scale factors from the run's 1 GiB device-to-device copy",
+           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4), "kernels": {}}
+    for op, (rx, per, src) in TRAFFIC_KERNELS.items():
+        if op not in recs:
+            continue
+        reps = recs[op]["reps"]
+        pat = re.compile(rx)
+        f = [v for n, v in fetch if pat.search(n)][-reps * per:]
+        w = [v for n, v in write if pat.search(n)][-reps * per:]
+        fk, wk = sum(f) / reps, sum(w) / reps
+        sha = hashlib.sha256(open(os.path.join(root, src), "rb").read()).hexdigest()
+        out["kernels"][op] = {
+            "kernel_regex": rx, "dispatches_per_launch": per, "launches": reps,
+            "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+            "traffic_bytes": int(round((fk * fs + wk * ws) * 1024)),
+            "algorithmic_bytes": recs[op]["bytes"], "source_file": src, "source_sha256": sha}
+    return out
+
+
 def main(argv=None):
+    if argv is None:
+        argv = sys.argv[1:]
+    if argv and argv[0] == "--traffic":
+        import json
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        print(json.dumps(traffic(argv[1], argv[2], argv[3], root), indent=1))
+        return 0
     ap = argparse.ArgumentParser()
     ap.add_argument("dir")
     ap.add_argument("--kernel", required=True, help="regex selecting the timed kernel")
