@@ -144,20 +144,26 @@ def roofline_op(op, reps, torch):
         desc = {"op": op, "shape": shape, "in": (0,), "out": (1, 2, 3, 4),
                 "fparam": (-51.2, -51.2, 5.0)}
     ptrs = [int(x.data_ptr()) for x in t]
+    need = capi.kernel_workspace(desc)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+
+    def launch(s):
+        capi.kernel_launch_ws(desc, ptrs, int(ws.data_ptr()), need, s)
+
     stream = torch.cuda.Stream()
     # a buffer larger than the 256 MB Infinity Cache, rewritten between
     # launches of HBM-bound kernels so every launch streams from HBM
     flush = torch.empty(512 << 20 >> 2, device=dev) if bound == "hbm" else None
     with torch.cuda.stream(stream):
         for _ in range(3):
-            capi.kernel_launch(desc, ptrs, stream.cuda_stream)
+            launch(stream.cuda_stream)
         ms = []
         for _ in range(reps):
             if flush is not None:
                 flush.fill_(1.0)
             s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             s.record(stream)
-            capi.kernel_launch(desc, ptrs, stream.cuda_stream)
+            launch(stream.cuda_stream)
             e.record(stream)
             ms.append((s, e))
     torch.cuda.synchronize()
@@ -167,12 +173,41 @@ def roofline_op(op, reps, torch):
         achieved, peak, unit = flops / avg / 1e12, PEAK_FP32_MFMA / 1e12, "TFLOP/s"
     else:
         achieved, peak, unit = nbytes / avg / 1e9, PEAK_HBM / 1e9, "GB/s"
-    del t, flush
+    del t, flush, ws
     torch.cuda.empty_cache()
     return {"kernel": op, "shape": list(shape), "bound": bound, "achieved": round(achieved, 2),
             "peak": peak, "unit": unit, "frac": round(achieved / peak, 4),
             "avg_us": round(avg * 1e6, 2), "median_us": round(dur[len(dur) // 2] * 1e6, 2),
             "reps": reps, "flops": flops, "bytes": nbytes, "traffic": measured_traffic(op)}
+
+
+def copy_ceiling(torch, reps=10):
+    """Practical HBM ceiling: a 1 GiB device-to-device copy (2 GiB moved),
+    timed like the HBM kernels (flush write before each launch)."""
+    dev = "cuda:0"
+    a = torch.empty(1 << 28, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    flush = torch.empty(512 << 20 >> 2, device=dev)
+    stream = torch.cuda.Stream()
+    ms = []
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            b.copy_(a)
+        for _ in range(reps):
+            flush.fill_(1.0)
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record(stream)
+            b.copy_(a)
+            e.record(stream)
+            ms.append((s, e))
+    torch.cuda.synchronize()
+    dur = [s.elapsed_time(e) * 1e-3 for s, e in ms]
+    avg = sum(dur) / len(dur)
+    del a, b, flush
+    torch.cuda.empty_cache()
+    gbs = 2 * (1 << 30) / avg / 1e9
+    return {"what": "1 GiB device-to-device copy (torch), read + write", "avg_us": round(avg * 1e6, 2),
+            "achieved": round(gbs, 1), "unit": "GB/s", "frac_of_peak": round(gbs * 1e9 / PEAK_HBM, 4)}
 
 
 # ----------------------------------------------------------------------------
@@ -358,6 +393,8 @@ def main():
         kernels.append(r)
         log("roofline:", json.dumps(r))
     roof = next(r for r in kernels if r["kernel"] == dominant)
+    ceiling = copy_ceiling(torch)
+    log("hbm copy ceiling:", json.dumps(ceiling))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -393,6 +430,7 @@ def main():
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
         | {"kernel": roof["kernel"], "shape": roof["shape"], "avg_us": roof["avg_us"]},
         "kernels": kernels,
+        "hbm_copy_ceiling": ceiling,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -42,7 +42,7 @@ typedef int32_t ug_status;
 enum {
   UG_OK = 0,
   UG_EINVAL = -1,    /* invalid argument (shape, slot, id, size, null)       */
-  UG_ENOMEM = -2,    /* host allocation failed                               */
+  UG_ENOMEM = -2,    /* host or device allocation failed                     */
   UG_EDEVICE = -3,   /* a HIP call failed; sticky for the context            */
   UG_EAGAIN = -4,    /* submission queue full; retry after polling           */
   UG_ETIMEDOUT = -5, /* ug_drain timed out                                   */
@@ -224,7 +224,8 @@ const char* ug_status_str(ug_status s);
 ug_status ug_create(const ug_config* cfg, void** out);
 
 /* Stops the gate thread (without waiting for in-flight frames), releases
- * streams and events.  Buffers of unfinished frames are left untouched. */
+ * streams, events and kernel workspaces.  Buffers of unfinished frames are
+ * left untouched. */
 void ug_destroy(void* ctx);
 
 /* Message of the last error on ctx (storage of the context); with ctx NULL,
@@ -233,8 +234,10 @@ const char* ug_last_error(void* ctx);
 
 /* Registers a chain: a period (informational), an end-to-end deadline and
  * an ordered task list (Sec. 4.1).  n_buffers is the number of buffer slots
- * each frame supplies.  Descriptors are deep-copied.  Only before ug_start.
- * Errors: UG_EINVAL (bad op/shape/slot), UG_ESTATE (already started). */
+ * each frame supplies.  Descriptors are deep-copied; the device workspace a
+ * kernel needs (ug_kernel_workspace) is allocated here, never on the launch
+ * path, and released by ug_destroy.  Only before ug_start.  Errors:
+ * UG_EINVAL (bad op/shape/slot), UG_ESTATE (already started), UG_ENOMEM. */
 ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
                             const ug_task* tasks, uint32_t n_tasks,
                             uint32_t n_buffers, uint32_t* chain_id);
@@ -334,6 +337,22 @@ ug_status ug_replay_instant(void* ctx, int64_t t, const ug_record* inputs,
  * UG_EINVAL (bad descriptor or missing buffer), UG_EDEVICE. */
 ug_status ug_kernel_launch(const ug_kernel* k, void* const* buffers,
                            uint32_t n_buffers, void* hip_stream);
+
+/* Bytes of device workspace a kernel needs beside its buffers (*bytes = 0
+ * for most kernels; the voxel scatter of large clouds bins its points
+ * through one).  A context allocates the workspace of every registered
+ * kernel in ug_chain_register (UG_ENOMEM if that fails); ug_kernel_launch
+ * takes a stream-ordered allocation per call.  Errors: UG_EINVAL. */
+ug_status ug_kernel_workspace(const ug_kernel* k, uint64_t* bytes);
+
+/* ug_kernel_launch with a caller-owned device workspace of workspace_bytes
+ * (>= ug_kernel_workspace; may be NULL when that is 0), which must stay
+ * untouched until the kernel has finished on hip_stream.  It holds no state
+ * between launches.  Errors: UG_EINVAL (also: workspace missing or too
+ * small), UG_EDEVICE. */
+ug_status ug_kernel_launch_ws(const ug_kernel* k, void* const* buffers,
+                              uint32_t n_buffers, void* workspace,
+                              uint64_t workspace_bytes, void* hip_stream);
 
 /* Static utilisation of a kernel's launch on `device` (U_k of Sec. 4.1): the
  * fraction of the device's compute units its grid occupies,

@@ -37,7 +37,7 @@ EXPORTED = [
     "ug_profile", "ug_set_threshold", "ug_set_flags", "ug_start", "ug_frame_submit",
     "ug_poll_complete", "ug_drain", "ug_stop", "ug_get_stats", "ug_trace_read",
     "ug_calibration_read", "ug_calibration_threshold", "ug_get_metrics", "ug_replay_instant",
-    "ug_kernel_launch", "ug_kernel_util",
+    "ug_kernel_launch", "ug_kernel_util", "ug_kernel_workspace", "ug_kernel_launch_ws",
 ]
 
 
@@ -147,6 +147,9 @@ def lib():
                                         C.POINTER(Record), C.c_uint32, C.POINTER(C.c_uint32)]
         L.ug_kernel_launch.argtypes = [C.POINTER(Kernel), C.POINTER(vp), C.c_uint32, vp]
         L.ug_kernel_util.argtypes = [C.POINTER(Kernel), C.c_int32, C.POINTER(C.c_float)]
+        L.ug_kernel_workspace.argtypes = [C.POINTER(Kernel), C.POINTER(C.c_uint64)]
+        L.ug_kernel_launch_ws.argtypes = [C.POINTER(Kernel), C.POINTER(vp), C.c_uint32, vp,
+                                          C.c_uint64, vp]
         for name in ("ug_create", "ug_chain_register", "ug_kernel_set_estimate",
                      "ug_kernel_get_estimate", "ug_profile", "ug_set_threshold", "ug_set_flags",
                      "ug_start", "ug_frame_submit", "ug_poll_complete", "ug_drain", "ug_stop",
@@ -206,6 +209,25 @@ def kernel_launch(k, ptrs, stream=None):
     st = lib().ug_kernel_launch(C.byref(ks), arr, len(ptrs), C.c_void_p(stream or 0))
     if st != OK:
         raise UgError(st, f"ug_kernel_launch({OP_NAMES.get(ks.op, ks.op)})")
+
+
+def kernel_workspace(k):
+    """Bytes of device workspace kernel ``k`` needs beside its buffers."""
+    n = C.c_uint64()
+    st = lib().ug_kernel_workspace(C.byref(kernel_struct(k)), C.byref(n))
+    if st != OK:
+        raise UgError(st, "ug_kernel_workspace")
+    return int(n.value)
+
+
+def kernel_launch_ws(k, ptrs, ws_ptr, ws_bytes, stream=None):
+    """Launch one kernel with a caller-owned device workspace."""
+    ks = kernel_struct(k)
+    arr = pointer_array(ptrs)
+    st = lib().ug_kernel_launch_ws(C.byref(ks), arr, len(ptrs), C.c_void_p(ws_ptr or 0),
+                                   ws_bytes, C.c_void_p(stream or 0))
+    if st != OK:
+        raise UgError(st, f"ug_kernel_launch_ws({OP_NAMES.get(ks.op, ks.op)})")
 
 
 def kernel_util(k, device=0):

@@ -62,6 +62,11 @@ struct Ctx {
   std::vector<hipEvent_t> all_events;
   std::map<EvKey, hipEvent_t> live_events;
   std::map<ug::Key, hipStream_t> bound;
+  // device workspace of each registered kernel ([chain][kernel], null when
+  // the kernel needs none): a kernel runs for one frame at a time, so one
+  // workspace per kernel suffices
+  std::vector<std::vector<void*>> ws;
+  std::vector<std::vector<size_t>> ws_bytes;
   std::map<ug::Key, Frame> frames;                      // arrived, not completed
   std::vector<Frame> pending;                           // submitted, not arrived
 
@@ -200,7 +205,8 @@ bool execute(Ctx* c, const std::vector<ug_record>& dec) {
         const ug::ChainSpec& ch = c->policy.chains()[d.chain];
         const Frame& fr = c->frames.at(key);
         const int64_t t0 = mono_ns();
-        hipError_t err = ug::launch_kernel(ch.kernels[d.kernel], fr.buffers.data(), c->bound.at(key));
+        hipError_t err = ug::launch_kernel(ch.kernels[d.kernel], fr.buffers.data(), c->bound.at(key),
+                                           c->ws[d.chain][d.kernel], c->ws_bytes[d.chain][d.kernel]);
         c->st_launch_ns += mono_ns() - t0;
         if (err != hipSuccess) {
           hip_fail(c, err, "kernel launch");
@@ -451,6 +457,9 @@ void ug_destroy(void* ctx) {
       (void)hipStreamDestroy(s);
     }
     for (hipEvent_t e : c->all_events) (void)hipEventDestroy(e);
+    for (auto& v : c->ws)
+      for (void* p : v)
+        if (p) (void)hipFree(p);
   }
   delete c;
 }
@@ -499,6 +508,21 @@ ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
     spec.task_end.push_back(static_cast<int32_t>(spec.kernels.size()));
     spec.cpu.push_back(t.cpu_ns);
   }
+  std::vector<void*> ws(spec.kernels.size(), nullptr);
+  std::vector<size_t> wsb(spec.kernels.size(), 0);
+  for (size_t k = 0; k < spec.kernels.size(); ++k) {
+    wsb[k] = ug::workspace_bytes(spec.kernels[k]);
+    if (wsb[k] == 0 || !c->has_device) continue;
+    (void)hipSetDevice(c->cfg.device);
+    if (hipMalloc(&ws[k], wsb[k]) != hipSuccess) {
+      (void)hipGetLastError();
+      for (void* p : ws)
+        if (p) (void)hipFree(p);
+      return fail(c, UG_ENOMEM, "kernel workspace allocation failed");
+    }
+  }
+  c->ws.push_back(std::move(ws));
+  c->ws_bytes.push_back(std::move(wsb));
   const uint32_t id = c->policy.add_chain(std::move(spec));
   c->next_frame.push_back(0);
   if (chain_id) *chain_id = id;
@@ -561,12 +585,16 @@ ug_status ug_profile(void* ctx, uint32_t chain, void* const* buffers, uint32_t n
       ch.est[k] = it->second;
       continue;
     }
-    for (uint32_t w = 0; w < warmup; ++w)
-      if ((e = ug::launch_kernel(kd, buffers, s)) != hipSuccess) st = hip_fail(c, e, "profile launch");
+    void* w = c->ws[chain][k];
+    const size_t wb = c->ws_bytes[chain][k];
+    for (uint32_t i = 0; i < warmup; ++i)
+      if ((e = ug::launch_kernel(kd, buffers, s, w, wb)) != hipSuccess)
+        st = hip_fail(c, e, "profile launch");
     std::vector<float> ms(reps);
     for (uint32_t r = 0; r < reps && st == UG_OK; ++r) {
       (void)hipEventRecord(ev[2 * r], s);
-      if ((e = ug::launch_kernel(kd, buffers, s)) != hipSuccess) st = hip_fail(c, e, "profile launch");
+      if ((e = ug::launch_kernel(kd, buffers, s, w, wb)) != hipSuccess)
+        st = hip_fail(c, e, "profile launch");
       (void)hipEventRecord(ev[2 * r + 1], s);
     }
     if (st != UG_OK) break;
@@ -843,7 +871,39 @@ ug_status ug_kernel_launch(const ug_kernel* k, void* const* buffers, uint32_t n_
       const int32_t s = slots[a][i];
       if (s >= 0 && (static_cast<uint32_t>(s) >= n_buffers || !buffers[s])) return UG_EINVAL;
     }
-  hipError_t e = ug::launch_kernel(*k, buffers, static_cast<hipStream_t>(hip_stream));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t wb = ug::workspace_bytes(*k);
+  void* w = nullptr;
+  // stream-ordered workspace: served from the device's memory pool after
+  // the first call, released once the kernel has finished
+  if (wb && hipMallocAsync(&w, wb, st) != hipSuccess) return UG_ENOMEM;
+  hipError_t e = ug::launch_kernel(*k, buffers, st, w, wb);
+  if (w) (void)hipFreeAsync(w, st);
+  return e == hipSuccess ? UG_OK : UG_EDEVICE;
+}
+
+ug_status ug_kernel_workspace(const ug_kernel* k, uint64_t* bytes) {
+  if (!k || !bytes) return UG_EINVAL;
+  if (ug::validate_kernel(*k, 16)) return UG_EINVAL;
+  *bytes = ug::workspace_bytes(*k);
+  return UG_OK;
+}
+
+ug_status ug_kernel_launch_ws(const ug_kernel* k, void* const* buffers, uint32_t n_buffers,
+                              void* workspace, uint64_t workspace_bytes, void* hip_stream) {
+  if (!k || !buffers) return UG_EINVAL;
+  if (ug::validate_kernel(*k, n_buffers)) return UG_EINVAL;
+  const int32_t* slots[2] = {k->in, k->out};
+  const int counts[2] = {3, 4};
+  for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < counts[a]; ++i) {
+      const int32_t s = slots[a][i];
+      if (s >= 0 && (static_cast<uint32_t>(s) >= n_buffers || !buffers[s])) return UG_EINVAL;
+    }
+  const size_t need = ug::workspace_bytes(*k);
+  if (need && (!workspace || workspace_bytes < need)) return UG_EINVAL;
+  hipError_t e = ug::launch_kernel(*k, buffers, static_cast<hipStream_t>(hip_stream), workspace,
+                                   static_cast<size_t>(workspace_bytes));
   return e == hipSuccess ? UG_OK : UG_EDEVICE;
 }
 

@@ -55,7 +55,13 @@ const char* validate_kernel(const ug_kernel& k, uint32_t nb) {
   }
 }
 
-hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st) {
+size_t workspace_bytes(const ug_kernel& k) {
+  if (k.op == UG_OP_VOXEL_F32) return voxel_f32_workspace(k.shape[0], (int)k.shape[1], (int)k.shape[2]);
+  return 0;
+}
+
+hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, void* ws,
+                         size_t ws_bytes) {
   const int64_t* s = k.shape;
   auto F = [&](int32_t slot) { return static_cast<float*>(b[slot]); };
   auto I = [&](int32_t slot) { return static_cast<int*>(b[slot]); };
@@ -73,7 +79,7 @@ hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st) {
     case UG_OP_VOXEL_F32:
       return voxel_f32_launch(F(k.in[0]), I(k.out[0]), I(k.out[1]), F(k.out[2]), I(k.out[3]),
                               s[0], (int)s[1], (int)s[2], k.fparam[0], k.fparam[1], k.fparam[2],
-                              st);
+                              ws, ws_bytes, st);
     default:
       return hipErrorInvalidValue;
   }
@@ -93,7 +99,7 @@ OpPlan plan_kernel(const ug_kernel& k) {
     case UG_OP_SOFTMAX_F32:
       return softmax_f32_plan(s[0], s[1], s[1] % 4 == 0);
     case UG_OP_VOXEL_F32:
-      return voxel_f32_plan(s[0]);
+      return voxel_f32_plan(s[0], (int)s[1], (int)s[2]);
     default:
       return OpPlan{};
   }

@@ -36,17 +36,27 @@ hipError_t rowsum_f32_launch(const float* Z, float* r, int64_t R, int64_t C, hip
 OpPlan softmax_f32_plan(int64_t R, int64_t L, bool vec);
 hipError_t softmax_f32_launch(const float* X, float* Y, int64_t R, int64_t L, hipStream_t s);
 
-OpPlan voxel_f32_plan(int64_t N);
+// Device workspace the voxel scatter needs (0: none); the launch fails with
+// hipErrorInvalidValue if it needs one and `ws` is missing or too small.
+size_t voxel_f32_workspace(int64_t N, int nx, int ny);
+OpPlan voxel_f32_plan(int64_t N, int nx, int ny);
 hipError_t voxel_f32_launch(const float* pts, int* vidx, int* count, float* zmax, int* first,
                             int64_t N, int nx, int ny, float xmin, float ymin, float scale,
-                            hipStream_t s);
+                            void* ws, size_t ws_bytes, hipStream_t s);
 
 // Checks a descriptor against n_buffers slots.  Returns nullptr if valid,
 // else a static message.
 const char* validate_kernel(const ug_kernel& k, uint32_t n_buffers);
 
-// Launches the operation with buffers[slot] pointers.  Asynchronous.
-hipError_t launch_kernel(const ug_kernel& k, void* const* buffers, hipStream_t s);
+// Bytes of device workspace the operation needs beside its buffers (0 for
+// most operations).  The workspace holds no state between launches.
+size_t workspace_bytes(const ug_kernel& k);
+
+// Launches the operation with buffers[slot] pointers and a workspace of
+// ws_bytes >= workspace_bytes(k) (may be null when none is needed).
+// Asynchronous.
+hipError_t launch_kernel(const ug_kernel& k, void* const* buffers, hipStream_t s,
+                         void* ws = nullptr, size_t ws_bytes = 0);
 
 // Main-kernel launch shape of an operation.
 OpPlan plan_kernel(const ug_kernel& k);

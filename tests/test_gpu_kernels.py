@@ -233,6 +233,109 @@ def test_voxel_small_grid_ragged():
         assert np.array_equal(np.asarray(g).view(np.uint32), np.asarray(w).view(np.uint32))
 
 
+def _same(got, want):
+    for g, w in zip(got, want):
+        assert np.array_equal(np.asarray(g).view(np.uint32), np.asarray(w).view(np.uint32))
+
+
+def _cloud(seed, n, sigma=20.0):
+    r = rng(seed)
+    return np.concatenate([r.normal(0, sigma, (n, 3)), r.uniform(0, 1, (n, 1))],
+                          axis=1).astype(np.float32)
+
+
+# Large clouds take the binned path (tiles of 4096 cells, chunks of 8192
+# points, segments of 65536 records): sizes that are ragged in all three.
+@pytest.mark.parametrize("n", [1 << 20, 1_100_003])
+def test_voxel_binned_bit_exact(n):
+    P = _cloud(n, n)
+    assert capi.kernel_workspace({"op": "voxel", "shape": (n, 512, 512), "in": (0,),
+                                  "out": (1, 2, 3, 4)}) > 0
+    _same(run_voxel(P), OK.voxel_scatter(P))
+
+
+def test_voxel_binned_hot_cell_many_segments():
+    # 1.2 M points in one cell (19 segments of one tile), signed zeros and
+    # -inf among its z values, a few points elsewhere and outside
+    n = 1_200_000
+    r = rng(11)
+    P = np.zeros((n, 4), np.float32)
+    P[:, 0], P[:, 1] = 0.05, 0.05
+    P[:, 2] = r.uniform(-5, 0, n).astype(np.float32)
+    P[7, 2], P[8, 2], P[9, 2] = -0.0, 0.0, -np.inf
+    P[::1000, 0] = r.uniform(-60, 60, len(P[::1000])).astype(np.float32)
+    P[5, 2] = np.float32(-1e-30)
+    got = run_voxel(P)
+    want = OK.voxel_scatter(P)
+    _same(got, want)
+    assert got[1].max() > 1_000_000
+
+
+def test_voxel_binned_odd_grid_and_workspace_api():
+    # G = 30000 cells: 8 tiles, the last one partial; explicit workspace
+    n, nx, ny = (1 << 20) + 5, 300, 100
+    fp = (-30.0, -10.0, 5.0)
+    r = rng(5)
+    P = np.concatenate([r.uniform(-31, 31, (n, 1)), r.uniform(-11, 11, (n, 1)),
+                        r.normal(0, 3, (n, 1)), r.uniform(0, 1, (n, 1))], 1).astype(np.float32)
+    desc = {"op": "voxel", "shape": (n, nx, ny), "in": (0,), "out": (1, 2, 3, 4), "fparam": fp}
+    need = capi.kernel_workspace(desc)
+    assert need > 0
+    p = dev(P.reshape(-1))
+    G = nx * ny
+    outs = [torch.full((n,), 7, dtype=torch.int32, device=DEV),
+            torch.full((G,), 7, dtype=torch.int32, device=DEV), torch.full((G,), 7.0, device=DEV),
+            torch.full((G,), 7, dtype=torch.int32, device=DEV)]
+    ptrs = [int(t.data_ptr()) for t in [p] + outs]
+    small = torch.empty(need // 2, dtype=torch.uint8, device=DEV)
+    with pytest.raises(capi.UgError) as e:
+        capi.kernel_launch_ws(desc, ptrs, int(small.data_ptr()), small.numel())
+    assert e.value.status == capi.EINVAL
+    ws = torch.full((need,), 0xA5, dtype=torch.uint8, device=DEV)   # stale contents
+    for _ in range(2):                                               # reuse holds no state
+        capi.kernel_launch_ws(desc, ptrs, int(ws.data_ptr()), need)
+        torch.cuda.synchronize()
+        got = [t.cpu().numpy() for t in outs]
+        _same(got, OK.voxel_scatter(P, nx, ny, np.float32(fp[0]), np.float32(fp[1]),
+                                    np.float32(fp[2])))
+
+
+def test_voxel_large_grid_takes_direct_path():
+    # 4096 x 4096 cells exceed the binned path's 1024 tiles: no workspace
+    n, nx, ny = 1 << 20, 4096, 4096
+    fp = (-51.2, -51.2, 40.0)
+    desc = {"op": "voxel", "shape": (n, nx, ny), "in": (0,), "out": (1, 2, 3, 4), "fparam": fp}
+    assert capi.kernel_workspace(desc) == 0
+    P = _cloud(2, n)
+    _same(run_voxel(P, nx, ny, fp),
+          OK.voxel_scatter(P, nx, ny, np.float32(fp[0]), np.float32(fp[1]), np.float32(fp[2])))
+
+
+def test_voxel_binned_through_the_gate():
+    # a registered kernel gets its workspace at registration
+    n = 1_050_000
+    P = _cloud(9, n)
+    desc = {"op": "voxel", "shape": (n, 512, 512), "in": (0,), "out": (1, 2, 3, 4),
+            "fparam": (-51.2, -51.2, 5.0)}
+    G = 512 * 512
+    p = dev(P.reshape(-1))
+    outs = [torch.full((n,), 7, dtype=torch.int32, device=DEV),
+            torch.full((G,), 7, dtype=torch.int32, device=DEV), torch.full((G,), 7.0, device=DEV),
+            torch.full((G,), 7, dtype=torch.int32, device=DEV)]
+    ptrs = [int(t.data_ptr()) for t in [p] + outs]
+    g = capi.Gate("urgency")
+    g.register_chain(100_000_000, 100_000_000, [{"kernels": [desc]}], 5)
+    g.profile(0, ptrs, warmup=1, reps=2)
+    g.start()
+    g.submit(0, -1, ptrs)
+    g.drain(30.0)
+    comps = g.poll()
+    g.stop()
+    g.close()
+    assert len(comps) == 1
+    _same([t.cpu().numpy() for t in outs], OK.voxel_scatter(P))
+
+
 def test_kernel_launch_rejects_bad_descriptors():
     a = torch.zeros(16, device=DEV)
     with pytest.raises(capi.UgError):
