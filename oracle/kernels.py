@@ -17,6 +17,9 @@ reordering:
 * voxel scatter   bird's-eye-view pillar binning of a point cloud (LiDAR
   3D detection front end): per-point cell index and per-cell count, highest
   z and first point index.
+* FP8 matrix product  C = A B with A, B in the OCP FP8 E4M3 format and an
+  FP32 result (the best-effort overload load: large low-precision products
+  that share the GPU with the deadline chains).
 
 Floating point results are computed in float64 from the float32 inputs.  The
 two operations whose results must be bit-exact take their decisions in
@@ -218,3 +221,50 @@ def voxel_scatter(pts, nx=VOXEL_NX, ny=VOXEL_NY, xmin=VOXEL_XMIN,
     np.minimum.at(first, cells, sel.astype(np.int64))
     first = np.where(count > 0, first, -1).astype(np.int32)
     return vidx, count, zmax, first
+
+
+# --------------------------------------------------------------------------
+# FP8 (OCP E4M3) matrix product with an FP32 result
+# --------------------------------------------------------------------------
+def e4m3_decode(codes):
+    """Value of each OCP FP8 E4M3 code as float64.
+
+    Bit 7 is the sign, bits 6..3 the exponent field e (bias 7), bits 2..0 the
+    mantissa m.  e = 0 encodes subnormals (m / 8) * 2^-6; otherwise the value
+    is (1 + m / 8) * 2^(e - 7).  The format has no infinities: exponent and
+    mantissa all ones (0x7f, 0xff) is NaN, so the largest finite magnitude is
+    0x7e = 1.75 * 2^8 = 448.
+    """
+    c = np.asarray(codes, dtype=np.uint8).astype(np.int64)
+    sign = np.where(c & 0x80, -1.0, 1.0)
+    e = (c >> 3) & 0xF
+    m = (c & 0x7).astype(np.float64)
+    mag = np.where(e == 0, (m / 8.0) * 2.0 ** -6, (1.0 + m / 8.0) * np.exp2(e - 7.0))
+    mag = np.where((e == 0xF) & (c & 0x7 == 0x7), np.nan, mag)
+    return sign * mag
+
+
+def gemm_fp8_f64(A8, Bt8):
+    """C[m, n] = sum_k a(A8[m, k]) * a(Bt8[n, k]), a = e4m3_decode.
+
+    A8 is [M, K] and Bt8 is B transposed, [N, K] (both K-contiguous), as
+    uint8 codes.  A product of two E4M3 values has at most 8 significant bits
+    and is exact in float64, as are sums of up to 2^40 of them at these
+    magnitudes, so this is the exact product for the sizes used here.
+    """
+    A = e4m3_decode(A8)
+    B = e4m3_decode(Bt8)
+    assert A.ndim == 2 and B.ndim == 2 and A.shape[1] == B.shape[1]
+    return A @ B.T
+
+
+def gemm_fp8_abs_f64(A8, Bt8):
+    """|A| |B| for the componentwise error scale of the FP8 product."""
+    return np.abs(e4m3_decode(A8)) @ np.abs(e4m3_decode(Bt8)).T
+
+
+def gemm_fp8_entry_f64(A8, Bt8, m, n):
+    """One entry C[m, n] and its scale (|A| |B|)[m, n] for sampled checks."""
+    a = e4m3_decode(A8[m])
+    b = e4m3_decode(Bt8[n])
+    return float(np.dot(a, b)), float(np.dot(np.abs(a), np.abs(b)))

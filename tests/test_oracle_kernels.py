@@ -238,3 +238,53 @@ def test_voxel_signed_zero_max():
     v2 = K.voxel_cell_f32(pts[2:])[0]
     assert zmax[v0] == 0 and not np.signbit(zmax[v0])
     assert zmax[v2] == 0 and np.signbit(zmax[v2])
+
+
+# ------------------------------------------------------------- FP8 (E4M3)
+def test_e4m3_published_values():
+    # OCP 8-bit floating point specification, E4M3 table: max normal 448,
+    # min normal 2^-6, min subnormal 2^-9, NaN at S.1111.111, no infinities
+    d = K.e4m3_decode(np.array([0x7E, 0x08, 0x01, 0x00, 0x80, 0x38, 0xC0, 0x7F, 0xFF, 0x78],
+                               np.uint8))
+    assert d[0] == 448.0 and d[1] == 2.0 ** -6 and d[2] == 2.0 ** -9
+    assert d[3] == 0.0 and not np.signbit(d[3]) and d[4] == 0.0 and np.signbit(d[4])
+    assert d[5] == 1.0 and d[6] == -2.0 and np.isnan(d[7]) and np.isnan(d[8])
+    assert d[9] == 256.0                        # 0x78: exponent field 15, mantissa 0
+    assert np.all(np.isfinite(np.delete(K.e4m3_decode(np.arange(256)), [0x7F, 0xFF])))
+
+
+def test_e4m3_all_codes_match_torch_float8():
+    codes = np.arange(256, dtype=np.uint8)
+    ref = torch.from_numpy(codes).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    got = K.e4m3_decode(codes)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.array_equal(got[ok], ref[ok])
+    assert np.array_equal(np.signbit(got[ok]), np.signbit(ref[ok]))
+    # monotone on the positive finite codes
+    assert np.all(np.diff(got[:0x7F]) > 0)
+
+
+def test_gemm_fp8_integer_codes_exact():
+    # codes of 0, +-1, +-2: the product is an integer matrix product
+    r = np.random.default_rng(4)
+    table = np.array([0x00, 0x38, 0xB8, 0x40, 0xC0], np.uint8)
+    value = np.array([0, 1, -1, 2, -2], np.int64)
+    ia, ib = r.integers(0, 5, (9, 37)), r.integers(0, 5, (11, 37))
+    C = K.gemm_fp8_f64(table[ia], table[ib])
+    assert np.array_equal(C, (value[ia] @ value[ib].T).astype(np.float64))
+
+
+def test_gemm_fp8_matches_torch_float8_path():
+    r = np.random.default_rng(5)
+    A8 = r.integers(0, 256, (33, 70), dtype=np.uint8)
+    B8 = r.integers(0, 256, (21, 70), dtype=np.uint8)
+    A8[A8 & 0x7F == 0x7F] = 0x30                # no NaN codes
+    B8[B8 & 0x7F == 0x7F] = 0xB1
+    a = torch.from_numpy(A8).view(torch.float8_e4m3fn).to(torch.float64)
+    b = torch.from_numpy(B8).view(torch.float8_e4m3fn).to(torch.float64)
+    ref = (a @ b.T).numpy()
+    got = K.gemm_fp8_f64(A8, B8)
+    assert np.allclose(got, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+    v, sc = K.gemm_fp8_entry_f64(A8, B8, 5, 7)
+    assert v == got[5, 7] and sc == K.gemm_fp8_abs_f64(A8, B8)[5, 7]
