@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fifo", action="store_true")
+    ap.add_argument("--sweep", choices=sorted(SWEEPS),
+                    help="instead of the benchmark line: one JSON line per variant of a "
+                         "sweep (urgency gate vs FIFO on the same arrivals)")
+    ap.add_argument("--seeds", type=int, default=1, help="workload seeds per sweep point")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the per-kernel roofline leg (plus a 1 GiB device copy of known "
                          "size, the scale for HBM byte counters)")
@@ -49,6 +53,76 @@ def parse():
 
 
 # ----------------------------------------------------------------------------
+# Sweeps (the paper's ablation structure, Sec. 6): each point runs the FIFO
+# baseline and urgency-gate variants on the same arrivals; every urgency
+# variant calibrates TH_urgent on the warm-up windows with its own settings.
+FULL = 1 | 2 | 4          # UG_F_BIND | UG_F_DELAY | UG_F_BATCH
+SWEEPS = {
+    # mechanism ablation (Sec. 6.4): each mechanism alone, all, none
+    "ablation": [{"name": "none", "flags": 0}, {"name": "bind", "flags": 1 | 4},
+                 {"name": "delay", "flags": 2 | 4}, {"name": "batch", "flags": 4},
+                 {"name": "bind+delay", "flags": 1 | 2}, {"name": "full", "flags": FULL}],
+    # batching window Delta_eval (Sec. 4.4.5)
+    "delta": [{"name": f"delta_{d}ms", "cfg": {"delta_eval_ns": int(d * MS)}}
+              for d in (0.1, 0.25, 0.5, 1.0, 2.0)],
+    # stream pool: lanes per level (level 0 reserved)
+    "lanes": [{"name": "lanes_" + "_".join(map(str, l)), "cfg": {"lanes": l}}
+              for l in ([1, 1], [2, 2], [2, 6], [4, 4], [2, 3, 3], [1, 2, 5])],
+    # TH_urgent percentile
+    "threshold": [{"name": f"th_p{p}", "pct": p} for p in (99, 95, 90, 85)],
+    # arrival-rate and deadline factors (Sec. 6.2): FIFO and the full gate
+    "fa": [{"name": f"fa_{f}", "f_a": f} for f in (0.7, 0.9, 1.0, 1.1, 1.3)],
+    "fd": [{"name": f"fd_{f}", "f_d": f} for f in (0.7, 1.0, 1.5)],
+    # run-to-run and seed spread at the default point
+    "seeds": [{"name": "default"}],
+}
+
+
+def sweep_main(args, torch, capi, runner, synth):
+    W, K = args.warmup, args.steps
+    groups = {}
+    for v in SWEEPS[args.sweep]:
+        groups.setdefault((v.get("f_a", args.f_a), v.get("f_d", args.f_d)), []).append(v)
+    for seed in range(args.seed, args.seed + args.seeds):
+        for (fa, fd), variants in groups.items():
+            wl = synth.config1(seed=seed, f_a=fa, f_d=fd, window_s=float(W + K))
+            warm = [(c, f, t) for c, f, t in wl.arrivals if t < W * 1e9]
+            timed = [(c, f, t - W * 10 ** 9) for c, f, t in wl.arrivals if t >= W * 1e9]
+            dw = runner.DeviceWorkload(wl, n_sets=4)
+            prof = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16)
+            runner.profile(prof, dw, warmup=2, reps=5)
+            point = {"seed": seed, "f_a": fa, "f_d": fd, "frames": len(timed), "window_s": K}
+            fifo = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16)
+            runner.copy_estimates(prof, fifo, wl)
+            run_policy(fifo, dw, warm[: len(warm) // 2], torch)
+            _, m, st, wall = run_policy(fifo, dw, timed, torch)
+            fifo_sum = summarise(m, st, wall, len(timed))
+            fifo.close()
+            for v in variants:
+                g = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16,
+                                     **v.get("cfg", {}))
+                runner.copy_estimates(prof, g, wl)
+                flags = v.get("flags", FULL)
+                g.set_flags((flags & ~capi.F_DELAY) | capi.F_CALIBRATE)
+                g.set_threshold(0)
+                run_policy(g, dw, warm, torch)
+                th = g.calibration_threshold(v.get("pct", 95))
+                g.set_threshold(th)
+                g.set_flags(flags)
+                _, m, st, wall = run_policy(g, dw, timed, torch)
+                u = summarise(m, st, wall, len(timed))
+                g.close()
+                print(json.dumps({"sweep": args.sweep, "variant": v["name"], **point,
+                                  "th_urgent_slack_ms": round(th / 1e6, 3), "urgency": u,
+                                  "fifo": fifo_sum}), flush=True)
+                log(f"{args.sweep} seed {seed} {v['name']}: urgency {u['miss_ratio_pct']} % "
+                    f"p99 {u['p99_ms']} ms | fifo {fifo_sum['miss_ratio_pct']} % "
+                    f"p99 {fifo_sum['p99_ms']} ms")
+            prof.close()
+            del dw
+            torch.cuda.empty_cache()
+
+
 def run_policy(g, dw, arrivals, torch):
     from paper_2509_12207_amd import runner
     g.start()
@@ -311,6 +385,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     capi.lib()
+    if args.sweep:
+        sweep_main(args, torch, capi, runner, synth)
+        return
     if args.roofline_only:
         kernels = [roofline_op(op, args.roofline_reps if op != "voxel" else 5, torch)
                    for op in ROOF_SHAPES]

@@ -89,6 +89,12 @@ enum {
  *                       likewise, inside iff 0 <= ix < nx and 0 <= iy < ny;
  *                       vidx = iy*nx + ix or -1.  Empty cells: count 0,
  *                       zmax -inf, first -1.  z must not be NaN.
+ *  UG_OP_GEMM_FP8       C = A B with A, B in OCP FP8 E4M3 (one byte per
+ *                       value) and an FP32 result, FP32 accumulation on the
+ *                       FP8 matrix cores.  shape {M, N, K}, K a multiple of
+ *                       16; in {A[M,K] row-major, Bt[N,K] = B transposed
+ *                       (K contiguous)}; out {C[M,N] fp32}; A and Bt 16-byte
+ *                       aligned.  The best-effort load of an overloaded GPU.
  */
 enum {
   UG_OP_GEMM_F32 = 1,
@@ -96,7 +102,8 @@ enum {
   UG_OP_CONV3X3_F32 = 3,
   UG_OP_ROWSUM_F32 = 4,
   UG_OP_SOFTMAX_F32 = 5,
-  UG_OP_VOXEL_F32 = 6
+  UG_OP_VOXEL_F32 = 6,
+  UG_OP_GEMM_FP8 = 7
 };
 
 /* One kernel of a task (a row of the paper's lookup table, Tab. "Example
@@ -233,11 +240,17 @@ void ug_destroy(void* ctx);
 const char* ug_last_error(void* ctx);
 
 /* Registers a chain: a period (informational), an end-to-end deadline and
- * an ordered task list (Sec. 4.1).  n_buffers is the number of buffer slots
+ * an ordered task list (Sec. 4.1).  deadline_ns = 0 registers a best-effort
+ * chain (background load with no deadline): it has no urgency (ranked below
+ * every deadline instance), is never truly urgent, all its kernels are
+ * subject to delayed launching whatever their utilisation, it is not sampled
+ * for TH_urgent, and its frames complete with missed = 0 and stay out of
+ * ug_get_metrics.  n_buffers is the number of buffer slots
  * each frame supplies.  Descriptors are deep-copied; the device workspace a
  * kernel needs (ug_kernel_workspace) is allocated here, never on the launch
  * path, and released by ug_destroy.  Only before ug_start.  Errors:
- * UG_EINVAL (bad op/shape/slot), UG_ESTATE (already started), UG_ENOMEM. */
+ * UG_EINVAL (bad op/shape/slot, deadline < 0), UG_ESTATE (already started),
+ * UG_ENOMEM. */
 ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
                             const ug_task* tasks, uint32_t n_tasks,
                             uint32_t n_buffers, uint32_t* chain_id);

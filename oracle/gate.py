@@ -25,7 +25,11 @@ exact rational comparison of urgencies with ties to the lower (chain, frame);
 a task binds when its first kernel is actually released; the delay rule holds
 a kernel only for a *more urgent* truly urgent instance of another chain;
 frames of one chain run each task in arrival order, one frame per task at a
-time; a CPU segment is a host-side delay before the task's kernels.
+time; a CPU segment is a host-side delay before the task's kernels.  A chain
+registered with deadline 0 is best-effort (the overload load): it has no
+urgency (ranked below every deadline instance), is never truly urgent, its
+kernels are delayable whatever their utilisation, and it is not sampled for
+TH_urgent.
 
 Decision records (tuples):
     ("COMPLETE", c, f, t_done)
@@ -55,6 +59,9 @@ class ChainSpec:
 
     def __init__(self, spec):
         self.deadline = int(spec["deadline_ns"])
+        # deadline 0: a best-effort chain (never urgent, always delayable,
+        # ranked below every deadline instance, outside the miss ratio)
+        self.best_effort = self.deadline == 0
         self.task_first = []      # first global kernel index of each task
         self.task_end = []        # one past the last global kernel index
         self.cpu = []             # CPU-segment estimate of each task (ns)
@@ -157,6 +164,8 @@ class GateModel:
     # ------------------------------------------------------------------
     def slack(self, inst, t):
         ch = inst.chain
+        if ch.best_effort:
+            return None
         return P.slack_ns(t, inst.t_arr, ch.deadline, ch.gpu_rem[inst.i_gpu],
                           ch.cpu_rem[inst.i_cpu])
 
@@ -235,7 +244,8 @@ class GateModel:
         self.last_snapshot = dict(slack)
         # 5. sample the highest urgency among active kernels (Sec. 4.4.3)
         if self.cfg["calibrate"]:
-            fl = [(slack[i.key], i.key, None) for i in active if i.in_flight()]
+            fl = [(slack[i.key], i.key, None) for i in active
+                  if i.in_flight() and not i.chain.best_effort]
             if fl:
                 self.samples.append(P.rank_sort(fl)[0][0])
         # 6. launch requests, most urgent first
@@ -297,7 +307,8 @@ class GateModel:
         while inst.g_next < end and not inst.waits:
             g = inst.g_next
             if (self.urgency_policy and self.cfg["delay"]
-                    and ch.util[g] >= self.u_exempt and self._blocked(inst, slack, active)):
+                    and (ch.best_effort or ch.util[g] >= self.u_exempt)
+                    and self._blocked(inst, slack, active)):
                 out.append(("HOLD", inst.c, inst.f, g))
                 poll = self.cfg["delay_poll_ns"]
                 inst.wake = t + poll if poll > 0 else None

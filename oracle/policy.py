@@ -37,7 +37,15 @@ def urgency(slack):
 
 
 def ul_greater(s1, s2):
-    """True iff UL(s1) > UL(s2), exactly (Eq. (2))."""
+    """True iff UL(s1) > UL(s2), exactly (Eq. (2)).
+
+    A slack of None marks an instance of a best-effort chain (no deadline):
+    its urgency is below every deadline instance's, late ones included.
+    """
+    if s1 is None:
+        return False
+    if s2 is None:
+        return True
     u1, u2 = urgency(s1), urgency(s2)
     if u1 is None:
         return u2 is not None
@@ -76,7 +84,7 @@ def is_truly_urgent(slack, th_slack):
     th_slack > 0; th_slack <= 0 stands for TH_urgent = +infinity, which no
     urgency exceeds.
     """
-    if th_slack <= 0:
+    if th_slack <= 0 or slack is None:
         return False
     return ul_greater(slack, th_slack)
 

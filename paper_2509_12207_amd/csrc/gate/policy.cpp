@@ -7,6 +7,9 @@ namespace ug {
 
 // ---------------------------------------------------------------- Eq. (2)
 bool ul_greater(int64_t s1, int64_t s2) {
+  // best-effort instances have no urgency: below every deadline instance
+  if (s1 == kBestEffortSlack) return false;
+  if (s2 == kBestEffortSlack) return true;
   // 1/0 is +infinity: above every finite level, not above itself.
   if (s1 == 0) return s2 != 0;
   if (s2 == 0) return false;
@@ -194,13 +197,15 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
   for (Instance* in : active) {
     const ChainSpec& ch = chains_[in->c];
     slack[{in->c, in->f}] =
-        in->t_arr + ch.deadline_ns - ch.gpu_rem[in->i_gpu] - ch.cpu_rem[in->i_cpu] - t;
+        ch.best_effort
+            ? kBestEffortSlack
+            : in->t_arr + ch.deadline_ns - ch.gpu_rem[in->i_gpu] - ch.cpu_rem[in->i_cpu] - t;
   }
   // 5. highest urgency among active kernels, for TH_urgent calibration
   if (cfg_.calibrate) {
     const Instance* top = nullptr;
     for (Instance* in : active) {
-      if (!in->in_flight()) continue;
+      if (!in->in_flight() || chains_[in->c].best_effort) continue;
       if (!top || more_urgent(slack[{in->c, in->f}], {in->c, in->f},
                               slack[{top->c, top->f}], {top->c, top->f}))
         top = in;
@@ -284,7 +289,8 @@ void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& acti
   const bool batching = gated && cfg_.batch;
   while (me.g_next < end && me.waits.empty()) {
     const int32_t g = me.g_next;
-    if (gated && cfg_.delay && ch.util[g] >= cfg_.util_exempt && blocked(me, active, slack)) {
+    if (gated && cfg_.delay && (ch.best_effort || ch.util[g] >= cfg_.util_exempt) &&
+        blocked(me, active, slack)) {
       out.push_back(rec(UG_REC_HOLD, me.c, me.f, me.task, g, 0, 0, 0));
       me.n_holds += 1;
       if (cfg_.delay_poll_ns > 0) {

@@ -20,6 +20,7 @@
 //      launching holds it.
 #pragma once
 
+#include <climits>
 #include <cstdint>
 #include <deque>
 #include <map>
@@ -40,8 +41,13 @@ struct PolicyConfig {
   std::vector<int32_t> lanes{2, 6};
 };
 
+// Slack of an instance of a best-effort chain (registered with deadline 0):
+// no urgency at all, below every deadline instance including late ones.
+constexpr int64_t kBestEffortSlack = INT64_MIN;
+
 struct ChainSpec {
   int64_t period_ns = 0, deadline_ns = 0;
+  bool best_effort = false;           // deadline 0: never urgent, always delayable
   uint32_t n_buffers = 0;
   std::vector<ug_kernel> kernels;     // all tasks, in order
   std::vector<int64_t> est;           // E_k
@@ -153,7 +159,7 @@ class Policy {
 };
 
 // Exact comparison of urgency levels UL = 1/slack (Eq. 2): true iff
-// 1/s1 > 1/s2, with 1/0 = +infinity.
+// 1/s1 > 1/s2, with 1/0 = +infinity and kBestEffortSlack below everything.
 bool ul_greater(int64_t s1, int64_t s2);
 // Strict total order: higher UL first, then lower (chain, frame).
 bool more_urgent(int64_t s1, const Key& k1, int64_t s2, const Key& k2);

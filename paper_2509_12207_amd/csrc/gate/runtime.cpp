@@ -237,13 +237,17 @@ void deliver_completions(Ctx* c) {
     out.t_arr_ns = f.t_arr;
     out.t_done_ns = f.t_done;
     out.latency_ns = f.t_done - f.t_arr;
-    out.missed = out.latency_ns > ch.deadline_ns ? 1 : 0;
+    // best-effort chains have no deadline: never missed, and outside the
+    // miss ratio and the latency percentiles
+    out.missed = (!ch.best_effort && out.latency_ns > ch.deadline_ns) ? 1 : 0;
     out.n_holds = f.n_holds;
     out.n_batches = f.n_batches;
     c->outbox.push_back(out);
-    c->latencies.push_back(out.latency_ns);
-    c->chain_done[f.c] += 1;
-    c->chain_missed[f.c] += out.missed;
+    if (!ch.best_effort) {
+      c->latencies.push_back(out.latency_ns);
+      c->chain_done[f.c] += 1;
+      c->chain_missed[f.c] += out.missed;
+    }
     c->frames.erase({f.c, f.f});
     c->bound.erase({f.c, f.f});
     c->st_completed++;
@@ -478,11 +482,12 @@ ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
   if (!c) return UG_EINVAL;
   if (sticky(c)) return UG_EDEVICE;
   if (c->started || c->finalized) return fail(c, UG_ESTATE, "chains are registered before start");
-  if (!tasks || n_tasks == 0 || deadline_ns <= 0 || period_ns < 0)
-    return fail(c, UG_EINVAL, "chain needs tasks and a positive deadline");
+  if (!tasks || n_tasks == 0 || deadline_ns < 0 || period_ns < 0)
+    return fail(c, UG_EINVAL, "chain needs tasks and a deadline >= 0");
   ug::ChainSpec spec;
   spec.period_ns = period_ns;
   spec.deadline_ns = deadline_ns;
+  spec.best_effort = deadline_ns == 0;
   spec.n_buffers = n_buffers;
     for (uint32_t j = 0; j < n_tasks; ++j) {
     const ug_task& t = tasks[j];

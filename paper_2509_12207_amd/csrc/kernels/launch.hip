@@ -50,6 +50,14 @@ const char* validate_kernel(const ug_kernel& k, uint32_t nb) {
           !slot_ok(k.out[2], nb) || !slot_ok(k.out[3], nb))
         return "voxel: needs in {pts}, out {vidx, count, zmax, first}";
       return nullptr;
+    case UG_OP_GEMM_FP8:
+      if (!pos(s[0]) || !pos(s[1]) || !pos(s[2])) return "gemm_fp8: M, N, K must be in [1, 2^31)";
+      if (s[2] % 16 != 0) return "gemm_fp8: K must be a multiple of 16";
+      if (s[0] * s[2] >= kMaxDim * 32 || s[1] * s[2] >= kMaxDim * 32 || s[0] * s[1] >= kMaxDim * 8)
+        return "gemm_fp8: operand too large";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
+        return "gemm_fp8: needs in {A, Bt}, out {C}";
+      return nullptr;
     default:
       return "unknown op";
   }
@@ -80,6 +88,13 @@ hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, voi
       return voxel_f32_launch(F(k.in[0]), I(k.out[0]), I(k.out[1]), F(k.out[2]), I(k.out[3]),
                               s[0], (int)s[1], (int)s[2], k.fparam[0], k.fparam[1], k.fparam[2],
                               ws, ws_bytes, st);
+    case UG_OP_GEMM_FP8: {
+      const auto* a = static_cast<const unsigned char*>(b[k.in[0]]);
+      const auto* bt = static_cast<const unsigned char*>(b[k.in[1]]);
+      if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(bt)) & 15)
+        return hipErrorInvalidValue;
+      return gemm_fp8_launch(a, bt, F(k.out[0]), s[0], s[1], s[2], st);
+    }
     default:
       return hipErrorInvalidValue;
   }
@@ -100,6 +115,8 @@ OpPlan plan_kernel(const ug_kernel& k) {
       return softmax_f32_plan(s[0], s[1], s[1] % 4 == 0);
     case UG_OP_VOXEL_F32:
       return voxel_f32_plan(s[0], (int)s[1], (int)s[2]);
+    case UG_OP_GEMM_FP8:
+      return gemm_fp8_plan(s[0], s[1], s[2]);
     default:
       return OpPlan{};
   }

@@ -36,6 +36,10 @@ hipError_t rowsum_f32_launch(const float* Z, float* r, int64_t R, int64_t C, hip
 OpPlan softmax_f32_plan(int64_t R, int64_t L, bool vec);
 hipError_t softmax_f32_launch(const float* X, float* Y, int64_t R, int64_t L, hipStream_t s);
 
+OpPlan gemm_fp8_plan(int64_t M, int64_t N, int64_t K);
+hipError_t gemm_fp8_launch(const unsigned char* A, const unsigned char* Bt, float* C, int64_t M,
+                           int64_t N, int64_t K, hipStream_t s);
+
 // Device workspace the voxel scatter needs (0: none); the launch fails with
 // hipErrorInvalidValue if it needs one and `ws` is missing or too small.
 size_t voxel_f32_workspace(int64_t N, int nx, int ny);

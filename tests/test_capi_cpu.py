@@ -117,8 +117,9 @@ def _random_workload(r, n_chains, n_frames):
             tasks.append({"cpu_ns": int(r.integers(0, 3)) * 150 * US,
                           "est_ns": [e for e, _ in ks], "util": [u for _, u in ks]})
         period = int(r.integers(3, 12)) * MS
-        chains.append({"deadline_ns": int(period * r.choice([0.5, 1.0])), "tasks": tasks,
-                       "period_ns": period})
+        # one chain in four is best-effort (deadline 0)
+        deadline = 0 if r.random() < 0.25 else int(period * r.choice([0.5, 1.0]))
+        chains.append({"deadline_ns": deadline, "tasks": tasks, "period_ns": period})
         phase = int(r.integers(0, period))
         for f in range(n_frames):
             arrivals.append((c, f, phase + f * period + int(r.integers(0, 500)) * US))

@@ -350,3 +350,71 @@ def test_kernel_launch_rejects_bad_descriptors():
     assert u == 2 / 256          # 2 workgroups of 256 CUs
     u = capi.kernel_util({"op": "gemm", "shape": (256, 256, 256), "in": (0, 1), "out": (2,)})
     assert u == 64 / 256         # 32 x 32 tiles
+
+
+# ----------------------------------------------------------------- FP8 GEMM
+def _fp8_codes(r, shape, lo=4, hi=9):
+    """Random finite E4M3 codes: random sign and mantissa, exponent field in
+    [lo, hi] (magnitudes 2^-3 .. 7.5 for the defaults)."""
+    s = r.integers(0, 2, shape) << 7
+    e = r.integers(lo, hi + 1, shape) << 3
+    m = r.integers(0, 8, shape)
+    return (s | e | m).astype(np.uint8)
+
+
+def run_gemm_fp8(A8, Bt8):
+    M, K = A8.shape
+    N = Bt8.shape[0]
+    a, b = dev(A8), dev(Bt8)
+    c = torch.full((M, N), float("nan"), device=DEV)
+    launch({"op": "gemm_fp8", "shape": (M, N, K), "in": (0, 1), "out": (2,)}, [a, b, c])
+    return c.cpu().numpy()
+
+
+def test_gemm_fp8_integer_codes_bit_exact():
+    # codes of 0, +-1, +-2: every partial sum is a small integer, exact in
+    # any order; two tiles by two, ragged M and N, K tail not a multiple of
+    # the 128-byte step
+    r = rng(21)
+    table = np.array([0x00, 0x38, 0xB8, 0x40, 0xC0], np.uint8)
+    M, N, K = 300, 270, 208
+    A8, B8 = table[r.integers(0, 5, (M, K))], table[r.integers(0, 5, (N, K))]
+    C = run_gemm_fp8(A8, B8)
+    assert np.array_equal(C, OK.gemm_fp8_f64(A8, B8).astype(np.float32))
+
+
+@pytest.mark.parametrize("M,N,K", [(256, 256, 128), (512, 768, 1024), (77, 513, 16),
+                                   (1, 1, 16), (1000, 300, 4096)])
+def test_gemm_fp8_parity(M, N, K):
+    r = rng(M + 3 * N + 7 * K)
+    A8, B8 = _fp8_codes(r, (M, K)), _fp8_codes(r, (N, K))
+    C = run_gemm_fp8(A8, B8)
+    ref = OK.gemm_fp8_f64(A8, B8)
+    scale = OK.gemm_fp8_abs_f64(A8, B8)
+    assert np.all(np.abs(C - ref) <= TOL * scale), np.max(np.abs(C - ref) / scale)
+
+
+def test_gemm_fp8_full_size_sampled():
+    # the 8192^3 product of the overload workload, checked on sampled entries
+    M = N = K = 8192
+    r = rng(8)
+    A8, B8 = _fp8_codes(r, (M, K)), _fp8_codes(r, (N, K))
+    C = run_gemm_fp8(A8, B8)
+    assert not np.isnan(C).any()
+    for m, n in zip(r.integers(0, M, 64), r.integers(0, N, 64)):
+        v, sc = OK.gemm_fp8_entry_f64(A8, B8, m, n)
+        assert abs(C[m, n] - v) <= TOL * sc, (m, n, C[m, n], v)
+    for m, n in [(0, 0), (M - 1, N - 1), (255, 256), (4095, 8191)]:
+        v, sc = OK.gemm_fp8_entry_f64(A8, B8, m, n)
+        assert abs(C[m, n] - v) <= TOL * sc, (m, n)
+
+
+def test_gemm_fp8_rejects_bad_k_and_alignment():
+    a = torch.zeros(4096, dtype=torch.uint8, device=DEV)
+    c = torch.zeros(64, device=DEV)
+    with pytest.raises(capi.UgError):
+        capi.kernel_launch({"op": "gemm_fp8", "shape": (8, 8, 24), "in": (0, 1), "out": (2,)},
+                           [a.data_ptr(), a.data_ptr(), c.data_ptr()])
+    with pytest.raises(capi.UgError):
+        capi.kernel_launch({"op": "gemm_fp8", "shape": (8, 8, 32), "in": (0, 1), "out": (2,)},
+                           [a.data_ptr() + 1, a.data_ptr(), c.data_ptr()])

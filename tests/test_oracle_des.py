@@ -117,6 +117,36 @@ def test_low_utilisation_kernels_are_exempt():
     assert not any(d[0] == "HOLD" for _, _, _, ds in res["instants"] for d in ds)
 
 
+def test_best_effort_kernels_are_always_delayable():
+    # the same case as the exemption test, with the low-utilisation kernel in
+    # a best-effort chain: it is held while the urgent chain runs, released
+    # at the first wake after A's completion, and takes the unreserved level
+    ch = [chain(3 * MS, [(0, [(int(1.5 * MS), 1.0)])]),
+          chain(0, [(0, [(1 * MS, 0.09)])])]
+    cfg = {"policy": "urgency", "th_slack_ns": 2 * MS}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 0)], by_est(ch))
+    holds = [(t, d[1]) for t, _, _, ds in res["instants"] for d in ds if d[0] == "HOLD"]
+    rel = [(t, d[4]) for t, _, _, ds in res["instants"] for d in ds
+           if d[0] == "LAUNCH" and d[1] == 1]
+    assert holds == [(0, 1), (1 * MS, 1)]
+    assert rel == [(2 * MS, 1)]
+    des.check_log(ch, cfg, res["instants"])
+
+
+def test_best_effort_ranks_last_and_is_not_sampled():
+    # a best-effort instance ranks below a deadline instance that is already
+    # late, and calibration samples ignore it even when it is the only one
+    # in flight
+    assert P.more_urgent(-5 * MS, (1, 0), None, (0, 0))
+    assert not P.more_urgent(None, (0, 0), -5 * MS, (1, 0))
+    assert not P.is_truly_urgent(None, 10 * MS)
+    ch = [chain(0, [(0, [(1 * MS, 1.0), (1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "th_slack_ns": 0, "calibrate": True}
+    res = des.simulate(ch, cfg, [(0, 0, 0)], by_est(ch))
+    assert res["gate"].samples == []
+    assert res["completed"] == [(0, 0, 0, 2 * MS)]
+
+
 def test_same_chain_never_blocks_itself():
     # two frames of one chain, pipelined over two tasks; the urgent older
     # frame must not hold the newer one back
