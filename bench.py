@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 
 MS = 1_000_000
 PEAK_FP32_MFMA = 157.3e12
+PEAK_FP8_MFMA = 5.0e15
 PEAK_HBM = 8.0e12
 METRIC = "deadline-miss ratio & p99 chain latency vs FIFO launch; kernel % of roofline"
 
@@ -42,6 +43,9 @@ def parse():
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fifo", action="store_true")
+    ap.add_argument("--overload", action="store_true",
+                    help="the overload workload instead: the eleven chains at a lower base "
+                         "load plus a closed-loop best-effort chain of 8192^3 FP8 products")
     ap.add_argument("--sweep", choices=sorted(SWEEPS),
                     help="instead of the benchmark line: one JSON line per variant of a "
                          "sweep (urgency gate vs FIFO on the same arrivals)")
@@ -123,12 +127,12 @@ def sweep_main(args, torch, capi, runner, synth):
             torch.cuda.empty_cache()
 
 
-def run_policy(g, dw, arrivals, torch):
+def run_policy(g, dw, arrivals, torch, be=None):
     from paper_2509_12207_amd import runner
     g.start()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    comps, _ = runner.run(g, dw, arrivals, timeout_s=120.0)
+    comps, _ = runner.run(g, dw, arrivals, timeout_s=120.0, be=be)
     g.drain(120.0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -161,6 +165,7 @@ def summarise(m, st, wall, n_frames):
 ROOF_SHAPES = {
     # op: (shape, algorithmic flops, algorithmic bytes, bound)
     "gemm": ((4096, 4096, 4096), 2 * 4096 ** 3, 4 * 3 * 4096 ** 2, "mfma"),
+    "gemm_fp8": ((8192, 8192, 8192), 2 * 8192 ** 3, (1 + 1 + 4) * 8192 ** 2, "mfma_fp8"),
     "conv3x3": ((1, 256, 256, 256), 18 * 256 ** 2 * 256 ** 2, 4 * (2 * 256 ** 3 + 9 * 256 ** 2), "mfma"),
     "bias_relu": ((16384, 16384, 0), 2 * 16384 ** 2, 8 * 16384 ** 2 + 4 * 16384, "hbm"),
     "rowsum": ((16384, 16384), 16384 ** 2, 4 * 16384 ** 2 + 4 * 16384, "hbm"),
@@ -191,6 +196,16 @@ def roofline_op(op, reps, torch):
     if op == "gemm":
         M, N, K = shape
         t = [torch.rand(M * K, device=dev), torch.rand(K * N, device=dev), torch.empty(M * N, device=dev)]
+        desc = {"op": op, "shape": shape, "in": (0, 1), "out": (2,)}
+    elif op == "gemm_fp8":
+        M, N, K = shape
+
+        def codes(n):
+            # finite E4M3 codes: sign, exponent field 4..9, mantissa
+            return ((torch.randint(0, 2, (n,), device=dev) << 7)
+                    | (torch.randint(4, 10, (n,), device=dev) << 3)
+                    | torch.randint(0, 8, (n,), device=dev)).to(torch.uint8)
+        t = [codes(M * K), codes(N * K), torch.empty(M * N, device=dev)]
         desc = {"op": op, "shape": shape, "in": (0, 1), "out": (2,)}
     elif op == "conv3x3":
         _, C, H, W = shape
@@ -243,8 +258,10 @@ def roofline_op(op, reps, torch):
     torch.cuda.synchronize()
     dur = sorted(s.elapsed_time(e) * 1e-3 for s, e in ms)
     avg = sum(dur) / len(dur)
-    if bound == "mfma":
-        achieved, peak, unit = flops / avg / 1e12, PEAK_FP32_MFMA / 1e12, "TFLOP/s"
+    if bound in ("mfma", "mfma_fp8"):
+        peak = (PEAK_FP8_MFMA if bound == "mfma_fp8" else PEAK_FP32_MFMA) / 1e12
+        achieved, unit = flops / avg / 1e12, "TFLOP/s"
+        bound = "mfma"
     else:
         achieved, peak, unit = nbytes / avg / 1e9, PEAK_HBM / 1e9, "GB/s"
     del t, flush, ws
@@ -399,11 +416,18 @@ def main():
         print(json.dumps({"kernels": kernels, "copy_bytes_each_way": a.numel() * 4}), flush=True)
         return
     W, K = args.warmup, args.steps
-    wl = synth.config1(seed=args.seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + K))
+    if args.overload:
+        wl = synth.config4(seed=args.seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + K))
+        c_be = wl.meta["be_chain"]
+        be_warm = (c_be, wl.meta["be_depth"], W * 10 ** 9)
+        be_timed = (c_be, wl.meta["be_depth"], K * 10 ** 9)
+    else:
+        wl = synth.config1(seed=args.seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + K))
+        c_be, be_warm, be_timed = None, None, None
     warm = [(c, f, t) for c, f, t in wl.arrivals if t < W * 1e9]
     timed = [(c, f, t - W * 10 ** 9) for c, f, t in wl.arrivals if t >= W * 1e9]
     n_kernels = sum(len(t["kernels"]) for ch in wl.chains for t in ch.tasks)
-    log(f"cfg1: {len(wl.chains)} chains, {n_kernels} kernels per hyper-frame set, "
+    log(f"{wl.name}: {len(wl.chains)} chains, {n_kernels} kernels per hyper-frame set, "
         f"{len(warm)} warm-up + {len(timed)} timed frames")
     t = time.time()
     dw = runner.DeviceWorkload(wl, n_sets=4)
@@ -417,7 +441,11 @@ def main():
     log(f"profiled in {time.time() - t:.1f} s")
     util = 0.0
     by_op = {}
+    be_frame_ns = 0
     for c, ch in enumerate(wl.chains):
+        if c == c_be:
+            be_frame_ns = sum(est[(c, g)][0] for g in range(len(ch.tasks[0]["kernels"])))
+            continue
         e_frame = 0
         g = 0
         for task in ch.tasks:
@@ -435,15 +463,23 @@ def main():
     # calibration sampling on, take the 95th percentile (Sec. 4.4.3)
     urg.set_flags(capi.F_BIND | capi.F_BATCH | capi.F_CALIBRATE)
     urg.set_threshold(0)
-    run_policy(urg, dw, warm, torch)
+    run_policy(urg, dw, warm, torch, be=be_warm)
     th = urg.calibration_threshold(95)
     urg.set_threshold(th)
     urg.set_flags(capi.F_BIND | capi.F_DELAY | capi.F_BATCH)
     log(f"TH_urgent calibrated: slack {th / 1e6:.3f} ms")
 
     # timed: urgency gate
-    comps_u, m_u, st_u, wall_u = run_policy(urg, dw, timed, torch)
-    urg_sum = summarise(m_u, st_u, wall_u, len(timed))
+    def be_rate(comps, wall):
+        # best-effort work done in the window: FP8 TFLOP/s and frames
+        if c_be is None:
+            return {}
+        n = int((comps["chain"] == c_be).sum())
+        d, kpf = wl.meta["be_dim"], wl.meta["be_gemms"]
+        return {"be_frames": n, "be_tflops": round(n * kpf * 2 * d ** 3 / wall / 1e12, 1)}
+
+    comps_u, m_u, st_u, wall_u = run_policy(urg, dw, timed, torch, be=be_timed)
+    urg_sum = summarise(m_u, st_u, wall_u, len(timed)) | be_rate(comps_u, wall_u)
     log("urgency:", json.dumps(urg_sum))
     collisions = urg.stats()["collisions"]
     urg_sum["collisions"] = int(collisions)
@@ -454,8 +490,8 @@ def main():
         for (c, k), (e, u) in est.items():
             fifo.set_estimate(c, k, e, u)
         run_policy(fifo, dw, warm[: len(warm) // 2], torch)     # warm the FIFO streams
-        comps_f, m_f, st_f, wall_f = run_policy(fifo, dw, timed, torch)
-        fifo_sum = summarise(m_f, st_f, wall_f, len(timed))
+        comps_f, m_f, st_f, wall_f = run_policy(fifo, dw, timed, torch, be=be_timed)
+        fifo_sum = summarise(m_f, st_f, wall_f, len(timed)) | be_rate(comps_f, wall_f)
         log("fifo:", json.dumps(fifo_sum))
         fifo.close()
     urg.close()
@@ -493,10 +529,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "11 chains x 2-6 tasks x 50-300 fp32 kernels (GEMM M,N,K 256..4096, "
-                               "conv3x3 C 32..256 H=W 32..256, softmax, row sum, voxel scatter "
-                               "30k-120k pts), periods 33-500 ms, deadlines 0.5-1.0 x period, "
-                               "urgency gate vs FIFO",
+        "config": {"workload": ("overload: " if args.overload else "")
+                   + "11 chains x 2-6 tasks x 50-300 fp32 kernels (GEMM M,N,K 256..4096, "
+                     "conv3x3 C 32..256 H=W 32..256, softmax, row sum, voxel scatter "
+                     "30k-120k pts), periods 33-500 ms, deadlines 0.5-1.0 x period, "
+                   + ("plus a closed-loop best-effort chain of 4 x 8192^3 FP8 E4M3 GEMMs per "
+                      "frame, " if args.overload else "")
+                   + "urgency gate vs FIFO",
+                   "be_frame_ms": round(be_frame_ns / 1e6, 3) if args.overload else None,
                    "seed": args.seed, "f_a": args.f_a, "f_d": args.f_d, "window_s": K,
                    "frames": len(timed), "kernels_per_round": n_kernels,
                    "isolated_utilisation": round(util, 3), "th_urgent_slack_ms": round(th / 1e6, 3)},

@@ -40,7 +40,8 @@ class DeviceWorkload:
                 outs = {}
                 for s, b in enumerate(ch.buffers):
                     if b.role == "out":
-                        dt = torch.float32 if b.kind == "f32" else torch.int32
+                        dt = {"f32": torch.float32, "i32": torch.int32,
+                              "u8": torch.uint8}[b.kind]
                         outs[s] = torch.zeros(b.n, dtype=dt, device=self.device)
                 sets.append(outs)
             self.inputs.append(ins)
@@ -58,8 +59,8 @@ class DeviceWorkload:
     def nbytes(self):
         tot = 0
         for ins, sets in zip(self.inputs, self.outputs):
-            tot += sum(t.numel() * 4 for t in ins.values())
-            tot += sum(t.numel() * 4 for s in sets for t in s.values())
+            tot += sum(t.numel() * t.element_size() for t in ins.values())
+            tot += sum(t.numel() * t.element_size() for s in sets for t in s.values())
         return tot
 
 
@@ -93,25 +94,43 @@ def estimates(g, wl):
     return out
 
 
-def run(g, dw, arrivals, lead_ns=20_000_000, timeout_s=120.0, progress=None):
+def run(g, dw, arrivals, lead_ns=20_000_000, timeout_s=120.0, progress=None, be=None):
     """Submit every arrival (offsets relative to a start time ``lead_ns``
     from now), wait for all completions and return them.  The gate must be
-    started; it is left running."""
+    started; it is left running.
+
+    ``be = (chain, depth, window_ns)`` adds a closed-loop best-effort source:
+    ``depth`` frames of ``chain`` are submitted at the start time and each of
+    their completions submits the next frame at once, until ``window_ns``
+    after the start time."""
     t0 = capi.now_ns() + lead_ns
     for c, f, t in arrivals:
         fid = g.submit(c, t0 + t, dw.ptrs[c][f % dw.n_sets])
         if fid is None:
             raise RuntimeError("submission queue full")
+    n_be = 0
+    if be is not None:
+        c_be, depth, win = be
+        for _ in range(depth):
+            if g.submit(c_be, t0, dw.ptrs[c_be][n_be % dw.n_sets]) is None:
+                raise RuntimeError("submission queue full")
+            n_be += 1
     done = []
     n_done = 0
     deadline = time.time() + timeout_s + (max(t for _, _, t in arrivals) / 1e9 if arrivals else 0)
-    while n_done < len(arrivals):
+    while n_done < len(arrivals) + n_be:
         got = g.poll()
         if len(got):
             done.append(got)
             n_done += len(got)
+            if be is not None:
+                for _ in range(int(np.count_nonzero(got["chain"] == c_be))):
+                    if capi.now_ns() < t0 + win:
+                        if g.submit(c_be, -1, dw.ptrs[c_be][n_be % dw.n_sets]) is None:
+                            raise RuntimeError("submission queue full")
+                        n_be += 1
         elif time.time() > deadline:
-            raise TimeoutError(f"{n_done} of {len(arrivals)} frames completed")
+            raise TimeoutError(f"{n_done} of {len(arrivals) + n_be} frames completed")
         else:
             time.sleep(0.002)
     out = np.concatenate(done) if done else np.zeros(0, capi.COMPLETION_DTYPE)

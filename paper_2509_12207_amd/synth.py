@@ -44,14 +44,15 @@ VOXEL_FPARAM = (-51.2, -51.2, 5.0)
 @dataclasses.dataclass
 class Buffer:
     name: str
-    kind: str        # "f32" or "i32"
+    kind: str        # "f32", "i32" or "u8" (FP8 E4M3 codes)
     n: int           # elements
     role: str        # "in" (read-only, shared by every frame) or "out"
-    init: tuple = ("uniform", -1.0, 1.0)   # for inputs: ("uniform", lo, hi) | ("points", sigma)
+    init: tuple = ("uniform", -1.0, 1.0)   # for inputs: ("uniform", lo, hi) |
+    #                                        ("points", sigma) | ("e4m3", e_lo, e_hi)
 
     @property
     def nbytes(self):
-        return 4 * self.n
+        return (1 if self.kind == "u8" else 4) * self.n
 
 
 @dataclasses.dataclass
@@ -105,6 +106,14 @@ def input_array(seed, chain, slot, buf):
         xyz = rng.normal(0.0, sigma, (n, 3))
         inten = rng.uniform(0.0, 1.0, (n, 1))
         return np.concatenate([xyz, inten], axis=1).astype(np.float32).reshape(-1)
+    if kind == "e4m3":
+        # finite FP8 E4M3 codes: random sign and mantissa, exponent field
+        # uniform in [e_lo, e_hi]
+        e_lo, e_hi = buf.init[1], buf.init[2]
+        sign = rng.integers(0, 2, buf.n) << 7
+        expo = rng.integers(e_lo, e_hi + 1, buf.n) << 3
+        mant = rng.integers(0, 8, buf.n)
+        return (sign | expo | mant).astype(np.uint8)
     raise ValueError(kind)
 
 
@@ -125,6 +134,10 @@ def k_conv(N, Cc, H, W, x, w, y):
 
 def k_rowsum(R, Cn, z, r):
     return {"op": "rowsum", "shape": (R, Cn), "in": (z,), "out": (r,)}
+
+
+def k_gemm_fp8(M, N, K, a, bt, c):
+    return {"op": "gemm_fp8", "shape": (M, N, K), "in": (a, bt), "out": (c,)}
 
 
 def k_softmax(R, L, x, y):
@@ -188,6 +201,9 @@ def _model_ns(op, shape):
         return floor + 4 * R * Cn / 4e12 * 1e9
     if op == "voxel":
         return 3 * floor + 20 * shape[0] / 1e12 * 1e9
+    if op == "gemm_fp8":
+        M, N, K = shape
+        return floor + 2 * M * N * K / 2.5e15 * 1e9
     raise ValueError(op)
 
 
@@ -423,6 +439,29 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
     return Workload("cfg1", chains, arr, seed, meta)
 
 
+def config4(seed=0, f_a=1.0, f_d=1.0, u_deadline=0.85, be_gemms=4, be_dim=8192, be_depth=2,
+            window_s=10.0, **kw):
+    """Overload: the eleven chains of configuration 1 at a base load of
+    ``u_deadline`` plus one best-effort chain (deadline 0) whose frames are
+    ``be_gemms`` back-to-back FP8 E4M3 products be_dim^3 with an FP32
+    result.  The best-effort chain is a closed loop: ``be_depth`` of its
+    frames are outstanding from the start, and each completion submits the
+    next one until the window ends, so it takes all the GPU time the
+    deadline chains leave (and, without gating, some they need).  Its frames
+    are not in ``arrivals``; ``meta`` names the chain and the depth."""
+    wl = config1(seed=seed, f_a=f_a, f_d=f_d, u_target=u_deadline, window_s=window_s, **kw)
+    d = be_dim
+    bufs = [Buffer("A8", "u8", d * d, "in", ("e4m3", 4, 9)),
+            Buffer("Bt8", "u8", d * d, "in", ("e4m3", 4, 9)),
+            Buffer("C", "f32", d * d, "out")]
+    kernels = [k_gemm_fp8(d, d, d, 0, 1, 2) for _ in range(be_gemms)]
+    e_frame = int(be_gemms * _model_ns("gemm_fp8", (d, d, d)))
+    be = ChainDef("be_fp8_gemm", e_frame, 0, [{"cpu_ns": 0, "kernels": kernels}], bufs, [])
+    meta = dict(wl.meta, u_deadline=u_deadline, be_chain=len(wl.chains), be_depth=be_depth,
+                be_gemms=be_gemms, be_dim=d)
+    return Workload("cfg4", wl.chains + [be], list(wl.arrivals), seed, meta)
+
+
 def model_utilisation(wl, f_a=1.0):
     """sum_c (model GPU time per frame) / P'_c under the generator's model."""
     u = 0.0
@@ -430,9 +469,8 @@ def model_utilisation(wl, f_a=1.0):
         t = 0.0
         for task in ch.tasks:
             for k in task["kernels"]:
-                t += _model_ns(k["op"], tuple(k["shape"][:4 if k["op"] == "conv3x3" else
-                                                         (3 if k["op"] == "gemm" else
-                                                          (1 if k["op"] == "voxel" else 2))]))
+                dims = {"conv3x3": 4, "gemm": 3, "gemm_fp8": 3, "voxel": 1}.get(k["op"], 2)
+                t += _model_ns(k["op"], tuple(k["shape"][:dims]))
         u += t / (ch.period_ns / f_a)
     return u
 
