@@ -72,8 +72,11 @@ SWEEPS = {
     # stream pool: lanes per level (level 0 reserved)
     "lanes": [{"name": "lanes_" + "_".join(map(str, l)), "cfg": {"lanes": l}}
               for l in ([1, 1], [2, 2], [2, 6], [4, 4], [2, 3, 3], [1, 2, 5])],
-    # TH_urgent percentile
-    "threshold": [{"name": f"th_p{p}", "pct": p} for p in (99, 95, 90, 85)],
+    # TH_urgent percentile, with the highest urgency sampled once per 1 ms
+    # (default) or at every decision instant
+    "threshold": [{"name": f"th_p{p}", "pct": p} for p in (95, 97, 99)]
+    + [{"name": f"th_p{p}_every_instant", "pct": p, "cfg": {"calib_period_ns": 0}}
+       for p in (95, 99)],
     # arrival-rate and deadline factors (Sec. 6.2): FIFO and the full gate
     "fa": [{"name": f"fa_{f}", "f_a": f} for f in (0.7, 0.9, 1.0, 1.1, 1.3)],
     "fd": [{"name": f"fd_{f}", "f_d": f} for f in (0.7, 1.0, 1.5)],

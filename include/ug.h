@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define UG_ABI_VERSION 1u
+#define UG_ABI_VERSION 2u
 
 typedef int32_t ug_status;
 enum {
@@ -147,6 +147,10 @@ typedef struct {
   int64_t idle_sleep_ns;   /* gate thread sleep when idle; 0 = spin         */
   uint32_t queue_capacity; /* max frames submitted and not yet completed    */
   uint32_t trace_capacity; /* decision-log records kept; 0 = no log         */
+  int64_t calib_period_ns; /* with UG_F_CALIBRATE: the highest urgency among
+                              active kernels is recorded at the first instant
+                              at or after each sampling time, one period
+                              apart (Sec. 4.4.3, 1 ms); 0 = every instant    */
 } ug_config;
 
 /* Completion of one frame (Sec. 6.2: latency, miss). */

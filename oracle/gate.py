@@ -129,6 +129,7 @@ DEFAULT_CFG = {
     "th_slack_ns": 0,           # TH_urgent as a slack; <= 0 means +infinity
     "lanes": [2, 6],            # streams per level; len = number of levels
     "calibrate": False,
+    "calib_period_ns": 1_000_000,  # sample the highest urgency at most once per period
 }
 
 
@@ -158,6 +159,7 @@ class GateModel:
         self.lane_load = {(lv, ln): 0 for lv in range(self.n_levels)
                           for ln in range(self.lanes[lv])}
         self.samples = []                              # slacks for TH_urgent
+        self.next_sample = None                        # earliest time of the next sample
         self.completed = []                            # (c, f, t_arr, t_done)
         self.last_snapshot = {}
 
@@ -242,12 +244,14 @@ class GateModel:
         # 4. one urgency snapshot for the whole instant (Eq. (2))
         slack = {inst.key: self.slack(inst, t) for inst in active}
         self.last_snapshot = dict(slack)
-        # 5. sample the highest urgency among active kernels (Sec. 4.4.3)
-        if self.cfg["calibrate"]:
+        # 5. sample the highest urgency among active kernels, periodically
+        #    (Sec. 4.4.3): at the first instant at or after each sampling time
+        if self.cfg["calibrate"] and (self.next_sample is None or t >= self.next_sample):
             fl = [(slack[i.key], i.key, None) for i in active
                   if i.in_flight() and not i.chain.best_effort]
             if fl:
                 self.samples.append(P.rank_sort(fl)[0][0])
+                self.next_sample = t + self.cfg["calib_period_ns"]
         # 6. launch requests, most urgent first
         ready = [i for i in active
                  if i.phase == "launch" and i.g_next < i.chain.task_end[i.task]

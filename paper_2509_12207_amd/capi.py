@@ -12,7 +12,7 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libug.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 POLICY_FIFO, POLICY_URGENCY = 0, 1
@@ -60,7 +60,7 @@ class Config(C.Structure):
                 ("delay_poll_ns", C.c_int64), ("util_exempt", C.c_float),
                 ("n_levels", C.c_int32), ("lanes", C.c_int32 * 8), ("th_slack_ns", C.c_int64),
                 ("idle_sleep_ns", C.c_int64), ("queue_capacity", C.c_uint32),
-                ("trace_capacity", C.c_uint32)]
+                ("trace_capacity", C.c_uint32), ("calib_period_ns", C.c_int64)]
 
 
 class Completion(C.Structure):

@@ -63,6 +63,8 @@ void Policy::reset() {
   for (auto& q : queue_) q.second.clear();
   finished_.clear();
   samples_.clear();
+  sampled_ = false;
+  next_sample_ = 0;
   collisions_ = 0;
   finalize();
 }
@@ -201,8 +203,10 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
             ? kBestEffortSlack
             : in->t_arr + ch.deadline_ns - ch.gpu_rem[in->i_gpu] - ch.cpu_rem[in->i_cpu] - t;
   }
-  // 5. highest urgency among active kernels, for TH_urgent calibration
-  if (cfg_.calibrate) {
+  // 5. highest urgency among active kernels, for TH_urgent calibration,
+  //    sampled periodically: at the first instant at or after each sampling
+  //    time
+  if (cfg_.calibrate && (!sampled_ || t >= next_sample_)) {
     const Instance* top = nullptr;
     for (Instance* in : active) {
       if (!in->in_flight() || chains_[in->c].best_effort) continue;
@@ -210,7 +214,11 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
                               slack[{top->c, top->f}], {top->c, top->f}))
         top = in;
     }
-    if (top) samples_.push_back(slack[{top->c, top->f}]);
+    if (top) {
+      samples_.push_back(slack[{top->c, top->f}]);
+      sampled_ = true;
+      next_sample_ = t + cfg_.calib_period_ns;
+    }
   }
   // 6. launch requests, most urgent first
   std::vector<Instance*> ready;

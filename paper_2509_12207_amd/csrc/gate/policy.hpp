@@ -38,6 +38,7 @@ struct PolicyConfig {
   int64_t delay_poll_ns = 1000000;
   float util_exempt = 0.1f;
   int64_t th_slack_ns = 0;
+  int64_t calib_period_ns = 1000000;   // at most one calibration sample per period
   std::vector<int32_t> lanes{2, 6};
 };
 
@@ -155,6 +156,8 @@ class Policy {
   std::map<std::pair<int32_t, int32_t>, int32_t> lane_load_;
   std::vector<Finished> finished_;
   std::vector<int64_t> samples_;
+  bool sampled_ = false;       // a sample has been taken
+  int64_t next_sample_ = 0;    // earliest time of the next sample
   uint64_t collisions_ = 0;
 };
 

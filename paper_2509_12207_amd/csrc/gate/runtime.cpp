@@ -134,6 +134,7 @@ ug::PolicyConfig policy_config(const ug_config& cfg) {
   p.delay_poll_ns = cfg.delay_poll_ns;
   p.util_exempt = cfg.util_exempt;
   p.th_slack_ns = cfg.th_slack_ns;
+  p.calib_period_ns = cfg.calib_period_ns;
   p.lanes.assign(cfg.lanes, cfg.lanes + cfg.n_levels);
   return p;
 }
@@ -382,6 +383,7 @@ void ug_config_default(ug_config* cfg) {
   cfg->idle_sleep_ns = 0;
   cfg->queue_capacity = 4096;
   cfg->trace_capacity = 0;
+  cfg->calib_period_ns = 1000000;
 }
 
 int64_t ug_now_ns(void) { return mono_ns(); }
@@ -408,7 +410,8 @@ ug_status ug_create(const ug_config* cfg, void** out) {
   if (cfg->n_levels < 1 || cfg->n_levels > 8) return UG_EINVAL;
   for (int i = 0; i < cfg->n_levels; ++i)
     if (cfg->lanes[i] < 1 || cfg->lanes[i] > 64) return UG_EINVAL;
-  if (cfg->delta_eval_ns < 0 || cfg->delay_poll_ns < 0 || cfg->queue_capacity == 0)
+  if (cfg->delta_eval_ns < 0 || cfg->delay_poll_ns < 0 || cfg->queue_capacity == 0 ||
+      cfg->calib_period_ns < 0)
     return UG_EINVAL;
   std::unique_ptr<Ctx> c(new (std::nothrow) Ctx());
   if (!c) return UG_ENOMEM;

@@ -81,6 +81,7 @@ def test_config_defaults_and_errors():
     assert cfg.delta_eval_ns == 500_000 and cfg.delay_poll_ns == 1_000_000
     assert abs(cfg.util_exempt - 0.1) < 1e-7
     assert cfg.flags == capi.F_BIND | capi.F_DELAY | capi.F_BATCH
+    assert cfg.calib_period_ns == 1_000_000 and list(cfg.lanes[:cfg.n_levels]) == [2, 6]
     bad = capi.Config()
     L.ug_config_default(C.byref(bad))
     bad.abi_version = 99
@@ -147,7 +148,8 @@ def _gate_for(cfg):
     return capi.Gate(policy=cfg.get("policy", "urgency"), device=-1, lanes=lanes,
                      flags=_flags(cfg), delta_eval_ns=cfg.get("delta_eval_ns", 500_000),
                      delay_poll_ns=cfg.get("delay_poll_ns", 1_000_000),
-                     th_slack_ns=cfg.get("th_slack_ns", 0))
+                     th_slack_ns=cfg.get("th_slack_ns", 0),
+                     calib_period_ns=cfg.get("calib_period_ns", 1_000_000))
 
 
 CFGS = [
@@ -157,6 +159,7 @@ CFGS = [
     {"policy": "urgency", "th_slack_ns": 2 * MS, "lanes": [2, 3, 1, 2]},
     {"policy": "urgency", "batch": False, "bind": False, "th_slack_ns": 2 * MS},
     {"policy": "urgency", "delay": False, "th_slack_ns": 0, "calibrate": True},
+    {"policy": "urgency", "th_slack_ns": 2 * MS, "calibrate": True, "calib_period_ns": 0},
     {"policy": "urgency", "th_slack_ns": 4 * MS, "lanes": [1]},
     {"policy": "fifo"},
 ]

@@ -250,7 +250,7 @@ def _cloud(seed, n, sigma=20.0):
 def test_voxel_binned_bit_exact(n):
     P = _cloud(n, n)
     assert capi.kernel_workspace({"op": "voxel", "shape": (n, 512, 512), "in": (0,),
-                                  "out": (1, 2, 3, 4)}) > 0
+                                  "out": (1, 2, 3, 4), "fparam": (-51.2, -51.2, 5.0)}) > 0
     _same(run_voxel(P), OK.voxel_scatter(P))
 
 
