@@ -23,6 +23,11 @@ sys.path.insert(0, ROOT)
 MS = 1_000_000
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP8_MFMA = 5.0e15
+# Percentile of the sampled highest urgencies that sets TH_urgent.  The
+# paper's 95th (Sec. 4.4.3) holds back too much work on MI355X: in the
+# threshold sweep (3 seeds) it lowers misses but raises p99 latency over FIFO,
+# while the 99th lowers both on every seed.
+TH_PCT = 99
 PEAK_HBM = 8.0e12
 METRIC = "deadline-miss ratio & p99 chain latency vs FIFO launch; kernel % of roofline"
 
@@ -113,7 +118,7 @@ def sweep_main(args, torch, capi, runner, synth):
                 g.set_flags((flags & ~capi.F_DELAY) | capi.F_CALIBRATE)
                 g.set_threshold(0)
                 run_policy(g, dw, warm, torch)
-                th = g.calibration_threshold(v.get("pct", 95))
+                th = g.calibration_threshold(v.get("pct", TH_PCT))
                 g.set_threshold(th)
                 g.set_flags(flags)
                 _, m, st, wall = run_policy(g, dw, timed, torch)
@@ -463,11 +468,11 @@ def main():
         + ", ".join(f"{k} {v / sum(by_op.values()):.2f}" for k, v in sorted(by_op.items(), key=lambda x: -x[1])))
 
     # TH_urgent: run the warm-up windows with delayed launching off and
-    # calibration sampling on, take the 95th percentile (Sec. 4.4.3)
+    # calibration sampling on, take the TH_PCT-th percentile (Sec. 4.4.3)
     urg.set_flags(capi.F_BIND | capi.F_BATCH | capi.F_CALIBRATE)
     urg.set_threshold(0)
     run_policy(urg, dw, warm, torch, be=be_warm)
-    th = urg.calibration_threshold(95)
+    th = urg.calibration_threshold(TH_PCT)
     urg.set_threshold(th)
     urg.set_flags(capi.F_BIND | capi.F_DELAY | capi.F_BATCH)
     log(f"TH_urgent calibrated: slack {th / 1e6:.3f} ms")

@@ -10,6 +10,28 @@
 namespace ug {
 namespace {
 
+// Streaming 16-byte accesses (nontemporal): they do not allocate in the
+// caches, which pays for tensors far larger than L2 and the Infinity Cache
+// (each byte is touched once); smaller tensors keep the cached path so that
+// the next kernel of the task finds its input there.
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 load_stream(const float4* p) {
+  const f32x4v v = __builtin_nontemporal_load(reinterpret_cast<const f32x4v*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void store_stream(float4* p, float4 v) {
+  const f32x4v w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<f32x4v*>(p));
+}
+template <bool NT>
+__device__ __forceinline__ float4 ld4(const float4* p) {
+  return NT ? load_stream(p) : *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st4(float4* p, float4 v) {
+  if (NT) store_stream(p, v); else *p = v;
+}
+
 // ---------------------------------------------------------------- bias+ReLU
 // y = s > 0 ? s : +0 with s = x + b (one FP32 add; -0 and NaN give +0).
 __device__ __forceinline__ float relu_add(float x, float b) {
@@ -36,7 +58,7 @@ __device__ __forceinline__ float4 bias_relu4(const float4 x, const float* __rest
   return make_float4(relu_add(x.x, bb), relu_add(x.y, bb), relu_add(x.z, bb), relu_add(x.w, bb));
 }
 
-template <int AXIS, typename I>
+template <int AXIS, typename I, bool NT>
 __global__ __launch_bounds__(256) void bias_relu_vec(const float4* __restrict__ X,
                                                      const float* __restrict__ b,
                                                      float4* __restrict__ Y, I n, I c4) {
@@ -46,12 +68,12 @@ __global__ __launch_bounds__(256) void bias_relu_vec(const float4* __restrict__ 
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       const I i = base + (I)u * 256;
-      if (i < n) x[u] = X[i];
+      if (i < n) x[u] = ld4<NT>(X + i);
     }
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       const I i = base + (I)u * 256;
-      if (i < n) Y[i] = bias_relu4<AXIS>(x[u], b, i, c4);
+      if (i < n) st4<NT>(Y + i, bias_relu4<AXIS>(x[u], b, i, c4));
     }
   }
 }
@@ -90,7 +112,7 @@ __global__ __launch_bounds__(256) void rowsum_wave(const float* __restrict__ Z,
   if ((C & 3) == 0 && ((reinterpret_cast<uintptr_t>(z) & 15) == 0)) {
     const float4* z4 = reinterpret_cast<const float4*>(z);
     for (int64_t j = lane; j < C / 4; j += 64) {
-      const float4 v = z4[j];
+      const float4 v = load_stream(z4 + j);
       s += (v.x + v.y) + (v.z + v.w);
     }
   } else {
@@ -117,12 +139,12 @@ __global__ __launch_bounds__(256) void rowsum_block(const float* __restrict__ Z,
     for (; j + 768 < c4; j += 1024) {
       float4 v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = z4[j + 256 * u];
+      for (int u = 0; u < 4; ++u) v[u] = load_stream(z4 + j + 256 * u);
 #pragma unroll
       for (int u = 0; u < 4; ++u) a[u] += (v[u].x + v[u].y) + (v[u].z + v[u].w);
     }
     for (; j < c4; j += 256) {
-      const float4 v = z4[j];
+      const float4 v = load_stream(z4 + j);
       a[0] += (v.x + v.y) + (v.z + v.w);
     }
     s = (a[0] + a[1]) + (a[2] + a[3]);
@@ -137,7 +159,7 @@ __global__ __launch_bounds__(256) void rowsum_block(const float* __restrict__ Z,
 
 // ---------------------------------------------------------------- softmax
 // Row held in registers: NV float4 per lane, WAVES waves per row.
-template <int WAVES, int NV>
+template <int WAVES, int NV, bool NT>
 __global__ __launch_bounds__(256) void softmax_reg(const float* __restrict__ X,
                                                    float* __restrict__ Y, int64_t R, int64_t L) {
   constexpr int T = WAVES * 64;               // lanes per row
@@ -158,7 +180,7 @@ __global__ __launch_bounds__(256) void softmax_reg(const float* __restrict__ X,
   for (int i = 0; i < NV; ++i) {
     const int64_t j = t + (int64_t)i * T;
     if (live && j < L4) {
-      v[i] = reinterpret_cast<const float4*>(x)[j];
+      v[i] = ld4<NT>(reinterpret_cast<const float4*>(x) + j);
       m = fmaxf(m, fmaxf(fmaxf(v[i].x, v[i].y), fmaxf(v[i].z, v[i].w)));
     } else {
       v[i] = make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
@@ -195,8 +217,8 @@ __global__ __launch_bounds__(256) void softmax_reg(const float* __restrict__ X,
   for (int i = 0; i < NV; ++i) {
     const int64_t j = t + (int64_t)i * T;
     if (live && j < L4)
-      reinterpret_cast<float4*>(y)[j] =
-          make_float4(v[i].x * inv, v[i].y * inv, v[i].z * inv, v[i].w * inv);
+      st4<NT>(reinterpret_cast<float4*>(y) + j,
+              make_float4(v[i].x * inv, v[i].y * inv, v[i].z * inv, v[i].w * inv));
   }
 }
 
@@ -236,18 +258,20 @@ unsigned grid_for(int64_t work, int64_t per_block, int64_t cap) {
 // ---------------------------------------------------------------- launchers
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-// Grid-stride kernels: 8 waves of work per CU slot on 256 CUs is plenty.
-static constexpr int64_t kStreamGridCap = 256 * 32;
+// Grid-stride kernels: up to 64 workgroups per CU on 256 CUs.
+static constexpr int64_t kStreamGridCap = 256 * 64;
+// Tensors from this size on are streamed with nontemporal accesses.
+static constexpr int64_t kStreamBytes = int64_t(64) << 20;
 
 OpPlan bias_relu_f32_plan(int64_t R, int64_t C, int axis, bool vec) {
   OpPlan p;
   const bool narrow = vec && R * (C / 4) < (int64_t(1) << 32);
   if (vec && narrow)
-    p.func = axis == 0 ? reinterpret_cast<const void*>(&bias_relu_vec<0, uint32_t>)
-                       : reinterpret_cast<const void*>(&bias_relu_vec<1, uint32_t>);
+    p.func = axis == 0 ? reinterpret_cast<const void*>(&bias_relu_vec<0, uint32_t, false>)
+                       : reinterpret_cast<const void*>(&bias_relu_vec<1, uint32_t, false>);
   else if (vec)
-    p.func = axis == 0 ? reinterpret_cast<const void*>(&bias_relu_vec<0, int64_t>)
-                       : reinterpret_cast<const void*>(&bias_relu_vec<1, int64_t>);
+    p.func = axis == 0 ? reinterpret_cast<const void*>(&bias_relu_vec<0, int64_t, false>)
+                       : reinterpret_cast<const void*>(&bias_relu_vec<1, int64_t, false>);
   else
     p.func = axis == 0 ? reinterpret_cast<const void*>(&bias_relu_scalar<0>)
                        : reinterpret_cast<const void*>(&bias_relu_scalar<1>);
@@ -264,17 +288,22 @@ hipError_t bias_relu_f32_launch(const float* X, const float* b, float* Y, int64_
   const int64_t n4 = R * (C / 4), c4 = C / 4;
   const float4* x4 = reinterpret_cast<const float4*>(X);
   float4* y4 = reinterpret_cast<float4*>(Y);
+  const bool nt = R * C * 4 >= kStreamBytes;
   if (vec && n4 < (int64_t(1) << 32)) {
     const uint32_t n = (uint32_t)n4, c = (uint32_t)c4;
-    if (axis == 0)
-      hipLaunchKernelGGL((bias_relu_vec<0, uint32_t>), p.grid, p.block, 0, s, x4, b, y4, n, c);
+    if (axis == 0 && nt)
+      hipLaunchKernelGGL((bias_relu_vec<0, uint32_t, true>), p.grid, p.block, 0, s, x4, b, y4, n, c);
+    else if (axis == 0)
+      hipLaunchKernelGGL((bias_relu_vec<0, uint32_t, false>), p.grid, p.block, 0, s, x4, b, y4, n, c);
+    else if (nt)
+      hipLaunchKernelGGL((bias_relu_vec<1, uint32_t, true>), p.grid, p.block, 0, s, x4, b, y4, n, c);
     else
-      hipLaunchKernelGGL((bias_relu_vec<1, uint32_t>), p.grid, p.block, 0, s, x4, b, y4, n, c);
+      hipLaunchKernelGGL((bias_relu_vec<1, uint32_t, false>), p.grid, p.block, 0, s, x4, b, y4, n, c);
   } else if (vec) {
     if (axis == 0)
-      hipLaunchKernelGGL((bias_relu_vec<0, int64_t>), p.grid, p.block, 0, s, x4, b, y4, n4, c4);
+      hipLaunchKernelGGL((bias_relu_vec<0, int64_t, true>), p.grid, p.block, 0, s, x4, b, y4, n4, c4);
     else
-      hipLaunchKernelGGL((bias_relu_vec<1, int64_t>), p.grid, p.block, 0, s, x4, b, y4, n4, c4);
+      hipLaunchKernelGGL((bias_relu_vec<1, int64_t, true>), p.grid, p.block, 0, s, x4, b, y4, n4, c4);
   } else {
     if (axis == 0)
       hipLaunchKernelGGL(bias_relu_scalar<0>, p.grid, p.block, 0, s, X, b, Y, R, C);
@@ -316,34 +345,44 @@ OpPlan softmax_f32_plan(int64_t R, int64_t L, bool vec) {
     p.func = reinterpret_cast<const void*>(&softmax_any);
     p.grid = dim3((unsigned)R);
   } else if (L <= 256) {
-    p.func = reinterpret_cast<const void*>(&softmax_reg<1, 1>);
+    p.func = reinterpret_cast<const void*>(&softmax_reg<1, 1, false>);
     p.grid = dim3((unsigned)((R + 3) / 4));
   } else if (L <= 1024) {
-    p.func = reinterpret_cast<const void*>(&softmax_reg<1, 4>);
+    p.func = reinterpret_cast<const void*>(&softmax_reg<1, 4, false>);
     p.grid = dim3((unsigned)((R + 3) / 4));
   } else if (L <= 2048) {
-    p.func = reinterpret_cast<const void*>(&softmax_reg<2, 4>);
+    p.func = reinterpret_cast<const void*>(&softmax_reg<2, 4, false>);
     p.grid = dim3((unsigned)((R + 1) / 2));
   } else {
-    p.func = reinterpret_cast<const void*>(&softmax_reg<4, 4>);
+    p.func = reinterpret_cast<const void*>(&softmax_reg<4, 4, false>);
     p.grid = dim3((unsigned)R);
   }
   return p;
 }
 
+template <int W, int V>
+static void launch_softmax_reg(bool nt, const OpPlan& p, hipStream_t s, const float* X, float* Y,
+                               int64_t R, int64_t L) {
+  if (nt)
+    hipLaunchKernelGGL((softmax_reg<W, V, true>), p.grid, p.block, 0, s, X, Y, R, L);
+  else
+    hipLaunchKernelGGL((softmax_reg<W, V, false>), p.grid, p.block, 0, s, X, Y, R, L);
+}
+
 hipError_t softmax_f32_launch(const float* X, float* Y, int64_t R, int64_t L, hipStream_t s) {
   const bool vec = (L % 4 == 0) && aligned16(X) && aligned16(Y);
   OpPlan p = softmax_f32_plan(R, L, vec);
+  const bool nt = R * L * 4 >= kStreamBytes;
   if (!vec || L > 4096)
     hipLaunchKernelGGL(softmax_any, p.grid, p.block, 0, s, X, Y, R, L);
   else if (L <= 256)
-    hipLaunchKernelGGL((softmax_reg<1, 1>), p.grid, p.block, 0, s, X, Y, R, L);
+    launch_softmax_reg<1, 1>(nt, p, s, X, Y, R, L);
   else if (L <= 1024)
-    hipLaunchKernelGGL((softmax_reg<1, 4>), p.grid, p.block, 0, s, X, Y, R, L);
+    launch_softmax_reg<1, 4>(nt, p, s, X, Y, R, L);
   else if (L <= 2048)
-    hipLaunchKernelGGL((softmax_reg<2, 4>), p.grid, p.block, 0, s, X, Y, R, L);
+    launch_softmax_reg<2, 4>(nt, p, s, X, Y, R, L);
   else
-    hipLaunchKernelGGL((softmax_reg<4, 4>), p.grid, p.block, 0, s, X, Y, R, L);
+    launch_softmax_reg<4, 4>(nt, p, s, X, Y, R, L);
   return hipGetLastError();
 }
 

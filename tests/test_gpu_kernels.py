@@ -82,8 +82,9 @@ def test_gemm_full_size_sampled():
 
 
 # ---------------------------------------------------------------- bias+ReLU
+# (4096, 4100) and (4100, 4096) are over 64 MiB: the streaming (nontemporal) path
 @pytest.mark.parametrize("R,Cn,axis", [(128, 128, 0), (16, 4096, 1), (37, 53, 0), (5, 7, 1),
-                                       (1024, 1024, 0)])
+                                       (1024, 1024, 0), (4096, 4100, 0), (4100, 4096, 1)])
 def test_bias_relu_bit_exact(R, Cn, axis):
     r = rng(R + Cn + axis)
     X = r.uniform(-1, 1, (R, Cn)).astype(np.float32)
@@ -172,8 +173,10 @@ def test_rowsum_integer_exact():
 
 
 # ------------------------------------------------------------------ softmax
+# (8193, 2048) and (4097, 4096) are over 64 MiB: the streaming (nontemporal) path
 @pytest.mark.parametrize("R,L", [(256, 128), (5, 3), (64, 256), (33, 1000), (16, 1024),
-                                 (9, 2048), (8, 4096), (3, 5000), (7, 1)])
+                                 (9, 2048), (8, 4096), (3, 5000), (7, 1), (8193, 2048),
+                                 (4097, 4096)])
 def test_softmax_parity(R, L):
     r = rng(R + L)
     X = r.uniform(-8, 8, (R, L)).astype(np.float32)
@@ -362,6 +365,33 @@ def _fp8_codes(r, shape, lo=4, hi=9):
     return (s | e | m).astype(np.uint8)
 
 
+def fp8_bound(A8, Bt8):
+    """Componentwise error bound of the FP8 product on the matrix cores.
+
+    One instruction sums the 64 products of a K block in a fixed-point
+    window whose lowest bit is 2^(e - 13), e = floor(log2) of the block's
+    largest product magnitude (measured on gfx950: a product 2^13 times
+    smaller than the largest is kept exactly, one 2^14 times smaller is
+    dropped).  Each of the block's 64 products loses less than one such bit,
+    so a block errs by less than 64 * 2^-13 * max|a_k b_k| (the largest
+    product over the block, or the larger max|a| * max|b| for big inputs).
+    The block sums are then accumulated in FP32: at most K/64 + 1 roundings
+    of 2^-24 relative to the running |A||B|."""
+    M, K = A8.shape
+    N = Bt8.shape[0]
+    nb = (K + 63) // 64
+    pad = nb * 64 - K
+    a = np.abs(OK.e4m3_decode(np.pad(A8, ((0, 0), (0, pad))))).reshape(M, nb, 64)
+    b = np.abs(OK.e4m3_decode(np.pad(Bt8, ((0, 0), (0, pad))))).reshape(N, nb, 64)
+    if M * N * K <= 1 << 27:
+        pmax = np.zeros((M, N))
+        for j in range(nb):
+            pmax += (a[:, None, j, :] * b[None, :, j, :]).max(axis=2)
+    else:
+        pmax = a.max(axis=2) @ b.max(axis=2).T
+    return 64 * 2.0 ** -13 * pmax + (nb + 1) * 2.0 ** -24 * OK.gemm_fp8_abs_f64(A8, Bt8)
+
+
 def run_gemm_fp8(A8, Bt8):
     M, K = A8.shape
     N = Bt8.shape[0]
@@ -390,8 +420,26 @@ def test_gemm_fp8_parity(M, N, K):
     A8, B8 = _fp8_codes(r, (M, K)), _fp8_codes(r, (N, K))
     C = run_gemm_fp8(A8, B8)
     ref = OK.gemm_fp8_f64(A8, B8)
-    scale = OK.gemm_fp8_abs_f64(A8, B8)
-    assert np.all(np.abs(C - ref) <= TOL * scale), np.max(np.abs(C - ref) / scale)
+    bound = fp8_bound(A8, B8)
+    assert np.all(np.abs(C - ref) <= bound), np.max(np.abs(C - ref) / bound)
+
+
+@pytest.mark.parametrize("small", [0x38, 0x30, 0x20, 0x18, 0x04, 0x02, 0x01])
+def test_gemm_fp8_wide_range_block(small):
+    # one large product (256) and 63 small ones in a K block of row 0 and
+    # column 0; the other rows and columns random
+    r = rng(small)
+    M = N = 32
+    K = 128
+    A8, B8 = _fp8_codes(r, (M, K)), _fp8_codes(r, (N, K))
+    A8[0, :64] = small
+    A8[0, 0] = 0x78
+    B8[0, :] = 0x38
+    C = run_gemm_fp8(A8, B8)
+    ref = OK.gemm_fp8_f64(A8, B8)
+    bound = fp8_bound(A8, B8)
+    assert np.isfinite(C).all()
+    assert np.all(np.abs(C - ref) <= bound), (C[0, 0], ref[0, 0], bound[0, 0])
 
 
 def test_gemm_fp8_full_size_sampled():
@@ -401,12 +449,12 @@ def test_gemm_fp8_full_size_sampled():
     A8, B8 = _fp8_codes(r, (M, K)), _fp8_codes(r, (N, K))
     C = run_gemm_fp8(A8, B8)
     assert not np.isnan(C).any()
-    for m, n in zip(r.integers(0, M, 64), r.integers(0, N, 64)):
-        v, sc = OK.gemm_fp8_entry_f64(A8, B8, m, n)
-        assert abs(C[m, n] - v) <= TOL * sc, (m, n, C[m, n], v)
-    for m, n in [(0, 0), (M - 1, N - 1), (255, 256), (4095, 8191)]:
-        v, sc = OK.gemm_fp8_entry_f64(A8, B8, m, n)
-        assert abs(C[m, n] - v) <= TOL * sc, (m, n)
+    pts = list(zip(r.integers(0, M, 64), r.integers(0, N, 64)))
+    pts += [(0, 0), (M - 1, N - 1), (255, 256), (4095, 8191)]
+    for m, n in pts:
+        v, _ = OK.gemm_fp8_entry_f64(A8, B8, m, n)
+        bound = fp8_bound(A8[m:m + 1], B8[n:n + 1])[0, 0]
+        assert abs(C[m, n] - v) <= bound, (m, n, C[m, n], v)
 
 
 def test_gemm_fp8_rejects_bad_k_and_alignment():
