@@ -87,6 +87,10 @@ SWEEPS = {
     "fd": [{"name": f"fd_{f}", "f_d": f} for f in (0.7, 1.0, 1.5)],
     # run-to-run and seed spread at the default point
     "seeds": [{"name": "default"}],
+    # urgency-ordered admission under a cap on launched, unconfirmed work
+    "admit": [{"name": "full"}]
+    + [{"name": f"admit_{n}", "flags": FULL | 16, "cfg": {"admit_tasks": n}}
+       for n in (2, 3, 4, 6, 8)],
 }
 
 
@@ -107,8 +111,8 @@ def sweep_main(args, torch, capi, runner, synth):
             fifo = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16)
             runner.copy_estimates(prof, fifo, wl)
             run_policy(fifo, dw, warm[: len(warm) // 2], torch)
-            _, m, st, wall = run_policy(fifo, dw, timed, torch)
-            fifo_sum = summarise(m, st, wall, len(timed))
+            cf, m, st, wall = run_policy(fifo, dw, timed, torch)
+            fifo_sum = summarise(m, st, wall, len(timed)) | {"per_chain": per_chain(cf, wl)}
             fifo.close()
             for v in variants:
                 g = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16,
@@ -121,8 +125,8 @@ def sweep_main(args, torch, capi, runner, synth):
                 th = g.calibration_threshold(v.get("pct", TH_PCT))
                 g.set_threshold(th)
                 g.set_flags(flags)
-                _, m, st, wall = run_policy(g, dw, timed, torch)
-                u = summarise(m, st, wall, len(timed))
+                cu, m, st, wall = run_policy(g, dw, timed, torch)
+                u = summarise(m, st, wall, len(timed)) | {"per_chain": per_chain(cu, wl)}
                 g.close()
                 print(json.dumps({"sweep": args.sweep, "variant": v["name"], **point,
                                   "th_urgent_slack_ms": round(th / 1e6, 3), "urgency": u,
@@ -148,6 +152,19 @@ def run_policy(g, dw, arrivals, torch, be=None):
     st = g.stats()
     g.stop()
     return comps, m, st, t1 - t0
+
+
+def per_chain(comps, wl):
+    """[chain, missed, frames, deadline ms, p99 latency ms] of every deadline chain."""
+    import numpy as np
+    out = []
+    for c, ch in enumerate(wl.chains):
+        sel = comps[comps["chain"] == c]
+        if ch.deadline_ns == 0 or not len(sel):
+            continue
+        out.append([c, int(sel["missed"].sum()), int(len(sel)), round(ch.deadline_ns / 1e6, 1),
+                    round(float(np.percentile(sel["latency_ns"], 99)) / 1e6, 1)])
+    return out
 
 
 def summarise(m, st, wall, n_frames):
@@ -487,7 +504,8 @@ def main():
         return {"be_frames": n, "be_tflops": round(n * kpf * 2 * d ** 3 / wall / 1e12, 1)}
 
     comps_u, m_u, st_u, wall_u = run_policy(urg, dw, timed, torch, be=be_timed)
-    urg_sum = summarise(m_u, st_u, wall_u, len(timed)) | be_rate(comps_u, wall_u)
+    urg_sum = (summarise(m_u, st_u, wall_u, len(timed)) | be_rate(comps_u, wall_u)
+               | {"per_chain": per_chain(comps_u, wl)})
     log("urgency:", json.dumps(urg_sum))
     collisions = urg.stats()["collisions"]
     urg_sum["collisions"] = int(collisions)
@@ -499,7 +517,8 @@ def main():
             fifo.set_estimate(c, k, e, u)
         run_policy(fifo, dw, warm[: len(warm) // 2], torch)     # warm the FIFO streams
         comps_f, m_f, st_f, wall_f = run_policy(fifo, dw, timed, torch, be=be_timed)
-        fifo_sum = summarise(m_f, st_f, wall_f, len(timed)) | be_rate(comps_f, wall_f)
+        fifo_sum = (summarise(m_f, st_f, wall_f, len(timed)) | be_rate(comps_f, wall_f)
+                    | {"per_chain": per_chain(comps_f, wl)})
         log("fifo:", json.dumps(fifo_sum))
         fifo.close()
     urg.close()

@@ -63,7 +63,11 @@ enum {
   UG_F_BIND = 1u,      /* task-level stream binding with reservation (4.4.3) */
   UG_F_DELAY = 2u,     /* delayed launching (4.4.4)                          */
   UG_F_BATCH = 4u,     /* batched launching with batch overlap (4.4.5)       */
-  UG_F_CALIBRATE = 8u  /* record highest-urgency samples for TH_urgent (4.4.3) */
+  UG_F_CALIBRATE = 8u, /* record highest-urgency samples for TH_urgent (4.4.3) */
+  UG_F_ADMIT = 16u     /* urgency-ordered admission: a task that is not truly
+                          urgent starts only while fewer than admit_tasks
+                          instances have kernels in flight (stands in for
+                          stream priorities, see ug_config)               */
 };
 
 /* Operations.  Shapes and slot meaning per op; all float buffers are fp32,
@@ -151,6 +155,8 @@ typedef struct {
                               active kernels is recorded at the first instant
                               at or after each sampling time, one period
                               apart (Sec. 4.4.3, 1 ms); 0 = every instant    */
+  int64_t admit_tasks;     /* with UG_F_ADMIT: instances with kernels in
+                              flight before new tasks wait (4)              */
 } ug_config;
 
 /* Completion of one frame (Sec. 6.2: latency, miss). */

@@ -130,6 +130,8 @@ DEFAULT_CFG = {
     "lanes": [2, 6],            # streams per level; len = number of levels
     "calibrate": False,
     "calib_period_ns": 1_000_000,  # sample the highest urgency at most once per period
+    "admit": False,             # urgency-ordered task admission (no stream priorities)
+    "admit_tasks": 4,           # instances with kernels in flight before new tasks wait
 }
 
 
@@ -258,6 +260,7 @@ class GateModel:
                  and not i.waits and (i.wake is None or i.wake <= t)]
         if self.urgency_policy:
             ready = [r[2] for r in P.rank_sort([(slack[i.key], i.key, i) for i in ready])]
+        self.n_active = sum(1 for i in active if i.in_flight())
         for inst in ready:
             self._release(inst, t, slack, active, out)
         return out
@@ -317,6 +320,16 @@ class GateModel:
                 poll = self.cfg["delay_poll_ns"]
                 inst.wake = t + poll if poll > 0 else None
                 return
+            # task admission: a task that is not truly urgent starts only
+            # while fewer than admit_tasks instances have kernels in flight
+            if (self.urgency_policy and self.cfg["admit"] and not inst.bound
+                    and self.n_active >= self.cfg["admit_tasks"]
+                    and not self._urgent(slack[inst.key])):
+                out.append(("HOLD", inst.c, inst.f, g))
+                inst.wake = None
+                return
+            if not inst.bound and not inst.in_flight():
+                self.n_active += 1
             inst.wake = None
             if not inst.bound:
                 self._bind(inst, slack, active, out)

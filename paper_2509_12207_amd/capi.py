@@ -16,7 +16,7 @@ ABI_VERSION = 2
 
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 POLICY_FIFO, POLICY_URGENCY = 0, 1
-F_BIND, F_DELAY, F_BATCH, F_CALIBRATE = 1, 2, 4, 8
+F_BIND, F_DELAY, F_BATCH, F_CALIBRATE, F_ADMIT = 1, 2, 4, 8, 16
 
 OP_GEMM_F32 = 1
 OP_BIAS_RELU_F32 = 2
@@ -60,7 +60,8 @@ class Config(C.Structure):
                 ("delay_poll_ns", C.c_int64), ("util_exempt", C.c_float),
                 ("n_levels", C.c_int32), ("lanes", C.c_int32 * 8), ("th_slack_ns", C.c_int64),
                 ("idle_sleep_ns", C.c_int64), ("queue_capacity", C.c_uint32),
-                ("trace_capacity", C.c_uint32), ("calib_period_ns", C.c_int64)]
+                ("trace_capacity", C.c_uint32), ("calib_period_ns", C.c_int64),
+                ("admit_tasks", C.c_int64)]
 
 
 class Completion(C.Structure):

@@ -220,6 +220,10 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
       next_sample_ = t + cfg_.calib_period_ns;
     }
   }
+  // instances with launched, unconfirmed kernels (the AKB's entries)
+  active_ = 0;
+  for (Instance* in : active)
+    if (in->in_flight()) ++active_;
   // 6. launch requests, most urgent first
   std::vector<Instance*> ready;
   for (Instance* in : active) {
@@ -309,6 +313,17 @@ void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& acti
       }
       return;
     }
+    // admission: a task that is not truly urgent starts only while fewer
+    // than admit_tasks instances have kernels in flight; waiting tasks are
+    // re-checked at every instant, most urgent first
+    if (gated && cfg_.admit && !me.bound && active_ >= cfg_.admit_tasks &&
+        !urgent(slack.at({me.c, me.f}))) {
+      out.push_back(rec(UG_REC_HOLD, me.c, me.f, me.task, g, 1, 0, 0));
+      me.n_holds += 1;
+      me.has_wake = false;
+      return;
+    }
+    if (!me.bound && !me.in_flight()) ++active_;
     me.has_wake = false;
     if (!me.bound) bind(me, active, slack, out);
     if (!me.batch_open) {

@@ -33,7 +33,8 @@ namespace ug {
 
 struct PolicyConfig {
   int policy = UG_POLICY_URGENCY;
-  bool bind = true, delay = true, batch = true, calibrate = false;
+  bool bind = true, delay = true, batch = true, calibrate = false, admit = false;
+  int64_t admit_tasks = 4;             // tasks in flight before new ones wait
   int64_t delta_eval_ns = 500000;
   int64_t delay_poll_ns = 1000000;
   float util_exempt = 0.1f;
@@ -156,6 +157,7 @@ class Policy {
   std::map<std::pair<int32_t, int32_t>, int32_t> lane_load_;
   std::vector<Finished> finished_;
   std::vector<int64_t> samples_;
+  int64_t active_ = 0;         // instances with launched, unconfirmed kernels
   bool sampled_ = false;       // a sample has been taken
   int64_t next_sample_ = 0;    // earliest time of the next sample
   uint64_t collisions_ = 0;

@@ -135,6 +135,8 @@ ug::PolicyConfig policy_config(const ug_config& cfg) {
   p.util_exempt = cfg.util_exempt;
   p.th_slack_ns = cfg.th_slack_ns;
   p.calib_period_ns = cfg.calib_period_ns;
+  p.admit = (cfg.flags & UG_F_ADMIT) != 0;
+  p.admit_tasks = cfg.admit_tasks;
   p.lanes.assign(cfg.lanes, cfg.lanes + cfg.n_levels);
   return p;
 }
@@ -384,6 +386,7 @@ void ug_config_default(ug_config* cfg) {
   cfg->queue_capacity = 4096;
   cfg->trace_capacity = 0;
   cfg->calib_period_ns = 1000000;
+  cfg->admit_tasks = 4;
 }
 
 int64_t ug_now_ns(void) { return mono_ns(); }
@@ -411,7 +414,7 @@ ug_status ug_create(const ug_config* cfg, void** out) {
   for (int i = 0; i < cfg->n_levels; ++i)
     if (cfg->lanes[i] < 1 || cfg->lanes[i] > 64) return UG_EINVAL;
   if (cfg->delta_eval_ns < 0 || cfg->delay_poll_ns < 0 || cfg->queue_capacity == 0 ||
-      cfg->calib_period_ns < 0)
+      cfg->calib_period_ns < 0 || cfg->admit_tasks < 1)
     return UG_EINVAL;
   std::unique_ptr<Ctx> c(new (std::nothrow) Ctx());
   if (!c) return UG_ENOMEM;
@@ -642,6 +645,7 @@ ug_status ug_set_flags(void* ctx, int32_t policy, uint32_t flags) {
   p.delay = (flags & UG_F_DELAY) != 0;
   p.batch = (flags & UG_F_BATCH) != 0;
   p.calibrate = (flags & UG_F_CALIBRATE) != 0;
+  p.admit = (flags & UG_F_ADMIT) != 0;
   return UG_OK;
 }
 

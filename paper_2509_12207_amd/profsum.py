@@ -48,7 +48,7 @@ TRAFFIC_KERNELS = {
                 "paper_2509_12207_amd/csrc/kernels/conv3x3_f32.hip"),
     "bias_relu": (r"bias_relu_vec<0", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
     "rowsum": (r"rowsum_block", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
-    "softmax": (r"softmax_reg<4, 4>", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
+    "softmax": (r"softmax_reg<4, 4, ", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
     "voxel": (r"voxel_(init|scatter|finalize|count|scan|place|reduce|merge)", 5,
               "paper_2509_12207_amd/csrc/kernels/voxel.hip"),
     "gemm_fp8": (r"gemm_fp8_kernel", 1, "paper_2509_12207_amd/csrc/kernels/gemm_fp8.hip"),

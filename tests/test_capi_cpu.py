@@ -140,7 +140,8 @@ def _register(g, chains):
 def _flags(cfg):
     return ((capi.F_BIND if cfg.get("bind", True) else 0) | (capi.F_DELAY if cfg.get("delay", True) else 0)
             | (capi.F_BATCH if cfg.get("batch", True) else 0)
-            | (capi.F_CALIBRATE if cfg.get("calibrate", False) else 0))
+            | (capi.F_CALIBRATE if cfg.get("calibrate", False) else 0)
+            | (capi.F_ADMIT if cfg.get("admit", False) else 0))
 
 
 def _gate_for(cfg):
@@ -149,7 +150,8 @@ def _gate_for(cfg):
                      flags=_flags(cfg), delta_eval_ns=cfg.get("delta_eval_ns", 500_000),
                      delay_poll_ns=cfg.get("delay_poll_ns", 1_000_000),
                      th_slack_ns=cfg.get("th_slack_ns", 0),
-                     calib_period_ns=cfg.get("calib_period_ns", 1_000_000))
+                     calib_period_ns=cfg.get("calib_period_ns", 1_000_000),
+                     admit_tasks=cfg.get("admit_tasks", 4))
 
 
 CFGS = [
@@ -160,6 +162,8 @@ CFGS = [
     {"policy": "urgency", "batch": False, "bind": False, "th_slack_ns": 2 * MS},
     {"policy": "urgency", "delay": False, "th_slack_ns": 0, "calibrate": True},
     {"policy": "urgency", "th_slack_ns": 2 * MS, "calibrate": True, "calib_period_ns": 0},
+    {"policy": "urgency", "th_slack_ns": 2 * MS, "admit": True, "admit_tasks": 2},
+    {"policy": "urgency", "th_slack_ns": 0, "admit": True, "admit_tasks": 1, "lanes": [1, 2]},
     {"policy": "urgency", "th_slack_ns": 4 * MS, "lanes": [1]},
     {"policy": "fifo"},
 ]
