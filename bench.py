@@ -39,7 +39,7 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10, help="timed one-second windows per policy")
+    ap.add_argument("--steps", type=int, default=20, help="timed one-second windows per policy")
     ap.add_argument("--warmup", type=int, default=2, help="untimed one-second windows")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--f-a", type=float, default=1.0, help="arrival-rate factor")
@@ -65,12 +65,15 @@ def parse():
 # Sweeps (the paper's ablation structure, Sec. 6): each point runs the FIFO
 # baseline and urgency-gate variants on the same arrivals; every urgency
 # variant calibrates TH_urgent on the warm-up windows with its own settings.
-FULL = 1 | 2 | 4          # UG_F_BIND | UG_F_DELAY | UG_F_BATCH
+PAPER = 1 | 2 | 4         # UG_F_BIND | UG_F_DELAY | UG_F_BATCH: the paper's mechanisms
+ADMIT = 16                # UG_F_ADMIT: task admission, the stand-in for stream priorities
+FULL = PAPER | ADMIT      # the gate as benchmarked
 SWEEPS = {
     # mechanism ablation (Sec. 6.4): each mechanism alone, all, none
     "ablation": [{"name": "none", "flags": 0}, {"name": "bind", "flags": 1 | 4},
                  {"name": "delay", "flags": 2 | 4}, {"name": "batch", "flags": 4},
-                 {"name": "bind+delay", "flags": 1 | 2}, {"name": "full", "flags": FULL}],
+                 {"name": "bind+delay", "flags": 1 | 2}, {"name": "paper", "flags": PAPER},
+                 {"name": "admit", "flags": 4 | ADMIT}, {"name": "full", "flags": FULL}],
     # batching window Delta_eval (Sec. 4.4.5)
     "delta": [{"name": f"delta_{d}ms", "cfg": {"delta_eval_ns": int(d * MS)}}
               for d in (0.1, 0.25, 0.5, 1.0, 2.0)],
@@ -88,8 +91,8 @@ SWEEPS = {
     # run-to-run and seed spread at the default point
     "seeds": [{"name": "default"}],
     # urgency-ordered admission under a cap on launched, unconfirmed work
-    "admit": [{"name": "full"}]
-    + [{"name": f"admit_{n}", "flags": FULL | 16, "cfg": {"admit_tasks": n}}
+    "admit": [{"name": "paper", "flags": PAPER}]
+    + [{"name": f"admit_{n}", "flags": FULL, "cfg": {"admit_tasks": n}}
        for n in (2, 3, 4, 6, 8)],
 }
 
@@ -486,12 +489,12 @@ def main():
 
     # TH_urgent: run the warm-up windows with delayed launching off and
     # calibration sampling on, take the TH_PCT-th percentile (Sec. 4.4.3)
-    urg.set_flags(capi.F_BIND | capi.F_BATCH | capi.F_CALIBRATE)
+    urg.set_flags((FULL & ~capi.F_DELAY) | capi.F_CALIBRATE)
     urg.set_threshold(0)
     run_policy(urg, dw, warm, torch, be=be_warm)
     th = urg.calibration_threshold(TH_PCT)
     urg.set_threshold(th)
-    urg.set_flags(capi.F_BIND | capi.F_DELAY | capi.F_BATCH)
+    urg.set_flags(FULL)
     log(f"TH_urgent calibrated: slack {th / 1e6:.3f} ms")
 
     # timed: urgency gate

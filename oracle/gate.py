@@ -130,7 +130,7 @@ DEFAULT_CFG = {
     "lanes": [2, 6],            # streams per level; len = number of levels
     "calibrate": False,
     "calib_period_ns": 1_000_000,  # sample the highest urgency at most once per period
-    "admit": False,             # urgency-ordered task admission (no stream priorities)
+    "admit": True,              # urgency-ordered task admission (no stream priorities)
     "admit_tasks": 4,           # instances with kernels in flight before new tasks wait
 }
 

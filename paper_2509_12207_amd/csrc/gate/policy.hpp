@@ -33,7 +33,7 @@ namespace ug {
 
 struct PolicyConfig {
   int policy = UG_POLICY_URGENCY;
-  bool bind = true, delay = true, batch = true, calibrate = false, admit = false;
+  bool bind = true, delay = true, batch = true, calibrate = false, admit = true;
   int64_t admit_tasks = 4;             // tasks in flight before new ones wait
   int64_t delta_eval_ns = 500000;
   int64_t delay_poll_ns = 1000000;

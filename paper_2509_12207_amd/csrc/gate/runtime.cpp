@@ -373,7 +373,7 @@ void ug_config_default(ug_config* cfg) {
   std::memset(cfg, 0, sizeof(*cfg));
   cfg->abi_version = UG_ABI_VERSION;
   cfg->policy = UG_POLICY_URGENCY;
-  cfg->flags = UG_F_BIND | UG_F_DELAY | UG_F_BATCH;
+  cfg->flags = UG_F_BIND | UG_F_DELAY | UG_F_BATCH | UG_F_ADMIT;
   cfg->device = 0;
   cfg->delta_eval_ns = 500000;
   cfg->delay_poll_ns = 1000000;

@@ -14,11 +14,12 @@
 //
 // Workgroup tile 256 x 256, four waves of 128 x 128 (4 x 4 instructions per
 // 64-byte K slice, 256 accumulators per lane).  K advances 128 bytes a step:
-// the next step is fetched into registers (16 x 16 bytes a lane) while the
-// current one, in LDS, feeds the matrix cores; one barrier per step, two LDS
-// stages of 2 x 256 rows x 144 bytes (rows padded by 16 bytes so the 16-byte
-// fragment reads of 16 consecutive rows hit distinct banks).  Workgroups are
-// remapped so each XCD computes a contiguous band of output tiles.
+// the next step is fetched into registers (16 x 16 bytes a lane, loads
+// without branches) while the current one, in LDS, feeds the matrix cores;
+// one barrier per step, two LDS stages of 2 x 256 rows x 144 bytes (rows
+// padded by 16 bytes so the 16-byte fragment reads of 16 consecutive rows
+// hit distinct banks).  Workgroups are remapped so each XCD computes a
+// contiguous band of output tiles.
 #include "mfma.hpp"
 #include "ops.hpp"
 
@@ -76,28 +77,28 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_kernel(const unsigned char* _
   const int m0 = tm * BM, n0 = tn * BN;
 
   // global -> register mapping: chunk c = tid + 256 u covers LDS row c / 8
-  // (rows 0..255 of A, 256..511 of Bt), bytes 16 (c % 8) of the step
-  const unsigned char* src[CHUNKS];
-  bool live[CHUNKS];
-#pragma unroll
-  for (int u = 0; u < CHUNKS; ++u) {
-    const int c = tid + 256 * u;
-    const int r = c >> 3, part = c & 7;
-    const bool isa = r < BM;
-    const int64_t grow = isa ? (int64_t)m0 + r : (int64_t)n0 + (r - BM);
-    live[u] = grow < (isa ? M : N);
-    src[u] = (isa ? A : Bt) + (live[u] ? grow : 0) * (int64_t)K + 16 * part;
-  }
-  uint4 reg[CHUNKS];
-  auto fetch = [&](int k0) {
+  // (rows 0..255 of A, 256..511 of Bt), bytes 16 (c % 8) of the step, i.e.
+  // row rA + 32 u of A (u < 8) or rB + 32 (u - 8) of Bt.  Chunks of rows
+  // past M or N, or past K, are zeroed: the loads themselves are
+  // unconditional (no branches in the stream).
+  const int part = tid & 7;
+  const int rA = m0 + (tid >> 3), rB = n0 + (tid >> 3);
+  auto fetch = [&](uint4 (&reg)[CHUNKS], int k0) {
+    const bool kin = k0 + 16 * part < K;
 #pragma unroll
     for (int u = 0; u < CHUNKS; ++u) {
-      const int k = k0 + 16 * ((tid + 256 * u) & 7);
-      reg[u] = (live[u] && k < K) ? *reinterpret_cast<const uint4*>(src[u] + k0)
-                                  : make_uint4(0, 0, 0, 0);
+      const bool isa = u < CHUNKS / 2;
+      const int row = (isa ? rA : rB) + 32 * (u % (CHUNKS / 2));
+      const bool ok = row < (isa ? M : N) && kin;
+      // a zeroed chunk reads the first 16 bytes of its matrix (always there:
+      // K >= 16), never past the end
+      const unsigned char* X = isa ? A : Bt;
+      const unsigned char* p = ok ? X + (int64_t)row * K + 16 * part + k0 : X;
+      const uint4 v = *reinterpret_cast<const uint4*>(p);
+      reg[u] = ok ? v : make_uint4(0, 0, 0, 0);
     }
   };
-  auto stash = [&](int stage) {
+  auto stash = [&](const uint4 (&reg)[CHUNKS], int stage) {
     unsigned char* base = lds + stage * STAGE;
 #pragma unroll
     for (int u = 0; u < CHUNKS; ++u) {
@@ -112,14 +113,9 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_kernel(const unsigned char* _
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = zero16();
 
-  const int steps = (K + BK - 1) / BK;
-  fetch(0);
-  stash(0);
-  __syncthreads();
   const int g = lane >> 5, r32 = lane & 31;
-  for (int s = 0; s < steps; ++s) {
-    if (s + 1 < steps) fetch((s + 1) * BK);
-    const unsigned char* base = lds + (s & 1) * STAGE;
+  auto compute = [&](int stage) {
+    const unsigned char* base = lds + stage * STAGE;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 64) {
       i32x8 a[4], b[4];
@@ -135,8 +131,22 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_kernel(const unsigned char* _
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i], b[j], acc[i][j], 0, 0,
                                                                       0, 127, 0, 127);
+      // keep each 64-byte slice's operands live on their own (64 VGPRs)
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (s + 1 < steps) stash((s + 1) & 1);
+  };
+
+  // the next step is fetched into registers while the current one, in LDS,
+  // feeds the matrix cores
+  const int steps = (K + BK - 1) / BK;
+  uint4 reg[CHUNKS];
+  fetch(reg, 0);
+  stash(reg, 0);
+  __syncthreads();
+  for (int s = 0; s < steps; ++s) {
+    if (s + 1 < steps) fetch(reg, (s + 1) * BK);
+    compute(s & 1);
+    if (s + 1 < steps) stash(reg, (s + 1) & 1);
     __syncthreads();
   }
 

@@ -4,8 +4,9 @@
 // line, in the record format of include/ug.h.
 //
 // input:
-//   cfg <policy> <bind> <delay> <batch> <calibrate> <delta> <poll> <th> <exempt> <nlevels> <lanes...>
-//   chain <deadline> <ntasks>
+//   cfg <policy> <bind> <delay> <batch> <calibrate> <delta> <poll> <th> <exempt>
+//       <calib_period> <admit> <admit_tasks> <nlevels> <lanes...>
+//   chain <deadline> <ntasks>        (deadline 0: a best-effort chain)
 //     task <cpu_ns> <nkernels> (<est_ns> <util>)*
 //   instant <t> <narr> <nev>
 //     a <chain> <frame> <t_arr>
@@ -24,10 +25,11 @@ int main() {
   ug::PolicyConfig cfg;
   std::cin >> tok;
   if (tok != "cfg") return 2;
-  int bind, delay, batch, cal, nlev;
+  int bind, delay, batch, cal, admit, nlev;
   std::cin >> cfg.policy >> bind >> delay >> batch >> cal >> cfg.delta_eval_ns >>
-      cfg.delay_poll_ns >> cfg.th_slack_ns >> cfg.util_exempt >> nlev;
-  cfg.bind = bind, cfg.delay = delay, cfg.batch = batch, cfg.calibrate = cal;
+      cfg.delay_poll_ns >> cfg.th_slack_ns >> cfg.util_exempt >> cfg.calib_period_ns >> admit >>
+      cfg.admit_tasks >> nlev;
+  cfg.bind = bind, cfg.delay = delay, cfg.batch = batch, cfg.calibrate = cal, cfg.admit = admit;
   cfg.lanes.assign(nlev, 0);
   for (int i = 0; i < nlev; ++i) std::cin >> cfg.lanes[i];
   ug::Policy pol(cfg);
@@ -38,6 +40,7 @@ int main() {
       ug::ChainSpec ch;
       int nt;
       std::cin >> ch.deadline_ns >> nt;
+      ch.best_effort = ch.deadline_ns == 0;
       for (int j = 0; j < nt; ++j) {
         std::string t;
         int64_t cpu;

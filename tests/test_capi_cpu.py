@@ -80,7 +80,8 @@ def test_config_defaults_and_errors():
     assert cfg.abi_version == capi.ABI_VERSION
     assert cfg.delta_eval_ns == 500_000 and cfg.delay_poll_ns == 1_000_000
     assert abs(cfg.util_exempt - 0.1) < 1e-7
-    assert cfg.flags == capi.F_BIND | capi.F_DELAY | capi.F_BATCH
+    assert cfg.flags == capi.F_BIND | capi.F_DELAY | capi.F_BATCH | capi.F_ADMIT
+    assert cfg.admit_tasks == 4
     assert cfg.calib_period_ns == 1_000_000 and list(cfg.lanes[:cfg.n_levels]) == [2, 6]
     bad = capi.Config()
     L.ug_config_default(C.byref(bad))
@@ -141,7 +142,7 @@ def _flags(cfg):
     return ((capi.F_BIND if cfg.get("bind", True) else 0) | (capi.F_DELAY if cfg.get("delay", True) else 0)
             | (capi.F_BATCH if cfg.get("batch", True) else 0)
             | (capi.F_CALIBRATE if cfg.get("calibrate", False) else 0)
-            | (capi.F_ADMIT if cfg.get("admit", False) else 0))
+            | (capi.F_ADMIT if cfg.get("admit", True) else 0))
 
 
 def _gate_for(cfg):
@@ -156,7 +157,8 @@ def _gate_for(cfg):
 
 CFGS = [
     {"policy": "urgency", "th_slack_ns": 3 * MS},
-    {"policy": "urgency", "th_slack_ns": 3 * MS, "delay_poll_ns": 0},
+    {"policy": "urgency", "th_slack_ns": 3 * MS, "admit": False},
+    {"policy": "urgency", "th_slack_ns": 3 * MS, "delay_poll_ns": 0, "admit": False},
     {"policy": "urgency", "th_slack_ns": 0, "lanes": [1, 1]},
     {"policy": "urgency", "th_slack_ns": 2 * MS, "lanes": [2, 3, 1, 2]},
     {"policy": "urgency", "batch": False, "bind": False, "th_slack_ns": 2 * MS},

@@ -50,12 +50,14 @@ def _tuple(line):
 def _encode(chains, cfg, instants):
     c = {"policy": "urgency", "bind": True, "delay": True, "batch": True, "calibrate": False,
          "delta_eval_ns": 500_000, "delay_poll_ns": 1_000_000, "th_slack_ns": 0,
-         "util_exempt": 0.1, "lanes": [2, 6]}
+         "util_exempt": 0.1, "calib_period_ns": 1_000_000, "admit": True, "admit_tasks": 4,
+         "lanes": [2, 6]}
     c.update(cfg)
     lines = [" ".join(str(x) for x in ["cfg", 1 if c["policy"] == "urgency" else 0, int(c["bind"]),
                                        int(c["delay"]), int(c["batch"]), int(c["calibrate"]),
                                        c["delta_eval_ns"], c["delay_poll_ns"], c["th_slack_ns"],
-                                       c["util_exempt"], len(c["lanes"]), *c["lanes"]])]
+                                       c["util_exempt"], c["calib_period_ns"], int(c["admit"]),
+                                       c["admit_tasks"], len(c["lanes"]), *c["lanes"]])]
     for ch in chains:
         lines.append(f"chain {ch['deadline_ns']} {len(ch['tasks'])}")
         for t in ch["tasks"]:
@@ -80,7 +82,9 @@ def test_sanitized_policy_matches_oracle(driver, seed):
                           "est_ns": [int(r.integers(20, 400)) * US for _ in range(n)],
                           "util": [float(r.choice([0.05, 0.1, 0.5, 1.0])) for _ in range(n)]})
         period = int(r.integers(3, 12)) * MS
-        chains.append({"deadline_ns": int(period * r.choice([0.5, 1.0])), "tasks": tasks})
+        # one chain in five is best-effort (deadline 0)
+        deadline = 0 if r.random() < 0.2 else int(period * r.choice([0.5, 1.0]))
+        chains.append({"deadline_ns": deadline, "tasks": tasks})
         phase = int(r.integers(0, period))
         for f in range(int(r.integers(2, 6))):
             arrivals.append((ci, f, phase + f * period + int(r.integers(0, 500)) * US))
@@ -94,6 +98,7 @@ def test_sanitized_policy_matches_oracle(driver, seed):
 
     for cfg in ({"th_slack_ns": 3 * MS}, {"th_slack_ns": 3 * MS, "delay_poll_ns": 0},
                 {"th_slack_ns": 0, "lanes": [2, 8, 8], "calibrate": True, "delay": False},
+                {"th_slack_ns": 2 * MS, "admit": False}, {"th_slack_ns": 0, "admit_tasks": 1},
                 {"policy": "fifo"}):
         res = des.simulate(chains, cfg, arrivals, dur)
         text = _encode(chains, cfg, res["instants"])
