@@ -151,9 +151,9 @@ def run_policy(g, dw, arrivals, torch, be=None):
     g.drain(120.0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    g.stop()
     m = g.metrics()
     st = g.stats()
-    g.stop()
     return comps, m, st, t1 - t0
 
 
@@ -168,6 +168,41 @@ def per_chain(comps, wl):
         out.append([c, int(sel["missed"].sum()), int(len(sel)), round(ch.deadline_ns / 1e6, 1),
                     round(float(np.percentile(sel["latency_ns"], 99)) / 1e6, 1)])
     return out
+
+
+def pooled(runs, wl, n_frames, be_rate):
+    """Metrics over the frames of several runs of the same arrivals: Eq. 3 from
+    the per-chain counts, nearest-rank percentiles of the pooled latencies
+    (deadline chains only), and the summed gate counters."""
+    import numpy as np
+    comps = np.concatenate([r[0] for r in runs])
+    dl = comps[np.isin(comps["chain"], [c for c, ch in enumerate(wl.chains) if ch.deadline_ns])]
+    ratios = []
+    for c, ch in enumerate(wl.chains):
+        sel = dl[dl["chain"] == c]
+        if len(sel):
+            ratios.append(sel["missed"].sum() / len(sel))
+    lat = np.sort(dl["latency_ns"])
+    n = len(lat)
+
+    def pct(p):
+        return round(float(lat[max(0, -(-p * n // 100) - 1)]) / 1e6, 3) if n else None
+    wall = sum(r[3] for r in runs)
+    st = {k: sum(int(r[2][k]) for r in runs) for k in ("launches", "holds", "batches",
+                                                        "instants", "decide_ns", "launch_ns",
+                                                        "collisions")}
+    out = {"miss_ratio_pct": round(100.0 * float(np.mean(ratios)) if ratios else 0.0, 3),
+           "p50_ms": pct(50), "p99_ms": pct(99), "max_ms": round(float(lat[-1]) / 1e6, 3) if n else None,
+           "mean_ms": round(float(lat.mean()) / 1e6, 3) if n else None,
+           "frames": int(n), "missed": int(dl["missed"].sum()), "runs": len(runs),
+           "frames_per_s": round(len(runs) * n_frames / wall, 2),
+           "launches": st["launches"], "holds": st["holds"], "batches": st["batches"],
+           "instants": st["instants"], "collisions": st["collisions"],
+           "gate_decide_us_per_instant": round(st["decide_ns"] / max(1, st["instants"]) / 1e3, 3),
+           "launch_us_per_launch": round(st["launch_ns"] / max(1, st["launches"]) / 1e3, 3),
+           "per_run_miss_ratio_pct": [round(100.0 * r[1]["miss_ratio"], 3) for r in runs],
+           "per_chain": per_chain(comps, wl)}
+    return out | be_rate(comps, wall)
 
 
 def summarise(m, st, wall, n_frames):
@@ -444,13 +479,21 @@ def main():
         print(json.dumps({"kernels": kernels, "copy_bytes_each_way": a.numel() * 4}), flush=True)
         return
     W, K = args.warmup, args.steps
+    # the timed arrival sequence lasts K/2 windows; each policy runs it twice,
+    # in the order urgency, FIFO, FIFO, urgency, so that drift over the run
+    # (clocks, caches, queues) cancels: K windows per policy in all
+    if K < 2 or K % 2:
+        print("--steps must be even and >= 2 (two runs of K/2 windows per policy)",
+              file=sys.stderr)
+        sys.exit(2)
+    H = K // 2
     if args.overload:
-        wl = synth.config4(seed=args.seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + K))
+        wl = synth.config4(seed=args.seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + H))
         c_be = wl.meta["be_chain"]
         be_warm = (c_be, wl.meta["be_depth"], W * 10 ** 9)
-        be_timed = (c_be, wl.meta["be_depth"], K * 10 ** 9)
+        be_timed = (c_be, wl.meta["be_depth"], H * 10 ** 9)
     else:
-        wl = synth.config1(seed=args.seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + K))
+        wl = synth.config1(seed=args.seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + H))
         c_be, be_warm, be_timed = None, None, None
     warm = [(c, f, t) for c, f, t in wl.arrivals if t < W * 1e9]
     timed = [(c, f, t - W * 10 ** 9) for c, f, t in wl.arrivals if t >= W * 1e9]
@@ -506,24 +549,29 @@ def main():
         d, kpf = wl.meta["be_dim"], wl.meta["be_gemms"]
         return {"be_frames": n, "be_tflops": round(n * kpf * 2 * d ** 3 / wall / 1e12, 1)}
 
-    comps_u, m_u, st_u, wall_u = run_policy(urg, dw, timed, torch, be=be_timed)
-    urg_sum = (summarise(m_u, st_u, wall_u, len(timed)) | be_rate(comps_u, wall_u)
-               | {"per_chain": per_chain(comps_u, wl)})
-    log("urgency:", json.dumps(urg_sum))
-    collisions = urg.stats()["collisions"]
-    urg_sum["collisions"] = int(collisions)
-
-    fifo_sum = None
+    fifo = None
     if not args.no_fifo:
         fifo = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16)
         for (c, k), (e, u) in est.items():
             fifo.set_estimate(c, k, e, u)
         run_policy(fifo, dw, warm[: len(warm) // 2], torch)     # warm the FIFO streams
-        comps_f, m_f, st_f, wall_f = run_policy(fifo, dw, timed, torch, be=be_timed)
-        fifo_sum = (summarise(m_f, st_f, wall_f, len(timed)) | be_rate(comps_f, wall_f)
-                    | {"per_chain": per_chain(comps_f, wl)})
+    runs = {"urgency": [], "fifo": []}
+    order = [("urgency", urg), ("fifo", fifo), ("fifo", fifo), ("urgency", urg)]
+    for name, g in order:
+        if g is None:
+            continue
+        comps, m, st, wall = run_policy(g, dw, timed, torch, be=be_timed)
+        runs[name].append((comps, m, st, wall))
+        log(f"{name} run {len(runs[name])}:",
+            json.dumps(summarise(m, st, wall, len(timed)) | be_rate(comps, wall)))
+    urg_sum = pooled(runs["urgency"], wl, len(timed), be_rate)
+    log("urgency:", json.dumps(urg_sum))
+    fifo_sum = None
+    if fifo is not None:
+        fifo_sum = pooled(runs["fifo"], wl, len(timed), be_rate)
         log("fifo:", json.dumps(fifo_sum))
         fifo.close()
+    wall_u = sum(r[3] for r in runs["urgency"])
     urg.close()
     del dw
     torch.cuda.empty_cache()
@@ -567,7 +615,8 @@ def main():
                       "frame, " if args.overload else "")
                    + "urgency gate vs FIFO",
                    "be_frame_ms": round(be_frame_ns / 1e6, 3) if args.overload else None,
-                   "seed": args.seed, "f_a": args.f_a, "f_d": args.f_d, "window_s": K,
+                   "seed": args.seed, "f_a": args.f_a, "f_d": args.f_d, "window_s": H,
+                   "runs_per_policy": 2, "order": "urgency, fifo, fifo, urgency",
                    "frames": len(timed), "kernels_per_round": n_kernels,
                    "isolated_utilisation": round(util, 3), "th_urgent_slack_ms": round(th / 1e6, 3)},
         "urgency": urg_sum,

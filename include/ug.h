@@ -311,6 +311,8 @@ ug_status ug_drain(void* ctx, int64_t timeout_ns);
  * context can be restarted with ug_start (e.g. after ug_set_threshold). */
 ug_status ug_stop(void* ctx);
 
+/* Counters since the last ug_start (submissions, completions, launches,
+ * holds, batches, decision instants, time spent deciding and launching). */
 ug_status ug_get_stats(void* ctx, ug_stats* out);
 
 /* Copies up to cap records of the decision log into out and removes them

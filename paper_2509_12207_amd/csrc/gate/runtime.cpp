@@ -678,6 +678,12 @@ ug_status ug_start(void* ctx) {
     c->chain_done.assign(c->policy.chains().size(), 0);
     c->chain_missed.assign(c->policy.chains().size(), 0);
   }
+  // counters cover the frames since this start, like the metrics
+  for (auto* a : {&c->st_submitted, &c->st_completed, &c->st_missed, &c->st_launches,
+                  &c->st_holds, &c->st_batches, &c->st_instants})
+    a->store(0);
+  c->st_decide_ns.store(0);
+  c->st_launch_ns.store(0);
   c->stop.store(false);
   c->started = true;
   c->thr = std::thread(gate_main, c);
