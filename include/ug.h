@@ -64,10 +64,13 @@ enum {
   UG_F_DELAY = 2u,     /* delayed launching (4.4.4)                          */
   UG_F_BATCH = 4u,     /* batched launching with batch overlap (4.4.5)       */
   UG_F_CALIBRATE = 8u, /* record highest-urgency samples for TH_urgent (4.4.3) */
-  UG_F_ADMIT = 16u     /* urgency-ordered admission: a task that is not truly
+  UG_F_ADMIT = 16u,    /* urgency-ordered admission: a task that is not truly
                           urgent starts only while fewer than admit_tasks
                           instances have kernels in flight (stands in for
                           stream priorities, see ug_config)               */
+  UG_F_EXIT = 32u      /* early chain exit (Sec. 4.3): a frame whose urgency
+                          is negative when a task would start leaves the
+                          chain; it completes as missed and exited        */
 };
 
 /* Operations.  Shapes and slot meaning per op; all float buffers are fp32,
@@ -167,10 +170,11 @@ typedef struct {
   int64_t t_arr_ns;
   int64_t t_done_ns;       /* when the gate observed the last kernel done   */
   int64_t latency_ns;      /* t_done - t_arr                                */
-  int32_t missed;          /* latency > deadline                            */
+  int32_t missed;          /* latency > deadline, or exited                 */
   int32_t n_holds;         /* launches of this frame that were held         */
   int32_t n_batches;       /* launch batches of this frame                  */
-  int32_t pad1;
+  int32_t exited;          /* left the chain early (UG_F_EXIT); t_done is
+                              the time it left, its later tasks never ran    */
 } ug_completion;
 
 /* Decision-log record.  The log is a sequence of instants; each INSTANT
@@ -180,6 +184,8 @@ typedef struct {
  *   ARRIVE   chain, frame, t = t_arr
  *   EVDONE   chain, frame, task, a = kind (0 batch start, 1 task end), b = seq
  *   COMPLETE chain, frame, t = t_done
+ *   EXIT     chain, frame, task, t: the frame leaves its chain instead of
+ *            starting task (early chain exit)
  *   TSTART   chain, frame, task
  *   BIND     chain, frame, task, a = level, b = lane
  *   HOLD     chain, frame, kernel
@@ -190,7 +196,7 @@ typedef struct {
 enum {
   UG_REC_INSTANT = 1, UG_REC_ARRIVE = 2, UG_REC_EVDONE = 3, UG_REC_COMPLETE = 4,
   UG_REC_TSTART = 5, UG_REC_BIND = 6, UG_REC_HOLD = 7, UG_REC_EVREC = 8,
-  UG_REC_LAUNCH = 9
+  UG_REC_LAUNCH = 9, UG_REC_EXIT = 10
 };
 typedef struct {
   int32_t type;

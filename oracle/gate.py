@@ -37,6 +37,7 @@ Decision records (tuples):
     ("BIND",     c, f, j, level, lane)
     ("HOLD",     c, f, g)
     ("EVREC",    c, f, j, kind, seq)      kind 0 = batch start, 1 = task end
+    ("EXIT",     c, f, j)                 early chain exit instead of starting task j
     ("LAUNCH",   c, f, g, level, lane)
 where c = chain, f = frame index within the chain, j = task, g = kernel index
 within the chain (kernels of all tasks numbered in order).  For a batch-start
@@ -132,6 +133,7 @@ DEFAULT_CFG = {
     "calib_period_ns": 1_000_000,  # sample the highest urgency at most once per period
     "admit": True,              # urgency-ordered task admission (no stream priorities)
     "admit_tasks": 4,           # instances with kernels in flight before new tasks wait
+    "exit": False,              # early chain exit (Sec. 4.3)
 }
 
 
@@ -163,6 +165,7 @@ class GateModel:
         self.samples = []                              # slacks for TH_urgent
         self.next_sample = None                        # earliest time of the next sample
         self.completed = []                            # (c, f, t_arr, t_done)
+        self.exited = set()                            # (c, f) that left their chain
         self.last_snapshot = {}
 
     # ------------------------------------------------------------------
@@ -230,12 +233,21 @@ class GateModel:
         for inst in sorted(finished, key=lambda i: i.key):
             out.append(("COMPLETE", inst.c, inst.f, t))
             self.completed.append((inst.c, inst.f, inst.t_arr, t))
-        # 2. tasks whose predecessor (in the chain and in the frame order) is done
+        # 2. tasks whose predecessor (in the chain and in the frame order) is
+        #    done.  With early exit, a frame whose urgency is negative when
+        #    its task would start leaves the chain instead (Sec. 4.3)
         for c, ch in enumerate(self.chains):
             for j in range(ch.n_tasks):
-                if self.slot[(c, j)] is None and self.queue[(c, j)]:
+                while self.slot[(c, j)] is None and self.queue[(c, j)]:
                     f = self.queue[(c, j)].popleft()
-                    self._start_task(self.inst[(c, f)], j, t, out)
+                    inst = self.inst[(c, f)]
+                    if self._exits(inst, t):
+                        out.append(("EXIT", c, f, j))
+                        inst.phase = "done"
+                        self.completed.append((c, f, inst.t_arr, t))
+                        self.exited.add((c, f))
+                        continue
+                    self._start_task(inst, j, t, out)
         # 3. CPU segments that have finished
         active = sorted((i for i in self.inst.values() if i.phase != "done"),
                         key=lambda i: i.key)
@@ -266,6 +278,12 @@ class GateModel:
         return out
 
     # ------------------------------------------------------------------
+    def _exits(self, inst, t):
+        """Early chain exit: UL < 0 (the slack is negative) at a task start."""
+        if not (self.urgency_policy and self.cfg["exit"]) or inst.chain.best_effort:
+            return False
+        return self.slack(inst, t) < 0
+
     def _urgent(self, s):
         return P.is_truly_urgent(s, self.cfg["th_slack_ns"])
 

@@ -16,7 +16,7 @@ ABI_VERSION = 2
 
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 POLICY_FIFO, POLICY_URGENCY = 0, 1
-F_BIND, F_DELAY, F_BATCH, F_CALIBRATE, F_ADMIT = 1, 2, 4, 8, 16
+F_BIND, F_DELAY, F_BATCH, F_CALIBRATE, F_ADMIT, F_EXIT = 1, 2, 4, 8, 16, 32
 
 OP_GEMM_F32 = 1
 OP_BIAS_RELU_F32 = 2
@@ -31,7 +31,7 @@ OP_NAMES = {OP_GEMM_F32: "gemm", OP_BIAS_RELU_F32: "bias_relu", OP_CONV3X3_F32: 
 OP_IDS = {v: k for k, v in OP_NAMES.items()}
 
 REC_INSTANT, REC_ARRIVE, REC_EVDONE, REC_COMPLETE = 1, 2, 3, 4
-REC_TSTART, REC_BIND, REC_HOLD, REC_EVREC, REC_LAUNCH = 5, 6, 7, 8, 9
+REC_TSTART, REC_BIND, REC_HOLD, REC_EVREC, REC_LAUNCH, REC_EXIT = 5, 6, 7, 8, 9, 10
 
 EXPORTED = [
     "ug_config_default", "ug_now_ns", "ug_status_str", "ug_create", "ug_destroy",
@@ -68,7 +68,7 @@ class Completion(C.Structure):
     _fields_ = [("chain", C.c_uint32), ("pad0", C.c_uint32), ("frame", C.c_uint64),
                 ("t_arr_ns", C.c_int64), ("t_done_ns", C.c_int64), ("latency_ns", C.c_int64),
                 ("missed", C.c_int32), ("n_holds", C.c_int32), ("n_batches", C.c_int32),
-                ("pad1", C.c_int32)]
+                ("exited", C.c_int32)]
 
 
 class Record(C.Structure):
@@ -97,7 +97,7 @@ RECORD_DTYPE = np.dtype([("type", np.int32), ("chain", np.int32), ("frame", np.i
 COMPLETION_DTYPE = np.dtype([("chain", np.uint32), ("pad0", np.uint32), ("frame", np.uint64),
                              ("t_arr_ns", np.int64), ("t_done_ns", np.int64),
                              ("latency_ns", np.int64), ("missed", np.int32),
-                             ("n_holds", np.int32), ("n_batches", np.int32), ("pad1", np.int32)])
+                             ("n_holds", np.int32), ("n_batches", np.int32), ("exited", np.int32)])
 
 _lib = None
 

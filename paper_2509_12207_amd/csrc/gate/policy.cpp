@@ -171,15 +171,27 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
     finished_.push_back({in.c, in.f, in.t_arr, t, in.n_holds, in.n_batches});
     inst_.erase(k);
   }
-  // 2. task starts, in (chain, task) order
+  // 2. task starts, in (chain, task) order.  With early exit, a frame whose
+  //    urgency is negative (slack < 0) when its task would start leaves the
+  //    chain instead (Sec. 4.3)
+  const bool exiting = cfg_.policy == UG_POLICY_URGENCY && cfg_.exit;
   for (int32_t c = 0; c < static_cast<int32_t>(chains_.size()); ++c) {
-    const int32_t nt = static_cast<int32_t>(chains_[c].task_first.size());
+    const ChainSpec& ch = chains_[c];
+    const int32_t nt = static_cast<int32_t>(ch.task_first.size());
     for (int32_t j = 0; j < nt; ++j) {
       auto& q = queue_[{c, j}];
-      if (slot_[{c, j}] < 0 && !q.empty()) {
+      while (slot_[{c, j}] < 0 && !q.empty()) {
         int64_t f = q.front();
         q.pop_front();
-        start_task(inst_.at({c, f}), j, t, out);
+        Instance& in = inst_.at({c, f});
+        if (exiting && !ch.best_effort &&
+            in.t_arr + ch.deadline_ns - ch.gpu_rem[in.i_gpu] - ch.cpu_rem[in.i_cpu] - t < 0) {
+          out.push_back(rec(UG_REC_EXIT, c, f, j, 0, 0, 0, t));
+          finished_.push_back({c, f, in.t_arr, t, in.n_holds, in.n_batches, true});
+          inst_.erase({c, f});
+          continue;
+        }
+        start_task(in, j, t, out);
       }
     }
   }

@@ -33,7 +33,7 @@ namespace ug {
 
 struct PolicyConfig {
   int policy = UG_POLICY_URGENCY;
-  bool bind = true, delay = true, batch = true, calibrate = false, admit = true;
+  bool bind = true, delay = true, batch = true, calibrate = false, admit = true, exit = false;
   int64_t admit_tasks = 4;             // tasks in flight before new ones wait
   int64_t delta_eval_ns = 500000;
   int64_t delay_poll_ns = 1000000;
@@ -105,6 +105,7 @@ struct Finished {
   int32_t c;
   int64_t f, t_arr, t_done;
   int32_t n_holds, n_batches;
+  bool exited = false;        // left the chain early (negative urgency at a task start)
 };
 
 using Key = std::pair<int32_t, int64_t>;  // (chain, frame)

@@ -136,6 +136,7 @@ ug::PolicyConfig policy_config(const ug_config& cfg) {
   p.th_slack_ns = cfg.th_slack_ns;
   p.calib_period_ns = cfg.calib_period_ns;
   p.admit = (cfg.flags & UG_F_ADMIT) != 0;
+  p.exit = (cfg.flags & UG_F_EXIT) != 0;
   p.admit_tasks = cfg.admit_tasks;
   p.lanes.assign(cfg.lanes, cfg.lanes + cfg.n_levels);
   return p;
@@ -242,12 +243,14 @@ void deliver_completions(Ctx* c) {
     out.latency_ns = f.t_done - f.t_arr;
     // best-effort chains have no deadline: never missed, and outside the
     // miss ratio and the latency percentiles
-    out.missed = (!ch.best_effort && out.latency_ns > ch.deadline_ns) ? 1 : 0;
+    // an exited frame counts as missed and stays out of the latencies
+    out.missed = (!ch.best_effort && (f.exited || out.latency_ns > ch.deadline_ns)) ? 1 : 0;
     out.n_holds = f.n_holds;
     out.n_batches = f.n_batches;
+    out.exited = f.exited ? 1 : 0;
     c->outbox.push_back(out);
     if (!ch.best_effort) {
-      c->latencies.push_back(out.latency_ns);
+      if (!f.exited) c->latencies.push_back(out.latency_ns);
       c->chain_done[f.c] += 1;
       c->chain_missed[f.c] += out.missed;
     }
@@ -646,6 +649,7 @@ ug_status ug_set_flags(void* ctx, int32_t policy, uint32_t flags) {
   p.batch = (flags & UG_F_BATCH) != 0;
   p.calibrate = (flags & UG_F_CALIBRATE) != 0;
   p.admit = (flags & UG_F_ADMIT) != 0;
+  p.exit = (flags & UG_F_EXIT) != 0;
   return UG_OK;
 }
 

@@ -5,7 +5,8 @@ import numpy as np
 from paper_2509_12207_amd import capi
 
 NAMES = {capi.REC_COMPLETE: "COMPLETE", capi.REC_TSTART: "TSTART", capi.REC_BIND: "BIND",
-         capi.REC_HOLD: "HOLD", capi.REC_EVREC: "EVREC", capi.REC_LAUNCH: "LAUNCH"}
+         capi.REC_HOLD: "HOLD", capi.REC_EVREC: "EVREC", capi.REC_LAUNCH: "LAUNCH",
+         capi.REC_EXIT: "EXIT"}
 
 
 def record_to_tuple(r):
@@ -23,6 +24,8 @@ def record_to_tuple(r):
         return ("EVREC", c, f, int(r["task"]), int(r["a"]), int(r["b"]))
     if t == capi.REC_LAUNCH:
         return ("LAUNCH", c, f, int(r["kernel"]), int(r["a"]), int(r["b"]))
+    if t == capi.REC_EXIT:
+        return ("EXIT", c, f, int(r["task"]))
     raise ValueError(t)
 
 

@@ -5,7 +5,7 @@
 //
 // input:
 //   cfg <policy> <bind> <delay> <batch> <calibrate> <delta> <poll> <th> <exempt>
-//       <calib_period> <admit> <admit_tasks> <nlevels> <lanes...>
+//       <calib_period> <admit> <admit_tasks> <exit> <nlevels> <lanes...>
 //   chain <deadline> <ntasks>        (deadline 0: a best-effort chain)
 //     task <cpu_ns> <nkernels> (<est_ns> <util>)*
 //   instant <t> <narr> <nev>
@@ -25,11 +25,12 @@ int main() {
   ug::PolicyConfig cfg;
   std::cin >> tok;
   if (tok != "cfg") return 2;
-  int bind, delay, batch, cal, admit, nlev;
+  int bind, delay, batch, cal, admit, ext, nlev;
   std::cin >> cfg.policy >> bind >> delay >> batch >> cal >> cfg.delta_eval_ns >>
       cfg.delay_poll_ns >> cfg.th_slack_ns >> cfg.util_exempt >> cfg.calib_period_ns >> admit >>
-      cfg.admit_tasks >> nlev;
+      cfg.admit_tasks >> ext >> nlev;
   cfg.bind = bind, cfg.delay = delay, cfg.batch = batch, cfg.calibrate = cal, cfg.admit = admit;
+  cfg.exit = ext;
   cfg.lanes.assign(nlev, 0);
   for (int i = 0; i < nlev; ++i) std::cin >> cfg.lanes[i];
   ug::Policy pol(cfg);

@@ -142,7 +142,8 @@ def _flags(cfg):
     return ((capi.F_BIND if cfg.get("bind", True) else 0) | (capi.F_DELAY if cfg.get("delay", True) else 0)
             | (capi.F_BATCH if cfg.get("batch", True) else 0)
             | (capi.F_CALIBRATE if cfg.get("calibrate", False) else 0)
-            | (capi.F_ADMIT if cfg.get("admit", True) else 0))
+            | (capi.F_ADMIT if cfg.get("admit", True) else 0)
+            | (capi.F_EXIT if cfg.get("exit", False) else 0))
 
 
 def _gate_for(cfg):
@@ -166,6 +167,8 @@ CFGS = [
     {"policy": "urgency", "th_slack_ns": 2 * MS, "calibrate": True, "calib_period_ns": 0},
     {"policy": "urgency", "th_slack_ns": 2 * MS, "admit": True, "admit_tasks": 2},
     {"policy": "urgency", "th_slack_ns": 0, "admit": True, "admit_tasks": 1, "lanes": [1, 2]},
+    {"policy": "urgency", "th_slack_ns": 3 * MS, "exit": True},
+    {"policy": "urgency", "th_slack_ns": 0, "exit": True, "admit": False, "batch": False},
     {"policy": "urgency", "th_slack_ns": 4 * MS, "lanes": [1]},
     {"policy": "fifo"},
 ]

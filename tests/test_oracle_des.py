@@ -147,6 +147,25 @@ def test_best_effort_ranks_last_and_is_not_sampled():
     assert res["completed"] == [(0, 0, 0, 2 * MS)]
 
 
+def test_early_chain_exit():
+    # two tasks of 2 ms each, D = 5 ms; the first frame runs alone and makes
+    # it.  The second frame arrives at 0.5 ms and waits for task 0 until
+    # 2 ms, where its slack is 0.5 + 5 - 4 - 2 = -0.5 ms: it leaves the chain
+    # instead of starting task 0.  A best-effort chain (D = 0) never exits,
+    # and FIFO launch never exits.
+    ch = [chain(5 * MS, [(0, [(2 * MS, 1.0)]), (0, [(2 * MS, 1.0)])]),
+          chain(0, [(0, [(1 * MS, 1.0)])])]
+    arr = [(0, 0, 0), (0, 1, 500 * US), (1, 0, 0)]
+    res = des.simulate(ch, {"policy": "urgency", "exit": True}, arr, by_est(ch))
+    exits = [(t, d) for t, _, _, ds in res["instants"] for d in ds if d[0] == "EXIT"]
+    assert exits == [(2 * MS, ("EXIT", 0, 1, 0))]
+    assert res["gate"].exited == {(0, 1)}
+    done = {(c, f): td for c, f, _, td in res["completed"]}
+    assert done[(0, 1)] == 2 * MS and (1, 0) in done and (0, 0) in done
+    res = des.simulate(ch, {"policy": "fifo", "exit": True}, arr, by_est(ch))
+    assert not any(d[0] == "EXIT" for _, _, _, ds in res["instants"] for d in ds)
+
+
 def test_same_chain_never_blocks_itself():
     # two frames of one chain, pipelined over two tasks; the urgent older
     # frame must not hold the newer one back

@@ -15,7 +15,7 @@ from oracle import des
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2509_12207_amd", "csrc")
 MS, US = 1_000_000, 1_000
-NAMES = {4: "COMPLETE", 5: "TSTART", 6: "BIND", 7: "HOLD", 8: "EVREC", 9: "LAUNCH"}
+NAMES = {4: "COMPLETE", 5: "TSTART", 6: "BIND", 7: "HOLD", 8: "EVREC", 9: "LAUNCH", 10: "EXIT"}
 
 
 @pytest.fixture(scope="module")
@@ -38,7 +38,7 @@ def _tuple(line):
     n = NAMES[ty]
     if n == "COMPLETE":
         return (n, c, fr, t)
-    if n == "TSTART":
+    if n in ("TSTART", "EXIT"):
         return (n, c, fr, task)
     if n == "HOLD":
         return (n, c, fr, k)
@@ -51,13 +51,14 @@ def _encode(chains, cfg, instants):
     c = {"policy": "urgency", "bind": True, "delay": True, "batch": True, "calibrate": False,
          "delta_eval_ns": 500_000, "delay_poll_ns": 1_000_000, "th_slack_ns": 0,
          "util_exempt": 0.1, "calib_period_ns": 1_000_000, "admit": True, "admit_tasks": 4,
-         "lanes": [2, 6]}
+         "exit": False, "lanes": [2, 6]}
     c.update(cfg)
     lines = [" ".join(str(x) for x in ["cfg", 1 if c["policy"] == "urgency" else 0, int(c["bind"]),
                                        int(c["delay"]), int(c["batch"]), int(c["calibrate"]),
                                        c["delta_eval_ns"], c["delay_poll_ns"], c["th_slack_ns"],
                                        c["util_exempt"], c["calib_period_ns"], int(c["admit"]),
-                                       c["admit_tasks"], len(c["lanes"]), *c["lanes"]])]
+                                       c["admit_tasks"], int(c["exit"]), len(c["lanes"]),
+                                       *c["lanes"]])]
     for ch in chains:
         lines.append(f"chain {ch['deadline_ns']} {len(ch['tasks'])}")
         for t in ch["tasks"]:
@@ -99,6 +100,7 @@ def test_sanitized_policy_matches_oracle(driver, seed):
     for cfg in ({"th_slack_ns": 3 * MS}, {"th_slack_ns": 3 * MS, "delay_poll_ns": 0},
                 {"th_slack_ns": 0, "lanes": [2, 8, 8], "calibrate": True, "delay": False},
                 {"th_slack_ns": 2 * MS, "admit": False}, {"th_slack_ns": 0, "admit_tasks": 1},
+                {"th_slack_ns": 2 * MS, "exit": True},
                 {"policy": "fifo"}):
         res = des.simulate(chains, cfg, arrivals, dur)
         text = _encode(chains, cfg, res["instants"])
