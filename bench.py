@@ -90,6 +90,9 @@ SWEEPS = {
     "fd": [{"name": f"fd_{f}", "f_d": f} for f in (0.7, 1.0, 1.5)],
     # run-to-run and seed spread at the default point
     "seeds": [{"name": "default"}],
+    # TH_urgent percentile with admission, with and without early chain exit
+    "threshold_exit": [{"name": f"th_p{p}", "pct": p} for p in (95, 97, 99)]
+    + [{"name": f"th_p{p}_exit", "pct": p, "flags": FULL | 32} for p in (95, 99)],
     # urgency-ordered admission under a cap on launched, unconfirmed work
     "admit": [{"name": "paper", "flags": PAPER}]
     + [{"name": f"admit_{n}", "flags": FULL, "cfg": {"admit_tasks": n}}

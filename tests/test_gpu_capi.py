@@ -108,3 +108,25 @@ def test_two_runs_bit_identical():
         torch.cuda.empty_cache()
     for key in outs[0]:
         assert np.array_equal(outs[0][key].view(np.uint32), outs[1][key].view(np.uint32)), key
+
+
+def test_early_exit_frames_complete_as_missed():
+    # deadlines of 1 us, far below the chains' profiled work: with early
+    # exit every frame leaves its chain at its first task start (negative
+    # urgency) and completes as missed and exited, outside the latencies
+    wl = synth.config0(frames=2)
+    dw = runner.DeviceWorkload(wl, n_sets=1)
+    g = capi.Gate("urgency", flags=capi.F_BIND | capi.F_DELAY | capi.F_BATCH | capi.F_EXIT,
+                  queue_capacity=64)
+    for ch in wl.chains:
+        g.register_chain(ch.period_ns, 1000, ch.tasks, len(ch.buffers))
+    runner.profile(g, dw, warmup=1, reps=2)
+    g.start()
+    comps, _ = runner.run(g, dw, [(c, f, t // 20) for c, f, t in wl.arrivals])
+    g.drain(30.0)
+    g.stop()
+    assert len(comps) == len(wl.arrivals)
+    assert np.all(comps["exited"] == 1) and np.all(comps["missed"] == 1)
+    m = g.metrics()
+    assert m["miss_ratio"] == 1.0 and m["frames"] == 0
+    g.close()
