@@ -57,6 +57,7 @@ struct Ctx {
   bool finalized = false;
 
   std::vector<std::vector<hipStream_t>> level_streams;  // [level][lane]
+  int queue_classes = 0;                                // hardware queues the lanes use
   std::vector<hipStream_t> fifo_streams;                // one per task of every chain
   std::vector<hipEvent_t> event_pool;
   std::vector<hipEvent_t> all_events;
@@ -432,14 +433,40 @@ ug_status ug_create(const ug_config* cfg, void** out) {
     }
     if ((e = hipSetDevice(cfg->device)) != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
     if (cfg->policy == UG_POLICY_URGENCY) {
-      c->level_streams.resize(cfg->n_levels);
-      for (int lv = 0; lv < cfg->n_levels; ++lv)
-        for (int ln = 0; ln < cfg->lanes[lv]; ++ln) {
-          hipStream_t s = nullptr;
-          if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
-            return hip_fail(nullptr, e, "hipStreamCreateWithFlags");
-          c->level_streams[lv].push_back(s);
+      // Lanes are placed round-robin over the hardware queues their streams
+      // landed on (HIP decides that from the process's stream history), so
+      // the first lanes of every level, which binding fills first, never
+      // share a queue while other queues are free.
+      std::vector<hipStream_t> pool;
+      int total = 0;
+      for (int lv = 0; lv < cfg->n_levels; ++lv) total += cfg->lanes[lv];
+      for (int i = 0; i < total; ++i) {
+        hipStream_t s = nullptr;
+        if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) {
+          for (hipStream_t x : pool) (void)hipStreamDestroy(x);
+          return hip_fail(nullptr, e, "hipStreamCreateWithFlags");
         }
+        pool.push_back(s);
+      }
+      std::vector<int> cls;
+      if ((e = ug::stream_queue_classes(pool, &cls)) != hipSuccess) {
+        for (hipStream_t x : pool) (void)hipStreamDestroy(x);
+        return hip_fail(nullptr, e, "hardware-queue probe");
+      }
+      std::vector<std::vector<hipStream_t>> by_queue;
+      for (size_t i = 0; i < pool.size(); ++i) {
+        if (static_cast<size_t>(cls[i]) >= by_queue.size()) by_queue.resize(cls[i] + 1);
+        by_queue[cls[i]].push_back(pool[i]);
+      }
+      std::vector<hipStream_t> order;
+      for (size_t round = 0; order.size() < pool.size(); ++round)
+        for (auto& q : by_queue)
+          if (round < q.size()) order.push_back(q[round]);
+      c->queue_classes = static_cast<int>(by_queue.size());
+      c->level_streams.resize(cfg->n_levels);
+      size_t next = 0;
+      for (int lv = 0; lv < cfg->n_levels; ++lv)
+        for (int ln = 0; ln < cfg->lanes[lv]; ++ln) c->level_streams[lv].push_back(order[next++]);
     }
     for (int i = 0; i < 1024; ++i) {
       hipEvent_t ev = nullptr;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "ug.h"
 
@@ -64,5 +65,11 @@ hipError_t launch_kernel(const ug_kernel& k, void* const* buffers, hipStream_t s
 
 // Main-kernel launch shape of an operation.
 OpPlan plan_kernel(const ug_kernel& k);
+
+// Hardware-queue class of each stream (streams with equal class share a
+// hardware queue), measured with two tiny kernels per pair of streams
+// tested; classes are numbered in order of first appearance.  Synchronous;
+// the device should be otherwise idle.
+hipError_t stream_queue_classes(const std::vector<hipStream_t>& s, std::vector<int>* cls);
 
 }  // namespace ug
