@@ -377,10 +377,10 @@ ug_status ug_kernel_launch(const ug_kernel* k, void* const* buffers,
 ug_status ug_kernel_workspace(const ug_kernel* k, uint64_t* bytes);
 
 /* ug_kernel_launch with a caller-owned device workspace of workspace_bytes
- * (>= ug_kernel_workspace; may be NULL when that is 0), which must stay
- * untouched until the kernel has finished on hip_stream.  It holds no state
- * between launches.  Errors: UG_EINVAL (also: workspace missing or too
- * small), UG_EDEVICE. */
+ * (>= ug_kernel_workspace, 256-byte aligned; may be NULL when that is 0),
+ * which must stay untouched until the kernel has finished on hip_stream.
+ * It holds no state between launches.  Errors: UG_EINVAL (also: workspace
+ * missing, too small or misaligned), UG_EDEVICE. */
 ug_status ug_kernel_launch_ws(const ug_kernel* k, void* const* buffers,
                               uint32_t n_buffers, void* workspace,
                               uint64_t workspace_bytes, void* hip_stream);

@@ -950,7 +950,9 @@ ug_status ug_kernel_launch_ws(const ug_kernel* k, void* const* buffers, uint32_t
       if (s >= 0 && (static_cast<uint32_t>(s) >= n_buffers || !buffers[s])) return UG_EINVAL;
     }
   const size_t need = ug::workspace_bytes(*k);
-  if (need && (!workspace || workspace_bytes < need)) return UG_EINVAL;
+  if (need && (!workspace || workspace_bytes < need ||
+               (reinterpret_cast<uintptr_t>(workspace) & 255)))
+    return UG_EINVAL;
   hipError_t e = ug::launch_kernel(*k, buffers, static_cast<hipStream_t>(hip_stream), workspace,
                                    static_cast<size_t>(workspace_bytes));
   return e == hipSuccess ? UG_OK : UG_EDEVICE;

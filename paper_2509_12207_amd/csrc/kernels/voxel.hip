@@ -19,13 +19,15 @@
 //                stored tile-major in the workspace;
 //     2. scan:   per tile, exclusive offsets of the chunks and the tile total;
 //     3. place:  per chunk, the cell of every point (vidx), and a record
-//                (z key, index, cell in tile) appended to the tile's range;
+//                (z key, index, cell in tile) per point, sorted by tile in
+//                LDS and written as one run per tile;
 //     4. reduce: per segment of at most kSeg records of one tile, count /
 //                max / min in LDS, written out as a partial tile;
 //     5. merge:  per cell, the partial tiles of its tile combined into the
 //                outputs (empty cells: count 0, zmax -inf, first -1).
 //   Global traffic is about 50 bytes per point, with no global atomics.
 #include <climits>
+#include <cstdint>
 
 #include "ops.hpp"
 
@@ -36,6 +38,7 @@ constexpr int kTileBits = 12;
 constexpr int kTileCells = 1 << kTileBits;        // cells per tile (48 KiB of LDS)
 constexpr int kMaxTiles = 1024;                   // binned grids: <= 4 Mi cells
 constexpr int64_t kChunk = 8192;                  // points per count/place block
+static_assert(kChunk <= 65536, "place keeps in-chunk indices in 16 bits");
 constexpr int64_t kSeg = 65536;                   // records per reduce block
 constexpr int64_t kBinnedMinPoints = int64_t(1) << 20;
 constexpr unsigned kKeyNegInf = 0x007fffffu;      // key of -inf
@@ -194,9 +197,12 @@ __global__ __launch_bounds__(256) void voxel_scan(int* __restrict__ H, int* __re
   if (threadIdx.x == 0) tcount[blockIdx.x] = carry;
 }
 
-// 3. cells and records.  Record r of tile t lies in [tbase[t], tbase[t] +
-//    tcount[t]); within a chunk's sub-range the order is arbitrary (the
-//    reductions do not depend on it).
+// 3. cells and records, one chunk per workgroup.  The chunk's records are
+//    first sorted by tile in LDS (a counting sort: the chunk's tile counts
+//    are known from step 1), then written out as one contiguous run per
+//    tile, so that the stores coalesce.  Record r of tile t lies in
+//    [tbase[t], tbase[t] + tcount[t]); within a chunk's run the order is
+//    arbitrary (the reductions do not depend on it).
 __global__ __launch_bounds__(256) void voxel_place(const float4* __restrict__ pts,
                                                    int* __restrict__ vidx,
                                                    const int* __restrict__ H,
@@ -206,16 +212,26 @@ __global__ __launch_bounds__(256) void voxel_place(const float4* __restrict__ pt
                                                    unsigned short* __restrict__ rc, int64_t N,
                                                    int nx, int ny, float xmin, float ymin,
                                                    float scale, int T, int nb) {
-  __shared__ int cur[kMaxTiles + 1];
-  __shared__ int lim[kMaxTiles];
+  __shared__ int gbase[kMaxTiles];     // global position of the chunk's run of tile t
+  __shared__ int loff[kMaxTiles + 1];  // local position of that run (exclusive scan)
+  __shared__ int cur[kMaxTiles];       // local cursors
   __shared__ int wsum[4];
-  block_scan_tiles(T, [&](int i) { return tcount[i]; }, cur, wsum);
-  for (int t = threadIdx.x; t < T; t += 256) {
-    lim[t] = cur[t] + tcount[t];
-    cur[t] += H[(int64_t)t * nb + blockIdx.x];
-  }
+  __shared__ unsigned sz[kChunk];         // z keys, by local position
+  __shared__ unsigned short si[kChunk];   // point index within the chunk
+  __shared__ unsigned short sc[kChunk];   // cell within the tile
+  const int c = blockIdx.x;
+  block_scan_tiles(T, [&](int i) { return tcount[i]; }, loff, wsum);
+  for (int t = threadIdx.x; t < T; t += 256) gbase[t] = loff[t] + H[(int64_t)t * nb + c];
   __syncthreads();
-  const int64_t beg = (int64_t)blockIdx.x * kChunk;
+  // H holds, per tile, the exclusive scan over chunks: this chunk's count of
+  // tile t is the step to the next chunk (or to the tile total)
+  block_scan_tiles(T, [&](int i) {
+    const int64_t h = (int64_t)i * nb + c;
+    return (c + 1 < nb ? H[h + 1] : tcount[i]) - H[h];
+  }, loff, wsum);
+  for (int t = threadIdx.x; t < T; t += 256) cur[t] = loff[t];
+  __syncthreads();
+  const int64_t beg = (int64_t)c * kChunk;
   const int64_t end = beg + kChunk < N ? beg + kChunk : N;
   for (int64_t i = beg + threadIdx.x; i < end; i += 4 * 256) {
     float4 p[4];
@@ -230,15 +246,29 @@ __global__ __launch_bounds__(256) void voxel_place(const float4* __restrict__ pt
         vidx[j] = v;
         if (v >= 0) {
           const int t = v >> kTileBits;
-          const int pos = atomicAdd(&cur[t], 1);
-          if (pos < lim[t]) {  // always true when counting and placing agree
-            rz[pos] = zkey(p[u].z);
-            ri[pos] = (int)j;
-            rc[pos] = (unsigned short)(v & (kTileCells - 1));
+          const int lp = atomicAdd(&cur[t], 1);
+          if (lp < loff[t + 1]) {  // always true when counting and placing agree
+            sz[lp] = zkey(p[u].z);
+            si[lp] = (unsigned short)(j - beg);
+            sc[lp] = (unsigned short)(v & (kTileCells - 1));
           }
         }
       }
     }
+  }
+  __syncthreads();
+  const int n = loff[T];
+  for (int lp = threadIdx.x; lp < n; lp += 256) {
+    // run of lp: the last tile t with loff[t] <= lp (empty runs are skipped)
+    int lo = 0, hi = T - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (loff[mid] <= lp) lo = mid; else hi = mid - 1;
+    }
+    const int pos = gbase[lo] + (lp - loff[lo]);
+    rz[pos] = sz[lp];
+    ri[pos] = (int)(beg + si[lp]);
+    rc[pos] = sc[lp];
   }
 }
 
@@ -277,11 +307,29 @@ __global__ __launch_bounds__(256) void voxel_reduce(const int* __restrict__ tcou
     acc_f[c] = INT_MAX;
   }
   __syncthreads();
-  for (int64_t r = start + threadIdx.x; r < end; r += 256) {
-    const int c = rc[r] & (kTileCells - 1);
-    atomicAdd(&acc_c[c], 1);
-    atomicMax(&acc_z[c], rz[r]);
-    atomicMin(&acc_f[c], ri[r]);
+  // eight records a lane per round (32-, 32- and 16-byte loads: the record
+  // arrays are 256-byte aligned and padded to a multiple of 8 records),
+  // from the multiple of 8 at or below the segment start; records outside
+  // [start, end) are read and skipped
+  for (int64_t r0 = (start & ~int64_t(7)) + 8 * threadIdx.x; r0 < end; r0 += 8 * 256) {
+    const uint4 z0 = *reinterpret_cast<const uint4*>(rz + r0);
+    const uint4 z1 = *reinterpret_cast<const uint4*>(rz + r0 + 4);
+    const int4 f0 = *reinterpret_cast<const int4*>(ri + r0);
+    const int4 f1 = *reinterpret_cast<const int4*>(ri + r0 + 4);
+    const uint4 c8 = *reinterpret_cast<const uint4*>(rc + r0);
+    const unsigned zz[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
+    const int ff[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+    const unsigned cc[4] = {c8.x, c8.y, c8.z, c8.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t r = r0 + k;
+      if (r >= start && r < end) {
+        const int c = (int)((cc[k >> 1] >> (16 * (k & 1))) & (kTileCells - 1));
+        atomicAdd(&acc_c[c], 1);
+        atomicMax(&acc_z[c], zz[k]);
+        atomicMin(&acc_f[c], ff[k]);
+      }
+    }
   }
   __syncthreads();
   const int64_t o = (int64_t)s * kTileCells;
@@ -349,9 +397,11 @@ Binned binned_layout(int64_t N, int64_t G) {
   };
   b.H = take(sizeof(int) * (size_t)b.T * b.nb);
   b.tcount = take(sizeof(int) * (size_t)b.T);
-  b.rz = take(sizeof(unsigned) * (size_t)N);
-  b.ri = take(sizeof(int) * (size_t)N);
-  b.rc = take(sizeof(unsigned short) * (size_t)N);
+  // record arrays padded to a multiple of 8 records (vector loads of eight)
+  const size_t n8 = (size_t)(N + 7) / 8 * 8;
+  b.rz = take(sizeof(unsigned) * n8);
+  b.ri = take(sizeof(int) * n8);
+  b.rc = take(sizeof(unsigned short) * n8);
   b.pc = take(sizeof(int) * (size_t)b.smax * kTileCells);
   b.pz = take(sizeof(unsigned) * (size_t)b.smax * kTileCells);
   b.pf = take(sizeof(int) * (size_t)b.smax * kTileCells);
@@ -389,7 +439,8 @@ hipError_t voxel_f32_launch(const float* pts, int* vidx, int* count, float* zmax
   const float4* p4 = reinterpret_cast<const float4*>(pts);
   if (use_binned(N, G)) {
     const Binned b = binned_layout(N, G);
-    if (!ws || ws_bytes < b.total) return hipErrorInvalidValue;
+    if (!ws || ws_bytes < b.total || (reinterpret_cast<uintptr_t>(ws) & 255))
+      return hipErrorInvalidValue;
     char* w = static_cast<char*>(ws);
     int* H = reinterpret_cast<int*>(w + b.H);
     int* tc = reinterpret_cast<int*>(w + b.tcount);

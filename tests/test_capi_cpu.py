@@ -106,6 +106,24 @@ def test_config_defaults_and_errors():
     g.close()
 
 
+def test_voxel_workspace_size_and_checks():
+    # host-side only: sizes, and the errors returned before anything runs
+    def desc(n, nx=512, ny=512):
+        return {"op": "voxel", "shape": (n, nx, ny), "in": (0,), "out": (1, 2, 3, 4),
+                "fparam": (-51.2, -51.2, 5.0)}
+    assert capi.kernel_workspace(desc(100_000)) == 0            # direct path
+    assert capi.kernel_workspace(desc(1 << 20, 4096, 4096)) == 0  # grid too large to bin
+    n = (1 << 20) + 3
+    need = capi.kernel_workspace(desc(n))
+    n8 = (n + 7) // 8 * 8
+    assert need >= 10 * n8 and need % 256 == 0
+    fake = [0x10000 * (i + 1) for i in range(5)]   # never dereferenced
+    for ws, nbytes in [(0, need), (0x100000, need - 1), (0x100000 + 16, need)]:
+        with pytest.raises(capi.UgError) as e:
+            capi.kernel_launch_ws(desc(n), fake, ws, nbytes)
+        assert e.value.status == capi.EINVAL
+
+
 # ----------------------------------------------------------------------------
 # C++ policy core == oracle gate model, instant by instant
 # ----------------------------------------------------------------------------
