@@ -3,23 +3,33 @@
 //
 // Operands are K-contiguous: A row-major [M, K], B given transposed as
 // Bt [N, K] (row n holds column n of B).  K must be a multiple of 16 (one
-// 16-byte load); M and N are arbitrary (tails are zero-filled on load and
-// masked on store).
+// 16-byte load); M and N are arbitrary (tails are read from the matrix's
+// first row or zero-filled, and never stored).
 //
 // v_mfma_scale_f32_32x32x64_f8f6f4 with both scale exponents 127 (x1):
 // D[32x32] += A[32x64] B[64x32], 131072 FLOP per instruction.  Lane l feeds
-// row (A) or column (B) l % 32 with 32 bytes of K; the K positions of those
-// bytes are given by kpos() below.  The accumulator layout is that of the
-// other 32x32 instructions (mfma32_row).
+// row (A) or column (B) l % 32 with 32 bytes of K, bytes 32 (l / 32) ..
+// 32 (l / 32) + 31 of the 64-byte K slice.  The accumulator layout is that
+// of the other 32x32 instructions (mfma32_row).  Workgroups are remapped so
+// each XCD computes a contiguous band of output tiles.
 //
-// Workgroup tile 256 x 256, four waves of 128 x 128 (4 x 4 instructions per
-// 64-byte K slice, 256 accumulators per lane).  K advances 128 bytes a step:
-// the next step is fetched into registers (16 x 16 bytes a lane, loads
-// without branches) while the current one, in LDS, feeds the matrix cores;
-// one barrier per step, two LDS stages of 2 x 256 rows x 144 bytes (rows
-// padded by 16 bytes so the 16-byte fragment reads of 16 consecutive rows
-// hit distinct banks).  Workgroups are remapped so each XCD computes a
-// contiguous band of output tiles.
+// Two kernels, both with a 256 x 256 workgroup tile:
+//
+// * gemm_fp8_ring (K a multiple of 64): eight waves of 128 x 64 (two per
+//   SIMD, 8 instructions per 64-byte K slice).  Global memory goes straight
+//   to LDS (global_load_lds_dwordx4) into a ring of four 32 KiB stages, three
+//   stages ahead of the matrix cores; the fragments of step s+1 are read from
+//   LDS while step s runs.  One barrier a step.  Rows are 64 bytes with the
+//   four 16-byte chunks of row r XOR-permuted by (r / 4) % 4: a 16-byte read
+//   of sixteen consecutive rows then touches all 64 LDS banks once.
+//   The direct-to-LDS loads are issued from inline assembly so that the
+//   compiler, which cannot tell them apart from the ring slots being read,
+//   does not wait for every load in flight before each LDS read; their
+//   completion is waited for explicitly (vmcnt) before each barrier.
+//
+// * gemm_fp8_kernel (any K multiple of 16): four waves of 128 x 128; the next
+//   128-byte K step is fetched into registers while the current one, in two
+//   padded LDS stages, feeds the matrix cores.
 #include "mfma.hpp"
 #include "ops.hpp"
 
@@ -36,6 +46,8 @@ constexpr int STAGE = ROWS * LDR;   // bytes per stage
 constexpr int CHUNKS = ROWS * BK / 16 / 256;   // 16-byte loads per thread per step
 constexpr int kXcds = 8;
 constexpr int kGroupM = 8;
+// s_waitcnt lgkmcnt(0) with the vmcnt and expcnt fields at their maxima
+constexpr int kWaitLdsOnly = 15 | (3 << 14) | (7 << 4) | (0 << 8);
 
 // K offset (within a 64-byte slice) of the 8-byte piece p (0..3) of lane
 // group g (= lane / 32) of a matrix-core operand.
@@ -163,21 +175,166 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_kernel(const unsigned char* _
     }
 }
 
+
+// ------------------------------------------------------------ ring kernel
+constexpr int RK = 64;                       // bytes of K per step
+constexpr int RNST = 4;                      // ring stages
+constexpr int RSTAGE = (BM + BN) * RK;       // 32 KiB per stage
+constexpr int RWAVES = 8;
+constexpr int RCPT = (BM + BN) * RK / 16 / (64 * RWAVES);   // 16-byte loads per lane per stage
+constexpr int RNF = 2;                       // B fragments per wave (wave tile 128 x 64)
+
+__device__ __forceinline__ int ring_swz(int row) { return (row >> 2) & 3; }
+
+// s_waitcnt vmcnt(N): all but this wave's N most recent ring loads are in LDS
+template <int N>
+__device__ __forceinline__ void ring_wait_loads() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"i"(N) : "memory");
+}
+
+// One 16-byte direct-to-LDS load: lane l writes LDS bytes [lds + 16 l, +16).
+// M0 holds the wave's LDS base; one wait state between writing M0 and the
+// load that reads it.  M0 has no other use in this kernel.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void ring_load16(const unsigned char* g, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+__global__ __launch_bounds__(64 * RWAVES, 1) void gemm_fp8_ring(const unsigned char* __restrict__ A,
+                                                                const unsigned char* __restrict__ Bt,
+                                                                float* __restrict__ C, int M, int N,
+                                                                int K) {
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[RNST * RSTAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;   // 2 x 4 waves
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  int tm, tn;
+  tile_of(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int steps = K / RK;
+
+  // A stage is 512 rows (256 of A, then 256 of Bt) of 64 bytes = 2048
+  // chunks; load i of wave w fills the 1 KiB block w * RCPT + i, lane l the
+  // chunk q = 64 (w RCPT + i) + l: row q / 4, stored chunk q % 4, which
+  // holds K chunk (q % 4) ^ ring_swz(row).  Rows past M or N read the
+  // matrix's first row (never stored).
+  const unsigned char* src[RCPT];
+#pragma unroll
+  for (int i = 0; i < RCPT; ++i) {
+    const int q = (wave * RCPT + i) * 64 + lane;
+    const int row = q >> 2, kc = (q & 3) ^ ring_swz(row);
+    const bool isa = row < BM;
+    const int grow = isa ? m0 + row : n0 + (row - BM);
+    const bool ok = grow < (isa ? M : N);
+    const unsigned char* X = isa ? A : Bt;
+    src[i] = (ok ? X + (int64_t)grow * K : X) + 16 * kc;
+  }
+  // Stages past the end re-load the last K slice into their own slot, which
+  // is never read again: every step issues the same number of loads, so the
+  // wait counts are constants.
+  auto issue = [&](int step) {
+    const int slot = step % RNST;
+    const int k0 = min(step, steps - 1) * RK;
+#pragma unroll
+    for (int i = 0; i < RCPT; ++i) {
+      const unsigned at = (unsigned)(uintptr_t)(lds + slot * RSTAGE + (wave * RCPT + i) * 1024);
+      ring_load16(src[i] + k0, __builtin_amdgcn_readfirstlane(at));
+    }
+  };
+
+  f32x16 acc[4][RNF];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < RNF; ++j) acc[i][j] = zero16();
+
+  // fragment of the 32 rows from `row0`: this lane's row, K chunks 2g, 2g+1
+  const int g = lane >> 5, r32 = lane & 31;
+  const int c0 = 16 * ((2 * g) ^ ring_swz(r32)), c1 = 16 * ((2 * g + 1) ^ ring_swz(r32));
+  auto frag = [&](const unsigned char* base, int row0) {
+    // row0 is a multiple of 32, so row0 + r32 has the swizzle of r32
+    const unsigned char* r = base + (row0 + r32) * RK;
+    const int4 x = *reinterpret_cast<const int4*>(r + c0);
+    const int4 y = *reinterpret_cast<const int4*>(r + c1);
+    i32x8 v;
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    return v;
+  };
+  auto read = [&](int step, i32x8 (&a)[4], i32x8 (&b)[RNF]) {
+    const unsigned char* base = lds + (step % RNST) * RSTAGE;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = frag(base, wm * 128 + i * 32);
+#pragma unroll
+    for (int j = 0; j < RNF; ++j) b[j] = frag(base, BM + wn * 64 + j * 32);
+  };
+  // Step s: wait until stage s+1 is in LDS for every wave (this wave's loads
+  // but the two latest stages, then the barrier) and this wave's reads of
+  // stage s are done; refill the slot of stage s (its fragments are in
+  // registers) with stage s+4; read stage s+1 (past the end: stale bytes,
+  // never used); multiply stage s.
+  auto step = [&](int s, const i32x8 (&ca)[4], const i32x8 (&cb)[RNF], i32x8 (&na)[4],
+                  i32x8 (&nb)[RNF]) {
+    ring_wait_loads<2 * RCPT>();
+    __builtin_amdgcn_s_waitcnt(kWaitLdsOnly);
+    asm volatile("s_barrier" ::: "memory");
+    issue(s + RNST);
+    read(s + 1, na, nb);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < RNF; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ca[i], cb[j], acc[i][j], 0, 0,
+                                                                    0, 127, 0, 127);
+  };
+
+  for (int s = 0; s < RNST; ++s) issue(s);
+  ring_wait_loads<3 * RCPT>();
+  asm volatile("s_barrier" ::: "memory");
+  i32x8 a0[4], b0[RNF], a1[4], b1[RNF];
+  read(0, a0, b0);
+  for (int s = 0; s < steps; s += 2) {
+    step(s, a0, b0, a1, b1);
+    if (s + 1 < steps) step(s + 1, a1, b1, a0, b0);
+  }
+  // no load may still be writing LDS when the workgroup ends
+  ring_wait_loads<0>();
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < RNF; ++j) {
+      const int col = n0 + wn * 64 + j * 32 + r32;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * 128 + i * 32 + mfma32_row(r, lane);
+        if (row < M && col < N) C[(int64_t)row * N + col] = acc[i][j][r];
+      }
+    }
+}
+
 }  // namespace
 
 OpPlan gemm_fp8_plan(int64_t M, int64_t N, int64_t K) {
-  (void)K;
   OpPlan p;
-  p.func = reinterpret_cast<const void*>(&gemm_fp8_kernel);
+  const bool ring = K % RK == 0;
+  p.func = ring ? reinterpret_cast<const void*>(&gemm_fp8_ring)
+                : reinterpret_cast<const void*>(&gemm_fp8_kernel);
   p.grid = dim3((unsigned)(((M + BM - 1) / BM) * ((N + BN - 1) / BN)));
-  p.block = dim3(256);
+  p.block = dim3(ring ? 64 * RWAVES : 256);
   return p;
 }
 
 hipError_t gemm_fp8_launch(const unsigned char* A, const unsigned char* Bt, float* C, int64_t M,
                            int64_t N, int64_t K, hipStream_t s) {
   OpPlan p = gemm_fp8_plan(M, N, K);
-  hipLaunchKernelGGL(gemm_fp8_kernel, p.grid, p.block, 0, s, A, Bt, C, (int)M, (int)N, (int)K);
+  if (K % RK == 0)
+    hipLaunchKernelGGL(gemm_fp8_ring, p.grid, p.block, 0, s, A, Bt, C, (int)M, (int)N, (int)K);
+  else
+    hipLaunchKernelGGL(gemm_fp8_kernel, p.grid, p.block, 0, s, A, Bt, C, (int)M, (int)N, (int)K);
   return hipGetLastError();
 }
 

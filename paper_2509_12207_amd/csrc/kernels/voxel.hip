@@ -233,13 +233,14 @@ __global__ __launch_bounds__(256) void voxel_place(const float4* __restrict__ pt
   __syncthreads();
   const int64_t beg = (int64_t)c * kChunk;
   const int64_t end = beg + kChunk < N ? beg + kChunk : N;
-  for (int64_t i = beg + threadIdx.x; i < end; i += 4 * 256) {
-    float4 p[4];
+  // eight points a lane in flight (two workgroups fit a CU)
+  for (int64_t i = beg + threadIdx.x; i < end; i += 8 * 256) {
+    float4 p[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 8; ++u)
       if (i + u * 256 < end) p[u] = pts[i + u * 256];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int64_t j = i + u * 256;
       if (j < end) {
         const int v = cell_of(p[u], nx, ny, xmin, ymin, scale);
@@ -257,18 +258,15 @@ __global__ __launch_bounds__(256) void voxel_place(const float4* __restrict__ pt
     }
   }
   __syncthreads();
-  const int n = loff[T];
-  for (int lp = threadIdx.x; lp < n; lp += 256) {
-    // run of lp: the last tile t with loff[t] <= lp (empty runs are skipped)
-    int lo = 0, hi = T - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (loff[mid] <= lp) lo = mid; else hi = mid - 1;
+  // one wavefront per tile run (tiles dealt round-robin to the four)
+  const int lane = threadIdx.x & 63;
+  for (int t = threadIdx.x >> 6; t < T; t += 4) {
+    const int a = loff[t], n = loff[t + 1] - a, g = gbase[t];
+    for (int k = lane; k < n; k += 64) {
+      rz[g + k] = sz[a + k];
+      ri[g + k] = (int)(beg + si[a + k]);
+      rc[g + k] = sc[a + k];
     }
-    const int pos = gbase[lo] + (lp - loff[lo]);
-    rz[pos] = sz[lp];
-    ri[pos] = (int)(beg + si[lp]);
-    rc[pos] = sc[lp];
   }
 }
 
@@ -281,13 +279,12 @@ __global__ __launch_bounds__(256) void voxel_reduce(const int* __restrict__ tcou
                                                     int* __restrict__ pc,
                                                     unsigned* __restrict__ pz,
                                                     int* __restrict__ pf, int T) {
+  // 52 KiB of LDS: three workgroups fit a CU
   __shared__ int segb[kMaxTiles + 1];
-  __shared__ int tbase[kMaxTiles + 1];
   __shared__ int wsum[4];
   __shared__ int acc_c[kTileCells];
   __shared__ unsigned acc_z[kTileCells];
   __shared__ int acc_f[kTileCells];
-  block_scan_tiles(T, [&](int i) { return tcount[i]; }, tbase, wsum);
   block_scan_tiles(T, [&](int i) { return (int)((tcount[i] + kSeg - 1) / kSeg); }, segb, wsum);
   const int s = blockIdx.x;
   if (s >= segb[T]) return;  // uniform across the workgroup
@@ -298,8 +295,15 @@ __global__ __launch_bounds__(256) void voxel_reduce(const int* __restrict__ tcou
     if (segb[mid] <= s) lo = mid; else hi = mid - 1;
   }
   const int t = lo;
-  const int64_t start = (int64_t)tbase[t] + (int64_t)(s - segb[t]) * kSeg;
-  const int64_t tend = (int64_t)tbase[t] + tcount[t];
+  // first record of tile t: the sum of the totals of the tiles before it
+  int part = 0;
+  for (int i = threadIdx.x; i < t; i += 256) part += tcount[i];
+  for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
+  __syncthreads();
+  const int tbase = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  const int64_t start = (int64_t)tbase + (int64_t)(s - segb[t]) * kSeg;
+  const int64_t tend = (int64_t)tbase + tcount[t];
   const int64_t end = start + kSeg < tend ? start + kSeg : tend;
   for (int c = threadIdx.x; c < kTileCells; c += 256) {
     acc_c[c] = 0;

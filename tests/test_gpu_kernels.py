@@ -413,8 +413,22 @@ def test_gemm_fp8_integer_codes_bit_exact():
     assert np.array_equal(C, OK.gemm_fp8_f64(A8, B8).astype(np.float32))
 
 
+def test_gemm_fp8_integer_codes_bit_exact_ring():
+    # the same integer codes through the K-multiple-of-64 kernel: one, two,
+    # three (odd) and five K steps, ragged M and N below and above one tile
+    r = rng(22)
+    table = np.array([0x00, 0x38, 0xB8, 0x40, 0xC0], np.uint8)
+    for M, N, K in [(300, 270, 64), (33, 257, 128), (256, 256, 192), (513, 100, 320)]:
+        A8, B8 = table[r.integers(0, 5, (M, K))], table[r.integers(0, 5, (N, K))]
+        C = run_gemm_fp8(A8, B8)
+        assert np.array_equal(C, OK.gemm_fp8_f64(A8, B8).astype(np.float32)), (M, N, K)
+
+
+# K a multiple of 64 takes the direct-to-LDS ring kernel, other multiples of
+# 16 the register-staged one
 @pytest.mark.parametrize("M,N,K", [(256, 256, 128), (512, 768, 1024), (77, 513, 16),
-                                   (1, 1, 16), (1000, 300, 4096)])
+                                   (1, 1, 16), (1000, 300, 4096), (1, 1, 64), (700, 900, 448),
+                                   (300, 257, 1088), (64, 1000, 208)])
 def test_gemm_fp8_parity(M, N, K):
     r = rng(M + 3 * N + 7 * K)
     A8, B8 = _fp8_codes(r, (M, K)), _fp8_codes(r, (N, K))
