@@ -20,6 +20,8 @@ reordering:
 * FP8 matrix product  C = A B with A, B in the OCP FP8 E4M3 format and an
   FP32 result (the best-effort overload load: large low-precision products
   that share the GPU with the deadline chains).
+* BF16 matrix product  C = A B with A, B in bfloat16 and an FP32 result
+  (the reduced-precision form of the dense layers).
 
 Floating point results are computed in float64 from the float32 inputs.  The
 two operations whose results must be bit-exact take their decisions in
@@ -267,4 +269,50 @@ def gemm_fp8_entry_f64(A8, Bt8, m, n):
     """One entry C[m, n] and its scale (|A| |B|)[m, n] for sampled checks."""
     a = e4m3_decode(A8[m])
     b = e4m3_decode(Bt8[n])
+    return float(np.dot(a, b)), float(np.dot(np.abs(a), np.abs(b)))
+
+
+def bf16_decode(codes):
+    """Value of each bfloat16 code as float64.
+
+    Bit 15 is the sign, bits 14..7 the exponent field e (bias 127), bits
+    6..0 the mantissa m.  e = 0 encodes zero and subnormals (m / 128) *
+    2^-126; e = 255 encodes infinity (m = 0) and NaN (m != 0); otherwise the
+    value is (1 + m / 128) * 2^(e - 127).  (The format is the upper half of
+    an IEEE binary32.)
+    """
+    c = np.asarray(codes, dtype=np.uint16).astype(np.int64)
+    sign = np.where(c & 0x8000, -1.0, 1.0)
+    e = (c >> 7) & 0xFF
+    m = (c & 0x7F).astype(np.float64)
+    with np.errstate(over="ignore"):
+        mag = np.where(e == 0, (m / 128.0) * 2.0 ** -126, (1.0 + m / 128.0) * np.exp2(e - 127.0))
+    mag = np.where(e == 0xFF, np.where(m == 0, np.inf, np.nan), mag)
+    return sign * mag
+
+
+def gemm_bf16_f64(A16, Bt16):
+    """C[m, n] = sum_k d(A16[m, k]) * d(Bt16[n, k]), d = bf16_decode.
+
+    A16 is [M, K] and Bt16 is B transposed, [N, K], as uint16 codes.  A
+    product of two bfloat16 values has at most 16 significant bits and is
+    exact in float64; for inputs whose exponents span a few binades (the
+    generators here) the sums of K <= 2^20 products stay within 53 bits, so
+    this is the exact product.
+    """
+    A = bf16_decode(A16)
+    B = bf16_decode(Bt16)
+    assert A.ndim == 2 and B.ndim == 2 and A.shape[1] == B.shape[1]
+    return A @ B.T
+
+
+def gemm_bf16_abs_f64(A16, Bt16):
+    """|A| |B| for the componentwise error scale of the BF16 product."""
+    return np.abs(bf16_decode(A16)) @ np.abs(bf16_decode(Bt16)).T
+
+
+def gemm_bf16_entry_f64(A16, Bt16, m, n):
+    """One entry C[m, n] and its scale (|A| |B|)[m, n] for sampled checks."""
+    a = bf16_decode(A16[m])
+    b = bf16_decode(Bt16[n])
     return float(np.dot(a, b)), float(np.dot(np.abs(a), np.abs(b)))

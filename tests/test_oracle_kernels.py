@@ -288,3 +288,52 @@ def test_gemm_fp8_matches_torch_float8_path():
     assert np.allclose(got, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
     v, sc = K.gemm_fp8_entry_f64(A8, B8, 5, 7)
     assert v == got[5, 7] and sc == K.gemm_fp8_abs_f64(A8, B8)[5, 7]
+
+
+# ------------------------------------------------------------------- BF16
+def test_bf16_published_values():
+    # bfloat16 = sign, 8 exponent bits (bias 127), 7 mantissa bits: 1.0 is
+    # 0x3F80, pi rounds to 0x4049 = 3.140625, the largest finite value is
+    # (2 - 2^-7) 2^127, the smallest subnormal 2^-133
+    d = K.bf16_decode(np.array([0x3F80, 0xBF80, 0x4049, 0x0001, 0x7F7F, 0x7F80, 0xFF80, 0x7FC0,
+                                0x8000, 0x0080, 0x4000], np.uint16))
+    assert d[0] == 1.0 and d[1] == -1.0 and d[2] == 3.140625 and d[3] == 2.0 ** -133
+    assert d[4] == (2 - 2.0 ** -7) * 2.0 ** 127
+    assert d[5] == np.inf and d[6] == -np.inf and np.isnan(d[7])
+    assert d[8] == 0.0 and np.signbit(d[8]) and d[9] == 2.0 ** -126 and d[10] == 2.0
+
+
+def test_bf16_all_codes_match_float32_upper_half():
+    # every code is the upper 16 bits of the binary32 with the same value
+    codes = np.arange(1 << 16, dtype=np.uint32)
+    with np.errstate(invalid="ignore"):      # NaN payloads widened to float64
+        ref = (codes << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    got = K.bf16_decode(codes.astype(np.uint16))
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.array_equal(got[ok], ref[ok])
+    assert np.array_equal(np.signbit(got[ok]), np.signbit(ref[ok]))
+
+
+def test_gemm_bf16_integer_codes_exact():
+    # codes of 0, +-1, +-2, +-3: the product is an integer matrix product
+    r = np.random.default_rng(6)
+    table = np.array([0x0000, 0x3F80, 0xBF80, 0x4000, 0xC000, 0x4040, 0xC040], np.uint16)
+    value = np.array([0, 1, -1, 2, -2, 3, -3], np.int64)
+    ia, ib = r.integers(0, 7, (13, 96)), r.integers(0, 7, (7, 96))
+    C = K.gemm_bf16_f64(table[ia], table[ib])
+    assert np.array_equal(C, (value[ia] @ value[ib].T).astype(np.float64))
+    v, sc = K.gemm_bf16_entry_f64(table[ia], table[ib], 3, 4)
+    assert v == C[3, 4] and sc == K.gemm_bf16_abs_f64(table[ia], table[ib])[3, 4]
+
+
+def test_gemm_bf16_matches_torch_bfloat16_path():
+    r = np.random.default_rng(7)
+    A = r.standard_normal((17, 64)).astype(np.float32)
+    B = r.standard_normal((9, 64)).astype(np.float32)
+    a16 = torch.from_numpy(A).to(torch.bfloat16)
+    b16 = torch.from_numpy(B).to(torch.bfloat16)
+    ref = (a16.to(torch.float64) @ b16.to(torch.float64).T).numpy()
+    got = K.gemm_bf16_f64(a16.view(torch.int16).numpy().view(np.uint16),
+                          b16.view(torch.int16).numpy().view(np.uint16))
+    assert np.array_equal(got, ref)
