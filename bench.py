@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 MS = 1_000_000
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP8_MFMA = 5.0e15
+PEAK_BF16_MFMA = 2.5e15
 # Percentile of the sampled highest urgencies that sets TH_urgent.  The
 # paper's 95th (Sec. 4.4.3) holds back too much work on MI355X: in the
 # threshold sweep (3 seeds) it lowers misses but raises p99 latency over FIFO,
@@ -232,6 +233,7 @@ ROOF_SHAPES = {
     # op: (shape, algorithmic flops, algorithmic bytes, bound)
     "gemm": ((4096, 4096, 4096), 2 * 4096 ** 3, 4 * 3 * 4096 ** 2, "mfma"),
     "gemm_fp8": ((8192, 8192, 8192), 2 * 8192 ** 3, (1 + 1 + 4) * 8192 ** 2, "mfma_fp8"),
+    "gemm_bf16": ((4096, 4096, 4096), 2 * 4096 ** 3, (2 + 2 + 4) * 4096 ** 2, "mfma_bf16"),
     "conv3x3": ((1, 256, 256, 256), 18 * 256 ** 2 * 256 ** 2, 4 * (2 * 256 ** 3 + 9 * 256 ** 2), "mfma"),
     "bias_relu": ((16384, 16384, 0), 2 * 16384 ** 2, 8 * 16384 ** 2 + 4 * 16384, "hbm"),
     "rowsum": ((16384, 16384), 16384 ** 2, 4 * 16384 ** 2 + 4 * 16384, "hbm"),
@@ -272,6 +274,12 @@ def roofline_op(op, reps, torch):
                     | (torch.randint(4, 10, (n,), device=dev) << 3)
                     | torch.randint(0, 8, (n,), device=dev)).to(torch.uint8)
         t = [codes(M * K), codes(N * K), torch.empty(M * N, device=dev)]
+        desc = {"op": op, "shape": shape, "in": (0, 1), "out": (2,)}
+    elif op == "gemm_bf16":
+        M, N, K = shape
+        # random finite bfloat16 values (rounded normals)
+        t = [torch.randn(M * K, device=dev).to(torch.bfloat16),
+             torch.randn(N * K, device=dev).to(torch.bfloat16), torch.empty(M * N, device=dev)]
         desc = {"op": op, "shape": shape, "in": (0, 1), "out": (2,)}
     elif op == "conv3x3":
         _, C, H, W = shape
@@ -324,8 +332,9 @@ def roofline_op(op, reps, torch):
     torch.cuda.synchronize()
     dur = sorted(s.elapsed_time(e) * 1e-3 for s, e in ms)
     avg = sum(dur) / len(dur)
-    if bound in ("mfma", "mfma_fp8"):
-        peak = (PEAK_FP8_MFMA if bound == "mfma_fp8" else PEAK_FP32_MFMA) / 1e12
+    if bound in ("mfma", "mfma_fp8", "mfma_bf16"):
+        peak = {"mfma": PEAK_FP32_MFMA, "mfma_fp8": PEAK_FP8_MFMA,
+                "mfma_bf16": PEAK_BF16_MFMA}[bound] / 1e12
         achieved, unit = flops / avg / 1e12, "TFLOP/s"
         bound = "mfma"
     else:

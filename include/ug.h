@@ -102,6 +102,14 @@ enum {
  *                       16; in {A[M,K] row-major, Bt[N,K] = B transposed
  *                       (K contiguous)}; out {C[M,N] fp32}; A and Bt 16-byte
  *                       aligned.  The best-effort load of an overloaded GPU.
+ *  UG_OP_GEMM_BF16      C = A B with A, B in bfloat16 (two bytes per value,
+ *                       the upper half of an IEEE binary32) and an FP32
+ *                       result, FP32 accumulation on the BF16 matrix cores.
+ *                       shape {M, N, K}, K a multiple of 32 below 2^30;
+ *                       in {A[M,K] row-major, Bt[N,K] = B transposed};
+ *                       out {C[M,N] fp32}; A and Bt 16-byte aligned.  The
+ *                       reduced-precision form of the GEMM (configuration
+ *                       with BF16 contractions).
  */
 enum {
   UG_OP_GEMM_F32 = 1,
@@ -110,7 +118,8 @@ enum {
   UG_OP_ROWSUM_F32 = 4,
   UG_OP_SOFTMAX_F32 = 5,
   UG_OP_VOXEL_F32 = 6,
-  UG_OP_GEMM_FP8 = 7
+  UG_OP_GEMM_FP8 = 7,
+  UG_OP_GEMM_BF16 = 8
 };
 
 /* One kernel of a task (a row of the paper's lookup table, Tab. "Example

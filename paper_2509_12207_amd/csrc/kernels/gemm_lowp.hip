@@ -1,35 +1,42 @@
-// C[M,N] = A[M,K] B[K,N] with A and B in OCP FP8 E4M3 and an FP32 result,
-// on the FP8 matrix cores of gfx950.
+// Low-precision GEMMs on the matrix cores of gfx950, FP32 result:
+//   FP8:  C[M,N] = A[M,K] B[K,N], A and B in OCP FP8 E4M3 (one byte each);
+//   BF16: the same with A and B in bfloat16 (two bytes each).
 //
 // Operands are K-contiguous: A row-major [M, K], B given transposed as
-// Bt [N, K] (row n holds column n of B).  K must be a multiple of 16 (one
-// 16-byte load); M and N are arbitrary (tails are read from the matrix's
-// first row or zero-filled, and never stored).
+// Bt [N, K] (row n holds column n of B).  M and N are arbitrary (rows past
+// M or N are read from the matrix's first row or zero-filled, and never
+// stored).  Workgroups are remapped so each XCD computes a contiguous band
+// of output tiles.
 //
-// v_mfma_scale_f32_32x32x64_f8f6f4 with both scale exponents 127 (x1):
-// D[32x32] += A[32x64] B[64x32], 131072 FLOP per instruction.  Lane l feeds
-// row (A) or column (B) l % 32 with 32 bytes of K, bytes 32 (l / 32) ..
-// 32 (l / 32) + 31 of the 64-byte K slice.  The accumulator layout is that
-// of the other 32x32 instructions (mfma32_row).  Workgroups are remapped so
-// each XCD computes a contiguous band of output tiles.
+// Instructions (both wave64, accumulator layout of the other 32x32
+// instructions, mfma32_row):
+// * v_mfma_scale_f32_32x32x64_f8f6f4, both scale exponents 127 (x1):
+//   D[32x32] += A[32x64] B[64x32], 131072 FLOP.  Lane l feeds row (A) or
+//   column (B) l % 32 with 32 bytes of K: bytes 32 (l / 32) .. +31 of the
+//   64-byte K slice.
+// * v_mfma_f32_32x32x16_bf16: D[32x32] += A[32x16] B[16x32], 32768 FLOP.
+//   Lane l feeds row / column l % 32 with 8 values of K: k = 8 (l / 32) ..
+//   +7.  A 64-byte K slice (32 values) takes two of them: lane l reads 16-
+//   byte chunk l / 32 for the first and chunk 2 + l / 32 for the second.
 //
-// Two kernels, both with a 256 x 256 workgroup tile:
+// Kernels, all with a 256 x 256 workgroup tile:
 //
-// * gemm_fp8_ring (K a multiple of 64): eight waves of 128 x 64 (two per
-//   SIMD, 8 instructions per 64-byte K slice).  Global memory goes straight
-//   to LDS (global_load_lds_dwordx4) into a ring of four 32 KiB stages, three
-//   stages ahead of the matrix cores; the fragments of step s+1 are read from
-//   LDS while step s runs.  One barrier a step.  Rows are 64 bytes with the
-//   four 16-byte chunks of row r XOR-permuted by (r / 4) % 4: a 16-byte read
-//   of sixteen consecutive rows then touches all 64 LDS banks once.
-//   The direct-to-LDS loads are issued from inline assembly so that the
-//   compiler, which cannot tell them apart from the ring slots being read,
-//   does not wait for every load in flight before each LDS read; their
-//   completion is waited for explicitly (vmcnt) before each barrier.
+// * gemm_ring<FP8 | BF16> (rows a multiple of 64 bytes: K % 64 == 0 for
+//   FP8, K % 32 == 0 for BF16): eight waves of 128 x 64 (two per SIMD).
+//   Global memory goes straight to LDS (global_load_lds_dwordx4) into a
+//   ring of four 32 KiB stages, three stages ahead of the matrix cores; the
+//   fragments of step s+1 are read from LDS while step s runs.  One barrier
+//   a step.  LDS rows are 64 bytes with the four 16-byte chunks of row r
+//   XOR-permuted by (r / 4) % 4: a 16-byte read by sixteen consecutive rows
+//   then touches all 64 LDS banks once.  The direct-to-LDS loads are issued
+//   from inline assembly so that the compiler, which cannot tell them apart
+//   from the ring slots being read, does not wait for every load in flight
+//   before each LDS read; their completion is waited for explicitly
+//   (vmcnt) before each barrier.
 //
-// * gemm_fp8_kernel (any K multiple of 16): four waves of 128 x 128; the next
-//   128-byte K step is fetched into registers while the current one, in two
-//   padded LDS stages, feeds the matrix cores.
+// * gemm_fp8_kernel (FP8, any K multiple of 16): four waves of 128 x 128;
+//   the next 128-byte K step is fetched into registers while the current
+//   one, in two padded LDS stages, feeds the matrix cores.
 #include "mfma.hpp"
 #include "ops.hpp"
 
@@ -183,6 +190,9 @@ constexpr int RSTAGE = (BM + BN) * RK;       // 32 KiB per stage
 constexpr int RWAVES = 8;
 constexpr int RCPT = (BM + BN) * RK / 16 / (64 * RWAVES);   // 16-byte loads per lane per stage
 constexpr int RNF = 2;                       // B fragments per wave (wave tile 128 x 64)
+enum RingType { kRingFp8 = 0, kRingBf16 = 1 };
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ int ring_swz(int row) { return (row >> 2) & 3; }
 
@@ -194,7 +204,7 @@ __device__ __forceinline__ void ring_wait_loads() {
 
 // One 16-byte direct-to-LDS load: lane l writes LDS bytes [lds + 16 l, +16).
 // M0 holds the wave's LDS base; one wait state between writing M0 and the
-// load that reads it.  M0 has no other use in this kernel.
+// load that reads it.  M0 has no other use in these kernels.
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winline-asm"
 __device__ __forceinline__ void ring_load16(const unsigned char* g, unsigned lds) {
@@ -203,10 +213,21 @@ __device__ __forceinline__ void ring_load16(const unsigned char* g, unsigned lds
 }
 #pragma clang diagnostic pop
 
-__global__ __launch_bounds__(64 * RWAVES, 1) void gemm_fp8_ring(const unsigned char* __restrict__ A,
-                                                                const unsigned char* __restrict__ Bt,
-                                                                float* __restrict__ C, int M, int N,
-                                                                int K) {
+// The two 16-byte chunks of a 64-byte K slice that lane group g (= lane /
+// 32) feeds to the matrix cores.
+template <int T>
+__device__ __forceinline__ int ring_chunk(int g, int h) {
+  return T == kRingFp8 ? 2 * g + h : g + 2 * h;
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(int4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// Operands: A and Bt as bytes, `kb` bytes per row (a multiple of 64).
+template <int T>
+__global__ __launch_bounds__(64 * RWAVES, 1) void gemm_ring(const unsigned char* __restrict__ A,
+                                                            const unsigned char* __restrict__ Bt,
+                                                            float* __restrict__ C, int M, int N,
+                                                            int kb) {
   __shared__ __attribute__((aligned(1024))) unsigned char lds[RNST * RSTAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 2, wn = wave & 3;   // 2 x 4 waves
@@ -214,7 +235,7 @@ __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_fp8_ring(const unsigned c
   int tm, tn;
   tile_of(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
   const int m0 = tm * BM, n0 = tn * BN;
-  const int steps = K / RK;
+  const int steps = kb / RK;
 
   // A stage is 512 rows (256 of A, then 256 of Bt) of 64 bytes = 2048
   // chunks; load i of wave w fills the 1 KiB block w * RCPT + i, lane l the
@@ -230,7 +251,7 @@ __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_fp8_ring(const unsigned c
     const int grow = isa ? m0 + row : n0 + (row - BM);
     const bool ok = grow < (isa ? M : N);
     const unsigned char* X = isa ? A : Bt;
-    src[i] = (ok ? X + (int64_t)grow * K : X) + 16 * kc;
+    src[i] = (ok ? X + (int64_t)grow * kb : X) + 16 * kc;
   }
   // Stages past the end re-load the last K slice into their own slot, which
   // is never read again: every step issues the same number of loads, so the
@@ -251,11 +272,12 @@ __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_fp8_ring(const unsigned c
 #pragma unroll
     for (int j = 0; j < RNF; ++j) acc[i][j] = zero16();
 
-  // fragment of the 32 rows from `row0`: this lane's row, K chunks 2g, 2g+1
+  // fragment of the 32 rows from `row0`: this lane's row, its two K chunks
+  // (row0 is a multiple of 32, so row0 + r32 has the swizzle of r32)
   const int g = lane >> 5, r32 = lane & 31;
-  const int c0 = 16 * ((2 * g) ^ ring_swz(r32)), c1 = 16 * ((2 * g + 1) ^ ring_swz(r32));
+  const int c0 = 16 * (ring_chunk<T>(g, 0) ^ ring_swz(r32));
+  const int c1 = 16 * (ring_chunk<T>(g, 1) ^ ring_swz(r32));
   auto frag = [&](const unsigned char* base, int row0) {
-    // row0 is a multiple of 32, so row0 + r32 has the swizzle of r32
     const unsigned char* r = base + (row0 + r32) * RK;
     const int4 x = *reinterpret_cast<const int4*>(r + c0);
     const int4 y = *reinterpret_cast<const int4*>(r + c1);
@@ -271,6 +293,25 @@ __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_fp8_ring(const unsigned c
 #pragma unroll
     for (int j = 0; j < RNF; ++j) b[j] = frag(base, BM + wn * 64 + j * 32);
   };
+  auto multiply = [&](const i32x8 (&a)[4], const i32x8 (&b)[RNF]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < RNF; ++j) {
+        if constexpr (T == kRingFp8) {
+          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i], b[j], acc[i][j], 0, 0,
+                                                                      0, 127, 0, 127);
+        } else {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int4 x = {a[i][4 * h], a[i][4 * h + 1], a[i][4 * h + 2], a[i][4 * h + 3]};
+            const int4 y = {b[j][4 * h], b[j][4 * h + 1], b[j][4 * h + 2], b[j][4 * h + 3]};
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(x), as_bf16x8(y),
+                                                                acc[i][j], 0, 0, 0);
+          }
+        }
+      }
+  };
   // Step s: wait until stage s+1 is in LDS for every wave (this wave's loads
   // but the two latest stages, then the barrier) and this wave's reads of
   // stage s are done; refill the slot of stage s (its fragments are in
@@ -283,12 +324,7 @@ __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_fp8_ring(const unsigned c
     asm volatile("s_barrier" ::: "memory");
     issue(s + RNST);
     read(s + 1, na, nb);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < RNF; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ca[i], cb[j], acc[i][j], 0, 0,
-                                                                    0, 127, 0, 127);
+    multiply(ca, cb);
   };
 
   for (int s = 0; s < RNST; ++s) issue(s);
@@ -321,7 +357,7 @@ __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_fp8_ring(const unsigned c
 OpPlan gemm_fp8_plan(int64_t M, int64_t N, int64_t K) {
   OpPlan p;
   const bool ring = K % RK == 0;
-  p.func = ring ? reinterpret_cast<const void*>(&gemm_fp8_ring)
+  p.func = ring ? reinterpret_cast<const void*>(&gemm_ring<kRingFp8>)
                 : reinterpret_cast<const void*>(&gemm_fp8_kernel);
   p.grid = dim3((unsigned)(((M + BM - 1) / BM) * ((N + BN - 1) / BN)));
   p.block = dim3(ring ? 64 * RWAVES : 256);
@@ -332,9 +368,28 @@ hipError_t gemm_fp8_launch(const unsigned char* A, const unsigned char* Bt, floa
                            int64_t N, int64_t K, hipStream_t s) {
   OpPlan p = gemm_fp8_plan(M, N, K);
   if (K % RK == 0)
-    hipLaunchKernelGGL(gemm_fp8_ring, p.grid, p.block, 0, s, A, Bt, C, (int)M, (int)N, (int)K);
+    hipLaunchKernelGGL(gemm_ring<kRingFp8>, p.grid, p.block, 0, s, A, Bt, C, (int)M, (int)N,
+                       (int)K);
   else
     hipLaunchKernelGGL(gemm_fp8_kernel, p.grid, p.block, 0, s, A, Bt, C, (int)M, (int)N, (int)K);
+  return hipGetLastError();
+}
+
+OpPlan gemm_bf16_plan(int64_t M, int64_t N, int64_t K) {
+  (void)K;
+  OpPlan p;
+  p.func = reinterpret_cast<const void*>(&gemm_ring<kRingBf16>);
+  p.grid = dim3((unsigned)(((M + BM - 1) / BM) * ((N + BN - 1) / BN)));
+  p.block = dim3(64 * RWAVES);
+  return p;
+}
+
+hipError_t gemm_bf16_launch(const uint16_t* A, const uint16_t* Bt, float* C, int64_t M,
+                            int64_t N, int64_t K, hipStream_t s) {
+  OpPlan p = gemm_bf16_plan(M, N, K);
+  hipLaunchKernelGGL(gemm_ring<kRingBf16>, p.grid, p.block, 0, s,
+                     reinterpret_cast<const unsigned char*>(A),
+                     reinterpret_cast<const unsigned char*>(Bt), C, (int)M, (int)N, (int)(2 * K));
   return hipGetLastError();
 }
 

@@ -58,6 +58,15 @@ const char* validate_kernel(const ug_kernel& k, uint32_t nb) {
       if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
         return "gemm_fp8: needs in {A, Bt}, out {C}";
       return nullptr;
+    case UG_OP_GEMM_BF16:
+      if (!pos(s[0]) || !pos(s[1]) || !pos(s[2]) || s[2] >= kMaxDim / 2)
+        return "gemm_bf16: M, N in [1, 2^31), K in [1, 2^30)";
+      if (s[2] % 32 != 0) return "gemm_bf16: K must be a multiple of 32";
+      if (s[0] * s[2] >= kMaxDim * 16 || s[1] * s[2] >= kMaxDim * 16 || s[0] * s[1] >= kMaxDim * 8)
+        return "gemm_bf16: operand too large";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
+        return "gemm_bf16: needs in {A, Bt}, out {C}";
+      return nullptr;
     default:
       return "unknown op";
   }
@@ -95,6 +104,13 @@ hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, voi
         return hipErrorInvalidValue;
       return gemm_fp8_launch(a, bt, F(k.out[0]), s[0], s[1], s[2], st);
     }
+    case UG_OP_GEMM_BF16: {
+      const auto* a = static_cast<const uint16_t*>(b[k.in[0]]);
+      const auto* bt = static_cast<const uint16_t*>(b[k.in[1]]);
+      if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(bt)) & 15)
+        return hipErrorInvalidValue;
+      return gemm_bf16_launch(a, bt, F(k.out[0]), s[0], s[1], s[2], st);
+    }
     default:
       return hipErrorInvalidValue;
   }
@@ -117,6 +133,8 @@ OpPlan plan_kernel(const ug_kernel& k) {
       return voxel_f32_plan(s[0], (int)s[1], (int)s[2]);
     case UG_OP_GEMM_FP8:
       return gemm_fp8_plan(s[0], s[1], s[2]);
+    case UG_OP_GEMM_BF16:
+      return gemm_bf16_plan(s[0], s[1], s[2]);
     default:
       return OpPlan{};
   }

@@ -41,6 +41,10 @@ OpPlan gemm_fp8_plan(int64_t M, int64_t N, int64_t K);
 hipError_t gemm_fp8_launch(const unsigned char* A, const unsigned char* Bt, float* C, int64_t M,
                            int64_t N, int64_t K, hipStream_t s);
 
+OpPlan gemm_bf16_plan(int64_t M, int64_t N, int64_t K);
+hipError_t gemm_bf16_launch(const uint16_t* A, const uint16_t* Bt, float* C, int64_t M,
+                            int64_t N, int64_t K, hipStream_t s);
+
 // Device workspace the voxel scatter needs (0: none); the launch fails with
 // hipErrorInvalidValue if it needs one and `ws` is missing or too small.
 size_t voxel_f32_workspace(int64_t N, int nx, int ny);

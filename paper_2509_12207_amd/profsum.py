@@ -51,7 +51,9 @@ TRAFFIC_KERNELS = {
     "softmax": (r"softmax_reg<4, 4, ", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
     "voxel": (r"voxel_(init|scatter|finalize|count|scan|place|reduce|merge)", 5,
               "paper_2509_12207_amd/csrc/kernels/voxel.hip"),
-    "gemm_fp8": (r"gemm_fp8_(kernel|ring)", 1, "paper_2509_12207_amd/csrc/kernels/gemm_fp8.hip"),
+    "gemm_fp8": (r"gemm_fp8_kernel|gemm_ring<0>", 1,
+                 "paper_2509_12207_amd/csrc/kernels/gemm_lowp.hip"),
+    "gemm_bf16": (r"gemm_ring<1>", 1, "paper_2509_12207_amd/csrc/kernels/gemm_lowp.hip"),
 }
 
 

@@ -480,3 +480,87 @@ def test_gemm_fp8_rejects_bad_k_and_alignment():
     with pytest.raises(capi.UgError):
         capi.kernel_launch({"op": "gemm_fp8", "shape": (8, 8, 32), "in": (0, 1), "out": (2,)},
                            [a.data_ptr() + 1, a.data_ptr(), c.data_ptr()])
+
+
+# ---------------------------------------------------------------- BF16 GEMM
+def _bf16_codes(r, shape, lo=124, hi=129):
+    """Random finite bfloat16 codes: random sign and mantissa, exponent field
+    in [lo, hi] (magnitudes 2^-3 .. 4 for the defaults)."""
+    s = r.integers(0, 2, shape) << 15
+    e = r.integers(lo, hi + 1, shape) << 7
+    m = r.integers(0, 128, shape)
+    return (s | e | m).astype(np.uint16)
+
+
+def bf16_bound(A16, Bt16):
+    """Componentwise error bound of the BF16 product with FP32 accumulation.
+
+    Every product of two bfloat16 values is exact in FP32 (16 significant
+    bits); the K products are then summed in FP32 in some order, each of the
+    at most K additions erring by less than one unit in the last place
+    (2^-23 relative, which covers truncation as well as rounding to
+    nearest), so |C - C64| <= gamma_K |A| |B| with gamma_K = K u / (1 - K u),
+    u = 2^-23."""
+    K = A16.shape[1]
+    u = 2.0 ** -23
+    return K * u / (1 - K * u) * OK.gemm_bf16_abs_f64(A16, Bt16)
+
+
+def run_gemm_bf16(A16, Bt16):
+    M, K = A16.shape
+    N = Bt16.shape[0]
+    a = torch.from_numpy(A16.view(np.int16).copy()).to(DEV)
+    b = torch.from_numpy(Bt16.view(np.int16).copy()).to(DEV)
+    c = torch.full((M, N), float("nan"), device=DEV)
+    launch({"op": "gemm_bf16", "shape": (M, N, K), "in": (0, 1), "out": (2,)}, [a, b, c])
+    return c.cpu().numpy()
+
+
+def test_gemm_bf16_integer_codes_bit_exact():
+    # codes of 0, +-1, +-2, +-3: every partial sum is a small integer, exact
+    # in any order; one, two, three (odd) and five K steps, ragged M and N
+    r = rng(31)
+    table = np.array([0x0000, 0x3F80, 0xBF80, 0x4000, 0xC000, 0x4040, 0xC040], np.uint16)
+    for M, N, K in [(300, 270, 32), (33, 257, 64), (256, 256, 96), (513, 100, 160)]:
+        A16, B16 = table[r.integers(0, 7, (M, K))], table[r.integers(0, 7, (N, K))]
+        C = run_gemm_bf16(A16, B16)
+        assert np.array_equal(C, OK.gemm_bf16_f64(A16, B16).astype(np.float32)), (M, N, K)
+
+
+@pytest.mark.parametrize("M,N,K", [(256, 256, 64), (512, 768, 1024), (77, 513, 32), (1, 1, 32),
+                                   (1000, 300, 4096), (700, 900, 224)])
+def test_gemm_bf16_parity(M, N, K):
+    r = rng(M + 5 * N + 11 * K)
+    A16, B16 = _bf16_codes(r, (M, K)), _bf16_codes(r, (N, K))
+    C = run_gemm_bf16(A16, B16)
+    ref = OK.gemm_bf16_f64(A16, B16)
+    bound = bf16_bound(A16, B16)
+    assert np.all(np.abs(C - ref) <= bound), np.max(np.abs(C - ref) / bound)
+    # and the componentwise criterion of the FP32 kernels
+    assert np.all(np.abs(C - ref) <= TOL * OK.gemm_bf16_abs_f64(A16, B16))
+
+
+def test_gemm_bf16_full_size_sampled():
+    # the 4096^3 roofline shape, checked on sampled entries
+    M = N = K = 4096
+    r = rng(9)
+    A16, B16 = _bf16_codes(r, (M, K)), _bf16_codes(r, (N, K))
+    C = run_gemm_bf16(A16, B16)
+    assert not np.isnan(C).any()
+    pts = list(zip(r.integers(0, M, 64), r.integers(0, N, 64)))
+    pts += [(0, 0), (M - 1, N - 1), (255, 256), (4095, 0)]
+    u = 2.0 ** -23
+    for m, n in pts:
+        v, sc = OK.gemm_bf16_entry_f64(A16, B16, m, n)
+        assert abs(C[m, n] - v) <= K * u / (1 - K * u) * sc, (m, n, C[m, n], v)
+
+
+def test_gemm_bf16_rejects_bad_k_and_alignment():
+    a = torch.zeros(4096, dtype=torch.int16, device=DEV)
+    c = torch.zeros(64, device=DEV)
+    with pytest.raises(capi.UgError):
+        capi.kernel_launch({"op": "gemm_bf16", "shape": (8, 8, 48), "in": (0, 1), "out": (2,)},
+                           [a.data_ptr(), a.data_ptr(), c.data_ptr()])
+    with pytest.raises(capi.UgError):
+        capi.kernel_launch({"op": "gemm_bf16", "shape": (8, 8, 32), "in": (0, 1), "out": (2,)},
+                           [a.data_ptr() + 2, a.data_ptr(), c.data_ptr()])
