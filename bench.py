@@ -69,6 +69,7 @@ def parse():
 PAPER = 1 | 2 | 4         # UG_F_BIND | UG_F_DELAY | UG_F_BATCH: the paper's mechanisms
 ADMIT = 16                # UG_F_ADMIT: task admission, the stand-in for stream priorities
 FULL = PAPER | ADMIT      # the gate as benchmarked
+NO_OVERLAP = 64           # UG_F_NO_OVERLAP: wait for a closed batch to finish
 SWEEPS = {
     # mechanism ablation (Sec. 6.4): each mechanism alone, all, none
     "ablation": [{"name": "none", "flags": 0}, {"name": "bind", "flags": 1 | 4},
@@ -94,6 +95,15 @@ SWEEPS = {
     # TH_urgent percentile with admission, with and without early chain exit
     "threshold_exit": [{"name": f"th_p{p}", "pct": p} for p in (95, 97, 99)]
     + [{"name": f"th_p{p}_exit", "pct": p, "flags": FULL | 32} for p in (95, 99)],
+    # launch synchronisation (Sec. 5.3): batched launching with overlap (the
+    # paper's), synchronous batched (a batch waits for the previous one to
+    # finish), asynchronous (a task's kernels at once, one end event),
+    # synchronous (every kernel waits for the previous one)
+    "launch": [{"name": "overlap", "flags": PAPER},
+               {"name": "sync_batched", "flags": PAPER | NO_OVERLAP},
+               {"name": "async", "flags": PAPER & ~4},
+               {"name": "sync", "flags": PAPER | NO_OVERLAP, "cfg": {"delta_eval_ns": 0}},
+               {"name": "overlap+admit", "flags": FULL}],
     # urgency-ordered admission under a cap on launched, unconfirmed work
     "admit": [{"name": "paper", "flags": PAPER}]
     + [{"name": f"admit_{n}", "flags": FULL, "cfg": {"admit_tasks": n}}

@@ -68,9 +68,16 @@ enum {
                           urgent starts only while fewer than admit_tasks
                           instances have kernels in flight (stands in for
                           stream priorities, see ug_config)               */
-  UG_F_EXIT = 32u      /* early chain exit (Sec. 4.3): a frame whose urgency
+  UG_F_EXIT = 32u,     /* early chain exit (Sec. 4.3): a frame whose urgency
                           is negative when a task would start leaves the
                           chain; it completes as missed and exited        */
+  UG_F_NO_OVERLAP = 64u /* launch-synchronisation variants (Sec. 5.3): a
+                          closed batch is waited for until it has finished
+                          (not until it has started) before the task's next
+                          batch is launched.  With UG_F_BATCH: synchronous
+                          batched launching; with delta_eval_ns = 0 as well:
+                          synchronous launching (one kernel per batch).
+                          UG_F_BATCH alone off: asynchronous launching     */
 };
 
 /* Operations.  Shapes and slot meaning per op; all float buffers are fp32,

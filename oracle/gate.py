@@ -105,6 +105,7 @@ class Instance:
         self.batch_sum = 0
         self.batch_first = []     # first kernel of each batch of the task
         self.waits = deque()      # events to observe, in order: (kind, seq)
+        self.seen = set()         # events of the current task already observed
         self.bound = False
         self.level = None
         self.lane = None
@@ -134,6 +135,7 @@ DEFAULT_CFG = {
     "admit": True,              # urgency-ordered task admission (no stream priorities)
     "admit_tasks": 4,           # instances with kernels in flight before new tasks wait
     "exit": False,              # early chain exit (Sec. 4.3)
+    "no_overlap": False,        # wait for a closed batch to finish (launch-sync variants)
 }
 
 
@@ -187,6 +189,7 @@ class GateModel:
         inst.batch_open = False
         inst.batch_sum = 0
         inst.batch_first = []
+        inst.seen = set()
         inst.waits = deque()
         inst.bound = False
         inst.level = inst.lane = None
@@ -214,6 +217,7 @@ class GateModel:
             assert inst.task == j and inst.waits and inst.waits[0] == (kind, seq), \
                 ("unexpected event", (c, f, j, kind, seq), list(inst.waits))
             inst.waits.popleft()
+            inst.seen.add((kind, seq))
             ch = inst.chain
             if kind == START:
                 # Batch `seq` has begun, so every earlier batch of the task is
@@ -325,6 +329,15 @@ class GateModel:
         inst.bound = True
         out.append(("BIND", inst.c, inst.f, inst.task, inst.level, inst.lane))
 
+    @staticmethod
+    def _wait(inst, ev):
+        """Wait for event ``ev`` of the instance's current task.  Every
+        recorded event is observed exactly once (the runtime releases it
+        when it has been seen), so waiting on one already consumed would
+        never end."""
+        assert ev not in inst.seen, ("wait on an event already observed", inst.key, ev)
+        inst.waits.append(ev)
+
     def _release(self, inst, t, slack, active, out):
         ch = inst.chain
         end = ch.task_end[inst.task]
@@ -361,13 +374,25 @@ class GateModel:
             inst.batch_sum += ch.est[g]
             last = g == end - 1
             if last or (delta is not None and inst.batch_sum > delta):
-                inst.waits.append((START, inst.batch))
+                # the start event of a batch opened ahead (no overlap) has
+                # already been waited for, before its first kernel was released
+                if not (self.urgency_policy and self.cfg["no_overlap"] and inst.batch > 0):
+                    self._wait(inst, (START, inst.batch))
                 if last:
                     out.append(("EVREC", inst.c, inst.f, inst.task, END, inst.batch + 1))
-                    inst.waits.append((END, inst.batch + 1))
+                    self._wait(inst, (END, inst.batch + 1))
                 inst.batch += 1
                 inst.batch_open = False
                 inst.batch_sum = 0
+                if not last and self.urgency_policy and self.cfg["no_overlap"]:
+                    # Launch-synchronisation variants (Sec. 5.3): the next
+                    # batch's start event is recorded right behind this
+                    # batch's last kernel and waited for too, so the next
+                    # batch is launched only once this one has finished.
+                    inst.batch_open = True
+                    inst.batch_first.append(g + 1)
+                    out.append(("EVREC", inst.c, inst.f, inst.task, START, inst.batch))
+                    self._wait(inst, (START, inst.batch))
 
     # ------------------------------------------------------------------
     def timers(self):

@@ -16,7 +16,7 @@ ABI_VERSION = 2
 
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 POLICY_FIFO, POLICY_URGENCY = 0, 1
-F_BIND, F_DELAY, F_BATCH, F_CALIBRATE, F_ADMIT, F_EXIT = 1, 2, 4, 8, 16, 32
+F_BIND, F_DELAY, F_BATCH, F_CALIBRATE, F_ADMIT, F_EXIT, F_NO_OVERLAP = 1, 2, 4, 8, 16, 32, 64
 
 OP_GEMM_F32 = 1
 OP_BIAS_RELU_F32 = 2

@@ -357,7 +357,9 @@ void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& acti
     me.batch_sum += ch.est[g];
     const bool last = g == end - 1;
     if (last || (batching && me.batch_sum > cfg_.delta_eval_ns)) {
-      me.waits.push_back({0, me.batch});
+      // the start event of a batch opened ahead (no overlap) has already
+      // been waited for, before its first kernel was released
+      if (!(gated && cfg_.no_overlap && me.batch > 0)) me.waits.push_back({0, me.batch});
       if (last) {
         out.push_back(rec(UG_REC_EVREC, me.c, me.f, me.task, 0, 1, me.batch + 1, 0));
         me.waits.push_back({1, me.batch + 1});
@@ -365,6 +367,16 @@ void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& acti
       me.batch += 1;
       me.batch_open = false;
       me.batch_sum = 0;
+      if (!last && gated && cfg_.no_overlap) {
+        // no overlap: the next batch's start event is recorded now, right
+        // after this batch's last kernel, and waited for as well, so the
+        // next batch is launched only once this one has finished
+        me.batch_open = true;
+        me.batch_first.push_back(g + 1);
+        me.n_batches += 1;
+        out.push_back(rec(UG_REC_EVREC, me.c, me.f, me.task, 0, 0, me.batch, 0));
+        me.waits.push_back({0, me.batch});
+      }
     }
   }
 }

@@ -34,6 +34,7 @@ namespace ug {
 struct PolicyConfig {
   int policy = UG_POLICY_URGENCY;
   bool bind = true, delay = true, batch = true, calibrate = false, admit = true, exit = false;
+  bool no_overlap = false;             // wait for a closed batch to finish
   int64_t admit_tasks = 4;             // tasks in flight before new ones wait
   int64_t delta_eval_ns = 500000;
   int64_t delay_poll_ns = 1000000;

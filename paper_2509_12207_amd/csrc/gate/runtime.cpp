@@ -138,6 +138,7 @@ ug::PolicyConfig policy_config(const ug_config& cfg) {
   p.calib_period_ns = cfg.calib_period_ns;
   p.admit = (cfg.flags & UG_F_ADMIT) != 0;
   p.exit = (cfg.flags & UG_F_EXIT) != 0;
+  p.no_overlap = (cfg.flags & UG_F_NO_OVERLAP) != 0;
   p.admit_tasks = cfg.admit_tasks;
   p.lanes.assign(cfg.lanes, cfg.lanes + cfg.n_levels);
   return p;
@@ -677,6 +678,7 @@ ug_status ug_set_flags(void* ctx, int32_t policy, uint32_t flags) {
   p.calibrate = (flags & UG_F_CALIBRATE) != 0;
   p.admit = (flags & UG_F_ADMIT) != 0;
   p.exit = (flags & UG_F_EXIT) != 0;
+  p.no_overlap = (flags & UG_F_NO_OVERLAP) != 0;
   return UG_OK;
 }
 

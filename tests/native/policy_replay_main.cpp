@@ -25,12 +25,12 @@ int main() {
   ug::PolicyConfig cfg;
   std::cin >> tok;
   if (tok != "cfg") return 2;
-  int bind, delay, batch, cal, admit, ext, nlev;
+  int bind, delay, batch, cal, admit, ext, nov, nlev;
   std::cin >> cfg.policy >> bind >> delay >> batch >> cal >> cfg.delta_eval_ns >>
       cfg.delay_poll_ns >> cfg.th_slack_ns >> cfg.util_exempt >> cfg.calib_period_ns >> admit >>
-      cfg.admit_tasks >> ext >> nlev;
+      cfg.admit_tasks >> ext >> nov >> nlev;
   cfg.bind = bind, cfg.delay = delay, cfg.batch = batch, cfg.calibrate = cal, cfg.admit = admit;
-  cfg.exit = ext;
+  cfg.exit = ext, cfg.no_overlap = nov;
   cfg.lanes.assign(nlev, 0);
   for (int i = 0; i < nlev; ++i) std::cin >> cfg.lanes[i];
   ug::Policy pol(cfg);

@@ -161,7 +161,8 @@ def _flags(cfg):
             | (capi.F_BATCH if cfg.get("batch", True) else 0)
             | (capi.F_CALIBRATE if cfg.get("calibrate", False) else 0)
             | (capi.F_ADMIT if cfg.get("admit", True) else 0)
-            | (capi.F_EXIT if cfg.get("exit", False) else 0))
+            | (capi.F_EXIT if cfg.get("exit", False) else 0)
+            | (capi.F_NO_OVERLAP if cfg.get("no_overlap", False) else 0))
 
 
 def _gate_for(cfg):
@@ -188,6 +189,8 @@ CFGS = [
     {"policy": "urgency", "th_slack_ns": 3 * MS, "exit": True},
     {"policy": "urgency", "th_slack_ns": 0, "exit": True, "admit": False, "batch": False},
     {"policy": "urgency", "th_slack_ns": 4 * MS, "lanes": [1]},
+    {"policy": "urgency", "th_slack_ns": 2 * MS, "no_overlap": True},
+    {"policy": "urgency", "th_slack_ns": 2 * MS, "no_overlap": True, "delta_eval_ns": 0},
     {"policy": "fifo"},
 ]
 

@@ -102,6 +102,35 @@ def test_cfg0_outputs_and_replay(policy):
     assert metrics["frames"] == 20
 
 
+@pytest.mark.parametrize("mode", ["sync_batched", "sync"])
+def test_cfg0_launch_synchronisation_modes(mode):
+    # the no-overlap launch variants (a closed batch is waited for until it
+    # has finished): every frame completes, outputs match the oracle and the
+    # log replays through the oracle gate model with the same flags
+    wl = synth.config0(frames=4)
+    arr = [(c, f, t // 10) for c, f, t in wl.arrivals]
+    delta = 0 if mode == "sync" else 20_000     # small batches: several per task
+    flags = capi.F_BIND | capi.F_DELAY | capi.F_BATCH | capi.F_ADMIT | capi.F_NO_OVERLAP
+    dw, comps, trace, est, stats, metrics = run_workload(wl, "urgency", arrivals=arr, flags=flags,
+                                                         delta_eval_ns=delta)
+    assert len(comps) == len(arr) and stats["trace_dropped"] == 0
+    check_cfg0_outputs(wl, dw, 0)
+    check_cfg0_outputs(wl, dw, 1)
+    inst = T.instants_from_trace(trace)
+    chains = T.oracle_chains(wl, est)
+    cfg = oracle_cfg("urgency", no_overlap=True, delta_eval_ns=delta)
+    assert des.replay(chains, cfg, inst) is None
+    des.check_log(chains, cfg, inst)
+    # at most one batch of a task on the device at a time: every batch after
+    # the first is preceded by its own start event, recorded behind the last one
+    n_launch = sum(1 for i in inst for d in i[3] if d[0] == "LAUNCH")
+    n_start = sum(1 for i in inst for d in i[3] if d[0] == "EVREC" and d[4] == 0)
+    if mode == "sync":
+        assert n_start == n_launch
+    else:
+        assert len(arr) * 3 < n_start <= n_launch
+
+
 # ----------------------------------------------------------------------------
 def _last_writers(ch):
     """slot name -> last block writing it, per task."""

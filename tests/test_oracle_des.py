@@ -69,6 +69,51 @@ def test_T2_batches_and_overlap_on_gate():
     des.check_log(ch, cfg, res["instants"])
 
 
+# ------------------------------------------------------------------ launch-synchronisation modes
+def _launch_times(res):
+    return {d[3]: t for t, _, _, ds in res["instants"] for d in ds if d[0] == "LAUNCH"}
+
+
+@pytest.mark.parametrize("mode", ["overlap", "sync_batched", "sync", "async"])
+def test_launch_synchronisation_modes(mode):
+    # the T2 chain: kernels of 200, 200, 200, 100, 600, 50 us on an idle
+    # device, Delta_eval = 0.5 ms.  Batches {0,1,2}, {3,4}, {5}.
+    #   overlap (the paper's):   batch b+1 goes out when batch b starts
+    #   synchronous batched:     ... when batch b has finished
+    #   synchronous:             every kernel is a batch, each waits for the last
+    #   asynchronous:            the whole task at once, one end event
+    est = [200 * US, 200 * US, 200 * US, 100 * US, 600 * US, 50 * US]
+    ch = [chain(100 * MS, [(0, [(e, 1.0) for e in est])])]
+    cfg = {"policy": "urgency", "delta_eval_ns": 500 * US,
+           "overlap": {}, "sync_batched": {"no_overlap": True},
+           "sync": {"no_overlap": True, "delta_eval_ns": 0}, "async": {"batch": False}}[mode]
+    cfg = dict({"policy": "urgency", "delta_eval_ns": 500 * US}, **cfg)
+    res = des.simulate(ch, cfg, [(0, 0, 0)], by_est(ch))
+    want = {"overlap": [0, 0, 0, 0, 0, 600],
+            "sync_batched": [0, 0, 0, 600, 600, 1300],
+            "sync": [0, 200, 400, 600, 700, 1300],
+            "async": [0, 0, 0, 0, 0, 0]}[mode]
+    got = _launch_times(res)
+    assert [got[g] for g in range(6)] == [w * US for w in want]
+    # the serial device finishes the frame at the same time in every mode
+    assert res["completed"] == [(0, 0, 0, 1350 * US)]
+    dec = [d for _, _, _, ds in res["instants"] for d in ds]
+    n_start = sum(1 for d in dec if d[0] == "EVREC" and d[4] == START)
+    assert n_start == {"overlap": 3, "sync_batched": 3, "sync": 6, "async": 1}[mode]
+    des.check_log(ch, cfg, res["instants"])
+
+
+def test_every_event_is_waited_for_once():
+    # a wait on an event that was already observed would never end on the
+    # device (the runtime releases an event once seen): the model refuses it
+    model = GateModel([chain(10 * MS, [(0, [(100 * US, 1.0)])])], {"policy": "urgency"})
+    model.instant(0, [(0, 0, 0)], [])
+    inst = model.inst[(0, 0)]
+    inst.seen.add((START, 5))
+    with pytest.raises(AssertionError):
+        GateModel._wait(inst, (START, 5))
+
+
 # ------------------------------------------------------------------ delay timelines
 def _delay_case(poll, deadline_a=3 * MS):
     # A: truly urgent (slack 1.5 ms < TH 2 ms at t = 0, 0.5 ms at 1 ms);

@@ -51,13 +51,14 @@ def _encode(chains, cfg, instants):
     c = {"policy": "urgency", "bind": True, "delay": True, "batch": True, "calibrate": False,
          "delta_eval_ns": 500_000, "delay_poll_ns": 1_000_000, "th_slack_ns": 0,
          "util_exempt": 0.1, "calib_period_ns": 1_000_000, "admit": True, "admit_tasks": 4,
-         "exit": False, "lanes": [2, 6]}
+         "exit": False, "no_overlap": False, "lanes": [2, 6]}
     c.update(cfg)
     lines = [" ".join(str(x) for x in ["cfg", 1 if c["policy"] == "urgency" else 0, int(c["bind"]),
                                        int(c["delay"]), int(c["batch"]), int(c["calibrate"]),
                                        c["delta_eval_ns"], c["delay_poll_ns"], c["th_slack_ns"],
                                        c["util_exempt"], c["calib_period_ns"], int(c["admit"]),
-                                       c["admit_tasks"], int(c["exit"]), len(c["lanes"]),
+                                       c["admit_tasks"], int(c["exit"]),
+                                       int(c["no_overlap"]), len(c["lanes"]),
                                        *c["lanes"]])]
     for ch in chains:
         lines.append(f"chain {ch['deadline_ns']} {len(ch['tasks'])}")
@@ -101,6 +102,8 @@ def test_sanitized_policy_matches_oracle(driver, seed):
                 {"th_slack_ns": 0, "lanes": [2, 8, 8], "calibrate": True, "delay": False},
                 {"th_slack_ns": 2 * MS, "admit": False}, {"th_slack_ns": 0, "admit_tasks": 1},
                 {"th_slack_ns": 2 * MS, "exit": True},
+                {"th_slack_ns": 2 * MS, "no_overlap": True},
+                {"th_slack_ns": 2 * MS, "no_overlap": True, "delta_eval_ns": 0},
                 {"policy": "fifo"}):
         res = des.simulate(chains, cfg, arrivals, dur)
         text = _encode(chains, cfg, res["instants"])
