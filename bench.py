@@ -56,6 +56,12 @@ def parse():
                     help="instead of the benchmark line: one JSON line per variant of a "
                          "sweep (urgency gate vs FIFO on the same arrivals)")
     ap.add_argument("--seeds", type=int, default=1, help="workload seeds per sweep point")
+    ap.add_argument("--serve", action="store_true",
+                    help="instead of the benchmark line: the serving workload (20 chains, "
+                         "Poisson arrivals, per-frame point counts, HBM-budget admission), "
+                         "urgency gate vs FIFO at a 64 GiB and at a tight budget")
+    ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--tight-budget-mib", type=float, default=512.0)
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the per-kernel roofline leg (plus a 1 GiB device copy of known "
                          "size, the scale for HBM byte counters)")
@@ -169,6 +175,98 @@ def run_policy(g, dw, arrivals, torch, be=None):
     m = g.metrics()
     st = g.stats()
     return comps, m, st, t1 - t0
+
+
+def run_serve(g, dw, arrivals, dims, torch):
+    from paper_2509_12207_amd import runner
+    g.start()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    comps, _, deferred = runner.serve(g, dw, arrivals, dims, timeout_s=180.0)
+    g.drain(120.0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.stop()
+    m = g.metrics()
+    st = g.stats()
+    st = dict(st, frames_deferred_distinct=deferred)
+    return comps, m, st, t1 - t0
+
+
+def serve_main(args, torch, capi, runner, synth):
+    """Serving form: config 3 under the urgency gate and FIFO launch, each
+    twice on the same arrivals (urgency, FIFO, FIFO, urgency), at the
+    configured HBM budget and at a tight one."""
+    W, K = args.warmup, args.steps
+    H = max(1, K // 2)
+    wl = synth.config3(seed=args.seed, f_a=args.f_a, window_s=float(W + H))
+    dims = wl.meta["dims"]
+    warm = [(c, f, t) for c, f, t in wl.arrivals if t < W * 1e9]
+    timed = [(c, f, t) for c, f, t in wl.arrivals if t >= W * 1e9]
+    n_kernels = sum(len(t["kernels"]) for ch in wl.chains for t in ch.tasks)
+    dw = runner.DeviceWorkload(wl, n_sets=3)
+    fps = [synth.footprint_bytes(ch) for ch in wl.chains]
+    log(f"{wl.name}: {len(wl.chains)} chains, {n_kernels} kernels, {len(warm)} warm-up + "
+        f"{len(timed)} timed frames; device buffers {dw.nbytes() / 2**30:.2f} GiB; "
+        f"footprints {min(fps) / 2**20:.1f}..{max(fps) / 2**20:.1f} MiB")
+    prof = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16)
+    runner.profile(prof, dw, warmup=2, reps=5)
+    est = runner.estimates(prof, wl)
+    util = sum(sum(est[(c, g)][0] for g in range(sum(len(t["kernels"]) for t in ch.tasks)))
+               / ch.period_ns for c, ch in enumerate(wl.chains))
+    prof.close()
+    points = []
+    for budget in (int(args.budget_gib * 2 ** 30), int(args.tight_budget_mib * 2 ** 20)):
+        gates = {}
+        for name in ("urgency", "fifo"):
+            g = runner.make_gate(wl, name, trace_capacity=0, queue_capacity=1 << 16,
+                                 hbm_budget_bytes=budget)
+            for (c, k), (e, u) in est.items():
+                g.set_estimate(c, k, e, u)
+            for c, fp in enumerate(fps):
+                g.set_footprint(c, fp)
+            gates[name] = g
+        urg = gates["urgency"]
+        urg.set_flags((FULL & ~capi.F_DELAY) | capi.F_CALIBRATE)
+        urg.set_threshold(0)
+        run_serve(urg, dw, warm, dims, torch)
+        th = urg.calibration_threshold(TH_PCT)
+        urg.set_threshold(th)
+        urg.set_flags(FULL)
+        run_serve(gates["fifo"], dw, warm, dims, torch)
+        runs = {"urgency": [], "fifo": []}
+        for name in ("urgency", "fifo", "fifo", "urgency"):
+            g = gates[name]
+            arr = [(c, f, t - W * 10 ** 9) for c, f, t in timed]
+            comps, m, st, wall = run_serve(g, dw, arr, dims, torch)
+            runs[name].append((comps, m, st, wall))
+            log(f"budget {budget / 2**30:.3f} GiB {name}:",
+                json.dumps(summarise(m, st, wall, len(timed))
+                           | {"deferred": int(st["frames_deferred"]),
+                              "hbm_peak_mib": round(st["hbm_peak_bytes"] / 2**20, 1)}))
+        point = {"budget_gib": round(budget / 2 ** 30, 3), "th_urgent_slack_ms": round(th / 1e6, 3)}
+        for name in ("urgency", "fifo"):
+            pr = pooled(runs[name], wl, len(timed), lambda c, w: {})
+            pr["frames_deferred"] = sum(int(r[2]["frames_deferred"]) for r in runs[name])
+            pr["hbm_peak_mib"] = round(max(r[2]["hbm_peak_bytes"] for r in runs[name]) / 2**20, 1)
+            point[name] = pr
+        points.append(point)
+        for g in gates.values():
+            g.close()
+    out = {"metric": "serving: deadline-miss ratio and p50/p99 latency, urgency gate vs FIFO",
+           "value": points[0]["urgency"]["miss_ratio_pct"], "unit": "% frames missed (Eq. 3)",
+           "higher_is_better": False, "n_gpus": 1, "steps": K, "warmup": W, "data": "synthetic",
+           "dtype": "f32",
+           "config": {"workload": "serving: 20 chains (the 11 of configuration 1, repeated), "
+                      "Poisson arrivals (per-chain rate jittered +-20 %), per-frame point counts "
+                      "20k-150k (voxel kernels sized per frame), camera image sizes 256-1024 "
+                      "square per chain, HBM-budget admission", "seed": args.seed,
+                      "f_a": args.f_a, "window_s": H, "frames": len(timed),
+                      "kernels_per_round": n_kernels, "isolated_utilisation": round(util, 3),
+                      "footprint_mib_total": round(sum(fps) / 2**20, 1),
+                      "runs_per_policy": 2, "order": "urgency, fifo, fifo, urgency"},
+           "points": points}
+    print(json.dumps(out), flush=True)
 
 
 def per_chain(comps, wl):
@@ -489,6 +587,9 @@ def main():
     capi.lib()
     if args.sweep:
         sweep_main(args, torch, capi, runner, synth)
+        return
+    if args.serve:
+        serve_main(args, torch, capi, runner, synth)
         return
     if args.roofline_only:
         kernels = [roofline_op(op, args.roofline_reps if op != "voxel" else 5, torch)

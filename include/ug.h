@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define UG_ABI_VERSION 2u
+#define UG_ABI_VERSION 3u
 
 typedef int32_t ug_status;
 enum {
@@ -139,7 +139,11 @@ typedef struct {
   float fparam[4];     /* op-specific float parameters                        */
   int64_t est_ns;      /* estimated execution time E_k; 0 = not yet profiled  */
   float util;          /* utilisation U_k in [0,1]; < 0 = derive from launch  */
-  int32_t pad1;
+  int32_t frame_dim;   /* 0: fixed shape.  d in 1..4: shape[0] varies per
+                          frame: each frame gives it as dims[d-1] in
+                          ug_frame_submit_dims, at most the registered
+                          shape[0] (the size its buffers, workspace and
+                          estimate are made for)                         */
 } ug_kernel;
 
 /* One task: a CPU segment (host-side time before the kernels may launch,
@@ -176,6 +180,11 @@ typedef struct {
                               apart (Sec. 4.4.3, 1 ms); 0 = every instant    */
   int64_t admit_tasks;     /* with UG_F_ADMIT: instances with kernels in
                               flight before new tasks wait (4)              */
+  uint64_t hbm_budget_bytes; /* serving admission: the device memory the
+                              frames in flight may hold, by the footprints
+                              set with ug_chain_set_footprint; a submission
+                              that would exceed it returns UG_EAGAIN.
+                              0 = no budget                                  */
 } ug_config;
 
 /* Completion of one frame (Sec. 6.2: latency, miss). */
@@ -239,6 +248,8 @@ typedef struct {
   int64_t launch_ns;       /* time spent in HIP launch/record calls         */
   uint64_t trace_records;  /* records currently in the log                  */
   uint64_t trace_dropped;  /* records lost because the log was full         */
+  uint64_t frames_deferred; /* submissions refused by the HBM budget        */
+  uint64_t hbm_peak_bytes; /* largest footprint of the frames in flight     */
 } ug_stats;
 
 /* ------------------------------------------------------------------------ */
@@ -315,11 +326,34 @@ ug_status ug_start(void* ctx);
  * is honoured: the frame arrives when the clock reaches it).  buffers[i] is
  * the device pointer of slot i; the caller keeps them alive and unmodified
  * until the frame is returned by ug_poll_complete (borrowed).  *frame gets
- * the frame index within the chain.  Errors: UG_EINVAL, UG_ESTATE (not
- * started), UG_EAGAIN (queue_capacity frames outstanding), UG_EDEVICE. */
+ * the frame index within the chain.  Errors: UG_EINVAL (also: the chain has
+ * per-frame sizes, see ug_frame_submit_dims), UG_ESTATE (not started),
+ * UG_EAGAIN (queue_capacity frames outstanding, or the HBM budget would be
+ * exceeded), UG_EDEVICE. */
 ug_status ug_frame_submit(void* ctx, uint32_t chain, int64_t t_arr_ns,
                           void* const* buffers, uint32_t n_buffers,
                           uint64_t* frame);
+
+/* ug_frame_submit for chains whose kernels have per-frame sizes
+ * (ug_kernel.frame_dim): dims[d] is this frame's value of every shape[0]
+ * registered with frame_dim = d + 1 (n_dims covers the chain's largest
+ * frame_dim; each value at least 1, or 0 for the voxel scatter, and at most
+ * the registered shape[0]).  Serving form (configuration with per-frame
+ * point counts).  Errors: those of ug_frame_submit; UG_EINVAL also for
+ * dims out of range. */
+ug_status ug_frame_submit_dims(void* ctx, uint32_t chain, int64_t t_arr_ns,
+                               void* const* buffers, uint32_t n_buffers,
+                               const int64_t* dims, uint32_t n_dims,
+                               uint64_t* frame);
+
+/* Device memory (bytes) one frame of `chain` holds from submission until
+ * its completion is delivered, for admission against
+ * ug_config.hbm_budget_bytes (serving form, device-resident frames).
+ * Default 0 (not counted).  A frame whose footprint would take the frames
+ * in flight past the budget is refused with UG_EAGAIN (nothing is queued:
+ * the caller retries after completions).  Only before ug_start.  Errors:
+ * UG_EINVAL, UG_ESTATE. */
+ug_status ug_chain_set_footprint(void* ctx, uint32_t chain, uint64_t bytes);
 
 /* Non-blocking: copies up to cap completions into out.  Returns how many
  * (>= 0), or UG_EDEVICE. */

@@ -12,7 +12,7 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libug.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 POLICY_FIFO, POLICY_URGENCY = 0, 1
@@ -41,13 +41,14 @@ EXPORTED = [
     "ug_poll_complete", "ug_drain", "ug_stop", "ug_get_stats", "ug_trace_read",
     "ug_calibration_read", "ug_calibration_threshold", "ug_get_metrics", "ug_replay_instant",
     "ug_kernel_launch", "ug_kernel_util", "ug_kernel_workspace", "ug_kernel_launch_ws",
+    "ug_frame_submit_dims", "ug_chain_set_footprint",
 ]
 
 
 class Kernel(C.Structure):
     _fields_ = [("op", C.c_int32), ("in_", C.c_int32 * 3), ("out", C.c_int32 * 4),
                 ("shape", C.c_int64 * 4), ("fparam", C.c_float * 4), ("est_ns", C.c_int64),
-                ("util", C.c_float), ("pad1", C.c_int32)]
+                ("util", C.c_float), ("frame_dim", C.c_int32)]
 
 
 class Task(C.Structure):
@@ -62,7 +63,7 @@ class Config(C.Structure):
                 ("n_levels", C.c_int32), ("lanes", C.c_int32 * 8), ("th_slack_ns", C.c_int64),
                 ("idle_sleep_ns", C.c_int64), ("queue_capacity", C.c_uint32),
                 ("trace_capacity", C.c_uint32), ("calib_period_ns", C.c_int64),
-                ("admit_tasks", C.c_int64)]
+                ("admit_tasks", C.c_int64), ("hbm_budget_bytes", C.c_uint64)]
 
 
 class Completion(C.Structure):
@@ -83,7 +84,8 @@ class Stats(C.Structure):
                 ("frames_missed", C.c_uint64), ("launches", C.c_uint64), ("holds", C.c_uint64),
                 ("batches", C.c_uint64), ("instants", C.c_uint64), ("collisions", C.c_uint64),
                 ("decide_ns", C.c_int64), ("launch_ns", C.c_int64),
-                ("trace_records", C.c_uint64), ("trace_dropped", C.c_uint64)]
+                ("trace_records", C.c_uint64), ("trace_dropped", C.c_uint64),
+                ("frames_deferred", C.c_uint64), ("hbm_peak_bytes", C.c_uint64)]
 
 
 class Metrics(C.Structure):
@@ -154,12 +156,17 @@ def lib():
         L.ug_kernel_workspace.argtypes = [C.POINTER(Kernel), C.POINTER(C.c_uint64)]
         L.ug_kernel_launch_ws.argtypes = [C.POINTER(Kernel), C.POINTER(vp), C.c_uint32, vp,
                                           C.c_uint64, vp]
+        L.ug_frame_submit_dims.argtypes = [vp, C.c_uint32, C.c_int64, C.POINTER(vp), C.c_uint32,
+                                           C.POINTER(C.c_int64), C.c_uint32,
+                                           C.POINTER(C.c_uint64)]
+        L.ug_chain_set_footprint.argtypes = [vp, C.c_uint32, C.c_uint64]
         for name in ("ug_create", "ug_chain_register", "ug_kernel_set_estimate",
                      "ug_kernel_get_estimate", "ug_profile", "ug_set_threshold", "ug_set_flags",
                      "ug_start", "ug_frame_submit", "ug_poll_complete", "ug_drain", "ug_stop",
                      "ug_get_stats", "ug_trace_read", "ug_calibration_read",
                      "ug_calibration_threshold", "ug_get_metrics", "ug_replay_instant",
-                     "ug_kernel_launch", "ug_kernel_util"):
+                     "ug_kernel_launch", "ug_kernel_util", "ug_frame_submit_dims",
+                     "ug_chain_set_footprint"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -177,7 +184,9 @@ def kernel_struct(k):
 
     dict keys: op (name or id), shape (<= 4 ints), in (<= 3 slots), out (<= 4
     slots), fparam (<= 4 floats), est_ns (int, default 0), util (float,
-    default -1 = derive from the launch shape).
+    default -1 = derive from the launch shape), frame_dim (int, default 0 =
+    fixed shape; d >= 1: shape[0] is the maximum, each frame gives its own
+    value as dims[d - 1]).
     """
     s = Kernel()
     op = k["op"]
@@ -196,6 +205,7 @@ def kernel_struct(k):
         s.fparam[i] = float(v)
     s.est_ns = int(k.get("est_ns", 0))
     s.util = float(k.get("util", -1.0))
+    s.frame_dim = int(k.get("frame_dim", 0))
     return s
 
 
@@ -336,14 +346,25 @@ class Gate:
     def stop(self):
         self._check(lib().ug_stop(self.h), "ug_stop")
 
-    def submit(self, chain, t_arr_ns, ptrs):
+    def submit(self, chain, t_arr_ns, ptrs, dims=None):
+        """Frame index, or None when refused with UG_EAGAIN (queue full or
+        HBM budget).  ``dims``: per-frame sizes (kernels with frame_dim)."""
         arr = pointer_array(ptrs)
         f = C.c_uint64()
-        st = lib().ug_frame_submit(self.h, chain, int(t_arr_ns), arr, len(ptrs), C.byref(f))
+        if dims is None:
+            st = lib().ug_frame_submit(self.h, chain, int(t_arr_ns), arr, len(ptrs), C.byref(f))
+        else:
+            d = (C.c_int64 * max(1, len(dims)))(*[int(x) for x in dims])
+            st = lib().ug_frame_submit_dims(self.h, chain, int(t_arr_ns), arr, len(ptrs), d,
+                                            len(dims), C.byref(f))
         if st == EAGAIN:
             return None
         self._check(st, "ug_frame_submit")
         return int(f.value)
+
+    def set_footprint(self, chain, nbytes):
+        self._check(lib().ug_chain_set_footprint(self.h, chain, int(nbytes)),
+                    "ug_chain_set_footprint")
 
     def poll(self, cap=4096):
         buf = (Completion * cap)()

@@ -45,6 +45,12 @@ struct Frame {
   int64_t f = 0;
   int64_t t_arr = 0;
   std::vector<void*> buffers;
+  std::vector<int64_t> dims;  // per-frame sizes (kernels with frame_dim > 0)
+};
+
+// Per-frame sizes a chain accepts: dims[d] in [lo[d], hi[d]].
+struct DimRange {
+  std::vector<int64_t> lo, hi;
 };
 
 using EvKey = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t>;  // c, f, task, kind, seq
@@ -77,6 +83,11 @@ struct Ctx {
   std::deque<ug_completion> outbox;
   std::vector<int64_t> next_frame;
   uint64_t outstanding = 0;
+  // serving admission (under mu): footprint of one frame per chain, bytes
+  // held by the frames in flight and their peak
+  std::vector<uint64_t> footprint;
+  std::vector<DimRange> dim_range;
+  uint64_t inflight_bytes = 0, hbm_peak = 0, st_deferred = 0;
 
   // completed-frame latencies and per-chain counts since start (under mu)
   std::vector<int64_t> latencies;
@@ -211,8 +222,17 @@ bool execute(Ctx* c, const std::vector<ug_record>& dec) {
         const ug::ChainSpec& ch = c->policy.chains()[d.chain];
         const Frame& fr = c->frames.at(key);
         const int64_t t0 = mono_ns();
-        hipError_t err = ug::launch_kernel(ch.kernels[d.kernel], fr.buffers.data(), c->bound.at(key),
-                                           c->ws[d.chain][d.kernel], c->ws_bytes[d.chain][d.kernel]);
+        const ug_kernel& kd = ch.kernels[d.kernel];
+        hipError_t err;
+        if (kd.frame_dim > 0) {
+          ug_kernel kf = kd;  // this frame's size (checked at submission)
+          kf.shape[0] = fr.dims[kd.frame_dim - 1];
+          err = ug::launch_kernel(kf, fr.buffers.data(), c->bound.at(key),
+                                  c->ws[d.chain][d.kernel], c->ws_bytes[d.chain][d.kernel]);
+        } else {
+          err = ug::launch_kernel(kd, fr.buffers.data(), c->bound.at(key),
+                                  c->ws[d.chain][d.kernel], c->ws_bytes[d.chain][d.kernel]);
+        }
         c->st_launch_ns += mono_ns() - t0;
         if (err != hipSuccess) {
           hip_fail(c, err, "kernel launch");
@@ -261,6 +281,7 @@ void deliver_completions(Ctx* c) {
     c->st_completed++;
     if (out.missed) c->st_missed++;
     if (c->outstanding > 0) --c->outstanding;
+    c->inflight_bytes -= std::min(c->inflight_bytes, c->footprint[f.c]);
   }
   fin.clear();
   c->cv_done.notify_all();
@@ -368,6 +389,44 @@ void stop_thread(Ctx* c) {
   c->stop.store(false);
 }
 
+ug_status submit_frame(Ctx* c, uint32_t chain, int64_t t_arr_ns, void* const* buffers,
+                 uint32_t n_buffers, const int64_t* dims, uint32_t n_dims, uint64_t* frame) {
+  if (!c) return UG_EINVAL;
+  if (sticky(c)) return UG_EDEVICE;
+  if (!c->started) return fail(c, UG_ESTATE, "not started");
+  const auto& chs = c->policy.chains();
+  if (chain >= chs.size() || !buffers || n_buffers != chs[chain].n_buffers)
+    return fail(c, UG_EINVAL, "submit: bad chain or buffer count");
+  for (uint32_t i = 0; i < n_buffers; ++i)
+    if (!buffers[i]) return fail(c, UG_EINVAL, "submit: null buffer");
+  const DimRange& dr = c->dim_range[chain];
+  if (n_dims < dr.lo.size() || (n_dims && !dims))
+    return fail(c, UG_EINVAL, "submit: the chain needs per-frame sizes (ug_frame_submit_dims)");
+  for (size_t d = 0; d < dr.lo.size(); ++d)
+    if (dims[d] < dr.lo[d] || dims[d] > dr.hi[d])
+      return fail(c, UG_EINVAL, "submit: per-frame size out of the registered range");
+  Frame f;
+  f.chain = chain;
+  f.t_arr = t_arr_ns < 0 ? mono_ns() : t_arr_ns;
+  f.buffers.assign(buffers, buffers + n_buffers);
+  if (n_dims) f.dims.assign(dims, dims + n_dims);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->outstanding >= c->cfg.queue_capacity) return UG_EAGAIN;
+  const uint64_t fp = c->footprint[chain];
+  if (c->cfg.hbm_budget_bytes && fp > c->cfg.hbm_budget_bytes - std::min(c->inflight_bytes,
+                                                                          c->cfg.hbm_budget_bytes)) {
+    ++c->st_deferred;
+    return UG_EAGAIN;
+  }
+  c->inflight_bytes += fp;
+  c->hbm_peak = std::max(c->hbm_peak, c->inflight_bytes);
+  f.f = c->next_frame[chain]++;
+  if (frame) *frame = static_cast<uint64_t>(f.f);
+  c->inbox.push_back(std::move(f));
+  ++c->outstanding;
+  c->st_submitted++;
+  return UG_OK;
+}
 }  // namespace
 
 // ========================================================================
@@ -392,6 +451,7 @@ void ug_config_default(ug_config* cfg) {
   cfg->trace_capacity = 0;
   cfg->calib_period_ns = 1000000;
   cfg->admit_tasks = 4;
+  cfg->hbm_budget_bytes = 0;
 }
 
 int64_t ug_now_ns(void) { return mono_ns(); }
@@ -526,7 +586,8 @@ ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
   spec.deadline_ns = deadline_ns;
   spec.best_effort = deadline_ns == 0;
   spec.n_buffers = n_buffers;
-    for (uint32_t j = 0; j < n_tasks; ++j) {
+  DimRange dr;
+  for (uint32_t j = 0; j < n_tasks; ++j) {
     const ug_task& t = tasks[j];
     if (!t.kernels || t.n_kernels == 0 || t.cpu_ns < 0)
       return fail(c, UG_EINVAL, "every task needs at least one kernel and cpu_ns >= 0");
@@ -535,6 +596,18 @@ ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
       const ug_kernel& kd = t.kernels[k];
       if (const char* why = ug::validate_kernel(kd, n_buffers)) return fail(c, UG_EINVAL, why);
       if (kd.est_ns < 0) return fail(c, UG_EINVAL, "est_ns must be >= 0");
+      if (kd.frame_dim < 0 || kd.frame_dim > 4) return fail(c, UG_EINVAL, "frame_dim must be in 0..4");
+      if (kd.frame_dim > 0) {
+        // per-frame shape[0]: at most the registered value, at least 1 (the
+        // voxel scatter takes empty clouds)
+        const size_t d = static_cast<size_t>(kd.frame_dim - 1);
+        if (dr.lo.size() <= d) {
+          dr.lo.resize(d + 1, 0);
+          dr.hi.resize(d + 1, INT64_MAX);
+        }
+        dr.lo[d] = std::max<int64_t>(dr.lo[d], kd.op == UG_OP_VOXEL_F32 ? 0 : 1);
+        dr.hi[d] = std::min(dr.hi[d], kd.shape[0]);
+      }
       float u = kd.util;
       if (u < 0.f) {
         if (c->has_device) {
@@ -563,10 +636,14 @@ ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
       return fail(c, UG_ENOMEM, "kernel workspace allocation failed");
     }
   }
+  for (size_t d = 0; d < dr.lo.size(); ++d)
+    if (dr.hi[d] == INT64_MAX) dr.lo[d] = dr.hi[d] = 0;  // an unused index accepts 0
   c->ws.push_back(std::move(ws));
   c->ws_bytes.push_back(std::move(wsb));
   const uint32_t id = c->policy.add_chain(std::move(spec));
   c->next_frame.push_back(0);
+  c->footprint.push_back(0);
+  c->dim_range.push_back(std::move(dr));
   if (chain_id) *chain_id = id;
   return UG_OK;
 }
@@ -710,6 +787,9 @@ ug_status ug_start(void* ctx) {
     c->latencies.clear();
     c->chain_done.assign(c->policy.chains().size(), 0);
     c->chain_missed.assign(c->policy.chains().size(), 0);
+    c->inflight_bytes = 0;   // no frame is outstanding at a start
+    c->hbm_peak = 0;
+    c->st_deferred = 0;
   }
   // counters cover the frames since this start, like the metrics
   for (auto* a : {&c->st_submitted, &c->st_completed, &c->st_missed, &c->st_launches,
@@ -725,26 +805,21 @@ ug_status ug_start(void* ctx) {
 
 ug_status ug_frame_submit(void* ctx, uint32_t chain, int64_t t_arr_ns, void* const* buffers,
                           uint32_t n_buffers, uint64_t* frame) {
+  return submit_frame(static_cast<Ctx*>(ctx), chain, t_arr_ns, buffers, n_buffers, nullptr, 0, frame);
+}
+
+ug_status ug_frame_submit_dims(void* ctx, uint32_t chain, int64_t t_arr_ns, void* const* buffers,
+                               uint32_t n_buffers, const int64_t* dims, uint32_t n_dims,
+                               uint64_t* frame) {
+  return submit_frame(static_cast<Ctx*>(ctx), chain, t_arr_ns, buffers, n_buffers, dims, n_dims, frame);
+}
+
+ug_status ug_chain_set_footprint(void* ctx, uint32_t chain, uint64_t bytes) {
   Ctx* c = static_cast<Ctx*>(ctx);
   if (!c) return UG_EINVAL;
-  if (sticky(c)) return UG_EDEVICE;
-  if (!c->started) return fail(c, UG_ESTATE, "not started");
-  const auto& chs = c->policy.chains();
-  if (chain >= chs.size() || !buffers || n_buffers != chs[chain].n_buffers)
-    return fail(c, UG_EINVAL, "submit: bad chain or buffer count");
-  for (uint32_t i = 0; i < n_buffers; ++i)
-    if (!buffers[i]) return fail(c, UG_EINVAL, "submit: null buffer");
-  Frame f;
-  f.chain = chain;
-  f.t_arr = t_arr_ns < 0 ? mono_ns() : t_arr_ns;
-  f.buffers.assign(buffers, buffers + n_buffers);
-  std::lock_guard<std::mutex> lk(c->mu);
-  if (c->outstanding >= c->cfg.queue_capacity) return UG_EAGAIN;
-  f.f = c->next_frame[chain]++;
-  if (frame) *frame = static_cast<uint64_t>(f.f);
-  c->inbox.push_back(std::move(f));
-  ++c->outstanding;
-  c->st_submitted++;
+  if (c->started || c->finalized) return fail(c, UG_ESTATE, "footprints are set before start");
+  if (chain >= c->footprint.size()) return fail(c, UG_EINVAL, "no such chain");
+  c->footprint[chain] = bytes;
   return UG_OK;
 }
 
@@ -810,6 +885,11 @@ ug_status ug_get_stats(void* ctx, ug_stats* out) {
   out->collisions = c->started ? 0 : c->policy.collisions();
   out->decide_ns = c->st_decide_ns.load();
   out->launch_ns = c->st_launch_ns.load();
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    out->frames_deferred = c->st_deferred;
+    out->hbm_peak_bytes = c->hbm_peak;
+  }
   std::lock_guard<std::mutex> lk(c->trace_mu);
   out->trace_records = c->trace.size();
   out->trace_dropped = c->trace_dropped;

@@ -94,6 +94,63 @@ def estimates(g, wl):
     return out
 
 
+def serve(g, dw, arrivals, dims=None, lead_ns=20_000_000, timeout_s=120.0):
+    """Serving driver: every frame is submitted when its arrival time comes
+    (not ahead), with its chain's buffer sets taken round robin (frame f
+    uses set f % n_sets; the gate numbers the frames it is given in its own
+    order).  A frame whose buffer set still holds an earlier
+    frame, or that the gate refuses with UG_EAGAIN (HBM budget, queue), waits
+    in a FIFO queue and is retried whenever completions come back; frames of
+    one chain are submitted in arrival order.  The submitted t_arr stays the
+    arrival time, so the wait counts in the frame's latency.  ``dims`` maps
+    (chain, frame) to the frame's per-frame sizes.  Returns (completions,
+    t0, deferrals), deferrals = submissions refused at least once."""
+    from collections import deque
+    t0 = capi.now_ns() + lead_ns
+    todo = deque(sorted(arrivals, key=lambda a: (a[2], a[0], a[1])))
+    waitq = []
+    busy = set()
+    deferred = set()
+    ours = {}            # (chain, frame index given by the gate) -> workload frame
+    done, n_done = [], 0
+    deadline = time.time() + timeout_s + (max(t for _, _, t in arrivals) / 1e9 if arrivals else 0)
+    while n_done < len(arrivals):
+        now = capi.now_ns()
+        while todo and t0 + todo[0][2] <= now:
+            waitq.append(todo.popleft())
+        blocked = set()
+        keep = []
+        for c, f, t in waitq:
+            key = (c, f % dw.n_sets)
+            if c in blocked or key in busy:
+                blocked.add(c)
+                keep.append((c, f, t))
+                continue
+            d = None if dims is None else dims.get((c, f))
+            fid = g.submit(c, t0 + t, dw.ptrs[c][f % dw.n_sets], d)
+            if fid is None:                  # over the HBM budget: retry later
+                deferred.add((c, f))
+                blocked.add(c)
+                keep.append((c, f, t))
+                continue
+            ours[(c, fid)] = f
+            busy.add(key)
+        waitq = keep
+        got = g.poll()
+        if len(got):
+            done.append(got)
+            n_done += len(got)
+            for r in got:
+                c = int(r["chain"])
+                busy.discard((c, ours.pop((c, int(r["frame"]))) % dw.n_sets))
+        elif time.time() > deadline:
+            raise TimeoutError(f"{n_done} of {len(arrivals)} frames completed")
+        elif not todo or t0 + todo[0][2] > capi.now_ns() + 200_000:
+            time.sleep(0.0002)
+    out = np.concatenate(done) if done else np.zeros(0, capi.COMPLETION_DTYPE)
+    return out, t0, len(deferred)
+
+
 def run(g, dw, arrivals, lead_ns=20_000_000, timeout_s=120.0, progress=None, be=None):
     """Submit every arrival (offsets relative to a start time ``lead_ns``
     from now), wait for all completions and return them.  The gate must be

@@ -259,6 +259,8 @@ def _draw_task(rng, modality, task_idx, n_tasks, budget_ns):
 def _shapes(b, s):
     if b["kind"] == "dense":
         return _gemm_shape(b["q"], s)
+    if b["kind"] == "conv" and "img" in b:     # serving: fixed image resolution
+        return (1, b["ch"], b["img"], b["img"])
     if b["kind"] == "conv":
         Cc = _pow2_pick(32, 256, b["q"][0], s)
         H = _pow2_pick(32, 256, b["q"][1], s)
@@ -460,6 +462,85 @@ def config4(seed=0, f_a=1.0, f_d=1.0, u_deadline=0.85, be_gemms=4, be_dim=8192, 
     meta = dict(wl.meta, u_deadline=u_deadline, be_chain=len(wl.chains), be_depth=be_depth,
                 be_gemms=be_gemms, be_dim=d)
     return Workload("cfg4", wl.chains + [be], list(wl.arrivals), seed, meta)
+
+
+def config3(seed=0, n_chains=20, f_a=1.0, u_target=1.3, window_s=10.0, pts=(20_000, 150_000),
+            img=(256, 1024), rate_jitter=0.2):
+    """Serving: ``n_chains`` chains (the rows of configuration 1, repeated),
+    built like configuration 1 with two per-frame / per-chain size draws:
+
+    * LiDAR chains take a different point count per frame, uniform in
+      ``pts``: their voxel kernels are registered at the maximum with
+      frame_dim = 1, and each frame passes its count as dims[0];
+    * camera chains process a per-chain image size (a power of two in
+      ``img``, square): each conv layer runs at that size / 2^(k+1) with
+      16 * 2^k channels, k in {0, 1, 2} (a stride-2 stem before the first).
+
+    Arrivals are a Poisson process per chain: exponential gaps of mean
+    P_c' = P_c * U(1 - rate_jitter, 1 + rate_jitter) / f_a (the rate of each
+    chain jittered by +-20 % once).  ``meta["dims"]`` maps (chain, frame) to
+    the frame's dims; ``meta["frame_dims"]`` lists the chains that need them.
+    """
+    rng = np.random.default_rng([seed, 31])
+    rows = [CHAINS_CFG1[i % len(CHAINS_CFG1)] for i in range(n_chains)]
+    lam = u_target / sum(e / p for _, _, p, e in rows)
+    n_tight = int(round(0.4 * n_chains))
+    tight = set(rng.permutation(n_chains)[:n_tight].tolist())
+    lo_i, hi_i = int(math.log2(img[0])), int(math.log2(img[1]))
+    chains, frame_dims = [], []
+    for ci, (name, modality, period_ms, egpu) in enumerate(rows):
+        crng = np.random.default_rng([seed, 32, ci])
+        e_chain = lam * egpu * MS
+        n_tasks = int(crng.integers(2, 5))
+        split = crng.dirichlet(np.full(n_tasks, 2.0))
+        size = 2 ** int(crng.integers(lo_i, hi_i + 1))
+        task_blocks, scales = [], []
+        for j in range(n_tasks):
+            budget = e_chain * split[j]
+            tb = _draw_task(crng, modality, j, n_tasks, budget)
+            for b in tb:
+                if b["kind"] == "voxel":
+                    b["n_points"] = pts[1]
+                elif b["kind"] == "conv" and modality == "camera":
+                    k = int(crng.integers(0, 3))
+                    b["img"] = max(size >> (k + 1), 8)
+                    b["ch"] = 16 << k
+            task_blocks.append(tb)
+            scales.append(_fit_scale(tb, budget))
+        period = period_ms * MS
+        deadline = int(period * (0.5 if ci in tight else 1.0))
+        ch = _build_chain(f"s{ci}_{name}", modality, period, deadline, task_blocks, scales)
+        var = False
+        for t in ch.tasks:
+            for k in t["kernels"]:
+                if k["op"] == "voxel":
+                    k["frame_dim"] = 1
+                    var = True
+        if var:
+            frame_dims.append(ci)
+        chains.append(ch)
+    arr, dims = [], {}
+    arng = np.random.default_rng([seed, 33])
+    window = int(window_s * 1e9)
+    for ci, ch in enumerate(chains):
+        mean = ch.period_ns * arng.uniform(1 - rate_jitter, 1 + rate_jitter) / f_a
+        t, f = arng.exponential(mean), 0
+        while t < window:
+            arr.append((ci, f, int(t)))
+            if ci in frame_dims:
+                dims[(ci, f)] = [int(arng.integers(pts[0], pts[1] + 1))]
+            f += 1
+            t += arng.exponential(mean)
+    arr.sort(key=lambda a: (a[2], a[0], a[1]))
+    meta = {"f_a": f_a, "u_target": u_target, "tight": sorted(tight), "window_s": window_s,
+            "dims": dims, "frame_dims": frame_dims, "pts": pts, "img": img}
+    return Workload("cfg3", chains, arr, seed, meta)
+
+
+def footprint_bytes(ch):
+    """Device bytes one frame of the chain holds: its output buffers (the
+    inputs are shared by every frame)."""
+    return sum(b.nbytes for b in ch.buffers if b.role == "out")
 
 
 def model_utilisation(wl, f_a=1.0):
