@@ -110,6 +110,11 @@ SWEEPS = {
                {"name": "async", "flags": PAPER & ~4},
                {"name": "sync", "flags": PAPER | NO_OVERLAP, "cfg": {"delta_eval_ns": 0}},
                {"name": "overlap+admit", "flags": FULL}],
+    # ranking order (Sec. 5.3, the policy comparison): urgency against EDF,
+    # SJF, HRRN and lowest chain utilisation first, the paper's mechanisms on
+    "keys": [{"name": k, "flags": PAPER, "cfg": {"order_key": k}}
+             for k in ("urgency", "edf", "sjf", "hrrn", "lcuf")]
+    + [{"name": "urgency+admit", "flags": FULL}],
     # urgency-ordered admission under a cap on launched, unconfirmed work
     "admit": [{"name": "paper", "flags": PAPER}]
     + [{"name": f"admit_{n}", "flags": FULL, "cfg": {"admit_tasks": n}}

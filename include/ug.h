@@ -80,6 +80,27 @@ enum {
                           UG_F_BATCH alone off: asynchronous launching     */
 };
 
+/* Orders that rank the instances (ug_config.order_key).  The paper's
+ * urgency (Eq. 2) is the default; the others are the alternatives of its
+ * policy comparison (Sec. 5.3), each with ties broken by (chain, frame):
+ *   EDF   earliest absolute deadline t_arr + D first;
+ *   SJF   least remaining estimated work (GPU and CPU, as in Eq. 2) first;
+ *   HRRN  highest response ratio (t - t_arr + R) / R first, R = remaining
+ *         work (R = 0 ranks first);
+ *   LCUF  lowest chain utilisation (a frame's estimated work / period)
+ *         first (period 0 ranks last).
+ * The key replaces urgency in the service order, the binding rank and the
+ * "more urgent than" of delayed launching; truly urgent (TH_urgent), the
+ * reserved level and calibration stay defined by urgency.  Best-effort
+ * instances rank last under every key. */
+enum {
+  UG_KEY_URGENCY = 0,
+  UG_KEY_EDF = 1,
+  UG_KEY_SJF = 2,
+  UG_KEY_HRRN = 3,
+  UG_KEY_LCUF = 4
+};
+
 /* Operations.  Shapes and slot meaning per op; all float buffers are fp32,
  * row-major / NCHW, densely packed.  "in"/"out" hold buffer-slot indices
  * into the pointer array passed with each frame (-1 = unused).
@@ -185,6 +206,8 @@ typedef struct {
                               set with ug_chain_set_footprint; a submission
                               that would exceed it returns UG_EAGAIN.
                               0 = no budget                                  */
+  int32_t order_key;       /* UG_KEY_* (urgency policy only; default URGENCY) */
+  uint32_t pad_end;
 } ug_config;
 
 /* Completion of one frame (Sec. 6.2: latency, miss). */

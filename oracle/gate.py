@@ -47,6 +47,8 @@ batches of the task.
 
 from collections import deque
 
+from fractions import Fraction
+
 import numpy as np
 
 from . import policy as P
@@ -60,6 +62,7 @@ class ChainSpec:
 
     def __init__(self, spec):
         self.deadline = int(spec["deadline_ns"])
+        self.period = int(spec.get("period_ns", 0))
         # deadline 0: a best-effort chain (never urgent, always delayable,
         # ranked below every deadline instance, outside the miss ratio)
         self.best_effort = self.deadline == 0
@@ -136,6 +139,7 @@ DEFAULT_CFG = {
     "admit_tasks": 4,           # instances with kernels in flight before new tasks wait
     "exit": False,              # early chain exit (Sec. 4.3)
     "no_overlap": False,        # wait for a closed batch to finish (launch-sync variants)
+    "key": "urgency",           # ranking order: urgency | edf | sjf | hrrn | lcuf
 }
 
 
@@ -146,6 +150,7 @@ class GateModel:
             self.cfg.update(cfg)
         self.chains = [c if isinstance(c, ChainSpec) else ChainSpec(c) for c in chains]
         self.urgency_policy = self.cfg["policy"] == "urgency"
+        self.now = 0
         self.u_exempt = np.float32(self.cfg["util_exempt"])
         self.lanes = list(self.cfg["lanes"])
         self.n_levels = len(self.lanes)
@@ -204,6 +209,7 @@ class GateModel:
         ``arrivals``: (c, f, t_arr) of frames first seen at this instant.
         ``evdones``: (c, f, j, kind, seq) of events observed complete.
         """
+        self.now = t
         out = []
         finished = []
         # 1. inputs, in canonical order
@@ -275,7 +281,7 @@ class GateModel:
                  if i.phase == "launch" and i.g_next < i.chain.task_end[i.task]
                  and not i.waits and (i.wake is None or i.wake <= t)]
         if self.urgency_policy:
-            ready = [r[2] for r in P.rank_sort([(slack[i.key], i.key, i) for i in ready])]
+            ready = self._order(ready, slack, t)
         self.n_active = sum(1 for i in active if i.in_flight())
         for inst in ready:
             self._release(inst, t, slack, active, out)
@@ -291,6 +297,44 @@ class GateModel:
     def _urgent(self, s):
         return P.is_truly_urgent(s, self.cfg["th_slack_ns"])
 
+    def _before(self, a, b, slack, t):
+        """True iff instance a ranks before b.  Urgency (Eq. 2) by default;
+        the alternatives of the policy comparison (Sec. 5.3) otherwise, each
+        with best-effort instances last and ties broken by (chain, frame):
+        EDF (earliest t_arr + D), SJF (least remaining work R, the two sums
+        of Eq. 2), HRRN (highest (t - t_arr + R) / R; R = 0 first), LCUF
+        (lowest estimated work per frame / period; period 0 last)."""
+        k = self.cfg["key"]
+        if k == "urgency":
+            return P.more_urgent(slack[a.key], a.key, slack[b.key], b.key)
+        ca, cb = a.chain, b.chain
+        if ca.best_effort != cb.best_effort:
+            return cb.best_effort
+        if not ca.best_effort:
+            ra = ca.gpu_rem[a.i_gpu] + ca.cpu_rem[a.i_cpu]
+            rb = cb.gpu_rem[b.i_gpu] + cb.cpu_rem[b.i_cpu]
+            if k == "edf":
+                va, vb = a.t_arr + ca.deadline, b.t_arr + cb.deadline
+            elif k == "sjf":
+                va, vb = ra, rb
+            elif k == "hrrn":
+                # larger ratio first: compare the negated ratios, R = 0 first
+                va = (0, 0) if ra == 0 else (1, -Fraction(t - a.t_arr + ra, ra))
+                vb = (0, 0) if rb == 0 else (1, -Fraction(t - b.t_arr + rb, rb))
+            elif k == "lcuf":
+                va = (1, 0) if ca.period <= 0 else (0, Fraction(ca.gpu_rem[0] + ca.cpu_rem[0], ca.period))
+                vb = (1, 0) if cb.period <= 0 else (0, Fraction(cb.gpu_rem[0] + cb.cpu_rem[0], cb.period))
+            else:
+                raise ValueError(k)
+            if va != vb:
+                return va < vb
+        return a.key < b.key
+
+    def _order(self, insts, slack, t):
+        from functools import cmp_to_key
+        return sorted(insts, key=cmp_to_key(
+            lambda a, b: -1 if self._before(a, b, slack, t) else (1 if self._before(b, a, slack, t) else 0)))
+
     def _blocked(self, inst, slack, active):
         """Sec. 4.4.4: another chain's truly urgent, more urgent instance is active."""
         si = slack[inst.key]
@@ -298,7 +342,7 @@ class GateModel:
             if o.c == inst.c or not o.in_flight():
                 continue
             so = slack[o.key]
-            if self._urgent(so) and P.more_urgent(so, o.key, si, inst.key):
+            if self._urgent(so) and self._before(o, inst, slack, self.now):
                 return True
         return False
 
@@ -316,10 +360,10 @@ class GateModel:
             elif self._urgent(si):
                 level = 0
             else:
-                group = [(slack[o.key], o.key, o) for o in active
+                group = [o for o in active
                          if o is not inst and o.in_flight() and not self._urgent(slack[o.key])]
-                group.append((si, inst.key, inst))
-                order = [g[2] for g in P.rank_sort(group)]
+                group.append(inst)
+                order = self._order(group, slack, self.now)
                 rank = order.index(inst) + 1
                 level = P.binding_level(rank, len(order), self.n_levels)
             loads = [(self.lane_load[(level, ln)], ln) for ln in range(self.lanes[level])]

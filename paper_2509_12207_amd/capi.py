@@ -18,6 +18,9 @@ OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, 
 POLICY_FIFO, POLICY_URGENCY = 0, 1
 F_BIND, F_DELAY, F_BATCH, F_CALIBRATE, F_ADMIT, F_EXIT, F_NO_OVERLAP = 1, 2, 4, 8, 16, 32, 64
 
+KEY_URGENCY, KEY_EDF, KEY_SJF, KEY_HRRN, KEY_LCUF = 0, 1, 2, 3, 4
+KEYS = {"urgency": KEY_URGENCY, "edf": KEY_EDF, "sjf": KEY_SJF, "hrrn": KEY_HRRN, "lcuf": KEY_LCUF}
+
 OP_GEMM_F32 = 1
 OP_BIAS_RELU_F32 = 2
 OP_CONV3X3_F32 = 3
@@ -63,7 +66,8 @@ class Config(C.Structure):
                 ("n_levels", C.c_int32), ("lanes", C.c_int32 * 8), ("th_slack_ns", C.c_int64),
                 ("idle_sleep_ns", C.c_int64), ("queue_capacity", C.c_uint32),
                 ("trace_capacity", C.c_uint32), ("calib_period_ns", C.c_int64),
-                ("admit_tasks", C.c_int64), ("hbm_budget_bytes", C.c_uint64)]
+                ("admit_tasks", C.c_int64), ("hbm_budget_bytes", C.c_uint64),
+                ("order_key", C.c_int32), ("pad_end", C.c_uint32)]
 
 
 class Completion(C.Structure):
@@ -273,6 +277,9 @@ class Gate:
         cfg.policy = POLICY_URGENCY if policy == "urgency" else POLICY_FIFO
         cfg.device = device
         lanes = kw.pop("lanes", None)
+        key = kw.pop("order_key", None)
+        if key is not None:
+            cfg.order_key = KEYS[key] if isinstance(key, str) else int(key)
         if lanes is not None:
             cfg.n_levels = len(lanes)
             for i in range(8):

@@ -112,6 +112,7 @@ void Policy::start_task(Instance& in, int32_t j, int64_t t, std::vector<ug_recor
 bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
                      std::vector<EvDone>& evdones, std::vector<ug_record>& out,
                      const char** err) {
+  now_ = t;
   // 1. inputs in canonical order
   std::sort(arrivals.begin(), arrivals.end(), [](const Arrival& a, const Arrival& b) {
     return a.c != b.c ? a.c < b.c : a.f < b.f;
@@ -247,22 +248,66 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
   }
   if (cfg_.policy == UG_POLICY_URGENCY) {
     std::sort(ready.begin(), ready.end(), [&](const Instance* a, const Instance* b) {
-      return more_urgent(slack[{a->c, a->f}], {a->c, a->f}, slack[{b->c, b->f}], {b->c, b->f});
+      return before(*a, *b, slack);
     });
   }
   for (Instance* in : ready) release(*in, t, active, slack, out);
   return true;
 }
 
+bool Policy::before(const Instance& a, const Instance& b,
+                    const std::map<Key, int64_t>& slack) const {
+  if (cfg_.order_key == UG_KEY_URGENCY)
+    return more_urgent(slack.at({a.c, a.f}), {a.c, a.f}, slack.at({b.c, b.f}), {b.c, b.f});
+  const ChainSpec& ca = chains_[a.c];
+  const ChainSpec& cb = chains_[b.c];
+  if (ca.best_effort != cb.best_effort) return cb.best_effort;
+  if (!ca.best_effort) {
+    int cmp = 0;  // < 0: a first
+    const int64_t ra = ca.gpu_rem[a.i_gpu] + ca.cpu_rem[a.i_cpu];
+    const int64_t rb = cb.gpu_rem[b.i_gpu] + cb.cpu_rem[b.i_cpu];
+    auto sign = [](__int128 x, __int128 y) { return x < y ? -1 : (x > y ? 1 : 0); };
+    switch (cfg_.order_key) {
+      case UG_KEY_EDF:
+        cmp = sign(a.t_arr + ca.deadline_ns, b.t_arr + cb.deadline_ns);
+        break;
+      case UG_KEY_SJF:
+        cmp = sign(ra, rb);
+        break;
+      case UG_KEY_HRRN:
+        // (w_a + R_a) / R_a > (w_b + R_b) / R_b, cross-multiplied; R = 0 first
+        if (ra == 0 || rb == 0)
+          cmp = (ra == 0) == (rb == 0) ? 0 : (ra == 0 ? -1 : 1);
+        else
+          cmp = -sign(static_cast<__int128>(now_ - a.t_arr + ra) * rb,
+                      static_cast<__int128>(now_ - b.t_arr + rb) * ra);
+        break;
+      case UG_KEY_LCUF: {
+        // E_a / P_a < E_b / P_b, cross-multiplied; P = 0 last
+        const int64_t pa = ca.period_ns, pb = cb.period_ns;
+        if (pa <= 0 || pb <= 0)
+          cmp = (pa <= 0) == (pb <= 0) ? 0 : (pa <= 0 ? 1 : -1);
+        else
+          cmp = sign(static_cast<__int128>(ca.gpu_rem[0] + ca.cpu_rem[0]) * pb,
+                     static_cast<__int128>(cb.gpu_rem[0] + cb.cpu_rem[0]) * pa);
+        break;
+      }
+      default:
+        break;
+    }
+    if (cmp) return cmp < 0;
+  }
+  return Key{a.c, a.f} < Key{b.c, b.f};
+}
+
 bool Policy::blocked(const Instance& me, const std::vector<Instance*>& active,
                      const std::map<Key, int64_t>& slack) const {
   // Delayed launching: another chain has an active kernel that is truly
-  // urgent and more urgent than this one.
-  const int64_t sm = slack.at({me.c, me.f});
+  // urgent and ranks before this one.
   for (const Instance* o : active) {
     if (o->c == me.c || !o->in_flight()) continue;
     const int64_t so = slack.at({o->c, o->f});
-    if (urgent(so) && more_urgent(so, {o->c, o->f}, sm, {me.c, me.f})) return true;
+    if (urgent(so) && before(*o, me, slack)) return true;
   }
   return false;
 }
@@ -290,7 +335,7 @@ void Policy::bind(Instance& me, const std::vector<Instance*>& active,
         const int64_t so = slack.at({o->c, o->f});
         if (urgent(so)) continue;
         ++n;
-        if (more_urgent(so, {o->c, o->f}, sm, {me.c, me.f})) ++rank;
+        if (before(*o, me, slack)) ++rank;
       }
       level = 1 + static_cast<int32_t>((static_cast<int64_t>(rank - 1) * (n_levels - 1)) / n);
     }

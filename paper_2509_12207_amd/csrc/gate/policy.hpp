@@ -35,6 +35,7 @@ struct PolicyConfig {
   int policy = UG_POLICY_URGENCY;
   bool bind = true, delay = true, batch = true, calibrate = false, admit = true, exit = false;
   bool no_overlap = false;             // wait for a closed batch to finish
+  int order_key = UG_KEY_URGENCY;      // ranking order (UG_KEY_*)
   int64_t admit_tasks = 4;             // tasks in flight before new ones wait
   int64_t delta_eval_ns = 500000;
   int64_t delay_poll_ns = 1000000;
@@ -141,6 +142,9 @@ class Policy {
 
  private:
   bool urgent(int64_t slack) const;
+  // true iff `a` ranks before `b` under the configured order at the
+  // current instant (strict total order)
+  bool before(const Instance& a, const Instance& b, const std::map<Key, int64_t>& slack) const;
   bool blocked(const Instance& me, const std::vector<Instance*>& active,
                const std::map<Key, int64_t>& slack) const;
   void bind(Instance& me, const std::vector<Instance*>& active,
@@ -163,6 +167,7 @@ class Policy {
   bool sampled_ = false;       // a sample has been taken
   int64_t next_sample_ = 0;    // earliest time of the next sample
   uint64_t collisions_ = 0;
+  int64_t now_ = 0;            // time of the instant being decided
 };
 
 // Exact comparison of urgency levels UL = 1/slack (Eq. 2): true iff

@@ -150,6 +150,7 @@ ug::PolicyConfig policy_config(const ug_config& cfg) {
   p.admit = (cfg.flags & UG_F_ADMIT) != 0;
   p.exit = (cfg.flags & UG_F_EXIT) != 0;
   p.no_overlap = (cfg.flags & UG_F_NO_OVERLAP) != 0;
+  p.order_key = cfg.order_key;
   p.admit_tasks = cfg.admit_tasks;
   p.lanes.assign(cfg.lanes, cfg.lanes + cfg.n_levels);
   return p;
@@ -452,6 +453,7 @@ void ug_config_default(ug_config* cfg) {
   cfg->calib_period_ns = 1000000;
   cfg->admit_tasks = 4;
   cfg->hbm_budget_bytes = 0;
+  cfg->order_key = UG_KEY_URGENCY;
 }
 
 int64_t ug_now_ns(void) { return mono_ns(); }
@@ -479,7 +481,8 @@ ug_status ug_create(const ug_config* cfg, void** out) {
   for (int i = 0; i < cfg->n_levels; ++i)
     if (cfg->lanes[i] < 1 || cfg->lanes[i] > 64) return UG_EINVAL;
   if (cfg->delta_eval_ns < 0 || cfg->delay_poll_ns < 0 || cfg->queue_capacity == 0 ||
-      cfg->calib_period_ns < 0 || cfg->admit_tasks < 1)
+      cfg->calib_period_ns < 0 || cfg->admit_tasks < 1 || cfg->order_key < UG_KEY_URGENCY ||
+      cfg->order_key > UG_KEY_LCUF)
     return UG_EINVAL;
   std::unique_ptr<Ctx> c(new (std::nothrow) Ctx());
   if (!c) return UG_ENOMEM;

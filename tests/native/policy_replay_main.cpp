@@ -28,7 +28,7 @@ int main() {
   int bind, delay, batch, cal, admit, ext, nov, nlev;
   std::cin >> cfg.policy >> bind >> delay >> batch >> cal >> cfg.delta_eval_ns >>
       cfg.delay_poll_ns >> cfg.th_slack_ns >> cfg.util_exempt >> cfg.calib_period_ns >> admit >>
-      cfg.admit_tasks >> ext >> nov >> nlev;
+      cfg.admit_tasks >> ext >> nov >> cfg.order_key >> nlev;
   cfg.bind = bind, cfg.delay = delay, cfg.batch = batch, cfg.calibrate = cal, cfg.admit = admit;
   cfg.exit = ext, cfg.no_overlap = nov;
   cfg.lanes.assign(nlev, 0);
@@ -40,7 +40,7 @@ int main() {
     if (tok == "chain") {
       ug::ChainSpec ch;
       int nt;
-      std::cin >> ch.deadline_ns >> nt;
+      std::cin >> ch.deadline_ns >> ch.period_ns >> nt;
       ch.best_effort = ch.deadline_ns == 0;
       for (int j = 0; j < nt; ++j) {
         std::string t;

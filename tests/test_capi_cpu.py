@@ -172,7 +172,8 @@ def _gate_for(cfg):
                      delay_poll_ns=cfg.get("delay_poll_ns", 1_000_000),
                      th_slack_ns=cfg.get("th_slack_ns", 0),
                      calib_period_ns=cfg.get("calib_period_ns", 1_000_000),
-                     admit_tasks=cfg.get("admit_tasks", 4))
+                     admit_tasks=cfg.get("admit_tasks", 4),
+                     order_key=cfg.get("key", "urgency"))
 
 
 CFGS = [
@@ -191,6 +192,10 @@ CFGS = [
     {"policy": "urgency", "th_slack_ns": 4 * MS, "lanes": [1]},
     {"policy": "urgency", "th_slack_ns": 2 * MS, "no_overlap": True},
     {"policy": "urgency", "th_slack_ns": 2 * MS, "no_overlap": True, "delta_eval_ns": 0},
+    {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "edf"},
+    {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "sjf"},
+    {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "hrrn"},
+    {"policy": "urgency", "th_slack_ns": 0, "key": "lcuf", "lanes": [2, 3, 3]},
     {"policy": "fifo"},
 ]
 

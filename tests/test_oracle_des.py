@@ -114,6 +114,42 @@ def test_every_event_is_waited_for_once():
         GateModel._wait(inst, (START, 5))
 
 
+# ------------------------------------------------------------------ alternative orders
+@pytest.mark.parametrize("key,want", [
+    # three chains, one one-kernel task each, all arriving at t = 0 on an idle
+    # device (nobody truly urgent, so every request launches at once in rank
+    # order):   A: D 10 ms, E 6 ms, P 100 ms  -> slack 4, deadline 10, util 0.06
+    #           B: D  8 ms, E 1 ms, P  10 ms  -> slack 7, deadline  8, util 0.1
+    #           C: D 20 ms, E 15 ms, P 500 ms -> slack 5, deadline 20, util 0.03
+    ("urgency", [0, 2, 1]),   # least slack first (highest 1/slack)
+    ("edf", [1, 0, 2]),       # earliest t_arr + D
+    ("sjf", [1, 0, 2]),       # least remaining work
+    ("lcuf", [2, 0, 1]),      # lowest E / P
+    ("hrrn", [0, 1, 2]),      # no waiting yet: every ratio is 1, ties by chain
+])
+def test_alternative_orders_rank_as_defined(key, want):
+    ch = [dict(chain(10 * MS, [(0, [(6 * MS, 1.0)])]), period_ns=100 * MS),
+          dict(chain(8 * MS, [(0, [(1 * MS, 1.0)])]), period_ns=10 * MS),
+          dict(chain(20 * MS, [(0, [(15 * MS, 1.0)])]), period_ns=500 * MS)]
+    model = GateModel(ch, {"policy": "urgency", "key": key, "admit": False})
+    dec = model.instant(0, [(0, 0, 0), (1, 0, 0), (2, 0, 0)], [])
+    assert [d[1] for d in dec if d[0] == "LAUNCH"] == want
+
+
+def test_hrrn_prefers_the_longer_wait():
+    # HRRN at t = 4 ms: A (arrived at 0, R = 6 ms) has (4 + 6) / 6 = 1.67;
+    # B (arrived at 3 ms, R = 1 ms) has (1 + 1) / 1 = 2: B first; SJF agrees
+    # here, EDF (A's 10 ms before B's 11 ms) does not
+    ch = [chain(10 * MS, [(0, [(6 * MS, 1.0)])]), chain(8 * MS, [(0, [(1 * MS, 1.0)])])]
+    for key, first in (("hrrn", 1), ("edf", 0)):
+        model = GateModel(ch, {"policy": "urgency", "key": key})
+        model.instant(4 * MS, [(0, 0, 0), (1, 0, 3 * MS)], [])
+        a, b = model.inst[(0, 0)], model.inst[(1, 0)]
+        slack = {i.key: model.slack(i, 4 * MS) for i in (a, b)}
+        order = model._order([a, b], slack, 4 * MS)
+        assert order[0].c == first, key
+
+
 # ------------------------------------------------------------------ delay timelines
 def _delay_case(poll, deadline_a=3 * MS):
     # A: truly urgent (slack 1.5 ms < TH 2 ms at t = 0, 0.5 ms at 1 ms);

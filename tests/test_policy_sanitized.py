@@ -12,6 +12,8 @@ import pytest
 
 from oracle import des
 
+KEYS = {"urgency": 0, "edf": 1, "sjf": 2, "hrrn": 3, "lcuf": 4}   # UG_KEY_* of ug.h
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2509_12207_amd", "csrc")
 MS, US = 1_000_000, 1_000
@@ -51,17 +53,17 @@ def _encode(chains, cfg, instants):
     c = {"policy": "urgency", "bind": True, "delay": True, "batch": True, "calibrate": False,
          "delta_eval_ns": 500_000, "delay_poll_ns": 1_000_000, "th_slack_ns": 0,
          "util_exempt": 0.1, "calib_period_ns": 1_000_000, "admit": True, "admit_tasks": 4,
-         "exit": False, "no_overlap": False, "lanes": [2, 6]}
+         "exit": False, "no_overlap": False, "key": "urgency", "lanes": [2, 6]}
     c.update(cfg)
     lines = [" ".join(str(x) for x in ["cfg", 1 if c["policy"] == "urgency" else 0, int(c["bind"]),
                                        int(c["delay"]), int(c["batch"]), int(c["calibrate"]),
                                        c["delta_eval_ns"], c["delay_poll_ns"], c["th_slack_ns"],
                                        c["util_exempt"], c["calib_period_ns"], int(c["admit"]),
                                        c["admit_tasks"], int(c["exit"]),
-                                       int(c["no_overlap"]), len(c["lanes"]),
+                                       int(c["no_overlap"]), KEYS[c["key"]], len(c["lanes"]),
                                        *c["lanes"]])]
     for ch in chains:
-        lines.append(f"chain {ch['deadline_ns']} {len(ch['tasks'])}")
+        lines.append(f"chain {ch['deadline_ns']} {ch.get('period_ns', 0)} {len(ch['tasks'])}")
         for t in ch["tasks"]:
             ks = " ".join(f"{e} {u!r}" for e, u in zip(t["est_ns"], t["util"]))
             lines.append(f"task {t['cpu_ns']} {len(t['est_ns'])} {ks}")
@@ -86,7 +88,7 @@ def test_sanitized_policy_matches_oracle(driver, seed):
         period = int(r.integers(3, 12)) * MS
         # one chain in five is best-effort (deadline 0)
         deadline = 0 if r.random() < 0.2 else int(period * r.choice([0.5, 1.0]))
-        chains.append({"deadline_ns": deadline, "tasks": tasks})
+        chains.append({"deadline_ns": deadline, "tasks": tasks, "period_ns": period})
         phase = int(r.integers(0, period))
         for f in range(int(r.integers(2, 6))):
             arrivals.append((ci, f, phase + f * period + int(r.integers(0, 500)) * US))
@@ -104,6 +106,8 @@ def test_sanitized_policy_matches_oracle(driver, seed):
                 {"th_slack_ns": 2 * MS, "exit": True},
                 {"th_slack_ns": 2 * MS, "no_overlap": True},
                 {"th_slack_ns": 2 * MS, "no_overlap": True, "delta_eval_ns": 0},
+                {"th_slack_ns": 2 * MS, "key": "edf"}, {"th_slack_ns": 2 * MS, "key": "sjf"},
+                {"th_slack_ns": 2 * MS, "key": "hrrn"}, {"th_slack_ns": 2 * MS, "key": "lcuf"},
                 {"policy": "fifo"}):
         res = des.simulate(chains, cfg, arrivals, dur)
         text = _encode(chains, cfg, res["instants"])
