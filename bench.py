@@ -115,6 +115,10 @@ SWEEPS = {
     "keys": [{"name": k, "flags": PAPER, "cfg": {"order_key": k}}
              for k in ("urgency", "edf", "sjf", "hrrn", "lcuf")]
     + [{"name": "urgency+admit", "flags": FULL}],
+    # estimate noise (Sec. 6.5): the estimates behind the urgency scaled per
+    # task instance by (1000 + k) / 1000, k uniform in [-n, n]
+    "noise": [{"name": f"noise_{n // 10}pct", "cfg": {"est_noise_permille": n, "noise_seed": 1}}
+              for n in (0, 100, 300, 500)],
     # urgency-ordered admission under a cap on launched, unconfirmed work
     "admit": [{"name": "paper", "flags": PAPER}]
     + [{"name": f"admit_{n}", "flags": FULL, "cfg": {"admit_tasks": n}}

@@ -207,7 +207,13 @@ typedef struct {
                               that would exceed it returns UG_EAGAIN.
                               0 = no budget                                  */
   int32_t order_key;       /* UG_KEY_* (urgency policy only; default URGENCY) */
-  uint32_t pad_end;
+  int32_t est_noise_permille; /* estimate-noise experiment (Sec. 6.5): n in
+                              0..1000; the estimates of task j of frame f of
+                              chain c enter the urgency (and SJF / HRRN) as
+                              E * (1000 + k) / 1000, k uniform in [-n, n]
+                              drawn by SplitMix64 from (noise_seed, c, f, j);
+                              batching keeps the profiled E.  0 = none      */
+  uint64_t noise_seed;
 } ug_config;
 
 /* Completion of one frame (Sec. 6.2: latency, miss). */

@@ -140,6 +140,8 @@ DEFAULT_CFG = {
     "exit": False,              # early chain exit (Sec. 4.3)
     "no_overlap": False,        # wait for a closed batch to finish (launch-sync variants)
     "key": "urgency",           # ranking order: urgency | edf | sjf | hrrn | lcuf
+    "est_noise_permille": 0,    # estimate noise n: per task instance, E * (1000 + k) / 1000
+    "noise_seed": 0,            #   with k uniform in [-n, n] (Sec. 6.5)
 }
 
 
@@ -180,8 +182,26 @@ class GateModel:
         ch = inst.chain
         if ch.best_effort:
             return None
-        return P.slack_ns(t, inst.t_arr, ch.deadline, ch.gpu_rem[inst.i_gpu],
-                          ch.cpu_rem[inst.i_cpu])
+        gpu, cpu = self.remaining(inst)
+        return P.slack_ns(t, inst.t_arr, ch.deadline, gpu, cpu)
+
+    def remaining(self, inst):
+        """Remaining GPU and CPU work of Eq. (2): the suffix sums, or, with
+        estimate noise, the same sums with every task's part scaled by that
+        task instance's factor (1000 + k) / 1000 (floor per task)."""
+        ch = inst.chain
+        n = self.cfg["est_noise_permille"]
+        if n <= 0:
+            return ch.gpu_rem[inst.i_gpu], ch.cpu_rem[inst.i_cpu]
+        gpu = cpu = 0
+        for j in range(ch.n_tasks):
+            fac = 1000 + P.noise_permille(self.cfg["noise_seed"], inst.c, inst.f, j, n)
+            lo = max(inst.i_gpu, ch.task_first[j])
+            if lo < ch.task_end[j]:
+                gpu += (ch.gpu_rem[lo] - ch.gpu_rem[ch.task_end[j]]) * fac // 1000
+            if j >= inst.i_cpu:
+                cpu += ch.cpu[j] * fac // 1000
+        return gpu, cpu
 
     def _start_task(self, inst, j, t, out):
         ch = inst.chain
@@ -311,8 +331,7 @@ class GateModel:
         if ca.best_effort != cb.best_effort:
             return cb.best_effort
         if not ca.best_effort:
-            ra = ca.gpu_rem[a.i_gpu] + ca.cpu_rem[a.i_cpu]
-            rb = cb.gpu_rem[b.i_gpu] + cb.cpu_rem[b.i_cpu]
+            ra, rb = sum(self.remaining(a)), sum(self.remaining(b))
             if k == "edf":
                 va, vb = a.t_arr + ca.deadline, b.t_arr + cb.deadline
             elif k == "sjf":

@@ -193,3 +193,28 @@ def percentile_nearest_rank(values, pct):
 def percentile_numpy_inverted_cdf(values, pct):
     """The same percentile through numpy's 'inverted_cdf' method (cross-check)."""
     return np.percentile(np.asarray(values), pct, method="inverted_cdf")
+
+
+# ------------------------------------------------------------ estimate noise
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(x):
+    """One output of the SplitMix64 generator (Steele, Lea and Flood, 2014)
+    whose state, before the step, is ``x``: the state advances by the 64-bit
+    golden ratio 0x9E3779B97F4A7C15, then is mixed by two xor-shift-multiply
+    rounds and a final xor-shift."""
+    z = (x + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def noise_permille(seed, c, f, j, n):
+    """Noise of the estimates of task j of frame f of chain c (Sec. 6.5: noise
+    drawn uniformly per task instance): an integer k uniform in [-n, n]; the
+    task's estimates are taken as E * (1000 + k) / 1000.  The draw is a pure
+    function of (seed, chain, frame, task): three chained SplitMix64 outputs,
+    reduced modulo 2n + 1."""
+    h = splitmix64(splitmix64(splitmix64((seed ^ c) & _M64) ^ f) ^ j)
+    return h % (2 * n + 1) - n

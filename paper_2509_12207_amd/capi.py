@@ -67,7 +67,8 @@ class Config(C.Structure):
                 ("idle_sleep_ns", C.c_int64), ("queue_capacity", C.c_uint32),
                 ("trace_capacity", C.c_uint32), ("calib_period_ns", C.c_int64),
                 ("admit_tasks", C.c_int64), ("hbm_budget_bytes", C.c_uint64),
-                ("order_key", C.c_int32), ("pad_end", C.c_uint32)]
+                ("order_key", C.c_int32), ("est_noise_permille", C.c_int32),
+                ("noise_seed", C.c_uint64)]
 
 
 class Completion(C.Structure):

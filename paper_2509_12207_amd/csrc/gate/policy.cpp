@@ -21,6 +21,20 @@ bool ul_greater(int64_t s1, int64_t s2) {
   return (num > 0) == prod_pos;
 }
 
+uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int32_t noise_permille(uint64_t seed, int32_t c, int64_t f, int32_t j, int32_t n) {
+  const uint64_t h = splitmix64(splitmix64(splitmix64(seed ^ static_cast<uint64_t>(c)) ^
+                                           static_cast<uint64_t>(f)) ^
+                                static_cast<uint64_t>(j));
+  return static_cast<int32_t>(h % static_cast<uint64_t>(2 * n + 1)) - n;
+}
+
 bool more_urgent(int64_t s1, const Key& k1, int64_t s2, const Key& k2) {
   if (ul_greater(s1, s2)) return true;
   if (ul_greater(s2, s1)) return false;
@@ -186,7 +200,7 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
         q.pop_front();
         Instance& in = inst_.at({c, f});
         if (exiting && !ch.best_effort &&
-            in.t_arr + ch.deadline_ns - ch.gpu_rem[in.i_gpu] - ch.cpu_rem[in.i_cpu] - t < 0) {
+            in.t_arr + ch.deadline_ns - remaining(in) - t < 0) {
           out.push_back(rec(UG_REC_EXIT, c, f, j, 0, 0, 0, t));
           finished_.push_back({c, f, in.t_arr, t, in.n_holds, in.n_batches, true});
           inst_.erase({c, f});
@@ -214,7 +228,7 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
     slack[{in->c, in->f}] =
         ch.best_effort
             ? kBestEffortSlack
-            : in->t_arr + ch.deadline_ns - ch.gpu_rem[in->i_gpu] - ch.cpu_rem[in->i_cpu] - t;
+            : in->t_arr + ch.deadline_ns - remaining(*in) - t;
   }
   // 5. highest urgency among active kernels, for TH_urgent calibration,
   //    sampled periodically: at the first instant at or after each sampling
@@ -255,6 +269,21 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
   return true;
 }
 
+int64_t Policy::remaining(const Instance& in) const {
+  const ChainSpec& ch = chains_[in.c];
+  const int32_t n = cfg_.est_noise_permille;
+  if (n <= 0) return ch.gpu_rem[in.i_gpu] + ch.cpu_rem[in.i_cpu];
+  int64_t gpu = 0, cpu = 0;
+  const int32_t nt = static_cast<int32_t>(ch.task_first.size());
+  for (int32_t j = 0; j < nt; ++j) {
+    const int64_t fac = 1000 + noise_permille(cfg_.noise_seed, in.c, in.f, j, n);
+    const int32_t lo = std::max(in.i_gpu, ch.task_first[j]);
+    if (lo < ch.task_end[j]) gpu += (ch.gpu_rem[lo] - ch.gpu_rem[ch.task_end[j]]) * fac / 1000;
+    if (j >= in.i_cpu) cpu += ch.cpu[j] * fac / 1000;
+  }
+  return gpu + cpu;
+}
+
 bool Policy::before(const Instance& a, const Instance& b,
                     const std::map<Key, int64_t>& slack) const {
   if (cfg_.order_key == UG_KEY_URGENCY)
@@ -264,8 +293,8 @@ bool Policy::before(const Instance& a, const Instance& b,
   if (ca.best_effort != cb.best_effort) return cb.best_effort;
   if (!ca.best_effort) {
     int cmp = 0;  // < 0: a first
-    const int64_t ra = ca.gpu_rem[a.i_gpu] + ca.cpu_rem[a.i_cpu];
-    const int64_t rb = cb.gpu_rem[b.i_gpu] + cb.cpu_rem[b.i_cpu];
+    const int64_t ra = remaining(a);
+    const int64_t rb = remaining(b);
     auto sign = [](__int128 x, __int128 y) { return x < y ? -1 : (x > y ? 1 : 0); };
     switch (cfg_.order_key) {
       case UG_KEY_EDF:

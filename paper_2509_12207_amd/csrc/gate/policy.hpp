@@ -36,6 +36,8 @@ struct PolicyConfig {
   bool bind = true, delay = true, batch = true, calibrate = false, admit = true, exit = false;
   bool no_overlap = false;             // wait for a closed batch to finish
   int order_key = UG_KEY_URGENCY;      // ranking order (UG_KEY_*)
+  int32_t est_noise_permille = 0;      // estimate noise n (per task instance)
+  uint64_t noise_seed = 0;
   int64_t admit_tasks = 4;             // tasks in flight before new ones wait
   int64_t delta_eval_ns = 500000;
   int64_t delay_poll_ns = 1000000;
@@ -142,6 +144,9 @@ class Policy {
 
  private:
   bool urgent(int64_t slack) const;
+  // remaining GPU + CPU work of Eq. (2) as the gate estimates it (with
+  // estimate noise, each task's part scaled by its instance's factor)
+  int64_t remaining(const Instance& in) const;
   // true iff `a` ranks before `b` under the configured order at the
   // current instant (strict total order)
   bool before(const Instance& a, const Instance& b, const std::map<Key, int64_t>& slack) const;
@@ -169,6 +174,13 @@ class Policy {
   uint64_t collisions_ = 0;
   int64_t now_ = 0;            // time of the instant being decided
 };
+
+// SplitMix64 output for the state x (Steele, Lea and Flood, 2014).
+uint64_t splitmix64(uint64_t x);
+// Estimate noise of task j of frame f of chain c: k uniform in [-n, n] from
+// three chained SplitMix64 outputs of (seed, c, f, j); estimates become
+// E * (1000 + k) / 1000.
+int32_t noise_permille(uint64_t seed, int32_t c, int64_t f, int32_t j, int32_t n);
 
 // Exact comparison of urgency levels UL = 1/slack (Eq. 2): true iff
 // 1/s1 > 1/s2, with 1/0 = +infinity and kBestEffortSlack below everything.

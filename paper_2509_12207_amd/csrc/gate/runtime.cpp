@@ -151,6 +151,8 @@ ug::PolicyConfig policy_config(const ug_config& cfg) {
   p.exit = (cfg.flags & UG_F_EXIT) != 0;
   p.no_overlap = (cfg.flags & UG_F_NO_OVERLAP) != 0;
   p.order_key = cfg.order_key;
+  p.est_noise_permille = cfg.est_noise_permille;
+  p.noise_seed = cfg.noise_seed;
   p.admit_tasks = cfg.admit_tasks;
   p.lanes.assign(cfg.lanes, cfg.lanes + cfg.n_levels);
   return p;
@@ -454,6 +456,8 @@ void ug_config_default(ug_config* cfg) {
   cfg->admit_tasks = 4;
   cfg->hbm_budget_bytes = 0;
   cfg->order_key = UG_KEY_URGENCY;
+  cfg->est_noise_permille = 0;
+  cfg->noise_seed = 0;
 }
 
 int64_t ug_now_ns(void) { return mono_ns(); }
@@ -482,7 +486,8 @@ ug_status ug_create(const ug_config* cfg, void** out) {
     if (cfg->lanes[i] < 1 || cfg->lanes[i] > 64) return UG_EINVAL;
   if (cfg->delta_eval_ns < 0 || cfg->delay_poll_ns < 0 || cfg->queue_capacity == 0 ||
       cfg->calib_period_ns < 0 || cfg->admit_tasks < 1 || cfg->order_key < UG_KEY_URGENCY ||
-      cfg->order_key > UG_KEY_LCUF)
+      cfg->order_key > UG_KEY_LCUF || cfg->est_noise_permille < 0 ||
+      cfg->est_noise_permille > 1000)
     return UG_EINVAL;
   std::unique_ptr<Ctx> c(new (std::nothrow) Ctx());
   if (!c) return UG_ENOMEM;

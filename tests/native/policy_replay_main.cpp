@@ -28,7 +28,8 @@ int main() {
   int bind, delay, batch, cal, admit, ext, nov, nlev;
   std::cin >> cfg.policy >> bind >> delay >> batch >> cal >> cfg.delta_eval_ns >>
       cfg.delay_poll_ns >> cfg.th_slack_ns >> cfg.util_exempt >> cfg.calib_period_ns >> admit >>
-      cfg.admit_tasks >> ext >> nov >> cfg.order_key >> nlev;
+      cfg.admit_tasks >> ext >> nov >> cfg.order_key >> cfg.est_noise_permille >> cfg.noise_seed >>
+      nlev;
   cfg.bind = bind, cfg.delay = delay, cfg.batch = batch, cfg.calibrate = cal, cfg.admit = admit;
   cfg.exit = ext, cfg.no_overlap = nov;
   cfg.lanes.assign(nlev, 0);

@@ -173,7 +173,9 @@ def _gate_for(cfg):
                      th_slack_ns=cfg.get("th_slack_ns", 0),
                      calib_period_ns=cfg.get("calib_period_ns", 1_000_000),
                      admit_tasks=cfg.get("admit_tasks", 4),
-                     order_key=cfg.get("key", "urgency"))
+                     order_key=cfg.get("key", "urgency"),
+                     est_noise_permille=cfg.get("est_noise_permille", 0),
+                     noise_seed=cfg.get("noise_seed", 0))
 
 
 CFGS = [
@@ -196,6 +198,9 @@ CFGS = [
     {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "sjf"},
     {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "hrrn"},
     {"policy": "urgency", "th_slack_ns": 0, "key": "lcuf", "lanes": [2, 3, 3]},
+    {"policy": "urgency", "th_slack_ns": 3 * MS, "est_noise_permille": 300, "noise_seed": 5},
+    {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "hrrn", "est_noise_permille": 500,
+     "noise_seed": 2 ** 63 + 9},
     {"policy": "fifo"},
 ]
 

@@ -150,6 +150,58 @@ def test_hrrn_prefers_the_longer_wait():
         assert order[0].c == first, key
 
 
+# ------------------------------------------------------------------ estimate noise
+def test_splitmix64_published_outputs():
+    # the first outputs of SplitMix64 from the state 0, as published with the
+    # generator (each state advances by 0x9E3779B97F4A7C15)
+    x, got = 0, []
+    for _ in range(4):
+        got.append(P.splitmix64(x))
+        x = (x + 0x9E3779B97F4A7C15) % (1 << 64)
+    assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F,
+                   0xF88BB8A8724C81EC]
+
+
+def test_noise_draws_are_uniform_and_keyed():
+    ks = [P.noise_permille(3, c, f, j, 2) for c in range(5) for f in range(200) for j in range(3)]
+    assert set(ks) == {-2, -1, 0, 1, 2}
+    counts = np.bincount(np.array(ks) + 2)
+    assert counts.min() > 0.8 * len(ks) / 5 and counts.max() < 1.2 * len(ks) / 5
+    # a pure function of (seed, chain, frame, task), different when any changes
+    base = P.noise_permille(3, 1, 2, 0, 300)
+    assert base == P.noise_permille(3, 1, 2, 0, 300)
+    assert len({base, P.noise_permille(4, 1, 2, 0, 300), P.noise_permille(3, 2, 2, 0, 300),
+                P.noise_permille(3, 1, 3, 0, 300), P.noise_permille(3, 1, 2, 1, 300)}) > 1
+    assert all(P.noise_permille(9, c, 0, 0, 0) == 0 for c in range(20))
+
+
+def test_noisy_slack_is_the_slack_of_scaled_estimates():
+    # the noisy remaining work of a frame equals the plain suffix sums of a
+    # chain whose task estimates are scaled by that frame's factors
+    tasks = [(300 * US, [(2 * MS, 1.0), (1 * MS, 1.0)]), (0, [(5 * MS, 1.0)]),
+             (100 * US, [(700 * US, 1.0), (300 * US, 1.0), (1 * MS, 1.0)])]
+    n, seed, f = 400, 77, 3
+    cfg = {"policy": "urgency", "est_noise_permille": n, "noise_seed": seed}
+    noisy = GateModel([chain(50 * MS, tasks)], cfg)
+    noisy.instant(0, [(0, f, 0)], [])
+    fac = [1000 + P.noise_permille(seed, 0, f, j, n) for j in range(3)]
+    # one task at a time, so per-task floors match: compare the first task
+    # alone (before any kernel is confirmed) with its scaled plain chain
+    scaled = [(cpu * fac[j] // 1000, [(e * fac[j] // 1000, u) for e, u in ks])
+              for j, (cpu, ks) in enumerate(tasks)]
+    plain = GateModel([chain(50 * MS, scaled)], {"policy": "urgency"})
+    plain.instant(0, [(0, f, 0)], [])
+    inst_n, inst_p = noisy.inst[(0, f)], plain.inst[(0, f)]
+    gpu_n, cpu_n = noisy.remaining(inst_n)
+    gpu_p = sum((e * fac[j] // 1000) for j, (_, ks) in enumerate(tasks) for e, _ in ks)
+    cpu_p = sum(cpu * fac[j] // 1000 for j, (cpu, _) in enumerate(tasks) if j >= inst_n.i_cpu)
+    # per-task floor of the scaled sum vs the sum of per-kernel floors differ
+    # by less than one nanosecond per kernel
+    assert abs(gpu_n - gpu_p) <= 6 and cpu_n == cpu_p
+    assert noisy.slack(inst_n, 0) == 50 * MS - gpu_n - cpu_n
+    assert abs(plain.slack(inst_p, 0) - noisy.slack(inst_n, 0)) <= 6
+
+
 # ------------------------------------------------------------------ delay timelines
 def _delay_case(poll, deadline_a=3 * MS):
     # A: truly urgent (slack 1.5 ms < TH 2 ms at t = 0, 0.5 ms at 1 ms);
