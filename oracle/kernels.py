@@ -22,6 +22,8 @@ reordering:
   that share the GPU with the deadline chains).
 * BF16 matrix product  C = A B with A, B in bfloat16 and an FP32 result
   (the reduced-precision form of the dense layers).
+* vector add      c = a + b (the custom kernel of the sensitivity
+  experiments, whose utilisation and duration are set directly).
 
 Floating point results are computed in float64 from the float32 inputs.  The
 two operations whose results must be bit-exact take their decisions in
@@ -316,3 +318,9 @@ def gemm_bf16_entry_f64(A16, Bt16, m, n):
     a = bf16_decode(A16[m])
     b = bf16_decode(Bt16[n])
     return float(np.dot(a, b)), float(np.dot(np.abs(a), np.abs(b)))
+
+
+def vecadd_f32(A, B):
+    """c = fl32(a + b) elementwise: one IEEE float32 addition (round to
+    nearest even).  The bit-exact reference of the custom vector-add kernel."""
+    return np.asarray(A, dtype=np.float32) + np.asarray(B, dtype=np.float32)

@@ -337,3 +337,19 @@ def test_gemm_bf16_matches_torch_bfloat16_path():
     got = K.gemm_bf16_f64(a16.view(torch.int16).numpy().view(np.uint16),
                           b16.view(torch.int16).numpy().view(np.uint16))
     assert np.array_equal(got, ref)
+
+
+
+# ----------------------------------------------------------------- vector add
+def test_vecadd_is_the_rounded_exact_sum():
+    # the sum of two float32 values is exact in float64; rounding it once to
+    # float32 is the IEEE float32 addition
+    r = np.random.default_rng(12)
+    a = (r.standard_normal(4096) * np.exp2(r.integers(-30, 30, 4096))).astype(np.float32)
+    b = (r.standard_normal(4096) * np.exp2(r.integers(-30, 30, 4096))).astype(np.float32)
+    want = (a.astype(np.float64) + b.astype(np.float64)).astype(np.float32)
+    assert np.array_equal(K.vecadd_f32(a, b).view(np.uint32), want.view(np.uint32))
+    sp = K.vecadd_f32(np.array([np.inf, -0.0, -0.0, 1.0], np.float32),
+                      np.array([-np.inf, -0.0, 0.0, -1.0], np.float32))
+    assert np.isnan(sp[0]) and np.signbit(sp[1]) and not np.signbit(sp[2])
+    assert sp[3] == 0 and not np.signbit(sp[3])
