@@ -115,6 +115,10 @@ SWEEPS = {
     "keys": [{"name": k, "flags": PAPER, "cfg": {"order_key": k}}
              for k in ("urgency", "edf", "sjf", "hrrn", "lcuf")]
     + [{"name": "urgency+admit", "flags": FULL}],
+    # task graphs (configuration 2): every task launched as one captured
+    # HIP graph, gated per task
+    "graph": [{"name": "paper", "flags": PAPER}, {"name": "paper+graph", "flags": PAPER | 128},
+              {"name": "full", "flags": FULL}, {"name": "full+graph", "flags": FULL | 128}],
     # estimate noise (Sec. 6.5): the estimates behind the urgency scaled per
     # task instance by (1000 + k) / 1000, k uniform in [-n, n]
     "noise": [{"name": f"noise_{n // 10}pct", "cfg": {"est_noise_permille": n, "noise_seed": 1}}

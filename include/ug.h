@@ -71,13 +71,20 @@ enum {
   UG_F_EXIT = 32u,     /* early chain exit (Sec. 4.3): a frame whose urgency
                           is negative when a task would start leaves the
                           chain; it completes as missed and exited        */
-  UG_F_NO_OVERLAP = 64u /* launch-synchronisation variants (Sec. 5.3): a
+  UG_F_NO_OVERLAP = 64u, /* launch-synchronisation variants (Sec. 5.3): a
                           closed batch is waited for until it has finished
                           (not until it has started) before the task's next
                           batch is launched.  With UG_F_BATCH: synchronous
                           batched launching; with delta_eval_ns = 0 as well:
                           synchronous launching (one kernel per batch).
                           UG_F_BATCH alone off: asynchronous launching     */
+  UG_F_GRAPH = 128u     /* task graphs (configuration 2): every task of a frame
+                          is captured once (per buffer set and per-frame
+                          sizes) into a HIP graph and launched as one graph
+                          on its bound stream; the gate decides per task
+                          (delayed launching at the task's first kernel,
+                          with the task's largest utilisation; no batches
+                          inside a task).  Applies to both policies.      */
 };
 
 /* Orders that rank the instances (ug_config.order_key).  The paper's
@@ -138,6 +145,13 @@ enum {
  *                       out {C[M,N] fp32}; A and Bt 16-byte aligned.  The
  *                       reduced-precision form of the GEMM (configuration
  *                       with BF16 contractions).
+ *  UG_OP_VECADD_F32     c = a + b (one float32 addition each).  shape {N, W,
+ *                       R}; in {A[N], B[N]}; out {C[N]}; run by exactly W
+ *                       workgroups of 256 lanes (1 <= W <= 65536), the pass
+ *                       repeated R times (0 or 1: once; <= 65536), so its
+ *                       utilisation is min(1, W / CUs) and its duration
+ *                       follows from N R / W: the custom kernel of the
+ *                       utilisation and kernel-time experiments (Sec. 6.5).
  */
 enum {
   UG_OP_GEMM_F32 = 1,
@@ -147,7 +161,8 @@ enum {
   UG_OP_SOFTMAX_F32 = 5,
   UG_OP_VOXEL_F32 = 6,
   UG_OP_GEMM_FP8 = 7,
-  UG_OP_GEMM_BF16 = 8
+  UG_OP_GEMM_BF16 = 8,
+  UG_OP_VECADD_F32 = 9
 };
 
 /* One kernel of a task (a row of the paper's lookup table, Tab. "Example

@@ -140,6 +140,7 @@ DEFAULT_CFG = {
     "exit": False,              # early chain exit (Sec. 4.3)
     "no_overlap": False,        # wait for a closed batch to finish (launch-sync variants)
     "key": "urgency",           # ranking order: urgency | edf | sjf | hrrn | lcuf
+    "graph": False,             # tasks launch as one graph each (configuration 2)
     "est_noise_permille": 0,    # estimate noise n: per task instance, E * (1000 + k) / 1000
     "noise_seed": 0,            #   with k uniform in [-n, n] (Sec. 6.5)
 }
@@ -404,11 +405,17 @@ class GateModel:
     def _release(self, inst, t, slack, active, out):
         ch = inst.chain
         end = ch.task_end[inst.task]
-        delta = self.cfg["delta_eval_ns"] if (self.urgency_policy and self.cfg["batch"]) else None
+        graph = self.urgency_policy and self.cfg["graph"]
+        delta = (self.cfg["delta_eval_ns"]
+                 if (self.urgency_policy and self.cfg["batch"] and not graph) else None)
         while inst.g_next < end and not inst.waits:
             g = inst.g_next
-            if (self.urgency_policy and self.cfg["delay"]
-                    and (ch.best_effort or ch.util[g] >= self.u_exempt)
+            # task graphs: the task is one launch, gated at its first kernel
+            # with the largest utilisation of its kernels, never inside
+            gate_here = not graph or g == ch.task_first[inst.task]
+            u = max(ch.util[g:end]) if graph and gate_here else ch.util[g]
+            if (self.urgency_policy and self.cfg["delay"] and gate_here
+                    and (ch.best_effort or u >= self.u_exempt)
                     and self._blocked(inst, slack, active)):
                 out.append(("HOLD", inst.c, inst.f, g))
                 poll = self.cfg["delay_poll_ns"]

@@ -17,6 +17,7 @@ ABI_VERSION = 3
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 POLICY_FIFO, POLICY_URGENCY = 0, 1
 F_BIND, F_DELAY, F_BATCH, F_CALIBRATE, F_ADMIT, F_EXIT, F_NO_OVERLAP = 1, 2, 4, 8, 16, 32, 64
+F_GRAPH = 128
 
 KEY_URGENCY, KEY_EDF, KEY_SJF, KEY_HRRN, KEY_LCUF = 0, 1, 2, 3, 4
 KEYS = {"urgency": KEY_URGENCY, "edf": KEY_EDF, "sjf": KEY_SJF, "hrrn": KEY_HRRN, "lcuf": KEY_LCUF}
@@ -29,9 +30,10 @@ OP_SOFTMAX_F32 = 5
 OP_VOXEL_F32 = 6
 OP_GEMM_FP8 = 7
 OP_GEMM_BF16 = 8
+OP_VECADD_F32 = 9
 OP_NAMES = {OP_GEMM_F32: "gemm", OP_BIAS_RELU_F32: "bias_relu", OP_CONV3X3_F32: "conv3x3",
             OP_ROWSUM_F32: "rowsum", OP_SOFTMAX_F32: "softmax", OP_VOXEL_F32: "voxel",
-            OP_GEMM_FP8: "gemm_fp8", OP_GEMM_BF16: "gemm_bf16"}
+            OP_GEMM_FP8: "gemm_fp8", OP_GEMM_BF16: "gemm_bf16", OP_VECADD_F32: "vecadd"}
 OP_IDS = {v: k for k, v in OP_NAMES.items()}
 
 REC_INSTANT, REC_ARRIVE, REC_EVDONE, REC_COMPLETE = 1, 2, 3, 4

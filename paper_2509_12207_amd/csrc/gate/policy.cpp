@@ -384,10 +384,17 @@ void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& acti
   const ChainSpec& ch = chains_[me.c];
   const int32_t end = ch.task_end[me.task];
   const bool gated = cfg_.policy == UG_POLICY_URGENCY;
-  const bool batching = gated && cfg_.batch;
+  const bool graph = gated && cfg_.graph;
+  const bool batching = gated && cfg_.batch && !graph;
   while (me.g_next < end && me.waits.empty()) {
     const int32_t g = me.g_next;
-    if (gated && cfg_.delay && (ch.best_effort || ch.util[g] >= cfg_.util_exempt) &&
+    // with task graphs the task is one launch: it is gated at its first
+    // kernel, with the largest utilisation of its kernels
+    const bool gate_here = !graph || g == ch.task_first[me.task];
+    float u = ch.util[g];
+    if (graph && gate_here)
+      for (int32_t k = g; k < end; ++k) u = std::max(u, ch.util[k]);
+    if (gated && cfg_.delay && gate_here && (ch.best_effort || u >= cfg_.util_exempt) &&
         blocked(me, active, slack)) {
       out.push_back(rec(UG_REC_HOLD, me.c, me.f, me.task, g, 0, 0, 0));
       me.n_holds += 1;

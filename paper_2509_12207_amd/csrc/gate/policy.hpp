@@ -35,6 +35,7 @@ struct PolicyConfig {
   int policy = UG_POLICY_URGENCY;
   bool bind = true, delay = true, batch = true, calibrate = false, admit = true, exit = false;
   bool no_overlap = false;             // wait for a closed batch to finish
+  bool graph = false;                  // tasks launch as one graph each
   int order_key = UG_KEY_URGENCY;      // ranking order (UG_KEY_*)
   int32_t est_noise_permille = 0;      // estimate noise n (per task instance)
   uint64_t noise_seed = 0;

@@ -54,6 +54,8 @@ struct DimRange {
 };
 
 using EvKey = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t>;  // c, f, task, kind, seq
+// a captured task: chain, task, the frame's buffer pointers and sizes
+using GraphKey = std::tuple<int32_t, int32_t, std::vector<void*>, std::vector<int64_t>>;
 
 struct Ctx {
   ug_config cfg{};
@@ -75,6 +77,10 @@ struct Ctx {
   std::vector<std::vector<void*>> ws;
   std::vector<std::vector<size_t>> ws_bytes;
   std::map<ug::Key, Frame> frames;                      // arrived, not completed
+  // task graphs (UG_F_GRAPH): captured on their own stream, launched on the
+  // task's bound stream; kept until the context is destroyed
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  hipStream_t capture_stream = nullptr;
   std::vector<Frame> pending;                           // submitted, not arrived
 
   std::mutex mu;  // inbox, outbox, counters, next_frame
@@ -150,6 +156,7 @@ ug::PolicyConfig policy_config(const ug_config& cfg) {
   p.admit = (cfg.flags & UG_F_ADMIT) != 0;
   p.exit = (cfg.flags & UG_F_EXIT) != 0;
   p.no_overlap = (cfg.flags & UG_F_NO_OVERLAP) != 0;
+  p.graph = (cfg.flags & UG_F_GRAPH) != 0;
   p.order_key = cfg.order_key;
   p.est_noise_permille = cfg.est_noise_permille;
   p.noise_seed = cfg.noise_seed;
@@ -193,6 +200,43 @@ hipEvent_t take_event(Ctx* c) {
   return e;
 }
 
+// Graph of task j of a chain for a frame's buffers and sizes: captured on
+// first use (every kernel of the task in order on the capture stream, in
+// relaxed mode so other threads' HIP calls are unaffected), instantiated and
+// cached.  On failure returns null with *err set.
+hipGraphExec_t task_graph(Ctx* c, int32_t chain, int32_t j, const Frame& fr, hipError_t* err) {
+  GraphKey gk{chain, j, fr.buffers, fr.dims};
+  auto it = c->graphs.find(gk);
+  if (it != c->graphs.end()) return it->second;
+  if (!c->capture_stream) {
+    *err = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+    if (*err != hipSuccess) return nullptr;
+  }
+  const ug::ChainSpec& ch = c->policy.chains()[chain];
+  *err = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed);
+  if (*err != hipSuccess) return nullptr;
+  hipError_t launch_err = hipSuccess;
+  for (int32_t g = ch.task_first[j]; g < ch.task_end[j] && launch_err == hipSuccess; ++g) {
+    ug_kernel k = ch.kernels[g];
+    if (k.frame_dim > 0) k.shape[0] = fr.dims[k.frame_dim - 1];
+    launch_err = ug::launch_kernel(k, fr.buffers.data(), c->capture_stream, c->ws[chain][g],
+                                   c->ws_bytes[chain][g]);
+  }
+  hipGraph_t graph = nullptr;
+  *err = hipStreamEndCapture(c->capture_stream, &graph);
+  if (launch_err != hipSuccess) *err = launch_err;
+  if (*err != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return nullptr;
+  }
+  hipGraphExec_t ge = nullptr;
+  *err = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (*err != hipSuccess) return nullptr;
+  c->graphs.emplace(std::move(gk), ge);
+  return ge;
+}
+
 // Executes the decisions of one instant.  Returns false on a device error.
 bool execute(Ctx* c, const std::vector<ug_record>& dec) {
   for (const ug_record& d : dec) {
@@ -227,7 +271,15 @@ bool execute(Ctx* c, const std::vector<ug_record>& dec) {
         const int64_t t0 = mono_ns();
         const ug_kernel& kd = ch.kernels[d.kernel];
         hipError_t err;
-        if (kd.frame_dim > 0) {
+        if (c->cfg.flags & UG_F_GRAPH) {
+          // the task's first kernel launches the task's graph; its other
+          // kernels are inside it
+          err = hipSuccess;
+          if (d.kernel == ch.task_first[d.task]) {
+            hipGraphExec_t ge = task_graph(c, d.chain, d.task, fr, &err);
+            if (ge) err = hipGraphLaunch(ge, c->bound.at(key));
+          }
+        } else if (kd.frame_dim > 0) {
           ug_kernel kf = kd;  // this frame's size (checked at submission)
           kf.shape[0] = fr.dims[kd.frame_dim - 1];
           err = ug::launch_kernel(kf, fr.buffers.data(), c->bound.at(key),
@@ -566,6 +618,8 @@ void ug_destroy(void* ctx) {
       (void)hipStreamDestroy(s);
     }
     for (hipEvent_t e : c->all_events) (void)hipEventDestroy(e);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto& v : c->ws)
       for (void* p : v)
         if (p) (void)hipFree(p);
@@ -764,6 +818,7 @@ ug_status ug_set_flags(void* ctx, int32_t policy, uint32_t flags) {
   p.admit = (flags & UG_F_ADMIT) != 0;
   p.exit = (flags & UG_F_EXIT) != 0;
   p.no_overlap = (flags & UG_F_NO_OVERLAP) != 0;
+  p.graph = (flags & UG_F_GRAPH) != 0;
   return UG_OK;
 }
 

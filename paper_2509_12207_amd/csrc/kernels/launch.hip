@@ -58,6 +58,12 @@ const char* validate_kernel(const ug_kernel& k, uint32_t nb) {
       if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
         return "gemm_fp8: needs in {A, Bt}, out {C}";
       return nullptr;
+    case UG_OP_VECADD_F32:
+      if (!pos(s[0]) || s[1] < 1 || s[1] > 65536 || s[2] < 0 || s[2] > 65536)
+        return "vecadd: N >= 1, 1 <= W <= 65536, 0 <= R <= 65536 (0 = 1)";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
+        return "vecadd: needs in {A, B}, out {C}";
+      return nullptr;
     case UG_OP_GEMM_BF16:
       if (!pos(s[0]) || !pos(s[1]) || !pos(s[2]) || s[2] >= kMaxDim / 2)
         return "gemm_bf16: M, N in [1, 2^31), K in [1, 2^30)";
@@ -104,6 +110,9 @@ hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, voi
         return hipErrorInvalidValue;
       return gemm_fp8_launch(a, bt, F(k.out[0]), s[0], s[1], s[2], st);
     }
+    case UG_OP_VECADD_F32:
+      return vecadd_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1],
+                               s[2] > 0 ? s[2] : 1, st);
     case UG_OP_GEMM_BF16: {
       const auto* a = static_cast<const uint16_t*>(b[k.in[0]]);
       const auto* bt = static_cast<const uint16_t*>(b[k.in[1]]);
@@ -135,6 +144,8 @@ OpPlan plan_kernel(const ug_kernel& k) {
       return gemm_fp8_plan(s[0], s[1], s[2]);
     case UG_OP_GEMM_BF16:
       return gemm_bf16_plan(s[0], s[1], s[2]);
+    case UG_OP_VECADD_F32:
+      return vecadd_f32_plan(s[0], s[1]);
     default:
       return OpPlan{};
   }

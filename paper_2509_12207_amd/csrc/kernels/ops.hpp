@@ -41,6 +41,10 @@ OpPlan gemm_fp8_plan(int64_t M, int64_t N, int64_t K);
 hipError_t gemm_fp8_launch(const unsigned char* A, const unsigned char* Bt, float* C, int64_t M,
                            int64_t N, int64_t K, hipStream_t s);
 
+OpPlan vecadd_f32_plan(int64_t n, int64_t w);
+hipError_t vecadd_f32_launch(const float* a, const float* b, float* c, int64_t n, int64_t w,
+                             int64_t r, hipStream_t s);
+
 OpPlan gemm_bf16_plan(int64_t M, int64_t N, int64_t K);
 hipError_t gemm_bf16_launch(const uint16_t* A, const uint16_t* Bt, float* C, int64_t M,
                             int64_t N, int64_t K, hipStream_t s);

@@ -386,4 +386,57 @@ hipError_t softmax_f32_launch(const float* X, float* Y, int64_t R, int64_t L, hi
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ vector add
+// c = a + b over n floats by exactly `w` workgroups of 256 lanes (grid
+// stride; float4 accesses when all three arrays are 16-byte aligned), the
+// whole pass repeated `r` times (same result).  The custom kernel of the
+// sensitivity experiments: its utilisation is w / CUs and its duration
+// follows from n r / w, with small buffers.
+namespace {
+template <bool VEC>
+__global__ __launch_bounds__(256) void vecadd_kernel(const float* __restrict__ a,
+                                                     const float* __restrict__ b,
+                                                     float* __restrict__ c, int64_t n, int r) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int64_t first = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int rep = 0; rep < r; ++rep) {
+    int64_t done = 0;
+    if (VEC) {
+      const int64_t n4 = n / 4;
+      const float4* a4 = reinterpret_cast<const float4*>(a);
+      const float4* b4 = reinterpret_cast<const float4*>(b);
+      float4* c4 = reinterpret_cast<float4*>(c);
+      for (int64_t i = first; i < n4; i += stride) {
+        const float4 x = a4[i], y = b4[i];
+        c4[i] = make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+      }
+      done = 4 * n4;
+    }
+    for (int64_t i = done + first; i < n; i += stride) c[i] = a[i] + b[i];
+  }
+}
+}  // namespace
+
+OpPlan vecadd_f32_plan(int64_t n, int64_t w) {
+  (void)n;
+  OpPlan p;
+  p.func = reinterpret_cast<const void*>(&vecadd_kernel<true>);
+  p.grid = dim3((unsigned)w);
+  p.block = dim3(256);
+  return p;
+}
+
+hipError_t vecadd_f32_launch(const float* a, const float* b, float* c, int64_t n, int64_t w,
+                             int64_t r, hipStream_t s) {
+  const bool vec = ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) |
+                     reinterpret_cast<uintptr_t>(c)) & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL(vecadd_kernel<true>, dim3((unsigned)w), dim3(256), 0, s, a, b, c, n,
+                       (int)r);
+  else
+    hipLaunchKernelGGL(vecadd_kernel<false>, dim3((unsigned)w), dim3(256), 0, s, a, b, c, n,
+                       (int)r);
+  return hipGetLastError();
+}
+
 }  // namespace ug

@@ -136,6 +136,10 @@ def k_rowsum(R, Cn, z, r):
     return {"op": "rowsum", "shape": (R, Cn), "in": (z,), "out": (r,)}
 
 
+def k_vecadd(N, W, R, a, b, c):
+    return {"op": "vecadd", "shape": (N, W, R), "in": (a, b), "out": (c,)}
+
+
 def k_gemm_fp8(M, N, K, a, bt, c):
     return {"op": "gemm_fp8", "shape": (M, N, K), "in": (a, bt), "out": (c,)}
 
@@ -204,6 +208,10 @@ def _model_ns(op, shape):
     if op == "gemm_fp8":
         M, N, K = shape
         return floor + 2 * M * N * K / 2.5e15 * 1e9
+    if op == "vecadd":
+        # streaming at a rate proportional to the workgroups (256 CUs), R passes
+        N, W, R = shape
+        return floor + 12 * N * max(R, 1) / (5e12 * min(W, 256) / 256) * 1e9
     raise ValueError(op)
 
 
@@ -257,6 +265,8 @@ def _draw_task(rng, modality, task_idx, n_tasks, budget_ns):
 
 
 def _shapes(b, s):
+    if b["kind"] == "vecadd":
+        return (b["n"], b["w"], b["r"])
     if b["kind"] == "dense":
         return _gemm_shape(b["q"], s)
     if b["kind"] == "conv" and "img" in b:     # serving: fixed image resolution
@@ -269,6 +279,8 @@ def _shapes(b, s):
 
 
 def _block_time(b, s):
+    if b["kind"] == "vecadd":
+        return b["count"] * _model_ns("vecadd", (b["n"], b["w"], b["r"]))
     shp = _shapes(b, s)
     if b["kind"] == "dense":
         M, N, K = shp
@@ -285,6 +297,18 @@ def _block_time(b, s):
             t += _model_ns("rowsum", (Cc, H * W))
         return t
     return _model_ns("voxel", shp)
+
+
+def _custom_block(custom, task_ns, n=1 << 20):
+    """Vector-add kernels over n floats with utilisation custom["util"], each
+    repeated to take about custom["kernel_us"] under the time model, as many
+    as fill task_ns of modelled time."""
+    w = max(1, int(round(custom["util"] * 256)))
+    t_k = custom["kernel_us"] * US
+    per_pass = _model_ns("vecadd", (n, w, 1)) - 6 * US
+    r = max(1, int(round((t_k - 6 * US) / per_pass)))
+    count = max(1, int(round(task_ns / _model_ns("vecadd", (n, w, r)))))
+    return {"kind": "vecadd", "n": n, "w": w, "r": r, "count": count, "q": [0.0, 0.0, 0.0]}
 
 
 def _fit_scale(blocks, budget_ns):
@@ -334,6 +358,11 @@ def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales):
                 want("C1", Cc * H * W, "out")
                 if b["rowsum"]:
                     want("RS", Cc, "out")
+            elif b["kind"] == "vecadd":
+                n = shp[0]
+                want("VA", n, "in")
+                want("VB", n, "in")
+                want("VS", n, "out")
             else:
                 n = shp[0]
                 G = VOXEL_GRID[0] * VOXEL_GRID[1]
@@ -373,6 +402,12 @@ def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales):
                 if b["rowsum"]:
                     ks.append(k_rowsum(Cc, H * W, out, slot[f"t{j}.RS"]))
                     outs["RS"] = f"t{j}.RS"
+            elif b["kind"] == "vecadd":
+                n, w, rr = shp
+                for _ in range(b["count"]):
+                    ks.append(k_vecadd(n, w, rr, slot[f"t{j}.VA"], slot[f"t{j}.VB"],
+                                       slot[f"t{j}.VS"]))
+                outs = {"C": f"t{j}.VS"}
             else:
                 n = shp[0]
                 ks.append(k_voxel(n, slot[f"t{j}.pts"], slot[f"t{j}.VI"], slot[f"t{j}.VC"],
@@ -385,7 +420,7 @@ def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales):
 
 
 def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
-            jitter_ms=15.0, chains_subset=None):
+            jitter_ms=15.0, chains_subset=None, custom=None):
     """Eleven chains of 2-6 tasks with 50-300 FP32 kernels per task.
 
     Per-chain GPU work per frame is proportional to the paper's E_gpu of the
@@ -397,6 +432,12 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
     seed) get half-period deadlines, the rest a deadline equal to the period;
     all deadlines are scaled by f_d.  Arrivals: per-chain phase U[0, P'),
     nominal k * P' with P' = P / f_a, plus uniform jitter of +-jitter_ms/2.
+
+    ``custom = {"util": U, "kernel_us": T}`` (the sensitivity experiments,
+    Sec. 6.5): every odd-indexed task of every chain is replaced by custom
+    vector-add kernels run by round(U * 256) workgroups (utilisation U on
+    256 CUs), each sized to take about T us under the time model, as many as
+    keep the task's modelled time (fewer, longer kernels as T grows).
     """
     rng = np.random.default_rng([seed, 1])
     rows = CHAINS_CFG1 if chains_subset is None else [CHAINS_CFG1[i] for i in chains_subset]
@@ -414,6 +455,8 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
         for j in range(n_tasks):
             budget = e_chain * split[j]
             tb = _draw_task(crng, modality, j, n_tasks, budget)
+            if custom is not None and j % 2 == 1:
+                tb = [_custom_block(custom, sum(_block_time(b, _fit_scale(tb, budget)) for b in tb))]
             task_blocks.append(tb)
             scales.append(_fit_scale(tb, budget))
         period = period_ms * MS
@@ -550,7 +593,7 @@ def model_utilisation(wl, f_a=1.0):
         t = 0.0
         for task in ch.tasks:
             for k in task["kernels"]:
-                dims = {"conv3x3": 4, "gemm": 3, "gemm_fp8": 3, "voxel": 1}.get(k["op"], 2)
+                dims = {"conv3x3": 4, "gemm": 3, "gemm_fp8": 3, "voxel": 1, "vecadd": 3}.get(k["op"], 2)
                 t += _model_ns(k["op"], tuple(k["shape"][:dims]))
         u += t / (ch.period_ns / f_a)
     return u

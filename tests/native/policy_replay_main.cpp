@@ -25,13 +25,13 @@ int main() {
   ug::PolicyConfig cfg;
   std::cin >> tok;
   if (tok != "cfg") return 2;
-  int bind, delay, batch, cal, admit, ext, nov, nlev;
+  int bind, delay, batch, cal, admit, ext, nov, graph, nlev;
   std::cin >> cfg.policy >> bind >> delay >> batch >> cal >> cfg.delta_eval_ns >>
       cfg.delay_poll_ns >> cfg.th_slack_ns >> cfg.util_exempt >> cfg.calib_period_ns >> admit >>
-      cfg.admit_tasks >> ext >> nov >> cfg.order_key >> cfg.est_noise_permille >> cfg.noise_seed >>
-      nlev;
+      cfg.admit_tasks >> ext >> nov >> graph >> cfg.order_key >> cfg.est_noise_permille >>
+      cfg.noise_seed >> nlev;
   cfg.bind = bind, cfg.delay = delay, cfg.batch = batch, cfg.calibrate = cal, cfg.admit = admit;
-  cfg.exit = ext, cfg.no_overlap = nov;
+  cfg.exit = ext, cfg.no_overlap = nov, cfg.graph = graph;
   cfg.lanes.assign(nlev, 0);
   for (int i = 0; i < nlev; ++i) std::cin >> cfg.lanes[i];
   ug::Policy pol(cfg);

@@ -162,7 +162,8 @@ def _flags(cfg):
             | (capi.F_CALIBRATE if cfg.get("calibrate", False) else 0)
             | (capi.F_ADMIT if cfg.get("admit", True) else 0)
             | (capi.F_EXIT if cfg.get("exit", False) else 0)
-            | (capi.F_NO_OVERLAP if cfg.get("no_overlap", False) else 0))
+            | (capi.F_NO_OVERLAP if cfg.get("no_overlap", False) else 0)
+            | (capi.F_GRAPH if cfg.get("graph", False) else 0))
 
 
 def _gate_for(cfg):
@@ -199,6 +200,8 @@ CFGS = [
     {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "hrrn"},
     {"policy": "urgency", "th_slack_ns": 0, "key": "lcuf", "lanes": [2, 3, 3]},
     {"policy": "urgency", "th_slack_ns": 3 * MS, "est_noise_permille": 300, "noise_seed": 5},
+    {"policy": "urgency", "th_slack_ns": 3 * MS, "graph": True},
+    {"policy": "urgency", "th_slack_ns": 0, "graph": True, "admit": False, "delay_poll_ns": 0},
     {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "hrrn", "est_noise_permille": 500,
      "noise_seed": 2 ** 63 + 9},
     {"policy": "fifo"},

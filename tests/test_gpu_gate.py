@@ -131,6 +131,28 @@ def test_cfg0_launch_synchronisation_modes(mode):
         assert len(arr) * 3 < n_start <= n_launch
 
 
+@pytest.mark.parametrize("policy", ["urgency", "fifo"])
+def test_cfg0_task_graphs(policy):
+    # every task launched as one captured graph: outputs match the oracle
+    # (both output copies, so each buffer set's graph is exercised) and the
+    # log replays through the oracle gate model with graphs on
+    wl = synth.config0(frames=4)
+    arr = [(c, f, t // 10) for c, f, t in wl.arrivals]
+    flags = (capi.F_BIND | capi.F_DELAY | capi.F_BATCH | capi.F_ADMIT | capi.F_GRAPH
+             if policy == "urgency" else capi.F_GRAPH)
+    dw, comps, trace, est, stats, metrics = run_workload(wl, policy, arrivals=arr, flags=flags)
+    assert len(comps) == len(arr) and stats["trace_dropped"] == 0
+    check_cfg0_outputs(wl, dw, 0)
+    check_cfg0_outputs(wl, dw, 1)
+    inst = T.instants_from_trace(trace)
+    chains = T.oracle_chains(wl, est)
+    cfg = oracle_cfg(policy, graph=True)
+    assert des.replay(chains, cfg, inst) is None
+    # one start event per task: no batches inside a task
+    n_start = sum(1 for i in inst for d in i[3] if d[0] == "EVREC" and d[4] == 0)
+    assert n_start == len(arr) * 3
+
+
 # ----------------------------------------------------------------------------
 def _last_writers(ch):
     """slot name -> last block writing it, per task."""
@@ -242,6 +264,19 @@ def test_cfg1_window_replay_and_sampled_outputs():
     assert des.replay(chains, oracle_cfg("urgency", th=3 * MS), inst) is None
     assert _no_set_overlap(comps, n_sets)
     assert check_cfg1_outputs(wl, dw, 0, samples=4, seed=0) >= 8
+
+
+def test_cfg1_window_task_graphs_replay_and_sampled_outputs():
+    wl = synth.config1(seed=2, window_s=0.3)
+    n_sets = _frames_per_chain(wl)
+    flags = capi.F_BIND | capi.F_DELAY | capi.F_BATCH | capi.F_ADMIT | capi.F_GRAPH
+    dw, comps, trace, est, stats, metrics = run_workload(wl, "urgency", n_sets=n_sets, th=3 * MS,
+                                                         flags=flags)
+    assert len(comps) == len(wl.arrivals) and stats["trace_dropped"] == 0
+    inst = T.instants_from_trace(trace)
+    chains = T.oracle_chains(wl, est)
+    assert des.replay(chains, oracle_cfg("urgency", th=3 * MS, graph=True), inst) is None
+    assert check_cfg1_outputs(wl, dw, 0, samples=3, seed=1) >= 8
 
 
 def test_alone_and_in_the_mix_bit_identical():

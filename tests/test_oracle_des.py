@@ -250,6 +250,28 @@ def test_low_utilisation_kernels_are_exempt():
     assert not any(d[0] == "HOLD" for _, _, _, ds in res["instants"] for d in ds)
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_task_graphs_gate_the_whole_task_at_its_first_kernel(graph):
+    # A truly urgent and running; B's task = a 0.09-utilisation kernel then a
+    # full one.  Per kernel: B's first kernel passes (exempt), the second is
+    # held.  As one graph: the task's largest utilisation (1.0) decides, so
+    # the whole task is held at its first kernel and then released at once
+    ch = [chain(3 * MS, [(0, [(int(1.5 * MS), 1.0)])]),
+          chain(100 * MS, [(0, [(200 * US, 0.09), (1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "th_slack_ns": 2 * MS, "graph": graph}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 0)], by_est(ch))
+    holds = [(t, d[3]) for t, _, _, ds in res["instants"] for d in ds if d[0] == "HOLD"]
+    rel = {d[3]: t for t, _, _, ds in res["instants"] for d in ds if d[0] == "LAUNCH" and d[1] == 1}
+    if graph:
+        assert holds == [(0, 0), (1 * MS, 0)] and rel == {0: 2 * MS, 1: 2 * MS}
+        # one batch for the task: a start and an end event only
+        evs = [d for _, _, _, ds in res["instants"] for d in ds if d[0] == "EVREC" and d[1] == 1]
+        assert [(e[4], e[5]) for e in evs] == [(START, 0), (END, 1)]
+    else:
+        assert holds[0] == (0, 1) and rel[0] == 0 and rel[1] == 2 * MS
+    des.check_log(ch, cfg, res["instants"])
+
+
 def test_best_effort_kernels_are_always_delayable():
     # the same case as the exemption test, with the low-utilisation kernel in
     # a best-effort chain: it is held while the urgent chain runs, released

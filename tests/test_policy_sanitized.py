@@ -53,7 +53,8 @@ def _encode(chains, cfg, instants):
     c = {"policy": "urgency", "bind": True, "delay": True, "batch": True, "calibrate": False,
          "delta_eval_ns": 500_000, "delay_poll_ns": 1_000_000, "th_slack_ns": 0,
          "util_exempt": 0.1, "calib_period_ns": 1_000_000, "admit": True, "admit_tasks": 4,
-         "exit": False, "no_overlap": False, "key": "urgency", "est_noise_permille": 0,
+         "exit": False, "no_overlap": False, "graph": False, "key": "urgency",
+         "est_noise_permille": 0,
          "noise_seed": 0, "lanes": [2, 6]}
     c.update(cfg)
     lines = [" ".join(str(x) for x in ["cfg", 1 if c["policy"] == "urgency" else 0, int(c["bind"]),
@@ -61,7 +62,7 @@ def _encode(chains, cfg, instants):
                                        c["delta_eval_ns"], c["delay_poll_ns"], c["th_slack_ns"],
                                        c["util_exempt"], c["calib_period_ns"], int(c["admit"]),
                                        c["admit_tasks"], int(c["exit"]),
-                                       int(c["no_overlap"]), KEYS[c["key"]],
+                                       int(c["no_overlap"]), int(c["graph"]), KEYS[c["key"]],
                                        c["est_noise_permille"], c["noise_seed"], len(c["lanes"]),
                                        *c["lanes"]])]
     for ch in chains:
@@ -111,6 +112,7 @@ def test_sanitized_policy_matches_oracle(driver, seed):
                 {"th_slack_ns": 2 * MS, "key": "edf"}, {"th_slack_ns": 2 * MS, "key": "sjf"},
                 {"th_slack_ns": 2 * MS, "key": "hrrn"}, {"th_slack_ns": 2 * MS, "key": "lcuf"},
                 {"th_slack_ns": 2 * MS, "est_noise_permille": 300, "noise_seed": 11},
+                {"th_slack_ns": 2 * MS, "graph": True},
                 {"policy": "fifo"}):
         res = des.simulate(chains, cfg, arrivals, dur)
         text = _encode(chains, cfg, res["instants"])
