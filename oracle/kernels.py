@@ -22,6 +22,8 @@ reordering:
   that share the GPU with the deadline chains).
 * BF16 matrix product  C = A B with A, B in bfloat16 and an FP32 result
   (the reduced-precision form of the dense layers).
+* BF16 3x3 convolution  the same convolution with bfloat16 activations in
+  NHWC and weights in OHWI (channels innermost) and an FP32 NCHW result.
 * vector add      c = a + b (the custom kernel of the sensitivity
   experiments, whose utilisation and duration are set directly).
 
@@ -324,3 +326,22 @@ def vecadd_f32(A, B):
     """c = fl32(a + b) elementwise: one IEEE float32 addition (round to
     nearest even).  The bit-exact reference of the custom vector-add kernel."""
     return np.asarray(A, dtype=np.float32) + np.asarray(B, dtype=np.float32)
+
+
+def conv3x3_bf16_f64(X16, W16):
+    """The 3x3 convolution of conv3x3_f64 on bfloat16 operands in channels-
+    innermost layouts: X16 is [H, W, C] (NHWC of one image), W16 is
+    [C_out, 3, 3, C_in] (OHWI), both uint16 codes; the result is [1, C_out,
+    H, W] (NCHW) in float64, exact for the sizes used here (every product
+    has 16 significant bits)."""
+    X = bf16_decode(X16)
+    Wt = bf16_decode(W16)
+    assert X.ndim == 3 and Wt.ndim == 4 and Wt.shape[1:3] == (3, 3) and Wt.shape[3] == X.shape[2]
+    return conv3x3_f64(X.transpose(2, 0, 1)[None], Wt.transpose(0, 3, 1, 2))
+
+
+def conv3x3_bf16_abs_f64(X16, W16):
+    """|W| * |X| for the componentwise error scale of the BF16 convolution."""
+    X = np.abs(bf16_decode(X16))
+    Wt = np.abs(bf16_decode(W16))
+    return conv3x3_f64(X.transpose(2, 0, 1)[None], Wt.transpose(0, 3, 1, 2))

@@ -349,7 +349,32 @@ def test_vecadd_is_the_rounded_exact_sum():
     b = (r.standard_normal(4096) * np.exp2(r.integers(-30, 30, 4096))).astype(np.float32)
     want = (a.astype(np.float64) + b.astype(np.float64)).astype(np.float32)
     assert np.array_equal(K.vecadd_f32(a, b).view(np.uint32), want.view(np.uint32))
-    sp = K.vecadd_f32(np.array([np.inf, -0.0, -0.0, 1.0], np.float32),
-                      np.array([-np.inf, -0.0, 0.0, -1.0], np.float32))
+    with np.errstate(invalid="ignore"):     # inf - inf
+        sp = K.vecadd_f32(np.array([np.inf, -0.0, -0.0, 1.0], np.float32),
+                          np.array([-np.inf, -0.0, 0.0, -1.0], np.float32))
     assert np.isnan(sp[0]) and np.signbit(sp[1]) and not np.signbit(sp[2])
     assert sp[3] == 0 and not np.signbit(sp[3])
+
+
+
+def test_conv3x3_bf16_layouts_against_brute_force():
+    # NHWC activations, OHWI weights: a direct six-loop sum in those layouts
+    r = np.random.default_rng(13)
+    H, W, C, O = 3, 4, 2, 3
+    table = np.array([0x0000, 0x3F80, 0xBF80, 0x4000, 0xC000, 0x3F00, 0x4040], np.uint16)
+    X16 = table[r.integers(0, 7, (H, W, C))]
+    W16 = table[r.integers(0, 7, (O, 3, 3, C))]
+    x, w = K.bf16_decode(X16), K.bf16_decode(W16)
+    want = np.zeros((1, O, H, W))
+    for o in range(O):
+        for y in range(H):
+            for xx in range(W):
+                for dy in range(3):
+                    for dx in range(3):
+                        yy, xc = y + dy - 1, xx + dx - 1
+                        if 0 <= yy < H and 0 <= xc < W:
+                            for c in range(C):
+                                want[0, o, y, xx] += w[o, dy, dx, c] * x[yy, xc, c]
+    assert np.array_equal(K.conv3x3_bf16_f64(X16, W16), want)
+    assert np.array_equal(K.conv3x3_bf16_abs_f64(X16, W16),
+                          K.conv3x3_bf16_f64(X16 & 0x7FFF, W16 & 0x7FFF))
