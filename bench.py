@@ -119,6 +119,12 @@ SWEEPS = {
     # HIP graph, gated per task
     "graph": [{"name": "paper", "flags": PAPER}, {"name": "paper+graph", "flags": PAPER | 128},
               {"name": "full", "flags": FULL}, {"name": "full+graph", "flags": FULL | 128}],
+    # kernel utilisation and kernel time (Sec. 6.5): every other task is
+    # replaced by custom vector adds of the given utilisation / duration
+    "util": [{"name": f"util_{u}", "custom": {"util": u, "kernel_us": 500}}
+             for u in (0.25, 0.5, 0.75, 1.0)],
+    "ktime": [{"name": f"ktime_{k}us", "custom": {"util": 0.5, "kernel_us": k}}
+              for k in (50, 200, 500, 1000, 2000)],
     # estimate noise (Sec. 6.5): the estimates behind the urgency scaled per
     # task instance by (1000 + k) / 1000, k uniform in [-n, n]
     "noise": [{"name": f"noise_{n // 10}pct", "cfg": {"est_noise_permille": n, "noise_seed": 1}}
@@ -134,16 +140,20 @@ def sweep_main(args, torch, capi, runner, synth):
     W, K = args.warmup, args.steps
     groups = {}
     for v in SWEEPS[args.sweep]:
-        groups.setdefault((v.get("f_a", args.f_a), v.get("f_d", args.f_d)), []).append(v)
+        cu = v.get("custom")
+        groups.setdefault((v.get("f_a", args.f_a), v.get("f_d", args.f_d),
+                           json.dumps(cu, sort_keys=True) if cu else None), []).append(v)
     for seed in range(args.seed, args.seed + args.seeds):
-        for (fa, fd), variants in groups.items():
-            wl = synth.config1(seed=seed, f_a=fa, f_d=fd, window_s=float(W + K))
+        for (fa, fd, cu), variants in groups.items():
+            wl = synth.config1(seed=seed, f_a=fa, f_d=fd, window_s=float(W + K),
+                               custom=json.loads(cu) if cu else None)
             warm = [(c, f, t) for c, f, t in wl.arrivals if t < W * 1e9]
             timed = [(c, f, t - W * 10 ** 9) for c, f, t in wl.arrivals if t >= W * 1e9]
             dw = runner.DeviceWorkload(wl, n_sets=4)
             prof = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16)
             runner.profile(prof, dw, warmup=2, reps=5)
-            point = {"seed": seed, "f_a": fa, "f_d": fd, "frames": len(timed), "window_s": K}
+            point = {"seed": seed, "f_a": fa, "f_d": fd, "frames": len(timed), "window_s": K,
+                     "custom": json.loads(cu) if cu else None}
             fifo = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16)
             runner.copy_estimates(prof, fifo, wl)
             run_policy(fifo, dw, warm[: len(warm) // 2], torch)
@@ -355,6 +365,8 @@ ROOF_SHAPES = {
     "gemm": ((4096, 4096, 4096), 2 * 4096 ** 3, 4 * 3 * 4096 ** 2, "mfma"),
     "gemm_fp8": ((8192, 8192, 8192), 2 * 8192 ** 3, (1 + 1 + 4) * 8192 ** 2, "mfma_fp8"),
     "gemm_bf16": ((4096, 4096, 4096), 2 * 4096 ** 3, (2 + 2 + 4) * 4096 ** 2, "mfma_bf16"),
+    "conv3x3_bf16": ((1, 256, 256, 256), 18 * 256 ** 2 * 256 ** 2,
+                     2 * 256 ** 3 + 2 * 9 * 256 ** 2 + 4 * 256 ** 3, "mfma_bf16"),
     "conv3x3": ((1, 256, 256, 256), 18 * 256 ** 2 * 256 ** 2, 4 * (2 * 256 ** 3 + 9 * 256 ** 2), "mfma"),
     "bias_relu": ((16384, 16384, 0), 2 * 16384 ** 2, 8 * 16384 ** 2 + 4 * 16384, "hbm"),
     "rowsum": ((16384, 16384), 16384 ** 2, 4 * 16384 ** 2 + 4 * 16384, "hbm"),
@@ -401,6 +413,12 @@ def roofline_op(op, reps, torch):
         # random finite bfloat16 values (rounded normals)
         t = [torch.randn(M * K, device=dev).to(torch.bfloat16),
              torch.randn(N * K, device=dev).to(torch.bfloat16), torch.empty(M * N, device=dev)]
+        desc = {"op": op, "shape": shape, "in": (0, 1), "out": (2,)}
+    elif op == "conv3x3_bf16":
+        _, C, H, W = shape
+        t = [torch.randn(H * W * C, device=dev).to(torch.bfloat16),
+             (torch.randn(C * 9 * C, device=dev) * 0.05).to(torch.bfloat16),
+             torch.empty(C * H * W, device=dev)]
         desc = {"op": op, "shape": shape, "in": (0, 1), "out": (2,)}
     elif op == "conv3x3":
         _, C, H, W = shape

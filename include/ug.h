@@ -145,6 +145,12 @@ enum {
  *                       out {C[M,N] fp32}; A and Bt 16-byte aligned.  The
  *                       reduced-precision form of the GEMM (configuration
  *                       with BF16 contractions).
+ *  UG_OP_CONV3X3_BF16   the 3x3 convolution of UG_OP_CONV3X3_F32 on bfloat16
+ *                       operands, FP32 result, FP32 accumulation on the
+ *                       BF16 matrix cores.  shape {1, C, H, W}, C a multiple
+ *                       of 32 (<= 8192); in {X[H,W,C] (NHWC, channels
+ *                       innermost), W[C,3,3,C] (OHWI)}; out {Y[C,H,W] fp32
+ *                       NCHW}; X and W 16-byte aligned.
  *  UG_OP_VECADD_F32     c = a + b (one float32 addition each).  shape {N, W,
  *                       R}; in {A[N], B[N]}; out {C[N]}; run by exactly W
  *                       workgroups of 256 lanes (1 <= W <= 65536), the pass
@@ -162,7 +168,8 @@ enum {
   UG_OP_VOXEL_F32 = 6,
   UG_OP_GEMM_FP8 = 7,
   UG_OP_GEMM_BF16 = 8,
-  UG_OP_VECADD_F32 = 9
+  UG_OP_VECADD_F32 = 9,
+  UG_OP_CONV3X3_BF16 = 10
 };
 
 /* One kernel of a task (a row of the paper's lookup table, Tab. "Example

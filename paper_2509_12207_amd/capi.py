@@ -31,9 +31,11 @@ OP_VOXEL_F32 = 6
 OP_GEMM_FP8 = 7
 OP_GEMM_BF16 = 8
 OP_VECADD_F32 = 9
+OP_CONV3X3_BF16 = 10
 OP_NAMES = {OP_GEMM_F32: "gemm", OP_BIAS_RELU_F32: "bias_relu", OP_CONV3X3_F32: "conv3x3",
             OP_ROWSUM_F32: "rowsum", OP_SOFTMAX_F32: "softmax", OP_VOXEL_F32: "voxel",
-            OP_GEMM_FP8: "gemm_fp8", OP_GEMM_BF16: "gemm_bf16", OP_VECADD_F32: "vecadd"}
+            OP_GEMM_FP8: "gemm_fp8", OP_GEMM_BF16: "gemm_bf16", OP_VECADD_F32: "vecadd",
+            OP_CONV3X3_BF16: "conv3x3_bf16"}
 OP_IDS = {v: k for k, v in OP_NAMES.items()}
 
 REC_INSTANT, REC_ARRIVE, REC_EVDONE, REC_COMPLETE = 1, 2, 3, 4

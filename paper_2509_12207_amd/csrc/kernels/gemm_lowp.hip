@@ -222,12 +222,21 @@ __device__ __forceinline__ int ring_chunk(int g, int h) {
 
 __device__ __forceinline__ bf16x8 as_bf16x8(int4 v) { return __builtin_bit_cast(bf16x8, v); }
 
+// 64 zero bytes: the K slice of a pixel outside the image (3x3 convolution)
+__device__ __attribute__((aligned(64))) unsigned char kZeroSlice[64];
+
 // Operands: A and Bt as bytes, `kb` bytes per row (a multiple of 64).
-template <int T>
+// CONV (BF16 only): the 3x3 convolution as an implicit GEMM on NHWC
+// activations `Bt` ([H, W, Cc]) and OHWI weights `A` ([M, 3, 3, Cc], i.e.
+// rows of kb = 18 Cc bytes): M output channels, N = H W pixels, and K slice
+// s = (tap, 32-channel group) of a pixel row read at the pixel shifted by the
+// tap (zero slice outside the image).
+template <int T, bool CONV = false>
 __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_ring(const unsigned char* __restrict__ A,
                                                             const unsigned char* __restrict__ Bt,
                                                             float* __restrict__ C, int M, int N,
-                                                            int kb) {
+                                                            int kb, int H = 0, int W = 0,
+                                                            int Cc = 0) {
   __shared__ __attribute__((aligned(1024))) unsigned char lds[RNST * RSTAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 2, wn = wave & 3;   // 2 x 4 waves
@@ -243,6 +252,7 @@ __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_ring(const unsigned char*
   // holds K chunk (q % 4) ^ ring_swz(row).  Rows past M or N read the
   // matrix's first row (never stored).
   const unsigned char* src[RCPT];
+  int py[RCPT], px[RCPT], kcs[RCPT];   // convolution: this lane's pixels
 #pragma unroll
   for (int i = 0; i < RCPT; ++i) {
     const int q = (wave * RCPT + i) * 64 + lane;
@@ -252,17 +262,36 @@ __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_ring(const unsigned char*
     const bool ok = grow < (isa ? M : N);
     const unsigned char* X = isa ? A : Bt;
     src[i] = (ok ? X + (int64_t)grow * kb : X) + 16 * kc;
+    if constexpr (CONV) {
+      // pixel rows past the image get y = -2: outside for every tap
+      py[i] = ok ? grow / W : -2;
+      px[i] = ok ? grow % W : 0;
+      kcs[i] = kc;
+    }
   }
+  const int groups = CONV ? Cc / 32 : 1;   // 32-channel groups per tap
   // Stages past the end re-load the last K slice into their own slot, which
   // is never read again: every step issues the same number of loads, so the
   // wait counts are constants.
   auto issue = [&](int step) {
     const int slot = step % RNST;
-    const int k0 = min(step, steps - 1) * RK;
+    const int sc = min(step, steps - 1);
+    const int k0 = sc * RK;
+    const int tap = sc / groups, grp = sc - tap * groups;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
 #pragma unroll
     for (int i = 0; i < RCPT; ++i) {
       const unsigned at = (unsigned)(uintptr_t)(lds + slot * RSTAGE + (wave * RCPT + i) * 1024);
-      ring_load16(src[i] + k0, __builtin_amdgcn_readfirstlane(at));
+      const unsigned char* g = src[i] + k0;
+      if constexpr (CONV) {
+        if (wave * RCPT + i >= BM / 16) {   // activation rows (wave-uniform)
+          const int yy = py[i] + dy, xx = px[i] + dx;
+          g = (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                  ? Bt + (((int64_t)yy * W + xx) * Cc + grp * 32) * 2 + 16 * kcs[i]
+                  : kZeroSlice + 16 * kcs[i];
+        }
+      }
+      ring_load16(g, __builtin_amdgcn_readfirstlane(at));
     }
   };
 
@@ -390,6 +419,24 @@ hipError_t gemm_bf16_launch(const uint16_t* A, const uint16_t* Bt, float* C, int
   hipLaunchKernelGGL(gemm_ring<kRingBf16>, p.grid, p.block, 0, s,
                      reinterpret_cast<const unsigned char*>(A),
                      reinterpret_cast<const unsigned char*>(Bt), C, (int)M, (int)N, (int)(2 * K));
+  return hipGetLastError();
+}
+
+OpPlan conv3x3_bf16_plan(int64_t C, int64_t H, int64_t W) {
+  OpPlan p;
+  p.func = reinterpret_cast<const void*>(&gemm_ring<kRingBf16, true>);
+  p.grid = dim3((unsigned)(((C + BM - 1) / BM) * ((H * W + BN - 1) / BN)));
+  p.block = dim3(64 * RWAVES);
+  return p;
+}
+
+hipError_t conv3x3_bf16_launch(const uint16_t* X, const uint16_t* Wt, float* Y, int64_t C,
+                               int64_t H, int64_t W, hipStream_t s) {
+  OpPlan p = conv3x3_bf16_plan(C, H, W);
+  hipLaunchKernelGGL((gemm_ring<kRingBf16, true>), p.grid, p.block, 0, s,
+                     reinterpret_cast<const unsigned char*>(Wt),
+                     reinterpret_cast<const unsigned char*>(X), Y, (int)C, (int)(H * W),
+                     (int)(18 * C), (int)H, (int)W, (int)C);
   return hipGetLastError();
 }
 

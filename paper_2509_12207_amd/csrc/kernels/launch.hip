@@ -58,6 +58,13 @@ const char* validate_kernel(const ug_kernel& k, uint32_t nb) {
       if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
         return "gemm_fp8: needs in {A, Bt}, out {C}";
       return nullptr;
+    case UG_OP_CONV3X3_BF16:
+      if (s[0] != 1) return "conv3x3_bf16: one image (N = 1)";
+      if (!pos(s[1]) || s[1] % 32 != 0 || s[1] > 8192) return "conv3x3_bf16: C a multiple of 32, <= 8192";
+      if (!pos(s[2]) || !pos(s[3]) || s[2] * s[3] >= kMaxDim / 64) return "conv3x3_bf16: bad H, W";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
+        return "conv3x3_bf16: needs in {X, W}, out {Y}";
+      return nullptr;
     case UG_OP_VECADD_F32:
       if (!pos(s[0]) || s[1] < 1 || s[1] > 65536 || s[2] < 0 || s[2] > 65536)
         return "vecadd: N >= 1, 1 <= W <= 65536, 0 <= R <= 65536 (0 = 1)";
@@ -110,6 +117,13 @@ hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, voi
         return hipErrorInvalidValue;
       return gemm_fp8_launch(a, bt, F(k.out[0]), s[0], s[1], s[2], st);
     }
+    case UG_OP_CONV3X3_BF16: {
+      const auto* x = static_cast<const uint16_t*>(b[k.in[0]]);
+      const auto* w = static_cast<const uint16_t*>(b[k.in[1]]);
+      if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(w)) & 15)
+        return hipErrorInvalidValue;
+      return conv3x3_bf16_launch(x, w, F(k.out[0]), s[1], s[2], s[3], st);
+    }
     case UG_OP_VECADD_F32:
       return vecadd_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1],
                                s[2] > 0 ? s[2] : 1, st);
@@ -146,6 +160,8 @@ OpPlan plan_kernel(const ug_kernel& k) {
       return gemm_bf16_plan(s[0], s[1], s[2]);
     case UG_OP_VECADD_F32:
       return vecadd_f32_plan(s[0], s[1]);
+    case UG_OP_CONV3X3_BF16:
+      return conv3x3_bf16_plan(s[1], s[2], s[3]);
     default:
       return OpPlan{};
   }

@@ -45,6 +45,10 @@ OpPlan vecadd_f32_plan(int64_t n, int64_t w);
 hipError_t vecadd_f32_launch(const float* a, const float* b, float* c, int64_t n, int64_t w,
                              int64_t r, hipStream_t s);
 
+OpPlan conv3x3_bf16_plan(int64_t C, int64_t H, int64_t W);
+hipError_t conv3x3_bf16_launch(const uint16_t* X, const uint16_t* Wt, float* Y, int64_t C,
+                               int64_t H, int64_t W, hipStream_t s);
+
 OpPlan gemm_bf16_plan(int64_t M, int64_t N, int64_t K);
 hipError_t gemm_bf16_launch(const uint16_t* A, const uint16_t* Bt, float* C, int64_t M,
                             int64_t N, int64_t K, hipStream_t s);

@@ -51,9 +51,10 @@ TRAFFIC_KERNELS = {
     "softmax": (r"softmax_reg<4, 4, ", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
     "voxel": (r"voxel_(init|scatter|finalize|count|scan|place|reduce|merge)", 5,
               "paper_2509_12207_amd/csrc/kernels/voxel.hip"),
-    "gemm_fp8": (r"gemm_fp8_kernel|gemm_ring<0>", 1,
+    "gemm_fp8": (r"gemm_fp8_kernel|gemm_ring<0, false>", 1,
                  "paper_2509_12207_amd/csrc/kernels/gemm_lowp.hip"),
-    "gemm_bf16": (r"gemm_ring<1>", 1, "paper_2509_12207_amd/csrc/kernels/gemm_lowp.hip"),
+    "gemm_bf16": (r"gemm_ring<1, false>", 1, "paper_2509_12207_amd/csrc/kernels/gemm_lowp.hip"),
+    "conv3x3_bf16": (r"gemm_ring<1, true>", 1, "paper_2509_12207_amd/csrc/kernels/gemm_lowp.hip"),
 }
 
 

@@ -564,3 +564,89 @@ def test_gemm_bf16_rejects_bad_k_and_alignment():
     with pytest.raises(capi.UgError):
         capi.kernel_launch({"op": "gemm_bf16", "shape": (8, 8, 32), "in": (0, 1), "out": (2,)},
                            [a.data_ptr() + 2, a.data_ptr(), c.data_ptr()])
+
+
+# --------------------------------------------------------------- vector add
+@pytest.mark.parametrize("n,w,r,off", [(1, 1, 1, 0), (1000003, 256, 1, 0), (4099, 3, 2, 0),
+                                       (65536, 64, 0, 1), (777, 1024, 3, 3)])
+def test_vecadd_bit_exact(n, w, r, off):
+    # off > 0 shifts every array by `off` floats: misaligned, scalar path
+    g = rng(n + w)
+    A = (g.standard_normal(n + off) * 1e3).astype(np.float32)
+    B = (g.standard_normal(n + off) * 1e-3).astype(np.float32)
+    a, b = dev(A), dev(B)
+    c = torch.full((n + off,), float("nan"), device=DEV)
+    ptrs = [int(a.data_ptr()) + 4 * off, int(b.data_ptr()) + 4 * off, int(c.data_ptr()) + 4 * off]
+    capi.kernel_launch({"op": "vecadd", "shape": (n, w, r), "in": (0, 1), "out": (2,)}, ptrs)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy()[off:]
+    assert np.array_equal(got.view(np.uint32), OK.vecadd_f32(A[off:], B[off:]).view(np.uint32))
+    assert capi.kernel_util({"op": "vecadd", "shape": (n, w, r), "in": (0, 1), "out": (2,)}) == \
+        min(1.0, w / 256)
+
+
+# ---------------------------------------------------------------- BF16 conv
+def run_conv_bf16(X16, W16):
+    H, W, C = X16.shape
+    x = torch.from_numpy(X16.view(np.int16).copy()).to(DEV)
+    w = torch.from_numpy(W16.view(np.int16).copy()).to(DEV)
+    y = torch.full((C * H * W,), float("nan"), device=DEV)
+    launch({"op": "conv3x3_bf16", "shape": (1, C, H, W), "in": (0, 1), "out": (2,)}, [x, w, y])
+    return y.cpu().numpy().reshape(1, C, H, W)
+
+
+def test_conv3x3_bf16_integer_codes_bit_exact():
+    r = rng(51)
+    table = np.array([0x0000, 0x3F80, 0xBF80, 0x4000, 0xC000], np.uint16)
+    for C, H, W in [(32, 5, 7), (64, 17, 23), (32, 1, 1)]:
+        X16 = table[r.integers(0, 5, (H, W, C))]
+        W16 = table[r.integers(0, 5, (C, 3, 3, C))]
+        got = run_conv_bf16(X16, W16)
+        assert np.array_equal(got, OK.conv3x3_bf16_f64(X16, W16).astype(np.float32)), (C, H, W)
+
+
+@pytest.mark.parametrize("C,H,W", [(32, 8, 8), (96, 33, 30), (256, 16, 20), (128, 3, 300)])
+def test_conv3x3_bf16_parity(C, H, W):
+    r = rng(C + 7 * H + 13 * W)
+    X16, W16 = _bf16_codes(r, (H, W, C)), _bf16_codes(r, (C, 3, 3, C))
+    got = run_conv_bf16(X16, W16)
+    ref = OK.conv3x3_bf16_f64(X16, W16)
+    scale = OK.conv3x3_bf16_abs_f64(X16, W16)
+    K = 9 * C
+    u = 2.0 ** -23
+    assert np.all(np.abs(got - ref) <= K * u / (1 - K * u) * scale)
+    assert np.all(np.abs(got - ref) <= TOL * scale)
+
+
+def test_conv3x3_bf16_full_size_sampled():
+    # the roofline shape, C = 256 at 256 x 256, on sampled outputs
+    C, H, W = 256, 256, 256
+    r = rng(52)
+    X16, W16 = _bf16_codes(r, (H, W, C)), _bf16_codes(r, (C, 3, 3, C))
+    got = run_conv_bf16(X16, W16)
+    assert not np.isnan(got).any()
+    x, w = OK.bf16_decode(X16), OK.bf16_decode(W16)
+    K = 9 * C
+    u = 2.0 ** -23
+    pts = [(int(o), int(y), int(xx)) for o, y, xx in zip(r.integers(0, C, 48), r.integers(0, H, 48),
+                                                          r.integers(0, W, 48))]
+    pts += [(0, 0, 0), (C - 1, H - 1, W - 1), (5, 0, W - 1), (200, H - 1, 0)]
+    for o, y, xx in pts:
+        v = sc = 0.0
+        for dy in range(3):
+            for dx in range(3):
+                yy, xc = y + dy - 1, xx + dx - 1
+                if 0 <= yy < H and 0 <= xc < W:
+                    p = w[o, dy, dx, :] * x[yy, xc, :]
+                    v += float(p.sum())
+                    sc += float(np.abs(p).sum())
+        assert abs(got[0, o, y, xx] - v) <= K * u / (1 - K * u) * sc, (o, y, xx)
+
+
+def test_conv3x3_bf16_rejects_bad_shapes():
+    a = torch.zeros(4096, dtype=torch.int16, device=DEV)
+    c = torch.zeros(4096, device=DEV)
+    for shape in [(1, 48, 4, 4), (2, 32, 4, 4), (1, 32, 0, 4)]:
+        with pytest.raises(capi.UgError):
+            capi.kernel_launch({"op": "conv3x3_bf16", "shape": shape, "in": (0, 1), "out": (2,)},
+                               [a.data_ptr(), a.data_ptr(), c.data_ptr()])
