@@ -209,9 +209,11 @@ def _model_ns(op, shape):
         M, N, K = shape
         return floor + 2 * M * N * K / 2.5e15 * 1e9
     if op == "vecadd":
-        # streaming at a rate proportional to the workgroups (256 CUs), R passes
+        # repeated passes over small vectors run from the caches at about
+        # 62.5 GB/s per workgroup (measured on MI355X over 2^20 floats:
+        # 58-75 GB/s per workgroup for 32..256 workgroups)
         N, W, R = shape
-        return floor + 12 * N * max(R, 1) / (5e12 * min(W, 256) / 256) * 1e9
+        return floor + 12 * N * max(R, 1) / (16e12 * min(W, 256) / 256) * 1e9
     raise ValueError(op)
 
 
