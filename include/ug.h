@@ -118,8 +118,9 @@ enum {
  *                       b}; out {Y[R,C]} (Y may alias X).  axis 0: b[C] per
  *                       column; axis 1: b[R] per row (NCHW channel bias).
  *  UG_OP_CONV3X3_F32    3x3 cross-correlation, stride 1, zero pad 1, as many
- *                       output as input channels.  shape {N, C, H, W};
- *                       in {X[N,C,H,W], W[C,C,3,3]}; out {Y[N,C,H,W]}.
+ *                       output as input channels.  shape {N, C, H, W},
+ *                       H * W < 2^26, 9 C^2 < 2^33; in {X[N,C,H,W],
+ *                       W[C,C,3,3]}; out {Y[N,C,H,W]}.
  *  UG_OP_ROWSUM_F32     r_i = sum_j Z_ij.  shape {R, C}; in {Z[R,C]}; out {r[R]}.
  *  UG_OP_SOFTMAX_F32    row softmax.  shape {R, L}; in {X[R,L]}; out {Y[R,L]}
  *                       (Y may alias X).

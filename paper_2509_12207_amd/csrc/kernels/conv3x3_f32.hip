@@ -11,7 +11,8 @@
 // LDS) and the input patch with its one-pixel halo (4 x (TH+2) x (TW+2)).
 // The im2col operand is never materialised: each MFMA lane reads its
 // (c, dy, dx)-shifted pixel straight from the patch.  The next step is
-// prefetched into registers while the current one is consumed.  With KS > 1
+// prefetched into registers while the current one is consumed (32-bit
+// offsets from a per-step uniform base).  With KS > 1
 // the K slices are summed through LDS in slice order at the end, so results
 // do not depend on scheduling.
 //
@@ -66,30 +67,58 @@ __global__ __launch_bounds__(256) void conv3x3_f32_kernel(const float* __restric
   float rw[Cf::W_PER];
   float rx[Cf::X_PER];
 
-  // stage KS chunks starting at input channel c0 (chunk s covers c0 + 4 s ..)
+  // Byte offsets of this thread's staged elements from the step's base
+  // (weights: row o0, input channel c0; input: image n, channel c0), fixed
+  // for the whole K loop; ~0u marks padding (outside the tile, the output
+  // channels or the image).  32-bit offsets from a uniform base keep one
+  // register per element instead of a 64-bit address; the launcher bounds
+  // H * W so that 16 planes stay under 4 GiB.
+  uint32_t wo[Cf::W_PER], xo[Cf::X_PER];
+#pragma unroll
+  for (int i = 0; i < Cf::W_PER; ++i) {
+    const int idx = tid + 256 * i;
+    const int s = idx / (BM * KC), rem = idx % (BM * KC);
+    const int o = rem / KC, k = rem % KC;
+    wo[i] = (idx < KS * BM * KC && o0 + o < C)
+                ? (uint32_t)(((int64_t)(o * C + s * CC) * 9 + k) * 4) : ~0u;
+  }
+#pragma unroll
+  for (int i = 0; i < Cf::X_PER; ++i) {
+    const int idx = tid + 256 * i;
+    const int s = idx / Cf::XS, rem = idx % Cf::XS;
+    const int c = rem / PLANE, r = rem % PLANE;
+    const int yy = y0 - 1 + r / PW, xx = x0 - 1 + r % PW;
+    xo[i] = (idx < KS * Cf::XS && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                ? (uint32_t)((((int64_t)(s * CC + c) * H + yy) * W + xx) * 4) : ~0u;
+  }
+
+  // stage KS chunks starting at input channel c0 (chunk s covers c0 + 4 s ..);
+  // only a step that runs past the last channel checks channels per element
   auto load = [&](int c0) {
+    const char* wbase = reinterpret_cast<const char*>(Wt + ((size_t)o0 * C + c0) * 9);
+    const char* xbase = reinterpret_cast<const char*>(Xn + (size_t)c0 * plane);
+    if (c0 + KS * CC <= C) {
 #pragma unroll
-    for (int i = 0; i < Cf::W_PER; ++i) {
-      const int idx = tid + 256 * i;
-      const int s = idx / (BM * KC), rem = idx % (BM * KC);
-      const int o = rem / KC, k = rem % KC;
-      const int cb = c0 + s * CC;
-      float v = 0.f;
-      if (idx < KS * BM * KC && o0 + o < C && cb + k / 9 < C)
-        v = Wt[((size_t)(o0 + o) * C + cb) * 9 + k];
-      rw[i] = v;
-    }
+      for (int i = 0; i < Cf::W_PER; ++i)
+        rw[i] = wo[i] != ~0u ? *reinterpret_cast<const float*>(wbase + wo[i]) : 0.f;
 #pragma unroll
-    for (int i = 0; i < Cf::X_PER; ++i) {
-      const int idx = tid + 256 * i;
-      const int s = idx / Cf::XS, rem = idx % Cf::XS;
-      const int c = rem / PLANE, r = rem % PLANE;
-      const int yy = y0 - 1 + r / PW, xx = x0 - 1 + r % PW;
-      const int cc = c0 + s * CC + c;
-      float v = 0.f;
-      if (idx < KS * Cf::XS && cc < C && yy >= 0 && yy < H && xx >= 0 && xx < W)
-        v = Xn[(size_t)cc * plane + (size_t)yy * W + xx];
-      rx[i] = v;
+      for (int i = 0; i < Cf::X_PER; ++i)
+        rx[i] = xo[i] != ~0u ? *reinterpret_cast<const float*>(xbase + xo[i]) : 0.f;
+    } else {
+#pragma unroll
+      for (int i = 0; i < Cf::W_PER; ++i) {
+        const int idx = tid + 256 * i;
+        const int s = idx / (BM * KC), k = (idx % (BM * KC)) % KC;
+        rw[i] = (wo[i] != ~0u && c0 + s * CC + k / 9 < C)
+                    ? *reinterpret_cast<const float*>(wbase + wo[i]) : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < Cf::X_PER; ++i) {
+        const int idx = tid + 256 * i;
+        const int s = idx / Cf::XS, c = (idx % Cf::XS) / PLANE;
+        rx[i] = (xo[i] != ~0u && c0 + s * CC + c < C)
+                    ? *reinterpret_cast<const float*>(xbase + xo[i]) : 0.f;
+      }
     }
   };
   auto store = [&]() {
@@ -114,16 +143,19 @@ __global__ __launch_bounds__(256) void conv3x3_f32_kernel(const float* __restric
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = zero16();
 
+  // MFMA step kk of a chunk: lane half h supplies K index k = kk + 18 h, so
+  // the lower half walks input channels 0-1 of the chunk and the upper half
+  // channels 2-3.  Both operands' LDS offsets then differ between the halves
+  // by a per-lane constant, and every step's offset is a compile-time
+  // immediate once the loop is unrolled.
   const int half = lane >> 5, col = lane & 31;
-  int pix[TN];  // patch offset of this lane's pixel in each N tile
+  const float* wb = Ws0 + ks * Cf::WS + half * (KC / 2) * SW + wm * TM * 32 + col;
+  const float* xb[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int p = (wn * TN + j) * 32 + col;
-    pix[j] = (p / TW) * PW + (p % TW);
+    xb[j] = Xs0 + ks * Cf::XS + half * (CC / 2) * PLANE + (p / TW) * PW + (p % TW);
   }
-  const int om = wm * TM * 32 + col;
-  const float* ws = Ws0 + ks * Cf::WS;
-  const float* xs = Xs0 + ks * Cf::XS;
 
   const int nsteps = (C + KS * CC - 1) / (KS * CC);
   load(0);
@@ -132,26 +164,19 @@ __global__ __launch_bounds__(256) void conv3x3_f32_kernel(const float* __restric
     store();
     __syncthreads();
     if (st + 1 < nsteps) load((st + 1) * KS * CC);
-    int c = 0, r = half;      // k = 9 c + r, advanced by 2 per MFMA step
-#pragma unroll 4
+#pragma unroll
     for (int kk = 0; kk < KC / 2; ++kk) {
-      const int k = 2 * kk + half;
-      const int dy = r >= 6 ? 2 : (r >= 3 ? 1 : 0);
-      const int koff = c * PLANE + dy * PW + (r - 3 * dy);
+      const int r = kk % 9;
+      const int xo = (kk / 9) * PLANE + (r / 3) * PW + (r % 3);
       float a[TM], b[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = ws[k * SW + om + 32 * i];
+      for (int i = 0; i < TM; ++i) a[i] = wb[kk * SW + 32 * i];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = xs[koff + pix[j]];
+      for (int j = 0; j < TN; ++j) b[j] = xb[j][xo];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = mfma_32x32x2(a[i], b[j], acc[i][j]);
-      r += 2;
-      if (r >= 9) {
-        r -= 9;
-        c += 1;
-      }
     }
   }
 

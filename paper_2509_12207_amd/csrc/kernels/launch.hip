@@ -29,8 +29,8 @@ const char* validate_kernel(const ug_kernel& k, uint32_t nb) {
     case UG_OP_CONV3X3_F32:
       if (!pos(s[0]) || !pos(s[1]) || !pos(s[2]) || !pos(s[3]))
         return "conv3x3: shape {N, C, H, W} must be positive";
-      if (s[2] * s[3] >= kMaxDim || s[1] * s[1] * 9 >= kMaxDim * 4)
-        return "conv3x3: plane or weights too large";
+      if (s[2] * s[3] >= (int64_t(1) << 26) || s[1] * s[1] * 9 >= kMaxDim * 4)
+        return "conv3x3: H * W must be below 2^26 and 9 C^2 below 2^33";
       if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
         return "conv3x3: needs in {X, W}, out {Y}";
       return nullptr;
