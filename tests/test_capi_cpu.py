@@ -124,6 +124,16 @@ def test_voxel_workspace_size_and_checks():
         assert e.value.status == capi.EINVAL
 
 
+def test_conv3x3_shape_limits():
+    # host-side only: the FP32 convolution stages by 32-bit byte offsets, so
+    # a plane of 2^26 pixels or more is refused before anything runs
+    fake = [0x10000 * (i + 1) for i in range(3)]   # never dereferenced
+    for shape in [(1, 4, 8192, 8192), (1, 4, 1 << 26, 1), (1, 0, 8, 8), (1, 40000, 8, 8)]:
+        with pytest.raises(capi.UgError) as e:
+            capi.kernel_launch({"op": "conv3x3", "shape": shape, "in": (0, 1), "out": (2,)}, fake)
+        assert e.value.status == capi.EINVAL, shape
+
+
 # ----------------------------------------------------------------------------
 # C++ policy core == oracle gate model, instant by instant
 # ----------------------------------------------------------------------------
