@@ -71,8 +71,9 @@ __global__ __launch_bounds__(256) void conv3x3_f32_kernel(const float* __restric
   // (weights: row o0, input channel c0; input: image n, channel c0), fixed
   // for the whole K loop; ~0u marks padding (outside the tile, the output
   // channels or the image).  32-bit offsets from a uniform base keep one
-  // register per element instead of a 64-bit address; the launcher bounds
-  // H * W so that 16 planes stay under 4 GiB.
+  // register per element instead of a 64-bit address; the operation's
+  // validation keeps H * W below 2^26, so the byte offsets of the KS * CC
+  // (at most 16) planes of one step fit in 32 bits.
   uint32_t wo[Cf::W_PER], xo[Cf::X_PER];
 #pragma unroll
   for (int i = 0; i < Cf::W_PER; ++i) {
