@@ -16,7 +16,8 @@
 // the K slices are summed through LDS in slice order at the end, so results
 // do not depend on scheduling.
 //
-// The launcher picks the largest tile that still gives ~two workgroups per CU.
+// The launcher picks the largest tile that still gives ~two workgroups per CU,
+// or one per CU for a tile without a K split (measured faster than a K split).
 #include "mfma.hpp"
 #include "ops.hpp"
 
@@ -239,15 +240,16 @@ int64_t wgs(const Shape& s, int64_t N, int64_t C, int64_t H, int64_t W) {
   return ((H + s.th - 1) / s.th) * ((W + s.tw - 1) / s.tw) * N * ((C + s.bm - 1) / s.bm);
 }
 
-// First (largest) tile with enough workgroups; else the one with the most.
+// First (largest) tile with ~two workgroups per CU, or one per CU if it has no
+// K split; else the one with the most workgroups.
 int pick(int64_t N, int64_t C, int64_t H, int64_t W) {
-  constexpr int64_t kWant = 480;
+  constexpr int64_t kWant = 480, kOnePerCu = 256;
   int best = 4;
   int64_t most = 0;
   for (int i = 0; i < 5; ++i) {
     if (kShapes[i].bm > 32 && C <= kShapes[i].bm / 2) continue;   // mostly padding
     const int64_t n = wgs(kShapes[i], N, C, H, W);
-    if (n >= kWant) return i;
+    if (n >= kWant || (i < 3 && n >= kOnePerCu)) return i;       // tiles 0-2: no K split
     if (n > most) {
       most = n;
       best = i;

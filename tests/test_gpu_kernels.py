@@ -111,13 +111,15 @@ def run_conv(X, W):
     return y.cpu().numpy()
 
 
-# tile variants: (1, 64, 128, 128) -> 64 ch x 2x16 px with a K split,
-# (1, 32, 256, 256) -> 32 ch x 8x16 px, the rest -> 32 ch x 2x16 px with a K
-# split; 64 ch x 8x16 px and 128 ch x 8x16 px in the sampled tests below
+# tile variants: (1, 96, 96, 96) -> 64 ch x 2x16 px with a K split,
+# (1, 64, 128, 128) and (1, 32, 256, 256) -> 32 ch x 8x16 px, (1, 1, 1, 1) ->
+# 32 ch x 8x16 px (one workgroup either way; ties go to the larger tile), the
+# rest -> 32 ch x 2x16 px with a K split; 64 ch x 8x16 px and 128 ch x 8x16 px
+# in the sampled tests below
 @pytest.mark.parametrize("n,c,h,w", [(1, 16, 64, 64), (1, 32, 32, 32), (1, 64, 32, 48),
                                      (1, 130, 20, 20), (2, 3, 13, 21), (1, 1, 1, 1),
                                      (1, 256, 16, 16), (1, 64, 128, 128), (1, 32, 256, 256),
-                                     (1, 100, 33, 47)])
+                                     (1, 100, 33, 47), (1, 96, 96, 96)])
 def test_conv_parity(n, c, h, w):
     r = rng(n + 5 * c + 7 * h + w)
     X = r.uniform(-1, 1, (n, c, h, w)).astype(np.float32)
