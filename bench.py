@@ -604,8 +604,8 @@ def _oracle_exec(OK, k, bufs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by chain "
-              "with one gate per GPU, which this build does not launch", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); several GPUs would shard "
+              "the chains with one gate per GPU, which is not implemented", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
