@@ -35,7 +35,7 @@ Decision records (tuples):
     ("COMPLETE", c, f, t_done)
     ("TSTART",   c, f, j)
     ("BIND",     c, f, j, level, lane)
-    ("HOLD",     c, f, g)
+    ("HOLD",     c, f, g, why)            why 0 = delayed launching, 1 = task admission
     ("EVREC",    c, f, j, kind, seq)      kind 0 = batch start, 1 = task end
     ("EXIT",     c, f, j)                 early chain exit instead of starting task j
     ("LAUNCH",   c, f, g, level, lane)
@@ -55,6 +55,8 @@ from . import policy as P
 
 START = 0
 END = 1
+HOLD_DELAY = 0      # held by delayed launching (Sec. 4.4.4)
+HOLD_ADMIT = 1      # held by task admission (no free place among admit_tasks)
 
 
 class ChainSpec:
@@ -417,7 +419,7 @@ class GateModel:
             if (self.urgency_policy and self.cfg["delay"] and gate_here
                     and (ch.best_effort or u >= self.u_exempt)
                     and self._blocked(inst, slack, active)):
-                out.append(("HOLD", inst.c, inst.f, g))
+                out.append(("HOLD", inst.c, inst.f, g, HOLD_DELAY))
                 poll = self.cfg["delay_poll_ns"]
                 inst.wake = t + poll if poll > 0 else None
                 return
@@ -426,7 +428,7 @@ class GateModel:
             if (self.urgency_policy and self.cfg["admit"] and not inst.bound
                     and self.n_active >= self.cfg["admit_tasks"]
                     and not self._urgent(slack[inst.key])):
-                out.append(("HOLD", inst.c, inst.f, g))
+                out.append(("HOLD", inst.c, inst.f, g, HOLD_ADMIT))
                 inst.wake = None
                 return
             if not inst.bound and not inst.in_flight():

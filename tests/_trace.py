@@ -19,7 +19,7 @@ def record_to_tuple(r):
     if t == capi.REC_BIND:
         return ("BIND", c, f, int(r["task"]), int(r["a"]), int(r["b"]))
     if t == capi.REC_HOLD:
-        return ("HOLD", c, f, int(r["kernel"]))
+        return ("HOLD", c, f, int(r["kernel"]), int(r["a"]))
     if t == capi.REC_EVREC:
         return ("EVREC", c, f, int(r["task"]), int(r["a"]), int(r["b"]))
     if t == capi.REC_LAUNCH:

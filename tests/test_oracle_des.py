@@ -13,7 +13,7 @@ import pytest
 
 from oracle import brute, des
 from oracle import policy as P
-from oracle.gate import END, START, GateModel
+from oracle.gate import END, HOLD_ADMIT, START, GateModel
 
 MS = 1_000_000
 US = 1_000
@@ -510,3 +510,174 @@ def test_calibration_samples_and_threshold():
         # at most 5 % of the samples are more urgent than the threshold
         more = sum(1 for v in s if P.ul_greater(v, th))
         assert more <= 0.05 * len(s) + 1
+
+
+# ------------------------------------------------------------------ task admission
+def _holds(res):
+    return [(t, d[1], d[4]) for t, _, _, ds in res["instants"] for d in ds if d[0] == "HOLD"]
+
+
+def _first_launch(res):
+    out = {}
+    for t, _, _, ds in res["instants"]:
+        for d in ds:
+            if d[0] == "LAUNCH":
+                out.setdefault(d[1], t)
+    return out
+
+
+@pytest.mark.parametrize("admit_tasks", [1, 2])
+def test_admission_holds_a_task_until_the_in_flight_count_drops(admit_tasks):
+    # admit_tasks - 1 long fillers (chains 2..) and chain 0 occupy every place;
+    # chain 1 arrives at 0.5 ms, is not truly urgent (TH = +inf) and waits
+    # (HOLD, reason admission) until the first task end of another chain is
+    # observed, where the count of instances with kernels in flight drops
+    # below the cap
+    ch = [chain(100 * MS, [(0, [(2 * MS, 1.0)])]),
+          chain(50 * MS, [(0, [(1 * MS, 1.0)])])]
+    ch += [chain(100 * MS, [(0, [(5 * MS, 1.0)])]) for _ in range(admit_tasks - 1)]
+    arr = [(0, 0, 0), (1, 0, 500 * US)] + [(c, 0, 0) for c in range(2, len(ch))]
+    cfg = {"policy": "urgency", "th_slack_ns": 0, "admit_tasks": admit_tasks}
+    res = des.simulate(ch, cfg, arr, by_est(ch))
+    holds = _holds(res)
+    assert holds and all(h[1] == 1 and h[2] == HOLD_ADMIT for h in holds)
+    assert holds[0][0] == 500 * US
+    # while the others run the cap is full; chain 1 is admitted at the
+    # first task end observed (the count drops below the cap), not earlier
+    first_end = min(td for c, f, _, td in res["completed"] if c != 1)
+    assert _first_launch(res)[1] == first_end
+    assert all(t < first_end for t, _, _ in holds)
+    assert len(res["completed"]) == len(arr)
+    des.check_log(ch, cfg, res["instants"])
+    # without admission, chain 1 launches on arrival
+    res = des.simulate(ch, dict(cfg, admit=False), arr, by_est(ch))
+    assert _first_launch(res)[1] == 500 * US and not _holds(res)
+
+
+def test_admission_timeline_one_place():
+    # admit_tasks = 1, nobody truly urgent.  A (2 ms kernel) starts at 0; B
+    # arrives at 0.5 ms and is held; A's end is observed at 2 ms, B launches
+    # then and ends at 3 ms.
+    ch = [chain(100 * MS, [(0, [(2 * MS, 1.0)])]), chain(50 * MS, [(0, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "th_slack_ns": 0, "admit_tasks": 1}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 500 * US)], by_est(ch))
+    assert _holds(res) == [(500 * US, 1, HOLD_ADMIT)]
+    assert _first_launch(res) == {0: 0, 1: 2 * MS}
+    assert sorted(res["completed"]) == [(0, 0, 0, 2 * MS), (1, 0, 500 * US, 3 * MS)]
+
+
+@pytest.mark.parametrize("th_ms,urgent", [(5, True), (0, False)])
+def test_truly_urgent_task_bypasses_admission(th_ms, urgent):
+    # admit_tasks = 1 and A (lax, slack 98 ms) holds the only place.  B
+    # arrives at 0.5 ms with D = 4 ms: slack 0.5 + 4 - 1 - 0.5 = 3 ms.  With
+    # TH_urgent at a 5 ms slack B is truly urgent: it starts at once on the
+    # reserved level; with TH = +inf it waits for A like any other task.
+    ch = [chain(100 * MS, [(0, [(2 * MS, 1.0)])]), chain(4 * MS, [(0, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "th_slack_ns": th_ms * MS, "admit_tasks": 1}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 500 * US)], by_est(ch))
+    binds = {d[1]: d[4] for _, _, _, ds in res["instants"] for d in ds if d[0] == "BIND"}
+    if urgent:
+        assert _holds(res) == [] and _first_launch(res)[1] == 500 * US and binds[1] == 0
+    else:
+        assert _holds(res) == [(500 * US, 1, HOLD_ADMIT)] and _first_launch(res)[1] == 2 * MS
+        assert binds[1] == 1
+    des.check_log(ch, cfg, res["instants"])
+
+
+def test_admission_releases_the_most_urgent_waiting_task_first():
+    # admit_tasks = 1, nobody truly urgent.  A runs 0..2 ms.  B (D 60 ms)
+    # arrives at 0.5 ms, C (D 20 ms) at 0.6 ms; both wait.  When A's end is
+    # observed at 2 ms the place goes to C, the more urgent (slack 17.6 ms
+    # against B's 57.5 ms), and B waits again until C ends at 3 ms.
+    ch = [chain(100 * MS, [(0, [(2 * MS, 1.0)])]),
+          chain(60 * MS, [(0, [(1 * MS, 1.0)])]),
+          chain(20 * MS, [(0, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "th_slack_ns": 0, "admit_tasks": 1}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 500 * US), (2, 0, 600 * US)], by_est(ch))
+    # (the second hold at 2 ms is the re-check at the instant that observes
+    # C's batch start: a waiting task is re-checked at every instant)
+    assert _holds(res) == [(500 * US, 1, HOLD_ADMIT),
+                           (600 * US, 2, HOLD_ADMIT), (600 * US, 1, HOLD_ADMIT),
+                           (2 * MS, 1, HOLD_ADMIT), (2 * MS, 1, HOLD_ADMIT)]
+    assert _first_launch(res) == {0: 0, 2: 2 * MS, 1: 3 * MS}
+    assert sorted(res["completed"]) == [(0, 0, 0, 2 * MS), (1, 0, 500 * US, 4 * MS),
+                                        (2, 0, 600 * US, 3 * MS)]
+    des.check_log(ch, cfg, res["instants"])
+
+
+def test_admission_of_pipelined_frames_of_one_chain():
+    # one place, two frames of a two-task chain: frame 1 waits for task 0's
+    # slot, then for the place; no deadlock, every frame completes in order
+    ch = [chain(20 * MS, [(0, [(1 * MS, 1.0)]), (0, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "th_slack_ns": 0, "admit_tasks": 1}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (0, 1, 500 * US)], by_est(ch))
+    # at 1 ms frame 0 may start task 1 and frame 1 task 0.  Frame 1 is the
+    # more urgent (slack 0.5 + 20 - 2 - 1 = 17.5 ms against frame 0's
+    # 20 - 1 - 1 = 18 ms: all its work is still ahead) and takes the place;
+    # frame 0 waits until 2 ms, and frame 1's task 1 waits for frame 0 to
+    # leave that task's slot at 3 ms
+    holds = [(t, d[2], d[3], d[4]) for t, _, _, ds in res["instants"] for d in ds if d[0] == "HOLD"]
+    assert holds and set(holds) == {(1 * MS, 0, 1, HOLD_ADMIT)}
+    launch = {(d[2], d[3]): t for t, _, _, ds in res["instants"] for d in ds if d[0] == "LAUNCH"}
+    assert launch == {(0, 0): 0, (1, 0): 1 * MS, (0, 1): 2 * MS, (1, 1): 3 * MS}
+    assert sorted(res["completed"]) == [(0, 0, 0, 3 * MS), (0, 1, 500 * US, 4 * MS)]
+
+
+@pytest.mark.parametrize("admit_tasks", [1, 2, 3])
+@pytest.mark.parametrize("seed", range(3))
+def test_admission_never_deadlocks_on_random_workloads(admit_tasks, seed):
+    r = np.random.default_rng(200 + seed)
+    chains, arrivals = _random_workload(r)
+    for th in (0, 3 * MS):
+        cfg = {"policy": "urgency", "th_slack_ns": th, "admit_tasks": admit_tasks}
+        res = des.simulate(chains, cfg, arrivals, by_est(chains))
+        assert len(res["completed"]) == len(arrivals)
+        # the cap holds: with nobody truly urgent, no instant ends with more
+        # than admit_tasks instances holding launched, unconfirmed kernels
+        g = GateModel(chains, cfg)
+        peak = 0
+        for t, arr, evs, dec in res["instants"]:
+            assert g.instant(t, arr, evs) == list(dec)
+            n = sum(1 for i in g.inst.values() if i.phase != "done" and i.in_flight())
+            peak = max(peak, n)
+            if th == 0:
+                assert n <= admit_tasks, (t, n)
+        if th == 0:
+            assert peak == admit_tasks
+        des.check_log(chains, cfg, res["instants"])
+
+
+# ------------------------------------------------------------------ calibration sampling
+def test_calibration_samples_at_the_first_instant_of_each_period():
+    # A (D 20 ms, one 10 ms kernel) runs from t = 0; best-effort frames of
+    # chain 1 arrive at chosen times to create instants; C (D 8 ms, 1 ms)
+    # arrives at 2.25 ms and is then the most urgent.  With a 1 ms period the
+    # highest urgency is sampled at the first instant at or after each
+    # sampling time: 0.3 (first sample: nothing was in flight at 0), 1.3
+    # (exactly one period later), 2.3 and 3.35 ms.
+    ch = [chain(20 * MS, [(0, [(10 * MS, 1.0)])]), chain(0, [(0, [(100 * US, 1.0)])]),
+          chain(8 * MS, [(0, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "delay": False, "admit": False, "th_slack_ns": 0,
+           "calibrate": True, "calib_period_ns": 1 * MS}
+    g = GateModel(ch, cfg)
+    g.instant(0, [(0, 0, 0)], [])
+    times = [300, 900, 1300, 1500, 2200, 2250, 2300, 2400, 3350]
+    f = 0
+    for t_us in times:
+        t = t_us * US
+        if t_us == 2250:
+            g.instant(t, [(2, 0, t)], [])
+        else:
+            g.instant(t, [(1, f, t)], [])
+            f += 1
+    # slack of A: 20 - 10 - t; of C: 2.25 + 8 - 1 - t (ms)
+    assert g.samples == [int(9.7 * MS), int(8.7 * MS), int(6.95 * MS), int(5.9 * MS)]
+    # a zero period samples at every instant with something in flight
+    g = GateModel(ch, dict(cfg, calib_period_ns=0))
+    g.instant(0, [(0, 0, 0)], [])
+    f = 0
+    for t_us in times:
+        t = t_us * US
+        g.instant(t, [(2, 0, t)] if t_us == 2250 else [(1, f, t)], [])
+        f += t_us != 2250
+    assert len(g.samples) == len(times)

@@ -43,7 +43,7 @@ def _tuple(line):
     if n in ("TSTART", "EXIT"):
         return (n, c, fr, task)
     if n == "HOLD":
-        return (n, c, fr, k)
+        return (n, c, fr, k, a)
     if n in ("BIND", "EVREC"):
         return (n, c, fr, task, a, b)
     return (n, c, fr, k, a, b)
