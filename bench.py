@@ -101,7 +101,7 @@ SWEEPS = {
     # TH_urgent percentile with admission, with and without early chain exit
     "threshold_exit": [{"name": f"th_p{p}", "pct": p} for p in (95, 97, 99)]
     + [{"name": f"th_p{p}_exit", "pct": p, "flags": FULL | 32} for p in (95, 99)],
-    # launch synchronisation (Sec. 5.3): batched launching with overlap (the
+    # launch synchronisation (Sec. 6.4): batched launching with overlap (the
     # paper's), synchronous batched (a batch waits for the previous one to
     # finish), asynchronous (a task's kernels at once, one end event),
     # synchronous (every kernel waits for the previous one)
@@ -110,7 +110,7 @@ SWEEPS = {
                {"name": "async", "flags": PAPER & ~4},
                {"name": "sync", "flags": PAPER | NO_OVERLAP, "cfg": {"delta_eval_ns": 0}},
                {"name": "overlap+admit", "flags": FULL}],
-    # ranking order (Sec. 5.3, the policy comparison): urgency against EDF,
+    # ranking order (Sec. 6.4, the policy comparison): urgency against EDF,
     # SJF, HRRN and lowest chain utilisation first, the paper's mechanisms on
     "keys": [{"name": k, "flags": PAPER, "cfg": {"order_key": k}}
              for k in ("urgency", "edf", "sjf", "hrrn", "lcuf")]
@@ -119,13 +119,13 @@ SWEEPS = {
     # HIP graph, gated per task
     "graph": [{"name": "paper", "flags": PAPER}, {"name": "paper+graph", "flags": PAPER | 128},
               {"name": "full", "flags": FULL}, {"name": "full+graph", "flags": FULL | 128}],
-    # kernel utilisation and kernel time (Sec. 6.5): every other task is
+    # kernel utilisation and kernel time (Sec. 6.6): every other task is
     # replaced by custom vector adds of the given utilisation / duration
     "util": [{"name": f"util_{u}", "custom": {"util": u, "kernel_us": 500}}
              for u in (0.25, 0.5, 0.75, 1.0)],
     "ktime": [{"name": f"ktime_{k}us", "custom": {"util": 0.5, "kernel_us": k}}
               for k in (50, 200, 500, 1000, 2000)],
-    # estimate noise (Sec. 6.5): the estimates behind the urgency scaled per
+    # estimate noise (Sec. 6.6): the estimates behind the urgency scaled per
     # task instance by (1000 + k) / 1000, k uniform in [-n, n]
     "noise": [{"name": f"noise_{n // 10}pct", "cfg": {"est_noise_permille": n, "noise_seed": 1}}
               for n in (0, 100, 300, 500)],

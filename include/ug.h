@@ -71,7 +71,7 @@ enum {
   UG_F_EXIT = 32u,     /* early chain exit (Sec. 4.3): a frame whose urgency
                           is negative when a task would start leaves the
                           chain; it completes as missed and exited        */
-  UG_F_NO_OVERLAP = 64u, /* launch-synchronisation variants (Sec. 5.3): a
+  UG_F_NO_OVERLAP = 64u, /* launch-synchronisation variants (Sec. 6.4): a
                           closed batch is waited for until it has finished
                           (not until it has started) before the task's next
                           batch is launched.  With UG_F_BATCH: synchronous
@@ -89,7 +89,7 @@ enum {
 
 /* Orders that rank the instances (ug_config.order_key).  The paper's
  * urgency (Eq. 2) is the default; the others are the alternatives of its
- * policy comparison (Sec. 5.3), each with ties broken by (chain, frame):
+ * policy comparison (Sec. 6.4), each with ties broken by (chain, frame):
  *   EDF   earliest absolute deadline t_arr + D first;
  *   SJF   least remaining estimated work (GPU and CPU, as in Eq. 2) first;
  *   HRRN  highest response ratio (t - t_arr + R) / R first, R = remaining
@@ -158,7 +158,7 @@ enum {
  *                       repeated R times (0 or 1: once; <= 65536), so its
  *                       utilisation is min(1, W / CUs) and its duration
  *                       follows from N R / W: the custom kernel of the
- *                       utilisation and kernel-time experiments (Sec. 6.5).
+ *                       utilisation and kernel-time experiments (Sec. 6.6).
  */
 enum {
   UG_OP_GEMM_F32 = 1,
@@ -230,7 +230,7 @@ typedef struct {
                               that would exceed it returns UG_EAGAIN.
                               0 = no budget                                  */
   int32_t order_key;       /* UG_KEY_* (urgency policy only; default URGENCY) */
-  int32_t est_noise_permille; /* estimate-noise experiment (Sec. 6.5): n in
+  int32_t est_noise_permille; /* estimate-noise experiment (Sec. 6.6): n in
                               0..1000; the estimates of task j of frame f of
                               chain c enter the urgency (and SJF / HRRN) as
                               E * (1000 + k) / 1000, k uniform in [-n, n]
@@ -330,8 +330,10 @@ ug_status ug_create(const ug_config* cfg, void** out);
  * left untouched. */
 void ug_destroy(void* ctx);
 
-/* Message of the last error on ctx (storage of the context); with ctx NULL,
- * the message of the last failed ug_create in the process. */
+/* Message of the last error on ctx; with ctx NULL, the message of the last
+ * failed ug_create in the process.  The text is a copy owned by the calling
+ * thread, valid until that thread's next ug_last_error call; any thread may
+ * call it while others fail calls on the same context. */
 const char* ug_last_error(void* ctx);
 
 /* Registers a chain: a period (informational), an end-to-end deadline and

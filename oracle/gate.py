@@ -144,7 +144,7 @@ DEFAULT_CFG = {
     "key": "urgency",           # ranking order: urgency | edf | sjf | hrrn | lcuf
     "graph": False,             # tasks launch as one graph each (configuration 2)
     "est_noise_permille": 0,    # estimate noise n: per task instance, E * (1000 + k) / 1000
-    "noise_seed": 0,            #   with k uniform in [-n, n] (Sec. 6.5)
+    "noise_seed": 0,            #   with k uniform in [-n, n] (Sec. 6.6)
 }
 
 
@@ -322,7 +322,7 @@ class GateModel:
 
     def _before(self, a, b, slack, t):
         """True iff instance a ranks before b.  Urgency (Eq. 2) by default;
-        the alternatives of the policy comparison (Sec. 5.3) otherwise, each
+        the alternatives of the policy comparison (Sec. 6.4) otherwise, each
         with best-effort instances last and ties broken by (chain, frame):
         EDF (earliest t_arr + D), SJF (least remaining work R, the two sums
         of Eq. 2), HRRN (highest (t - t_arr + R) / R; R = 0 first), LCUF
@@ -457,7 +457,7 @@ class GateModel:
                 inst.batch_open = False
                 inst.batch_sum = 0
                 if not last and self.urgency_policy and self.cfg["no_overlap"]:
-                    # Launch-synchronisation variants (Sec. 5.3): the next
+                    # Launch-synchronisation variants (Sec. 6.4): the next
                     # batch's start event is recorded right behind this
                     # batch's last kernel and waited for too, so the next
                     # batch is launched only once this one has finished.

@@ -211,7 +211,7 @@ def splitmix64(x):
 
 
 def noise_permille(seed, c, f, j, n):
-    """Noise of the estimates of task j of frame f of chain c (Sec. 6.5: noise
+    """Noise of the estimates of task j of frame f of chain c (Sec. 6.6: noise
     drawn uniformly per task instance): an integer k uniform in [-n, n]; the
     task's estimates are taken as E * (1000 + k) / 1000.  The draw is a pure
     function of (seed, chain, frame, task): three chained SplitMix64 outputs,

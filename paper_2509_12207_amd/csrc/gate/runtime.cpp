@@ -106,6 +106,8 @@ struct Ctx {
   std::thread thr;
   std::atomic<bool> stop{false};
   std::atomic<int> device_error{0};
+  // messages written by caller threads and the gate thread alike
+  std::mutex err_mu;
   std::string last_error;
   std::string device_msg;
 
@@ -116,8 +118,14 @@ struct Ctx {
   std::atomic<int64_t> st_decide_ns{0}, st_launch_ns{0};
 };
 
+void set_error(Ctx* c, const std::string& msg, bool device) {
+  std::lock_guard<std::mutex> lk(c->err_mu);
+  c->last_error = msg;
+  if (device) c->device_msg = msg;
+}
+
 ug_status fail(Ctx* c, ug_status s, const std::string& msg) {
-  if (c) c->last_error = msg;
+  if (c) set_error(c, msg, false);
   return s;
 }
 
@@ -132,9 +140,8 @@ ug_status hip_fail(Ctx* c, hipError_t e, const char* what) {
     g_create_error = m;
   }
   if (c) {
+    set_error(c, m, true);
     c->device_error.store(1);
-    c->device_msg = m;
-    c->last_error = m;
   }
   return UG_EDEVICE;
 }
@@ -412,9 +419,8 @@ void gate_main(Ctx* c) {
     c->st_decide_ns += mono_ns() - t0;
     c->st_instants++;
     if (!ok) {
-      c->last_error = err ? err : "policy error";
+      set_error(c, err ? err : "policy error", true);
       c->device_error.store(1);
-      c->device_msg = c->last_error;
       break;
     }
     {
@@ -628,10 +634,18 @@ void ug_destroy(void* ctx) {
 }
 
 const char* ug_last_error(void* ctx) {
+  // a copy per calling thread: the context's message may be replaced by
+  // another thread at any time
+  static thread_local std::string copy;
   Ctx* c = static_cast<Ctx*>(ctx);
-  if (c) return c->last_error.c_str();
-  std::lock_guard<std::mutex> lk(g_create_mu);
-  return g_create_error.c_str();
+  if (c) {
+    std::lock_guard<std::mutex> lk(c->err_mu);
+    copy = c->last_error;
+  } else {
+    std::lock_guard<std::mutex> lk(g_create_mu);
+    copy = g_create_error;
+  }
+  return copy.c_str();
 }
 
 ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,

@@ -436,7 +436,7 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
     nominal k * P' with P' = P / f_a, plus uniform jitter of +-jitter_ms/2.
 
     ``custom = {"util": U, "kernel_us": T}`` (the sensitivity experiments,
-    Sec. 6.5): every odd-indexed task of every chain is replaced by custom
+    Sec. 6.6): every odd-indexed task of every chain is replaced by custom
     vector-add kernels run by round(U * 256) workgroups (utilisation U on
     256 CUs), each sized to take about T us under the time model, as many as
     keep the task's modelled time (fewer, longer kernels as T grows).

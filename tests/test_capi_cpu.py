@@ -254,3 +254,39 @@ def test_cpp_replay_rejects_unexpected_event():
     with pytest.raises(capi.UgError):
         g.replay_instant(1, inputs_to_records([], [(0, 0, 0, 1, 5)]))
     g.close()
+
+
+def test_errors_from_many_threads_on_one_context():
+    # several threads fail calls on one context (each failure records its
+    # message) while others read the message: every read is one of the
+    # messages written, never a torn or freed string
+    import threading
+    L = capi.lib()
+    g = capi.Gate(device=-1)
+    g.register_chain(1, 10, [{"kernels": [{"op": "rowsum", "shape": (4, 4), "in": (0,),
+                                           "out": (1,)}]}], 2)
+    ptrs = capi.pointer_array([0x1000, 0x2000])
+    seen, bad = set(), []
+
+    def fail_submit():
+        for _ in range(2000):
+            assert L.ug_frame_submit(g.h, 0, 0, ptrs, 2, None) == capi.ESTATE
+
+    def fail_estimate():
+        for _ in range(2000):
+            assert L.ug_kernel_set_estimate(g.h, 0, 99, 1, -1.0) == capi.EINVAL
+
+    def read():
+        for _ in range(4000):
+            m = L.ug_last_error(g.h).decode()
+            seen.add(m)
+            if m not in ("not started", "no such kernel", ""):
+                bad.append(m)
+
+    th = [threading.Thread(target=f) for f in (fail_submit, fail_estimate, read, read)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not bad and seen <= {"not started", "no such kernel", ""}
+    g.close()
