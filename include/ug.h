@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define UG_ABI_VERSION 3u
+#define UG_ABI_VERSION 4u
 
 typedef int32_t ug_status;
 enum {
@@ -78,13 +78,20 @@ enum {
                           batched launching; with delta_eval_ns = 0 as well:
                           synchronous launching (one kernel per batch).
                           UG_F_BATCH alone off: asynchronous launching     */
-  UG_F_GRAPH = 128u     /* task graphs (configuration 2): every task of a frame
+  UG_F_GRAPH = 128u,    /* task graphs (configuration 2): every task of a frame
                           is captured once (per buffer set and per-frame
                           sizes) into a HIP graph and launched as one graph
                           on its bound stream; the gate decides per task
                           (delayed launching at the task's first kernel,
                           with the task's largest utilisation; no batches
                           inside a task).  Applies to both policies.      */
+  UG_F_PLACE = 256u     /* queue placement of the stream pool: when streams
+                          are attached (or created), the library measures
+                          which hardware queue each one uses and assigns
+                          lanes (FIFO: task streams) round-robin over the
+                          queues, so that the first lanes of every level
+                          never share a queue while another is free.
+                          Applies to both policies; decided at attach.    */
 };
 
 /* Orders that rank the instances (ug_config.order_key).  The paper's
@@ -237,6 +244,11 @@ typedef struct {
                               drawn by SplitMix64 from (noise_seed, c, f, j);
                               batching keeps the profiled E.  0 = none      */
   uint64_t noise_seed;
+  int32_t own_streams;     /* 0: the caller provides the stream pool with
+                              ug_attach_streams before ug_start (streams made
+                              by torch); 1: the library creates its own
+                              default-priority streams at ug_start          */
+  int32_t pad1;
 } ug_config;
 
 /* Completion of one frame (Sec. 6.2: latency, miss). */
@@ -306,28 +318,35 @@ typedef struct {
 
 /* ------------------------------------------------------------------------ */
 
-/* Fills *cfg with the defaults: URGENCY with BIND|DELAY|BATCH, Delta_eval
- * 0.5 ms, 1 ms sleep step, U exemption 0.1 (the paper's values), device 0,
+/* Fills *cfg with the defaults: URGENCY with BIND|DELAY|BATCH (Sec. 4.4.3-
+ * 4.4.5) plus ADMIT and PLACE, Delta_eval 0.5 ms (Sec. 4.4.5), 1 ms sleep
+ * step (Sec. 4.4.4), U exemption 0.1 (the paper's values), device 0,
  * 2 levels with lanes {2, 6} (the reserved level and one shared level: all
  * streams have the same hardware priority, so further levels only split
  * lanes), no truly-urgent threshold, spinning gate thread. */
 void ug_config_default(ug_config* cfg);
 
-/* CLOCK_MONOTONIC in ns: the clock of every time argument. */
+/* CLOCK_MONOTONIC in ns: the clock of every time argument (arrival times
+ * and the elapsed time of Eq. 2). */
 int64_t ug_now_ns(void);
 
-/* Static text of a status code. */
+/* Static text of a status code (never NULL). */
 const char* ug_status_str(ug_status s);
 
-/* Creates a context.  With cfg->device >= 0 it creates its streams (all at
- * the default priority) and events on that device.  *out is owned by the
- * caller and released with ug_destroy.  Errors: UG_EINVAL, UG_ENOMEM,
- * UG_EDEVICE. */
+/* Creates a context: one gate (its policy, Active Kernel Buffer and event
+ * pool) for the chains that will share one GPU (the system of Sec. 3 and
+ * Sec. 4.4).  cfg is copied.  With cfg->device >= 0 it creates a pool of
+ * events on that device; the streams come from ug_attach_streams (or, with
+ * own_streams, are created at ug_start).  *out is owned by the caller and
+ * released with ug_destroy.  Errors: UG_EINVAL (a field out of range, wrong
+ * abi_version), UG_ENOMEM, UG_EDEVICE (no such device, event creation). */
 ug_status ug_create(const ug_config* cfg, void** out);
 
-/* Stops the gate thread (without waiting for in-flight frames), releases
- * streams, events and kernel workspaces.  Buffers of unfinished frames are
- * left untouched. */
+/* Stops the gate thread (without waiting for in-flight frames), waits for
+ * every stream of the pool to drain, then releases events, task graphs,
+ * kernel workspaces and the streams the library created itself (attached
+ * streams stay the caller's).  Buffers of unfinished frames are left
+ * untouched. */
 void ug_destroy(void* ctx);
 
 /* Message of the last error on ctx; with ctx NULL, the message of the last
@@ -368,16 +387,24 @@ ug_status ug_kernel_get_estimate(void* ctx, uint32_t chain, uint32_t kernel,
 ug_status ug_profile(void* ctx, uint32_t chain, void* const* buffers,
                      uint32_t n_buffers, uint32_t warmup, uint32_t reps);
 
-/* Changes TH_urgent (as a slack) or turns calibration sampling on/off.
- * Only while not started. */
+/* Changes TH_urgent (as a slack; Sec. 4.4.3) or the policy's switches (the
+ * mechanisms of Sec. 4.4.3-4.4.5 and calibration sampling).  Only while not
+ * started; the policy itself is fixed at creation.  Errors: UG_EINVAL,
+ * UG_ESTATE. */
 ug_status ug_set_threshold(void* ctx, int64_t th_slack_ns);
 ug_status ug_set_flags(void* ctx, int32_t policy, uint32_t flags);
 
-/* Starts the gate thread.  Registration is closed from here on. */
+/* Starts the gate thread, which runs the decision instants of Sec. 4.4
+ * (urgency evaluation, binding, delayed and batched launching) until
+ * ug_stop.  Registration is closed from here on.  Errors: UG_ENODEV,
+ * UG_ESTATE (already started; no streams attached and own_streams 0),
+ * UG_EDEVICE. */
 ug_status ug_start(void* ctx);
 
 /* Submits one frame of `chain` arriving at t_arr_ns (< 0: now; a future time
- * is honoured: the frame arrives when the clock reaches it).  buffers[i] is
+ * is honoured: the frame arrives when the clock reaches it): a data frame
+ * that starts an instance of the chain (Sec. 4.2, the arrival that sets
+ * t_arr in Eq. 2).  Non-blocking.  buffers[i] is
  * the device pointer of slot i; the caller keeps them alive and unmodified
  * until the frame is returned by ug_poll_complete (borrowed).  *frame gets
  * the frame index within the chain.  Errors: UG_EINVAL (also: the chain has
@@ -409,29 +436,58 @@ ug_status ug_frame_submit_dims(void* ctx, uint32_t chain, int64_t t_arr_ns,
  * UG_EINVAL, UG_ESTATE. */
 ug_status ug_chain_set_footprint(void* ctx, uint32_t chain, uint64_t bytes);
 
-/* Non-blocking: copies up to cap completions into out.  Returns how many
- * (>= 0), or UG_EDEVICE. */
+/* Number of streams ug_attach_streams expects: the sum of ug_config.lanes
+ * (urgency policy: the stream pool of Sec. 4.4.3, level by level), or one
+ * per task of every registered chain (FIFO launch: each task on its own
+ * stream, the baseline of Sec. 6.3).  Errors: UG_EINVAL. */
+ug_status ug_streams_needed(void* ctx, uint32_t* n);
+
+/* Gives the context its stream pool (Sec. 4.4.3: the streams that tasks are
+ * bound to).  hip_streams[i] are n distinct HIP streams (hipStream_t) on the
+ * context's device, created by the caller at the default priority (e.g.
+ * torch.cuda.Stream()); n = ug_streams_needed.  Borrowed: the caller keeps
+ * them alive until ug_destroy and issues no work on them meanwhile; the
+ * library never destroys them.  The urgency policy takes them as the lanes
+ * of level 0, then level 1, ...; FIFO launch as the streams of the chains'
+ * tasks in order (register the chains first).  With UG_F_PLACE the order is
+ * first rearranged round-robin over the hardware queues the streams use
+ * (a probe of about 0.5 ms per stream and queue, synchronous).  Once per
+ * context, before ug_start.  Errors: UG_EINVAL (count, null or repeated
+ * stream), UG_ESTATE (started, attached before, FIFO without chains),
+ * UG_ENODEV, UG_EDEVICE (the probe failed). */
+ug_status ug_attach_streams(void* ctx, void* const* hip_streams, uint32_t n);
+
+/* Completed frames (Sec. 6.2: end-to-end latency and deadline miss).
+ * Non-blocking: copies up to cap completions into out (caller-owned), oldest
+ * first, and removes them from the context.  Returns how many (>= 0), or
+ * UG_EDEVICE once a device error has occurred and nothing is left. */
 int32_t ug_poll_complete(void* ctx, ug_completion* out, uint32_t cap);
 
-/* Waits until every submitted frame has completed (completions stay
- * queued for ug_poll_complete).  Errors: UG_ETIMEDOUT, UG_EDEVICE. */
+/* Waits up to timeout_ns until every submitted frame has completed
+ * (completions stay queued for ug_poll_complete): the end of a run over
+ * which Eq. 3 is evaluated.  Errors: UG_ETIMEDOUT, UG_EDEVICE. */
 ug_status ug_drain(void* ctx, int64_t timeout_ns);
 
-/* Stops the gate thread after ug_drain; registration stays closed.  The
- * context can be restarted with ug_start (e.g. after ug_set_threshold). */
+/* Stops the gate thread after ug_drain and waits for the stream pool to
+ * drain; registration stays closed.  The context can be restarted with
+ * ug_start (e.g. after ug_set_threshold, Sec. 4.4.3's calibration run
+ * followed by the real one).  Errors: UG_EDEVICE. */
 ug_status ug_stop(void* ctx);
 
 /* Counters since the last ug_start (submissions, completions, launches,
- * holds, batches, decision instants, time spent deciding and launching). */
+ * holds, batches, decision instants, time spent deciding and launching):
+ * the scheduler-overhead figures of Sec. 6.5.  Errors: UG_EINVAL. */
 ug_status ug_get_stats(void* ctx, ug_stats* out);
 
-/* Copies up to cap records of the decision log into out and removes them
- * from the log.  Returns how many (>= 0). */
+/* Copies up to cap records of the decision log (every instant's inputs and
+ * decisions, for the offline replay of Sec. 4.4's policy) into out and
+ * removes them from the log.  Returns how many (>= 0), or UG_EINVAL. */
 int32_t ug_trace_read(void* ctx, ug_record* out, uint32_t cap);
 
-/* Copies the calibration samples (slack of the most urgent active
- * instance at each instant, ns) recorded under UG_F_CALIBRATE; returns the
- * number copied. */
+/* Copies the calibration samples recorded under UG_F_CALIBRATE (Sec.
+ * 4.4.3, the periodically recorded highest urgency among active kernels, as
+ * a slack in ns) into out; returns the number copied, UG_EINVAL, or
+ * UG_ESTATE while started. */
 int32_t ug_calibration_read(void* ctx, int64_t* out, uint32_t cap);
 
 /* TH_urgent from the recorded samples (Sec. 4.4.3): the samples are ordered
@@ -457,8 +513,8 @@ typedef struct {
 } ug_metrics;
 ug_status ug_get_metrics(void* ctx, ug_metrics* out);
 
-/* Offline replay of one decision instant on a context created with
- * device < 0: applies `inputs` (ARRIVE and EVDONE records) at time t,
+/* Offline replay of one decision instant of Sec. 4.4's policy on a context
+ * created with device < 0: applies `inputs` (ARRIVE and EVDONE records) at time t,
  * decides, and writes the decisions to out (COMPLETE..LAUNCH records).
  * *n_out receives their number.  Errors: UG_ESTATE (context has a device),
  * UG_EINVAL (an input the state does not expect), UG_ENOMEM (cap too small). */
@@ -467,20 +523,24 @@ ug_status ug_replay_instant(void* ctx, int64_t t, const ug_record* inputs,
                             uint32_t* n_out);
 
 /* Launches one kernel directly on a HIP stream (NULL = default stream) with
- * the given buffer pointers, outside any context.  Used by the profiling
- * stage and for testing each kernel alone.  Asynchronous.  Errors:
+ * the given buffer pointers, outside any context: a kernel of the lookup
+ * table of Sec. 4.1 run in isolation.  Used by the profiling stage and for
+ * testing each kernel alone.  The workspace a kernel needs is taken from
+ * the device's stream-ordered memory pool.  Asynchronous.  Errors:
  * UG_EINVAL (bad descriptor or missing buffer), UG_EDEVICE. */
 ug_status ug_kernel_launch(const ug_kernel* k, void* const* buffers,
                            uint32_t n_buffers, void* hip_stream);
 
-/* Bytes of device workspace a kernel needs beside its buffers (*bytes = 0
+/* Bytes of device workspace a kernel (Sec. 4.1's lookup-table entry) needs
+ * beside its buffers (*bytes = 0
  * for most kernels; the voxel scatter of large clouds bins its points
  * through one).  A context allocates the workspace of every registered
  * kernel in ug_chain_register (UG_ENOMEM if that fails); ug_kernel_launch
  * takes a stream-ordered allocation per call.  Errors: UG_EINVAL. */
 ug_status ug_kernel_workspace(const ug_kernel* k, uint64_t* bytes);
 
-/* ug_kernel_launch with a caller-owned device workspace of workspace_bytes
+/* ug_kernel_launch (one kernel of Sec. 4.1 in isolation) with a
+ * caller-owned device workspace of workspace_bytes
  * (>= ug_kernel_workspace, 256-byte aligned; may be NULL when that is 0),
  * which must stay untouched until the kernel has finished on hip_stream.
  * It holds no state between launches.  Errors: UG_EINVAL (also: workspace
@@ -489,9 +549,10 @@ ug_status ug_kernel_launch_ws(const ug_kernel* k, void* const* buffers,
                               uint32_t n_buffers, void* workspace,
                               uint64_t workspace_bytes, void* hip_stream);
 
-/* Static utilisation of a kernel's launch on `device` (U_k of Sec. 4.1): the
- * fraction of the device's compute units its grid occupies,
- * min(1, workgroups / CUs). */
+/* Static utilisation of a kernel's launch on `device` (U_k of Sec. 4.1 and
+ * Tab. "Example lookup table"): the fraction of the device's compute units
+ * its grid occupies, min(1, workgroups / CUs).  Errors: UG_EINVAL,
+ * UG_EDEVICE. */
 ug_status ug_kernel_util(const ug_kernel* k, int32_t device, float* util);
 
 #ifdef __cplusplus

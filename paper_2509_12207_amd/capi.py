@@ -12,12 +12,13 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libug.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 POLICY_FIFO, POLICY_URGENCY = 0, 1
 F_BIND, F_DELAY, F_BATCH, F_CALIBRATE, F_ADMIT, F_EXIT, F_NO_OVERLAP = 1, 2, 4, 8, 16, 32, 64
 F_GRAPH = 128
+F_PLACE = 256
 
 KEY_URGENCY, KEY_EDF, KEY_SJF, KEY_HRRN, KEY_LCUF = 0, 1, 2, 3, 4
 KEYS = {"urgency": KEY_URGENCY, "edf": KEY_EDF, "sjf": KEY_SJF, "hrrn": KEY_HRRN, "lcuf": KEY_LCUF}
@@ -48,7 +49,7 @@ EXPORTED = [
     "ug_poll_complete", "ug_drain", "ug_stop", "ug_get_stats", "ug_trace_read",
     "ug_calibration_read", "ug_calibration_threshold", "ug_get_metrics", "ug_replay_instant",
     "ug_kernel_launch", "ug_kernel_util", "ug_kernel_workspace", "ug_kernel_launch_ws",
-    "ug_frame_submit_dims", "ug_chain_set_footprint",
+    "ug_frame_submit_dims", "ug_chain_set_footprint", "ug_streams_needed", "ug_attach_streams",
 ]
 
 
@@ -72,7 +73,7 @@ class Config(C.Structure):
                 ("trace_capacity", C.c_uint32), ("calib_period_ns", C.c_int64),
                 ("admit_tasks", C.c_int64), ("hbm_budget_bytes", C.c_uint64),
                 ("order_key", C.c_int32), ("est_noise_permille", C.c_int32),
-                ("noise_seed", C.c_uint64)]
+                ("noise_seed", C.c_uint64), ("own_streams", C.c_int32), ("pad1", C.c_int32)]
 
 
 class Completion(C.Structure):
@@ -169,13 +170,15 @@ def lib():
                                            C.POINTER(C.c_int64), C.c_uint32,
                                            C.POINTER(C.c_uint64)]
         L.ug_chain_set_footprint.argtypes = [vp, C.c_uint32, C.c_uint64]
+        L.ug_streams_needed.argtypes = [vp, C.POINTER(C.c_uint32)]
+        L.ug_attach_streams.argtypes = [vp, C.POINTER(vp), C.c_uint32]
         for name in ("ug_create", "ug_chain_register", "ug_kernel_set_estimate",
                      "ug_kernel_get_estimate", "ug_profile", "ug_set_threshold", "ug_set_flags",
                      "ug_start", "ug_frame_submit", "ug_poll_complete", "ug_drain", "ug_stop",
                      "ug_get_stats", "ug_trace_read", "ug_calibration_read",
                      "ug_calibration_threshold", "ug_get_metrics", "ug_replay_instant",
                      "ug_kernel_launch", "ug_kernel_util", "ug_frame_submit_dims",
-                     "ug_chain_set_footprint"):
+                     "ug_chain_set_footprint", "ug_streams_needed", "ug_attach_streams"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -272,7 +275,13 @@ class Gate:
     """One libug context.
 
     ``policy``: "urgency" or "fifo".  Keyword arguments override the fields
-    of ug_config (``lanes`` takes a list, one entry per level).
+    of ug_config (``lanes`` takes a list, one entry per level).  FIFO launch
+    takes no flags unless given (in particular no queue placement: the
+    baseline keeps HIP's own stream-to-queue mapping).
+
+    The stream pool comes from torch: ``start`` attaches default-priority
+    ``torch.cuda.Stream`` objects (kept alive by this object) unless streams
+    were attached before or the library owns its streams (``own_streams=1``).
     """
 
     def __init__(self, policy="urgency", device=0, **kw):
@@ -281,6 +290,8 @@ class Gate:
         L.ug_config_default(C.byref(cfg))
         cfg.policy = POLICY_URGENCY if policy == "urgency" else POLICY_FIFO
         cfg.device = device
+        if cfg.policy == POLICY_FIFO:
+            cfg.flags = 0
         lanes = kw.pop("lanes", None)
         key = kw.pop("order_key", None)
         if key is not None:
@@ -298,6 +309,7 @@ class Gate:
             raise UgError(st, "ug_create: " + L.ug_last_error(None).decode())
         self.h = h
         self._keep = []
+        self._streams = None      # torch streams lent to the library
 
     def _check(self, st, what):
         if st != OK:
@@ -306,8 +318,9 @@ class Gate:
 
     def close(self):
         if self.h:
-            lib().ug_destroy(self.h)
+            lib().ug_destroy(self.h)     # drains the streams before returning
             self.h = None
+        self._streams = None
 
     def __del__(self):
         try:
@@ -352,7 +365,27 @@ class Gate:
         self._check(lib().ug_set_flags(self.h, self.cfg.policy, int(flags)), "ug_set_flags")
         self.cfg.flags = flags
 
+    def streams_needed(self):
+        n = C.c_uint32()
+        self._check(lib().ug_streams_needed(self.h, C.byref(n)), "ug_streams_needed")
+        return int(n.value)
+
+    def attach_streams(self, streams=None):
+        """Lend the library its stream pool: ``streams`` is a list of
+        ``torch.cuda.Stream`` (default: new ones at the default priority, as
+        many as ``ug_streams_needed``).  They stay referenced here until
+        ``close``."""
+        if streams is None:
+            import torch
+            dev = torch.device("cuda", self.cfg.device)
+            streams = [torch.cuda.Stream(device=dev) for _ in range(self.streams_needed())]
+        arr = pointer_array([s.cuda_stream for s in streams])
+        self._check(lib().ug_attach_streams(self.h, arr, len(streams)), "ug_attach_streams")
+        self._streams = list(streams)
+
     def start(self):
+        if self._streams is None and not self.cfg.own_streams and self.cfg.device >= 0:
+            self.attach_streams()
         self._check(lib().ug_start(self.h), "ug_start")
 
     def stop(self):

@@ -67,6 +67,10 @@ struct Ctx {
   std::vector<std::vector<hipStream_t>> level_streams;  // [level][lane]
   int queue_classes = 0;                                // hardware queues the lanes use
   std::vector<hipStream_t> fifo_streams;                // one per task of every chain
+  // streams attached by the caller (ug_attach_streams) are borrowed; only
+  // streams the library created itself (own_streams) are destroyed
+  bool streams_attached = false;
+  std::vector<hipStream_t> owned_streams;
   std::vector<hipEvent_t> event_pool;
   std::vector<hipEvent_t> all_events;
   std::map<EvKey, hipEvent_t> live_events;
@@ -242,6 +246,68 @@ hipGraphExec_t task_graph(Ctx* c, int32_t chain, int32_t j, const Frame& fr, hip
   if (*err != hipSuccess) return nullptr;
   c->graphs.emplace(std::move(gk), ge);
   return ge;
+}
+
+// Orders `pool` so that consecutive entries sit on different hardware queues
+// wherever the queues allow: streams are grouped by the queue the probe finds
+// them on, then taken round-robin over the groups.  Returns the number of
+// queues seen in *n_queues.
+hipError_t place_over_queues(std::vector<hipStream_t>* pool, int* n_queues) {
+  std::vector<int> cls;
+  hipError_t e = ug::stream_queue_classes(*pool, &cls);
+  if (e != hipSuccess) return e;
+  std::vector<std::vector<hipStream_t>> by_queue;
+  for (size_t i = 0; i < pool->size(); ++i) {
+    if (static_cast<size_t>(cls[i]) >= by_queue.size()) by_queue.resize(cls[i] + 1);
+    by_queue[cls[i]].push_back((*pool)[i]);
+  }
+  std::vector<hipStream_t> order;
+  for (size_t round = 0; order.size() < pool->size(); ++round)
+    for (auto& q : by_queue)
+      if (round < q.size()) order.push_back(q[round]);
+  *pool = std::move(order);
+  *n_queues = static_cast<int>(by_queue.size());
+  return hipSuccess;
+}
+
+// Gives the policy its streams: the lanes of every level in order (urgency
+// policy) or one stream per task of every chain (FIFO), from `pool`, placed
+// over the hardware queues first when UG_F_PLACE is set.
+hipError_t assign_streams(Ctx* c, std::vector<hipStream_t> pool) {
+  if (c->cfg.flags & UG_F_PLACE) {
+    hipError_t e = place_over_queues(&pool, &c->queue_classes);
+    if (e != hipSuccess) return e;
+  }
+  if (c->cfg.policy == UG_POLICY_FIFO) {
+    c->fifo_streams = std::move(pool);
+    return hipSuccess;
+  }
+  c->level_streams.assign(c->cfg.n_levels, {});
+  size_t next = 0;
+  for (int lv = 0; lv < c->cfg.n_levels; ++lv)
+    for (int ln = 0; ln < c->cfg.lanes[lv]; ++ln) c->level_streams[lv].push_back(pool[next++]);
+  return hipSuccess;
+}
+
+uint32_t streams_needed(const Ctx* c) {
+  if (c->cfg.policy == UG_POLICY_FIFO) return static_cast<uint32_t>(c->policy.fifo_lanes());
+  uint32_t n = 0;
+  for (int lv = 0; lv < c->cfg.n_levels; ++lv) n += static_cast<uint32_t>(c->cfg.lanes[lv]);
+  return n;
+}
+
+// Library-owned streams (own_streams): created at the default priority.
+hipError_t create_own_streams(Ctx* c) {
+  std::vector<hipStream_t> pool;
+  const uint32_t n = streams_needed(c);
+  for (uint32_t i = 0; i < n; ++i) {
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    c->owned_streams.push_back(st);
+    pool.push_back(st);
+  }
+  return assign_streams(c, std::move(pool));
 }
 
 // Executes the decisions of one instant.  Returns false on a device error.
@@ -498,7 +564,7 @@ void ug_config_default(ug_config* cfg) {
   std::memset(cfg, 0, sizeof(*cfg));
   cfg->abi_version = UG_ABI_VERSION;
   cfg->policy = UG_POLICY_URGENCY;
-  cfg->flags = UG_F_BIND | UG_F_DELAY | UG_F_BATCH | UG_F_ADMIT;
+  cfg->flags = UG_F_BIND | UG_F_DELAY | UG_F_BATCH | UG_F_ADMIT | UG_F_PLACE;
   cfg->device = 0;
   cfg->delta_eval_ns = 500000;
   cfg->delay_poll_ns = 1000000;
@@ -516,6 +582,7 @@ void ug_config_default(ug_config* cfg) {
   cfg->order_key = UG_KEY_URGENCY;
   cfg->est_noise_permille = 0;
   cfg->noise_seed = 0;
+  cfg->own_streams = 0;
 }
 
 int64_t ug_now_ns(void) { return mono_ns(); }
@@ -542,6 +609,7 @@ ug_status ug_create(const ug_config* cfg, void** out) {
   if (cfg->n_levels < 1 || cfg->n_levels > 8) return UG_EINVAL;
   for (int i = 0; i < cfg->n_levels; ++i)
     if (cfg->lanes[i] < 1 || cfg->lanes[i] > 64) return UG_EINVAL;
+  if (cfg->own_streams != 0 && cfg->own_streams != 1) return UG_EINVAL;
   if (cfg->delta_eval_ns < 0 || cfg->delay_poll_ns < 0 || cfg->queue_capacity == 0 ||
       cfg->calib_period_ns < 0 || cfg->admit_tasks < 1 || cfg->order_key < UG_KEY_URGENCY ||
       cfg->order_key > UG_KEY_LCUF || cfg->est_noise_permille < 0 ||
@@ -559,42 +627,6 @@ ug_status ug_create(const ug_config* cfg, void** out) {
       return e != hipSuccess ? hip_fail(nullptr, e, "hipGetDeviceCount") : UG_EINVAL;
     }
     if ((e = hipSetDevice(cfg->device)) != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
-    if (cfg->policy == UG_POLICY_URGENCY) {
-      // Lanes are placed round-robin over the hardware queues their streams
-      // landed on (HIP decides that from the process's stream history), so
-      // the first lanes of every level, which binding fills first, never
-      // share a queue while other queues are free.
-      std::vector<hipStream_t> pool;
-      int total = 0;
-      for (int lv = 0; lv < cfg->n_levels; ++lv) total += cfg->lanes[lv];
-      for (int i = 0; i < total; ++i) {
-        hipStream_t s = nullptr;
-        if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) {
-          for (hipStream_t x : pool) (void)hipStreamDestroy(x);
-          return hip_fail(nullptr, e, "hipStreamCreateWithFlags");
-        }
-        pool.push_back(s);
-      }
-      std::vector<int> cls;
-      if ((e = ug::stream_queue_classes(pool, &cls)) != hipSuccess) {
-        for (hipStream_t x : pool) (void)hipStreamDestroy(x);
-        return hip_fail(nullptr, e, "hardware-queue probe");
-      }
-      std::vector<std::vector<hipStream_t>> by_queue;
-      for (size_t i = 0; i < pool.size(); ++i) {
-        if (static_cast<size_t>(cls[i]) >= by_queue.size()) by_queue.resize(cls[i] + 1);
-        by_queue[cls[i]].push_back(pool[i]);
-      }
-      std::vector<hipStream_t> order;
-      for (size_t round = 0; order.size() < pool.size(); ++round)
-        for (auto& q : by_queue)
-          if (round < q.size()) order.push_back(q[round]);
-      c->queue_classes = static_cast<int>(by_queue.size());
-      c->level_streams.resize(cfg->n_levels);
-      size_t next = 0;
-      for (int lv = 0; lv < cfg->n_levels; ++lv)
-        for (int ln = 0; ln < cfg->lanes[lv]; ++ln) c->level_streams[lv].push_back(order[next++]);
-    }
     for (int i = 0; i < 1024; ++i) {
       hipEvent_t ev = nullptr;
       if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
@@ -614,15 +646,11 @@ void ug_destroy(void* ctx) {
   stop_thread(c);
   if (c->has_device) {
     (void)hipSetDevice(c->cfg.device);
+    // every stream the gate launched on has drained before anything is freed
     for (auto& lv : c->level_streams)
-      for (hipStream_t s : lv) {
-        (void)hipStreamSynchronize(s);
-        (void)hipStreamDestroy(s);
-      }
-    for (hipStream_t s : c->fifo_streams) {
-      (void)hipStreamSynchronize(s);
-      (void)hipStreamDestroy(s);
-    }
+      for (hipStream_t s : lv) (void)hipStreamSynchronize(s);
+    for (hipStream_t s : c->fifo_streams) (void)hipStreamSynchronize(s);
+    for (hipStream_t s : c->owned_streams) (void)hipStreamDestroy(s);
     for (hipEvent_t e : c->all_events) (void)hipEventDestroy(e);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -843,14 +871,13 @@ ug_status ug_start(void* ctx) {
   if (!c->has_device) return fail(c, UG_ENODEV, "no device");
   if (c->started) return fail(c, UG_ESTATE, "already started");
   (void)hipSetDevice(c->cfg.device);
-  if (c->cfg.policy == UG_POLICY_FIFO &&
-      static_cast<int32_t>(c->fifo_streams.size()) < c->policy.fifo_lanes()) {
-    for (int32_t i = static_cast<int32_t>(c->fifo_streams.size()); i < c->policy.fifo_lanes(); ++i) {
-      hipStream_t s = nullptr;
-      hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-      if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreateWithFlags");
-      c->fifo_streams.push_back(s);
-    }
+  if (!c->streams_attached) {
+    if (!c->cfg.own_streams)
+      return fail(c, UG_ESTATE, "no streams: attach them with ug_attach_streams (or set own_streams)");
+    if (c->policy.chains().empty()) return fail(c, UG_ESTATE, "no chain registered");
+    hipError_t e = create_own_streams(c);
+    if (e != hipSuccess) return hip_fail(c, e, "stream creation");
+    c->streams_attached = true;
   }
   c->policy.reset();
   c->finalized = true;
@@ -897,6 +924,40 @@ ug_status ug_chain_set_footprint(void* ctx, uint32_t chain, uint64_t bytes) {
   if (c->started || c->finalized) return fail(c, UG_ESTATE, "footprints are set before start");
   if (chain >= c->footprint.size()) return fail(c, UG_EINVAL, "no such chain");
   c->footprint[chain] = bytes;
+  return UG_OK;
+}
+
+ug_status ug_streams_needed(void* ctx, uint32_t* n) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c || !n) return UG_EINVAL;
+  *n = streams_needed(c);
+  return UG_OK;
+}
+
+ug_status ug_attach_streams(void* ctx, void* const* hip_streams, uint32_t n) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (sticky(c)) return UG_EDEVICE;
+  if (!c->has_device) return fail(c, UG_ENODEV, "streams need a device");
+  if (c->started) return fail(c, UG_ESTATE, "streams are attached before start");
+  if (c->streams_attached) return fail(c, UG_ESTATE, "streams are already attached");
+  if (c->cfg.policy == UG_POLICY_FIFO && c->policy.chains().empty())
+    return fail(c, UG_ESTATE, "FIFO launch: register the chains before attaching streams");
+  if (!hip_streams || n != streams_needed(c))
+    return fail(c, UG_EINVAL, "attach: wrong number of streams (see ug_streams_needed)");
+  std::vector<hipStream_t> pool;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (!hip_streams[i]) return fail(c, UG_EINVAL, "attach: null stream (the default stream is not accepted)");
+    pool.push_back(static_cast<hipStream_t>(hip_streams[i]));
+  }
+  std::vector<hipStream_t> sorted_pool = pool;
+  std::sort(sorted_pool.begin(), sorted_pool.end());
+  if (std::adjacent_find(sorted_pool.begin(), sorted_pool.end()) != sorted_pool.end())
+    return fail(c, UG_EINVAL, "attach: a stream is given twice");
+  (void)hipSetDevice(c->cfg.device);
+  hipError_t e = assign_streams(c, std::move(pool));
+  if (e != hipSuccess) return hip_fail(c, e, "hardware-queue probe");
+  c->streams_attached = true;
   return UG_OK;
 }
 

@@ -80,7 +80,8 @@ def test_config_defaults_and_errors():
     assert cfg.abi_version == capi.ABI_VERSION
     assert cfg.delta_eval_ns == 500_000 and cfg.delay_poll_ns == 1_000_000
     assert abs(cfg.util_exempt - 0.1) < 1e-7
-    assert cfg.flags == capi.F_BIND | capi.F_DELAY | capi.F_BATCH | capi.F_ADMIT
+    assert cfg.flags == capi.F_BIND | capi.F_DELAY | capi.F_BATCH | capi.F_ADMIT | capi.F_PLACE
+    assert cfg.own_streams == 0
     assert cfg.admit_tasks == 4
     assert cfg.calib_period_ns == 1_000_000 and list(cfg.lanes[:cfg.n_levels]) == [2, 6]
     bad = capi.Config()
@@ -100,6 +101,17 @@ def test_config_defaults_and_errors():
     with pytest.raises(capi.UgError) as e:
         g.start()
     assert e.value.status == capi.ENODEV
+    # the stream pool: the sum of the lanes for the urgency policy; streams
+    # need a device
+    assert g.streams_needed() == 8
+    arr = capi.pointer_array([0x10] * 8)
+    assert L.ug_attach_streams(g.h, arr, 8) == capi.ENODEV
+    f = capi.Gate("fifo", device=-1)
+    assert f.cfg.flags == 0
+    f.register_chain(1, 10, [{"kernels": [{"op": "rowsum", "shape": (4, 4), "in": (0,),
+                                           "out": (1,)}]}] * 3, 2)
+    assert f.streams_needed() == 3
+    f.close()
     with pytest.raises(capi.UgError) as e:
         g.submit(0, 0, [1, 2, 3])
     assert e.value.status in (capi.ESTATE, capi.EINVAL)
