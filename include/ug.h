@@ -244,6 +244,11 @@ typedef struct {
                               drawn by SplitMix64 from (noise_seed, c, f, j);
                               batching keeps the profiled E.  0 = none      */
   uint64_t noise_seed;
+  int64_t max_hold_ns;     /* hold-age bound (urgency policy): once a task
+                              has waited this long since its first hold
+                              (delayed launching or admission), it is not
+                              held again; a timer re-decides it when the
+                              bound is reached.  0 = no bound (the paper) */
   int32_t own_streams;     /* 0: the caller provides the stream pool with
                               ug_attach_streams before ug_start (streams made
                               by torch); 1: the library creates its own

@@ -115,6 +115,8 @@ class Instance:
         self.level = None
         self.lane = None
         self.wake = None          # re-check time of a held launch (sleep loop)
+        self.held_since = None    # first hold of the current task (hold-age bound)
+        self.expire = None        # while held: when the hold age reaches its bound
 
     @property
     def key(self):
@@ -145,6 +147,8 @@ DEFAULT_CFG = {
     "graph": False,             # tasks launch as one graph each (configuration 2)
     "est_noise_permille": 0,    # estimate noise n: per task instance, E * (1000 + k) / 1000
     "noise_seed": 0,            #   with k uniform in [-n, n] (Sec. 6.6)
+    "max_hold_ns": 0,           # hold-age bound: a task first held at t0 is not held
+                                #   again from t0 + max_hold_ns on; 0 = no bound
 }
 
 
@@ -222,6 +226,8 @@ class GateModel:
         inst.bound = False
         inst.level = inst.lane = None
         inst.wake = None
+        inst.held_since = None
+        inst.expire = None
         self.slot[(inst.c, j)] = inst.f
         out.append(("TSTART", inst.c, inst.f, j))
 
@@ -302,7 +308,8 @@ class GateModel:
         # 6. launch requests, most urgent first
         ready = [i for i in active
                  if i.phase == "launch" and i.g_next < i.chain.task_end[i.task]
-                 and not i.waits and (i.wake is None or i.wake <= t)]
+                 and not i.waits
+                 and (i.wake is None or i.wake <= t or (i.expire is not None and i.expire <= t))]
         if self.urgency_policy:
             ready = self._order(ready, slack, t)
         self.n_active = sum(1 for i in active if i.in_flight())
@@ -410,30 +417,38 @@ class GateModel:
         graph = self.urgency_policy and self.cfg["graph"]
         delta = (self.cfg["delta_eval_ns"]
                  if (self.urgency_policy and self.cfg["batch"] and not graph) else None)
+        max_hold = self.cfg["max_hold_ns"]
         while inst.g_next < end and not inst.waits:
             g = inst.g_next
+            # hold-age bound: once the task has waited max_hold since its
+            # first hold, neither delayed launching nor admission holds it
+            aged = (max_hold > 0 and inst.held_since is not None
+                    and t >= inst.held_since + max_hold)
             # task graphs: the task is one launch, gated at its first kernel
             # with the largest utilisation of its kernels, never inside
             gate_here = not graph or g == ch.task_first[inst.task]
             u = max(ch.util[g:end]) if graph and gate_here else ch.util[g]
-            if (self.urgency_policy and self.cfg["delay"] and gate_here
+            if (self.urgency_policy and self.cfg["delay"] and gate_here and not aged
                     and (ch.best_effort or u >= self.u_exempt)
                     and self._blocked(inst, slack, active)):
                 out.append(("HOLD", inst.c, inst.f, g, HOLD_DELAY))
                 poll = self.cfg["delay_poll_ns"]
                 inst.wake = t + poll if poll > 0 else None
+                self._held(inst, t)
                 return
             # task admission: a task that is not truly urgent starts only
             # while fewer than admit_tasks instances have kernels in flight
-            if (self.urgency_policy and self.cfg["admit"] and not inst.bound
+            if (self.urgency_policy and self.cfg["admit"] and not inst.bound and not aged
                     and self.n_active >= self.cfg["admit_tasks"]
                     and not self._urgent(slack[inst.key])):
                 out.append(("HOLD", inst.c, inst.f, g, HOLD_ADMIT))
                 inst.wake = None
+                self._held(inst, t)
                 return
             if not inst.bound and not inst.in_flight():
                 self.n_active += 1
             inst.wake = None
+            inst.expire = None
             if not inst.bound:
                 self._bind(inst, slack, active, out)
             if not inst.batch_open:
@@ -466,6 +481,16 @@ class GateModel:
                     out.append(("EVREC", inst.c, inst.f, inst.task, START, inst.batch))
                     self._wait(inst, (START, inst.batch))
 
+    def _held(self, inst, t):
+        """A hold of the task at t: its first hold starts the hold age, and
+        while it waits a timer fires when the age reaches its bound."""
+        max_hold = self.cfg["max_hold_ns"]
+        if max_hold <= 0:
+            return
+        if inst.held_since is None:
+            inst.held_since = t
+        inst.expire = inst.held_since + max_hold
+
     # ------------------------------------------------------------------
     def timers(self):
         """Earliest future time at which the gate must run without an input."""
@@ -475,6 +500,8 @@ class GateModel:
                 ts.append(inst.cpu_ready)
             if inst.phase == "launch" and inst.wake is not None:
                 ts.append(inst.wake)
+            if inst.phase == "launch" and inst.expire is not None:
+                ts.append(inst.expire)
         return min(ts) if ts else None
 
     def due(self, t):

@@ -73,7 +73,8 @@ class Config(C.Structure):
                 ("trace_capacity", C.c_uint32), ("calib_period_ns", C.c_int64),
                 ("admit_tasks", C.c_int64), ("hbm_budget_bytes", C.c_uint64),
                 ("order_key", C.c_int32), ("est_noise_permille", C.c_int32),
-                ("noise_seed", C.c_uint64), ("own_streams", C.c_int32), ("pad1", C.c_int32)]
+                ("noise_seed", C.c_uint64), ("max_hold_ns", C.c_int64),
+                ("own_streams", C.c_int32), ("pad1", C.c_int32)]
 
 
 class Completion(C.Structure):

@@ -118,6 +118,8 @@ void Policy::start_task(Instance& in, int32_t j, int64_t t, std::vector<ug_recor
   in.bound = false;
   in.level = in.lane = -1;
   in.has_wake = false;
+  in.has_held = false;
+  in.has_expire = false;
   slot_[{in.c, j}] = in.f;
   out.push_back(rec(UG_REC_TSTART, in.c, in.f, j, 0, 0, 0, 0));
 }
@@ -257,7 +259,7 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
     if (in->phase != kLaunch) continue;
     if (in->g_next >= chains_[in->c].task_end[in->task]) continue;
     if (!in->waits.empty()) continue;
-    if (in->has_wake && in->wake > t) continue;
+    if (in->has_wake && in->wake > t && !(in->has_expire && in->expire <= t)) continue;
     ready.push_back(in);
   }
   if (cfg_.policy == UG_POLICY_URGENCY) {
@@ -386,15 +388,29 @@ void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& acti
   const bool gated = cfg_.policy == UG_POLICY_URGENCY;
   const bool graph = gated && cfg_.graph;
   const bool batching = gated && cfg_.batch && !graph;
+  // a hold of the task at t: the first one starts the hold age; while the
+  // task waits, a timer fires when the age reaches the bound
+  auto held = [&]() {
+    if (cfg_.max_hold_ns <= 0) return;
+    if (!me.has_held) {
+      me.has_held = true;
+      me.held_since = t;
+    }
+    me.has_expire = true;
+    me.expire = me.held_since + cfg_.max_hold_ns;
+  };
   while (me.g_next < end && me.waits.empty()) {
     const int32_t g = me.g_next;
+    // hold-age bound: once the task has waited max_hold_ns since its first
+    // hold, neither delayed launching nor admission holds it again
+    const bool aged = cfg_.max_hold_ns > 0 && me.has_held && t >= me.held_since + cfg_.max_hold_ns;
     // with task graphs the task is one launch: it is gated at its first
     // kernel, with the largest utilisation of its kernels
     const bool gate_here = !graph || g == ch.task_first[me.task];
     float u = ch.util[g];
     if (graph && gate_here)
       for (int32_t k = g; k < end; ++k) u = std::max(u, ch.util[k]);
-    if (gated && cfg_.delay && gate_here && (ch.best_effort || u >= cfg_.util_exempt) &&
+    if (gated && cfg_.delay && gate_here && !aged && (ch.best_effort || u >= cfg_.util_exempt) &&
         blocked(me, active, slack)) {
       out.push_back(rec(UG_REC_HOLD, me.c, me.f, me.task, g, 0, 0, 0));
       me.n_holds += 1;
@@ -404,20 +420,23 @@ void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& acti
       } else {
         me.has_wake = false;
       }
+      held();
       return;
     }
     // admission: a task that is not truly urgent starts only while fewer
     // than admit_tasks instances have kernels in flight; waiting tasks are
     // re-checked at every instant, most urgent first
-    if (gated && cfg_.admit && !me.bound && active_ >= cfg_.admit_tasks &&
+    if (gated && cfg_.admit && !me.bound && !aged && active_ >= cfg_.admit_tasks &&
         !urgent(slack.at({me.c, me.f}))) {
       out.push_back(rec(UG_REC_HOLD, me.c, me.f, me.task, g, 1, 0, 0));
       me.n_holds += 1;
       me.has_wake = false;
+      held();
       return;
     }
     if (!me.bound && !me.in_flight()) ++active_;
     me.has_wake = false;
+    me.has_expire = false;
     if (!me.bound) bind(me, active, slack, out);
     if (!me.batch_open) {
       me.batch_open = true;
@@ -473,6 +492,10 @@ bool Policy::next_timer(int64_t* t) const {
     }
     if (in.phase == kLaunch && in.has_wake && (!any || in.wake < best)) {
       best = in.wake;
+      any = true;
+    }
+    if (in.phase == kLaunch && in.has_expire && (!any || in.expire < best)) {
+      best = in.expire;
       any = true;
     }
   }

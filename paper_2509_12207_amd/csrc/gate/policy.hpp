@@ -45,6 +45,7 @@ struct PolicyConfig {
   float util_exempt = 0.1f;
   int64_t th_slack_ns = 0;
   int64_t calib_period_ns = 1000000;   // at most one calibration sample per period
+  int64_t max_hold_ns = 0;             // hold-age bound per task; 0 = none
   std::vector<int32_t> lanes{2, 6};
 };
 
@@ -92,6 +93,12 @@ struct Instance {
   int32_t level = -1, lane = -1;
   bool has_wake = false;
   int64_t wake = 0;
+  // hold-age bound: time of the task's first hold, and while the task is
+  // held the time at which that age reaches the bound
+  bool has_held = false;
+  int64_t held_since = 0;
+  bool has_expire = false;
+  int64_t expire = 0;
   int32_t n_holds = 0, n_batches = 0;
   bool in_flight() const { return released_hi > i_gpu; }
 };

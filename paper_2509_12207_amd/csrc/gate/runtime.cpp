@@ -172,6 +172,7 @@ ug::PolicyConfig policy_config(const ug_config& cfg) {
   p.est_noise_permille = cfg.est_noise_permille;
   p.noise_seed = cfg.noise_seed;
   p.admit_tasks = cfg.admit_tasks;
+  p.max_hold_ns = cfg.max_hold_ns;
   p.lanes.assign(cfg.lanes, cfg.lanes + cfg.n_levels);
   return p;
 }
@@ -583,6 +584,7 @@ void ug_config_default(ug_config* cfg) {
   cfg->est_noise_permille = 0;
   cfg->noise_seed = 0;
   cfg->own_streams = 0;
+  cfg->max_hold_ns = 0;
 }
 
 int64_t ug_now_ns(void) { return mono_ns(); }
@@ -610,6 +612,7 @@ ug_status ug_create(const ug_config* cfg, void** out) {
   for (int i = 0; i < cfg->n_levels; ++i)
     if (cfg->lanes[i] < 1 || cfg->lanes[i] > 64) return UG_EINVAL;
   if (cfg->own_streams != 0 && cfg->own_streams != 1) return UG_EINVAL;
+  if (cfg->max_hold_ns < 0) return UG_EINVAL;
   if (cfg->delta_eval_ns < 0 || cfg->delay_poll_ns < 0 || cfg->queue_capacity == 0 ||
       cfg->calib_period_ns < 0 || cfg->admit_tasks < 1 || cfg->order_key < UG_KEY_URGENCY ||
       cfg->order_key > UG_KEY_LCUF || cfg->est_noise_permille < 0 ||

@@ -5,7 +5,8 @@
 //
 // input:
 //   cfg <policy> <bind> <delay> <batch> <calibrate> <delta> <poll> <th> <exempt>
-//       <calib_period> <admit> <admit_tasks> <exit> <nlevels> <lanes...>
+//       <calib_period> <admit> <admit_tasks> <exit> <no_overlap> <graph> <key>
+//       <noise_permille> <noise_seed> <max_hold> <nlevels> <lanes...>
 //   chain <deadline> <ntasks>        (deadline 0: a best-effort chain)
 //     task <cpu_ns> <nkernels> (<est_ns> <util>)*
 //   instant <t> <narr> <nev>
@@ -29,7 +30,7 @@ int main() {
   std::cin >> cfg.policy >> bind >> delay >> batch >> cal >> cfg.delta_eval_ns >>
       cfg.delay_poll_ns >> cfg.th_slack_ns >> cfg.util_exempt >> cfg.calib_period_ns >> admit >>
       cfg.admit_tasks >> ext >> nov >> graph >> cfg.order_key >> cfg.est_noise_permille >>
-      cfg.noise_seed >> nlev;
+      cfg.noise_seed >> cfg.max_hold_ns >> nlev;
   cfg.bind = bind, cfg.delay = delay, cfg.batch = batch, cfg.calibrate = cal, cfg.admit = admit;
   cfg.exit = ext, cfg.no_overlap = nov, cfg.graph = graph;
   cfg.lanes.assign(nlev, 0);

@@ -198,7 +198,8 @@ def _gate_for(cfg):
                      admit_tasks=cfg.get("admit_tasks", 4),
                      order_key=cfg.get("key", "urgency"),
                      est_noise_permille=cfg.get("est_noise_permille", 0),
-                     noise_seed=cfg.get("noise_seed", 0))
+                     noise_seed=cfg.get("noise_seed", 0),
+                     max_hold_ns=cfg.get("max_hold_ns", 0))
 
 
 CFGS = [
@@ -226,6 +227,9 @@ CFGS = [
     {"policy": "urgency", "th_slack_ns": 0, "graph": True, "admit": False, "delay_poll_ns": 0},
     {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "hrrn", "est_noise_permille": 500,
      "noise_seed": 2 ** 63 + 9},
+    {"policy": "urgency", "th_slack_ns": 3 * MS, "max_hold_ns": 2 * MS},
+    {"policy": "urgency", "th_slack_ns": 3 * MS, "max_hold_ns": 700_000, "delay_poll_ns": 0},
+    {"policy": "urgency", "th_slack_ns": 0, "max_hold_ns": 1 * MS, "admit_tasks": 1},
     {"policy": "fifo"},
 ]
 

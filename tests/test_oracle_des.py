@@ -681,3 +681,98 @@ def test_calibration_samples_at_the_first_instant_of_each_period():
         g.instant(t, [(2, 0, t)] if t_us == 2250 else [(1, f, t)], [])
         f += t_us != 2250
     assert len(g.samples) == len(times)
+
+
+# ------------------------------------------------------------------ hold-age bound
+def _long_urgent_case(poll, max_hold, b_kernels=((1 * MS, 1.0),)):
+    # A: D 10 ms, one 4.5 ms kernel, truly urgent for its whole run (slack
+    # 5.5 - t ms, between 1 and 5.5 ms, under TH 6 ms); B: lax (D 100 ms),
+    # high utilisation, arrives at 0
+    ch = [chain(10 * MS, [(0, [(int(4.5 * MS), 1.0)])]),
+          chain(100 * MS, [(0, list(b_kernels))])]
+    cfg = {"policy": "urgency", "th_slack_ns": 6 * MS, "delay_poll_ns": poll,
+           "max_hold_ns": max_hold}
+    return ch, cfg, des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 0)], by_est(ch))
+
+
+@pytest.mark.parametrize("poll", [1 * MS, 0])
+def test_hold_age_bounds_delayed_launching(poll):
+    # unbounded: B is held while A runs and released at the 5 ms wake (sleep
+    # loop) or when A's end is observed at 4.5 ms (event-driven).  With a
+    # 2.5 ms bound, B is released at 2.5 ms by the bound's own timer, A still
+    # running: a timer, not an input, makes that instant
+    ch, cfg, res = _long_urgent_case(poll, 0)
+    assert _first_launch(res)[1] == (5 * MS if poll else int(4.5 * MS))
+    ch, cfg, res = _long_urgent_case(poll, int(2.5 * MS))
+    holds = [t for t, _, _, ds in res["instants"] for d in ds if d[0] == "HOLD"]
+    # (event-driven: re-checked at the instant that observes A's batch start)
+    assert holds == ([0, 1 * MS, 2 * MS] if poll else [0, 0])
+    assert _first_launch(res)[1] == int(2.5 * MS)
+    t_rel = [t for t, arr, evs, ds in res["instants"]
+             if any(d[0] == "LAUNCH" and d[1] == 1 for d in ds)]
+    assert t_rel == [int(2.5 * MS)]
+    assert not next(i for i in res["instants"] if i[0] == int(2.5 * MS))[2]   # no input
+    des.check_log(ch, cfg, res["instants"])
+    assert des.replay(ch, cfg, res["instants"]) is None
+
+
+def test_hold_age_exemption_lasts_for_the_rest_of_the_task():
+    # B has two kernels; once its first is released by the bound, its second
+    # is not held either, although A is still truly urgent and running
+    ch, cfg, res = _long_urgent_case(1 * MS, int(2.5 * MS),
+                                     b_kernels=((1 * MS, 1.0), (1 * MS, 1.0)))
+    holds = [(t, d[3]) for t, _, _, ds in res["instants"] for d in ds if d[0] == "HOLD"]
+    assert holds == [(0, 0), (1 * MS, 0), (2 * MS, 0)]
+    rel = {d[3]: t for t, _, _, ds in res["instants"] for d in ds if d[0] == "LAUNCH" and d[1] == 1}
+    assert rel[0] == int(2.5 * MS) and rel[1] < int(4.5 * MS)
+
+
+def test_hold_age_bounds_admission():
+    # one place; A runs 10 ms; B arrives at 0.5 ms and waits for the place.
+    # With a 3 ms bound it starts at 3.5 ms, beside A; unbounded at 10 ms
+    ch = [chain(100 * MS, [(0, [(10 * MS, 1.0)])]), chain(50 * MS, [(0, [(1 * MS, 1.0)])])]
+    base = {"policy": "urgency", "th_slack_ns": 0, "admit_tasks": 1}
+    arr = [(0, 0, 0), (1, 0, 500 * US)]
+    res = des.simulate(ch, base, arr, by_est(ch))
+    assert _first_launch(res)[1] == 10 * MS
+    cfg = dict(base, max_hold_ns=3 * MS)
+    res = des.simulate(ch, cfg, arr, by_est(ch))
+    assert _holds(res) == [(500 * US, 1, HOLD_ADMIT)]
+    assert _first_launch(res)[1] == int(3.5 * MS)
+    des.check_log(ch, cfg, res["instants"])
+
+
+def test_hold_age_restarts_with_every_task():
+    # driven by hand.  A (D 20 ms, one 10 ms kernel) is truly urgent until
+    # 10 ms (slack 10 - t ms, TH 20 ms).  B (two one-kernel tasks) is held
+    # from 0 and released by the 2.5 ms bound; its first task ends at 2.6 ms;
+    # its second task is held afresh (a new hold age) and released by the
+    # bound at 5.1 ms, not at once
+    ch = [chain(20 * MS, [(0, [(10 * MS, 1.0)])]),
+          chain(100 * MS, [(0, [(1 * MS, 1.0)]), (0, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "th_slack_ns": 20 * MS, "delay_poll_ns": 1 * MS,
+           "max_hold_ns": int(2.5 * MS)}
+    g = GateModel(ch, cfg)
+    log = []
+
+    def step(t, arr=(), evs=()):
+        log.extend((t, d) for d in g.instant(t, list(arr), list(evs)))
+
+    step(0, [(0, 0, 0), (1, 0, 0)])
+    step(50 * US, evs=[(0, 0, 0, START, 0)])
+    while True:
+        nt = g.timers()
+        if nt is None or nt > 2 * MS + 600 * US:
+            break
+        step(nt)
+    step(2 * MS + 600 * US, evs=[(1, 0, 0, START, 0), (1, 0, 0, END, 1)])
+    while True:
+        nt = g.timers()
+        if nt is None or nt > 8 * MS:
+            break
+        step(nt)
+    holds = [(t, d[3]) for t, d in log if d[0] == "HOLD"]
+    launch = {d[3]: t for t, d in log if d[0] == "LAUNCH" and d[1] == 1}
+    assert holds == [(0, 0), (1 * MS, 0), (2 * MS, 0),
+                     (2 * MS + 600 * US, 1), (3 * MS + 600 * US, 1), (4 * MS + 600 * US, 1)]
+    assert launch == {0: int(2.5 * MS), 1: 5 * MS + 100 * US}

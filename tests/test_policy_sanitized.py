@@ -55,7 +55,7 @@ def _encode(chains, cfg, instants):
          "util_exempt": 0.1, "calib_period_ns": 1_000_000, "admit": True, "admit_tasks": 4,
          "exit": False, "no_overlap": False, "graph": False, "key": "urgency",
          "est_noise_permille": 0,
-         "noise_seed": 0, "lanes": [2, 6]}
+         "noise_seed": 0, "max_hold_ns": 0, "lanes": [2, 6]}
     c.update(cfg)
     lines = [" ".join(str(x) for x in ["cfg", 1 if c["policy"] == "urgency" else 0, int(c["bind"]),
                                        int(c["delay"]), int(c["batch"]), int(c["calibrate"]),
@@ -63,7 +63,8 @@ def _encode(chains, cfg, instants):
                                        c["util_exempt"], c["calib_period_ns"], int(c["admit"]),
                                        c["admit_tasks"], int(c["exit"]),
                                        int(c["no_overlap"]), int(c["graph"]), KEYS[c["key"]],
-                                       c["est_noise_permille"], c["noise_seed"], len(c["lanes"]),
+                                       c["est_noise_permille"], c["noise_seed"],
+                                       c["max_hold_ns"], len(c["lanes"]),
                                        *c["lanes"]])]
     for ch in chains:
         lines.append(f"chain {ch['deadline_ns']} {ch.get('period_ns', 0)} {len(ch['tasks'])}")
@@ -113,6 +114,8 @@ def test_sanitized_policy_matches_oracle(driver, seed):
                 {"th_slack_ns": 2 * MS, "key": "hrrn"}, {"th_slack_ns": 2 * MS, "key": "lcuf"},
                 {"th_slack_ns": 2 * MS, "est_noise_permille": 300, "noise_seed": 11},
                 {"th_slack_ns": 2 * MS, "graph": True},
+                {"th_slack_ns": 3 * MS, "max_hold_ns": 2 * MS},
+                {"th_slack_ns": 0, "max_hold_ns": 1 * MS, "admit_tasks": 1, "delay_poll_ns": 0},
                 {"policy": "fifo"}):
         res = des.simulate(chains, cfg, arrivals, dur)
         text = _encode(chains, cfg, res["instants"])
