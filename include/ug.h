@@ -554,6 +554,25 @@ ug_status ug_kernel_launch_ws(const ug_kernel* k, void* const* buffers,
                               uint32_t n_buffers, void* workspace,
                               uint64_t workspace_bytes, void* hip_stream);
 
+/* Bytes of the static device workspace of ug_kernel_launch_noalloc, one
+ * per GPU the library runs on, held until the process ends. */
+#define UG_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* ug_kernel_launch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no allocating routine.  A kernel that needs a
+ * workspace (ug_kernel_workspace > 0) uses a static device array of
+ * UG_STATIC_SCRATCH_BYTES on the current device instead, located on the
+ * first call on that device.  The array is shared by every call on that
+ * GPU and keeps the last call's contents (no kernel reads what an earlier
+ * call left): calls on one stream are ordered, but calls that overlap in
+ * time on one GPU (other streams, other threads) race and give wrong
+ * results.  Asynchronous.  Errors: UG_EINVAL (bad descriptor or missing
+ * buffer; a workspace above UG_STATIC_SCRATCH_BYTES, checked before any
+ * device call), UG_EDEVICE. */
+ug_status ug_kernel_launch_noalloc(const ug_kernel* k, void* const* buffers,
+                                   uint32_t n_buffers, void* hip_stream);
+
 /* Static utilisation of a kernel's launch on `device` (U_k of Sec. 4.1 and
  * Tab. "Example lookup table"): the fraction of the device's compute units
  * its grid occupies, min(1, workgroups / CUs).  Errors: UG_EINVAL,

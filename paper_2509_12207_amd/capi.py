@@ -50,6 +50,7 @@ EXPORTED = [
     "ug_calibration_read", "ug_calibration_threshold", "ug_get_metrics", "ug_replay_instant",
     "ug_kernel_launch", "ug_kernel_util", "ug_kernel_workspace", "ug_kernel_launch_ws",
     "ug_frame_submit_dims", "ug_chain_set_footprint", "ug_streams_needed", "ug_attach_streams",
+    "ug_kernel_launch_noalloc",
 ]
 
 
@@ -173,13 +174,15 @@ def lib():
         L.ug_chain_set_footprint.argtypes = [vp, C.c_uint32, C.c_uint64]
         L.ug_streams_needed.argtypes = [vp, C.POINTER(C.c_uint32)]
         L.ug_attach_streams.argtypes = [vp, C.POINTER(vp), C.c_uint32]
+        L.ug_kernel_launch_noalloc.argtypes = [C.POINTER(Kernel), C.POINTER(vp), C.c_uint32, vp]
         for name in ("ug_create", "ug_chain_register", "ug_kernel_set_estimate",
                      "ug_kernel_get_estimate", "ug_profile", "ug_set_threshold", "ug_set_flags",
                      "ug_start", "ug_frame_submit", "ug_poll_complete", "ug_drain", "ug_stop",
                      "ug_get_stats", "ug_trace_read", "ug_calibration_read",
                      "ug_calibration_threshold", "ug_get_metrics", "ug_replay_instant",
                      "ug_kernel_launch", "ug_kernel_util", "ug_frame_submit_dims",
-                     "ug_chain_set_footprint", "ug_streams_needed", "ug_attach_streams"):
+                     "ug_chain_set_footprint", "ug_streams_needed", "ug_attach_streams",
+                     "ug_kernel_launch_noalloc"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -236,6 +239,18 @@ def kernel_launch(k, ptrs, stream=None):
     st = lib().ug_kernel_launch(C.byref(ks), arr, len(ptrs), C.c_void_p(stream or 0))
     if st != OK:
         raise UgError(st, f"ug_kernel_launch({OP_NAMES.get(ks.op, ks.op)})")
+
+
+STATIC_SCRATCH_BYTES = 64 << 20   # UG_STATIC_SCRATCH_BYTES
+
+
+def kernel_launch_noalloc(k, ptrs, stream=None):
+    """Launch one kernel without allocating (static device workspace)."""
+    ks = kernel_struct(k)
+    arr = pointer_array(ptrs)
+    st = lib().ug_kernel_launch_noalloc(C.byref(ks), arr, len(ptrs), C.c_void_p(stream or 0))
+    if st != OK:
+        raise UgError(st, f"ug_kernel_launch_noalloc({OP_NAMES.get(ks.op, ks.op)})")
 
 
 def kernel_workspace(k):

@@ -1154,6 +1154,25 @@ ug_status ug_kernel_launch(const ug_kernel* k, void* const* buffers, uint32_t n_
   return e == hipSuccess ? UG_OK : UG_EDEVICE;
 }
 
+ug_status ug_kernel_launch_noalloc(const ug_kernel* k, void* const* buffers, uint32_t n_buffers,
+                                   void* hip_stream) {
+  if (!k || !buffers) return UG_EINVAL;
+  if (ug::validate_kernel(*k, n_buffers)) return UG_EINVAL;
+  const int32_t* slots[2] = {k->in, k->out};
+  const int counts[2] = {3, 4};
+  for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < counts[a]; ++i) {
+      const int32_t s = slots[a][i];
+      if (s >= 0 && (static_cast<uint32_t>(s) >= n_buffers || !buffers[s])) return UG_EINVAL;
+    }
+  const size_t wb = ug::workspace_bytes(*k);
+  if (wb > ug::kStaticScratchBytes) return UG_EINVAL;
+  void* w = nullptr;
+  if (wb && ug::static_scratch(&w) != hipSuccess) return UG_EDEVICE;
+  hipError_t e = ug::launch_kernel(*k, buffers, static_cast<hipStream_t>(hip_stream), w, wb);
+  return e == hipSuccess ? UG_OK : UG_EDEVICE;
+}
+
 ug_status ug_kernel_workspace(const ug_kernel* k, uint64_t* bytes) {
   if (!k || !bytes) return UG_EINVAL;
   if (ug::validate_kernel(*k, 16)) return UG_EINVAL;

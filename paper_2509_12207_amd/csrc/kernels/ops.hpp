@@ -61,6 +61,13 @@ hipError_t voxel_f32_launch(const float* pts, int* vidx, int* count, float* zmax
                             int64_t N, int nx, int ny, float xmin, float ymin, float scale,
                             void* ws, size_t ws_bytes, hipStream_t s);
 
+// Size of the static device workspace of ug_kernel_launch_noalloc, per GPU.
+constexpr size_t kStaticScratchBytes = size_t(UG_STATIC_SCRATCH_BYTES);
+
+// Device address of the static workspace on the current device (located on
+// the first call per device, then cached).  Allocates nothing.
+hipError_t static_scratch(void** ptr);
+
 // Checks a descriptor against n_buffers slots.  Returns nullptr if valid,
 // else a static message.
 const char* validate_kernel(const ug_kernel& k, uint32_t n_buffers);
