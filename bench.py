@@ -133,6 +133,16 @@ SWEEPS = {
     "admit": [{"name": "paper", "flags": PAPER}]
     + [{"name": f"admit_{n}", "flags": FULL, "cfg": {"admit_tasks": n}}
        for n in (2, 3, 4, 6, 8)],
+    # TH_urgent percentile against the hold-age bound: the full gate and the
+    # paper's three mechanisms, each without a bound and with 5 / 20 ms
+    "hold": [{"name": f"{n}_p{p}_hold{h}", "pct": p, "flags": f,
+              "cfg": {"max_hold_ns": h * MS}}
+             for n, f, ps, hs in (("full", FULL, (85, 90, 95, 99), (0, 5, 20)),
+                                  ("paper", PAPER, (90, 95, 99), (0, 20)))
+             for p in ps for h in hs],
+    # FIFO launch with the gate's probe-based queue placement beside plain FIFO
+    "fifo_placed": [{"name": "fifo_placed", "policy": "fifo", "flags": 256},
+                    {"name": "full", "flags": FULL}],
 }
 
 
@@ -161,10 +171,26 @@ def sweep_main(args, torch, capi, runner, synth):
             fifo_sum = summarise(m, st, wall, len(timed)) | {"per_chain": per_chain(cf, wl)}
             fifo.close()
             for v in variants:
+                if v.get("policy") == "fifo":
+                    g = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16,
+                                         flags=v.get("flags", 0), **v.get("cfg", {}))
+                    runner.copy_estimates(prof, g, wl)
+                    run_policy(g, dw, warm[: len(warm) // 2], torch)
+                    th = 0
+                    cu, m, st, wall = run_policy(g, dw, timed, torch)
+                    u = summarise(m, st, wall, len(timed)) | {"per_chain": per_chain(cu, wl)}
+                    g.close()
+                    print(json.dumps({"sweep": args.sweep, "variant": v["name"], **point,
+                                      "th_urgent_slack_ms": 0, "urgency": u,
+                                      "fifo": fifo_sum}), flush=True)
+                    log(f"{args.sweep} seed {seed} {v['name']}: {u['miss_ratio_pct']} % "
+                        f"p99 {u['p99_ms']} ms | fifo {fifo_sum['miss_ratio_pct']} % "
+                        f"p99 {fifo_sum['p99_ms']} ms")
+                    continue
                 g = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16,
                                      **v.get("cfg", {}))
                 runner.copy_estimates(prof, g, wl)
-                flags = v.get("flags", FULL)
+                flags = v.get("flags", FULL) | capi.F_PLACE
                 g.set_flags((flags & ~capi.F_DELAY) | capi.F_CALIBRATE)
                 g.set_threshold(0)
                 run_policy(g, dw, warm, torch)
@@ -235,6 +261,7 @@ def serve_main(args, torch, capi, runner, synth):
     prof = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16)
     runner.profile(prof, dw, warmup=2, reps=5)
     est = runner.estimates(prof, wl)
+    profs = runner.profiles(prof, wl)
     util = sum(sum(est[(c, g)][0] for g in range(sum(len(t["kernels"]) for t in ch.tasks)))
                / ch.period_ns for c, ch in enumerate(wl.chains))
     prof.close()
@@ -246,16 +273,18 @@ def serve_main(args, torch, capi, runner, synth):
                                  hbm_budget_bytes=budget)
             for (c, k), (e, u) in est.items():
                 g.set_estimate(c, k, e, u)
+            for (c, k), pts in profs.items():
+                g.set_profile(c, k, pts)
             for c, fp in enumerate(fps):
                 g.set_footprint(c, fp)
             gates[name] = g
         urg = gates["urgency"]
-        urg.set_flags((FULL & ~capi.F_DELAY) | capi.F_CALIBRATE)
+        urg.set_flags((FULL & ~capi.F_DELAY) | capi.F_CALIBRATE | capi.F_PLACE)
         urg.set_threshold(0)
         run_serve(urg, dw, warm, dims, torch)
         th = urg.calibration_threshold(TH_PCT)
         urg.set_threshold(th)
-        urg.set_flags(FULL)
+        urg.set_flags(FULL | capi.F_PLACE)
         run_serve(gates["fifo"], dw, warm, dims, torch)
         runs = {"urgency": [], "fifo": []}
         for name in ("urgency", "fifo", "fifo", "urgency"):
@@ -686,12 +715,12 @@ def main():
 
     # TH_urgent: run the warm-up windows with delayed launching off and
     # calibration sampling on, take the TH_PCT-th percentile (Sec. 4.4.3)
-    urg.set_flags((FULL & ~capi.F_DELAY) | capi.F_CALIBRATE)
+    urg.set_flags((FULL & ~capi.F_DELAY) | capi.F_CALIBRATE | capi.F_PLACE)
     urg.set_threshold(0)
     run_policy(urg, dw, warm, torch, be=be_warm)
     th = urg.calibration_threshold(TH_PCT)
     urg.set_threshold(th)
-    urg.set_flags(FULL)
+    urg.set_flags(FULL | capi.F_PLACE)
     log(f"TH_urgent calibrated: slack {th / 1e6:.3f} ms")
 
     # timed: urgency gate

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define UG_ABI_VERSION 4u
+#define UG_ABI_VERSION 5u
 
 typedef int32_t ug_status;
 enum {
@@ -141,10 +141,15 @@ enum {
  *                       zmax -inf, first -1.  z must not be NaN.
  *  UG_OP_GEMM_FP8       C = A B with A, B in OCP FP8 E4M3 (one byte per
  *                       value) and an FP32 result, FP32 accumulation on the
- *                       FP8 matrix cores.  shape {M, N, K}, K a multiple of
- *                       16; in {A[M,K] row-major, Bt[N,K] = B transposed
- *                       (K contiguous)}; out {C[M,N] fp32}; A and Bt 16-byte
- *                       aligned.  The best-effort load of an overloaded GPU.
+ *                       FP8 matrix cores.  shape {M, N, K, m0}, K a multiple
+ *                       of 16; in {A[m0+M,K] row-major, Bt[N,K] = B
+ *                       transposed (K contiguous)}; out {C[m0+M,N] fp32}:
+ *                       rows m0 .. m0+M-1 of C from the same rows of A
+ *                       (m0 = 0: the whole product; m0 > 0: one row band of
+ *                       a product split into sub-kernels, the kernel
+ *                       splitting of the cCUDA baseline, Sec. 6.3); A and
+ *                       Bt 16-byte aligned.  The best-effort load of an
+ *                       overloaded GPU.
  *  UG_OP_GEMM_BF16      C = A B with A, B in bfloat16 (two bytes per value,
  *                       the upper half of an IEEE binary32) and an FP32
  *                       result, FP32 accumulation on the BF16 matrix cores.
@@ -177,11 +182,20 @@ enum {
   UG_OP_GEMM_FP8 = 7,
   UG_OP_GEMM_BF16 = 8,
   UG_OP_VECADD_F32 = 9,
-  UG_OP_CONV3X3_BF16 = 10
+  UG_OP_CONV3X3_BF16 = 10,
+  UG_OP_UPLOAD_H2D = 11,
+  UG_OP_ACCUM_I32 = 12
 };
 
 /* One kernel of a task (a row of the paper's lookup table, Tab. "Example
- * lookup table", plus its buffer bindings). */
+ * lookup table", plus its buffer bindings).  UPLOAD_H2D is a host-to-device
+ * copy (the cuMemCpy row of Tab. "Intercepted function calls": delayed like
+ * a launch, bound to the task's stream; its utilisation is taken as 1 unless
+ * given).  shape {N, unit bytes}; in {source: host memory the caller pinned
+ * (hipHostMalloc, torch pin_memory)}; out {device destination}; copies
+ * N * unit bytes.  ACCUM_I32 updates device-resident chain state: state_i +=
+ * x_i in int32 (wrapping); shape {N}; in {x[N]}; out {state[N]}, a buffer
+ * every frame of the chain shares, updated in frame order. */
 typedef struct {
   int32_t op;          /* UG_OP_*                                             */
   int32_t in[3];       /* input buffer slots, -1 = unused                     */
@@ -190,12 +204,27 @@ typedef struct {
   float fparam[4];     /* op-specific float parameters                        */
   int64_t est_ns;      /* estimated execution time E_k; 0 = not yet profiled  */
   float util;          /* utilisation U_k in [0,1]; < 0 = derive from launch  */
-  int32_t frame_dim;   /* 0: fixed shape.  d in 1..4: shape[0] varies per
-                          frame: each frame gives it as dims[d-1] in
-                          ug_frame_submit_dims, at most the registered
-                          shape[0] (the size its buffers, workspace and
-                          estimate are made for)                         */
+  int32_t frame_dim;   /* 0: fixed shape.  d in 1..4: a per-frame size: each
+                          frame gives a value v as dims[d-1] in
+                          ug_frame_submit_dims, and s = v >> frame_shift
+                          sets the op's frame dimension (below); the
+                          registered shape is the largest (the size its
+                          buffers and workspace are made for)            */
+  int32_t frame_shift; /* 0..30 (see frame_dim)                             */
+  int32_t pad0;
 } ug_kernel;
+
+/* The frame dimension each op takes from s = v >> frame_shift (other ops
+ * take no per-frame size: registration fails with UG_EINVAL):
+ *   VOXEL_F32     N = s points (s may be 0)
+ *   UPLOAD_H2D    N = s units (s may be 0)
+ *   GEMM_F32      M = s rows          SOFTMAX_F32   R = s rows
+ *   CONV3X3_*     H = W = s (registered square)
+ *   BIAS_RELU_F32 axis 1: C = s * s (the image plane of a channel);
+ *                 axis 0: R = s rows
+ *   ROWSUM_F32    C = s * s (each row is an image plane)
+ * The estimate E_k of such a kernel follows the frame's size through its
+ * profile points (ug_kernel_set_profile). */
 
 /* One task: a CPU segment (host-side time before the kernels may launch,
  * Sec. 4.2) followed by kernels that run in order on one stream. */
@@ -272,10 +301,13 @@ typedef struct {
 } ug_completion;
 
 /* Decision-log record.  The log is a sequence of instants; each INSTANT
- * record is followed by its inputs (ARRIVE, EVDONE) and then the decisions
- * taken at that instant (COMPLETE, TSTART, BIND, HOLD, EVREC, LAUNCH).
+ * record is followed by its inputs (ARRIVE with its DIMS, EVDONE) and then
+ * the decisions taken at that instant (COMPLETE, TSTART, BIND, HOLD, EVREC,
+ * LAUNCH).
  *   INSTANT  t = instant time, a = #arrivals, b = #observed events
  *   ARRIVE   chain, frame, t = t_arr
+ *   DIMS     chain, frame, a = index d, t = the frame's dims[d] (after the
+ *            frame's ARRIVE; frames submitted with per-frame sizes)
  *   EVDONE   chain, frame, task, a = kind (0 batch start, 1 task end), b = seq
  *   COMPLETE chain, frame, t = t_done
  *   EXIT     chain, frame, task, t: the frame leaves its chain instead of
@@ -290,7 +322,7 @@ typedef struct {
 enum {
   UG_REC_INSTANT = 1, UG_REC_ARRIVE = 2, UG_REC_EVDONE = 3, UG_REC_COMPLETE = 4,
   UG_REC_TSTART = 5, UG_REC_BIND = 6, UG_REC_HOLD = 7, UG_REC_EVREC = 8,
-  UG_REC_LAUNCH = 9, UG_REC_EXIT = 10
+  UG_REC_LAUNCH = 9, UG_REC_EXIT = 10, UG_REC_DIMS = 11
 };
 typedef struct {
   int32_t type;
@@ -384,9 +416,25 @@ ug_status ug_kernel_set_estimate(void* ctx, uint32_t chain, uint32_t kernel,
 ug_status ug_kernel_get_estimate(void* ctx, uint32_t chain, uint32_t kernel,
                                  int64_t* est_ns, float* util);
 
+/* Profile points of a kernel with a per-frame size (frame_dim > 0): its
+ * estimate at n frame values v[i] (strictly increasing) is e[i] ns.  A frame
+ * of value v then enters Eq. 2 and the batch sums with the estimate at v:
+ * linear between neighbouring points (rounded down), the end point's
+ * estimate beyond either end -- the lookup of Sec. 4.1 / Tab. "Example
+ * lookup table" keyed by launch size.  n = 0 removes the points (the fixed
+ * E_k applies).  ug_profile sets them.  Only before ug_start.  Errors:
+ * UG_EINVAL (no such kernel, no frame_dim, n > 16, v not increasing, e < 0),
+ * UG_ESTATE.  get: copies up to cap points and sets *n to their number. */
+ug_status ug_kernel_set_profile(void* ctx, uint32_t chain, uint32_t kernel,
+                                const int64_t* v, const int64_t* e, uint32_t n);
+ug_status ug_kernel_get_profile(void* ctx, uint32_t chain, uint32_t kernel,
+                                int64_t* v, int64_t* e, uint32_t cap, uint32_t* n);
+
 /* Offline profiling stage (Sec. 4.1): runs every kernel of the chain in
  * isolation on the given frame buffers (warmup, then reps timed with HIP
- * events; the median is E_k) and stores the estimates.  Kernels with the
+ * events; the median is E_k) and stores the estimates.  A kernel with a
+ * per-frame size is measured at the largest frame value and at 1/2, 1/4 and
+ * 1/8 of it (its profile points; E_k is the largest).  Kernels with the
  * same (op, shape) share one measurement.  Overwrites the buffers' contents.
  * Only before ug_start.  Errors: UG_ENODEV, UG_EINVAL, UG_EDEVICE. */
 ug_status ug_profile(void* ctx, uint32_t chain, void* const* buffers,

@@ -73,10 +73,15 @@ class ChainSpec:
         self.cpu = []             # CPU-segment estimate of each task (ns)
         self.est = []             # estimated time of each kernel (ns)
         self.util = []            # utilisation of each kernel (float32)
+        self.fdim = []            # per-frame size index + 1 of each kernel (0: fixed)
+        self.prof = []            # profile points [(v, E), ...] of each kernel, or None
         for task in spec["tasks"]:
             self.task_first.append(len(self.est))
             self.est.extend(int(e) for e in task["est_ns"])
             self.util.extend(np.float32(u) for u in task["util"])
+            nk = len(task["est_ns"])
+            self.fdim.extend(int(d) for d in task.get("frame_dim", [0] * nk))
+            self.prof.extend(task.get("prof", [None] * nk))
             self.task_end.append(len(self.est))
             self.cpu.append(int(task.get("cpu_ns", 0)))
             assert self.task_end[-1] > self.task_first[-1], "a task needs kernels"
@@ -90,6 +95,17 @@ class ChainSpec:
         self.cpu_rem = [0] * (self.n_tasks + 1)
         for j in range(self.n_tasks - 1, -1, -1):
             self.cpu_rem[j] = self.cpu_rem[j + 1] + self.cpu[j]
+        # a kernel with a per-frame size and profile points is estimated per
+        # frame, at that frame's size
+        self.per_frame = any(d > 0 and p for d, p in zip(self.fdim, self.prof))
+
+    def frame_estimates(self, dims):
+        """E of every kernel for a frame with sizes ``dims``."""
+        est = list(self.est)
+        for g, (d, pts) in enumerate(zip(self.fdim, self.prof)):
+            if d > 0 and pts:
+                est[g] = P.profile_estimate(pts, dims[d - 1])
+        return est
 
 
 class Instance:
@@ -115,6 +131,8 @@ class Instance:
         self.level = None
         self.lane = None
         self.wake = None          # re-check time of a held launch (sleep loop)
+        self.est = None           # this frame's estimates (per-frame sizes), else None
+        self.gpu_rem = None       # their suffix sums
         self.held_since = None    # first hold of the current task (hold-age bound)
         self.expire = None        # while held: when the hold age reaches its bound
 
@@ -197,15 +215,16 @@ class GateModel:
         estimate noise, the same sums with every task's part scaled by that
         task instance's factor (1000 + k) / 1000 (floor per task)."""
         ch = inst.chain
+        rem = ch.gpu_rem if inst.gpu_rem is None else inst.gpu_rem
         n = self.cfg["est_noise_permille"]
         if n <= 0:
-            return ch.gpu_rem[inst.i_gpu], ch.cpu_rem[inst.i_cpu]
+            return rem[inst.i_gpu], ch.cpu_rem[inst.i_cpu]
         gpu = cpu = 0
         for j in range(ch.n_tasks):
             fac = 1000 + P.noise_permille(self.cfg["noise_seed"], inst.c, inst.f, j, n)
             lo = max(inst.i_gpu, ch.task_first[j])
             if lo < ch.task_end[j]:
-                gpu += (ch.gpu_rem[lo] - ch.gpu_rem[ch.task_end[j]]) * fac // 1000
+                gpu += (rem[lo] - rem[ch.task_end[j]]) * fac // 1000
             if j >= inst.i_cpu:
                 cpu += ch.cpu[j] * fac // 1000
         return gpu, cpu
@@ -235,16 +254,24 @@ class GateModel:
     def instant(self, t, arrivals=(), evdones=()):
         """Process one decision instant.  Returns the list of decisions.
 
-        ``arrivals``: (c, f, t_arr) of frames first seen at this instant.
+        ``arrivals``: (c, f, t_arr) of frames first seen at this instant, or
+        (c, f, t_arr, dims) for a frame with per-frame sizes.
         ``evdones``: (c, f, j, kind, seq) of events observed complete.
         """
         self.now = t
         out = []
         finished = []
         # 1. inputs, in canonical order
-        for c, f, t_arr in sorted(arrivals):
+        for a in sorted(arrivals):
+            c, f, t_arr = a[:3]
             assert (c, f) not in self.inst, "frame arrives twice"
             inst = Instance(c, f, t_arr, self.chains[c])
+            if inst.chain.per_frame:
+                inst.est = inst.chain.frame_estimates(a[3])
+                n = len(inst.est)
+                inst.gpu_rem = [0] * (n + 1)
+                for g in range(n - 1, -1, -1):
+                    inst.gpu_rem[g] = inst.gpu_rem[g + 1] + inst.est[g]
             self.inst[(c, f)] = inst
             self.queue[(c, 0)].append(f)
         for c, f, j, kind, seq in sorted(evdones, key=lambda e: (e[0], e[1], e[2], e[4], e[3])):
@@ -458,9 +485,12 @@ class GateModel:
             out.append(("LAUNCH", inst.c, inst.f, g, inst.level, inst.lane))
             inst.released_hi = g + 1
             inst.g_next = g + 1
-            inst.batch_sum += ch.est[g]
+            inst.batch_sum += ch.est[g] if inst.est is None else inst.est[g]
             last = g == end - 1
-            if last or (delta is not None and inst.batch_sum > delta):
+            # a best-effort kernel is a batch of its own: the gate decides
+            # again before each of them (each is a point where deadline work
+            # can overtake the background load)
+            if last or (delta is not None and (ch.best_effort or inst.batch_sum > delta)):
                 # the start event of a batch opened ahead (no overlap) has
                 # already been waited for, before its first kernel was released
                 if not (self.urgency_policy and self.cfg["no_overlap"] and inst.batch > 0):

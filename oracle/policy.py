@@ -218,3 +218,19 @@ def noise_permille(seed, c, f, j, n):
     reduced modulo 2n + 1."""
     h = splitmix64(splitmix64(splitmix64((seed ^ c) & _M64) ^ f) ^ j)
     return h % (2 * n + 1) - n
+
+
+def profile_estimate(points, v):
+    """Estimate of a kernel for a frame of size v from its profile points
+    [(v_0, E_0), (v_1, E_1), ...] (v increasing): the launch-size lookup of
+    Sec. 4.1 (Tab. "Example lookup table"), read between table rows as the
+    straight line through the two neighbouring points, rounded down, and as
+    the nearest end point's estimate outside the table."""
+    if v <= points[0][0]:
+        return points[0][1]
+    if v >= points[-1][0]:
+        return points[-1][1]
+    for (v0, e0), (v1, e1) in zip(points, points[1:]):
+        if v0 <= v < v1:
+            return e0 + ((e1 - e0) * (v - v0)) // (v1 - v0)
+    raise AssertionError("unreachable")

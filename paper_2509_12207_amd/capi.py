@@ -12,7 +12,7 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libug.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 POLICY_FIFO, POLICY_URGENCY = 0, 1
@@ -33,14 +33,16 @@ OP_GEMM_FP8 = 7
 OP_GEMM_BF16 = 8
 OP_VECADD_F32 = 9
 OP_CONV3X3_BF16 = 10
+OP_UPLOAD_H2D = 11
+OP_ACCUM_I32 = 12
 OP_NAMES = {OP_GEMM_F32: "gemm", OP_BIAS_RELU_F32: "bias_relu", OP_CONV3X3_F32: "conv3x3",
             OP_ROWSUM_F32: "rowsum", OP_SOFTMAX_F32: "softmax", OP_VOXEL_F32: "voxel",
             OP_GEMM_FP8: "gemm_fp8", OP_GEMM_BF16: "gemm_bf16", OP_VECADD_F32: "vecadd",
-            OP_CONV3X3_BF16: "conv3x3_bf16"}
+            OP_CONV3X3_BF16: "conv3x3_bf16", OP_UPLOAD_H2D: "upload", OP_ACCUM_I32: "accum_i32"}
 OP_IDS = {v: k for k, v in OP_NAMES.items()}
 
 REC_INSTANT, REC_ARRIVE, REC_EVDONE, REC_COMPLETE = 1, 2, 3, 4
-REC_TSTART, REC_BIND, REC_HOLD, REC_EVREC, REC_LAUNCH, REC_EXIT = 5, 6, 7, 8, 9, 10
+REC_TSTART, REC_BIND, REC_HOLD, REC_EVREC, REC_LAUNCH, REC_EXIT, REC_DIMS = 5, 6, 7, 8, 9, 10, 11
 
 EXPORTED = [
     "ug_config_default", "ug_now_ns", "ug_status_str", "ug_create", "ug_destroy",
@@ -50,14 +52,15 @@ EXPORTED = [
     "ug_calibration_read", "ug_calibration_threshold", "ug_get_metrics", "ug_replay_instant",
     "ug_kernel_launch", "ug_kernel_util", "ug_kernel_workspace", "ug_kernel_launch_ws",
     "ug_frame_submit_dims", "ug_chain_set_footprint", "ug_streams_needed", "ug_attach_streams",
-    "ug_kernel_launch_noalloc",
+    "ug_kernel_launch_noalloc", "ug_kernel_set_profile", "ug_kernel_get_profile",
 ]
 
 
 class Kernel(C.Structure):
     _fields_ = [("op", C.c_int32), ("in_", C.c_int32 * 3), ("out", C.c_int32 * 4),
                 ("shape", C.c_int64 * 4), ("fparam", C.c_float * 4), ("est_ns", C.c_int64),
-                ("util", C.c_float), ("frame_dim", C.c_int32)]
+                ("util", C.c_float), ("frame_dim", C.c_int32), ("frame_shift", C.c_int32),
+                ("pad0", C.c_int32)]
 
 
 class Task(C.Structure):
@@ -175,6 +178,11 @@ def lib():
         L.ug_streams_needed.argtypes = [vp, C.POINTER(C.c_uint32)]
         L.ug_attach_streams.argtypes = [vp, C.POINTER(vp), C.c_uint32]
         L.ug_kernel_launch_noalloc.argtypes = [C.POINTER(Kernel), C.POINTER(vp), C.c_uint32, vp]
+        L.ug_kernel_set_profile.argtypes = [vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_int64),
+                                            C.POINTER(C.c_int64), C.c_uint32]
+        L.ug_kernel_get_profile.argtypes = [vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_int64),
+                                            C.POINTER(C.c_int64), C.c_uint32,
+                                            C.POINTER(C.c_uint32)]
         for name in ("ug_create", "ug_chain_register", "ug_kernel_set_estimate",
                      "ug_kernel_get_estimate", "ug_profile", "ug_set_threshold", "ug_set_flags",
                      "ug_start", "ug_frame_submit", "ug_poll_complete", "ug_drain", "ug_stop",
@@ -182,7 +190,8 @@ def lib():
                      "ug_calibration_threshold", "ug_get_metrics", "ug_replay_instant",
                      "ug_kernel_launch", "ug_kernel_util", "ug_frame_submit_dims",
                      "ug_chain_set_footprint", "ug_streams_needed", "ug_attach_streams",
-                     "ug_kernel_launch_noalloc"):
+                     "ug_kernel_launch_noalloc", "ug_kernel_set_profile",
+                     "ug_kernel_get_profile"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -201,8 +210,8 @@ def kernel_struct(k):
     dict keys: op (name or id), shape (<= 4 ints), in (<= 3 slots), out (<= 4
     slots), fparam (<= 4 floats), est_ns (int, default 0), util (float,
     default -1 = derive from the launch shape), frame_dim (int, default 0 =
-    fixed shape; d >= 1: shape[0] is the maximum, each frame gives its own
-    value as dims[d - 1]).
+    fixed shape; d >= 1: a per-frame size, each frame gives its own value as
+    dims[d - 1]), frame_shift (int, default 0).
     """
     s = Kernel()
     op = k["op"]
@@ -222,6 +231,7 @@ def kernel_struct(k):
     s.est_ns = int(k.get("est_ns", 0))
     s.util = float(k.get("util", -1.0))
     s.frame_dim = int(k.get("frame_dim", 0))
+    s.frame_shift = int(k.get("frame_shift", 0))
     return s
 
 
@@ -298,6 +308,10 @@ class Gate:
     The stream pool comes from torch: ``start`` attaches default-priority
     ``torch.cuda.Stream`` objects (kept alive by this object) unless streams
     were attached before or the library owns its streams (``own_streams=1``).
+    torch hands out streams from a fixed pool of 32 per device, so FIFO
+    launch, which needs one stream per task of every chain, lets the
+    library create its own unless given ``own_streams=0`` (then attach
+    distinct streams before ``start``).
     """
 
     def __init__(self, policy="urgency", device=0, **kw):
@@ -308,6 +322,7 @@ class Gate:
         cfg.device = device
         if cfg.policy == POLICY_FIFO:
             cfg.flags = 0
+            cfg.own_streams = 1
         lanes = kw.pop("lanes", None)
         key = kw.pop("order_key", None)
         if key is not None:
@@ -370,6 +385,20 @@ class Gate:
                     "ug_kernel_get_estimate")
         return int(e.value), float(u.value)
 
+    def set_profile(self, chain, kernel, points):
+        """Profile points [(v, E_ns), ...] of a kernel with a per-frame size."""
+        n = len(points)
+        v = (C.c_int64 * max(1, n))(*[int(p[0]) for p in points])
+        e = (C.c_int64 * max(1, n))(*[int(p[1]) for p in points])
+        self._check(lib().ug_kernel_set_profile(self.h, chain, kernel, v, e, n),
+                    "ug_kernel_set_profile")
+
+    def get_profile(self, chain, kernel, cap=16):
+        v, e, n = (C.c_int64 * cap)(), (C.c_int64 * cap)(), C.c_uint32()
+        self._check(lib().ug_kernel_get_profile(self.h, chain, kernel, v, e, cap, C.byref(n)),
+                    "ug_kernel_get_profile")
+        return [(int(v[i]), int(e[i])) for i in range(min(cap, n.value))]
+
     def profile(self, chain, ptrs, warmup=3, reps=10):
         arr = pointer_array(ptrs)
         self._check(lib().ug_profile(self.h, chain, arr, len(ptrs), warmup, reps), "ug_profile")
@@ -394,7 +423,11 @@ class Gate:
         if streams is None:
             import torch
             dev = torch.device("cuda", self.cfg.device)
-            streams = [torch.cuda.Stream(device=dev) for _ in range(self.streams_needed())]
+            n = self.streams_needed()
+            if n > 32:
+                raise ValueError(f"{n} streams: more than torch's pool of 32 distinct streams "
+                                 "(create the context with own_streams=1)")
+            streams = [torch.cuda.Stream(device=dev) for _ in range(n)]
         arr = pointer_array([s.cuda_stream for s in streams])
         self._check(lib().ug_attach_streams(self.h, arr, len(streams)), "ug_attach_streams")
         self._streams = list(streams)

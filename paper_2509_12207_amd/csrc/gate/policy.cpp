@@ -49,6 +49,27 @@ void ChainSpec::finalize() {
   const size_t m = cpu.size();
   cpu_rem.assign(m + 1, 0);
   for (size_t j = m; j-- > 0;) cpu_rem[j] = cpu_rem[j + 1] + cpu[j];
+  fdim.resize(n, 0);
+  prof.resize(n);
+  per_frame = false;
+  for (size_t g = 0; g < n; ++g)
+    if (fdim[g] > 0 && !prof[g].empty()) per_frame = true;
+}
+
+static int64_t floor_div(__int128 a, int64_t b) {
+  __int128 q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return static_cast<int64_t>(q);
+}
+
+int64_t profile_estimate(const std::vector<std::pair<int64_t, int64_t>>& p, int64_t v) {
+  if (v <= p.front().first) return p.front().second;
+  if (v >= p.back().first) return p.back().second;
+  size_t i = 0;
+  while (p[i + 1].first <= v) ++i;
+  const int64_t v0 = p[i].first, v1 = p[i + 1].first;
+  const int64_t e0 = p[i].second, e1 = p[i + 1].second;
+  return e0 + floor_div(static_cast<__int128>(e1 - e0) * (v - v0), v1 - v0);
 }
 
 uint32_t Policy::add_chain(ChainSpec&& spec) {
@@ -142,6 +163,24 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
     in.c = a.c;
     in.f = a.f;
     in.t_arr = a.t_arr;
+    const ChainSpec& ch = chains_[a.c];
+    if (ch.per_frame) {
+      // this frame's estimates: a kernel with profile points takes the
+      // estimate of the frame's size, the others their fixed one
+      const size_t n = ch.est.size();
+      in.est = ch.est;
+      for (size_t g = 0; g < n; ++g) {
+        if (ch.fdim[g] <= 0 || ch.prof[g].empty()) continue;
+        const size_t d = static_cast<size_t>(ch.fdim[g] - 1);
+        if (d >= a.dims.size()) {
+          *err = "arrival without the frame's sizes";
+          return false;
+        }
+        in.est[g] = profile_estimate(ch.prof[g], a.dims[d]);
+      }
+      in.gpu_rem.assign(n + 1, 0);
+      for (size_t g = n; g-- > 0;) in.gpu_rem[g] = in.gpu_rem[g + 1] + in.est[g];
+    }
     inst_.emplace(Key{a.c, a.f}, std::move(in));
     queue_[{a.c, 0}].push_back(a.f);
   }
@@ -274,13 +313,14 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
 int64_t Policy::remaining(const Instance& in) const {
   const ChainSpec& ch = chains_[in.c];
   const int32_t n = cfg_.est_noise_permille;
-  if (n <= 0) return ch.gpu_rem[in.i_gpu] + ch.cpu_rem[in.i_cpu];
+  const std::vector<int64_t>& rem = in.gpu_rem.empty() ? ch.gpu_rem : in.gpu_rem;
+  if (n <= 0) return rem[in.i_gpu] + ch.cpu_rem[in.i_cpu];
   int64_t gpu = 0, cpu = 0;
   const int32_t nt = static_cast<int32_t>(ch.task_first.size());
   for (int32_t j = 0; j < nt; ++j) {
     const int64_t fac = 1000 + noise_permille(cfg_.noise_seed, in.c, in.f, j, n);
     const int32_t lo = std::max(in.i_gpu, ch.task_first[j]);
-    if (lo < ch.task_end[j]) gpu += (ch.gpu_rem[lo] - ch.gpu_rem[ch.task_end[j]]) * fac / 1000;
+    if (lo < ch.task_end[j]) gpu += (rem[lo] - rem[ch.task_end[j]]) * fac / 1000;
     if (j >= in.i_cpu) cpu += ch.cpu[j] * fac / 1000;
   }
   return gpu + cpu;
@@ -454,9 +494,11 @@ void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& acti
     out.push_back(rec(UG_REC_LAUNCH, me.c, me.f, me.task, g, me.level, me.lane, 0));
     me.released_hi = g + 1;
     me.g_next = g + 1;
-    me.batch_sum += ch.est[g];
+    me.batch_sum += me.est.empty() ? ch.est[g] : me.est[g];
     const bool last = g == end - 1;
-    if (last || (batching && me.batch_sum > cfg_.delta_eval_ns)) {
+    // a best-effort kernel is a batch of its own, so the gate decides again
+    // before each one
+    if (last || (batching && (ch.best_effort || me.batch_sum > cfg_.delta_eval_ns))) {
       // the start event of a batch opened ahead (no overlap) has already
       // been waited for, before its first kernel was released
       if (!(gated && cfg_.no_overlap && me.batch > 0)) me.waits.push_back({0, me.batch});

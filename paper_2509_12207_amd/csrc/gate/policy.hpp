@@ -64,8 +64,19 @@ struct ChainSpec {
   std::vector<int64_t> cpu;           // CPU segment of each task
   std::vector<int64_t> gpu_rem;       // sum_{k >= g} E_k, size N + 1
   std::vector<int64_t> cpu_rem;       // sum_{j' >= j} E^cpu_j', size M + 1
+  // per-frame sizes: the frame dimension each kernel takes (0 = none) and
+  // its profile points (v, E) sorted by v; a kernel with points has a
+  // per-frame estimate
+  std::vector<int32_t> fdim;
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> prof;
+  bool per_frame = false;             // some kernel has a per-frame estimate
   void finalize();
 };
+
+// Estimate of a kernel for a frame of size v from its profile points:
+// linear between neighbouring points (floor), the end point's value beyond
+// either end.
+int64_t profile_estimate(const std::vector<std::pair<int64_t, int64_t>>& p, int64_t v);
 
 struct Wait {
   int32_t kind;  // 0 batch start, 1 task end
@@ -100,6 +111,9 @@ struct Instance {
   bool has_expire = false;
   int64_t expire = 0;
   int32_t n_holds = 0, n_batches = 0;
+  // per-frame estimates (chains with per-frame sizes): E of every kernel
+  // for this frame and their suffix sums; empty otherwise
+  std::vector<int64_t> est, gpu_rem;
   bool in_flight() const { return released_hi > i_gpu; }
 };
 
@@ -107,6 +121,7 @@ struct Arrival {
   int32_t c;
   int64_t f;
   int64_t t_arr;
+  std::vector<int64_t> dims;  // the frame's sizes (chains with per-frame sizes)
 };
 struct EvDone {
   int32_t c;

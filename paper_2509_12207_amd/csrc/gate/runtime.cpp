@@ -230,7 +230,7 @@ hipGraphExec_t task_graph(Ctx* c, int32_t chain, int32_t j, const Frame& fr, hip
   hipError_t launch_err = hipSuccess;
   for (int32_t g = ch.task_first[j]; g < ch.task_end[j] && launch_err == hipSuccess; ++g) {
     ug_kernel k = ch.kernels[g];
-    if (k.frame_dim > 0) k.shape[0] = fr.dims[k.frame_dim - 1];
+    if (k.frame_dim > 0) k = ug::frame_kernel(k, fr.dims[k.frame_dim - 1]);
     launch_err = ug::launch_kernel(k, fr.buffers.data(), c->capture_stream, c->ws[chain][g],
                                    c->ws_bytes[chain][g]);
   }
@@ -354,8 +354,8 @@ bool execute(Ctx* c, const std::vector<ug_record>& dec) {
             if (ge) err = hipGraphLaunch(ge, c->bound.at(key));
           }
         } else if (kd.frame_dim > 0) {
-          ug_kernel kf = kd;  // this frame's size (checked at submission)
-          kf.shape[0] = fr.dims[kd.frame_dim - 1];
+          // this frame's size (checked at submission)
+          const ug_kernel kf = ug::frame_kernel(kd, fr.dims[kd.frame_dim - 1]);
           err = ug::launch_kernel(kf, fr.buffers.data(), c->bound.at(key),
                                   c->ws[d.chain][d.kernel], c->ws_bytes[d.chain][d.kernel]);
         } else {
@@ -460,7 +460,7 @@ void gate_main(Ctx* c) {
     for (size_t i = 0; i < c->pending.size();) {
       if (c->pending[i].t_arr <= now) {
         Frame& f = c->pending[i];
-        arr.push_back({static_cast<int32_t>(f.chain), f.f, f.t_arr});
+        arr.push_back({static_cast<int32_t>(f.chain), f.f, f.t_arr, f.dims});
         c->frames[{static_cast<int32_t>(f.chain), f.f}] = std::move(f);
         if (i + 1 != c->pending.size()) c->pending[i] = std::move(c->pending.back());
         c->pending.pop_back();
@@ -493,7 +493,11 @@ void gate_main(Ctx* c) {
     {
       std::lock_guard<std::mutex> lk(c->trace_mu);
       push_trace(c, make_rec(UG_REC_INSTANT, 0, 0, 0, 0, (int32_t)arr.size(), (int32_t)evs.size(), now));
-      for (const auto& a : arr) push_trace(c, make_rec(UG_REC_ARRIVE, a.c, a.f, 0, 0, 0, 0, a.t_arr));
+      for (const auto& a : arr) {
+        push_trace(c, make_rec(UG_REC_ARRIVE, a.c, a.f, 0, 0, 0, 0, a.t_arr));
+        for (size_t d = 0; d < a.dims.size(); ++d)
+          push_trace(c, make_rec(UG_REC_DIMS, a.c, a.f, 0, 0, static_cast<int32_t>(d), 0, a.dims[d]));
+      }
       for (const auto& e : evs)
         push_trace(c, make_rec(UG_REC_EVDONE, e.c, e.f, e.task, 0, e.kind, e.seq, 0));
       for (const auto& d : dec) push_trace(c, d);
@@ -705,17 +709,25 @@ ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
       if (kd.est_ns < 0) return fail(c, UG_EINVAL, "est_ns must be >= 0");
       if (kd.frame_dim < 0 || kd.frame_dim > 4) return fail(c, UG_EINVAL, "frame_dim must be in 0..4");
       if (kd.frame_dim > 0) {
-        // per-frame shape[0]: at most the registered value, at least 1 (the
-        // voxel scatter takes empty clouds)
+        // the per-frame values this kernel accepts, by its op's frame
+        // dimension (at most the registered size)
+        int64_t lo = 0, hi = 0;
+        if (!ug::frame_range(kd, &lo, &hi))
+          return fail(c, UG_EINVAL, "this op or registered shape takes no per-frame size");
         const size_t d = static_cast<size_t>(kd.frame_dim - 1);
         if (dr.lo.size() <= d) {
           dr.lo.resize(d + 1, 0);
           dr.hi.resize(d + 1, INT64_MAX);
         }
-        dr.lo[d] = std::max<int64_t>(dr.lo[d], kd.op == UG_OP_VOXEL_F32 ? 0 : 1);
-        dr.hi[d] = std::min(dr.hi[d], kd.shape[0]);
+        dr.lo[d] = std::max(dr.lo[d], lo);
+        dr.hi[d] = std::min(dr.hi[d], hi);
+        if (dr.lo[d] > dr.hi[d])
+          return fail(c, UG_EINVAL, "the kernels sharing a per-frame size admit no common value");
+      } else if (kd.frame_shift != 0) {
+        return fail(c, UG_EINVAL, "frame_shift without frame_dim");
       }
       float u = kd.util;
+      if (u < 0.f && kd.op == UG_OP_UPLOAD_H2D) u = 1.0f;   // delayed like a full launch
       if (u < 0.f) {
         if (c->has_device) {
           if (ug_kernel_util(&kd, c->cfg.device, &u) != UG_OK) u = 1.0f;
@@ -726,6 +738,7 @@ ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
       spec.kernels.push_back(kd);
       spec.est.push_back(kd.est_ns);
       spec.util.push_back(u);
+      spec.fdim.push_back(kd.frame_dim);
     }
     spec.task_end.push_back(static_cast<int32_t>(spec.kernels.size()));
     spec.cpu.push_back(t.cpu_ns);
@@ -803,41 +816,107 @@ ug_status ug_profile(void* ctx, uint32_t chain, void* const* buffers, uint32_t n
   std::map<std::vector<int64_t>, int64_t> measured;
   ug::ChainSpec& ch = chs[chain];
   ug_status st = UG_OK;
-  for (size_t k = 0; k < ch.kernels.size() && st == UG_OK; ++k) {
-    const ug_kernel& kd = ch.kernels[k];
+  // median of `reps` isolated runs of one kernel shape (shared by equal shapes)
+  auto measure = [&](const ug_kernel& kd, void* w, size_t wb, int64_t* out) -> bool {
     std::vector<int64_t> key{kd.op, kd.shape[0], kd.shape[1], kd.shape[2], kd.shape[3]};
     auto it = measured.find(key);
     if (it != measured.end()) {
-      ch.est[k] = it->second;
-      continue;
+      *out = it->second;
+      return true;
     }
-    void* w = c->ws[chain][k];
-    const size_t wb = c->ws_bytes[chain][k];
     for (uint32_t i = 0; i < warmup; ++i)
-      if ((e = ug::launch_kernel(kd, buffers, s, w, wb)) != hipSuccess)
+      if ((e = ug::launch_kernel(kd, buffers, s, w, wb)) != hipSuccess) {
         st = hip_fail(c, e, "profile launch");
+        return false;
+      }
     std::vector<float> ms(reps);
-    for (uint32_t r = 0; r < reps && st == UG_OK; ++r) {
+    for (uint32_t r = 0; r < reps; ++r) {
       (void)hipEventRecord(ev[2 * r], s);
-      if ((e = ug::launch_kernel(kd, buffers, s, w, wb)) != hipSuccess)
+      if ((e = ug::launch_kernel(kd, buffers, s, w, wb)) != hipSuccess) {
         st = hip_fail(c, e, "profile launch");
+        return false;
+      }
       (void)hipEventRecord(ev[2 * r + 1], s);
     }
-    if (st != UG_OK) break;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) {
       st = hip_fail(c, e, "hipStreamSynchronize");
-      break;
+      return false;
     }
     for (uint32_t r = 0; r < reps; ++r) (void)hipEventElapsedTime(&ms[r], ev[2 * r], ev[2 * r + 1]);
     std::sort(ms.begin(), ms.end());
-    const int64_t est = static_cast<int64_t>(ms[reps / 2] * 1.0e6);
-    measured[key] = est;
-    ch.est[k] = est;
+    *out = static_cast<int64_t>(ms[reps / 2] * 1.0e6);
+    measured[key] = *out;
+    return true;
+  };
+  for (size_t k = 0; k < ch.kernels.size() && st == UG_OK; ++k) {
+    const ug_kernel& kd = ch.kernels[k];
+    void* w = c->ws[chain][k];
+    const size_t wb = c->ws_bytes[chain][k];
+    if (kd.frame_dim <= 0) {
+      int64_t est = 0;
+      if (!measure(kd, w, wb, &est)) break;
+      ch.est[k] = est;
+      continue;
+    }
+    // a per-frame size: profile points at the largest value the chain
+    // accepts and at 1/2, 1/4, 1/8 of it (no lower than the smallest)
+    const DimRange& dr = c->dim_range[chain];
+    const size_t d = static_cast<size_t>(kd.frame_dim - 1);
+    const int64_t hi = dr.hi[d], lo = std::max<int64_t>(dr.lo[d], 1);
+    std::vector<std::pair<int64_t, int64_t>> pts;
+    for (int q = 3; q >= 0 && st == UG_OK; --q) {
+      const int64_t v = std::max(lo, hi >> q);
+      if (!pts.empty() && pts.back().first >= v) continue;
+      int64_t est = 0;
+      if (!measure(ug::frame_kernel(kd, v), w, wb, &est)) break;
+      pts.push_back({v, est});
+    }
+    if (st != UG_OK) break;
+    ch.prof[k] = pts;
+    ch.est[k] = pts.back().second;
   }
   ch.finalize();
   for (auto& x : ev) (void)hipEventDestroy(x);
   (void)hipStreamDestroy(s);
   return st;
+}
+
+ug_status ug_kernel_set_profile(void* ctx, uint32_t chain, uint32_t kernel, const int64_t* v,
+                                const int64_t* e, uint32_t n) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (c->started) return fail(c, UG_ESTATE, "profiles are set before start");
+  auto& chs = c->policy.chains();
+  if (chain >= chs.size() || kernel >= chs[chain].est.size())
+    return fail(c, UG_EINVAL, "no such kernel");
+  ug::ChainSpec& ch = chs[chain];
+  if (ch.fdim[kernel] <= 0) return fail(c, UG_EINVAL, "the kernel has no per-frame size");
+  if (n > 16 || (n && (!v || !e))) return fail(c, UG_EINVAL, "profile: at most 16 points");
+  std::vector<std::pair<int64_t, int64_t>> pts;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (e[i] < 0 || (i && v[i] <= v[i - 1]))
+      return fail(c, UG_EINVAL, "profile: values increasing, estimates >= 0");
+    pts.push_back({v[i], e[i]});
+  }
+  ch.prof[kernel] = pts;
+  ch.finalize();
+  return UG_OK;
+}
+
+ug_status ug_kernel_get_profile(void* ctx, uint32_t chain, uint32_t kernel, int64_t* v,
+                                int64_t* e, uint32_t cap, uint32_t* n) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c || !n || (cap && (!v || !e))) return UG_EINVAL;
+  const auto& chs = c->policy.chains();
+  if (chain >= chs.size() || kernel >= chs[chain].est.size())
+    return fail(c, UG_EINVAL, "no such kernel");
+  const auto& pts = chs[chain].prof[kernel];
+  *n = static_cast<uint32_t>(pts.size());
+  for (uint32_t i = 0; i < cap && i < pts.size(); ++i) {
+    v[i] = pts[i].first;
+    e[i] = pts[i].second;
+  }
+  return UG_OK;
 }
 
 ug_status ug_set_threshold(void* ctx, int64_t th_slack_ns) {
@@ -1115,12 +1194,17 @@ ug_status ug_replay_instant(void* ctx, int64_t t, const ug_record* inputs, uint3
   std::vector<ug::EvDone> evs;
   for (uint32_t i = 0; i < n_inputs; ++i) {
     const ug_record& r = inputs[i];
-    if (r.type == UG_REC_ARRIVE)
-      arr.push_back({r.chain, r.frame, r.t});
-    else if (r.type == UG_REC_EVDONE)
+    if (r.type == UG_REC_ARRIVE) {
+      arr.push_back({r.chain, r.frame, r.t, {}});
+    } else if (r.type == UG_REC_DIMS) {
+      if (arr.empty() || arr.back().c != r.chain || arr.back().f != r.frame ||
+          r.a != static_cast<int32_t>(arr.back().dims.size()))
+        return fail(c, UG_EINVAL, "replay: DIMS follow their frame's ARRIVE, in index order");
+      arr.back().dims.push_back(r.t);
+    } else if (r.type == UG_REC_EVDONE)
       evs.push_back({r.chain, r.frame, r.task, r.a, r.b});
     else
-      return fail(c, UG_EINVAL, "replay inputs are ARRIVE and EVDONE records");
+      return fail(c, UG_EINVAL, "replay inputs are ARRIVE, DIMS and EVDONE records");
   }
   std::vector<ug_record> dec;
   const char* err = nullptr;

@@ -53,7 +53,9 @@ const char* validate_kernel(const ug_kernel& k, uint32_t nb) {
     case UG_OP_GEMM_FP8:
       if (!pos(s[0]) || !pos(s[1]) || !pos(s[2])) return "gemm_fp8: M, N, K must be in [1, 2^31)";
       if (s[2] % 16 != 0) return "gemm_fp8: K must be a multiple of 16";
-      if (s[0] * s[2] >= kMaxDim * 32 || s[1] * s[2] >= kMaxDim * 32 || s[0] * s[1] >= kMaxDim * 8)
+      if (s[3] < 0 || s[3] >= kMaxDim) return "gemm_fp8: the row offset must be in [0, 2^31)";
+      if ((s[0] + s[3]) * s[2] >= kMaxDim * 32 || s[1] * s[2] >= kMaxDim * 32 ||
+          (s[0] + s[3]) * s[1] >= kMaxDim * 8)
         return "gemm_fp8: operand too large";
       if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
         return "gemm_fp8: needs in {A, Bt}, out {C}";
@@ -70,6 +72,17 @@ const char* validate_kernel(const ug_kernel& k, uint32_t nb) {
         return "vecadd: N >= 1, 1 <= W <= 65536, 0 <= R <= 65536 (0 = 1)";
       if (!slot_ok(k.in[0], nb) || !slot_ok(k.in[1], nb) || !slot_ok(k.out[0], nb))
         return "vecadd: needs in {A, B}, out {C}";
+      return nullptr;
+    case UG_OP_UPLOAD_H2D:
+      if (s[0] < 0 || s[0] >= kMaxDim || !pos(s[1]) || s[0] * s[1] >= kMaxDim * 32)
+        return "upload: shape {N >= 0, unit bytes >= 1}, at most 64 GiB";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.out[0], nb))
+        return "upload: needs in {host source}, out {device destination}";
+      return nullptr;
+    case UG_OP_ACCUM_I32:
+      if (s[0] < 0 || s[0] >= kMaxDim) return "accum_i32: N must be in [0, 2^31)";
+      if (!slot_ok(k.in[0], nb) || !slot_ok(k.out[0], nb))
+        return "accum_i32: needs in {x}, out {state}";
       return nullptr;
     case UG_OP_GEMM_BF16:
       if (!pos(s[0]) || !pos(s[1]) || !pos(s[2]) || s[2] >= kMaxDim / 2)
@@ -88,6 +101,76 @@ const char* validate_kernel(const ug_kernel& k, uint32_t nb) {
 size_t workspace_bytes(const ug_kernel& k) {
   if (k.op == UG_OP_VOXEL_F32) return voxel_f32_workspace(k.shape[0], (int)k.shape[1], (int)k.shape[2]);
   return 0;
+}
+
+namespace {
+int64_t isqrt(int64_t x) {
+  int64_t r = 0;
+  while ((r + 1) * (r + 1) <= x) ++r;
+  return r;
+}
+}  // namespace
+
+bool frame_range(const ug_kernel& k, int64_t* lo, int64_t* hi) {
+  const int64_t* s = k.shape;
+  int64_t smin = 1, smax = 0;
+  switch (k.op) {
+    case UG_OP_VOXEL_F32:
+    case UG_OP_UPLOAD_H2D:
+      smin = 0;
+      smax = s[0];
+      break;
+    case UG_OP_GEMM_F32:
+    case UG_OP_SOFTMAX_F32:
+      smax = s[0];
+      break;
+    case UG_OP_CONV3X3_F32:
+    case UG_OP_CONV3X3_BF16:
+      if (s[2] != s[3]) return false;   // square images
+      smax = s[2];
+      break;
+    case UG_OP_BIAS_RELU_F32:
+      smax = s[2] == 1 ? isqrt(s[1]) : s[0];
+      break;
+    case UG_OP_ROWSUM_F32:
+      smax = isqrt(s[1]);
+      break;
+    default:
+      return false;
+  }
+  if (k.frame_shift < 0 || k.frame_shift > 30 || smax < smin || smax < 1) return false;
+  *lo = smin << k.frame_shift;
+  *hi = (smax << k.frame_shift) | ((int64_t(1) << k.frame_shift) - 1);
+  return true;
+}
+
+ug_kernel frame_kernel(const ug_kernel& k, int64_t v) {
+  ug_kernel f = k;
+  const int64_t s = v >> k.frame_shift;
+  switch (k.op) {
+    case UG_OP_VOXEL_F32:
+    case UG_OP_UPLOAD_H2D:
+    case UG_OP_GEMM_F32:
+    case UG_OP_SOFTMAX_F32:
+      f.shape[0] = s;
+      break;
+    case UG_OP_CONV3X3_F32:
+    case UG_OP_CONV3X3_BF16:
+      f.shape[2] = f.shape[3] = s;
+      break;
+    case UG_OP_BIAS_RELU_F32:
+      if (k.shape[2] == 1)
+        f.shape[1] = s * s;   // per-channel bias over an image plane
+      else
+        f.shape[0] = s;       // per-column bias over s rows
+      break;
+    case UG_OP_ROWSUM_F32:
+      f.shape[1] = s * s;     // the row is an image plane
+      break;
+    default:
+      break;
+  }
+  return f;
 }
 
 hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, void* ws,
@@ -111,11 +194,14 @@ hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, voi
                               s[0], (int)s[1], (int)s[2], k.fparam[0], k.fparam[1], k.fparam[2],
                               ws, ws_bytes, st);
     case UG_OP_GEMM_FP8: {
-      const auto* a = static_cast<const unsigned char*>(b[k.in[0]]);
+      // rows [m0, m0 + M) of A and C (a row band: one sub-kernel of a split
+      // product); K is a multiple of 16, so the band of A stays aligned
+      const int64_t m0 = s[3];
+      const auto* a = static_cast<const unsigned char*>(b[k.in[0]]) + m0 * s[2];
       const auto* bt = static_cast<const unsigned char*>(b[k.in[1]]);
       if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(bt)) & 15)
         return hipErrorInvalidValue;
-      return gemm_fp8_launch(a, bt, F(k.out[0]), s[0], s[1], s[2], st);
+      return gemm_fp8_launch(a, bt, F(k.out[0]) + m0 * s[1], s[0], s[1], s[2], st);
     }
     case UG_OP_CONV3X3_BF16: {
       const auto* x = static_cast<const uint16_t*>(b[k.in[0]]);
@@ -127,6 +213,14 @@ hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, voi
     case UG_OP_VECADD_F32:
       return vecadd_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1],
                                s[2] > 0 ? s[2] : 1, st);
+    case UG_OP_UPLOAD_H2D:
+      // a per-frame input arriving from host memory (pinned by the caller)
+      if (s[0] == 0) return hipSuccess;
+      return hipMemcpyAsync(b[k.out[0]], b[k.in[0]], static_cast<size_t>(s[0] * s[1]),
+                            hipMemcpyHostToDevice, st);
+    case UG_OP_ACCUM_I32:
+      if (s[0] == 0) return hipSuccess;
+      return accum_i32_launch(I(k.in[0]), I(k.out[0]), s[0], st);
     case UG_OP_GEMM_BF16: {
       const auto* a = static_cast<const uint16_t*>(b[k.in[0]]);
       const auto* bt = static_cast<const uint16_t*>(b[k.in[1]]);
@@ -162,6 +256,8 @@ OpPlan plan_kernel(const ug_kernel& k) {
       return vecadd_f32_plan(s[0], s[1]);
     case UG_OP_CONV3X3_BF16:
       return conv3x3_bf16_plan(s[1], s[2], s[3]);
+    case UG_OP_ACCUM_I32:
+      return accum_i32_plan(s[0]);
     default:
       return OpPlan{};
   }

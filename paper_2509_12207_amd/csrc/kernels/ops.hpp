@@ -49,6 +49,9 @@ OpPlan conv3x3_bf16_plan(int64_t C, int64_t H, int64_t W);
 hipError_t conv3x3_bf16_launch(const uint16_t* X, const uint16_t* Wt, float* Y, int64_t C,
                                int64_t H, int64_t W, hipStream_t s);
 
+OpPlan accum_i32_plan(int64_t n);
+hipError_t accum_i32_launch(const int* x, int* st, int64_t n, hipStream_t s);
+
 OpPlan gemm_bf16_plan(int64_t M, int64_t N, int64_t K);
 hipError_t gemm_bf16_launch(const uint16_t* A, const uint16_t* Bt, float* C, int64_t M,
                             int64_t N, int64_t K, hipStream_t s);
@@ -67,6 +70,14 @@ constexpr size_t kStaticScratchBytes = size_t(UG_STATIC_SCRATCH_BYTES);
 // Device address of the static workspace on the current device (located on
 // the first call per device, then cached).  Allocates nothing.
 hipError_t static_scratch(void** ptr);
+
+// Per-frame sizes (ug_kernel.frame_dim > 0): the range [lo, hi] of the
+// frame's value v that kernel k accepts (false: the op takes no per-frame
+// size, or the registered shape cannot carry one), and the kernel's shape
+// for a frame with value v (s = v >> frame_shift sets the op's frame
+// dimension; see include/ug.h).
+bool frame_range(const ug_kernel& k, int64_t* lo, int64_t* hi);
+ug_kernel frame_kernel(const ug_kernel& k, int64_t v);
 
 // Checks a descriptor against n_buffers slots.  Returns nullptr if valid,
 // else a static message.

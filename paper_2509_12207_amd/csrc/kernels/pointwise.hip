@@ -439,4 +439,58 @@ hipError_t vecadd_f32_launch(const float* a, const float* b, float* c, int64_t n
   return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------ state += x
+// Device-resident chain state: s_i += x_i in int32 (two's-complement
+// wrap), four lanes' worth per vector access when both are 16-byte aligned.
+namespace {
+template <bool Vec>
+__global__ __launch_bounds__(256) void accum_i32_kernel(const int* __restrict__ x,
+                                                        int* __restrict__ st, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (Vec) {
+    const int64_t n4 = n / 4;
+    const int4* x4 = reinterpret_cast<const int4*>(x);
+    int4* s4 = reinterpret_cast<int4*>(st);
+    for (int64_t i = t; i < n4; i += stride) {
+      const int4 a = x4[i];
+      int4 b = s4[i];
+      b.x = (int)((unsigned)b.x + (unsigned)a.x);
+      b.y = (int)((unsigned)b.y + (unsigned)a.y);
+      b.z = (int)((unsigned)b.z + (unsigned)a.z);
+      b.w = (int)((unsigned)b.w + (unsigned)a.w);
+      s4[i] = b;
+    }
+    for (int64_t i = 4 * n4 + t; i < n; i += stride)
+      st[i] = (int)((unsigned)st[i] + (unsigned)x[i]);
+  } else {
+    for (int64_t i = t; i < n; i += stride) st[i] = (int)((unsigned)st[i] + (unsigned)x[i]);
+  }
+}
+
+unsigned accum_grid(int64_t n) {
+  int64_t g = (n / 4 + 255) / 256;
+  if (g > 2048) g = 2048;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+}  // namespace
+
+OpPlan accum_i32_plan(int64_t n) {
+  OpPlan p;
+  p.func = reinterpret_cast<const void*>(&accum_i32_kernel<true>);
+  p.grid = dim3(accum_grid(n));
+  p.block = dim3(256);
+  return p;
+}
+
+hipError_t accum_i32_launch(const int* x, int* st, int64_t n, hipStream_t s) {
+  const bool vec = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(st)) & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL(accum_i32_kernel<true>, dim3(accum_grid(n)), dim3(256), 0, s, x, st, n);
+  else
+    hipLaunchKernelGGL(accum_i32_kernel<false>, dim3(accum_grid(n)), dim3(256), 0, s, x, st, n);
+  return hipGetLastError();
+}
+
 }  // namespace ug

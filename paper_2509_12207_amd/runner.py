@@ -1,9 +1,10 @@
 """Drive a synthetic workload through libug on torch-allocated device memory.
 
-Torch provides device memory only; every kernel and every scheduling
-decision runs in libug.  Read-only inputs are uploaded once per chain;
-outputs come in ``n_sets`` copies and frame f of a chain writes copy
-f % n_sets.
+Torch provides device memory (and pinned host memory for per-frame
+inputs) only; every kernel, copy and scheduling decision runs in libug.
+Read-only inputs are uploaded once per chain; outputs and per-frame host
+inputs come in ``n_sets`` copies and frame f of a chain uses copy
+f % n_sets; device-resident chain state is one buffer per chain.
 """
 
 import time
@@ -26,28 +27,56 @@ class DeviceWorkload:
         self.wl = wl
         self.device = torch.device(device)
         self.n_sets = n_sets
-        self.inputs = []          # per chain: {slot: tensor}
-        self.outputs = []         # per chain: [ {slot: tensor} per set ]
+        self.inputs = []          # per chain: {slot: tensor} (read-only and state)
+        self.outputs = []         # per chain: [ {slot: tensor} per set ] (outputs, host inputs)
         self.ptrs = []            # per chain: [ [ptr per slot] per set ]
+        dts = {"f32": torch.float32, "i32": torch.int32, "u8": torch.uint8}
         for c, ch in enumerate(wl.chains):
             ins = {}
             for s, b in enumerate(ch.buffers):
                 if b.role == "in":
                     host = synth.input_array(wl.seed, c, s, b)
                     ins[s] = torch.from_numpy(host).to(self.device)
+                elif b.role == "state":
+                    ins[s] = torch.zeros(b.n, dtype=dts[b.kind], device=self.device)
             sets = []
             for _ in range(n_sets):
                 outs = {}
                 for s, b in enumerate(ch.buffers):
                     if b.role == "out":
-                        dt = {"f32": torch.float32, "i32": torch.int32,
-                              "u8": torch.uint8}[b.kind]
-                        outs[s] = torch.zeros(b.n, dtype=dt, device=self.device)
+                        outs[s] = torch.zeros(b.n, dtype=dts[b.kind], device=self.device)
+                    elif b.role == "host":
+                        outs[s] = torch.zeros(b.n, dtype=dts[b.kind], pin_memory=True)
                 sets.append(outs)
             self.inputs.append(ins)
             self.outputs.append(sets)
             self.ptrs.append([[int((ins.get(s) if s in ins else sets[k][s]).data_ptr())
                                for s in range(len(ch.buffers))] for k in range(n_sets)])
+        torch.cuda.synchronize(self.device)
+
+    def load_frame(self, c, f, dims=None):
+        """Write frame f's own host inputs into its buffer set (before it is
+        submitted; the set must not hold an unfinished frame)."""
+        ch = self.wl.chains[c]
+        k = f % self.n_sets
+        for s, b in enumerate(ch.buffers):
+            if b.role == "host":
+                n = dims[0] if dims else None
+                self.outputs[c][k][s].numpy()[:] = synth.frame_input(self.wl.seed, c, f, s, b, n)
+
+    def frame_host_input(self, c, f, slot, n=None):
+        return synth.frame_input(self.wl.seed, c, f, slot, self.wl.chains[c].buffers[slot], n)
+
+    def state(self, c, slot):
+        return self.inputs[c][slot].cpu().numpy()
+
+    def reset_state(self):
+        """Zero every chain's device-resident state."""
+        for c, ch in enumerate(self.wl.chains):
+            for s, b in enumerate(ch.buffers):
+                if b.role == "state":
+                    self.inputs[c][s].zero_()
+        import torch
         torch.cuda.synchronize(self.device)
 
     def host_input(self, c, slot):
@@ -57,10 +86,11 @@ class DeviceWorkload:
         return self.outputs[c][k][slot].cpu().numpy()
 
     def nbytes(self):
+        """Device bytes (pinned host inputs are not counted)."""
         tot = 0
         for ins, sets in zip(self.inputs, self.outputs):
             tot += sum(t.numel() * t.element_size() for t in ins.values())
-            tot += sum(t.numel() * t.element_size() for s in sets for t in s.values())
+            tot += sum(t.numel() * t.element_size() for s in sets for t in s.values() if t.is_cuda)
         return tot
 
 
@@ -77,12 +107,15 @@ def profile(g, dw, warmup=3, reps=10):
 
 
 def copy_estimates(src, dst, wl):
-    """Give ``dst`` the estimates profiled on ``src`` (same chains)."""
+    """Give ``dst`` the estimates (and per-frame profile points) profiled on
+    ``src`` (same chains)."""
     for c, ch in enumerate(wl.chains):
-        n = sum(len(t["kernels"]) for t in ch.tasks)
-        for k in range(n):
-            e, u = src.get_estimate(c, k)
-            dst.set_estimate(c, k, e, u)
+        ks = [k for t in ch.tasks for k in t["kernels"]]
+        for i, k in enumerate(ks):
+            e, u = src.get_estimate(c, i)
+            dst.set_estimate(c, i, e, u)
+            if k.get("frame_dim", 0):
+                dst.set_profile(c, i, src.get_profile(c, i))
 
 
 def estimates(g, wl):
@@ -91,6 +124,17 @@ def estimates(g, wl):
         n = sum(len(t["kernels"]) for t in ch.tasks)
         for k in range(n):
             out[(c, k)] = g.get_estimate(c, k)
+    return out
+
+
+def profiles(g, wl):
+    """Profile points of every kernel with a per-frame size."""
+    out = {}
+    for c, ch in enumerate(wl.chains):
+        ks = [k for t in ch.tasks for k in t["kernels"]]
+        for i, k in enumerate(ks):
+            if k.get("frame_dim", 0):
+                out[(c, i)] = g.get_profile(c, i)
     return out
 
 
@@ -127,6 +171,7 @@ def serve(g, dw, arrivals, dims=None, lead_ns=20_000_000, timeout_s=120.0):
                 keep.append((c, f, t))
                 continue
             d = None if dims is None else dims.get((c, f))
+            dw.load_frame(c, f, d)
             fid = g.submit(c, t0 + t, dw.ptrs[c][f % dw.n_sets], d)
             if fid is None:                  # over the HBM budget: retry later
                 deferred.add((c, f))

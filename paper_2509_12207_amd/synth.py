@@ -46,7 +46,11 @@ class Buffer:
     name: str
     kind: str        # "f32", "i32" or "u8" (FP8 E4M3 codes)
     n: int           # elements
-    role: str        # "in" (read-only, shared by every frame) or "out"
+    role: str        # "in" (read-only, shared by every frame), "out" (one
+    #                  copy per buffer set), "host" (pinned host memory, one
+    #                  copy per buffer set, filled with each frame's own data
+    #                  before it is submitted) or "state" (device memory
+    #                  shared by every frame, updated in frame order)
     init: tuple = ("uniform", -1.0, 1.0)   # for inputs: ("uniform", lo, hi) |
     #                                        ("points", sigma) | ("e4m3", e_lo, e_hi)
 
@@ -93,6 +97,18 @@ class Workload:
 # ----------------------------------------------------------------------------
 # input data
 # ----------------------------------------------------------------------------
+def frame_input(seed, chain, frame, slot, buf, n_valid=None):
+    """Deterministic host data of a per-frame input (role "host") for frame
+    ``frame``: a point cloud of ``n_valid`` points (the rest zero)."""
+    rng = np.random.default_rng([seed, chain, slot, frame, 8])
+    out = np.zeros(buf.n, np.float32)
+    n = buf.n // 4 if n_valid is None else n_valid
+    xyz = rng.normal(0.0, buf.init[1], (n, 3))
+    inten = rng.uniform(0.0, 1.0, (n, 1))
+    out[: 4 * n] = np.concatenate([xyz, inten], axis=1).astype(np.float32).reshape(-1)
+    return out
+
+
 def input_array(seed, chain, slot, buf):
     """Deterministic host data of an input buffer (float32 or int32)."""
     rng = np.random.default_rng([seed, chain, slot, 7])
@@ -140,8 +156,8 @@ def k_vecadd(N, W, R, a, b, c):
     return {"op": "vecadd", "shape": (N, W, R), "in": (a, b), "out": (c,)}
 
 
-def k_gemm_fp8(M, N, K, a, bt, c):
-    return {"op": "gemm_fp8", "shape": (M, N, K), "in": (a, bt), "out": (c,)}
+def k_gemm_fp8(M, N, K, a, bt, c, m0=0):
+    return {"op": "gemm_fp8", "shape": (M, N, K, m0), "in": (a, bt), "out": (c,)}
 
 
 def k_softmax(R, L, x, y):
@@ -214,6 +230,10 @@ def _model_ns(op, shape):
         # 58-75 GB/s per workgroup for 32..256 workgroups)
         N, W, R = shape
         return floor + 12 * N * max(R, 1) / (16e12 * min(W, 256) / 256) * 1e9
+    if op == "upload":        # host-to-device copy over PCIe
+        return 2 * floor + shape[0] * shape[1] / 25e9 * 1e9
+    if op == "accum_i32":
+        return floor + 12 * shape[0] / 4e12 * 1e9
     raise ValueError(op)
 
 
@@ -328,7 +348,11 @@ def _fit_scale(blocks, budget_ns):
     return lo
 
 
-def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales):
+def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales, serving=False):
+    """``serving``: voxel blocks take their points per frame (frame dim 1):
+    uploaded from pinned host memory by a gated copy, binned, and added to
+    the chain's device-resident cell counts; conv blocks with a
+    ``frame_shift`` take the frame's image size (frame dim 2)."""
     buffers, tasks, blocks = [], [], []
     for j, (tb, s) in enumerate(zip(task_blocks, scales)):
         shapes = [_shapes(b, s) for b in tb]
@@ -368,7 +392,12 @@ def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales):
             else:
                 n = shp[0]
                 G = VOXEL_GRID[0] * VOXEL_GRID[1]
-                want("pts", 4 * n, "in", ("points", 20.0))
+                if serving:
+                    want("pts_host", 4 * n, "host", ("points", 20.0))
+                    want("pts", 4 * n, "out")
+                    want("VSTATE", G, "state", kind="i32")
+                else:
+                    want("pts", 4 * n, "in", ("points", 20.0))
                 want("VI", n, "out", kind="i32")
                 want("VC", G, "out", kind="i32")
                 want("VZ", G, "out")
@@ -404,6 +433,11 @@ def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales):
                 if b["rowsum"]:
                     ks.append(k_rowsum(Cc, H * W, out, slot[f"t{j}.RS"]))
                     outs["RS"] = f"t{j}.RS"
+                if serving and "frame_shift" in b:
+                    # the frame's image size v sets H = W = v >> shift (and
+                    # the planes of the bias and the row sum)
+                    for k in ks[first:]:
+                        k["frame_dim"], k["frame_shift"] = 2, b["frame_shift"]
             elif b["kind"] == "vecadd":
                 n, w, rr = shp
                 for _ in range(b["count"]):
@@ -412,9 +446,21 @@ def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales):
                 outs = {"C": f"t{j}.VS"}
             else:
                 n = shp[0]
+                if serving:
+                    # the frame's points arrive from host memory (a gated
+                    # copy), then are binned; the counts are added to the
+                    # chain's device-resident state
+                    ks.append({"op": "upload", "shape": (n, 16), "in": (slot[f"t{j}.pts_host"],),
+                               "out": (slot[f"t{j}.pts"],), "frame_dim": 1})
                 ks.append(k_voxel(n, slot[f"t{j}.pts"], slot[f"t{j}.VI"], slot[f"t{j}.VC"],
                                   slot[f"t{j}.VZ"], slot[f"t{j}.VF"]))
                 outs = {"VI": f"t{j}.VI", "VC": f"t{j}.VC", "VZ": f"t{j}.VZ", "VF": f"t{j}.VF"}
+                if serving:
+                    ks[-1]["frame_dim"] = 1
+                    G = VOXEL_GRID[0] * VOXEL_GRID[1]
+                    ks.append({"op": "accum_i32", "shape": (G,), "in": (slot[f"t{j}.VC"],),
+                               "out": (slot[f"t{j}.VSTATE"],)})
+                    outs["STATE"] = f"t{j}.VSTATE"
             blocks.append(Block(b["kind"], j, list(range(first, len(ks))), shp, outs))
         tasks.append({"cpu_ns": 0, "kernels": ks})
         del base
@@ -487,7 +533,7 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
 
 
 def config4(seed=0, f_a=1.0, f_d=1.0, u_deadline=0.85, be_gemms=4, be_dim=8192, be_depth=2,
-            window_s=10.0, **kw):
+            window_s=10.0, be_chunks=1, **kw):
     """Overload: the eleven chains of configuration 1 at a base load of
     ``u_deadline`` plus one best-effort chain (deadline 0) whose frames are
     ``be_gemms`` back-to-back FP8 E4M3 products be_dim^3 with an FP32
@@ -495,31 +541,41 @@ def config4(seed=0, f_a=1.0, f_d=1.0, u_deadline=0.85, be_gemms=4, be_dim=8192, 
     frames are outstanding from the start, and each completion submits the
     next one until the window ends, so it takes all the GPU time the
     deadline chains leave (and, without gating, some they need).  Its frames
-    are not in ``arrivals``; ``meta`` names the chain and the depth."""
+    are not in ``arrivals``; ``meta`` names the chain and the depth.
+    ``be_chunks`` > 1 splits every product into that many row bands, each a
+    kernel of its own (a separate gated launch: a preemption point)."""
     wl = config1(seed=seed, f_a=f_a, f_d=f_d, u_target=u_deadline, window_s=window_s, **kw)
     d = be_dim
     bufs = [Buffer("A8", "u8", d * d, "in", ("e4m3", 4, 9)),
             Buffer("Bt8", "u8", d * d, "in", ("e4m3", 4, 9)),
             Buffer("C", "f32", d * d, "out")]
-    kernels = [k_gemm_fp8(d, d, d, 0, 1, 2) for _ in range(be_gemms)]
+    assert d % (256 * be_chunks) == 0, "row bands are whole 256-row tiles"
+    band = d // be_chunks
+    kernels = [k_gemm_fp8(band, d, d, 0, 1, 2, m0=i * band)
+               for _ in range(be_gemms) for i in range(be_chunks)]
     e_frame = int(be_gemms * _model_ns("gemm_fp8", (d, d, d)))
     be = ChainDef("be_fp8_gemm", e_frame, 0, [{"cpu_ns": 0, "kernels": kernels}], bufs, [])
     meta = dict(wl.meta, u_deadline=u_deadline, be_chain=len(wl.chains), be_depth=be_depth,
-                be_gemms=be_gemms, be_dim=d)
+                be_gemms=be_gemms, be_dim=d, be_chunks=be_chunks)
     return Workload("cfg4", wl.chains + [be], list(wl.arrivals), seed, meta)
 
 
 def config3(seed=0, n_chains=20, f_a=1.0, u_target=1.3, window_s=10.0, pts=(20_000, 150_000),
-            img=(256, 1024), rate_jitter=0.2):
+            img=(256, 1024), rate_jitter=0.2, img_typical=672):
     """Serving: ``n_chains`` chains (the rows of configuration 1, repeated),
-    built like configuration 1 with two per-frame / per-chain size draws:
+    built like configuration 1 with per-frame sizes:
 
-    * LiDAR chains take a different point count per frame, uniform in
-      ``pts``: their voxel kernels are registered at the maximum with
-      frame_dim = 1, and each frame passes its count as dims[0];
-    * camera chains process a per-chain image size (a power of two in
-      ``img``, square): each conv layer runs at that size / 2^(k+1) with
-      16 * 2^k channels, k in {0, 1, 2} (a stride-2 stem before the first).
+    * chains with a voxel scatter take a different point count per frame,
+      uniform in ``pts``, as dims[0]: each frame's points are written to
+      pinned host memory, uploaded by a gated copy, binned (kernels
+      registered at the maximum count), and the cell counts are added to the
+      chain's device-resident state;
+    * camera chains take a different image size per frame, a multiple of 32
+      uniform in ``img``, square, as dims[1]: each conv layer runs at that
+      size / 2^(k+1) with 16 * 2^k channels, k in {0, 1, 2} (a stride-2
+      stem before the first), registered at the largest size; the task
+      budgets are fitted at ``img_typical`` (about the root mean square of
+      the size distribution).
 
     Arrivals are a Poisson process per chain: exponential gaps of mean
     P_c' = P_c * U(1 - rate_jitter, 1 + rate_jitter) / f_a (the rate of each
@@ -531,14 +587,12 @@ def config3(seed=0, n_chains=20, f_a=1.0, u_target=1.3, window_s=10.0, pts=(20_0
     lam = u_target / sum(e / p for _, _, p, e in rows)
     n_tight = int(round(0.4 * n_chains))
     tight = set(rng.permutation(n_chains)[:n_tight].tolist())
-    lo_i, hi_i = int(math.log2(img[0])), int(math.log2(img[1]))
     chains, frame_dims = [], []
     for ci, (name, modality, period_ms, egpu) in enumerate(rows):
         crng = np.random.default_rng([seed, 32, ci])
         e_chain = lam * egpu * MS
         n_tasks = int(crng.integers(2, 5))
         split = crng.dirichlet(np.full(n_tasks, 2.0))
-        size = 2 ** int(crng.integers(lo_i, hi_i + 1))
         task_blocks, scales = [], []
         for j in range(n_tasks):
             budget = e_chain * split[j]
@@ -548,20 +602,19 @@ def config3(seed=0, n_chains=20, f_a=1.0, u_target=1.3, window_s=10.0, pts=(20_0
                     b["n_points"] = pts[1]
                 elif b["kind"] == "conv" and modality == "camera":
                     k = int(crng.integers(0, 3))
-                    b["img"] = max(size >> (k + 1), 8)
+                    b["img"] = img_typical >> (k + 1)
                     b["ch"] = 16 << k
+                    b["frame_shift"] = k + 1
             task_blocks.append(tb)
             scales.append(_fit_scale(tb, budget))
+            for b in tb:
+                if "frame_shift" in b:
+                    b["img"] = img[1] >> b["frame_shift"]    # registered at the largest
         period = period_ms * MS
         deadline = int(period * (0.5 if ci in tight else 1.0))
-        ch = _build_chain(f"s{ci}_{name}", modality, period, deadline, task_blocks, scales)
-        var = False
-        for t in ch.tasks:
-            for k in t["kernels"]:
-                if k["op"] == "voxel":
-                    k["frame_dim"] = 1
-                    var = True
-        if var:
+        ch = _build_chain(f"s{ci}_{name}", modality, period, deadline, task_blocks, scales,
+                          serving=True)
+        if any(k.get("frame_dim", 0) for t in ch.tasks for k in t["kernels"]):
             frame_dims.append(ci)
         chains.append(ch)
     arr, dims = [], {}
@@ -570,10 +623,15 @@ def config3(seed=0, n_chains=20, f_a=1.0, u_target=1.3, window_s=10.0, pts=(20_0
     for ci, ch in enumerate(chains):
         mean = ch.period_ns * arng.uniform(1 - rate_jitter, 1 + rate_jitter) / f_a
         t, f = arng.exponential(mean), 0
+        has_pts = any(k["op"] == "voxel" for t_ in ch.tasks for k in t_["kernels"])
+        has_img = any(k["op"] == "conv3x3" and k.get("frame_dim", 0) == 2
+                      for t_ in ch.tasks for k in t_["kernels"])
         while t < window:
             arr.append((ci, f, int(t)))
             if ci in frame_dims:
-                dims[(ci, f)] = [int(arng.integers(pts[0], pts[1] + 1))]
+                n = int(arng.integers(pts[0], pts[1] + 1)) if has_pts else 0
+                v = 32 * int(arng.integers(img[0] // 32, img[1] // 32 + 1)) if has_img else 0
+                dims[(ci, f)] = [n, v]
             f += 1
             t += arng.exponential(mean)
     arr.sort(key=lambda a: (a[2], a[0], a[1]))
@@ -595,7 +653,8 @@ def model_utilisation(wl, f_a=1.0):
         t = 0.0
         for task in ch.tasks:
             for k in task["kernels"]:
-                dims = {"conv3x3": 4, "gemm": 3, "gemm_fp8": 3, "voxel": 1, "vecadd": 3}.get(k["op"], 2)
+                dims = {"conv3x3": 4, "gemm": 3, "gemm_fp8": 3, "voxel": 1, "vecadd": 3,
+                        "accum_i32": 1}.get(k["op"], 2)
                 t += _model_ns(k["op"], tuple(k["shape"][:dims]))
         u += t / (ch.period_ns / f_a)
     return u

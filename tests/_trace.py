@@ -30,11 +30,17 @@ def record_to_tuple(r):
 
 
 def inputs_to_records(arrivals, evdones):
-    recs = np.zeros(len(arrivals) + len(evdones), capi.RECORD_DTYPE)
+    n_dims = sum(len(a[3]) for a in arrivals if len(a) > 3)
+    recs = np.zeros(len(arrivals) + n_dims + len(evdones), capi.RECORD_DTYPE)
     i = 0
-    for c, f, t_arr in arrivals:
+    for a in arrivals:
+        c, f, t_arr = a[:3]
         recs[i]["type"], recs[i]["chain"], recs[i]["frame"], recs[i]["t"] = capi.REC_ARRIVE, c, f, t_arr
         i += 1
+        for d, v in enumerate(a[3] if len(a) > 3 else ()):
+            r = recs[i]
+            r["type"], r["chain"], r["frame"], r["a"], r["t"] = capi.REC_DIMS, c, f, d, v
+            i += 1
     for c, f, j, kind, seq in evdones:
         r = recs[i]
         r["type"], r["chain"], r["frame"], r["task"], r["a"], r["b"] = capi.REC_EVDONE, c, f, j, kind, seq
@@ -54,6 +60,11 @@ def instants_from_trace(recs):
             cur = (int(r["t"]), [], [], [])
         elif t == capi.REC_ARRIVE:
             cur[1].append((int(r["chain"]), int(r["frame"]), int(r["t"])))
+        elif t == capi.REC_DIMS:
+            c, f, t_arr = cur[1][-1][:3]
+            assert (c, f) == (int(r["chain"]), int(r["frame"]))
+            dims = cur[1][-1][3] if len(cur[1][-1]) > 3 else ()
+            cur[1][-1] = (c, f, t_arr, dims + (int(r["t"]),))
         elif t == capi.REC_EVDONE:
             cur[2].append((int(r["chain"]), int(r["frame"]), int(r["task"]), int(r["a"]), int(r["b"])))
         else:
@@ -63,23 +74,28 @@ def instants_from_trace(recs):
     return out
 
 
-def oracle_chains(wl_or_chains, estimates=None):
+def oracle_chains(wl_or_chains, estimates=None, profiles=None):
     """Plain-data chain descriptions for the oracle from synth ChainDefs.
 
     ``estimates``: optional {(chain, kernel): (est_ns, util)} as read back
-    from the library (the policy sees the same numbers on both sides)."""
+    from the library (the policy sees the same numbers on both sides).
+    ``profiles``: optional {(chain, kernel): [(v, E), ...]} profile points of
+    kernels with a per-frame size, as read back from the library."""
     chains = wl_or_chains.chains if hasattr(wl_or_chains, "chains") else wl_or_chains
     out = []
     for c, ch in enumerate(chains):
         tasks = []
         g = 0
         for task in ch.tasks:
-            est, util = [], []
+            est, util, fdim, prof = [], [], [], []
             for k in task["kernels"]:
                 e, u = estimates[(c, g)] if estimates else (k.get("est_ns", 0), k.get("util", 1.0))
                 est.append(e)
                 util.append(u)
+                fdim.append(int(k.get("frame_dim", 0)))
+                prof.append((profiles or {}).get((c, g)) or None)
                 g += 1
-            tasks.append({"cpu_ns": task.get("cpu_ns", 0), "est_ns": est, "util": util})
+            tasks.append({"cpu_ns": task.get("cpu_ns", 0), "est_ns": est, "util": util,
+                          "frame_dim": fdim, "prof": prof})
         out.append({"deadline_ns": ch.deadline_ns, "tasks": tasks})
     return out

@@ -7,10 +7,10 @@
 //   cfg <policy> <bind> <delay> <batch> <calibrate> <delta> <poll> <th> <exempt>
 //       <calib_period> <admit> <admit_tasks> <exit> <no_overlap> <graph> <key>
 //       <noise_permille> <noise_seed> <max_hold> <nlevels> <lanes...>
-//   chain <deadline> <ntasks>        (deadline 0: a best-effort chain)
-//     task <cpu_ns> <nkernels> (<est_ns> <util>)*
+//   chain <deadline> <period> <ntasks>   (deadline 0: a best-effort chain)
+//     task <cpu_ns> <nkernels> (<est_ns> <util> <frame_dim> <npts> (<v> <e>)*)*
 //   instant <t> <narr> <nev>
-//     a <chain> <frame> <t_arr>
+//     a <chain> <frame> <t_arr> <ndims> <dims...>
 //     e <chain> <frame> <task> <kind> <seq>
 // output: per instant "instant <t> <ndecisions>" then one line per record:
 //   <type> <chain> <frame> <task> <kernel> <a> <b> <t>
@@ -53,10 +53,15 @@ int main() {
         for (int k = 0; k < nk; ++k) {
           int64_t e;
           float u;
-          std::cin >> e >> u;
+          int fd, np;
+          std::cin >> e >> u >> fd >> np;
           ch.est.push_back(e);
           ch.util.push_back(u);
           ch.kernels.push_back(ug_kernel{});
+          ch.fdim.push_back(fd);
+          std::vector<std::pair<int64_t, int64_t>> pts(np);
+          for (auto& p : pts) std::cin >> p.first >> p.second;
+          ch.prof.push_back(pts);
         }
         ch.task_end.push_back(static_cast<int32_t>(ch.est.size()));
         ch.cpu.push_back(cpu);
@@ -72,7 +77,12 @@ int main() {
       std::cin >> t >> na >> ne;
       std::vector<ug::Arrival> arr(na);
       std::vector<ug::EvDone> ev(ne);
-      for (auto& a : arr) std::cin >> tok >> a.c >> a.f >> a.t_arr;
+      for (auto& a : arr) {
+        int nd;
+        std::cin >> tok >> a.c >> a.f >> a.t_arr >> nd;
+        a.dims.resize(nd);
+        for (auto& d : a.dims) std::cin >> d;
+      }
       for (auto& e : ev) std::cin >> tok >> e.c >> e.f >> e.task >> e.kind >> e.seq;
       out.clear();
       const char* err = nullptr;

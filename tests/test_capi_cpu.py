@@ -168,14 +168,50 @@ def _random_workload(r, n_chains, n_frames):
     return chains, arrivals
 
 
-def _register(g, chains):
+SHIFT = 10      # sized kernels are registered as 4 x 4 row sums of planes: s = v >> 10 <= 2
+
+
+def _sized_variant(r, chains, arrivals):
+    """Per-frame sizes: in about half of the chains about half of the kernels
+    take the frame's size v in [1024, 3071] and have two or three profile
+    points there; every frame draws its v."""
+    out = []
     for ch in chains:
+        ch = dict(ch, tasks=[dict(t) for t in ch["tasks"]])
+        sized = r.random() < 0.5
+        for t in ch["tasks"]:
+            nk = len(t["est_ns"])
+            t["frame_dim"], t["prof"] = [], []
+            for _ in range(nk):
+                if sized and r.random() < 0.5:
+                    vs = sorted(r.choice(np.arange(1024, 3072), int(r.integers(2, 4)), replace=False))
+                    t["frame_dim"].append(1)
+                    t["prof"].append([(int(v), int(r.integers(20, 600)) * US) for v in vs])
+                else:
+                    t["frame_dim"].append(0)
+                    t["prof"].append(None)
+        out.append(ch)
+    arr = [(c, f, t, (int(r.integers(1024, 3072)),)) for c, f, t in arrivals]
+    return out, arr
+
+
+def _register(g, chains):
+    for c, ch in enumerate(chains):
         tasks = []
         for t in ch["tasks"]:
+            nk = len(t["est_ns"])
+            fds = t.get("frame_dim", [0] * nk)
             ks = [{"op": "rowsum", "shape": (4, 4), "in": (0,), "out": (1,), "est_ns": e,
-                   "util": u} for e, u in zip(t["est_ns"], t["util"])]
+                   "util": u, "frame_dim": fd, "frame_shift": SHIFT if fd else 0}
+                  for e, u, fd in zip(t["est_ns"], t["util"], fds)]
             tasks.append({"cpu_ns": t["cpu_ns"], "kernels": ks})
         g.register_chain(ch.get("period_ns", 0), ch["deadline_ns"], tasks, 2)
+        g_idx = 0
+        for t in ch["tasks"]:
+            for pts in t.get("prof", [None] * len(t["est_ns"])):
+                if pts:
+                    g.set_profile(c, g_idx, pts)
+                g_idx += 1
 
 
 def _flags(cfg):
@@ -234,10 +270,13 @@ CFGS = [
 ]
 
 
+@pytest.mark.parametrize("sized", [False, True])
 @pytest.mark.parametrize("seed", range(8))
-def test_cpp_policy_replays_oracle_decisions(seed):
+def test_cpp_policy_replays_oracle_decisions(seed, sized):
     r = np.random.default_rng(500 + seed)
     chains, arrivals = _random_workload(r, int(r.integers(2, 6)), int(r.integers(2, 6)))
+    if sized:
+        chains, arrivals = _sized_variant(r, chains, arrivals)
     noise = {}
 
     def dur(c, f, g):
@@ -246,7 +285,7 @@ def test_cpp_policy_replays_oracle_decisions(seed):
             noise[(c, f, g)] = max(1, int(est[g] * r.uniform(0.5, 1.6)))
         return noise[(c, f, g)]
 
-    for cfg in CFGS:
+    for cfg in (CFGS[::3] if sized else CFGS):
         res = des.simulate(chains, cfg, arrivals, dur)
         g = _gate_for(cfg)
         _register(g, chains)

@@ -1,8 +1,11 @@
 """Serving form on the GPU, through the C-ABI: per-frame kernel sizes
 (ug_frame_submit_dims) against the oracle, admission against an HBM budget
-(UG_EAGAIN, deferral and peak counters), and a short window of the serving
-workload (20 chains, Poisson arrivals, per-frame point counts, a tight
-budget) whose decision log replays through the oracle gate model."""
+(UG_EAGAIN, deferral and peak counters), and windows of the serving workload
+(20 chains, Poisson arrivals, per-frame point counts and image sizes, gated
+uploads of each frame's points from pinned host memory, device-resident
+chain state): decision logs replay through the oracle gate model, every
+frame's outputs match the oracle, the state is the sum over the frames, and
+frames give bit-identical outputs alone and in the mix."""
 
 import numpy as np
 import pytest
@@ -105,6 +108,7 @@ def test_serving_window_tight_budget_and_replay():
         g.set_footprint(c, fp)
     runner.profile(g, dw, warmup=1, reps=2)
     est = runner.estimates(g, wl)
+    profs = runner.profiles(g, wl)
     g.start()
     comps, _, deferred = runner.serve(g, dw, wl.arrivals, wl.meta["dims"], timeout_s=120.0)
     g.drain(60.0)
@@ -116,6 +120,169 @@ def test_serving_window_tight_budget_and_replay():
     assert st["hbm_peak_bytes"] <= budget
     assert deferred > 0 and st["frames_deferred"] >= deferred
     inst = T.instants_from_trace(trace)
-    chains = T.oracle_chains(wl, est)
+    chains = T.oracle_chains(wl, est, profs)
     cfg = {"policy": "urgency", "th_slack_ns": 3 * MS}
     assert des.replay(chains, cfg, inst) is None
+
+
+# ----------------------------------------------------------------------------
+def _last_writers(ch):
+    last = {}
+    for b in ch.blocks:
+        for role, name in b.outputs.items():
+            last[name] = (b, role)
+    return last
+
+
+def _frame_outputs(wl, dw, c, f):
+    """Every output buffer of frame f of chain c (its buffer set), copied."""
+    k = f % dw.n_sets
+    return {s: dw.output(c, s, k).copy() for s, b in enumerate(wl.chains[c].buffers)
+            if b.role == "out"}
+
+
+def check_cfg3_frame(wl, dw, c, f, dims, samples=4, seed=0):
+    """Outputs of frame f of chain c at its own sizes against the oracle:
+    voxel outputs bit-exact on the frame's uploaded points, sampled conv
+    outputs at the frame's image size (and the plane row sums), sampled
+    dense outputs.  Returns the kinds of blocks checked."""
+    ch = wl.chains[c]
+    r = np.random.default_rng([seed, c, f])
+    slot = {b.name: i for i, b in enumerate(ch.buffers)}
+    k = f % dw.n_sets
+    kinds = set()
+    for name, (blk, role) in _last_writers(ch).items():
+        j = blk.task
+        if role == "STATE":
+            continue
+        got = dw.output(c, slot[name], k)
+        if blk.kind == "voxel":
+            n = dims[0]
+            P = dw.frame_host_input(c, f, slot[f"t{j}.pts_host"], n)[: 4 * n].reshape(n, 4)
+            want = OK.voxel_scatter(P)
+            w = np.asarray(want[{"VI": 0, "VC": 1, "VZ": 2, "VF": 3}[role]])
+            assert np.array_equal(got[: len(w)].view(np.uint32), w.view(np.uint32)), (ch.name, f, name)
+            kinds.add("voxel")
+        elif blk.kind == "conv":
+            shift = next(kk.get("frame_shift", 0) for kk in
+                         (ch.tasks[j]["kernels"][i] for i in blk.kernels))
+            _, Cc, H, _ = blk.shape
+            s = dims[1] >> shift if shift else H
+            X = dw.host_input(c, slot[f"t{j}.in_x"])[: Cc * s * s].reshape(1, Cc, s, s)
+            Wt = dw.host_input(c, slot[f"t{j}.in_w"])[: Cc * Cc * 9].reshape(Cc, Cc, 3, 3)
+            bias = dw.host_input(c, slot[f"t{j}.bias_row"])[:Cc]
+            if role == "Y":
+                for o, y, x in zip(r.integers(0, Cc, samples), r.integers(0, s, samples),
+                                   r.integers(0, s, samples)):
+                    v, sc = OK.conv3x3_entry_f64(X, Wt, 0, o, y, x)
+                    want = max(np.float32(v) + bias[o], 0)
+                    assert abs(got[(o * s + y) * s + x] - want) <= 1e-5 * (sc + abs(bias[o])), \
+                        (ch.name, f, name, s)
+            elif role == "RS":
+                o = int(r.integers(0, Cc))
+                full = OK.conv3x3_f64(X, Wt[o:o + 1])[0, 0]
+                plane = np.maximum(full + bias[o], 0).reshape(-1)
+                sc = (OK.conv3x3_abs_f64(X, Wt[o:o + 1])[0, 0] + abs(bias[o])).reshape(-1)
+                assert abs(got[o] - plane.sum()) <= 1e-5 * sc.sum(), (ch.name, f, name, s)
+            kinds.add("conv")
+        elif blk.kind == "dense" and role == "C":
+            M, N, K = blk.shape
+            A = dw.host_input(c, slot[f"t{j}.in_a"])[: M * K].reshape(M, K)
+            B = dw.host_input(c, slot[f"t{j}.in_b"])[: K * N].reshape(K, N)
+            bias = dw.host_input(c, slot[f"t{j}.bias_col"])[:N]
+            m = int(r.integers(0, M))
+            row = A[m].astype(np.float64) @ B.astype(np.float64)
+            sc = np.abs(A[m]).astype(np.float64) @ np.abs(B).astype(np.float64) + np.abs(bias)
+            want = OK.bias_relu_f32(row.astype(np.float32)[None, :], bias, 0)[0]
+            assert np.all(np.abs(got[m * N:(m + 1) * N] - want) <= 1e-5 * sc), (ch.name, f, name)
+            kinds.add("dense")
+    return kinds
+
+
+def _frames_per_chain(wl):
+    return max(sum(1 for c, _, _ in wl.arrivals if c == ci) for ci in range(len(wl.chains)))
+
+
+def _serve(wl, dw, arrivals, est=None, profs=None, **cfg):
+    g = runner.make_gate(wl, "urgency", trace_capacity=1 << 22, th_slack_ns=3 * MS,
+                         queue_capacity=1 << 14, **cfg)
+    if est is None:
+        runner.profile(g, dw, warmup=1, reps=2)
+    else:
+        for (c, k), (e, u) in est.items():
+            g.set_estimate(c, k, e, u)
+        for (c, k), pts in profs.items():
+            g.set_profile(c, k, pts)
+    est, profs = runner.estimates(g, wl), runner.profiles(g, wl)
+    dw.reset_state()
+    g.start()
+    comps, _, _ = runner.serve(g, dw, arrivals, wl.meta["dims"], timeout_s=120.0)
+    g.drain(60.0)
+    g.stop()
+    trace = g.trace()
+    g.close()
+    return comps, trace, est, profs
+
+
+def test_cfg3_window_every_frame_state_and_replay():
+    # each frame its own buffer set: every frame's outputs are checked at
+    # its own point count / image size; the device-resident state of every
+    # chain with a point cloud is the sum of its frames' cell counts; the
+    # log (with the frames' sizes) replays through the oracle gate model,
+    # whose estimates follow each frame's size
+    wl = synth.config3(seed=2, window_s=0.25)
+    dims = wl.meta["dims"]
+    dw = runner.DeviceWorkload(wl, n_sets=_frames_per_chain(wl))
+    comps, trace, est, profs = _serve(wl, dw, wl.arrivals)
+    assert len(comps) == len(wl.arrivals)
+    assert any(p for p in profs.values())
+    kinds = set()
+    for c, f, _ in wl.arrivals:
+        kinds |= check_cfg3_frame(wl, dw, c, f, dims.get((c, f), [0, 0]), samples=2)
+    assert kinds == {"voxel", "conv", "dense"}
+    n_state = 0
+    for c, ch in enumerate(wl.chains):
+        for s, b in enumerate(ch.buffers):
+            if b.role != "state":
+                continue
+            vc = ch.slot(b.name.replace("VSTATE", "VC"))
+            want = np.zeros(b.n, np.int64)
+            for cc, f, _ in wl.arrivals:
+                if cc == c:
+                    want += dw.output(c, vc, f % dw.n_sets)
+            assert np.array_equal(dw.state(c, s).astype(np.int64), want), ch.name
+            n_state += 1
+    assert n_state >= 2
+    inst = T.instants_from_trace(trace)
+    assert any(len(a) > 3 for i in inst for a in i[1])       # sizes are in the log
+    chains = T.oracle_chains(wl, est, profs)
+    assert des.replay(chains, {"policy": "urgency", "th_slack_ns": 3 * MS}, inst) is None
+
+
+def test_cfg3_frames_alone_and_in_the_mix_bit_identical():
+    # a frame of each of a few chains (point clouds and camera images, of
+    # their own sizes) alone on the GPU, then the whole window together:
+    # every output of those frames is bit-identical
+    wl = synth.config3(seed=3, window_s=0.2)
+    dw = runner.DeviceWorkload(wl, n_sets=_frames_per_chain(wl))
+    lidar = [c for c in wl.meta["frame_dims"] if wl.meta["dims"][(c, 0)][0] > 0][:2]
+    cams = [c for c in wl.meta["frame_dims"] if wl.meta["dims"][(c, 0)][1] > 0][:2]
+    picks = [(c, 0) for c in lidar + cams]
+    assert len(picks) == 4
+    est = profs = None
+    alone = {}
+    for c, f in picks:
+        _, _, est, profs = _serve(wl, dw, [(c, f, 0)], est, profs)
+        alone[(c, f)] = _frame_outputs(wl, dw, c, f)
+    for s in dw.outputs:
+        for outs in s:
+            for t in outs.values():
+                t.zero_()
+    torch.cuda.synchronize()
+    comps, _, _, _ = _serve(wl, dw, wl.arrivals, est, profs)
+    assert len(comps) == len(wl.arrivals)
+    for (c, f), ref in alone.items():
+        mix = _frame_outputs(wl, dw, c, f)
+        for s, a in ref.items():
+            assert np.array_equal(a.view(np.uint8), mix[s].view(np.uint8)), \
+                (wl.chains[c].name, wl.chains[c].buffers[s].name)

@@ -776,3 +776,94 @@ def test_hold_age_restarts_with_every_task():
     assert holds == [(0, 0), (1 * MS, 0), (2 * MS, 0),
                      (2 * MS + 600 * US, 1), (3 * MS + 600 * US, 1), (4 * MS + 600 * US, 1)]
     assert launch == {0: int(2.5 * MS), 1: 5 * MS + 100 * US}
+
+
+# ------------------------------------------------------------------ split best-effort work
+@pytest.mark.parametrize("chunks", [1, 4])
+def test_split_best_effort_product_gives_way_between_chunks(chunks):
+    # a best-effort task of 1.2 ms of work, as one kernel or as four 0.3 ms
+    # row bands; each best-effort kernel is a batch of its own.  A (D 4 ms,
+    # one 1 ms kernel) arrives at 0.45 ms truly urgent.  Split: bands 0-2
+    # are out (band b + 1 goes when band b starts), band 3 is held at 0.6 ms
+    # and released at the 2.6 ms wake, so A runs 0.9-1.9 ms.  Whole: A waits
+    # for the whole product, 1.2-2.2 ms.
+    be = chain(0, [(0, [(1200 * US // chunks, 1.0)] * chunks)])
+    ch = [chain(4 * MS, [(0, [(1 * MS, 1.0)])]), be]
+    cfg = {"policy": "urgency", "th_slack_ns": 4 * MS}
+    res = des.simulate(ch, cfg, [(1, 0, 0), (0, 0, 450 * US)], by_est(ch))
+    done = {c: td for c, f, _, td in res["completed"]}
+    holds = [(t, d[1], d[3]) for t, _, _, ds in res["instants"] for d in ds if d[0] == "HOLD"]
+    if chunks == 4:
+        assert holds == [(600 * US, 1, 3), (1600 * US, 1, 3)]
+        assert done == {0: 1900 * US, 1: 2900 * US}
+        evs = [d for _, _, _, ds in res["instants"] for d in ds if d[0] == "EVREC" and d[1] == 1]
+        assert [e[5] for e in evs if e[4] == START] == [0, 1, 2, 3]
+    else:
+        assert holds == [] and done == {0: 2200 * US, 1: 1200 * US}
+    des.check_log(ch, cfg, res["instants"])
+
+
+# ------------------------------------------------------------------ per-frame estimates
+def test_profile_estimate_is_the_piecewise_linear_lookup():
+    # against numpy's piecewise-linear interpolation (which also clamps to
+    # the end values), rounded down; and exactly linear data stays linear
+    import math
+    pts = [(1000, 100_000), (2000, 300_000), (4000, 500_000), (8000, 2_000_000)]
+    vs, es = [p[0] for p in pts], [p[1] for p in pts]
+    for v in [0, 1, 999, 1000, 1001, 1500, 1999, 2000, 2001, 3333, 4000, 7999, 8000, 10 ** 6]:
+        want = math.floor(float(np.interp(v, vs, es)) + 1e-6)
+        assert P.profile_estimate(pts, v) == want, v
+    lin = [(v, 7 * v + 1000) for v in (16, 48, 256)]
+    for v in range(16, 257, 5):
+        assert P.profile_estimate(lin, v) == 7 * v + 1000
+    # a falling segment (noisy profiles) rounds down too
+    assert P.profile_estimate([(10, 50), (30, 40)], 13) == 48
+    assert P.profile_estimate([(5, 9)], 1) == P.profile_estimate([(5, 9)], 99) == 9
+
+
+def _sized_chain(deadline, pts):
+    return {"deadline_ns": deadline,
+            "tasks": [{"cpu_ns": 0, "est_ns": [pts[-1][1]], "util": [1.0],
+                       "frame_dim": [1], "prof": [pts]}]}
+
+
+def test_frames_of_different_size_rank_by_their_own_estimates():
+    # two chains, same deadline (10 ms), one sized kernel each, profiled at
+    # 1000 -> 1 ms and 4000 -> 4 ms.  Chain 0's frame has 1000 points (slack
+    # 9 ms), chain 1's 4000 (slack 6 ms): chain 1 is the more urgent and is
+    # served first.  With the fixed (largest) estimate both slacks are 6 ms
+    # and the tie goes to chain 0.
+    pts = [(1000, 1 * MS), (4000, 4 * MS)]
+    ch = [_sized_chain(10 * MS, pts), _sized_chain(10 * MS, pts)]
+    cfg = {"policy": "urgency", "th_slack_ns": 0, "admit": False}
+    g = GateModel(ch, cfg)
+    dec = g.instant(0, [(0, 0, 0, (1000,)), (1, 0, 0, (4000,))], [])
+    assert g.last_snapshot == {(0, 0): 9 * MS, (1, 0): 6 * MS}
+    assert [d[1] for d in dec if d[0] == "LAUNCH"] == [1, 0]
+    fixed = [dict(c, tasks=[dict(c["tasks"][0], prof=[None])]) for c in ch]
+    g = GateModel(fixed, cfg)
+    dec = g.instant(0, [(0, 0, 0, (1000,)), (1, 0, 0, (4000,))], [])
+    assert g.last_snapshot == {(0, 0): 6 * MS, (1, 0): 6 * MS}
+    assert [d[1] for d in dec if d[0] == "LAUNCH"] == [0, 1]
+    # a frame between profile points: 2500 -> 2.5 ms, slack 7.5 ms
+    g = GateModel(ch, cfg)
+    g.instant(0, [(0, 0, 0, (2500,))], [])
+    assert g.last_snapshot == {(0, 0): int(7.5 * MS)}
+
+
+def test_frame_estimates_set_the_batches():
+    # a task of a sized kernel then a fixed 300 us one, Delta_eval 0.5 ms: a
+    # small frame (100 us) batches both together, a large one (800 us)
+    # closes the first batch at the sized kernel
+    pts = [(100, 100 * US), (800, 800 * US)]
+    ch = [{"deadline_ns": 50 * MS,
+           "tasks": [{"cpu_ns": 0, "est_ns": [800 * US, 300 * US], "util": [1.0, 1.0],
+                      "frame_dim": [1, 0], "prof": [pts, None]}]}]
+    cfg = {"policy": "urgency", "delta_eval_ns": 500 * US}
+    for size, n_batches in ((100, 1), (800, 2)):
+        res = des.simulate(ch, cfg, [(0, 0, 0, (size,))],
+                           lambda c, f, g: (size * US if g == 0 else 300 * US))
+        starts = [d for _, _, _, ds in res["instants"] for d in ds if d[0] == "EVREC" and d[4] == START]
+        assert len(starts) == n_batches
+        des.check_log(ch, cfg, res["instants"])
+        assert des.replay(ch, cfg, res["instants"]) is None

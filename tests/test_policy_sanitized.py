@@ -69,17 +69,25 @@ def _encode(chains, cfg, instants):
     for ch in chains:
         lines.append(f"chain {ch['deadline_ns']} {ch.get('period_ns', 0)} {len(ch['tasks'])}")
         for t in ch["tasks"]:
-            ks = " ".join(f"{e} {u!r}" for e, u in zip(t["est_ns"], t["util"]))
-            lines.append(f"task {t['cpu_ns']} {len(t['est_ns'])} {ks}")
+            nk = len(t["est_ns"])
+            ks = []
+            for e, u, fd, pts in zip(t["est_ns"], t["util"], t.get("frame_dim", [0] * nk),
+                                     t.get("prof", [None] * nk)):
+                pts = pts or []
+                ks.append(f"{e} {u!r} {fd} {len(pts)} " + " ".join(f"{v} {x}" for v, x in pts))
+            lines.append(f"task {t['cpu_ns']} {nk} {' '.join(ks)}")
     for t, arr, evs, _ in instants:
         lines.append(f"instant {t} {len(arr)} {len(evs)}")
-        lines += [f"a {a} {b} {c_}" for a, b, c_ in arr]
+        for a in arr:
+            dims = a[3] if len(a) > 3 else ()
+            lines.append(f"a {a[0]} {a[1]} {a[2]} {len(dims)} " + " ".join(map(str, dims)))
         lines += [f"e {a} {b} {j} {k} {s}" for a, b, j, k, s in evs]
     return "\n".join(lines) + "\n"
 
 
+@pytest.mark.parametrize("sized", [False, True])
 @pytest.mark.parametrize("seed", range(4))
-def test_sanitized_policy_matches_oracle(driver, seed):
+def test_sanitized_policy_matches_oracle(driver, seed, sized):
     r = np.random.default_rng(900 + seed)
     chains, arrivals = [], []
     for ci in range(int(r.integers(2, 6))):
@@ -96,6 +104,17 @@ def test_sanitized_policy_matches_oracle(driver, seed):
         phase = int(r.integers(0, period))
         for f in range(int(r.integers(2, 6))):
             arrivals.append((ci, f, phase + f * period + int(r.integers(0, 500)) * US))
+    if sized:
+        # per-frame sizes on some kernels, with profile points (frame values
+        # 1024..3071); every frame draws its value
+        for ch in chains:
+            for t in ch["tasks"]:
+                n = len(t["est_ns"])
+                t["frame_dim"] = [int(r.random() < 0.5) for _ in range(n)]
+                t["prof"] = [sorted((int(v), int(r.integers(20, 600)) * US)
+                                    for v in r.choice(np.arange(1024, 3072), 2, replace=False))
+                             if fd else None for fd in t["frame_dim"]]
+        arrivals = [(c, f, t, (int(r.integers(1024, 3072)),)) for c, f, t in arrivals]
     noise = {}
 
     def dur(c, f, g):
