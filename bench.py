@@ -48,7 +48,12 @@ def parse():
     ap.add_argument("--roofline-reps", type=int, default=20)
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fifo", action="store_true")
+    ap.add_argument("--no-fifo", action="store_true",
+                    help="run the urgency gate only (no FIFO, paper or placed-FIFO runs)")
+    ap.add_argument("--extra-seeds", type=int, default=2,
+                    help="further workload seeds run once per policy (half windows) and pooled")
+    ap.add_argument("--overload-s", type=int, default=4,
+                    help="window of the overload run beside the main line (0 = none)")
     ap.add_argument("--overload", action="store_true",
                     help="the overload workload instead: the eleven chains at a lower base "
                          "load plus a closed-loop best-effort chain of 8192^3 FP8 products")
@@ -76,6 +81,7 @@ PAPER = 1 | 2 | 4         # UG_F_BIND | UG_F_DELAY | UG_F_BATCH: the paper's mec
 ADMIT = 16                # UG_F_ADMIT: task admission, the stand-in for stream priorities
 FULL = PAPER | ADMIT      # the gate as benchmarked
 NO_OVERLAP = 64           # UG_F_NO_OVERLAP: wait for a closed batch to finish
+CPU_PRIO = 512            # UG_F_CPU_PRIO: urgency-centric CPU scheduling
 SWEEPS = {
     # mechanism ablation (Sec. 6.4): each mechanism alone, all, none
     "ablation": [{"name": "none", "flags": 0}, {"name": "bind", "flags": 1 | 4},
@@ -111,9 +117,11 @@ SWEEPS = {
                {"name": "sync", "flags": PAPER | NO_OVERLAP, "cfg": {"delta_eval_ns": 0}},
                {"name": "overlap+admit", "flags": FULL}],
     # ranking order (Sec. 6.4, the policy comparison): urgency against EDF,
-    # SJF, HRRN and lowest chain utilisation first, the paper's mechanisms on
+    # the EDF variants on per-task deadlines from an equal-slack (SAEDF) or
+    # equal-flexibility (EQDF) split, SJF, HRRN and lowest chain utilisation
+    # first, the paper's mechanisms on
     "keys": [{"name": k, "flags": PAPER, "cfg": {"order_key": k}}
-             for k in ("urgency", "edf", "sjf", "hrrn", "lcuf")]
+             for k in ("urgency", "edf", "saedf", "eqdf", "sjf", "hrrn", "lcuf")]
     + [{"name": "urgency+admit", "flags": FULL}],
     # task graphs (configuration 2): every task launched as one captured
     # HIP graph, gated per task
@@ -140,6 +148,14 @@ SWEEPS = {
              for n, f, ps, hs in (("full", FULL, (85, 90, 95, 99), (0, 5, 20)),
                                   ("paper", PAPER, (90, 95, 99), (0, 20)))
              for p in ps for h in hs],
+    # urgency-centric CPU scheduling (Sec. 4.3): every task gets a CPU segment
+    # (the paper's E_cpu / E_gpu per chain) and the segments share 2 or 3
+    # cores (about 1.2 cores of demand); first come, first served against
+    # urgency-ranked fixed priorities with preemption; FIFO launch with the
+    # same cores, first come, first served
+    "cpu": [{"name": f"{n}_cores{k}{'_prio' if pr else ''}", "cpu": 1.0, "cores": k,
+             "flags": f | (CPU_PRIO if pr else 0)}
+            for k in (2, 3) for n, f in (("full", FULL), ("paper", PAPER)) for pr in (False, True)],
     # FIFO launch with the gate's probe-based queue placement beside plain FIFO
     "fifo_placed": [{"name": "fifo_placed", "policy": "fifo", "flags": 256},
                     {"name": "full", "flags": FULL}],
@@ -152,19 +168,21 @@ def sweep_main(args, torch, capi, runner, synth):
     for v in SWEEPS[args.sweep]:
         cu = v.get("custom")
         groups.setdefault((v.get("f_a", args.f_a), v.get("f_d", args.f_d),
-                           json.dumps(cu, sort_keys=True) if cu else None), []).append(v)
+                           json.dumps(cu, sort_keys=True) if cu else None, v.get("cpu", 0.0),
+                           v.get("cores", 0)), []).append(v)
     for seed in range(args.seed, args.seed + args.seeds):
-        for (fa, fd, cu), variants in groups.items():
+        for (fa, fd, cu, cpu, cores), variants in groups.items():
             wl = synth.config1(seed=seed, f_a=fa, f_d=fd, window_s=float(W + K),
-                               custom=json.loads(cu) if cu else None)
+                               custom=json.loads(cu) if cu else None, cpu=cpu)
             warm = [(c, f, t) for c, f, t in wl.arrivals if t < W * 1e9]
             timed = [(c, f, t - W * 10 ** 9) for c, f, t in wl.arrivals if t >= W * 1e9]
             dw = runner.DeviceWorkload(wl, n_sets=4)
             prof = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16)
             runner.profile(prof, dw, warmup=2, reps=5)
             point = {"seed": seed, "f_a": fa, "f_d": fd, "frames": len(timed), "window_s": K,
-                     "custom": json.loads(cu) if cu else None}
-            fifo = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16)
+                     "custom": json.loads(cu) if cu else None, "cpu": cpu, "cpu_cores": cores}
+            fifo = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16,
+                                    cpu_cores=cores)
             runner.copy_estimates(prof, fifo, wl)
             run_policy(fifo, dw, warm[: len(warm) // 2], torch)
             cf, m, st, wall = run_policy(fifo, dw, timed, torch)
@@ -173,7 +191,8 @@ def sweep_main(args, torch, capi, runner, synth):
             for v in variants:
                 if v.get("policy") == "fifo":
                     g = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16,
-                                         flags=v.get("flags", 0), **v.get("cfg", {}))
+                                         flags=v.get("flags", 0),
+                                         **({"cpu_cores": cores} | v.get("cfg", {})))
                     runner.copy_estimates(prof, g, wl)
                     run_policy(g, dw, warm[: len(warm) // 2], torch)
                     th = 0
@@ -188,7 +207,7 @@ def sweep_main(args, torch, capi, runner, synth):
                         f"p99 {fifo_sum['p99_ms']} ms")
                     continue
                 g = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16,
-                                     **v.get("cfg", {}))
+                                     **({"cpu_cores": cores} | v.get("cfg", {})))
                 runner.copy_estimates(prof, g, wl)
                 flags = v.get("flags", FULL) | capi.F_PLACE
                 g.set_flags((flags & ~capi.F_DELAY) | capi.F_CALIBRATE)
@@ -209,6 +228,136 @@ def sweep_main(args, torch, capi, runner, synth):
             prof.close()
             del dw
             torch.cuda.empty_cache()
+
+
+# Policies of the benchmark line, each on the same arrivals:
+#   urgency      the gate as benchmarked: the paper's three mechanisms plus
+#                task admission, TH_urgent at the TH_PCT-th percentile
+#   paper        the paper's three mechanisms only (binding, delayed and
+#                batched launching) at its 95th percentile (Sec. 4.4.3)
+#   fifo         plain FIFO launch, HIP's own stream-to-queue mapping
+#   fifo_placed  FIFO launch on streams placed over the hardware queues by the
+#                same probe as the gate's lanes (UG_F_PLACE)
+POLICIES = {
+    "urgency": {"policy": "urgency", "flags": FULL, "pct": TH_PCT},
+    "paper": {"policy": "urgency", "flags": PAPER, "pct": 95},
+    "fifo": {"policy": "fifo", "flags": 0},
+    "fifo_placed": {"policy": "fifo", "flags": 256},
+}
+
+
+def seed_run(args, torch, runner, synth, seed, W, H, names, reps=2, overload=False):
+    """One workload seed: generate, upload, profile (a1), calibrate each
+    urgency variant's TH_urgent on the W warm-up windows (delayed launching
+    off, sampling on), then run the H-second timed arrival sequence ``reps``
+    times per policy in a mirrored order.  Returns the runs and the
+    workload's figures."""
+    from paper_2509_12207_amd import capi
+    if overload:
+        wl = synth.config4(seed=seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + H))
+        c_be = wl.meta["be_chain"]
+        be_warm = (c_be, wl.meta["be_depth"], W * 10 ** 9)
+        be_timed = (c_be, wl.meta["be_depth"], H * 10 ** 9)
+    else:
+        wl = synth.config1(seed=seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + H))
+        c_be, be_warm, be_timed = None, None, None
+    warm = [(c, f, t) for c, f, t in wl.arrivals if t < W * 1e9]
+    timed = [(c, f, t - W * 10 ** 9) for c, f, t in wl.arrivals if t >= W * 1e9]
+    n_kernels = sum(len(t["kernels"]) for ch in wl.chains for t in ch.tasks)
+    log(f"{wl.name} seed {seed}: {len(wl.chains)} chains, {n_kernels} kernels per hyper-frame "
+        f"set, {len(warm)} warm-up + {len(timed)} timed frames")
+    t = time.time()
+    dw = runner.DeviceWorkload(wl, n_sets=4)
+    log(f"device buffers {dw.nbytes() / 2**30:.2f} GiB in {time.time() - t:.1f} s")
+    prof = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16)
+    t = time.time()
+    runner.profile(prof, dw, warmup=2, reps=7)
+    est = runner.estimates(prof, wl)
+    log(f"profiled in {time.time() - t:.1f} s")
+    util, by_op, be_frame_ns = 0.0, {}, 0
+    for c, ch in enumerate(wl.chains):
+        if c == c_be:
+            be_frame_ns = sum(est[(c, g)][0] for g in range(len(ch.tasks[0]["kernels"])))
+            continue
+        e_frame, g = 0, 0
+        for task in ch.tasks:
+            for k in task["kernels"]:
+                e = est[(c, g)][0]
+                e_frame += e
+                by_op[k["op"]] = by_op.get(k["op"], 0) + e * 1e9 / ch.period_ns
+                g += 1
+        util += e_frame / (ch.period_ns / args.f_a)
+    log(f"isolated-kernel utilisation {util:.3f}; GPU time share by op "
+        + ", ".join(f"{k} {v / sum(by_op.values()):.2f}"
+                    for k, v in sorted(by_op.items(), key=lambda x: -x[1])))
+
+    def be_rate(comps, wall):
+        # best-effort work done in the window: FP8 TFLOP/s and frames
+        if c_be is None:
+            return {}
+        n = int((comps["chain"] == c_be).sum())
+        d, kpf = wl.meta["be_dim"], wl.meta["be_gemms"]
+        return {"be_frames": n, "be_tflops": round(n * kpf * 2 * d ** 3 / wall / 1e12, 1)}
+
+    gates, th = {}, {}
+    for n in names:
+        p = POLICIES[n]
+        g = runner.make_gate(wl, p["policy"], trace_capacity=0, queue_capacity=1 << 16,
+                             flags=p["flags"] | (capi.F_PLACE if p["policy"] == "urgency" else 0))
+        for (c, k), (e, u) in est.items():
+            g.set_estimate(c, k, e, u)
+        if p["policy"] == "urgency":
+            # TH_urgent: the warm-up windows with delayed launching off and
+            # calibration sampling on, then the pct-th percentile (Sec. 4.4.3)
+            g.set_flags((p["flags"] & ~capi.F_DELAY) | capi.F_CALIBRATE | capi.F_PLACE)
+            g.set_threshold(0)
+            run_policy(g, dw, warm, torch, be=be_warm)
+            th[n] = g.calibration_threshold(p["pct"])
+            g.set_threshold(th[n])
+            g.set_flags(p["flags"] | capi.F_PLACE)
+            log(f"{n}: TH_urgent (p{p['pct']}) slack {th[n] / 1e6:.3f} ms")
+        else:
+            run_policy(g, dw, warm[: len(warm) // 2], torch)     # warm the FIFO streams
+        gates[n] = g
+    prof.close()
+    runs = {n: [] for n in names}
+    order = names + names[::-1] if reps == 2 else names
+    for n in order:
+        comps, m, st, wall = run_policy(gates[n], dw, timed, torch, be=be_timed)
+        runs[n].append((comps, m, st, wall))
+        log(f"seed {seed} {n} run {len(runs[n])}:",
+            json.dumps(summarise(m, st, wall, len(timed)) | be_rate(comps, wall)))
+    for g in gates.values():
+        g.close()
+    del dw
+    return {"wl": wl, "util": util, "by_op": by_op, "th": th, "runs": runs, "timed": timed,
+            "n_kernels": n_kernels, "be_rate": be_rate, "be_frame_ns": be_frame_ns}
+
+
+def pooled_seeds(seed_runs):
+    """Eq. 3 over every (seed, chain) pair with completions and nearest-rank
+    percentiles of the pooled latencies of several workload seeds (each a
+    list of runs of its own arrivals)."""
+    import numpy as np
+    ratios, lats, frames, missed = [], [], 0, 0
+    for runs, wl in seed_runs:
+        comps = np.concatenate([r[0] for r in runs])
+        for c, ch in enumerate(wl.chains):
+            if not ch.deadline_ns:
+                continue
+            sel = comps[comps["chain"] == c]
+            if len(sel):
+                ratios.append(sel["missed"].sum() / len(sel))
+                lats.append(sel["latency_ns"])
+                frames += len(sel)
+                missed += int(sel["missed"].sum())
+    lat = np.sort(np.concatenate(lats)) if lats else np.zeros(0)
+    n = len(lat)
+
+    def pct(p):
+        return round(float(lat[max(0, -(-p * n // 100) - 1)]) / 1e6, 3) if n else None
+    return {"miss_ratio_pct": round(100.0 * float(np.mean(ratios)) if ratios else 0.0, 3),
+            "p50_ms": pct(50), "p99_ms": pct(99), "frames": frames, "missed": missed}
 
 
 def run_policy(g, dw, arrivals, torch, be=None):
@@ -663,101 +812,66 @@ def main():
         return
     W, K = args.warmup, args.steps
     # the timed arrival sequence lasts K/2 windows; each policy runs it twice,
-    # in the order urgency, FIFO, FIFO, urgency, so that drift over the run
-    # (clocks, caches, queues) cancels: K windows per policy in all
+    # in a mirrored order (urgency, paper, fifo, fifo_placed, fifo_placed,
+    # fifo, paper, urgency), so that drift over the run (clocks, caches,
+    # queues) cancels: K windows per policy in all
     if K < 2 or K % 2:
         print("--steps must be even and >= 2 (two runs of K/2 windows per policy)",
               file=sys.stderr)
         sys.exit(2)
     H = K // 2
-    if args.overload:
-        wl = synth.config4(seed=args.seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + H))
-        c_be = wl.meta["be_chain"]
-        be_warm = (c_be, wl.meta["be_depth"], W * 10 ** 9)
-        be_timed = (c_be, wl.meta["be_depth"], H * 10 ** 9)
-    else:
-        wl = synth.config1(seed=args.seed, f_a=args.f_a, f_d=args.f_d, window_s=float(W + H))
-        c_be, be_warm, be_timed = None, None, None
-    warm = [(c, f, t) for c, f, t in wl.arrivals if t < W * 1e9]
-    timed = [(c, f, t - W * 10 ** 9) for c, f, t in wl.arrivals if t >= W * 1e9]
-    n_kernels = sum(len(t["kernels"]) for ch in wl.chains for t in ch.tasks)
-    log(f"{wl.name}: {len(wl.chains)} chains, {n_kernels} kernels per hyper-frame set, "
-        f"{len(warm)} warm-up + {len(timed)} timed frames")
-    t = time.time()
-    dw = runner.DeviceWorkload(wl, n_sets=4)
-    log(f"device buffers {dw.nbytes() / 2**30:.2f} GiB in {time.time() - t:.1f} s")
-
-    # a1: offline profiling stage (isolated kernel times, utilisation)
-    urg = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16)
-    t = time.time()
-    runner.profile(urg, dw, warmup=2, reps=7)
-    est = runner.estimates(urg, wl)
-    log(f"profiled in {time.time() - t:.1f} s")
-    util = 0.0
-    by_op = {}
-    be_frame_ns = 0
-    for c, ch in enumerate(wl.chains):
-        if c == c_be:
-            be_frame_ns = sum(est[(c, g)][0] for g in range(len(ch.tasks[0]["kernels"])))
-            continue
-        e_frame = 0
-        g = 0
-        for task in ch.tasks:
-            for k in task["kernels"]:
-                e = est[(c, g)][0]
-                e_frame += e
-                by_op[k["op"]] = by_op.get(k["op"], 0) + e * 1e9 / ch.period_ns
-                g += 1
-        util += e_frame / (ch.period_ns / args.f_a)
+    names = ["urgency"] if args.no_fifo else list(POLICIES)
+    main_run = seed_run(args, torch, runner, synth, args.seed, W, H, names, reps=2,
+                        overload=args.overload)
+    wl, util, by_op, th = main_run["wl"], main_run["util"], main_run["by_op"], main_run["th"]
+    runs, timed, n_kernels = main_run["runs"], main_run["timed"], main_run["n_kernels"]
+    be_rate, be_frame_ns = main_run["be_rate"], main_run["be_frame_ns"]
     dominant = max(by_op, key=by_op.get)
-    log(f"isolated-kernel utilisation {util:.3f}; GPU time share by op "
-        + ", ".join(f"{k} {v / sum(by_op.values()):.2f}" for k, v in sorted(by_op.items(), key=lambda x: -x[1])))
-
-    # TH_urgent: run the warm-up windows with delayed launching off and
-    # calibration sampling on, take the TH_PCT-th percentile (Sec. 4.4.3)
-    urg.set_flags((FULL & ~capi.F_DELAY) | capi.F_CALIBRATE | capi.F_PLACE)
-    urg.set_threshold(0)
-    run_policy(urg, dw, warm, torch, be=be_warm)
-    th = urg.calibration_threshold(TH_PCT)
-    urg.set_threshold(th)
-    urg.set_flags(FULL | capi.F_PLACE)
-    log(f"TH_urgent calibrated: slack {th / 1e6:.3f} ms")
-
-    # timed: urgency gate
-    def be_rate(comps, wall):
-        # best-effort work done in the window: FP8 TFLOP/s and frames
-        if c_be is None:
-            return {}
-        n = int((comps["chain"] == c_be).sum())
-        d, kpf = wl.meta["be_dim"], wl.meta["be_gemms"]
-        return {"be_frames": n, "be_tflops": round(n * kpf * 2 * d ** 3 / wall / 1e12, 1)}
-
-    fifo = None
-    if not args.no_fifo:
-        fifo = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16)
-        for (c, k), (e, u) in est.items():
-            fifo.set_estimate(c, k, e, u)
-        run_policy(fifo, dw, warm[: len(warm) // 2], torch)     # warm the FIFO streams
-    runs = {"urgency": [], "fifo": []}
-    order = [("urgency", urg), ("fifo", fifo), ("fifo", fifo), ("urgency", urg)]
-    for name, g in order:
-        if g is None:
-            continue
-        comps, m, st, wall = run_policy(g, dw, timed, torch, be=be_timed)
-        runs[name].append((comps, m, st, wall))
-        log(f"{name} run {len(runs[name])}:",
-            json.dumps(summarise(m, st, wall, len(timed)) | be_rate(comps, wall)))
-    urg_sum = pooled(runs["urgency"], wl, len(timed), be_rate)
-    log("urgency:", json.dumps(urg_sum))
-    fifo_sum = None
-    if fifo is not None:
-        fifo_sum = pooled(runs["fifo"], wl, len(timed), be_rate)
-        log("fifo:", json.dumps(fifo_sum))
-        fifo.close()
+    summary = {n: pooled(runs[n], wl, len(timed), be_rate) for n in names}
+    for n in names:
+        log(f"{n}:", json.dumps(summary[n]))
+    urg_sum = summary["urgency"]
+    fifo_sum = summary.get("fifo")
     wall_u = sum(r[3] for r in runs["urgency"])
-    urg.close()
-    del dw
+    del main_run
     torch.cuda.empty_cache()
+
+    # the same comparison on further seeds (one shorter run per policy each),
+    # pooled with the main seed: Eq. 3 over every (seed, chain) pair, nearest-
+    # rank percentiles of all latencies
+    seeds_pooled = None
+    if args.extra_seeds > 0 and not args.overload:
+        per_seed = {n: [(runs[n], wl)] for n in names}
+        hs = max(1, H // 2)
+        for s in range(args.seed + 1, args.seed + 1 + args.extra_seeds):
+            r = seed_run(args, torch, runner, synth, s, W, hs, names, reps=1)
+            for n in names:
+                per_seed[n].append((r["runs"][n], r["wl"]))
+                log(f"seed {s} {n}:", json.dumps(pooled(r["runs"][n], r["wl"], len(r["timed"]),
+                                                        lambda c, w: {})))
+            del r
+            torch.cuda.empty_cache()
+        seeds_pooled = {"seeds": list(range(args.seed, args.seed + 1 + args.extra_seeds)),
+                        "window_s": {"main": H, "other": hs}}
+        for n in names:
+            seeds_pooled[n] = pooled_seeds(per_seed[n])
+        log("seeds pooled:", json.dumps(seeds_pooled))
+
+    # the overload workload (configuration 1 plus a closed-loop best-effort
+    # chain of FP8 products), urgency gate and FIFO, one shorter run each
+    overload = None
+    if args.overload_s > 0 and not args.overload:
+        r = seed_run(args, torch, runner, synth, args.seed, W, args.overload_s,
+                     ["urgency", "fifo"], reps=1, overload=True)
+        overload = {"window_s": args.overload_s, "seed": args.seed,
+                    "isolated_utilisation_deadline_chains": round(r["util"], 3),
+                    "be_frame_ms": round(r["be_frame_ns"] / 1e6, 3)}
+        for n in ("urgency", "fifo"):
+            overload[n] = {k: v for k, v in pooled(r["runs"][n], r["wl"], len(r["timed"]),
+                                                   r["be_rate"]).items() if k != "per_chain"}
+        log("overload:", json.dumps(overload))
+        del r
+        torch.cuda.empty_cache()
 
     # roofline of every kernel at its saturating shape; the dominant one is
     # reported as `roofline`
@@ -796,16 +910,25 @@ def main():
                      "30k-120k pts), periods 33-500 ms, deadlines 0.5-1.0 x period, "
                    + ("plus a closed-loop best-effort chain of 4 x 8192^3 FP8 E4M3 GEMMs per "
                       "frame, " if args.overload else "")
-                   + "urgency gate vs FIFO",
+                   + "urgency gate vs FIFO (also: the paper's three mechanisms at p95, FIFO on "
+                     "placed streams)",
                    "be_frame_ms": round(be_frame_ns / 1e6, 3) if args.overload else None,
                    "seed": args.seed, "f_a": args.f_a, "f_d": args.f_d, "window_s": H,
-                   "runs_per_policy": 2, "order": "urgency, fifo, fifo, urgency",
+                   "runs_per_policy": 2, "order": ", ".join(names + names[::-1]),
                    "frames": len(timed), "kernels_per_round": n_kernels,
-                   "isolated_utilisation": round(util, 3), "th_urgent_slack_ms": round(th / 1e6, 3)},
+                   "isolated_utilisation": round(util, 3),
+                   "th_urgent_slack_ms": round(th["urgency"] / 1e6, 3),
+                   "th_urgent_pct": TH_PCT},
         "urgency": urg_sum,
         "fifo": fifo_sum,
+        "paper": summary.get("paper"),
+        "fifo_placed": summary.get("fifo_placed"),
+        "th_urgent_paper_p95_ms": round(th["paper"] / 1e6, 3) if "paper" in th else None,
+        "seeds_pooled": seeds_pooled,
+        "overload": overload,
         "miss_ratio_fifo_pct": fifo_sum["miss_ratio_pct"] if fifo_sum else None,
-        "p99_ms": {"urgency": urg_sum["p99_ms"], "fifo": fifo_sum["p99_ms"] if fifo_sum else None},
+        "p99_ms": {n: summary[n]["p99_ms"] for n in names},
+        "miss_ratio_pct": {n: summary[n]["miss_ratio_pct"] for n in names},
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
         | {"kernel": roof["kernel"], "shape": roof["shape"], "avg_us": roof["avg_us"]},
         "kernels": kernels,

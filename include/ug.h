@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define UG_ABI_VERSION 5u
+#define UG_ABI_VERSION 6u
 
 typedef int32_t ug_status;
 enum {
@@ -85,6 +85,13 @@ enum {
                           (delayed launching at the task's first kernel,
                           with the task's largest utilisation; no batches
                           inside a task).  Applies to both policies.      */
+  UG_F_CPU_PRIO = 512u, /* urgency-centric CPU scheduling (Sec. 4.3), with
+                          ug_config.cpu_cores > 0: whenever a chain starts a
+                          CPU segment, every active instance is ranked by
+                          urgency, and the cores run the segments of the
+                          best ranks, preempting worse ones (fixed
+                          priorities, as SCHED_FIFO); without it the cores
+                          serve segments first come, first served      */
   UG_F_PLACE = 256u     /* queue placement of the stream pool: when streams
                           are attached (or created), the library measures
                           which hardware queue each one uses and assigns
@@ -102,7 +109,14 @@ enum {
  *   HRRN  highest response ratio (t - t_arr + R) / R first, R = remaining
  *         work (R = 0 ranks first);
  *   LCUF  lowest chain utilisation (a frame's estimated work / period)
- *         first (period 0 ranks last).
+ *         first (period 0 ranks last);
+ *   SAEDF, EQDF  earliest deadline of the instance's current task, where
+ *         the chain's remaining slack S = t_arr + D - t_ref - W (t_ref: the
+ *         task's start, W: the estimated work of it and every later task)
+ *         is split over the remaining m tasks equally (SAEDF: S / m) or in
+ *         proportion to each task's estimated work w (EQDF: S w / W); the
+ *         task's deadline is t_ref + w + its share.  The paper names these
+ *         two by citation only; this is the reading built.
  * The key replaces urgency in the service order, the binding rank and the
  * "more urgent than" of delayed launching; truly urgent (TH_urgent), the
  * reserved level and calibration stay defined by urgency.  Best-effort
@@ -112,7 +126,9 @@ enum {
   UG_KEY_EDF = 1,
   UG_KEY_SJF = 2,
   UG_KEY_HRRN = 3,
-  UG_KEY_LCUF = 4
+  UG_KEY_LCUF = 4,
+  UG_KEY_SAEDF = 5,
+  UG_KEY_EQDF = 6
 };
 
 /* Operations.  Shapes and slot meaning per op; all float buffers are fp32,
@@ -282,7 +298,10 @@ typedef struct {
                               ug_attach_streams before ug_start (streams made
                               by torch); 1: the library creates its own
                               default-priority streams at ug_start          */
-  int32_t pad1;
+  int32_t cpu_cores;       /* CPU cores the tasks' CPU segments share (Sec.
+                              4.1: a segment runs on a core for its CPU time,
+                              one segment per core); 0 = every segment runs
+                              at once (no CPU contention).  0..1024 */
 } ug_config;
 
 /* Completion of one frame (Sec. 6.2: latency, miss). */
@@ -318,11 +337,13 @@ typedef struct {
  *   EVREC    chain, frame, task, a = kind, b = seq (batch index, or the
  *            number of batches for the end event)
  *   LAUNCH   chain, frame, kernel, a = level, b = lane
+ *   CPU      chain, frame, task, a = 1: the task's CPU segment takes a core,
+ *            0: it loses its core to a better-ranked one (cpu_cores > 0)
  * kernel = index within the chain (all tasks' kernels numbered in order). */
 enum {
   UG_REC_INSTANT = 1, UG_REC_ARRIVE = 2, UG_REC_EVDONE = 3, UG_REC_COMPLETE = 4,
   UG_REC_TSTART = 5, UG_REC_BIND = 6, UG_REC_HOLD = 7, UG_REC_EVREC = 8,
-  UG_REC_LAUNCH = 9, UG_REC_EXIT = 10, UG_REC_DIMS = 11
+  UG_REC_LAUNCH = 9, UG_REC_EXIT = 10, UG_REC_DIMS = 11, UG_REC_CPU = 12
 };
 typedef struct {
   int32_t type;

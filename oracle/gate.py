@@ -116,6 +116,7 @@ class Instance:
         self.chain = chain
         self.phase = "wait"       # wait | cpu | launch | done
         self.task = -1
+        self.task_t0 = None       # when the current task started (its CPU segment)
         self.cpu_ready = None
         self.i_gpu = 0            # kernels confirmed complete (executing index)
         self.i_cpu = 0            # index of the first unfinished CPU segment
@@ -133,6 +134,11 @@ class Instance:
         self.wake = None          # re-check time of a held launch (sleep loop)
         self.est = None           # this frame's estimates (per-frame sizes), else None
         self.gpu_rem = None       # their suffix sums
+        self.cpu_left = 0         # CPU work of the current segment still to run (cores > 0)
+        self.cpu_req = None       # when the segment asked for a core
+        self.cpu_run = False      # holds a core
+        self.cpu_since = None     # last time its work was credited
+        self.cpu_prio = None      # CPU priority rank (1 = most urgent), Sec. 4.3
         self.held_since = None    # first hold of the current task (hold-age bound)
         self.expire = None        # while held: when the hold age reaches its bound
 
@@ -161,12 +167,14 @@ DEFAULT_CFG = {
     "admit_tasks": 4,           # instances with kernels in flight before new tasks wait
     "exit": False,              # early chain exit (Sec. 4.3)
     "no_overlap": False,        # wait for a closed batch to finish (launch-sync variants)
-    "key": "urgency",           # ranking order: urgency | edf | sjf | hrrn | lcuf
+    "key": "urgency",           # ranking order: urgency | edf | sjf | hrrn | lcuf | saedf | eqdf
     "graph": False,             # tasks launch as one graph each (configuration 2)
     "est_noise_permille": 0,    # estimate noise n: per task instance, E * (1000 + k) / 1000
     "noise_seed": 0,            #   with k uniform in [-n, n] (Sec. 6.6)
     "max_hold_ns": 0,           # hold-age bound: a task first held at t0 is not held
                                 #   again from t0 + max_hold_ns on; 0 = no bound
+    "cpu_cores": 0,             # CPU cores the CPU segments share; 0 = one each
+    "cpu_prio": False,          # urgency-centric CPU scheduling (Sec. 4.3)
 }
 
 
@@ -232,8 +240,13 @@ class GateModel:
     def _start_task(self, inst, j, t, out):
         ch = inst.chain
         inst.task = j
+        inst.task_t0 = t
         inst.phase = "cpu"
         inst.cpu_ready = t + ch.cpu[j]
+        inst.cpu_left = ch.cpu[j]
+        inst.cpu_req = t
+        inst.cpu_run = False
+        inst.cpu_since = None
         inst.g_next = ch.task_first[j]
         inst.released_hi = ch.task_first[j]
         inst.batch = 0
@@ -317,10 +330,13 @@ class GateModel:
         # 3. CPU segments that have finished
         active = sorted((i for i in self.inst.values() if i.phase != "done"),
                         key=lambda i: i.key)
-        for inst in active:
-            if inst.phase == "cpu" and inst.cpu_ready <= t:
-                inst.phase = "launch"
-                inst.i_cpu = inst.task + 1
+        if self.cfg["cpu_cores"] > 0:
+            self._cpu(t, active, any(d[0] == "TSTART" for d in out), out)
+        else:
+            for inst in active:
+                if inst.phase == "cpu" and inst.cpu_ready <= t:
+                    inst.phase = "launch"
+                    inst.i_cpu = inst.task + 1
         # 4. one urgency snapshot for the whole instant (Eq. (2))
         slack = {inst.key: self.slack(inst, t) for inst in active}
         self.last_snapshot = dict(slack)
@@ -345,6 +361,51 @@ class GateModel:
         return out
 
     # ------------------------------------------------------------------
+    def _cpu(self, t, active, started, out):
+        """CPU segments on ``cpu_cores`` cores.  Segments that held a core
+        since the last instant are credited the time in between; those with
+        no work left finish (the task may launch).  Without urgency-centric
+        scheduling the cores serve segments first come, first served, each
+        to its end.  With it (Sec. 4.3), whenever a chain starts a new CPU
+        segment every active instance is ranked by urgency at that instant
+        (rank 1 the most urgent), and the cores run the segments of the best
+        ranks, preempting worse-ranked ones (fixed-priority FIFO scheduling:
+        ties in chain, frame order).  A CPU record marks a segment taking a
+        core (1) or losing it (0)."""
+        cpu = [i for i in active if i.phase == "cpu"]
+        for inst in cpu:
+            if inst.cpu_run:
+                inst.cpu_left = max(0, inst.cpu_left - (t - inst.cpu_since))
+                inst.cpu_since = t
+        for inst in cpu:
+            if inst.cpu_left == 0:
+                inst.phase = "launch"
+                inst.i_cpu = inst.task + 1
+                inst.cpu_run = False
+        waiting = [i for i in cpu if i.phase == "cpu"]
+        prio = self.urgency_policy and self.cfg["cpu_prio"]
+        if prio and started:
+            slack = {i.key: self.slack(i, t) for i in active}
+            for r, inst in enumerate(self._order(active, slack, t)):
+                inst.cpu_prio = r + 1
+        k = self.cfg["cpu_cores"]
+        if prio:
+            want = sorted(waiting, key=lambda i: (i.cpu_prio, i.key))[:k]
+        else:
+            running = [i for i in waiting if i.cpu_run]
+            queued = sorted((i for i in waiting if not i.cpu_run), key=lambda i: (i.cpu_req, i.key))
+            want = running + queued[:max(0, k - len(running))]
+        chosen = {i.key for i in want}
+        for inst in waiting:
+            if inst.cpu_run and inst.key not in chosen:
+                inst.cpu_run = False
+                out.append(("CPU", inst.c, inst.f, inst.task, 0))
+        for inst in sorted(want, key=lambda i: i.key):
+            if not inst.cpu_run:
+                inst.cpu_run = True
+                inst.cpu_since = t
+                out.append(("CPU", inst.c, inst.f, inst.task, 1))
+
     def _exits(self, inst, t):
         """Early chain exit: UL < 0 (the slack is negative) at a task start."""
         if not (self.urgency_policy and self.cfg["exit"]) or inst.chain.best_effort:
@@ -360,7 +421,9 @@ class GateModel:
         with best-effort instances last and ties broken by (chain, frame):
         EDF (earliest t_arr + D), SJF (least remaining work R, the two sums
         of Eq. 2), HRRN (highest (t - t_arr + R) / R; R = 0 first), LCUF
-        (lowest estimated work per frame / period; period 0 last)."""
+        (lowest estimated work per frame / period; period 0 last), SAEDF and
+        EQDF (earliest deadline of the current task, the chain's slack split
+        equally or by work over its remaining tasks)."""
         k = self.cfg["key"]
         if k == "urgency":
             return P.more_urgent(slack[a.key], a.key, slack[b.key], b.key)
@@ -377,6 +440,8 @@ class GateModel:
                 # larger ratio first: compare the negated ratios, R = 0 first
                 va = (0, 0) if ra == 0 else (1, -Fraction(t - a.t_arr + ra, ra))
                 vb = (0, 0) if rb == 0 else (1, -Fraction(t - b.t_arr + rb, rb))
+            elif k in ("saedf", "eqdf"):
+                va, vb = self._subtask_deadline(a, t), self._subtask_deadline(b, t)
             elif k == "lcuf":
                 va = (1, 0) if ca.period <= 0 else (0, Fraction(ca.gpu_rem[0] + ca.cpu_rem[0], ca.period))
                 vb = (1, 0) if cb.period <= 0 else (0, Fraction(cb.gpu_rem[0] + cb.cpu_rem[0], cb.period))
@@ -385,6 +450,23 @@ class GateModel:
             if va != vb:
                 return va < vb
         return a.key < b.key
+
+    def _subtask_deadline(self, inst, t):
+        """Deadline of the instance's current task under the SAEDF / EQDF
+        slack split (policy.subtask_deadline), from the profiled estimates
+        (the frame's own with per-frame sizes): the task that has started,
+        else the next one, taken as starting now."""
+        ch = inst.chain
+        rem = ch.gpu_rem if inst.gpu_rem is None else inst.gpu_rem
+        if inst.phase in ("cpu", "launch"):
+            j, t_ref = inst.task, inst.task_t0
+        else:
+            j, t_ref = inst.task + 1, t
+        lo, hi = ch.task_first[j], ch.task_end[j]
+        w_task = ch.cpu[j] + rem[lo] - rem[hi]
+        w_rem = ch.cpu_rem[j] + rem[lo]
+        return P.subtask_deadline(self.cfg["key"], t_ref, inst.t_arr, ch.deadline, w_task,
+                                  w_rem, ch.n_tasks - j)
 
     def _order(self, insts, slack, t):
         from functools import cmp_to_key
@@ -525,9 +607,12 @@ class GateModel:
     def timers(self):
         """Earliest future time at which the gate must run without an input."""
         ts = []
+        cores = self.cfg["cpu_cores"]
         for inst in self.inst.values():
-            if inst.phase == "cpu":
+            if inst.phase == "cpu" and cores <= 0:
                 ts.append(inst.cpu_ready)
+            if inst.phase == "cpu" and cores > 0 and inst.cpu_run:
+                ts.append(inst.cpu_since + inst.cpu_left)
             if inst.phase == "launch" and inst.wake is not None:
                 ts.append(inst.wake)
             if inst.phase == "launch" and inst.expire is not None:

@@ -234,3 +234,28 @@ def profile_estimate(points, v):
         if v0 <= v < v1:
             return e0 + ((e1 - e0) * (v - v0)) // (v1 - v0)
     raise AssertionError("unreachable")
+
+
+# --------------------------------------------------------------------------
+# Sub-deadlines of the EDF family's chain variants (policy comparison,
+# Sec. 6.4: SAEDF and EQDF).  The paper names them by citation only; they are
+# read here as earliest-deadline-first on a per-task deadline obtained by
+# splitting the chain's remaining slack over its remaining tasks, the two
+# classic serial-task rules: equal slack (every remaining task gets the same
+# share; SAEDF) and equal flexibility (shares proportional to each task's
+# estimated work; EQDF).
+# --------------------------------------------------------------------------
+def subtask_deadline(rule, t_ref, t_arr, deadline, w_task, w_rem, m):
+    """Deadline of the task that started at ``t_ref``: its own estimated
+    work ``w_task`` plus its share of the slack S = t_arr + D - t_ref - w_rem
+    (``w_rem``: the estimated work of this and every later task, ``m``: the
+    number of those tasks, m >= 1).  rule "saedf": S / m; rule "eqdf":
+    S * w_task / w_rem (w_rem = 0: all of S).  Exact (a Fraction)."""
+    s = t_arr + deadline - t_ref - w_rem
+    if rule == "saedf":
+        share = Fraction(s, m)
+    elif rule == "eqdf":
+        share = Fraction(s) if w_rem == 0 else Fraction(s * w_task, w_rem)
+    else:
+        raise ValueError(rule)
+    return t_ref + w_task + share

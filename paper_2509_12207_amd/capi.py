@@ -12,16 +12,18 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libug.so")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 POLICY_FIFO, POLICY_URGENCY = 0, 1
 F_BIND, F_DELAY, F_BATCH, F_CALIBRATE, F_ADMIT, F_EXIT, F_NO_OVERLAP = 1, 2, 4, 8, 16, 32, 64
 F_GRAPH = 128
 F_PLACE = 256
+F_CPU_PRIO = 512
 
-KEY_URGENCY, KEY_EDF, KEY_SJF, KEY_HRRN, KEY_LCUF = 0, 1, 2, 3, 4
-KEYS = {"urgency": KEY_URGENCY, "edf": KEY_EDF, "sjf": KEY_SJF, "hrrn": KEY_HRRN, "lcuf": KEY_LCUF}
+KEY_URGENCY, KEY_EDF, KEY_SJF, KEY_HRRN, KEY_LCUF, KEY_SAEDF, KEY_EQDF = 0, 1, 2, 3, 4, 5, 6
+KEYS = {"urgency": KEY_URGENCY, "edf": KEY_EDF, "sjf": KEY_SJF, "hrrn": KEY_HRRN, "lcuf": KEY_LCUF,
+        "saedf": KEY_SAEDF, "eqdf": KEY_EQDF}
 
 OP_GEMM_F32 = 1
 OP_BIAS_RELU_F32 = 2
@@ -43,6 +45,7 @@ OP_IDS = {v: k for k, v in OP_NAMES.items()}
 
 REC_INSTANT, REC_ARRIVE, REC_EVDONE, REC_COMPLETE = 1, 2, 3, 4
 REC_TSTART, REC_BIND, REC_HOLD, REC_EVREC, REC_LAUNCH, REC_EXIT, REC_DIMS = 5, 6, 7, 8, 9, 10, 11
+REC_CPU = 12
 
 EXPORTED = [
     "ug_config_default", "ug_now_ns", "ug_status_str", "ug_create", "ug_destroy",
@@ -78,7 +81,7 @@ class Config(C.Structure):
                 ("admit_tasks", C.c_int64), ("hbm_budget_bytes", C.c_uint64),
                 ("order_key", C.c_int32), ("est_noise_permille", C.c_int32),
                 ("noise_seed", C.c_uint64), ("max_hold_ns", C.c_int64),
-                ("own_streams", C.c_int32), ("pad1", C.c_int32)]
+                ("own_streams", C.c_int32), ("cpu_cores", C.c_int32)]
 
 
 class Completion(C.Structure):

@@ -127,8 +127,13 @@ static ug_record rec(int32_t type, int32_t c, int64_t f, int32_t task,
 void Policy::start_task(Instance& in, int32_t j, int64_t t, std::vector<ug_record>& out) {
   const ChainSpec& ch = chains_[in.c];
   in.task = j;
+  in.task_t0 = t;
   in.phase = kCpu;
   in.cpu_ready = t + ch.cpu[j];
+  in.cpu_left = ch.cpu[j];
+  in.cpu_req = t;
+  in.cpu_run = false;
+  in.cpu_since = 0;
   in.g_next = ch.task_first[j];
   in.released_hi = ch.task_first[j];
   in.batch = 0;
@@ -150,6 +155,7 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
                      std::vector<EvDone>& evdones, std::vector<ug_record>& out,
                      const char** err) {
   now_ = t;
+  const size_t out0 = out.size();
   // 1. inputs in canonical order
   std::sort(arrivals.begin(), arrivals.end(), [](const Arrival& a, const Arrival& b) {
     return a.c != b.c ? a.c < b.c : a.f < b.f;
@@ -256,11 +262,16 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
   active.reserve(inst_.size());
   for (auto& kv : inst_) {
     Instance& in = kv.second;
-    if (in.phase == kCpu && in.cpu_ready <= t) {
+    if (cfg_.cpu_cores <= 0 && in.phase == kCpu && in.cpu_ready <= t) {
       in.phase = kLaunch;
       in.i_cpu = in.task + 1;
     }
     active.push_back(&in);
+  }
+  if (cfg_.cpu_cores > 0) {
+    bool started = false;
+    for (size_t i = out0; i < out.size(); ++i) started |= out[i].type == UG_REC_TSTART;
+    cpu_cores(t, active, started, out);
   }
   // 4. urgency snapshot: slack = t_arr + D - sum E^gpu - sum E^cpu - t
   std::map<Key, int64_t> slack;
@@ -310,6 +321,84 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
   return true;
 }
 
+void Policy::cpu_cores(int64_t t, const std::vector<Instance*>& active, bool started,
+                       std::vector<ug_record>& out) {
+  // CPU segments on cfg_.cpu_cores cores.  Segments that held a core since
+  // the last instant are credited the time in between; those with no work
+  // left finish (the task may launch).  Without urgency-centric scheduling
+  // the cores serve segments first come, first served, each to its end.
+  // With it (Sec. 4.3), a chain starting a new CPU segment ranks every active
+  // instance by urgency (rank 1 the most urgent), and the cores run the
+  // segments of the best ranks, preempting worse ones (fixed priorities,
+  // ties in (chain, frame) order).
+  std::vector<Instance*> waiting;
+  for (Instance* in : active) {
+    if (in->phase != kCpu) continue;
+    if (in->cpu_run) {
+      in->cpu_left = std::max<int64_t>(0, in->cpu_left - (t - in->cpu_since));
+      in->cpu_since = t;
+    }
+    if (in->cpu_left == 0) {
+      in->phase = kLaunch;
+      in->i_cpu = in->task + 1;
+      in->cpu_run = false;
+    } else {
+      waiting.push_back(in);
+    }
+  }
+  const bool prio = cfg_.policy == UG_POLICY_URGENCY && cfg_.cpu_prio;
+  if (prio && started) {
+    std::map<Key, int64_t> slack;
+    for (Instance* in : active) {
+      const ChainSpec& ch = chains_[in->c];
+      slack[{in->c, in->f}] = ch.best_effort ? kBestEffortSlack
+                                             : in->t_arr + ch.deadline_ns - remaining(*in) - t;
+    }
+    std::vector<Instance*> order(active);
+    std::sort(order.begin(), order.end(),
+              [&](const Instance* a, const Instance* b) { return before(*a, *b, slack); });
+    for (size_t r = 0; r < order.size(); ++r) order[r]->cpu_prio = static_cast<int32_t>(r + 1);
+  }
+  const size_t k = static_cast<size_t>(cfg_.cpu_cores);
+  std::vector<Instance*> want;
+  if (prio) {
+    want = waiting;
+    std::sort(want.begin(), want.end(), [](const Instance* a, const Instance* b) {
+      return a->cpu_prio != b->cpu_prio ? a->cpu_prio < b->cpu_prio
+                                        : Key{a->c, a->f} < Key{b->c, b->f};
+    });
+    if (want.size() > k) want.resize(k);
+  } else {
+    std::vector<Instance*> queued;
+    for (Instance* in : waiting) (in->cpu_run ? want : queued).push_back(in);
+    std::sort(queued.begin(), queued.end(), [](const Instance* a, const Instance* b) {
+      return a->cpu_req != b->cpu_req ? a->cpu_req < b->cpu_req
+                                      : Key{a->c, a->f} < Key{b->c, b->f};
+    });
+    for (Instance* in : queued)
+      if (want.size() < k) want.push_back(in);
+  }
+  auto chosen = [&](const Instance* in) {
+    return std::find(want.begin(), want.end(), in) != want.end();
+  };
+  for (Instance* in : waiting) {
+    if (in->cpu_run && !chosen(in)) {
+      in->cpu_run = false;
+      out.push_back(rec(UG_REC_CPU, in->c, in->f, in->task, 0, 0, 0, 0));
+    }
+  }
+  std::sort(want.begin(), want.end(), [](const Instance* a, const Instance* b) {
+    return Key{a->c, a->f} < Key{b->c, b->f};
+  });
+  for (Instance* in : want) {
+    if (!in->cpu_run) {
+      in->cpu_run = true;
+      in->cpu_since = t;
+      out.push_back(rec(UG_REC_CPU, in->c, in->f, in->task, 0, 1, 0, 0));
+    }
+  }
+}
+
 int64_t Policy::remaining(const Instance& in) const {
   const ChainSpec& ch = chains_[in.c];
   const int32_t n = cfg_.est_noise_permille;
@@ -353,6 +442,16 @@ bool Policy::before(const Instance& a, const Instance& b,
           cmp = -sign(static_cast<__int128>(now_ - a.t_arr + ra) * rb,
                       static_cast<__int128>(now_ - b.t_arr + rb) * ra);
         break;
+      case UG_KEY_SAEDF:
+      case UG_KEY_EQDF: {
+        // earliest deadline of the current task: t_ref + w + num / den
+        // for each side, compared as (base * den + num) / den cross-multiplied
+        __int128 base_a, num_a, den_a, base_b, num_b, den_b;
+        subtask_deadline(a, &base_a, &num_a, &den_a);
+        subtask_deadline(b, &base_b, &num_b, &den_b);
+        cmp = sign((base_a * den_a + num_a) * den_b, (base_b * den_b + num_b) * den_a);
+        break;
+      }
       case UG_KEY_LCUF: {
         // E_a / P_a < E_b / P_b, cross-multiplied; P = 0 last
         const int64_t pa = ca.period_ns, pb = cb.period_ns;
@@ -369,6 +468,42 @@ bool Policy::before(const Instance& a, const Instance& b,
     if (cmp) return cmp < 0;
   }
   return Key{a.c, a.f} < Key{b.c, b.f};
+}
+
+void Policy::subtask_deadline(const Instance& in, __int128* base, __int128* num,
+                              __int128* den) const {
+  // The chain's remaining slack S = t_arr + D - t_ref - w_rem split over its
+  // remaining tasks: SAEDF gives the current task S / m (equal slack), EQDF
+  // S * w / w_rem (equal flexibility; all of S when w_rem = 0).  The current
+  // task is the one that has started (from its start), else the next one
+  // (from now).  Estimates: the profiled ones (the frame's own with
+  // per-frame sizes), without estimate noise.
+  const ChainSpec& ch = chains_[in.c];
+  const std::vector<int64_t>& rem = in.gpu_rem.empty() ? ch.gpu_rem : in.gpu_rem;
+  int32_t j;
+  int64_t t_ref;
+  if (in.phase == kCpu || in.phase == kLaunch) {
+    j = in.task;
+    t_ref = in.task_t0;
+  } else {
+    j = in.task + 1;
+    t_ref = now_;
+  }
+  const int64_t w = ch.cpu[j] + rem[ch.task_first[j]] - rem[ch.task_end[j]];
+  const int64_t w_rem = ch.cpu_rem[j] + rem[ch.task_first[j]];
+  const int64_t m = static_cast<int64_t>(ch.task_first.size()) - j;
+  const __int128 s = static_cast<__int128>(in.t_arr) + ch.deadline_ns - t_ref - w_rem;
+  *base = static_cast<__int128>(t_ref) + w;
+  if (cfg_.order_key == UG_KEY_SAEDF) {
+    *num = s;
+    *den = m;
+  } else if (w_rem == 0) {
+    *num = s;
+    *den = 1;
+  } else {
+    *num = s * w;
+    *den = w_rem;
+  }
 }
 
 bool Policy::blocked(const Instance& me, const std::vector<Instance*>& active,
@@ -528,8 +663,13 @@ bool Policy::next_timer(int64_t* t) const {
   int64_t best = 0;
   for (const auto& kv : inst_) {
     const Instance& in = kv.second;
-    if (in.phase == kCpu && (!any || in.cpu_ready < best)) {
+    if (in.phase == kCpu && cfg_.cpu_cores <= 0 && (!any || in.cpu_ready < best)) {
       best = in.cpu_ready;
+      any = true;
+    }
+    if (in.phase == kCpu && cfg_.cpu_cores > 0 && in.cpu_run &&
+        (!any || in.cpu_since + in.cpu_left < best)) {
+      best = in.cpu_since + in.cpu_left;
       any = true;
     }
     if (in.phase == kLaunch && in.has_wake && (!any || in.wake < best)) {

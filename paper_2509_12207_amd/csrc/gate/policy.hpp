@@ -46,6 +46,8 @@ struct PolicyConfig {
   int64_t th_slack_ns = 0;
   int64_t calib_period_ns = 1000000;   // at most one calibration sample per period
   int64_t max_hold_ns = 0;             // hold-age bound per task; 0 = none
+  int32_t cpu_cores = 0;               // cores of the CPU segments; 0 = one each
+  bool cpu_prio = false;               // urgency-centric CPU scheduling (Sec. 4.3)
   std::vector<int32_t> lanes{2, 6};
 };
 
@@ -92,6 +94,13 @@ struct Instance {
   int64_t t_arr = 0;
   int phase = kWait;
   int32_t task = -1;
+  int64_t task_t0 = 0;                 // when the current task started
+  // CPU segment on the shared cores (cpu_cores > 0): work still to run, when
+  // it asked for a core, whether it holds one (since cpu_since), and its
+  // priority rank (1 = most urgent; urgency-centric scheduling)
+  int64_t cpu_left = 0, cpu_req = 0, cpu_since = 0;
+  bool cpu_run = false;
+  int32_t cpu_prio = 0;
   int64_t cpu_ready = 0;
   int32_t i_gpu = 0, i_cpu = 0;        // executing-kernel / CPU-segment index
   int32_t g_next = 0, released_hi = 0;
@@ -173,6 +182,11 @@ class Policy {
   // true iff `a` ranks before `b` under the configured order at the
   // current instant (strict total order)
   bool before(const Instance& a, const Instance& b, const std::map<Key, int64_t>& slack) const;
+  // deadline of the instance's current task under SAEDF / EQDF, as the
+  // rational base + num / den (den > 0)
+  void cpu_cores(int64_t t, const std::vector<Instance*>& active, bool started,
+                 std::vector<ug_record>& out);
+  void subtask_deadline(const Instance& in, __int128* base, __int128* num, __int128* den) const;
   bool blocked(const Instance& me, const std::vector<Instance*>& active,
                const std::map<Key, int64_t>& slack) const;
   void bind(Instance& me, const std::vector<Instance*>& active,

@@ -173,6 +173,8 @@ ug::PolicyConfig policy_config(const ug_config& cfg) {
   p.noise_seed = cfg.noise_seed;
   p.admit_tasks = cfg.admit_tasks;
   p.max_hold_ns = cfg.max_hold_ns;
+  p.cpu_cores = cfg.cpu_cores;
+  p.cpu_prio = (cfg.flags & UG_F_CPU_PRIO) != 0;
   p.lanes.assign(cfg.lanes, cfg.lanes + cfg.n_levels);
   return p;
 }
@@ -589,6 +591,7 @@ void ug_config_default(ug_config* cfg) {
   cfg->noise_seed = 0;
   cfg->own_streams = 0;
   cfg->max_hold_ns = 0;
+  cfg->cpu_cores = 0;
 }
 
 int64_t ug_now_ns(void) { return mono_ns(); }
@@ -617,9 +620,10 @@ ug_status ug_create(const ug_config* cfg, void** out) {
     if (cfg->lanes[i] < 1 || cfg->lanes[i] > 64) return UG_EINVAL;
   if (cfg->own_streams != 0 && cfg->own_streams != 1) return UG_EINVAL;
   if (cfg->max_hold_ns < 0) return UG_EINVAL;
+  if (cfg->cpu_cores < 0 || cfg->cpu_cores > 1024) return UG_EINVAL;
   if (cfg->delta_eval_ns < 0 || cfg->delay_poll_ns < 0 || cfg->queue_capacity == 0 ||
       cfg->calib_period_ns < 0 || cfg->admit_tasks < 1 || cfg->order_key < UG_KEY_URGENCY ||
-      cfg->order_key > UG_KEY_LCUF || cfg->est_noise_permille < 0 ||
+      cfg->order_key > UG_KEY_EQDF || cfg->est_noise_permille < 0 ||
       cfg->est_noise_permille > 1000)
     return UG_EINVAL;
   std::unique_ptr<Ctx> c(new (std::nothrow) Ctx());
@@ -943,6 +947,7 @@ ug_status ug_set_flags(void* ctx, int32_t policy, uint32_t flags) {
   p.exit = (flags & UG_F_EXIT) != 0;
   p.no_overlap = (flags & UG_F_NO_OVERLAP) != 0;
   p.graph = (flags & UG_F_GRAPH) != 0;
+  p.cpu_prio = (flags & UG_F_CPU_PRIO) != 0;
   return UG_OK;
 }
 

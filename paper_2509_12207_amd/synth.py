@@ -467,8 +467,12 @@ def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales, se
     return ChainDef(name, period_ns, deadline_ns, tasks, buffers, blocks)
 
 
+# E_cpu (ms) of the same rows of Tab. "Characteristics of an example workflow"
+ECPU_CFG1 = [17.4, 16.2, 21.0, 20.2, 21.8, 20.2, 21.8, 21.0, 21.3, 11.2, 17.8]
+
+
 def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
-            jitter_ms=15.0, chains_subset=None, custom=None):
+            jitter_ms=15.0, chains_subset=None, custom=None, cpu=0.0):
     """Eleven chains of 2-6 tasks with 50-300 FP32 kernels per task.
 
     Per-chain GPU work per frame is proportional to the paper's E_gpu of the
@@ -486,6 +490,11 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
     vector-add kernels run by round(U * 256) workgroups (utilisation U on
     256 CUs), each sized to take about T us under the time model, as many as
     keep the task's modelled time (fewer, longer kernels as T grows).
+
+    ``cpu`` > 0 gives every task a CPU segment (the CPU-scheduling
+    experiment, Sec. 4.3): a chain's CPU time per frame is cpu times its GPU
+    budget times the paper's E_cpu / E_gpu of the matching row, split over
+    the tasks like the GPU budget.
     """
     rng = np.random.default_rng([seed, 1])
     rows = CHAINS_CFG1 if chains_subset is None else [CHAINS_CFG1[i] for i in chains_subset]
@@ -509,7 +518,12 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
             scales.append(_fit_scale(tb, budget))
         period = period_ms * MS
         deadline = int(period * (0.5 if ci in tight else 1.0) * f_d)
-        chains.append(_build_chain(name, modality, period, deadline, task_blocks, scales))
+        ch = _build_chain(name, modality, period, deadline, task_blocks, scales)
+        if cpu > 0:
+            ecpu = ECPU_CFG1[CHAINS_CFG1.index(rows[ci])]
+            for j, task in enumerate(ch.tasks):
+                task["cpu_ns"] = int(cpu * e_chain * split[j] * ecpu / egpu)
+        chains.append(ch)
     arr = []
     arng = np.random.default_rng([seed, 3])
     window = int(window_s * 1e9)
@@ -528,7 +542,7 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
             k += 1
     arr.sort(key=lambda a: (a[2], a[0], a[1]))
     meta = {"f_a": f_a, "f_d": f_d, "f_tight": f_tight, "u_target": u_target,
-            "tight": sorted(tight), "window_s": window_s}
+            "tight": sorted(tight), "window_s": window_s, "cpu": cpu}
     return Workload("cfg1", chains, arr, seed, meta)
 
 

@@ -6,7 +6,7 @@ from paper_2509_12207_amd import capi
 
 NAMES = {capi.REC_COMPLETE: "COMPLETE", capi.REC_TSTART: "TSTART", capi.REC_BIND: "BIND",
          capi.REC_HOLD: "HOLD", capi.REC_EVREC: "EVREC", capi.REC_LAUNCH: "LAUNCH",
-         capi.REC_EXIT: "EXIT"}
+         capi.REC_EXIT: "EXIT", capi.REC_CPU: "CPU"}
 
 
 def record_to_tuple(r):
@@ -26,6 +26,8 @@ def record_to_tuple(r):
         return ("LAUNCH", c, f, int(r["kernel"]), int(r["a"]), int(r["b"]))
     if t == capi.REC_EXIT:
         return ("EXIT", c, f, int(r["task"]))
+    if t == capi.REC_CPU:
+        return ("CPU", c, f, int(r["task"]), int(r["a"]))
     raise ValueError(t)
 
 

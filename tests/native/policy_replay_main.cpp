@@ -6,7 +6,8 @@
 // input:
 //   cfg <policy> <bind> <delay> <batch> <calibrate> <delta> <poll> <th> <exempt>
 //       <calib_period> <admit> <admit_tasks> <exit> <no_overlap> <graph> <key>
-//       <noise_permille> <noise_seed> <max_hold> <nlevels> <lanes...>
+//       <noise_permille> <noise_seed> <max_hold> <cpu_cores> <cpu_prio> <nlevels>
+//       <lanes...>
 //   chain <deadline> <period> <ntasks>   (deadline 0: a best-effort chain)
 //     task <cpu_ns> <nkernels> (<est_ns> <util> <frame_dim> <npts> (<v> <e>)*)*
 //   instant <t> <narr> <nev>
@@ -26,13 +27,13 @@ int main() {
   ug::PolicyConfig cfg;
   std::cin >> tok;
   if (tok != "cfg") return 2;
-  int bind, delay, batch, cal, admit, ext, nov, graph, nlev;
+  int bind, delay, batch, cal, admit, ext, nov, graph, cprio, nlev;
   std::cin >> cfg.policy >> bind >> delay >> batch >> cal >> cfg.delta_eval_ns >>
       cfg.delay_poll_ns >> cfg.th_slack_ns >> cfg.util_exempt >> cfg.calib_period_ns >> admit >>
       cfg.admit_tasks >> ext >> nov >> graph >> cfg.order_key >> cfg.est_noise_permille >>
-      cfg.noise_seed >> cfg.max_hold_ns >> nlev;
+      cfg.noise_seed >> cfg.max_hold_ns >> cfg.cpu_cores >> cprio >> nlev;
   cfg.bind = bind, cfg.delay = delay, cfg.batch = batch, cfg.calibrate = cal, cfg.admit = admit;
-  cfg.exit = ext, cfg.no_overlap = nov, cfg.graph = graph;
+  cfg.exit = ext, cfg.no_overlap = nov, cfg.graph = graph, cfg.cpu_prio = cprio;
   cfg.lanes.assign(nlev, 0);
   for (int i = 0; i < nlev; ++i) std::cin >> cfg.lanes[i];
   ug::Policy pol(cfg);

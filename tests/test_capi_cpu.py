@@ -221,7 +221,8 @@ def _flags(cfg):
             | (capi.F_ADMIT if cfg.get("admit", True) else 0)
             | (capi.F_EXIT if cfg.get("exit", False) else 0)
             | (capi.F_NO_OVERLAP if cfg.get("no_overlap", False) else 0)
-            | (capi.F_GRAPH if cfg.get("graph", False) else 0))
+            | (capi.F_GRAPH if cfg.get("graph", False) else 0)
+            | (capi.F_CPU_PRIO if cfg.get("cpu_prio", False) else 0))
 
 
 def _gate_for(cfg):
@@ -235,7 +236,8 @@ def _gate_for(cfg):
                      order_key=cfg.get("key", "urgency"),
                      est_noise_permille=cfg.get("est_noise_permille", 0),
                      noise_seed=cfg.get("noise_seed", 0),
-                     max_hold_ns=cfg.get("max_hold_ns", 0))
+                     max_hold_ns=cfg.get("max_hold_ns", 0),
+                     cpu_cores=cfg.get("cpu_cores", 0))
 
 
 CFGS = [
@@ -258,6 +260,8 @@ CFGS = [
     {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "sjf"},
     {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "hrrn"},
     {"policy": "urgency", "th_slack_ns": 0, "key": "lcuf", "lanes": [2, 3, 3]},
+    {"policy": "urgency", "th_slack_ns": 2 * MS, "key": "saedf"},
+    {"policy": "urgency", "th_slack_ns": 0, "key": "eqdf", "admit_tasks": 2, "lanes": [1, 3]},
     {"policy": "urgency", "th_slack_ns": 3 * MS, "est_noise_permille": 300, "noise_seed": 5},
     {"policy": "urgency", "th_slack_ns": 3 * MS, "graph": True},
     {"policy": "urgency", "th_slack_ns": 0, "graph": True, "admit": False, "delay_poll_ns": 0},
@@ -266,6 +270,11 @@ CFGS = [
     {"policy": "urgency", "th_slack_ns": 3 * MS, "max_hold_ns": 2 * MS},
     {"policy": "urgency", "th_slack_ns": 3 * MS, "max_hold_ns": 700_000, "delay_poll_ns": 0},
     {"policy": "urgency", "th_slack_ns": 0, "max_hold_ns": 1 * MS, "admit_tasks": 1},
+    {"policy": "urgency", "th_slack_ns": 3 * MS, "cpu_cores": 1},
+    {"policy": "urgency", "th_slack_ns": 3 * MS, "cpu_cores": 1, "cpu_prio": True},
+    {"policy": "urgency", "th_slack_ns": 0, "cpu_cores": 2, "cpu_prio": True, "key": "edf",
+     "admit_tasks": 2},
+    {"policy": "fifo", "cpu_cores": 2},
     {"policy": "fifo"},
 ]
 

@@ -136,6 +136,69 @@ def test_alternative_orders_rank_as_defined(key, want):
     assert [d[1] for d in dec if d[0] == "LAUNCH"] == want
 
 
+@pytest.mark.parametrize("key,want", [
+    # four chains arriving at t = 0, CPU segments 0, one kernel per task,
+    # estimates in ms; every first task launches at once in rank order.
+    #   A: D 100, tasks [10, 10]  S = 80: SAEDF 10 + 80/2 = 50,  EQDF 10 + 80*10/20 = 50
+    #   B: D 100, tasks [40, 10]  S = 50: SAEDF 40 + 50/2 = 65,  EQDF 40 + 50*40/50 = 80
+    #   C: D 110, tasks [10, 50]  S = 50: SAEDF 10 + 50/2 = 35,  EQDF 10 + 50*10/60 = 18.3
+    #   D: D  70, tasks [30]      S = 40: SAEDF 30 + 40 = 70,    EQDF 30 + 40 = 70
+    ("saedf", [2, 0, 1, 3]),
+    ("eqdf", [2, 0, 3, 1]),
+    ("edf", [3, 0, 1, 2]),        # 70, 100, 100, 110 (tie A, B by chain)
+    ("urgency", [3, 1, 2, 0]),    # slack 40, 50, 50, 80 (tie B, C by chain)
+])
+def test_subtask_deadline_orders(key, want):
+    ch = [chain(100 * MS, [(0, [(10 * MS, 1.0)]), (0, [(10 * MS, 1.0)])]),
+          chain(100 * MS, [(0, [(40 * MS, 1.0)]), (0, [(10 * MS, 1.0)])]),
+          chain(110 * MS, [(0, [(10 * MS, 1.0)]), (0, [(50 * MS, 1.0)])]),
+          chain(70 * MS, [(0, [(30 * MS, 1.0)])])]
+    model = GateModel(ch, {"policy": "urgency", "key": key, "admit": False})
+    dec = model.instant(0, [(c, 0, 0) for c in range(4)], [])
+    assert [d[1] for d in dec if d[0] == "LAUNCH"] == want
+
+
+@pytest.mark.parametrize("rule", ["saedf", "eqdf"])
+def test_subtask_deadlines_split_the_slack_as_defined(rule):
+    # a chain whose every task starts exactly at its predecessor's deadline:
+    # the slack S0 = D - sum(w) is split into equal shares S0 / n (equal
+    # slack) or shares S0 * w_j / sum(w) (equal flexibility), and the last
+    # task's deadline is the chain's end-to-end deadline under both rules
+    from fractions import Fraction
+    w = [3 * MS, 11 * MS, 5 * MS, 7 * MS]
+    t_arr, D = 17 * MS, 61 * MS
+    s0 = D - sum(w)
+    t = Fraction(t_arr)
+    for j in range(len(w)):
+        d = P.subtask_deadline(rule, t, t_arr, D, w[j], sum(w[j:]), len(w) - j)
+        share = Fraction(s0, len(w)) if rule == "saedf" else Fraction(s0 * w[j], sum(w))
+        assert d - t - w[j] == share
+        t = d
+    assert t == t_arr + D
+    # a late task (negative slack) gets a deadline before its own work ends
+    assert P.subtask_deadline(rule, 50 * MS, 0, 40 * MS, 5 * MS, 10 * MS, 2) < 55 * MS
+    # no work left: the whole slack
+    assert P.subtask_deadline("eqdf", 5, 0, 20, 0, 0, 1) == 20
+
+
+def test_subtask_deadline_uses_the_current_task_and_its_start():
+    # chain A of the order test after its first task: task 1 started at 12 ms
+    # (task 0 ran 2 ms over its estimate), so S = 100 - 12 - 10 = 78 and both
+    # rules give task 1 (the last) the chain deadline, 100 ms; chain C's
+    # first task is still running: SAEDF 35 ms, EQDF 18.3 ms
+    from fractions import Fraction
+    ch = [chain(100 * MS, [(0, [(10 * MS, 1.0)]), (0, [(10 * MS, 1.0)])]),
+          chain(110 * MS, [(0, [(10 * MS, 1.0)]), (0, [(50 * MS, 1.0)])])]
+    for rule, want_c in (("saedf", Fraction(35 * MS)), ("eqdf", 10 * MS + Fraction(50 * MS, 6))):
+        model = GateModel(ch, {"policy": "urgency", "key": rule, "admit": False})
+        model.instant(0, [(0, 0, 0), (1, 0, 0)], [])
+        model.instant(12 * MS, [], [(0, 0, 0, START, 0), (0, 0, 0, END, 1)])
+        a, c = model.inst[(0, 0)], model.inst[(1, 0)]
+        assert a.task == 1 and a.task_t0 == 12 * MS
+        assert model._subtask_deadline(a, 12 * MS) == 100 * MS
+        assert model._subtask_deadline(c, 12 * MS) == want_c
+
+
 def test_hrrn_prefers_the_longer_wait():
     # HRRN at t = 4 ms: A (arrived at 0, R = 6 ms) has (4 + 6) / 6 = 1.67;
     # B (arrived at 3 ms, R = 1 ms) has (1 + 1) / 1 = 2: B first; SJF agrees
@@ -867,3 +930,89 @@ def test_frame_estimates_set_the_batches():
         assert len(starts) == n_batches
         des.check_log(ch, cfg, res["instants"])
         assert des.replay(ch, cfg, res["instants"]) is None
+
+
+# ------------------------------------------------------------------ CPU scheduling (Sec. 4.3)
+def _cpu_records(res):
+    return [(t, d[1], d[4]) for t, _, _, ds in res["instants"] for d in ds if d[0] == "CPU"]
+
+
+@pytest.mark.parametrize("prio", [False, True])
+def test_cpu_segments_share_one_core(prio):
+    # A: D 100 ms, CPU 5 ms, then a 1 ms kernel; B: D 10 ms, CPU 3 ms, then a
+    # 1 ms kernel; both arrive at 0 and there is one core.  First come, first
+    # served (ties by chain): A 0-5, B 5-8.  Urgency-centric: at 0 B's slack
+    # is 10 - 3 - 1 = 6 ms against A's 94 ms, so B runs 0-3, then A 3-8.
+    ch = [chain(100 * MS, [(5 * MS, [(1 * MS, 1.0)])]), chain(10 * MS, [(3 * MS, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "admit": False, "cpu_cores": 1, "cpu_prio": prio}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 0)], by_est(ch))
+    got = _launch_times_by_chain(res)
+    if prio:
+        assert got == {0: 8 * MS, 1: 3 * MS}
+        assert _cpu_records(res) == [(0, 1, 1), (3 * MS, 0, 1)]
+    else:
+        assert got == {0: 5 * MS, 1: 8 * MS}
+        assert _cpu_records(res) == [(0, 0, 1), (5 * MS, 1, 1)]
+    des.check_log(ch, cfg, res["instants"])
+
+
+def _launch_times_by_chain(res):
+    return {d[1]: t for t, _, _, ds in res["instants"] for d in ds if d[0] == "LAUNCH"}
+
+
+@pytest.mark.parametrize("prio", [False, True])
+def test_urgent_segment_preempts_on_its_start(prio):
+    # A (D 100 ms, CPU 5 ms) arrives at 0 and takes the core; B (D 10 ms,
+    # CPU 3 ms) arrives at 2 ms.  Urgency-centric: B's segment start ranks B
+    # first, A loses the core at 2 ms (2 ms of its 5 done) and resumes when
+    # B's segment ends at 5 ms, finishing at 8 ms.  First come, first served:
+    # A 0-5, B 5-8.
+    ch = [chain(100 * MS, [(5 * MS, [(1 * MS, 1.0)])]), chain(10 * MS, [(3 * MS, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "admit": False, "cpu_cores": 1, "cpu_prio": prio}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 2 * MS)], by_est(ch))
+    got = _launch_times_by_chain(res)
+    if prio:
+        assert got == {1: 5 * MS, 0: 8 * MS}
+        assert _cpu_records(res) == [(0, 0, 1), (2 * MS, 0, 0), (2 * MS, 1, 1), (5 * MS, 0, 1)]
+    else:
+        assert got == {0: 5 * MS, 1: 8 * MS}
+        assert _cpu_records(res) == [(0, 0, 1), (5 * MS, 1, 1)]
+
+
+def test_cpu_ranks_are_refreshed_only_at_segment_starts():
+    # two cores, three segments: A (D 50, CPU 4), B (D 40, CPU 4), C (D 30,
+    # CPU 4) arrive at 0, 0 and 1 ms, kernels of 1 ms.  At 0: ranks B, A; both
+    # run.  At 1 ms C starts: ranks C, B, A; A (the worst) yields its core to
+    # C and resumes at 4 ms, when B ends; C ends at 5 ms; A, with 3 ms left,
+    # ends at 7 ms.  The sleep of A is the only preemption.
+    ch = [chain(50 * MS, [(4 * MS, [(1 * MS, 1.0)])]), chain(40 * MS, [(4 * MS, [(1 * MS, 1.0)])]),
+          chain(30 * MS, [(4 * MS, [(1 * MS, 1.0)])])]
+    cfg = {"policy": "urgency", "admit": False, "cpu_cores": 2, "cpu_prio": True}
+    res = des.simulate(ch, cfg, [(0, 0, 0), (1, 0, 0), (2, 0, 1 * MS)], by_est(ch))
+    assert _cpu_records(res) == [(0, 0, 1), (0, 1, 1), (1 * MS, 0, 0), (1 * MS, 2, 1),
+                                 (4 * MS, 0, 1)]
+    assert _launch_times_by_chain(res) == {1: 4 * MS, 2: 5 * MS, 0: 7 * MS}
+    # without a CPU model (one core per segment) all three run at once
+    res = des.simulate(ch, {"policy": "urgency", "admit": False}, [(0, 0, 0), (1, 0, 0),
+                                                                 (2, 0, 1 * MS)], by_est(ch))
+    assert _cpu_records(res) == []
+    assert _launch_times_by_chain(res) == {0: 4 * MS, 1: 4 * MS, 2: 5 * MS}
+
+
+def test_cpu_model_with_enough_cores_changes_nothing():
+    # with as many cores as segments can ever run at once, the CPU model
+    # gives the same launches as one core per segment
+    r = np.random.default_rng(3)
+    chains = [chain(int(r.integers(20, 60)) * MS,
+                    [(int(r.integers(0, 4)) * 500 * US, [(int(r.integers(1, 5)) * 200 * US, 1.0)
+                                                         for _ in range(3)])
+                     for _ in range(3)]) for _ in range(4)]
+    arrivals = [(c, f, f * 10 * MS + c * 700 * US) for c in range(4) for f in range(4)]
+    base = des.simulate(chains, {"policy": "urgency", "th_slack_ns": 2 * MS}, arrivals,
+                        by_est(chains))
+    for prio in (False, True):
+        cfg = {"policy": "urgency", "th_slack_ns": 2 * MS, "cpu_cores": 64, "cpu_prio": prio}
+        res = des.simulate(chains, cfg, arrivals, by_est(chains))
+        strip = lambda ins: [[d for d in ds if d[0] != "CPU"] for _, _, _, ds in ins]
+        assert strip(res["instants"]) == strip(base["instants"])
+        assert res["completed"] == base["completed"]

@@ -12,12 +12,14 @@ import pytest
 
 from oracle import des
 
-KEYS = {"urgency": 0, "edf": 1, "sjf": 2, "hrrn": 3, "lcuf": 4}   # UG_KEY_* of ug.h
+KEYS = {"urgency": 0, "edf": 1, "sjf": 2, "hrrn": 3, "lcuf": 4, "saedf": 5,
+        "eqdf": 6}   # UG_KEY_* of ug.h
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2509_12207_amd", "csrc")
 MS, US = 1_000_000, 1_000
-NAMES = {4: "COMPLETE", 5: "TSTART", 6: "BIND", 7: "HOLD", 8: "EVREC", 9: "LAUNCH", 10: "EXIT"}
+NAMES = {4: "COMPLETE", 5: "TSTART", 6: "BIND", 7: "HOLD", 8: "EVREC", 9: "LAUNCH", 10: "EXIT",
+         12: "CPU"}
 
 
 @pytest.fixture(scope="module")
@@ -42,6 +44,8 @@ def _tuple(line):
         return (n, c, fr, t)
     if n in ("TSTART", "EXIT"):
         return (n, c, fr, task)
+    if n == "CPU":
+        return (n, c, fr, task, a)
     if n == "HOLD":
         return (n, c, fr, k, a)
     if n in ("BIND", "EVREC"):
@@ -55,7 +59,8 @@ def _encode(chains, cfg, instants):
          "util_exempt": 0.1, "calib_period_ns": 1_000_000, "admit": True, "admit_tasks": 4,
          "exit": False, "no_overlap": False, "graph": False, "key": "urgency",
          "est_noise_permille": 0,
-         "noise_seed": 0, "max_hold_ns": 0, "lanes": [2, 6]}
+         "noise_seed": 0, "max_hold_ns": 0, "cpu_cores": 0, "cpu_prio": False,
+         "lanes": [2, 6]}
     c.update(cfg)
     lines = [" ".join(str(x) for x in ["cfg", 1 if c["policy"] == "urgency" else 0, int(c["bind"]),
                                        int(c["delay"]), int(c["batch"]), int(c["calibrate"]),
@@ -64,7 +69,8 @@ def _encode(chains, cfg, instants):
                                        c["admit_tasks"], int(c["exit"]),
                                        int(c["no_overlap"]), int(c["graph"]), KEYS[c["key"]],
                                        c["est_noise_permille"], c["noise_seed"],
-                                       c["max_hold_ns"], len(c["lanes"]),
+                                       c["max_hold_ns"], c["cpu_cores"], int(c["cpu_prio"]),
+                                       len(c["lanes"]),
                                        *c["lanes"]])]
     for ch in chains:
         lines.append(f"chain {ch['deadline_ns']} {ch.get('period_ns', 0)} {len(ch['tasks'])}")
@@ -131,10 +137,13 @@ def test_sanitized_policy_matches_oracle(driver, seed, sized):
                 {"th_slack_ns": 2 * MS, "no_overlap": True, "delta_eval_ns": 0},
                 {"th_slack_ns": 2 * MS, "key": "edf"}, {"th_slack_ns": 2 * MS, "key": "sjf"},
                 {"th_slack_ns": 2 * MS, "key": "hrrn"}, {"th_slack_ns": 2 * MS, "key": "lcuf"},
+                {"th_slack_ns": 2 * MS, "key": "saedf"}, {"th_slack_ns": 2 * MS, "key": "eqdf"},
                 {"th_slack_ns": 2 * MS, "est_noise_permille": 300, "noise_seed": 11},
                 {"th_slack_ns": 2 * MS, "graph": True},
                 {"th_slack_ns": 3 * MS, "max_hold_ns": 2 * MS},
                 {"th_slack_ns": 0, "max_hold_ns": 1 * MS, "admit_tasks": 1, "delay_poll_ns": 0},
+                {"th_slack_ns": 3 * MS, "cpu_cores": 1, "cpu_prio": True},
+                {"th_slack_ns": 3 * MS, "cpu_cores": 2},
                 {"policy": "fifo"}):
         res = des.simulate(chains, cfg, arrivals, dur)
         text = _encode(chains, cfg, res["instants"])
