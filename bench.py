@@ -82,6 +82,8 @@ ADMIT = 16                # UG_F_ADMIT: task admission, the stand-in for stream 
 FULL = PAPER | ADMIT      # the gate as benchmarked
 NO_OVERLAP = 64           # UG_F_NO_OVERLAP: wait for a closed batch to finish
 CPU_PRIO = 512            # UG_F_CPU_PRIO: urgency-centric CPU scheduling
+GRAPH = 128               # UG_F_GRAPH: one captured graph per task
+FUSE = 1024               # UG_F_FUSE: tails run on the tail executor
 SWEEPS = {
     # mechanism ablation (Sec. 6.4): each mechanism alone, all, none
     "ablation": [{"name": "none", "flags": 0}, {"name": "bind", "flags": 1 | 4},
@@ -156,6 +158,14 @@ SWEEPS = {
     "cpu": [{"name": f"{n}_cores{k}{'_prio' if pr else ''}", "cpu": 1.0, "cores": k,
              "flags": f | (CPU_PRIO if pr else 0)}
             for k in (2, 3) for n, f in (("full", FULL), ("paper", PAPER)) for pr in (False, True)],
+    # configuration 2 (BF16 contractions, private block outputs): tails as
+    # launches, on the tail executor (device urgency queue), with task
+    # graphs; FIFO launch with fused tails beside plain FIFO
+    "fuse": [{"name": "paper", "wl": "cfg2", "flags": PAPER},
+             {"name": "paper+fuse", "wl": "cfg2", "flags": PAPER | FUSE},
+             {"name": "paper+graph+fuse", "wl": "cfg2", "flags": PAPER | GRAPH | FUSE},
+             {"name": "full+fuse", "wl": "cfg2", "flags": FULL | FUSE},
+             {"name": "fifo+fuse", "wl": "cfg2", "policy": "fifo", "flags": FUSE}],
     # FIFO launch with the gate's probe-based queue placement beside plain FIFO
     "fifo_placed": [{"name": "fifo_placed", "policy": "fifo", "flags": 256},
                     {"name": "full", "flags": FULL}],
@@ -169,18 +179,22 @@ def sweep_main(args, torch, capi, runner, synth):
         cu = v.get("custom")
         groups.setdefault((v.get("f_a", args.f_a), v.get("f_d", args.f_d),
                            json.dumps(cu, sort_keys=True) if cu else None, v.get("cpu", 0.0),
-                           v.get("cores", 0)), []).append(v)
+                           v.get("cores", 0), v.get("wl", "cfg1")), []).append(v)
     for seed in range(args.seed, args.seed + args.seeds):
-        for (fa, fd, cu, cpu, cores), variants in groups.items():
-            wl = synth.config1(seed=seed, f_a=fa, f_d=fd, window_s=float(W + K),
-                               custom=json.loads(cu) if cu else None, cpu=cpu)
+        for (fa, fd, cu, cpu, cores, wname), variants in groups.items():
+            if wname == "cfg2":
+                wl = synth.config2(seed=seed, f_a=fa, f_d=fd, window_s=float(W + K))
+            else:
+                wl = synth.config1(seed=seed, f_a=fa, f_d=fd, window_s=float(W + K),
+                                   custom=json.loads(cu) if cu else None, cpu=cpu)
             warm = [(c, f, t) for c, f, t in wl.arrivals if t < W * 1e9]
             timed = [(c, f, t - W * 10 ** 9) for c, f, t in wl.arrivals if t >= W * 1e9]
             dw = runner.DeviceWorkload(wl, n_sets=4)
             prof = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16)
             runner.profile(prof, dw, warmup=2, reps=5)
-            point = {"seed": seed, "f_a": fa, "f_d": fd, "frames": len(timed), "window_s": K,
-                     "custom": json.loads(cu) if cu else None, "cpu": cpu, "cpu_cores": cores}
+            point = {"seed": seed, "workload": wname, "f_a": fa, "f_d": fd, "frames": len(timed),
+                     "window_s": K, "custom": json.loads(cu) if cu else None, "cpu": cpu,
+                     "cpu_cores": cores}
             fifo = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16,
                                     cpu_cores=cores)
             runner.copy_estimates(prof, fifo, wl)
@@ -534,6 +548,8 @@ def summarise(m, st, wall, n_frames):
         "instants": int(st["instants"]),
         "gate_decide_us_per_instant": round(st["decide_ns"] / max(1, st["instants"]) / 1e3, 3),
         "launch_us_per_launch": round(st["launch_ns"] / max(1, st["launches"]) / 1e3, 3),
+        "tails_fused": int(st.get("tails_fused", 0)),
+        "executor_launches": int(st.get("executor_launches", 0)),
     }
 
 

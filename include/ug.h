@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define UG_ABI_VERSION 6u
+#define UG_ABI_VERSION 7u
 
 typedef int32_t ug_status;
 enum {
@@ -92,6 +92,20 @@ enum {
                           best ranks, preempting worse ones (fixed
                           priorities, as SCHED_FIFO); without it the cores
                           serve segments first come, first served      */
+  UG_F_FUSE = 1024u,    /* fused tails (configuration 2): the bias+ReLU
+                          after a contraction, with the row softmax and row
+                          sum of its output, runs as one work item of the
+                          tail executor (ug_tails_*) instead of as launches:
+                          the contraction counts its finished wavefronts on
+                          the device, the item is served from a device-side
+                          queue ordered by the gate's current urgency rank
+                          of its instance (Sec. 4.2), and the task's events
+                          count as observed only once the items published
+                          before them have finished.  A tail qualifies by
+                          the rule of ug_chain_tails; others launch as
+                          usual.  Applies to both policies (FIFO: items in
+                          publication order).  Decided at attach (the pool
+                          needs extra streams, see ug_streams_needed).    */
   UG_F_PLACE = 256u     /* queue placement of the stream pool: when streams
                           are attached (or created), the library measures
                           which hardware queue each one uses and assigns
@@ -302,6 +316,12 @@ typedef struct {
                               4.1: a segment runs on a core for its CPU time,
                               one segment per core); 0 = every segment runs
                               at once (no CPU contention).  0..1024 */
+  uint32_t fuse_workers;   /* with UG_F_FUSE: worker workgroups of the tail
+                              executor (1..1024, 64)                        */
+  int32_t pad1;
+  int64_t fuse_idle_ns;    /* with UG_F_FUSE: the executor leaves after this
+                              long without progress, and is launched again
+                              when items are pending (500 us)               */
 } ug_config;
 
 /* Completion of one frame (Sec. 6.2: latency, miss). */
@@ -372,6 +392,10 @@ typedef struct {
   uint64_t trace_dropped;  /* records lost because the log was full         */
   uint64_t frames_deferred; /* submissions refused by the HBM budget        */
   uint64_t hbm_peak_bytes; /* largest footprint of the frames in flight     */
+  uint64_t tails_fused;    /* tails published to the tail executor (FUSE)   */
+  uint64_t tails_unfused;  /* qualifying tails launched as kernels (no free
+                              slot, or buffers not 16-byte aligned)          */
+  uint64_t executor_launches; /* launches of the tail executor              */
 } ug_stats;
 
 /* ------------------------------------------------------------------------ */
@@ -513,7 +537,11 @@ ug_status ug_chain_set_footprint(void* ctx, uint32_t chain, uint64_t bytes);
 /* Number of streams ug_attach_streams expects: the sum of ug_config.lanes
  * (urgency policy: the stream pool of Sec. 4.4.3, level by level), or one
  * per task of every registered chain (FIFO launch: each task on its own
- * stream, the baseline of Sec. 6.3).  Errors: UG_EINVAL. */
+ * stream, the baseline of Sec. 6.3).  With UG_F_FUSE half as many again
+ * (rounded up): the tail executor runs on a stream of its own for as long
+ * as items keep coming, and a stream that shares its hardware queue would
+ * wait behind it, so the streams on that queue are set aside when others
+ * remain.  Errors: UG_EINVAL. */
 ug_status ug_streams_needed(void* ctx, uint32_t* n);
 
 /* Gives the context its stream pool (Sec. 4.4.3: the streams that tasks are
@@ -647,6 +675,84 @@ ug_status ug_kernel_launch_noalloc(const ug_kernel* k, void* const* buffers,
  * its grid occupies, min(1, workgroups / CUs).  Errors: UG_EINVAL,
  * UG_EDEVICE. */
 ug_status ug_kernel_util(const ug_kernel* k, int32_t device, float* util);
+
+/* ------------------------------------------------------------------------
+ * Fused tails (configuration 2, UG_F_FUSE).  The launch cost that batched
+ * launching amortises (Sec. 4.4.5) is, for the short pointwise and reduction
+ * kernels after each contraction, most of their time.  The tail executor is
+ * one long-lived kernel (one dispatcher and `workers` worker workgroups)
+ * that takes such tails from a queue in device memory: the host publishes an
+ * item with a key, the item becomes ready when its producer's completion
+ * counter reaches its target, and the executor serves ready items' tiles
+ * (groups of rows) smallest key first, so that the most urgent chain's work
+ * runs first (Sec. 4.2).  A tail computes y = max(x + b, +0) (the bias+ReLU
+ * of UG_OP_BIAS_RELU_F32, bit for bit), then optionally the softmax of each
+ * row of y and the sum of each row of y (FP32).  The gate uses it under
+ * UG_F_FUSE; the calls below drive it directly.  One thread at a time per
+ * queue. */
+typedef struct {
+  const float* x;          /* X[rows, cols] (device)                         */
+  float* y;                /* Y[rows, cols]; may equal x                     */
+  const float* bias;       /* b[cols] (axis 0) or b[rows] (axis 1)           */
+  float* sm;               /* softmax of the rows of Y [rows, cols]; NULL =
+                              none (cols <= 4096 with a softmax)            */
+  float* rs;               /* sums of the rows of Y [rows]; NULL = none       */
+  uint32_t* counter;       /* the producer's completion counter (device
+                              memory, zero before the producer's launch), or
+                              NULL: ready at once.  Reset to zero when the
+                              item becomes ready                             */
+  uint32_t counter_target; /* its value once the producer has finished (the
+                              *waves of ug_kernel_launch_signal)             */
+  uint32_t rows, cols;     /* cols a multiple of 4; x, y, sm and (axis 0)
+                              bias 16-byte aligned                          */
+  uint32_t axis;           /* 0: bias per column; 1: bias per row           */
+} ug_tail;
+
+/* Creates a queue with its executor's stream (default priority), pinned
+ * host memory and device memory (allocated here, freed by ug_tails_close).
+ * idle_ns: the executor leaves after this long without progress (it is
+ * launched again by ug_tails_kick).  log_cap (<= 8192): record the first
+ * log_cap tiles served as (publication << 24) | tile.  Errors: UG_EINVAL,
+ * UG_EDEVICE. */
+ug_status ug_tails_open(int32_t device, uint32_t workers, int64_t idle_ns, uint32_t log_cap,
+                        void** queue);
+/* Publishes an item with its key (smaller first); returns its slot and
+ * publication number.  Errors: UG_EINVAL (shape, alignment, NULL), UG_EAGAIN
+ * (all 512 slots hold unfinished items). */
+ug_status ug_tails_publish(void* queue, const ug_tail* t, uint64_t key, uint32_t* slot,
+                           uint64_t* pub);
+/* Rewrites the key of a published item (the gate's re-ranking). */
+ug_status ug_tails_set_key(void* queue, uint32_t slot, uint64_t key);
+/* Pause: while on, the executor starts no new tile (it still takes in
+ * items and keys). */
+ug_status ug_tails_pause(void* queue, int32_t on);
+/* Launches the executor if items are unfinished and it is not running. */
+ug_status ug_tails_kick(void* queue);
+/* 1 if the item published as `pub` in `slot` has finished (the slot is
+ * free again), 0 if not, < 0 on error. */
+int32_t ug_tails_finished(void* queue, uint32_t slot, uint64_t pub);
+/* Copies up to cap service-log entries; returns the count. */
+int32_t ug_tails_log(void* queue, uint64_t* out, uint32_t cap);
+/* Stops the executor, waits for it, frees everything. */
+ug_status ug_tails_close(void* queue);
+
+/* ug_kernel_launch with a completion counter: every wavefront of the
+ * kernel adds one to *counter (device memory) once its results are stored;
+ * *waves receives the total.  Only UG_OP_GEMM_F32, UG_OP_CONV3X3_F32,
+ * UG_OP_GEMM_BF16 and UG_OP_CONV3X3_BF16 take a counter (else UG_EINVAL). */
+ug_status ug_kernel_launch_signal(const ug_kernel* k, void* const* buffers,
+                                  uint32_t n_buffers, uint32_t* counter, uint32_t* waves,
+                                  void* hip_stream);
+
+/* The tails of a registered chain that UG_F_FUSE fuses: (first, end) kernel
+ * index ranges (chain-wide numbering), at most cap; returns the count or
+ * < 0.  A tail is a bias+ReLU right after a contraction whose output it
+ * reads, with at most one row softmax and one row sum of its output after
+ * it (same rows and row length); rows a multiple of 4 floats, at most 4096
+ * with a softmax; no per-frame sizes; and no later kernel of the task
+ * writes a buffer the tail reads or writes, or reads one it writes (so the
+ * tail may run outside the task's stream order). */
+int32_t ug_chain_tails(void* ctx, uint32_t chain, int32_t* first, int32_t* end, uint32_t cap);
 
 #ifdef __cplusplus
 }

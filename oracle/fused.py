@@ -16,12 +16,15 @@ Readings (the paper has no fused form; these are the choices built):
 
 * A tail is a bias+ReLU kernel whose input is the output of the kernel right
   before it in the task, that kernel being a contraction (FP32 or BF16 GEMM,
-  FP32 or BF16 3x3 convolution), followed by any number of row softmax and
-  row sum kernels that read the bias+ReLU output with the same rows and row
-  length.  It is fused only if no later kernel of the task writes a buffer
-  the tail reads or writes, or reads a buffer the tail writes, so that
-  running it outside the task's stream order changes no result; the task
-  counts as finished only once its tails have.
+  FP32 or BF16 3x3 convolution), followed by at most one row softmax and
+  at most one row sum (in either order) that read the bias+ReLU output with
+  the same rows and row length.  Rows are a multiple of 4 floats long, at
+  most 4096 with a softmax, and no kernel of the tail or its producer takes
+  a per-frame size (these are limits of the executor built).  It is fused
+  only if no later kernel of the task writes a buffer the tail reads or
+  writes, or reads a buffer the tail writes, so that running it outside the
+  task's stream order changes no result; the task counts as finished only
+  once its tails have.
 * An item's key is (rank of its chain instance in the gate's most recent
   urgency order, publication number): smaller keys are served first; two
   items of one instance keep their publication order.
@@ -37,6 +40,7 @@ The arithmetic of a tail is that of its kernels one after the other
 from . import kernels as K
 
 CONTRACTIONS = ("gemm", "conv3x3", "gemm_bf16", "conv3x3_bf16")
+MAX_SOFTMAX_ROW = 4096     # a fused softmax holds its row in registers
 
 
 def tail_outputs(x, bias, axis, softmax, rowsum):
@@ -76,10 +80,17 @@ def tail_runs(kernels):
         R, C = k["shape"][0], k["shape"][1]
         y = k["out"][0]
         end = i + 1
+        seen = set()
         while end < n and kernels[end]["op"] in ("softmax", "rowsum") \
+                and kernels[end]["op"] not in seen \
                 and kernels[end]["in"][0] == y \
                 and tuple(kernels[end]["shape"][:2]) == (R, C):
+            seen.add(kernels[end]["op"])
             end += 1
+        if C % 4 or ("softmax" in seen and C > MAX_SOFTMAX_ROW) \
+                or any(kk.get("frame_dim", 0) for kk in kernels[i - 1:end]):
+            i = end
+            continue
         reads, writes = set(), set()
         for kk in kernels[i:end]:
             reads |= _slots(kk["in"])

@@ -12,7 +12,7 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libug.so")
 
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ETIMEDOUT, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 POLICY_FIFO, POLICY_URGENCY = 0, 1
@@ -20,6 +20,7 @@ F_BIND, F_DELAY, F_BATCH, F_CALIBRATE, F_ADMIT, F_EXIT, F_NO_OVERLAP = 1, 2, 4, 
 F_GRAPH = 128
 F_PLACE = 256
 F_CPU_PRIO = 512
+F_FUSE = 1024
 
 KEY_URGENCY, KEY_EDF, KEY_SJF, KEY_HRRN, KEY_LCUF, KEY_SAEDF, KEY_EQDF = 0, 1, 2, 3, 4, 5, 6
 KEYS = {"urgency": KEY_URGENCY, "edf": KEY_EDF, "sjf": KEY_SJF, "hrrn": KEY_HRRN, "lcuf": KEY_LCUF,
@@ -56,6 +57,9 @@ EXPORTED = [
     "ug_kernel_launch", "ug_kernel_util", "ug_kernel_workspace", "ug_kernel_launch_ws",
     "ug_frame_submit_dims", "ug_chain_set_footprint", "ug_streams_needed", "ug_attach_streams",
     "ug_kernel_launch_noalloc", "ug_kernel_set_profile", "ug_kernel_get_profile",
+    "ug_tails_open", "ug_tails_publish", "ug_tails_set_key", "ug_tails_pause", "ug_tails_kick",
+    "ug_tails_finished", "ug_tails_log", "ug_tails_close", "ug_kernel_launch_signal",
+    "ug_chain_tails",
 ]
 
 
@@ -81,7 +85,8 @@ class Config(C.Structure):
                 ("admit_tasks", C.c_int64), ("hbm_budget_bytes", C.c_uint64),
                 ("order_key", C.c_int32), ("est_noise_permille", C.c_int32),
                 ("noise_seed", C.c_uint64), ("max_hold_ns", C.c_int64),
-                ("own_streams", C.c_int32), ("cpu_cores", C.c_int32)]
+                ("own_streams", C.c_int32), ("cpu_cores", C.c_int32),
+                ("fuse_workers", C.c_uint32), ("pad1", C.c_int32), ("fuse_idle_ns", C.c_int64)]
 
 
 class Completion(C.Structure):
@@ -103,7 +108,15 @@ class Stats(C.Structure):
                 ("batches", C.c_uint64), ("instants", C.c_uint64), ("collisions", C.c_uint64),
                 ("decide_ns", C.c_int64), ("launch_ns", C.c_int64),
                 ("trace_records", C.c_uint64), ("trace_dropped", C.c_uint64),
-                ("frames_deferred", C.c_uint64), ("hbm_peak_bytes", C.c_uint64)]
+                ("frames_deferred", C.c_uint64), ("hbm_peak_bytes", C.c_uint64),
+                ("tails_fused", C.c_uint64), ("tails_unfused", C.c_uint64),
+                ("executor_launches", C.c_uint64)]
+
+
+class Tail(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("bias", C.c_void_p), ("sm", C.c_void_p),
+                ("rs", C.c_void_p), ("counter", C.c_void_p), ("counter_target", C.c_uint32),
+                ("rows", C.c_uint32), ("cols", C.c_uint32), ("axis", C.c_uint32)]
 
 
 class Metrics(C.Structure):
@@ -186,6 +199,19 @@ def lib():
         L.ug_kernel_get_profile.argtypes = [vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_int64),
                                             C.POINTER(C.c_int64), C.c_uint32,
                                             C.POINTER(C.c_uint32)]
+        L.ug_tails_open.argtypes = [C.c_int32, C.c_uint32, C.c_int64, C.c_uint32, C.POINTER(vp)]
+        L.ug_tails_publish.argtypes = [vp, C.POINTER(Tail), C.c_uint64, C.POINTER(C.c_uint32),
+                                       C.POINTER(C.c_uint64)]
+        L.ug_tails_set_key.argtypes = [vp, C.c_uint32, C.c_uint64]
+        L.ug_tails_pause.argtypes = [vp, C.c_int32]
+        L.ug_tails_kick.argtypes = [vp]
+        L.ug_tails_finished.argtypes = [vp, C.c_uint32, C.c_uint64]
+        L.ug_tails_log.argtypes = [vp, C.POINTER(C.c_uint64), C.c_uint32]
+        L.ug_tails_close.argtypes = [vp]
+        L.ug_kernel_launch_signal.argtypes = [C.POINTER(Kernel), C.POINTER(vp), C.c_uint32, vp,
+                                              C.POINTER(C.c_uint32), vp]
+        L.ug_chain_tails.argtypes = [vp, C.c_uint32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.c_uint32]
         for name in ("ug_create", "ug_chain_register", "ug_kernel_set_estimate",
                      "ug_kernel_get_estimate", "ug_profile", "ug_set_threshold", "ug_set_flags",
                      "ug_start", "ug_frame_submit", "ug_poll_complete", "ug_drain", "ug_stop",
@@ -194,7 +220,10 @@ def lib():
                      "ug_kernel_launch", "ug_kernel_util", "ug_frame_submit_dims",
                      "ug_chain_set_footprint", "ug_streams_needed", "ug_attach_streams",
                      "ug_kernel_launch_noalloc", "ug_kernel_set_profile",
-                     "ug_kernel_get_profile"):
+                     "ug_kernel_get_profile", "ug_tails_open", "ug_tails_publish",
+                     "ug_tails_set_key", "ug_tails_pause", "ug_tails_kick", "ug_tails_finished",
+                     "ug_tails_log", "ug_tails_close", "ug_kernel_launch_signal",
+                     "ug_chain_tails"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -297,6 +326,79 @@ def now_ns():
     return int(lib().ug_now_ns())
 
 
+def kernel_launch_signal(k, ptrs, counter_ptr, stream=None):
+    """Launch a contraction that adds one per finished wavefront to the
+    device counter at ``counter_ptr``; returns the final count."""
+    ks = kernel_struct(k)
+    arr = pointer_array(ptrs)
+    waves = C.c_uint32()
+    st = lib().ug_kernel_launch_signal(C.byref(ks), arr, len(ptrs), C.c_void_p(counter_ptr),
+                                       C.byref(waves), C.c_void_p(stream or 0))
+    if st != OK:
+        raise UgError(st, f"ug_kernel_launch_signal({OP_NAMES.get(ks.op, ks.op)})")
+    return int(waves.value)
+
+
+class TailQueue:
+    """The tail executor's queue (ug_tails_*), driven directly."""
+
+    def __init__(self, device=0, workers=64, idle_ns=500_000, log_cap=0):
+        h = C.c_void_p()
+        st = lib().ug_tails_open(device, workers, idle_ns, log_cap, C.byref(h))
+        if st != OK:
+            raise UgError(st, "ug_tails_open")
+        self.h = h
+
+    def publish(self, x, y, bias, rows, cols, axis, key, sm=0, rs=0, counter=0, target=0):
+        t = Tail(x, y, bias, sm or None, rs or None, counter or None, target, rows, cols, axis)
+        slot, pub = C.c_uint32(), C.c_uint64()
+        st = lib().ug_tails_publish(self.h, C.byref(t), key, C.byref(slot), C.byref(pub))
+        if st != OK:
+            raise UgError(st, "ug_tails_publish")
+        return int(slot.value), int(pub.value)
+
+    def set_key(self, slot, key):
+        st = lib().ug_tails_set_key(self.h, slot, key)
+        if st != OK:
+            raise UgError(st, "ug_tails_set_key")
+
+    def pause(self, on):
+        st = lib().ug_tails_pause(self.h, 1 if on else 0)
+        if st != OK:
+            raise UgError(st, "ug_tails_pause")
+
+    def kick(self):
+        st = lib().ug_tails_kick(self.h)
+        if st != OK:
+            raise UgError(st, "ug_tails_kick")
+
+    def finished(self, slot, pub):
+        r = lib().ug_tails_finished(self.h, slot, pub)
+        if r < 0:
+            raise UgError(r, "ug_tails_finished")
+        return bool(r)
+
+    def log(self, cap=8192):
+        out = (C.c_uint64 * max(1, cap))()
+        n = lib().ug_tails_log(self.h, out, cap)
+        if n < 0:
+            raise UgError(n, "ug_tails_log")
+        return [int(out[i]) for i in range(n)]
+
+    def close(self):
+        if self.h:
+            st = lib().ug_tails_close(self.h)
+            self.h = None
+            if st != OK:
+                raise UgError(st, "ug_tails_close")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # --------------------------------------------------------------------------
 # context
 # --------------------------------------------------------------------------
@@ -377,6 +479,14 @@ class Gate:
                                      int(n_buffers), C.byref(cid))
         self._check(st, "ug_chain_register")
         return int(cid.value)
+
+    def chain_tails(self, chain, cap=4096):
+        """(first, end) kernel ranges of the chain's tails that UG_F_FUSE fuses."""
+        f = (C.c_int32 * max(1, cap))()
+        e = (C.c_int32 * max(1, cap))()
+        n = lib().ug_chain_tails(self.h, chain, f, e, cap)
+        self._check(min(n, 0), "ug_chain_tails")
+        return [(int(f[i]), int(e[i])) for i in range(n)]
 
     def set_estimate(self, chain, kernel, est_ns, util=-1.0):
         self._check(lib().ug_kernel_set_estimate(self.h, chain, kernel, int(est_ns), float(util)),

@@ -282,6 +282,16 @@ bool Policy::instant(int64_t t, std::vector<Arrival>& arrivals,
             ? kBestEffortSlack
             : in->t_arr + ch.deadline_ns - remaining(*in) - t;
   }
+  // the whole ranking, when asked for (the fused-tail queue's keys): every
+  // active instance, most urgent first
+  if (cfg_.keep_order) {
+    std::vector<Instance*> order(active);
+    if (cfg_.policy == UG_POLICY_URGENCY)
+      std::sort(order.begin(), order.end(),
+                [&](const Instance* a, const Instance* b) { return before(*a, *b, slack); });
+    order_.clear();
+    for (const Instance* in : order) order_.push_back({in->c, in->f});
+  }
   // 5. highest urgency among active kernels, for TH_urgent calibration,
   //    sampled periodically: at the first instant at or after each sampling
   //    time

@@ -48,6 +48,7 @@ struct PolicyConfig {
   int64_t max_hold_ns = 0;             // hold-age bound per task; 0 = none
   int32_t cpu_cores = 0;               // cores of the CPU segments; 0 = one each
   bool cpu_prio = false;               // urgency-centric CPU scheduling (Sec. 4.3)
+  bool keep_order = false;             // keep each instant's full ranking (order())
   std::vector<int32_t> lanes{2, 6};
 };
 
@@ -173,6 +174,10 @@ class Policy {
   uint64_t collisions() const { return collisions_; }
   int32_t fifo_lane(int32_t c, int32_t task) const { return fifo_base_[c] + task; }
   int32_t fifo_lanes() const { return fifo_total_; }
+  // Every active instance of the last instant, most urgent first under the
+  // configured order (FIFO policy: (chain, frame) order); kept only with
+  // keep_order.
+  const std::vector<Key>& order() const { return order_; }
 
  private:
   bool urgent(int64_t slack) const;
@@ -205,6 +210,7 @@ class Policy {
   std::map<std::pair<int32_t, int32_t>, int32_t> lane_load_;
   std::vector<Finished> finished_;
   std::vector<int64_t> samples_;
+  std::vector<Key> order_;
   int64_t active_ = 0;         // instances with launched, unconfirmed kernels
   bool sampled_ = false;       // a sample has been taken
   int64_t next_sample_ = 0;    // earliest time of the next sample

@@ -30,6 +30,7 @@
 
 #include "../kernels/ops.hpp"
 #include "policy.hpp"
+#include "tails.hpp"
 #include "ug.h"
 
 namespace {
@@ -54,8 +55,16 @@ struct DimRange {
 };
 
 using EvKey = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t>;  // c, f, task, kind, seq
-// a captured task: chain, task, the frame's buffer pointers and sizes
-using GraphKey = std::tuple<int32_t, int32_t, std::vector<void*>, std::vector<int64_t>>;
+// a captured task: chain, task, the frame's buffer pointers and sizes, and
+// whether its tails are fused (left out of the graph, producers counted)
+using GraphKey = std::tuple<int32_t, int32_t, std::vector<void*>, std::vector<int64_t>, bool>;
+using TaskKey = std::tuple<int32_t, int64_t, int32_t>;  // c, f, task
+
+// A tail published to the executor for an instance's task.
+struct TailRec {
+  uint32_t slot;
+  uint64_t pub;
+};
 
 struct Ctx {
   ug_config cfg{};
@@ -86,6 +95,27 @@ struct Ctx {
   std::map<GraphKey, hipGraphExec_t> graphs;
   hipStream_t capture_stream = nullptr;
   std::vector<Frame> pending;                           // submitted, not arrived
+
+  // fused tails (UG_F_FUSE): the tails of every chain ([chain][kernel]: the
+  // end of the tail the kernel starts, -1, or -2 inside a tail), the
+  // executor's queue and stream, one completion counter per kernel, the
+  // items published per task instance (in order) with the prefix seen
+  // finished, slots reserved by a producer's launch for its tail, the
+  // kernel up to which an instance's launches are covered by a fused tail,
+  // and the items each recorded event waits for
+  std::vector<std::vector<int32_t>> tail_mark;
+  std::unique_ptr<ug::TailQueue> tails;
+  hipStream_t fuse_stream = nullptr;
+  unsigned* counters = nullptr;
+  std::vector<size_t> counter_base;
+  std::map<TaskKey, std::vector<TailRec>> inst_tails;
+  std::map<TaskKey, size_t> inst_tails_done;
+  std::map<std::pair<ug::Key, int32_t>, uint32_t> reserved;
+  std::map<ug::Key, int32_t> covered_to;
+  std::map<EvKey, size_t> ev_tails;
+  std::vector<ug::Key> last_order;   // the ranking the queue's keys follow
+  std::atomic<uint64_t> st_tails{0}, st_tails_unfused{0};
+  uint64_t executor_launches = 0;    // of the last run (counted at ug_stop)
 
   std::mutex mu;  // inbox, outbox, counters, next_frame
   std::condition_variable cv_done;
@@ -175,6 +205,7 @@ ug::PolicyConfig policy_config(const ug_config& cfg) {
   p.max_hold_ns = cfg.max_hold_ns;
   p.cpu_cores = cfg.cpu_cores;
   p.cpu_prio = (cfg.flags & UG_F_CPU_PRIO) != 0;
+  p.keep_order = (cfg.flags & UG_F_FUSE) != 0;
   p.lanes.assign(cfg.lanes, cfg.lanes + cfg.n_levels);
   return p;
 }
@@ -214,12 +245,27 @@ hipEvent_t take_event(Ctx* c) {
   return e;
 }
 
+// True if the tail that kernel g of a chain starts is fused for this
+// frame: it qualifies (tail_mark) and the frame's buffers are aligned.
+bool tail_ok(const Ctx* c, int32_t chain, int32_t g, const Frame& fr, ug::FuseItem* it) {
+  const int32_t end = c->tail_mark[chain][g];
+  if (end <= g) return false;
+  ug::FuseItem tmp;
+  return ug::tail_item(c->policy.chains()[chain].kernels, g, end, fr.buffers.data(), it ? it : &tmp);
+}
+
+unsigned* counter_of(const Ctx* c, int32_t chain, int32_t g) {
+  return c->counters + c->counter_base[chain] + static_cast<size_t>(g);
+}
+
 // Graph of task j of a chain for a frame's buffers and sizes: captured on
 // first use (every kernel of the task in order on the capture stream, in
 // relaxed mode so other threads' HIP calls are unaffected), instantiated and
-// cached.  On failure returns null with *err set.
-hipGraphExec_t task_graph(Ctx* c, int32_t chain, int32_t j, const Frame& fr, hipError_t* err) {
-  GraphKey gk{chain, j, fr.buffers, fr.dims};
+// cached.  With `fused`, the task's fused tails are left out and their
+// producers count their wavefronts.  On failure returns null with *err set.
+hipGraphExec_t task_graph(Ctx* c, int32_t chain, int32_t j, const Frame& fr, bool fused,
+                          hipError_t* err) {
+  GraphKey gk{chain, j, fr.buffers, fr.dims, fused};
   auto it = c->graphs.find(gk);
   if (it != c->graphs.end()) return it->second;
   if (!c->capture_stream) {
@@ -231,10 +277,17 @@ hipGraphExec_t task_graph(Ctx* c, int32_t chain, int32_t j, const Frame& fr, hip
   if (*err != hipSuccess) return nullptr;
   hipError_t launch_err = hipSuccess;
   for (int32_t g = ch.task_first[j]; g < ch.task_end[j] && launch_err == hipSuccess; ++g) {
+    if (fused && tail_ok(c, chain, g, fr, nullptr)) {
+      g = c->tail_mark[chain][g] - 1;   // the tail runs on the executor
+      continue;
+    }
     ug_kernel k = ch.kernels[g];
     if (k.frame_dim > 0) k = ug::frame_kernel(k, fr.dims[k.frame_dim - 1]);
+    unsigned* sig = nullptr;
+    if (fused && g + 1 < ch.task_end[j] && tail_ok(c, chain, g + 1, fr, nullptr))
+      sig = counter_of(c, chain, g);
     launch_err = ug::launch_kernel(k, fr.buffers.data(), c->capture_stream, c->ws[chain][g],
-                                   c->ws_bytes[chain][g]);
+                                   c->ws_bytes[chain][g], sig);
   }
   hipGraph_t graph = nullptr;
   *err = hipStreamEndCapture(c->capture_stream, &graph);
@@ -249,6 +302,35 @@ hipGraphExec_t task_graph(Ctx* c, int32_t chain, int32_t j, const Frame& fr, hip
   if (*err != hipSuccess) return nullptr;
   c->graphs.emplace(std::move(gk), ge);
   return ge;
+}
+
+// Key of an item of instance `key`: the instance's rank in the gate's last
+// urgency order (1 = most urgent), then the publication number; FIFO
+// launch serves items in publication order.
+uint64_t tail_key(const Ctx* c, const ug::Key& key, uint64_t pub) {
+  if (c->cfg.policy == UG_POLICY_FIFO) return pub;
+  uint64_t rank = 0xffffffffull;
+  const auto& order = c->policy.order();
+  for (size_t r = 0; r < order.size(); ++r)
+    if (order[r] == key) {
+      rank = r + 1;
+      break;
+    }
+  return (rank << 32) | (pub & 0xffffffffull);
+}
+
+// Publishes the tail [g, end) of an instance's task into a reserved slot.
+void publish_tail(Ctx* c, const ug::Key& key, int32_t task, int32_t g, uint32_t slot,
+                  const Frame& fr) {
+  const ug::ChainSpec& ch = c->policy.chains()[key.first];
+  ug::FuseItem it;
+  (void)tail_item(ch.kernels, g, c->tail_mark[key.first][g], fr.buffers.data(), &it);
+  it.sig = reinterpret_cast<uint64_t>(counter_of(c, key.first, g - 1));
+  it.sig_expected = ug::signal_waves(ch.kernels[g - 1]);
+  const uint64_t pub = c->tails->publish(slot, it, tail_key(c, key, c->tails->next_pub()));
+  c->inst_tails[TaskKey{key.first, key.second, task}].push_back({slot, pub});
+  c->covered_to[key] = c->tail_mark[key.first][g];
+  c->st_tails++;
 }
 
 // Orders `pool` so that consecutive entries sit on different hardware queues
@@ -273,10 +355,32 @@ hipError_t place_over_queues(std::vector<hipStream_t>* pool, int* n_queues) {
   return hipSuccess;
 }
 
+uint32_t streams_used(const Ctx* c);
+
 // Gives the policy its streams: the lanes of every level in order (urgency
 // policy) or one stream per task of every chain (FIFO), from `pool`, placed
 // over the hardware queues first when UG_F_PLACE is set.
 hipError_t assign_streams(Ctx* c, std::vector<hipStream_t> pool) {
+  if (c->cfg.flags & UG_F_FUSE) {
+    // the executor's own stream, and the pool without the streams on its
+    // hardware queue (while any other remains); short of streams, lanes
+    // share the remaining ones in turn
+    hipError_t e = hipSuccess;
+    if (!c->fuse_stream &&
+        (e = hipStreamCreateWithFlags(&c->fuse_stream, hipStreamNonBlocking)) != hipSuccess)
+      return e;
+    std::vector<hipStream_t> probe{c->fuse_stream};
+    probe.insert(probe.end(), pool.begin(), pool.end());
+    std::vector<int> cls;
+    if ((e = ug::stream_queue_classes(probe, &cls)) != hipSuccess) return e;
+    std::vector<hipStream_t> keep;
+    for (size_t i = 1; i < probe.size(); ++i)
+      if (cls[i] != cls[0]) keep.push_back(probe[i]);
+    if (!keep.empty()) pool = std::move(keep);
+    const size_t n = streams_used(c), have = pool.size();
+    for (size_t i = have; i < n; ++i) pool.push_back(pool[i % have]);
+    pool.resize(n);
+  }
   if (c->cfg.flags & UG_F_PLACE) {
     hipError_t e = place_over_queues(&pool, &c->queue_classes);
     if (e != hipSuccess) return e;
@@ -292,11 +396,19 @@ hipError_t assign_streams(Ctx* c, std::vector<hipStream_t> pool) {
   return hipSuccess;
 }
 
-uint32_t streams_needed(const Ctx* c) {
+// Streams the policy uses: the lanes of every level, or one per task.
+uint32_t streams_used(const Ctx* c) {
   if (c->cfg.policy == UG_POLICY_FIFO) return static_cast<uint32_t>(c->policy.fifo_lanes());
   uint32_t n = 0;
   for (int lv = 0; lv < c->cfg.n_levels; ++lv) n += static_cast<uint32_t>(c->cfg.lanes[lv]);
   return n;
+}
+
+// Streams to attach: with fused tails half as many again, so that the
+// streams sharing the executor's hardware queue can be set aside.
+uint32_t streams_needed(const Ctx* c) {
+  const uint32_t n = streams_used(c);
+  return (c->cfg.flags & UG_F_FUSE) ? n + (n + 1) / 2 : n;
 }
 
 // Library-owned streams (own_streams): created at the default priority.
@@ -338,6 +450,12 @@ bool execute(Ctx* c, const std::vector<ug_record>& dec) {
           return false;
         }
         c->live_events[EvKey{d.chain, d.frame, d.task, d.a, d.b}] = e;
+        if (c->tails) {
+          // the event stands for every tail published before it as well
+          auto t = c->inst_tails.find(TaskKey{d.chain, d.frame, d.task});
+          c->ev_tails[EvKey{d.chain, d.frame, d.task, d.a, d.b}] =
+              t == c->inst_tails.end() ? 0 : t->second.size();
+        }
         if (d.a == 0) c->st_batches++;
         break;
       }
@@ -347,14 +465,66 @@ bool execute(Ctx* c, const std::vector<ug_record>& dec) {
         const int64_t t0 = mono_ns();
         const ug_kernel& kd = ch.kernels[d.kernel];
         hipError_t err;
+        const std::vector<int32_t>* mark = c->tails ? &c->tail_mark[d.chain] : nullptr;
         if (c->cfg.flags & UG_F_GRAPH) {
           // the task's first kernel launches the task's graph; its other
-          // kernels are inside it
+          // kernels are inside it.  With fused tails, every tail of the task
+          // that qualifies takes a slot and is published once the graph is
+          // launched (without enough free slots the unfused graph runs).
           err = hipSuccess;
           if (d.kernel == ch.task_first[d.task]) {
-            hipGraphExec_t ge = task_graph(c, d.chain, d.task, fr, &err);
+            std::vector<std::pair<int32_t, uint32_t>> pubs;
+            bool fused = false;
+            if (mark) {
+              fused = true;
+              for (int32_t g = ch.task_first[d.task]; g < ch.task_end[d.task]; ++g) {
+                if (!tail_ok(c, d.chain, g, fr, nullptr)) continue;
+                uint32_t slot = 0;
+                if (!c->tails->reserve(&slot)) {
+                  fused = false;
+                  break;
+                }
+                pubs.push_back({g, slot});
+              }
+              if (!fused) {
+                for (auto& p : pubs) c->tails->unreserve(p.second);
+                c->st_tails_unfused += pubs.size();
+                pubs.clear();
+              }
+            }
+            hipGraphExec_t ge = task_graph(c, d.chain, d.task, fr, fused && !pubs.empty(), &err);
             if (ge) err = hipGraphLaunch(ge, c->bound.at(key));
+            if (err == hipSuccess)
+              for (auto& p : pubs) publish_tail(c, key, d.task, p.first, p.second, fr);
           }
+        } else if (mark && (*mark)[d.kernel] == -2 && d.kernel < c->covered_to[key]) {
+          // inside a fused tail: the executor runs it
+          err = hipSuccess;
+        } else if (mark && (*mark)[d.kernel] > d.kernel) {
+          // the first kernel of a tail: published if its producer reserved
+          // a slot, else launched as usual
+          auto r = c->reserved.find({key, d.kernel});
+          if (r != c->reserved.end()) {
+            publish_tail(c, key, d.task, d.kernel, r->second, fr);
+            c->reserved.erase(r);
+            err = hipSuccess;
+          } else {
+            err = ug::launch_kernel(kd, fr.buffers.data(), c->bound.at(key));
+          }
+        } else if (mark && d.kernel + 1 < ch.task_end[d.task] &&
+                   tail_ok(c, d.chain, d.kernel + 1, fr, nullptr)) {
+          // the producer of a tail: counts its wavefronts when a slot is
+          // free for the tail
+          uint32_t slot = 0;
+          unsigned* sig = nullptr;
+          if (c->tails->reserve(&slot)) {
+            c->reserved[{key, d.kernel + 1}] = slot;
+            sig = counter_of(c, d.chain, d.kernel);
+          } else {
+            c->st_tails_unfused++;
+          }
+          err = ug::launch_kernel(kd, fr.buffers.data(), c->bound.at(key),
+                                  c->ws[d.chain][d.kernel], c->ws_bytes[d.chain][d.kernel], sig);
         } else if (kd.frame_dim > 0) {
           // this frame's size (checked at submission)
           const ug_kernel kf = ug::frame_kernel(kd, fr.dims[kd.frame_dim - 1]);
@@ -409,6 +579,7 @@ void deliver_completions(Ctx* c) {
     }
     c->frames.erase({f.c, f.f});
     c->bound.erase({f.c, f.f});
+    c->covered_to.erase({f.c, f.f});
     c->st_completed++;
     if (out.missed) c->st_missed++;
     if (c->outstanding > 0) --c->outstanding;
@@ -435,6 +606,16 @@ void gate_main(Ctx* c) {
     for (Frame& f : incoming) c->pending.push_back(std::move(f));
     incoming.clear();
 
+    // the tail executor runs while items are unfinished (it leaves when
+    // idle; launched again here)
+    if (c->tails && c->tails->outstanding()) {
+      const hipError_t e = c->tails->kick();
+      if (e != hipSuccess) {
+        hip_fail(c, e, "tail executor launch");
+        break;
+      }
+    }
+
     // 1. observe events: completed prefix of each instance's wait list
     evs.clear();
     bool dev_err = false;
@@ -449,6 +630,18 @@ void gate_main(Ctx* c) {
           hip_fail(c, q, "hipEventQuery");
           dev_err = true;
           break;
+        }
+        if (c->tails) {
+          // and the tails published before the event have finished
+          auto need = c->ev_tails.find(it->first);
+          if (need != c->ev_tails.end() && need->second > 0) {
+            const TaskKey tk{in.c, in.f, in.task};
+            const std::vector<TailRec>& recs = c->inst_tails[tk];
+            size_t& seen = c->inst_tails_done[tk];
+            while (seen < need->second && c->tails->finished(recs[seen].slot, recs[seen].pub))
+              ++seen;
+            if (seen < need->second) break;
+          }
         }
         evs.push_back({in.c, in.f, in.task, w.kind, w.seq});
       }
@@ -508,8 +701,31 @@ void gate_main(Ctx* c) {
       auto it = c->live_events.find(EvKey{e.c, e.f, e.task, e.kind, e.seq});
       c->event_pool.push_back(it->second);
       c->live_events.erase(it);
+      if (c->tails) {
+        c->ev_tails.erase(EvKey{e.c, e.f, e.task, e.kind, e.seq});
+        if (e.kind == 1) {   // task end: every item of the task has finished
+          c->inst_tails.erase(TaskKey{e.c, e.f, e.task});
+          c->inst_tails_done.erase(TaskKey{e.c, e.f, e.task});
+        }
+      }
     }
     if (!execute(c, dec)) break;
+    if (c->tails && c->tails->outstanding() && c->cfg.policy == UG_POLICY_URGENCY &&
+        c->policy.order() != c->last_order) {
+      // the device queue follows the gate's new ranking
+      c->last_order = c->policy.order();
+      std::map<ug::Key, uint64_t> rank;
+      for (size_t r = 0; r < c->last_order.size(); ++r) rank[c->last_order[r]] = r + 1;
+      for (const auto& kv : c->inst_tails) {
+        const ug::Key key{std::get<0>(kv.first), std::get<1>(kv.first)};
+        auto rk = rank.find(key);
+        const uint64_t hi = (rk == rank.end() ? 0xffffffffull : rk->second) << 32;
+        auto dn = c->inst_tails_done.find(kv.first);
+        for (size_t i = dn == c->inst_tails_done.end() ? 0 : dn->second; i < kv.second.size(); ++i)
+          c->tails->set_key(kv.second[i].slot, hi | (kv.second[i].pub & 0xffffffffull));
+      }
+      c->tails->commit_keys();
+    }
     deliver_completions(c);
   }
   c->cv_done.notify_all();
@@ -592,6 +808,8 @@ void ug_config_default(ug_config* cfg) {
   cfg->own_streams = 0;
   cfg->max_hold_ns = 0;
   cfg->cpu_cores = 0;
+  cfg->fuse_workers = 64;
+  cfg->fuse_idle_ns = 500000;
 }
 
 int64_t ug_now_ns(void) { return mono_ns(); }
@@ -621,6 +839,9 @@ ug_status ug_create(const ug_config* cfg, void** out) {
   if (cfg->own_streams != 0 && cfg->own_streams != 1) return UG_EINVAL;
   if (cfg->max_hold_ns < 0) return UG_EINVAL;
   if (cfg->cpu_cores < 0 || cfg->cpu_cores > 1024) return UG_EINVAL;
+  if ((cfg->flags & UG_F_FUSE) &&
+      (cfg->fuse_workers < 1 || cfg->fuse_workers > 1024 || cfg->fuse_idle_ns <= 0))
+    return UG_EINVAL;
   if (cfg->delta_eval_ns < 0 || cfg->delay_poll_ns < 0 || cfg->queue_capacity == 0 ||
       cfg->calib_period_ns < 0 || cfg->admit_tasks < 1 || cfg->order_key < UG_KEY_URGENCY ||
       cfg->order_key > UG_KEY_EQDF || cfg->est_noise_permille < 0 ||
@@ -657,6 +878,12 @@ void ug_destroy(void* ctx) {
   stop_thread(c);
   if (c->has_device) {
     (void)hipSetDevice(c->cfg.device);
+    c->tails.reset();
+    if (c->counters) (void)hipFree(c->counters);
+    if (c->fuse_stream) {
+      (void)hipStreamSynchronize(c->fuse_stream);
+      (void)hipStreamDestroy(c->fuse_stream);
+    }
     // every stream the gate launched on has drained before anything is freed
     for (auto& lv : c->level_streams)
       for (hipStream_t s : lv) (void)hipStreamSynchronize(s);
@@ -764,6 +991,10 @@ ug_status ug_chain_register(void* ctx, int64_t period_ns, int64_t deadline_ns,
     if (dr.hi[d] == INT64_MAX) dr.lo[d] = dr.hi[d] = 0;  // an unused index accepts 0
   c->ws.push_back(std::move(ws));
   c->ws_bytes.push_back(std::move(wsb));
+  std::vector<int32_t> mark(spec.kernels.size(), -1);
+  for (size_t j = 0; j < spec.task_first.size(); ++j)
+    ug::tail_runs(spec.kernels, spec.task_first[j], spec.task_end[j], &mark);
+  c->tail_mark.push_back(std::move(mark));
   const uint32_t id = c->policy.add_chain(std::move(spec));
   c->next_frame.push_back(0);
   c->footprint.push_back(0);
@@ -948,6 +1179,7 @@ ug_status ug_set_flags(void* ctx, int32_t policy, uint32_t flags) {
   p.no_overlap = (flags & UG_F_NO_OVERLAP) != 0;
   p.graph = (flags & UG_F_GRAPH) != 0;
   p.cpu_prio = (flags & UG_F_CPU_PRIO) != 0;
+  p.keep_order = (flags & UG_F_FUSE) != 0;
   return UG_OK;
 }
 
@@ -968,6 +1200,40 @@ ug_status ug_start(void* ctx) {
   }
   c->policy.reset();
   c->finalized = true;
+  c->inst_tails.clear();
+  c->inst_tails_done.clear();
+  c->reserved.clear();
+  c->covered_to.clear();
+  c->ev_tails.clear();
+  c->last_order.clear();
+  if (c->cfg.flags & UG_F_FUSE) {
+    if (c->cfg.fuse_workers < 1 || c->cfg.fuse_workers > 1024 || c->cfg.fuse_idle_ns <= 0)
+      return fail(c, UG_EINVAL, "fused tails need fuse_workers in 1..1024 and fuse_idle_ns > 0");
+    // one completion counter per kernel of every chain, zero between uses
+    size_t total = 0;
+    c->counter_base.clear();
+    for (const auto& ch : c->policy.chains()) {
+      c->counter_base.push_back(total);
+      total += ch.kernels.size();
+    }
+    hipError_t e = hipSuccess;
+    if (!c->fuse_stream &&
+        (e = hipStreamCreateWithFlags(&c->fuse_stream, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(c, e, "tail executor stream");
+    void* p = nullptr;
+    if ((e = hipMalloc(&p, std::max<size_t>(total, 1) * sizeof(unsigned))) != hipSuccess)
+      return hip_fail(c, e, "completion counters");
+    c->counters = static_cast<unsigned*>(p);
+    if ((e = hipMemset(p, 0, std::max<size_t>(total, 1) * sizeof(unsigned))) != hipSuccess)
+      return hip_fail(c, e, "completion counters");
+    c->tails.reset(new ug::TailQueue());
+    // lease: a minute per launch, renewed by the next launch
+    if ((e = c->tails->open(c->cfg.device, c->cfg.fuse_workers, c->cfg.fuse_idle_ns,
+                            int64_t(60) * 1000000000, 0, c->fuse_stream)) != hipSuccess) {
+      c->tails.reset();
+      return hip_fail(c, e, "tail executor");
+    }
+  }
   c->live_events.clear();
   c->event_pool = c->all_events;
   c->bound.clear();
@@ -984,7 +1250,8 @@ ug_status ug_start(void* ctx) {
   }
   // counters cover the frames since this start, like the metrics
   for (auto* a : {&c->st_submitted, &c->st_completed, &c->st_missed, &c->st_launches,
-                  &c->st_holds, &c->st_batches, &c->st_instants})
+                  &c->st_holds, &c->st_batches, &c->st_instants, &c->st_tails,
+                  &c->st_tails_unfused})
     a->store(0);
   c->st_decide_ns.store(0);
   c->st_launch_ns.store(0);
@@ -1083,9 +1350,14 @@ ug_status ug_stop(void* ctx) {
   c->started = false;
   if (c->has_device) {
     (void)hipSetDevice(c->cfg.device);
+    // the executor first: a stream on its hardware queue waits behind it
+    if (c->tails) c->executor_launches += c->tails->launches();
+    c->tails.reset();
     for (auto& lv : c->level_streams)
       for (hipStream_t s : lv) (void)hipStreamSynchronize(s);
     for (hipStream_t s : c->fifo_streams) (void)hipStreamSynchronize(s);
+    if (c->counters) (void)hipFree(c->counters);
+    c->counters = nullptr;
   }
   {
     std::lock_guard<std::mutex> lk(c->mu);
@@ -1110,6 +1382,9 @@ ug_status ug_get_stats(void* ctx, ug_stats* out) {
   out->collisions = c->started ? 0 : c->policy.collisions();
   out->decide_ns = c->st_decide_ns.load();
   out->launch_ns = c->st_launch_ns.load();
+  out->tails_fused = c->st_tails.load();
+  out->tails_unfused = c->st_tails_unfused.load();
+  out->executor_launches = c->executor_launches;
   {
     std::lock_guard<std::mutex> lk(c->mu);
     out->frames_deferred = c->st_deferred;
@@ -1302,6 +1577,126 @@ ug_status ug_kernel_util(const ug_kernel* k, int32_t device, float* util) {
   const double wgs = static_cast<double>(p.grid.x) * p.grid.y * p.grid.z;
   *util = static_cast<float>(std::min(1.0, wgs / static_cast<double>(cus)));
   return UG_OK;
+}
+
+// ---------------------------------------------------------------- tails
+
+ug_status ug_tails_open(int32_t device, uint32_t workers, int64_t idle_ns, uint32_t log_cap,
+                        void** queue) {
+  if (!queue || device < 0 || workers < 1 || workers > 1024 || idle_ns <= 0 ||
+      log_cap > ug::kFuseLogCap)
+    return UG_EINVAL;
+  *queue = nullptr;
+  std::unique_ptr<ug::TailQueue> q(new (std::nothrow) ug::TailQueue());
+  if (!q) return UG_ENOMEM;
+  const hipError_t e = q->open(device, workers, idle_ns, int64_t(60) * 1000000000, log_cap);
+  if (e != hipSuccess) return e == hipErrorInvalidValue ? UG_EINVAL : UG_EDEVICE;
+  *queue = q.release();
+  return UG_OK;
+}
+
+ug_status ug_tails_publish(void* queue, const ug_tail* t, uint64_t key, uint32_t* slot,
+                           uint64_t* pub) {
+  auto* q = static_cast<ug::TailQueue*>(queue);
+  if (!q || !t || !slot || !pub || !t->x || !t->y || !t->bias) return UG_EINVAL;
+  if (t->rows == 0 || t->cols == 0 || t->cols % 4 || t->axis > 1 ||
+      (t->sm && t->cols > ug::kFuseMaxSoftmaxRow) || (t->counter && t->counter_target == 0))
+    return UG_EINVAL;
+  uint64_t align = reinterpret_cast<uint64_t>(t->x) | reinterpret_cast<uint64_t>(t->y) |
+                   reinterpret_cast<uint64_t>(t->sm);
+  if (t->axis == 0) align |= reinterpret_cast<uint64_t>(t->bias);
+  if (align & 15) return UG_EINVAL;
+  ug::FuseItem it{};
+  it.x = reinterpret_cast<uint64_t>(t->x);
+  it.y = reinterpret_cast<uint64_t>(t->y);
+  it.bias = reinterpret_cast<uint64_t>(t->bias);
+  it.sm = reinterpret_cast<uint64_t>(t->sm);
+  it.rs = reinterpret_cast<uint64_t>(t->rs);
+  it.sig = reinterpret_cast<uint64_t>(t->counter);
+  it.sig_expected = t->counter_target;
+  it.R = t->rows;
+  it.C = t->cols;
+  it.axis = t->axis;
+  it.flags = (t->sm ? ug::kFuseSoftmax : 0u) | (t->rs ? ug::kFuseRowsum : 0u);
+  it.rows_per_tile = ug::fuse_rows_per_tile(it.C);
+  it.tiles = (it.R + it.rows_per_tile - 1) / it.rows_per_tile;
+  if (!q->reserve(slot)) return UG_EAGAIN;
+  *pub = q->publish(*slot, it, key);
+  return UG_OK;
+}
+
+ug_status ug_tails_set_key(void* queue, uint32_t slot, uint64_t key) {
+  auto* q = static_cast<ug::TailQueue*>(queue);
+  if (!q || slot >= ug::kFuseSlots) return UG_EINVAL;
+  q->set_key(slot, key);
+  q->commit_keys();
+  return UG_OK;
+}
+
+ug_status ug_tails_pause(void* queue, int32_t on) {
+  auto* q = static_cast<ug::TailQueue*>(queue);
+  if (!q) return UG_EINVAL;
+  q->set_pause(on != 0);
+  return UG_OK;
+}
+
+ug_status ug_tails_kick(void* queue) {
+  auto* q = static_cast<ug::TailQueue*>(queue);
+  if (!q) return UG_EINVAL;
+  return q->kick() == hipSuccess ? UG_OK : UG_EDEVICE;
+}
+
+int32_t ug_tails_finished(void* queue, uint32_t slot, uint64_t pub) {
+  auto* q = static_cast<ug::TailQueue*>(queue);
+  if (!q || slot >= ug::kFuseSlots) return UG_EINVAL;
+  return q->finished(slot, pub) ? 1 : 0;
+}
+
+int32_t ug_tails_log(void* queue, uint64_t* out, uint32_t cap) {
+  auto* q = static_cast<ug::TailQueue*>(queue);
+  if (!q || (!out && cap)) return UG_EINVAL;
+  return static_cast<int32_t>(q->read_log(out, cap));
+}
+
+ug_status ug_tails_close(void* queue) {
+  auto* q = static_cast<ug::TailQueue*>(queue);
+  if (!q) return UG_EINVAL;
+  const hipError_t e = q->halt();
+  delete q;
+  return e == hipSuccess ? UG_OK : UG_EDEVICE;
+}
+
+ug_status ug_kernel_launch_signal(const ug_kernel* k, void* const* buffers, uint32_t n_buffers,
+                                  uint32_t* counter, uint32_t* waves, void* hip_stream) {
+  if (!k || !buffers || !counter || !waves) return UG_EINVAL;
+  if (ug::validate_kernel(*k, n_buffers) || ug::signal_waves(*k) == 0) return UG_EINVAL;
+  const int32_t* slots[2] = {k->in, k->out};
+  const int counts[2] = {3, 4};
+  for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < counts[a]; ++i) {
+      const int32_t s = slots[a][i];
+      if (s >= 0 && (static_cast<uint32_t>(s) >= n_buffers || !buffers[s])) return UG_EINVAL;
+    }
+  *waves = ug::signal_waves(*k);
+  const hipError_t e = ug::launch_kernel(*k, buffers, static_cast<hipStream_t>(hip_stream),
+                                         nullptr, 0, counter);
+  return e == hipSuccess ? UG_OK : UG_EDEVICE;
+}
+
+int32_t ug_chain_tails(void* ctx, uint32_t chain, int32_t* first, int32_t* end, uint32_t cap) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c || chain >= c->tail_mark.size() || (cap && (!first || !end))) return UG_EINVAL;
+  const std::vector<int32_t>& m = c->tail_mark[chain];
+  uint32_t n = 0;
+  for (size_t g = 0; g < m.size(); ++g)
+    if (m[g] > static_cast<int32_t>(g)) {
+      if (n < cap) {
+        first[n] = static_cast<int32_t>(g);
+        end[n] = m[g];
+      }
+      ++n;
+    }
+  return static_cast<int32_t>(std::min(n, cap));
 }
 
 }  // extern "C"

@@ -20,6 +20,7 @@
 // or one per CU for a tile without a K split (measured faster than a K split).
 #include "mfma.hpp"
 #include "ops.hpp"
+#include "signal.hpp"
 
 namespace ug {
 namespace {
@@ -46,7 +47,7 @@ template <int WM, int WN, int TM, int TN, int KS, int TH, int TW>
 __global__ __launch_bounds__(256) void conv3x3_f32_kernel(const float* __restrict__ X,
                                                            const float* __restrict__ Wt,
                                                            float* __restrict__ Y, int C, int H,
-                                                           int W) {
+                                                           int W, unsigned* sig) {
   using Cf = ConvCfg<WM, WN, TM, TN, KS, TH, TW>;
   constexpr int BM = Cf::BM, SW = Cf::SW, PW = Cf::PW, PLANE = Cf::PLANE;
   __shared__ float lds[Cf::LDS];
@@ -195,7 +196,10 @@ __global__ __launch_bounds__(256) void conv3x3_f32_kernel(const float* __restric
           for (int q = 0; q < 16; ++q) red[((i * TN + j) * 16 + q) * 64 + lane] = acc[i][j][q];
     }
     __syncthreads();
-    if (ks > 0) return;
+    if (ks > 0) {
+      wave_done(sig);
+      return;
+    }
 #pragma unroll
     for (int s = 1; s < KS; ++s) {
       const float* red = lds + (s - 1) * PER * (WM * WN) + (wave % (WM * WN)) * PER;
@@ -222,6 +226,7 @@ __global__ __launch_bounds__(256) void conv3x3_f32_kernel(const float* __restric
         if (o < C) Yn[(size_t)o * plane + (size_t)yy * W + xx] = acc[i][j][q];
       }
   }
+  wave_done(sig);
 }
 
 // Tile shapes, largest first: {BM, TH, TW}.
@@ -260,9 +265,9 @@ int pick(int64_t N, int64_t C, int64_t H, int64_t W) {
 
 template <int WM, int WN, int TM, int TN, int KS, int TH, int TW>
 void launch(dim3 grid, hipStream_t s, const float* X, const float* Wt, float* Y, int C, int H,
-            int W) {
+            int W, unsigned* sig) {
   hipLaunchKernelGGL((conv3x3_f32_kernel<WM, WN, TM, TN, KS, TH, TW>), grid, dim3(256), 0, s, X,
-                     Wt, Y, C, H, W);
+                     Wt, Y, C, H, W, sig);
 }
 
 }  // namespace
@@ -284,15 +289,15 @@ OpPlan conv3x3_f32_plan(int64_t N, int64_t C, int64_t H, int64_t W) {
 }
 
 hipError_t conv3x3_f32_launch(const float* X, const float* Wt, float* Y, int64_t N, int64_t C,
-                              int64_t H, int64_t W, hipStream_t s) {
+                              int64_t H, int64_t W, hipStream_t s, unsigned* sig) {
   OpPlan p = conv3x3_f32_plan(N, C, H, W);
   const int c = (int)C, h = (int)H, w = (int)W;
   switch (pick(N, C, H, W)) {
-    case 0: launch<2, 2, 2, 2, 1, 8, 16>(p.grid, s, X, Wt, Y, c, h, w); break;
-    case 1: launch<1, 4, 2, 1, 1, 8, 16>(p.grid, s, X, Wt, Y, c, h, w); break;
-    case 2: launch<1, 4, 1, 1, 1, 8, 16>(p.grid, s, X, Wt, Y, c, h, w); break;
-    case 3: launch<1, 1, 2, 1, 4, 2, 16>(p.grid, s, X, Wt, Y, c, h, w); break;
-    default: launch<1, 1, 1, 1, 4, 2, 16>(p.grid, s, X, Wt, Y, c, h, w); break;
+    case 0: launch<2, 2, 2, 2, 1, 8, 16>(p.grid, s, X, Wt, Y, c, h, w, sig); break;
+    case 1: launch<1, 4, 2, 1, 1, 8, 16>(p.grid, s, X, Wt, Y, c, h, w, sig); break;
+    case 2: launch<1, 4, 1, 1, 1, 8, 16>(p.grid, s, X, Wt, Y, c, h, w, sig); break;
+    case 3: launch<1, 1, 2, 1, 4, 2, 16>(p.grid, s, X, Wt, Y, c, h, w, sig); break;
+    default: launch<1, 1, 1, 1, 4, 2, 16>(p.grid, s, X, Wt, Y, c, h, w, sig); break;
   }
   return hipGetLastError();
 }

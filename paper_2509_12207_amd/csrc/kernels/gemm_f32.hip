@@ -22,6 +22,7 @@
 // and B panels in its own L2), walked in groups of 8 tile-rows.
 #include "mfma.hpp"
 #include "ops.hpp"
+#include "signal.hpp"
 
 namespace ug {
 namespace {
@@ -60,7 +61,7 @@ template <int WM, int WN, int TM, int TN, int KS, bool VEC>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__ A,
                                                         const float* __restrict__ B,
                                                         float* __restrict__ C, int M, int N,
-                                                        int K) {
+                                                        int K, unsigned* sig) {
   using G = GemmCfg<WM, WN, TM, TN, KS>;
   constexpr int BM = G::BM, BN = G::BN, BKT = G::BKT, SA = G::SA, SB = G::SB;
   __shared__ float lds[G::LDS];
@@ -178,7 +179,10 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
           for (int r = 0; r < 16; ++r) red[((i * TN + j) * 16 + r) * 64 + lane] = acc[i][j][r];
     }
     __syncthreads();
-    if (ks > 0) return;
+    if (ks > 0) {
+      wave_done(sig);
+      return;
+    }
 #pragma unroll
     for (int s = 1; s < KS; ++s) {
       const float* red = lds + (s - 1) * PER * (WM * WN) + (wave % (WM * WN)) * PER;
@@ -203,6 +207,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
         if (m < M) C[(size_t)m * N + n] = acc[i][j][r];
       }
     }
+  wave_done(sig);
 }
 
 enum Shape { kBig = 0, kMid = 1, kSmall = 2 };
@@ -224,13 +229,13 @@ const void* fn(bool vec) {
 
 template <int WM, int WN, int TM, int TN, int KS>
 void launch(bool vec, dim3 grid, hipStream_t s, const float* A, const float* B, float* C, int M,
-            int N, int K) {
+            int N, int K, unsigned* sig) {
   if (vec)
     hipLaunchKernelGGL((gemm_f32_kernel<WM, WN, TM, TN, KS, true>), grid, dim3(256), 0, s, A, B,
-                       C, M, N, K);
+                       C, M, N, K, sig);
   else
     hipLaunchKernelGGL((gemm_f32_kernel<WM, WN, TM, TN, KS, false>), grid, dim3(256), 0, s, A, B,
-                       C, M, N, K);
+                       C, M, N, K, sig);
 }
 
 }  // namespace
@@ -258,18 +263,18 @@ OpPlan gemm_f32_plan(int64_t M, int64_t N, int64_t K, bool vec) {
 }
 
 hipError_t gemm_f32_launch(const float* A, const float* B, float* C, int64_t M, int64_t N,
-                           int64_t K, hipStream_t s) {
+                           int64_t K, hipStream_t s, unsigned* sig) {
   const bool vec = (K % 4 == 0) && (N % 4 == 0) && aligned16(A) && aligned16(B);
   OpPlan p = gemm_f32_plan(M, N, K, vec);
   switch (pick(M, N)) {
     case kBig:
-      launch<2, 2, 2, 2, 1>(vec, p.grid, s, A, B, C, (int)M, (int)N, (int)K);
+      launch<2, 2, 2, 2, 1>(vec, p.grid, s, A, B, C, (int)M, (int)N, (int)K, sig);
       break;
     case kMid:
-      launch<2, 2, 1, 1, 1>(vec, p.grid, s, A, B, C, (int)M, (int)N, (int)K);
+      launch<2, 2, 1, 1, 1>(vec, p.grid, s, A, B, C, (int)M, (int)N, (int)K, sig);
       break;
     default:
-      launch<1, 1, 1, 1, 4>(vec, p.grid, s, A, B, C, (int)M, (int)N, (int)K);
+      launch<1, 1, 1, 1, 4>(vec, p.grid, s, A, B, C, (int)M, (int)N, (int)K, sig);
   }
   return hipGetLastError();
 }

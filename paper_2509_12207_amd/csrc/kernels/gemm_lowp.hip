@@ -39,6 +39,7 @@
 //   one, in two padded LDS stages, feeds the matrix cores.
 #include "mfma.hpp"
 #include "ops.hpp"
+#include "signal.hpp"
 
 namespace ug {
 namespace {
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_ring(const unsigned char*
                                                             const unsigned char* __restrict__ Bt,
                                                             float* __restrict__ C, int M, int N,
                                                             int kb, int H = 0, int W = 0,
-                                                            int Cc = 0) {
+                                                            int Cc = 0, unsigned* sig = nullptr) {
   __shared__ __attribute__((aligned(1024))) unsigned char lds[RNST * RSTAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 2, wn = wave & 3;   // 2 x 4 waves
@@ -379,6 +380,7 @@ __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_ring(const unsigned char*
         if (row < M && col < N) C[(int64_t)row * N + col] = acc[i][j][r];
       }
     }
+  wave_done(sig);
 }
 
 }  // namespace
@@ -414,11 +416,12 @@ OpPlan gemm_bf16_plan(int64_t M, int64_t N, int64_t K) {
 }
 
 hipError_t gemm_bf16_launch(const uint16_t* A, const uint16_t* Bt, float* C, int64_t M,
-                            int64_t N, int64_t K, hipStream_t s) {
+                            int64_t N, int64_t K, hipStream_t s, unsigned* sig) {
   OpPlan p = gemm_bf16_plan(M, N, K);
   hipLaunchKernelGGL(gemm_ring<kRingBf16>, p.grid, p.block, 0, s,
                      reinterpret_cast<const unsigned char*>(A),
-                     reinterpret_cast<const unsigned char*>(Bt), C, (int)M, (int)N, (int)(2 * K));
+                     reinterpret_cast<const unsigned char*>(Bt), C, (int)M, (int)N, (int)(2 * K),
+                     0, 0, 0, sig);
   return hipGetLastError();
 }
 
@@ -431,12 +434,12 @@ OpPlan conv3x3_bf16_plan(int64_t C, int64_t H, int64_t W) {
 }
 
 hipError_t conv3x3_bf16_launch(const uint16_t* X, const uint16_t* Wt, float* Y, int64_t C,
-                               int64_t H, int64_t W, hipStream_t s) {
+                               int64_t H, int64_t W, hipStream_t s, unsigned* sig) {
   OpPlan p = conv3x3_bf16_plan(C, H, W);
   hipLaunchKernelGGL((gemm_ring<kRingBf16, true>), p.grid, p.block, 0, s,
                      reinterpret_cast<const unsigned char*>(Wt),
                      reinterpret_cast<const unsigned char*>(X), Y, (int)C, (int)(H * W),
-                     (int)(18 * C), (int)H, (int)W, (int)C);
+                     (int)(18 * C), (int)H, (int)W, (int)C, sig);
   return hipGetLastError();
 }
 

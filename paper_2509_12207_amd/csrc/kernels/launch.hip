@@ -174,17 +174,19 @@ ug_kernel frame_kernel(const ug_kernel& k, int64_t v) {
 }
 
 hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, void* ws,
-                         size_t ws_bytes) {
+                         size_t ws_bytes, unsigned* sig) {
+  if (sig && signal_waves(k) == 0) return hipErrorInvalidValue;
   const int64_t* s = k.shape;
   auto F = [&](int32_t slot) { return static_cast<float*>(b[slot]); };
   auto I = [&](int32_t slot) { return static_cast<int*>(b[slot]); };
   switch (k.op) {
     case UG_OP_GEMM_F32:
-      return gemm_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], s[2], st);
+      return gemm_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], s[2], st, sig);
     case UG_OP_BIAS_RELU_F32:
       return bias_relu_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], (int)s[2], st);
     case UG_OP_CONV3X3_F32:
-      return conv3x3_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], s[2], s[3], st);
+      return conv3x3_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], s[2], s[3], st,
+                                sig);
     case UG_OP_ROWSUM_F32:
       return rowsum_f32_launch(F(k.in[0]), F(k.out[0]), s[0], s[1], st);
     case UG_OP_SOFTMAX_F32:
@@ -208,7 +210,7 @@ hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, voi
       const auto* w = static_cast<const uint16_t*>(b[k.in[1]]);
       if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(w)) & 15)
         return hipErrorInvalidValue;
-      return conv3x3_bf16_launch(x, w, F(k.out[0]), s[1], s[2], s[3], st);
+      return conv3x3_bf16_launch(x, w, F(k.out[0]), s[1], s[2], s[3], st, sig);
     }
     case UG_OP_VECADD_F32:
       return vecadd_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1],
@@ -226,10 +228,24 @@ hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, voi
       const auto* bt = static_cast<const uint16_t*>(b[k.in[1]]);
       if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(bt)) & 15)
         return hipErrorInvalidValue;
-      return gemm_bf16_launch(a, bt, F(k.out[0]), s[0], s[1], s[2], st);
+      return gemm_bf16_launch(a, bt, F(k.out[0]), s[0], s[1], s[2], st, sig);
     }
     default:
       return hipErrorInvalidValue;
+  }
+}
+
+uint32_t signal_waves(const ug_kernel& k) {
+  switch (k.op) {
+    case UG_OP_GEMM_F32:
+    case UG_OP_CONV3X3_F32:
+    case UG_OP_GEMM_BF16:
+    case UG_OP_CONV3X3_BF16: {
+      const OpPlan p = plan_kernel(k);
+      return p.grid.x * p.grid.y * p.grid.z * (p.block.x * p.block.y * p.block.z / 64);
+    }
+    default:
+      return 0;
   }
 }
 

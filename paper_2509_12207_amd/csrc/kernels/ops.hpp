@@ -21,11 +21,11 @@ struct OpPlan {
 
 OpPlan gemm_f32_plan(int64_t M, int64_t N, int64_t K, bool vec);
 hipError_t gemm_f32_launch(const float* A, const float* B, float* C, int64_t M, int64_t N,
-                           int64_t K, hipStream_t s);
+                           int64_t K, hipStream_t s, unsigned* sig = nullptr);
 
 OpPlan conv3x3_f32_plan(int64_t N, int64_t C, int64_t H, int64_t W);
 hipError_t conv3x3_f32_launch(const float* X, const float* Wt, float* Y, int64_t N, int64_t C,
-                              int64_t H, int64_t W, hipStream_t s);
+                              int64_t H, int64_t W, hipStream_t s, unsigned* sig = nullptr);
 
 OpPlan bias_relu_f32_plan(int64_t R, int64_t C, int axis, bool vec);
 hipError_t bias_relu_f32_launch(const float* X, const float* b, float* Y, int64_t R, int64_t C,
@@ -47,14 +47,14 @@ hipError_t vecadd_f32_launch(const float* a, const float* b, float* c, int64_t n
 
 OpPlan conv3x3_bf16_plan(int64_t C, int64_t H, int64_t W);
 hipError_t conv3x3_bf16_launch(const uint16_t* X, const uint16_t* Wt, float* Y, int64_t C,
-                               int64_t H, int64_t W, hipStream_t s);
+                               int64_t H, int64_t W, hipStream_t s, unsigned* sig = nullptr);
 
 OpPlan accum_i32_plan(int64_t n);
 hipError_t accum_i32_launch(const int* x, int* st, int64_t n, hipStream_t s);
 
 OpPlan gemm_bf16_plan(int64_t M, int64_t N, int64_t K);
 hipError_t gemm_bf16_launch(const uint16_t* A, const uint16_t* Bt, float* C, int64_t M,
-                            int64_t N, int64_t K, hipStream_t s);
+                            int64_t N, int64_t K, hipStream_t s, unsigned* sig = nullptr);
 
 // Device workspace the voxel scatter needs (0: none); the launch fails with
 // hipErrorInvalidValue if it needs one and `ws` is missing or too small.
@@ -89,9 +89,16 @@ size_t workspace_bytes(const ug_kernel& k);
 
 // Launches the operation with buffers[slot] pointers and a workspace of
 // ws_bytes >= workspace_bytes(k) (may be null when none is needed).
+// `sig` (contractions only, see signal_waves) is a device counter to which
+// every wavefront of the kernel adds one once its results are stored.
 // Asynchronous.
 hipError_t launch_kernel(const ug_kernel& k, void* const* buffers, hipStream_t s,
-                         void* ws = nullptr, size_t ws_bytes = 0);
+                         void* ws = nullptr, size_t ws_bytes = 0, unsigned* sig = nullptr);
+
+// Wavefronts that add to a completion counter when the operation is
+// launched with one: 0 if the operation takes no counter (only the FP32 and
+// BF16 GEMM and 3x3 convolution do).
+uint32_t signal_waves(const ug_kernel& k);
 
 // Main-kernel launch shape of an operation.
 OpPlan plan_kernel(const ug_kernel& k);

@@ -30,7 +30,7 @@ class DeviceWorkload:
         self.inputs = []          # per chain: {slot: tensor} (read-only and state)
         self.outputs = []         # per chain: [ {slot: tensor} per set ] (outputs, host inputs)
         self.ptrs = []            # per chain: [ [ptr per slot] per set ]
-        dts = {"f32": torch.float32, "i32": torch.int32, "u8": torch.uint8}
+        dts = {"f32": torch.float32, "i32": torch.int32, "u8": torch.uint8, "bf16": torch.int16}
         for c, ch in enumerate(wl.chains):
             ins = {}
             for s, b in enumerate(ch.buffers):

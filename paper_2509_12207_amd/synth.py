@@ -44,7 +44,7 @@ VOXEL_FPARAM = (-51.2, -51.2, 5.0)
 @dataclasses.dataclass
 class Buffer:
     name: str
-    kind: str        # "f32", "i32" or "u8" (FP8 E4M3 codes)
+    kind: str        # "f32", "i32", "u8" (FP8 E4M3 codes) or "bf16" (bfloat16 codes)
     n: int           # elements
     role: str        # "in" (read-only, shared by every frame), "out" (one
     #                  copy per buffer set), "host" (pinned host memory, one
@@ -56,7 +56,7 @@ class Buffer:
 
     @property
     def nbytes(self):
-        return (1 if self.kind == "u8" else 4) * self.n
+        return {"u8": 1, "bf16": 2}.get(self.kind, 4) * self.n
 
 
 @dataclasses.dataclass
@@ -122,6 +122,12 @@ def input_array(seed, chain, slot, buf):
         xyz = rng.normal(0.0, sigma, (n, 3))
         inten = rng.uniform(0.0, 1.0, (n, 1))
         return np.concatenate([xyz, inten], axis=1).astype(np.float32).reshape(-1)
+    if kind == "bf16":
+        # bfloat16 codes: the upper halves of float32 values uniform in
+        # [lo, hi) (every one a bfloat16 value in that range), as int16
+        lo, hi = buf.init[1], buf.init[2]
+        f = rng.uniform(lo, hi, buf.n).astype(np.float32)
+        return (f.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
     if kind == "e4m3":
         # finite FP8 E4M3 codes: random sign and mantissa, exponent field
         # uniform in [e_lo, e_hi]
@@ -158,6 +164,14 @@ def k_vecadd(N, W, R, a, b, c):
 
 def k_gemm_fp8(M, N, K, a, bt, c, m0=0):
     return {"op": "gemm_fp8", "shape": (M, N, K, m0), "in": (a, bt), "out": (c,)}
+
+
+def k_gemm_bf16(M, N, K, a, bt, c):
+    return {"op": "gemm_bf16", "shape": (M, N, K), "in": (a, bt), "out": (c,)}
+
+
+def k_conv_bf16(Cc, H, W, x, w, y):
+    return {"op": "conv3x3_bf16", "shape": (1, Cc, H, W), "in": (x, w), "out": (y,)}
 
 
 def k_softmax(R, L, x, y):
@@ -221,6 +235,12 @@ def _model_ns(op, shape):
         return floor + 4 * R * Cn / 4e12 * 1e9
     if op == "voxel":
         return 3 * floor + 20 * shape[0] / 1e12 * 1e9
+    if op == "gemm_bf16":
+        M, N, K = shape
+        return floor + max(2 * M * N * K / 800e12, (2 * (M * K + K * N) + 4 * M * N) / 4e12) * 1e9
+    if op == "conv3x3_bf16":
+        _, Cc, H, W = shape
+        return floor + max(18 * Cc * Cc * H * W / 500e12, 6 * Cc * H * W / 4e12) * 1e9
     if op == "gemm_fp8":
         M, N, K = shape
         return floor + 2 * M * N * K / 2.5e15 * 1e9
@@ -300,13 +320,13 @@ def _shapes(b, s):
     return (b["n_points"],)
 
 
-def _block_time(b, s):
+def _block_time(b, s, bf16=False):
     if b["kind"] == "vecadd":
         return b["count"] * _model_ns("vecadd", (b["n"], b["w"], b["r"]))
     shp = _shapes(b, s)
     if b["kind"] == "dense":
         M, N, K = shp
-        t = _model_ns("gemm", shp) + _model_ns("bias_relu", (M, N))
+        t = _model_ns("gemm_bf16" if bf16 else "gemm", shp) + _model_ns("bias_relu", (M, N))
         if b["softmax"]:
             t += _model_ns("softmax", (M, N))
         if b["rowsum"]:
@@ -314,7 +334,8 @@ def _block_time(b, s):
         return t
     if b["kind"] == "conv":
         _, Cc, H, W = shp
-        t = _model_ns("conv3x3", shp) + _model_ns("bias_relu", (Cc, H * W))
+        t = _model_ns("conv3x3_bf16" if bf16 else "conv3x3", shp) + _model_ns("bias_relu",
+                                                                             (Cc, H * W))
         if b["rowsum"]:
             t += _model_ns("rowsum", (Cc, H * W))
         return t
@@ -333,26 +354,32 @@ def _custom_block(custom, task_ns, n=1 << 20):
     return {"kind": "vecadd", "n": n, "w": w, "r": r, "count": count, "q": [0.0, 0.0, 0.0]}
 
 
-def _fit_scale(blocks, budget_ns):
+def _fit_scale(blocks, budget_ns, bf16=False):
     lo, hi = 0.0, 1.0
-    if sum(_block_time(b, hi) for b in blocks) <= budget_ns:
+    if sum(_block_time(b, hi, bf16) for b in blocks) <= budget_ns:
         return hi
-    if sum(_block_time(b, lo) for b in blocks) >= budget_ns:
+    if sum(_block_time(b, lo, bf16) for b in blocks) >= budget_ns:
         return lo
     for _ in range(30):
         mid = 0.5 * (lo + hi)
-        if sum(_block_time(b, mid) for b in blocks) > budget_ns:
+        if sum(_block_time(b, mid, bf16) for b in blocks) > budget_ns:
             hi = mid
         else:
             lo = mid
     return lo
 
 
-def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales, serving=False):
+def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales, serving=False,
+                 private=False, bf16=False):
     """``serving``: voxel blocks take their points per frame (frame dim 1):
     uploaded from pinned host memory by a gated copy, binned, and added to
     the chain's device-resident cell counts; conv blocks with a
-    ``frame_shift`` take the frame's image size (frame dim 2)."""
+    ``frame_shift`` take the frame's image size (frame dim 2).
+    ``private``: every block writes buffers of its own (no double-buffered
+    outputs, no softmax / row-sum output shared by the task's blocks), so
+    that its epilogue may run outside stream order (fused tails).
+    ``bf16``: GEMMs and convolutions on bfloat16 operands (A row-major and B
+    transposed; NHWC activations and OHWI weights) with FP32 outputs."""
     buffers, tasks, blocks = [], [], []
     for j, (tb, s) in enumerate(zip(task_blocks, scales)):
         shapes = [_shapes(b, s) for b in tb]
@@ -363,27 +390,43 @@ def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales, se
             cur = need.get(key)
             need[key] = (max(n, cur[0]) if cur else n, role, init, kind)
 
-        for b, shp in zip(tb, shapes):
+        B16 = ("bf16", -1.0, 1.0)
+        for bi, (b, shp) in enumerate(zip(tb, shapes)):
+            sfx = str(bi) if private else ""
             if b["kind"] == "dense":
                 M, N, K = shp
-                want("in_a", M * K, "in")
-                want("in_b", K * N, "in")
+                if bf16:
+                    want("in_a16", M * K, "in", B16, "bf16")
+                    want("in_bt16", N * K, "in", B16, "bf16")
+                else:
+                    want("in_a", M * K, "in")
+                    want("in_b", K * N, "in")
                 want("bias_col", N, "in")
-                want("D0", M * N, "out")
-                want("D1", M * N, "out")
+                if private:
+                    want(f"D{bi}", M * N, "out")
+                else:
+                    want("D0", M * N, "out")
+                    want("D1", M * N, "out")
                 if b["softmax"]:
-                    want("SM", M * N, "out")
+                    want("SM" + sfx, M * N, "out")
                 if b["rowsum"]:
-                    want("RS", M, "out")
+                    want("RS" + sfx, M, "out")
             elif b["kind"] == "conv":
                 _, Cc, H, W = shp
-                want("in_x", Cc * H * W, "in")
-                want("in_w", Cc * Cc * 9, "in")
+                if bf16:
+                    want("in_x16", Cc * H * W, "in", B16, "bf16")
+                    want("in_w16", Cc * Cc * 9, "in", B16, "bf16")
+                else:
+                    want("in_x", Cc * H * W, "in")
+                    want("in_w", Cc * Cc * 9, "in")
                 want("bias_row", Cc, "in")
-                want("C0", Cc * H * W, "out")
-                want("C1", Cc * H * W, "out")
+                if private:
+                    want(f"C{bi}", Cc * H * W, "out")
+                else:
+                    want("C0", Cc * H * W, "out")
+                    want("C1", Cc * H * W, "out")
                 if b["rowsum"]:
-                    want("RS", Cc, "out")
+                    want("RS" + sfx, Cc, "out")
             elif b["kind"] == "vecadd":
                 n = shp[0]
                 want("VA", n, "in")
@@ -408,31 +451,40 @@ def _build_chain(name, modality, period_ns, deadline_ns, task_blocks, scales, se
         slot = {b.name: i for i, b in enumerate(buffers)}
         ks = []
         dn = cn = 0
-        for b, shp in zip(tb, shapes):
+        for bi, (b, shp) in enumerate(zip(tb, shapes)):
             first = len(ks)
+            sfx = str(bi) if private else ""
             if b["kind"] == "dense":
                 M, N, K = shp
-                out = slot[f"t{j}.D{dn % 2}"]
-                outs = {"C": f"t{j}.D{dn % 2}"}
+                dname = f"t{j}.D{bi}" if private else f"t{j}.D{dn % 2}"
+                out = slot[dname]
+                outs = {"C": dname}
                 dn += 1
-                ks.append(k_gemm(M, N, K, slot[f"t{j}.in_a"], slot[f"t{j}.in_b"], out))
+                if bf16:
+                    ks.append(k_gemm_bf16(M, N, K, slot[f"t{j}.in_a16"], slot[f"t{j}.in_bt16"], out))
+                else:
+                    ks.append(k_gemm(M, N, K, slot[f"t{j}.in_a"], slot[f"t{j}.in_b"], out))
                 ks.append(k_bias_relu(M, N, 0, out, slot[f"t{j}.bias_col"], out))
                 if b["softmax"]:
-                    ks.append(k_softmax(M, N, out, slot[f"t{j}.SM"]))
-                    outs["SM"] = f"t{j}.SM"
+                    ks.append(k_softmax(M, N, out, slot[f"t{j}.SM{sfx}"]))
+                    outs["SM"] = f"t{j}.SM{sfx}"
                 if b["rowsum"]:
-                    ks.append(k_rowsum(M, N, out, slot[f"t{j}.RS"]))
-                    outs["RS"] = f"t{j}.RS"
+                    ks.append(k_rowsum(M, N, out, slot[f"t{j}.RS{sfx}"]))
+                    outs["RS"] = f"t{j}.RS{sfx}"
             elif b["kind"] == "conv":
                 _, Cc, H, W = shp
-                out = slot[f"t{j}.C{cn % 2}"]
-                outs = {"Y": f"t{j}.C{cn % 2}"}
+                cname = f"t{j}.C{bi}" if private else f"t{j}.C{cn % 2}"
+                out = slot[cname]
+                outs = {"Y": cname}
                 cn += 1
-                ks.append(k_conv(1, Cc, H, W, slot[f"t{j}.in_x"], slot[f"t{j}.in_w"], out))
+                if bf16:
+                    ks.append(k_conv_bf16(Cc, H, W, slot[f"t{j}.in_x16"], slot[f"t{j}.in_w16"], out))
+                else:
+                    ks.append(k_conv(1, Cc, H, W, slot[f"t{j}.in_x"], slot[f"t{j}.in_w"], out))
                 ks.append(k_bias_relu(Cc, H * W, 1, out, slot[f"t{j}.bias_row"], out))
                 if b["rowsum"]:
-                    ks.append(k_rowsum(Cc, H * W, out, slot[f"t{j}.RS"]))
-                    outs["RS"] = f"t{j}.RS"
+                    ks.append(k_rowsum(Cc, H * W, out, slot[f"t{j}.RS{sfx}"]))
+                    outs["RS"] = f"t{j}.RS{sfx}"
                 if serving and "frame_shift" in b:
                     # the frame's image size v sets H = W = v >> shift (and
                     # the planes of the bias and the row sum)
@@ -472,7 +524,7 @@ ECPU_CFG1 = [17.4, 16.2, 21.0, 20.2, 21.8, 20.2, 21.8, 21.0, 21.3, 11.2, 17.8]
 
 
 def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
-            jitter_ms=15.0, chains_subset=None, custom=None, cpu=0.0):
+            jitter_ms=15.0, chains_subset=None, custom=None, cpu=0.0, private=False, bf16=False):
     """Eleven chains of 2-6 tasks with 50-300 FP32 kernels per task.
 
     Per-chain GPU work per frame is proportional to the paper's E_gpu of the
@@ -495,6 +547,8 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
     experiment, Sec. 4.3): a chain's CPU time per frame is cpu times its GPU
     budget times the paper's E_cpu / E_gpu of the matching row, split over
     the tasks like the GPU budget.
+
+    ``private`` and ``bf16``: see _build_chain (configuration 2).
     """
     rng = np.random.default_rng([seed, 1])
     rows = CHAINS_CFG1 if chains_subset is None else [CHAINS_CFG1[i] for i in chains_subset]
@@ -515,10 +569,11 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
             if custom is not None and j % 2 == 1:
                 tb = [_custom_block(custom, sum(_block_time(b, _fit_scale(tb, budget)) for b in tb))]
             task_blocks.append(tb)
-            scales.append(_fit_scale(tb, budget))
+            scales.append(_fit_scale(tb, budget, bf16))
         period = period_ms * MS
         deadline = int(period * (0.5 if ci in tight else 1.0) * f_d)
-        ch = _build_chain(name, modality, period, deadline, task_blocks, scales)
+        ch = _build_chain(name, modality, period, deadline, task_blocks, scales,
+                          private=private, bf16=bf16)
         if cpu > 0:
             ecpu = ECPU_CFG1[CHAINS_CFG1.index(rows[ci])]
             for j, task in enumerate(ch.tasks):
@@ -542,8 +597,22 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
             k += 1
     arr.sort(key=lambda a: (a[2], a[0], a[1]))
     meta = {"f_a": f_a, "f_d": f_d, "f_tight": f_tight, "u_target": u_target,
-            "tight": sorted(tight), "window_s": window_s, "cpu": cpu}
+            "tight": sorted(tight), "window_s": window_s, "cpu": cpu, "private": private,
+            "bf16": bf16}
     return Workload("cfg1", chains, arr, seed, meta)
+
+
+def config2(seed=0, f_a=1.0, f_d=1.0, u_target=1.6, window_s=10.0, **kw):
+    """Configuration 2: the eleven chains of configuration 1 drawn from the
+    same seeded streams, with BF16 GEMMs and convolutions (FP32 outputs) and
+    private block outputs, so that every bias+ReLU with its softmax / row
+    sum qualifies as a fused tail.  The generator sizes the contractions
+    with its BF16 time model, so the same u_target gives larger shapes than
+    configuration 1."""
+    wl = config1(seed=seed, f_a=f_a, f_d=f_d, u_target=u_target, window_s=window_s,
+                 private=True, bf16=True, **kw)
+    wl.name = "cfg2"
+    return wl
 
 
 def config4(seed=0, f_a=1.0, f_d=1.0, u_deadline=0.85, be_gemms=4, be_dim=8192, be_depth=2,

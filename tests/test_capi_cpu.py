@@ -51,7 +51,7 @@ def test_struct_layout_matches_c(tmp_path):
     probe = tmp_path / "probe.c"
     structs = {"ug_kernel": capi.Kernel, "ug_task": capi.Task, "ug_config": capi.Config,
                "ug_completion": capi.Completion, "ug_record": capi.Record,
-               "ug_stats": capi.Stats, "ug_metrics": capi.Metrics}
+               "ug_stats": capi.Stats, "ug_metrics": capi.Metrics, "ug_tail": capi.Tail}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ug.h"', 'int main(void){']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -353,4 +353,62 @@ def test_errors_from_many_threads_on_one_context():
     for t in th:
         t.join()
     assert not bad and seen <= {"not started", "no such kernel", ""}
+    g.close()
+
+
+def _random_task(rng):
+    """A task of contraction blocks over a few shared slots: bias+ReLU after
+    most contractions (on their output or not), optional softmax / row sum,
+    slots reused so that later kernels collide with earlier tails."""
+    nslot = int(rng.integers(4, 9))
+    ks = []
+    for _ in range(int(rng.integers(1, 6))):
+        out = int(rng.integers(0, nslot))
+        a, b = (int(v) for v in rng.integers(0, nslot, 2))
+        R = int(rng.choice([8, 32]))
+        C = int(rng.choice([32, 64, 6, 4100, 8192]))
+        kind = rng.choice(["gemm", "conv3x3", "gemm_bf16", "conv3x3_bf16", "softmax"])
+        if kind == "gemm":
+            ks.append({"op": "gemm", "shape": (R, C, 16), "in": (a, b), "out": (out,)})
+        elif kind == "gemm_bf16":
+            ks.append({"op": "gemm_bf16", "shape": (R, C, 32), "in": (a, b), "out": (out,)})
+        elif kind == "conv3x3":
+            ks.append({"op": "conv3x3", "shape": (1, 8, 4, 4), "in": (a, b), "out": (out,)})
+        elif kind == "conv3x3_bf16":
+            ks.append({"op": "conv3x3_bf16", "shape": (1, 32, 4, 4), "in": (a, b), "out": (out,)})
+        else:
+            ks.append({"op": "softmax", "shape": (R, C), "in": (a,), "out": (out,)})
+        if rng.uniform() < 0.8:
+            x = out if rng.uniform() < 0.85 else int(rng.integers(0, nslot))
+            y = x if rng.uniform() < 0.8 else int(rng.integers(0, nslot))
+            bias = int(rng.integers(0, nslot))
+            ks.append({"op": "bias_relu", "shape": (R, C, int(rng.integers(0, 2))),
+                       "in": (x, bias), "out": (y,)})
+            for op in rng.permutation(["softmax", "rowsum", "softmax"])[: int(rng.integers(0, 3))]:
+                src = y if rng.uniform() < 0.9 else int(rng.integers(0, nslot))
+                shp = (R, C) if rng.uniform() < 0.9 else (R, C + 4)
+                ks.append({"op": str(op), "shape": shp, "in": (src,),
+                           "out": (int(rng.integers(0, nslot)),)})
+    return ks, nslot
+
+
+def test_chain_tails_match_the_oracle():
+    """The tails the gate fuses (ug_chain_tails, C++) are the oracle's
+    (oracle.fused.tail_runs) on random tasks with colliding buffers."""
+    from oracle import fused as OF
+    rng = np.random.default_rng(7)
+    g = capi.Gate(device=-1)
+    total = 0
+    for _ in range(300):
+        tasks, expect, off, nb = [], [], 0, 1
+        for _ in range(int(rng.integers(1, 4))):
+            ks, nslot = _random_task(rng)
+            nb = max(nb, nslot)
+            tasks.append({"cpu_ns": 0, "kernels": [dict(k, est_ns=1000, util=1.0) for k in ks]})
+            expect += [(off + a, off + b) for a, b in OF.tail_runs(ks)]
+            off += len(ks)
+        cid = g.register_chain(100 * MS, 100 * MS, tasks, nb)
+        assert g.chain_tails(cid) == expect
+        total += len(expect)
+    assert total > 100
     g.close()

@@ -183,10 +183,16 @@ def check_cfg1_outputs(wl, dw, k=0, samples=6, seed=0):
         for name, (blk, role) in _last_writers(ch).items():
             j = blk.task
             got = dw.output(c, slot[name], k)
+            bf16 = f"t{j}.in_a16" in slot or f"t{j}.in_x16" in slot
             if blk.kind == "dense":
                 M, N, K = blk.shape
-                A = host(f"t{j}.in_a")[: M * K].reshape(M, K)
-                B = host(f"t{j}.in_b")[: K * N].reshape(K, N)
+                if bf16:
+                    # bfloat16 operands (B transposed), exact in float64
+                    A = OK.bf16_decode(host(f"t{j}.in_a16")[: M * K].view(np.uint16)).reshape(M, K)
+                    B = OK.bf16_decode(host(f"t{j}.in_bt16")[: N * K].view(np.uint16)).reshape(N, K).T
+                else:
+                    A = host(f"t{j}.in_a")[: M * K].reshape(M, K)
+                    B = host(f"t{j}.in_b")[: K * N].reshape(K, N)
                 bias = host(f"t{j}.bias_col")[:N]
                 rows = r.integers(0, M, samples)
                 for m in rows:
@@ -209,8 +215,15 @@ def check_cfg1_outputs(wl, dw, k=0, samples=6, seed=0):
                             (ch.name, name)
             elif blk.kind == "conv":
                 _, Cc, H, W = blk.shape
-                X = host(f"t{j}.in_x")[: Cc * H * W].reshape(1, Cc, H, W)
-                Wt = host(f"t{j}.in_w")[: Cc * Cc * 9].reshape(Cc, Cc, 3, 3)
+                if bf16:
+                    # NHWC activations and OHWI weights, as NCHW / OIHW values
+                    X = OK.bf16_decode(host(f"t{j}.in_x16")[: Cc * H * W].view(np.uint16)).reshape(
+                        H, W, Cc).transpose(2, 0, 1)[None]
+                    Wt = OK.bf16_decode(host(f"t{j}.in_w16")[: Cc * Cc * 9].view(np.uint16)).reshape(
+                        Cc, 3, 3, Cc).transpose(0, 3, 1, 2)
+                else:
+                    X = host(f"t{j}.in_x")[: Cc * H * W].reshape(1, Cc, H, W)
+                    Wt = host(f"t{j}.in_w")[: Cc * Cc * 9].reshape(Cc, Cc, 3, 3)
                 bias = host(f"t{j}.bias_row")[:Cc]
                 if role == "Y":
                     for o, y, x in zip(r.integers(0, Cc, samples), r.integers(0, H, samples),

@@ -73,6 +73,40 @@ def test_tail_runs_reused_buffers_stay_in_order():
     assert F.tail_runs(ks) == [(3, 4)]
 
 
+def test_tail_runs_needs_a_contraction_producing_the_input():
+    # bias+ReLU at the start of a task, after a softmax, or on a buffer the
+    # contraction did not write: not a tail
+    assert F.tail_runs([br(2, 3, 2), gemm(0, 1, 4)]) == []
+    assert F.tail_runs([gemm(0, 1, 2), sm(2, 4), br(4, 3, 4)]) == []
+    assert F.tail_runs([gemm(0, 1, 2), br(5, 3, 5)]) == []
+    # a softmax of another shape ends the tail before it, and then reads the
+    # tail's output later: nothing fuses
+    ks = [gemm(0, 1, 2), br(2, 3, 2), sm(2, 4, R=32, C=64)]
+    assert F.tail_runs(ks) == []
+    # the producer may read the tail's bias (it only writes the input)
+    ks = [gemm(0, 3, 2), br(2, 3, 2)]
+    assert F.tail_runs(ks) == [(1, 2)]
+
+
+def test_tail_runs_executor_limits():
+    # a second softmax ends the tail (and reads its output later)
+    ks = [gemm(0, 1, 2), br(2, 3, 2), sm(2, 4), sm(2, 5)]
+    assert F.tail_runs(ks) == []
+    # row sum then softmax is fine; rows of 4098 floats are not
+    ks = [gemm(0, 1, 2), br(2, 3, 2), rs(2, 5), sm(2, 4)]
+    assert F.tail_runs(ks) == [(1, 4)]
+    ks = [gemm(0, 1, 2), br(2, 3, 2, C=4098)]
+    assert F.tail_runs(ks) == []
+    # long rows without a softmax fuse; with one they do not
+    ks = [gemm(0, 1, 2), br(2, 3, 2, C=8192), rs(2, 5, C=8192)]
+    assert F.tail_runs(ks) == [(1, 3)]
+    ks = [gemm(0, 1, 2), br(2, 3, 2, C=8192), sm(2, 5, C=8192)]
+    assert F.tail_runs(ks) == []
+    # a per-frame size anywhere in the producer or the tail
+    ks = [dict(gemm(0, 1, 2), frame_dim=1), br(2, 3, 2)]
+    assert F.tail_runs(ks) == []
+
+
 def test_service_order_by_key_then_tiles():
     items = [{"key": (2, 0), "tiles": 2, "ready": 0},
              {"key": (1, 1), "tiles": 1, "ready": 0},
