@@ -67,6 +67,8 @@ def parse():
                          "urgency gate vs FIFO at a 64 GiB and at a tight budget")
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--tight-budget-mib", type=float, default=512.0)
+    ap.add_argument("--overhead", action="store_true",
+                    help="gate cost against the number of chains (Sec. 6.5), 2..44 chains")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the per-kernel roofline leg (plus a 1 GiB device copy of known "
                          "size, the scale for HBM byte counters)")
@@ -374,6 +376,63 @@ def pooled_seeds(seed_runs):
             "p50_ms": pct(50), "p99_ms": pct(99), "frames": frames, "missed": missed}
 
 
+def launch_floor(torch, capi):
+    """The raw launch loop (Sec. 6.5, Tab. "Basic operations"): host time
+    per launch call and device time per kernel of back-to-back launches on
+    one stream, for an almost empty kernel (a vector add of 64 floats by one
+    workgroup) and a small bias+ReLU (256 x 256)."""
+    out = {}
+    s = torch.cuda.Stream()
+    for name, k, n in (("empty", {"op": "vecadd", "shape": (64, 1, 1), "in": (0, 1), "out": (2,)},
+                        64),
+                       ("bias_relu_256x256", {"op": "bias_relu", "shape": (256, 256, 0),
+                                              "in": (0, 1), "out": (0,)}, 65536)):
+        bufs = [torch.zeros(n, device="cuda") for _ in range(3)]
+        torch.cuda.synchronize()
+        h, g = capi.launch_cost(k, [b.data_ptr() for b in bufs], n=4000, stream=s.cuda_stream)
+        out[name] = {"host_us_per_launch": round(h / 1e3, 3), "device_us_per_kernel": round(g / 1e3, 3)}
+    return out
+
+
+def overhead_main(args, torch, capi, runner, synth):
+    """Gate cost against the number of chains (Sec. 6.5, the scheduling-
+    overhead figure): configuration 1 with 2, 5 or 11 of its chains, or its
+    11 rows taken 2 or 4 times (22, 44 chains) at the same total load; the
+    full gate for K seconds each; decision time per instant and gate time
+    per launched kernel, beside the raw launch loop."""
+    W, K = args.warmup, args.steps
+    print(json.dumps({"overhead": "raw_launch_loop", **launch_floor(torch, capi)}), flush=True)
+    for n, subset, rep_ in ((2, [0, 3], 1), (5, [0, 2, 3, 8, 10], 1), (11, None, 1),
+                            (22, None, 2), (44, None, 4)):
+        wl = synth.config1(seed=args.seed, window_s=float(W + K), chains_subset=subset,
+                           repeat=rep_)
+        warm = [(c, f, t) for c, f, t in wl.arrivals if t < W * 1e9]
+        timed = [(c, f, t - W * 10 ** 9) for c, f, t in wl.arrivals if t >= W * 1e9]
+        dw = runner.DeviceWorkload(wl, n_sets=4)
+        g = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16)
+        runner.profile(g, dw, warmup=2, reps=5)
+        g.set_flags((FULL & ~capi.F_DELAY) | capi.F_CALIBRATE | capi.F_PLACE)
+        g.set_threshold(0)
+        run_policy(g, dw, warm, torch)
+        g.set_threshold(g.calibration_threshold(TH_PCT))
+        g.set_flags(FULL | capi.F_PLACE)
+        cu, m, st, wall = run_policy(g, dw, timed, torch)
+        u = summarise(m, st, wall, len(timed))
+        g.close()
+        rec = {"overhead": "chains", "n_chains": n, "frames": len(timed), "window_s": K,
+               "decide_us_per_instant": u["gate_decide_us_per_instant"],
+               "instants_per_s": round(st["instants"] / wall, 1),
+               "launch_us_per_launch": u["launch_us_per_launch"],
+               "gate_us_per_kernel": round((st["decide_ns"] + st["launch_ns"])
+                                           / max(1, st["launches"]) / 1e3, 3),
+               "gate_busy_pct": round(100.0 * (st["decide_ns"] + st["launch_ns"]) / (wall * 1e9), 2),
+               "miss_ratio_pct": u["miss_ratio_pct"], "p99_ms": u["p99_ms"]}
+        print(json.dumps(rec), flush=True)
+        log(f"overhead {n} chains: {rec}")
+        del dw
+        torch.cuda.empty_cache()
+
+
 def run_policy(g, dw, arrivals, torch, be=None):
     from paper_2509_12207_amd import runner
     g.start()
@@ -527,6 +586,10 @@ def pooled(runs, wl, n_frames, be_rate):
            "instants": st["instants"], "collisions": st["collisions"],
            "gate_decide_us_per_instant": round(st["decide_ns"] / max(1, st["instants"]) / 1e3, 3),
            "launch_us_per_launch": round(st["launch_ns"] / max(1, st["launches"]) / 1e3, 3),
+           "gate_us_per_kernel": round((st["decide_ns"] + st["launch_ns"])
+                                       / max(1, st["launches"]) / 1e3, 3),
+           "collision_hist_1_to_8plus": [sum(int(r[2]["collision_hist"][i]) for r in runs)
+                                         for i in range(8)],
            "per_run_miss_ratio_pct": [round(100.0 * r[1]["miss_ratio"], 3) for r in runs],
            "per_chain": per_chain(comps, wl)}
     return out | be_rate(comps, wall)
@@ -550,6 +613,8 @@ def summarise(m, st, wall, n_frames):
         "launch_us_per_launch": round(st["launch_ns"] / max(1, st["launches"]) / 1e3, 3),
         "tails_fused": int(st.get("tails_fused", 0)),
         "executor_launches": int(st.get("executor_launches", 0)),
+        "collisions": int(st.get("collisions", 0)),
+        "collision_hist_1_to_8plus": list(st.get("collision_hist", [])),
     }
 
 
@@ -724,6 +789,7 @@ def cpu_baseline(wl, budget_s):
     from paper_2509_12207_amd import synth
 
     per_chain = {}
+    frame_ms, deadline_ms = {}, {}
     kernels_done = 0
     kernels_total = 0
     spent = 0.0
@@ -751,13 +817,79 @@ def cpu_baseline(wl, budget_s):
         el = time.perf_counter() - t0
         spent += el
         per_chain[c] = (0 if done and el * 1e9 <= ch.deadline_ns else 1, 1)
+        # the whole frame on the CPU, projected from the kernels that ran
+        ran = max(1, kernels_done - sum(frame_ms.get("_k", [0])))
+        frame_ms[ch.name] = round(el / ran * n_k * 1e3, 1) if not done else round(el * 1e3, 1)
+        frame_ms.setdefault("_k", [0])[0] = kernels_done
+        deadline_ms[ch.name] = round(ch.deadline_ns / 1e6, 1)
+    frame_ms.pop("_k", None)
     miss = sum(m for m, _ in per_chain.values()) / len(per_chain)
     return {"value": round(100.0 * miss, 3), "unit": "% frames missed (Eq. 3)", "cores": threads,
             "kind": "oracle",
             "sample": (f"frame 0 of each of the {len(wl.chains)} chains, each run for at most its "
                        f"deadline; {kernels_done} of {kernels_total} kernels executed in "
                        f"{spent:.1f} s of CPU time"),
-            "kernels_per_s": round(kernels_done / max(spent, 1e-9), 2)}
+            "kernels_per_s": round(kernels_done / max(spent, 1e-9), 2),
+            "frame_ms_projected": frame_ms, "deadline_ms": deadline_ms,
+            **cpu_host(), "kernel_rates": cpu_kernel_rates()}
+
+
+def cpu_host():
+    """CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return {"cpu_model": model, "cores_usable": cores, "cpu_count": os.cpu_count()}
+
+
+def cpu_kernel_rates():
+    """The oracle's kernels (numpy, fp64 as written) on mid-size shapes,
+    timed on 1 core and on every core (threadpoolctl limits the BLAS
+    threads; the elementwise numpy parts use one core either way): best of
+    three, with the rate in the kernel's algorithmic FLOP or bytes."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import kernels as OK
+    r = np.random.default_rng(0)
+    A = r.uniform(-1, 1, (1024, 1024)).astype(np.float32)
+    X = r.uniform(-1, 1, (1, 64, 128, 128)).astype(np.float32)
+    Wt = r.uniform(-1, 1, (64, 64, 3, 3)).astype(np.float32)
+    Z = r.uniform(-1, 1, (2048, 2048)).astype(np.float32)
+    b = r.uniform(-1, 1, 2048).astype(np.float32)
+    n = 1 << 20
+    P = np.concatenate([r.normal(0, 20, (n, 3)), r.uniform(0, 1, (n, 1))], 1).astype(np.float32)
+    cases = [("gemm_1024^3", lambda: OK.gemm_f64(A, A), 2 * 1024 ** 3, "GFLOP/s"),
+             ("conv3x3_c64_128^2", lambda: OK.conv3x3_f64(X, Wt), 18 * 64 * 64 * 128 * 128,
+              "GFLOP/s"),
+             ("bias_relu_2048^2", lambda: OK.bias_relu_f32(Z, b, 0), 8 * 2048 * 2048, "GB/s"),
+             ("rowsum_2048^2", lambda: OK.rowsum_f64(Z), 4 * 2048 * 2048, "GB/s"),
+             ("softmax_2048^2", lambda: OK.softmax_f64(Z), 8 * 2048 * 2048, "GB/s"),
+             ("voxel_1Mi_points", lambda: OK.voxel_scatter(P), 20 * n, "GB/s")]
+    out = {}
+    for name, fn, work, unit in cases:
+        row = {}
+        for label, lim in (("1_core", 1), ("all_cores", None)):
+            with threadpool_limits(limits=lim):
+                best = min(_timed(fn) for _ in range(3))
+            row[label] = {"ms": round(best * 1e3, 3), unit: round(work / best / 1e9, 3)}
+        out[name] = row
+    return out
+
+
+def _timed(fn):
+    t = time.perf_counter()
+    fn()
+    return time.perf_counter() - t
 
 
 def _oracle_exec(OK, k, bufs):
@@ -815,6 +947,9 @@ def main():
         return
     if args.serve:
         serve_main(args, torch, capi, runner, synth)
+        return
+    if args.overhead:
+        overhead_main(args, torch, capi, runner, synth)
         return
     if args.roofline_only:
         kernels = [roofline_op(op, args.roofline_reps if op != "voxel" else 5, torch)
@@ -899,6 +1034,13 @@ def main():
     roof = next(r for r in kernels if r["kernel"] == dominant)
     ceiling = copy_ceiling(torch)
     log("hbm copy ceiling:", json.dumps(ceiling))
+    # gate cost per kernel against the raw launch loop (Sec. 6.5)
+    gate_overhead = {"raw_launch_loop": launch_floor(torch, capi)}
+    for n in names:
+        gate_overhead[n] = {k: summary[n][k] for k in ("gate_decide_us_per_instant",
+                                                        "launch_us_per_launch",
+                                                        "gate_us_per_kernel")}
+    log("gate overhead:", json.dumps(gate_overhead))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -949,6 +1091,7 @@ def main():
         | {"kernel": roof["kernel"], "shape": roof["shape"], "avg_us": roof["avg_us"]},
         "kernels": kernels,
         "hbm_copy_ceiling": ceiling,
+        "gate_overhead": gate_overhead,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -322,6 +322,9 @@ typedef struct {
   int64_t fuse_idle_ns;    /* with UG_F_FUSE: the executor leaves after this
                               long without progress, and is launched again
                               when items are pending (500 us)               */
+  const char* tile_table;  /* a tile-variant table file (ug_tile_load) read
+                              by ug_create into the process-wide table, or
+                              NULL                                           */
 } ug_config;
 
 /* Completion of one frame (Sec. 6.2: latency, miss). */
@@ -396,6 +399,9 @@ typedef struct {
   uint64_t tails_unfused;  /* qualifying tails launched as kernels (no free
                               slot, or buffers not 16-byte aligned)          */
   uint64_t executor_launches; /* launches of the tail executor              */
+  uint64_t collision_hist[8]; /* collisions by the number of other chains'
+                              instances with kernels in flight: 1, 2, ...,
+                              7, and 8 or more (Sec. 6.4)                  */
 } ug_stats;
 
 /* ------------------------------------------------------------------------ */
@@ -743,6 +749,43 @@ ug_status ug_tails_close(void* queue);
 ug_status ug_kernel_launch_signal(const ug_kernel* k, void* const* buffers,
                                   uint32_t n_buffers, uint32_t* counter, uint32_t* waves,
                                   void* hip_stream);
+
+/* The raw launch loop of the system-overhead comparison (Sec. 6.5, Tab.
+ * "Basic operations"): launches kernel k n times back to back on hip_stream
+ * (after 8 untimed launches), then waits.  *host_ns: mean host time per
+ * launch call; *gpu_ns: mean device time per kernel over the loop (HIP
+ * events around it, so it includes the gaps between kernels).  The cost
+ * the gate adds per kernel is set against these.  No workspace kernels
+ * (UG_EINVAL).  Synchronous.  Errors: UG_EINVAL, UG_EDEVICE. */
+ug_status ug_launch_cost(const ug_kernel* k, void* const* buffers, uint32_t n_buffers,
+                         uint32_t n, void* hip_stream, int64_t* host_ns, int64_t* gpu_ns);
+
+/* Tile variants (the autotuner of configuration 2).  The FP32 GEMM has 3
+ * tile shapes (0: 128x128, 1: 64x64, 2: 32x32 with a four-way K split) and
+ * the FP32 3x3 convolution 5 (output channels x pixel patch, 0: 128 x 8x16,
+ * 1: 64 x 8x16, 2: 32 x 8x16, 3: 64 x 2x16 and 4: 32 x 2x16 with a four-way
+ * K split); each launcher picks one by a fixed rule unless the process-wide
+ * tuning table names one for the exact (op, shape).  Every variant computes
+ * the same sums in its own order (results within the op's tolerance, exact
+ * for integer-valued inputs).  Set the table before launching (a change is
+ * published as a new copy; launches in flight see the old or the new one).
+ *   ug_tile_variants   number of variants of an op (0: one tile only)
+ *   ug_tile_set        table entry for (op, shape[4]); variant -1 removes it
+ *   ug_tile_clear      empty the table
+ *   ug_tile_get        the variant a launch of k takes now (-1: one tile)
+ *   ug_tile_load       add the entries of a table file: lines
+ *                      "op s0 s1 s2 s3 variant", '#' starts a comment;
+ *                      *n_added receives the count; a malformed line adds
+ *                      nothing (UG_EINVAL)
+ *   ug_kernel_launch_variant  ug_kernel_launch at a given variant (timing)
+ * Errors: UG_EINVAL. */
+int32_t ug_tile_variants(int32_t op);
+ug_status ug_tile_set(int32_t op, const int64_t* shape, int32_t variant);
+ug_status ug_tile_clear(void);
+int32_t ug_tile_get(const ug_kernel* k);
+ug_status ug_tile_load(const char* path, uint32_t* n_added);
+ug_status ug_kernel_launch_variant(const ug_kernel* k, void* const* buffers, uint32_t n_buffers,
+                                   int32_t variant, void* hip_stream);
 
 /* The tails of a registered chain that UG_F_FUSE fuses: (first, end) kernel
  * index ranges (chain-wide numbering), at most cap; returns the count or

@@ -59,7 +59,8 @@ EXPORTED = [
     "ug_kernel_launch_noalloc", "ug_kernel_set_profile", "ug_kernel_get_profile",
     "ug_tails_open", "ug_tails_publish", "ug_tails_set_key", "ug_tails_pause", "ug_tails_kick",
     "ug_tails_finished", "ug_tails_log", "ug_tails_close", "ug_kernel_launch_signal",
-    "ug_chain_tails",
+    "ug_chain_tails", "ug_launch_cost", "ug_tile_variants", "ug_tile_set", "ug_tile_clear",
+    "ug_tile_get", "ug_tile_load", "ug_kernel_launch_variant",
 ]
 
 
@@ -86,7 +87,8 @@ class Config(C.Structure):
                 ("order_key", C.c_int32), ("est_noise_permille", C.c_int32),
                 ("noise_seed", C.c_uint64), ("max_hold_ns", C.c_int64),
                 ("own_streams", C.c_int32), ("cpu_cores", C.c_int32),
-                ("fuse_workers", C.c_uint32), ("pad1", C.c_int32), ("fuse_idle_ns", C.c_int64)]
+                ("fuse_workers", C.c_uint32), ("pad1", C.c_int32), ("fuse_idle_ns", C.c_int64),
+                ("tile_table", C.c_char_p)]
 
 
 class Completion(C.Structure):
@@ -110,7 +112,7 @@ class Stats(C.Structure):
                 ("trace_records", C.c_uint64), ("trace_dropped", C.c_uint64),
                 ("frames_deferred", C.c_uint64), ("hbm_peak_bytes", C.c_uint64),
                 ("tails_fused", C.c_uint64), ("tails_unfused", C.c_uint64),
-                ("executor_launches", C.c_uint64)]
+                ("executor_launches", C.c_uint64), ("collision_hist", C.c_uint64 * 8)]
 
 
 class Tail(C.Structure):
@@ -212,6 +214,15 @@ def lib():
                                               C.POINTER(C.c_uint32), vp]
         L.ug_chain_tails.argtypes = [vp, C.c_uint32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                      C.c_uint32]
+        L.ug_launch_cost.argtypes = [C.POINTER(Kernel), C.POINTER(vp), C.c_uint32, C.c_uint32, vp,
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.ug_tile_variants.argtypes = [C.c_int32]
+        L.ug_tile_set.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.c_int32]
+        L.ug_tile_clear.argtypes = []
+        L.ug_tile_get.argtypes = [C.POINTER(Kernel)]
+        L.ug_tile_load.argtypes = [C.c_char_p, C.POINTER(C.c_uint32)]
+        L.ug_kernel_launch_variant.argtypes = [C.POINTER(Kernel), C.POINTER(vp), C.c_uint32,
+                                               C.c_int32, vp]
         for name in ("ug_create", "ug_chain_register", "ug_kernel_set_estimate",
                      "ug_kernel_get_estimate", "ug_profile", "ug_set_threshold", "ug_set_flags",
                      "ug_start", "ug_frame_submit", "ug_poll_complete", "ug_drain", "ug_stop",
@@ -223,7 +234,9 @@ def lib():
                      "ug_kernel_get_profile", "ug_tails_open", "ug_tails_publish",
                      "ug_tails_set_key", "ug_tails_pause", "ug_tails_kick", "ug_tails_finished",
                      "ug_tails_log", "ug_tails_close", "ug_kernel_launch_signal",
-                     "ug_chain_tails"):
+                     "ug_chain_tails", "ug_launch_cost", "ug_tile_variants", "ug_tile_set",
+                     "ug_tile_clear", "ug_tile_get", "ug_tile_load",
+                     "ug_kernel_launch_variant"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -339,6 +352,55 @@ def kernel_launch_signal(k, ptrs, counter_ptr, stream=None):
     return int(waves.value)
 
 
+def tile_variants(op):
+    return int(lib().ug_tile_variants(OP_IDS[op] if isinstance(op, str) else int(op)))
+
+
+def tile_set(op, shape, variant):
+    sh = (C.c_int64 * 4)(*(list(shape) + [0] * (4 - len(shape))))
+    st = lib().ug_tile_set(OP_IDS[op] if isinstance(op, str) else int(op), sh, int(variant))
+    if st != OK:
+        raise UgError(st, "ug_tile_set")
+
+
+def tile_clear():
+    lib().ug_tile_clear()
+
+
+def tile_get(k):
+    return int(lib().ug_tile_get(C.byref(kernel_struct(k))))
+
+
+def tile_load(path):
+    n = C.c_uint32()
+    st = lib().ug_tile_load(os.fsencode(path), C.byref(n))
+    if st != OK:
+        raise UgError(st, f"ug_tile_load({path})")
+    return int(n.value)
+
+
+def kernel_launch_variant(k, ptrs, variant, stream=None):
+    ks = kernel_struct(k)
+    arr = pointer_array(ptrs)
+    st = lib().ug_kernel_launch_variant(C.byref(ks), arr, len(ptrs), int(variant),
+                                        C.c_void_p(stream or 0))
+    if st != OK:
+        raise UgError(st, f"ug_kernel_launch_variant({OP_NAMES.get(ks.op, ks.op)}, {variant})")
+
+
+def launch_cost(k, ptrs, n=2000, stream=None):
+    """Raw launch loop of n kernels: (host ns per launch call, device ns per
+    kernel)."""
+    ks = kernel_struct(k)
+    arr = pointer_array(ptrs)
+    h, g = C.c_int64(), C.c_int64()
+    st = lib().ug_launch_cost(C.byref(ks), arr, len(ptrs), n, C.c_void_p(stream or 0),
+                              C.byref(h), C.byref(g))
+    if st != OK:
+        raise UgError(st, "ug_launch_cost")
+    return int(h.value), int(g.value)
+
+
 class TailQueue:
     """The tail executor's queue (ug_tails_*), driven directly."""
 
@@ -437,6 +499,8 @@ class Gate:
             for i in range(8):
                 cfg.lanes[i] = lanes[i] if i < len(lanes) else 0
         for key, v in kw.items():
+            if key == "tile_table" and isinstance(v, str):
+                v = os.fsencode(v)
             setattr(cfg, key, v)
         self.cfg = cfg
         h = C.c_void_p()
@@ -587,7 +651,8 @@ class Gate:
     def stats(self):
         s = Stats()
         self._check(lib().ug_get_stats(self.h, C.byref(s)), "ug_get_stats")
-        return {f: getattr(s, f) for f, _ in Stats._fields_}
+        return {f: (list(getattr(s, f)) if f == "collision_hist" else getattr(s, f))
+                for f, _ in Stats._fields_}
 
     def trace(self, cap=1 << 20):
         chunks = []

@@ -101,6 +101,7 @@ void Policy::reset() {
   sampled_ = false;
   next_sample_ = 0;
   collisions_ = 0;
+  collision_hist_.fill(0);
   finalize();
 }
 
@@ -630,11 +631,14 @@ void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& acti
       out.push_back(rec(UG_REC_EVREC, me.c, me.f, me.task, 0, 0, me.batch, 0));
     }
     if (gated && urgent(slack.at({me.c, me.f}))) {
+      // a collision, and how many other chains' instances it met
+      size_t others = 0;
       for (const Instance* o : active)
-        if (o->c != me.c && o->in_flight()) {
-          ++collisions_;
-          break;
-        }
+        if (o->c != me.c && o->in_flight()) ++others;
+      if (others) {
+        ++collisions_;
+        ++collision_hist_[std::min<size_t>(others, kCollisionBins) - 1];
+      }
     }
     out.push_back(rec(UG_REC_LAUNCH, me.c, me.f, me.task, g, me.level, me.lane, 0));
     me.released_hi = g + 1;

@@ -20,7 +20,9 @@
 //      launching holds it.
 #pragma once
 
+#include <array>
 #include <climits>
+#include <cstddef>
 #include <cstdint>
 #include <deque>
 #include <map>
@@ -172,6 +174,10 @@ class Policy {
   std::vector<Finished>& finished() { return finished_; }
   std::vector<int64_t>& samples() { return samples_; }
   uint64_t collisions() const { return collisions_; }
+  // collisions by the number of other chains' instances in flight (1, 2,
+  // ..., kCollisionBins or more)
+  static constexpr size_t kCollisionBins = 8;
+  const std::array<uint64_t, kCollisionBins>& collision_hist() const { return collision_hist_; }
   int32_t fifo_lane(int32_t c, int32_t task) const { return fifo_base_[c] + task; }
   int32_t fifo_lanes() const { return fifo_total_; }
   // Every active instance of the last instant, most urgent first under the
@@ -215,6 +221,7 @@ class Policy {
   bool sampled_ = false;       // a sample has been taken
   int64_t next_sample_ = 0;    // earliest time of the next sample
   uint64_t collisions_ = 0;
+  std::array<uint64_t, kCollisionBins> collision_hist_{};
   int64_t now_ = 0;            // time of the instant being decided
 };
 

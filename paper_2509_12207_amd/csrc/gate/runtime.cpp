@@ -847,9 +847,15 @@ ug_status ug_create(const ug_config* cfg, void** out) {
       cfg->order_key > UG_KEY_EQDF || cfg->est_noise_permille < 0 ||
       cfg->est_noise_permille > 1000)
     return UG_EINVAL;
+  if (cfg->tile_table && ug::tune_load(cfg->tile_table) < 0) {
+    std::lock_guard<std::mutex> lk(g_create_mu);
+    g_create_error = std::string("tile table unreadable or malformed: ") + cfg->tile_table;
+    return UG_EINVAL;
+  }
   std::unique_ptr<Ctx> c(new (std::nothrow) Ctx());
   if (!c) return UG_ENOMEM;
   c->cfg = *cfg;
+  c->cfg.tile_table = nullptr;   // read here; the caller's string is not kept
   c->policy = ug::Policy(policy_config(*cfg));
   c->has_device = cfg->device >= 0;
   if (c->has_device) {
@@ -1380,6 +1386,8 @@ ug_status ug_get_stats(void* ctx, ug_stats* out) {
   out->batches = c->st_batches.load();
   out->instants = c->st_instants.load();
   out->collisions = c->started ? 0 : c->policy.collisions();
+  if (!c->started)
+    for (size_t i = 0; i < 8; ++i) out->collision_hist[i] = c->policy.collision_hist()[i];
   out->decide_ns = c->st_decide_ns.load();
   out->launch_ns = c->st_launch_ns.load();
   out->tails_fused = c->st_tails.load();
@@ -1681,6 +1689,81 @@ ug_status ug_kernel_launch_signal(const ug_kernel* k, void* const* buffers, uint
   const hipError_t e = ug::launch_kernel(*k, buffers, static_cast<hipStream_t>(hip_stream),
                                          nullptr, 0, counter);
   return e == hipSuccess ? UG_OK : UG_EDEVICE;
+}
+
+int32_t ug_tile_variants(int32_t op) { return ug::tile_variants(op); }
+
+ug_status ug_tile_set(int32_t op, const int64_t* shape, int32_t variant) {
+  if (!shape) return UG_EINVAL;
+  return ug::tune_set(op, shape, variant) ? UG_OK : UG_EINVAL;
+}
+
+ug_status ug_tile_clear(void) {
+  ug::tune_clear();
+  return UG_OK;
+}
+
+int32_t ug_tile_get(const ug_kernel* k) {
+  if (!k || ug::validate_kernel(*k, 16)) return UG_EINVAL;
+  return ug::chosen_variant(*k);
+}
+
+ug_status ug_tile_load(const char* path, uint32_t* n_added) {
+  if (!path) return UG_EINVAL;
+  const int n = ug::tune_load(path);
+  if (n < 0) return UG_EINVAL;
+  if (n_added) *n_added = static_cast<uint32_t>(n);
+  return UG_OK;
+}
+
+ug_status ug_kernel_launch_variant(const ug_kernel* k, void* const* buffers, uint32_t n_buffers,
+                                   int32_t variant, void* hip_stream) {
+  if (!k || !buffers || ug::validate_kernel(*k, n_buffers)) return UG_EINVAL;
+  if (variant < 0 || variant >= ug::tile_variants(k->op)) return UG_EINVAL;
+  const int32_t* slots[2] = {k->in, k->out};
+  const int counts[2] = {3, 4};
+  for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < counts[a]; ++i) {
+      const int32_t s = slots[a][i];
+      if (s >= 0 && (static_cast<uint32_t>(s) >= n_buffers || !buffers[s])) return UG_EINVAL;
+    }
+  const hipError_t e = ug::launch_kernel(*k, buffers, static_cast<hipStream_t>(hip_stream),
+                                         nullptr, 0, nullptr, variant);
+  return e == hipSuccess ? UG_OK : UG_EDEVICE;
+}
+
+ug_status ug_launch_cost(const ug_kernel* k, void* const* buffers, uint32_t n_buffers,
+                         uint32_t n, void* hip_stream, int64_t* host_ns, int64_t* gpu_ns) {
+  if (!k || !buffers || !host_ns || !gpu_ns || n == 0) return UG_EINVAL;
+  if (ug::validate_kernel(*k, n_buffers) || ug::workspace_bytes(*k)) return UG_EINVAL;
+  const int32_t* slots[2] = {k->in, k->out};
+  const int counts[2] = {3, 4};
+  for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < counts[a]; ++i) {
+      const int32_t s = slots[a][i];
+      if (s >= 0 && (static_cast<uint32_t>(s) >= n_buffers || !buffers[s])) return UG_EINVAL;
+    }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 8 && e == hipSuccess; ++i) e = ug::launch_kernel(*k, buffers, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  const int64_t t0 = mono_ns();
+  for (uint32_t i = 0; i < n && e == hipSuccess; ++i) e = ug::launch_kernel(*k, buffers, st);
+  const int64_t t1 = mono_ns();
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return UG_EDEVICE;
+  *host_ns = (t1 - t0) / n;
+  *gpu_ns = static_cast<int64_t>(static_cast<double>(ms) * 1e6 / n);
+  return UG_OK;
 }
 
 int32_t ug_chain_tails(void* ctx, uint32_t chain, int32_t* first, int32_t* end, uint32_t cap) {

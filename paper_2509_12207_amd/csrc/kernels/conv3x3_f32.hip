@@ -17,7 +17,9 @@
 // do not depend on scheduling.
 //
 // The launcher picks the largest tile that still gives ~two workgroups per CU,
-// or one per CU for a tile without a K split (measured faster than a K split).
+// or one per CU for a tile without a K split (measured faster than a K split),
+// unless the tuning table (an autotuner's measurements) names a variant
+// (0..4, the order of kShapes) for the shape.
 #include "mfma.hpp"
 #include "ops.hpp"
 #include "signal.hpp"
@@ -247,6 +249,17 @@ int64_t wgs(const Shape& s, int64_t N, int64_t C, int64_t H, int64_t W) {
 
 // First (largest) tile with ~two workgroups per CU, or one per CU if it has no
 // K split; else the one with the most workgroups.
+int pick(int64_t N, int64_t C, int64_t H, int64_t W);
+
+// The variant asked for, else the tuning table's, else the rule below.
+int choose(int64_t N, int64_t C, int64_t H, int64_t W, int variant) {
+  if (variant < 0) {
+    const int64_t key[4] = {N, C, H, W};
+    variant = tune_get(UG_OP_CONV3X3_F32, key);
+  }
+  return variant >= 0 && variant < 5 ? variant : pick(N, C, H, W);
+}
+
 int pick(int64_t N, int64_t C, int64_t H, int64_t W) {
   constexpr int64_t kWant = 480, kOnePerCu = 256;
   int best = 4;
@@ -272,9 +285,9 @@ void launch(dim3 grid, hipStream_t s, const float* X, const float* Wt, float* Y,
 
 }  // namespace
 
-OpPlan conv3x3_f32_plan(int64_t N, int64_t C, int64_t H, int64_t W) {
+OpPlan conv3x3_f32_plan(int64_t N, int64_t C, int64_t H, int64_t W, int variant) {
   OpPlan p;
-  const int i = pick(N, C, H, W);
+  const int i = choose(N, C, H, W, variant);
   const Shape& s = kShapes[i];
   const void* f[] = {reinterpret_cast<const void*>(&conv3x3_f32_kernel<2, 2, 2, 2, 1, 8, 16>),
                      reinterpret_cast<const void*>(&conv3x3_f32_kernel<1, 4, 2, 1, 1, 8, 16>),
@@ -289,10 +302,11 @@ OpPlan conv3x3_f32_plan(int64_t N, int64_t C, int64_t H, int64_t W) {
 }
 
 hipError_t conv3x3_f32_launch(const float* X, const float* Wt, float* Y, int64_t N, int64_t C,
-                              int64_t H, int64_t W, hipStream_t s, unsigned* sig) {
-  OpPlan p = conv3x3_f32_plan(N, C, H, W);
+                              int64_t H, int64_t W, hipStream_t s, unsigned* sig, int variant) {
+  const int v = choose(N, C, H, W, variant);
+  OpPlan p = conv3x3_f32_plan(N, C, H, W, v);
   const int c = (int)C, h = (int)H, w = (int)W;
-  switch (pick(N, C, H, W)) {
+  switch (v) {
     case 0: launch<2, 2, 2, 2, 1, 8, 16>(p.grid, s, X, Wt, Y, c, h, w, sig); break;
     case 1: launch<1, 4, 2, 1, 1, 8, 16>(p.grid, s, X, Wt, Y, c, h, w, sig); break;
     case 2: launch<1, 4, 1, 1, 1, 8, 16>(p.grid, s, X, Wt, Y, c, h, w, sig); break;

@@ -10,7 +10,9 @@
 //                       workgroup and summed through LDS in a fixed order
 //                       (results do not depend on scheduling).
 // The launcher takes the largest tile that still gives two workgroups per CU
-// (or the small one), so a 256^3 product spreads over 64 CUs instead of 4.
+// (or the small one), so a 256^3 product spreads over 64 CUs instead of 4,
+// unless the tuning table (an autotuner's measurements) names a variant
+// (0 big, 1 mid, 2 small) for the shape.
 //
 // Operand tiles are staged through LDS, double buffered: the next K step is
 // fetched into registers while the current one feeds the matrix cores, then
@@ -221,6 +223,15 @@ Shape pick(int64_t M, int64_t N) {
   return kSmall;
 }
 
+// The variant asked for, else the tuning table's, else the rule above.
+Shape choose(int64_t M, int64_t N, int64_t K, int variant) {
+  if (variant < 0) {
+    const int64_t key[4] = {M, N, K, 0};
+    variant = tune_get(UG_OP_GEMM_F32, key);
+  }
+  return variant >= 0 && variant < 3 ? static_cast<Shape>(variant) : pick(M, N);
+}
+
 template <int WM, int WN, int TM, int TN, int KS>
 const void* fn(bool vec) {
   return vec ? reinterpret_cast<const void*>(&gemm_f32_kernel<WM, WN, TM, TN, KS, true>)
@@ -242,11 +253,10 @@ void launch(bool vec, dim3 grid, hipStream_t s, const float* A, const float* B, 
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-OpPlan gemm_f32_plan(int64_t M, int64_t N, int64_t K, bool vec) {
-  (void)K;
+OpPlan gemm_f32_plan(int64_t M, int64_t N, int64_t K, bool vec, int variant) {
   OpPlan p;
   p.block = dim3(256);
-  switch (pick(M, N)) {
+  switch (choose(M, N, K, variant)) {
     case kBig:
       p.func = fn<2, 2, 2, 2, 1>(vec);
       p.grid = dim3((unsigned)tiles(M, N, 128, 128));
@@ -263,10 +273,11 @@ OpPlan gemm_f32_plan(int64_t M, int64_t N, int64_t K, bool vec) {
 }
 
 hipError_t gemm_f32_launch(const float* A, const float* B, float* C, int64_t M, int64_t N,
-                           int64_t K, hipStream_t s, unsigned* sig) {
+                           int64_t K, hipStream_t s, unsigned* sig, int variant) {
   const bool vec = (K % 4 == 0) && (N % 4 == 0) && aligned16(A) && aligned16(B);
-  OpPlan p = gemm_f32_plan(M, N, K, vec);
-  switch (pick(M, N)) {
+  const Shape sh = choose(M, N, K, variant);
+  OpPlan p = gemm_f32_plan(M, N, K, vec, static_cast<int>(sh));
+  switch (sh) {
     case kBig:
       launch<2, 2, 2, 2, 1>(vec, p.grid, s, A, B, C, (int)M, (int)N, (int)K, sig);
       break;

@@ -174,19 +174,20 @@ ug_kernel frame_kernel(const ug_kernel& k, int64_t v) {
 }
 
 hipError_t launch_kernel(const ug_kernel& k, void* const* b, hipStream_t st, void* ws,
-                         size_t ws_bytes, unsigned* sig) {
+                         size_t ws_bytes, unsigned* sig, int variant) {
   if (sig && signal_waves(k) == 0) return hipErrorInvalidValue;
   const int64_t* s = k.shape;
   auto F = [&](int32_t slot) { return static_cast<float*>(b[slot]); };
   auto I = [&](int32_t slot) { return static_cast<int*>(b[slot]); };
   switch (k.op) {
     case UG_OP_GEMM_F32:
-      return gemm_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], s[2], st, sig);
+      return gemm_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], s[2], st, sig,
+                             variant);
     case UG_OP_BIAS_RELU_F32:
       return bias_relu_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], (int)s[2], st);
     case UG_OP_CONV3X3_F32:
       return conv3x3_f32_launch(F(k.in[0]), F(k.in[1]), F(k.out[0]), s[0], s[1], s[2], s[3], st,
-                                sig);
+                                sig, variant);
     case UG_OP_ROWSUM_F32:
       return rowsum_f32_launch(F(k.in[0]), F(k.out[0]), s[0], s[1], st);
     case UG_OP_SOFTMAX_F32:
@@ -249,15 +250,40 @@ uint32_t signal_waves(const ug_kernel& k) {
   }
 }
 
-OpPlan plan_kernel(const ug_kernel& k) {
+int chosen_variant(const ug_kernel& k) {
+  const int64_t* s = k.shape;
+  const int64_t gkey[4] = {s[0], s[1], s[2], 0};
+  switch (k.op) {
+    case UG_OP_GEMM_F32: {
+      const int v = tune_get(UG_OP_GEMM_F32, gkey);
+      if (v >= 0) return v;
+      // the plan's function tells the rule's choice apart
+      for (int i = 0; i < 3; ++i)
+        if (gemm_f32_plan(s[0], s[1], s[2], true, i).func == gemm_f32_plan(s[0], s[1], s[2], true).func)
+          return i;
+      return -1;
+    }
+    case UG_OP_CONV3X3_F32: {
+      for (int i = 0; i < 5; ++i)
+        if (conv3x3_f32_plan(s[0], s[1], s[2], s[3], i).func ==
+            conv3x3_f32_plan(s[0], s[1], s[2], s[3]).func)
+          return i;
+      return -1;
+    }
+    default:
+      return -1;
+  }
+}
+
+OpPlan plan_kernel(const ug_kernel& k, int variant) {
   const int64_t* s = k.shape;
   switch (k.op) {
     case UG_OP_GEMM_F32:
-      return gemm_f32_plan(s[0], s[1], s[2], (s[2] % 4 == 0) && (s[1] % 4 == 0));
+      return gemm_f32_plan(s[0], s[1], s[2], (s[2] % 4 == 0) && (s[1] % 4 == 0), variant);
     case UG_OP_BIAS_RELU_F32:
       return bias_relu_f32_plan(s[0], s[1], (int)s[2], s[1] % 4 == 0);
     case UG_OP_CONV3X3_F32:
-      return conv3x3_f32_plan(s[0], s[1], s[2], s[3]);
+      return conv3x3_f32_plan(s[0], s[1], s[2], s[3], variant);
     case UG_OP_ROWSUM_F32:
       return rowsum_f32_plan(s[0], s[1]);
     case UG_OP_SOFTMAX_F32:

@@ -19,13 +19,14 @@ struct OpPlan {
   size_t lds = 0;
 };
 
-OpPlan gemm_f32_plan(int64_t M, int64_t N, int64_t K, bool vec);
+OpPlan gemm_f32_plan(int64_t M, int64_t N, int64_t K, bool vec, int variant = -1);
 hipError_t gemm_f32_launch(const float* A, const float* B, float* C, int64_t M, int64_t N,
-                           int64_t K, hipStream_t s, unsigned* sig = nullptr);
+                           int64_t K, hipStream_t s, unsigned* sig = nullptr, int variant = -1);
 
-OpPlan conv3x3_f32_plan(int64_t N, int64_t C, int64_t H, int64_t W);
+OpPlan conv3x3_f32_plan(int64_t N, int64_t C, int64_t H, int64_t W, int variant = -1);
 hipError_t conv3x3_f32_launch(const float* X, const float* Wt, float* Y, int64_t N, int64_t C,
-                              int64_t H, int64_t W, hipStream_t s, unsigned* sig = nullptr);
+                              int64_t H, int64_t W, hipStream_t s, unsigned* sig = nullptr,
+                              int variant = -1);
 
 OpPlan bias_relu_f32_plan(int64_t R, int64_t C, int axis, bool vec);
 hipError_t bias_relu_f32_launch(const float* X, const float* b, float* Y, int64_t R, int64_t C,
@@ -93,15 +94,35 @@ size_t workspace_bytes(const ug_kernel& k);
 // every wavefront of the kernel adds one once its results are stored.
 // Asynchronous.
 hipError_t launch_kernel(const ug_kernel& k, void* const* buffers, hipStream_t s,
-                         void* ws = nullptr, size_t ws_bytes = 0, unsigned* sig = nullptr);
+                         void* ws = nullptr, size_t ws_bytes = 0, unsigned* sig = nullptr,
+                         int variant = -1);
 
 // Wavefronts that add to a completion counter when the operation is
 // launched with one: 0 if the operation takes no counter (only the FP32 and
 // BF16 GEMM and 3x3 convolution do).
 uint32_t signal_waves(const ug_kernel& k);
 
-// Main-kernel launch shape of an operation.
-OpPlan plan_kernel(const ug_kernel& k);
+// Main-kernel launch shape of an operation (at a tile variant, -1: the
+// launcher's choice).
+OpPlan plan_kernel(const ug_kernel& k, int variant = -1);
+// The tile variant the launcher takes for k (-1 for operations with one).
+int chosen_variant(const ug_kernel& k);
+
+// Tile variants of an operation's launcher (0: one tile shape only): FP32
+// GEMM 3 (128x128, 64x64, 32x32 with a four-way K split), FP32 convolution
+// 5 (see conv3x3_f32.hip).  The launchers and plans of those operations take
+// a variant; -1 means: the tuning table's entry for the shape, else the
+// launcher's fixed rule.
+int tile_variants(int32_t op);
+// Tuning table, process-wide, keyed (op, shape[0..3]): the variant, or -1.
+int tune_get(int32_t op, const int64_t* shape);
+bool tune_set(int32_t op, const int64_t* shape, int variant);   // -1 removes
+void tune_clear();
+size_t tune_size();
+// Adds the entries of a table file (lines "op s0 s1 s2 s3 variant", '#'
+// comments): returns the number added, -1 if unreadable, -2 if a line is
+// malformed (then nothing is added).
+int tune_load(const char* path);
 
 // Hardware-queue class of each stream (streams with equal class share a
 // hardware queue), measured with two tiny kernels per pair of streams

@@ -15,17 +15,20 @@
 //
 // * binned (large clouds): the grid is cut into tiles of kTileCells
 //   consecutive cells, small enough that one tile's accumulators live in LDS.
-//     1. count:  per chunk of kChunk points, a histogram of tiles (LDS),
-//                stored tile-major in the workspace;
-//     2. scan:   per tile, exclusive offsets of the chunks and the tile total;
-//     3. place:  per chunk, the cell of every point (vidx), and a record
-//                (z key, index, cell in tile) per point, sorted by tile in
-//                LDS and written as one run per tile;
-//     4. reduce: per segment of at most kSeg records of one tile, count /
-//                max / min in LDS, written out as a partial tile;
-//     5. merge:  per cell, the partial tiles of its tile combined into the
+//     1. bin:    per chunk of kChunk points (read once), the cell of every
+//                point (vidx) and an 8-byte record (z key, cell in tile,
+//                index in chunk) per point, counting-sorted by tile in LDS
+//                and written as one contiguous block, with the offsets of
+//                its tile runs;
+//     2. reduce: per (tile, group of chunks), the tile's runs of those
+//                chunks reduced in LDS (count / max / min), written out as a
+//                partial tile;
+//     3. merge:  per cell, the partial tiles of its tile combined into the
 //                outputs (empty cells: count 0, zmax -inf, first -1).
-//   Global traffic is about 50 bytes per point, with no global atomics.
+//   Global traffic is about 36 bytes per point (16 read and 4 written by
+//   the points themselves, a record written and read back), with no global
+//   atomics.
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 
@@ -37,9 +40,8 @@ namespace {
 constexpr int kTileBits = 12;
 constexpr int kTileCells = 1 << kTileBits;        // cells per tile (48 KiB of LDS)
 constexpr int kMaxTiles = 1024;                   // binned grids: <= 4 Mi cells
-constexpr int64_t kChunk = 8192;                  // points per count/place block
-static_assert(kChunk <= 65536, "place keeps in-chunk indices in 16 bits");
-constexpr int64_t kSeg = 65536;                   // records per reduce block
+constexpr int64_t kChunk = 8192;                  // points per bin workgroup
+static_assert(kChunk <= 8192, "a record keeps the index in its chunk in 13 bits");
 constexpr int64_t kBinnedMinPoints = int64_t(1) << 20;
 constexpr unsigned kKeyNegInf = 0x007fffffu;      // key of -inf
 
@@ -139,228 +141,143 @@ __device__ void block_scan_tiles(int n, F val, int* out, int* wsum) {
   __syncthreads();
 }
 
-// 1. tile histogram of each chunk; H is tile-major: H[tile * nb + chunk]
-__global__ __launch_bounds__(256) void voxel_count(const float4* __restrict__ pts,
-                                                   int* __restrict__ H, int64_t N, int nx, int ny,
-                                                   float xmin, float ymin, float scale, int T,
-                                                   int nb) {
-  __shared__ int hist[kMaxTiles];
-  for (int i = threadIdx.x; i < T; i += 256) hist[i] = 0;
-  __syncthreads();
-  const int64_t beg = (int64_t)blockIdx.x * kChunk;
-  const int64_t end = beg + kChunk < N ? beg + kChunk : N;
-  for (int64_t i = beg + threadIdx.x; i < end; i += 4 * 256) {
-    float4 p[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (i + u * 256 < end) p[u] = pts[i + u * 256];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (i + u * 256 < end) {
-        const int v = cell_of(p[u], nx, ny, xmin, ymin, scale);
-        if (v >= 0) atomicAdd(&hist[v >> kTileBits], 1);
-      }
-    }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < T; t += 256) H[(int64_t)t * nb + blockIdx.x] = hist[t];
+// 1. bin: one chunk of kChunk points per workgroup, read once.  Every lane
+//    keeps its 32 points' cells and z keys in registers while the chunk's
+//    tile histogram builds up in LDS; the exclusive scan of the histogram
+//    gives each tile's run, the points are placed into their runs in LDS
+//    (a counting sort by tile), and the chunk's records go out as one
+//    contiguous block (chunk-major) with the run offsets H[c][0..T].  A
+//    record is 8 bytes: z key (bits 0-31), cell within the tile (32-43),
+//    point index within the chunk (44-56).
+constexpr int kPerLane = kChunk / 256;
+
+__device__ __forceinline__ uint64_t record(unsigned zk, int cell, int idx) {
+  return (uint64_t)zk | ((uint64_t)(cell & (kTileCells - 1)) << 32) | ((uint64_t)idx << 44);
 }
 
-// 2. per tile (one workgroup each): exclusive scan of its nb chunk counts in
-//    place, and the tile total
-__global__ __launch_bounds__(256) void voxel_scan(int* __restrict__ H, int* __restrict__ tcount,
-                                                  int nb) {
+__global__ __launch_bounds__(256) void voxel_bin(const float4* __restrict__ pts,
+                                                 int* __restrict__ vidx, int* __restrict__ H,
+                                                 uint64_t* __restrict__ R, int64_t N, int nx,
+                                                 int ny, float xmin, float ymin, float scale,
+                                                 int T) {
+  __shared__ int cur[kMaxTiles];       // histogram, then cursors
+  __shared__ int off[kMaxTiles + 1];   // exclusive scan of the histogram
   __shared__ int wsum[4];
-  __shared__ int carry;
-  int* h = H + (int64_t)blockIdx.x * nb;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nb; base += 256) {
-    const int i = base + threadIdx.x;
-    const int x = i < nb ? h[i] : 0;
-    int incl = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int y = __shfl_up(incl, d, 64);
-      if (lane >= d) incl += y;
-    }
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    int off = carry + incl - x;
-    for (int w = 0; w < wave; ++w) off += wsum[w];
-    if (i < nb) h[i] = off;
-    __syncthreads();  // every lane has read carry and wsum
-    if (threadIdx.x == 255) carry = off + x;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) tcount[blockIdx.x] = carry;
-}
-
-// 3. cells and records, one chunk per workgroup.  The chunk's records are
-//    first sorted by tile in LDS (a counting sort: the chunk's tile counts
-//    are known from step 1), then written out as one contiguous run per
-//    tile, so that the stores coalesce.  Record r of tile t lies in
-//    [tbase[t], tbase[t] + tcount[t]); within a chunk's run the order is
-//    arbitrary (the reductions do not depend on it).
-__global__ __launch_bounds__(256) void voxel_place(const float4* __restrict__ pts,
-                                                   int* __restrict__ vidx,
-                                                   const int* __restrict__ H,
-                                                   const int* __restrict__ tcount,
-                                                   unsigned* __restrict__ rz,
-                                                   int* __restrict__ ri,
-                                                   unsigned short* __restrict__ rc, int64_t N,
-                                                   int nx, int ny, float xmin, float ymin,
-                                                   float scale, int T, int nb) {
-  __shared__ int gbase[kMaxTiles];     // global position of the chunk's run of tile t
-  __shared__ int loff[kMaxTiles + 1];  // local position of that run (exclusive scan)
-  __shared__ int cur[kMaxTiles];       // local cursors
-  __shared__ int wsum[4];
-  __shared__ unsigned sz[kChunk];         // z keys, by local position
-  __shared__ unsigned short si[kChunk];   // point index within the chunk
-  __shared__ unsigned short sc[kChunk];   // cell within the tile
+  __shared__ uint64_t rec[kChunk];     // the chunk's records, sorted by tile
   const int c = blockIdx.x;
-  block_scan_tiles(T, [&](int i) { return tcount[i]; }, loff, wsum);
-  for (int t = threadIdx.x; t < T; t += 256) gbase[t] = loff[t] + H[(int64_t)t * nb + c];
-  __syncthreads();
-  // H holds, per tile, the exclusive scan over chunks: this chunk's count of
-  // tile t is the step to the next chunk (or to the tile total)
-  block_scan_tiles(T, [&](int i) {
-    const int64_t h = (int64_t)i * nb + c;
-    return (c + 1 < nb ? H[h + 1] : tcount[i]) - H[h];
-  }, loff, wsum);
-  for (int t = threadIdx.x; t < T; t += 256) cur[t] = loff[t];
+  for (int t = threadIdx.x; t < T; t += 256) cur[t] = 0;
   __syncthreads();
   const int64_t beg = (int64_t)c * kChunk;
   const int64_t end = beg + kChunk < N ? beg + kChunk : N;
-  // eight points a lane in flight (two workgroups fit a CU)
-  for (int64_t i = beg + threadIdx.x; i < end; i += 8 * 256) {
+  int cell[kPerLane];
+  unsigned zk[kPerLane];
+  // eight points a lane in flight
+#pragma unroll
+  for (int u0 = 0; u0 < kPerLane; u0 += 8) {
     float4 p[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (i + u * 256 < end) p[u] = pts[i + u * 256];
+    for (int u = 0; u < 8; ++u) {
+      const int64_t j = beg + threadIdx.x + (int64_t)(u0 + u) * 256;
+      p[u] = j < end ? pts[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int64_t j = i + u * 256;
+      const int64_t j = beg + threadIdx.x + (int64_t)(u0 + u) * 256;
+      int v = -1;
       if (j < end) {
-        const int v = cell_of(p[u], nx, ny, xmin, ymin, scale);
+        v = cell_of(p[u], nx, ny, xmin, ymin, scale);
         vidx[j] = v;
-        if (v >= 0) {
-          const int t = v >> kTileBits;
-          const int lp = atomicAdd(&cur[t], 1);
-          if (lp < loff[t + 1]) {  // always true when counting and placing agree
-            sz[lp] = zkey(p[u].z);
-            si[lp] = (unsigned short)(j - beg);
-            sc[lp] = (unsigned short)(v & (kTileCells - 1));
-          }
-        }
+        if (v >= 0) atomicAdd(&cur[v >> kTileBits], 1);
       }
+      cell[u0 + u] = v;
+      zk[u0 + u] = zkey(p[u].z);
     }
   }
   __syncthreads();
-  // one wavefront per tile run (tiles dealt round-robin to the four)
-  const int lane = threadIdx.x & 63;
-  for (int t = threadIdx.x >> 6; t < T; t += 4) {
-    const int a = loff[t], n = loff[t + 1] - a, g = gbase[t];
-    for (int k = lane; k < n; k += 64) {
-      rz[g + k] = sz[a + k];
-      ri[g + k] = (int)(beg + si[a + k]);
-      rc[g + k] = sc[a + k];
+  block_scan_tiles(T, [&](int i) { return cur[i]; }, off, wsum);
+  int* h = H + (int64_t)c * (T + 1);
+  for (int t = threadIdx.x; t <= T; t += 256) h[t] = off[t];
+  for (int t = threadIdx.x; t < T; t += 256) cur[t] = off[t];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPerLane; ++u) {
+    if (cell[u] >= 0) {
+      const int lp = atomicAdd(&cur[cell[u] >> kTileBits], 1);
+      rec[lp] = record(zk[u], cell[u], threadIdx.x + u * 256);
     }
   }
+  __syncthreads();
+  const int n = off[T];
+  uint64_t* out = R + beg;
+  for (int i = threadIdx.x; i < n; i += 256) out[i] = rec[i];
 }
 
-// 4. one workgroup per segment of a tile's records: LDS reduction, then the
-//    partial tile.  Workgroups beyond the number of segments exit at once.
-__global__ __launch_bounds__(256) void voxel_reduce(const int* __restrict__ tcount,
-                                                    const unsigned* __restrict__ rz,
-                                                    const int* __restrict__ ri,
-                                                    const unsigned short* __restrict__ rc,
-                                                    int* __restrict__ pc,
-                                                    unsigned* __restrict__ pz,
-                                                    int* __restrict__ pf, int T) {
-  // 52 KiB of LDS: three workgroups fit a CU
-  __shared__ int segb[kMaxTiles + 1];
-  __shared__ int wsum[4];
+// 2. one workgroup per (tile, group of chunks): the tile's runs of those
+//    chunks reduced into LDS accumulators, written out as a partial tile.
+//    Each wavefront takes every fourth chunk's run.
+__global__ __launch_bounds__(256) void voxel_tile_reduce(const int* __restrict__ H,
+                                                         const uint64_t* __restrict__ R,
+                                                         int* __restrict__ pc,
+                                                         unsigned* __restrict__ pz,
+                                                         int* __restrict__ pf, int T, int nb,
+                                                         int groups, int cpg) {
+  // 48 KiB of LDS: three workgroups fit a CU
   __shared__ int acc_c[kTileCells];
   __shared__ unsigned acc_z[kTileCells];
   __shared__ int acc_f[kTileCells];
-  block_scan_tiles(T, [&](int i) { return (int)((tcount[i] + kSeg - 1) / kSeg); }, segb, wsum);
-  const int s = blockIdx.x;
-  if (s >= segb[T]) return;  // uniform across the workgroup
-  // tile of segment s: the last t with segb[t] <= s (segb is non-decreasing)
-  int lo = 0, hi = T - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (segb[mid] <= s) lo = mid; else hi = mid - 1;
-  }
-  const int t = lo;
-  // first record of tile t: the sum of the totals of the tiles before it
-  int part = 0;
-  for (int i = threadIdx.x; i < t; i += 256) part += tcount[i];
-  for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
-  __syncthreads();
-  const int tbase = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-  const int64_t start = (int64_t)tbase + (int64_t)(s - segb[t]) * kSeg;
-  const int64_t tend = (int64_t)tbase + tcount[t];
-  const int64_t end = start + kSeg < tend ? start + kSeg : tend;
-  for (int c = threadIdx.x; c < kTileCells; c += 256) {
-    acc_c[c] = 0;
-    acc_z[c] = kKeyNegInf;
-    acc_f[c] = INT_MAX;
+  const int t = blockIdx.x / groups, g = blockIdx.x % groups;
+  const int c0 = g * cpg, c1 = c0 + cpg < nb ? c0 + cpg : nb;
+  for (int i = threadIdx.x; i < kTileCells; i += 256) {
+    acc_c[i] = 0;
+    acc_z[i] = kKeyNegInf;
+    acc_f[i] = INT_MAX;
   }
   __syncthreads();
-  // eight records a lane per round (32-, 32- and 16-byte loads: the record
-  // arrays are 256-byte aligned and padded to a multiple of 8 records),
-  // from the multiple of 8 at or below the segment start; records outside
-  // [start, end) are read and skipped
-  for (int64_t r0 = (start & ~int64_t(7)) + 8 * threadIdx.x; r0 < end; r0 += 8 * 256) {
-    const uint4 z0 = *reinterpret_cast<const uint4*>(rz + r0);
-    const uint4 z1 = *reinterpret_cast<const uint4*>(rz + r0 + 4);
-    const int4 f0 = *reinterpret_cast<const int4*>(ri + r0);
-    const int4 f1 = *reinterpret_cast<const int4*>(ri + r0 + 4);
-    const uint4 c8 = *reinterpret_cast<const uint4*>(rc + r0);
-    const unsigned zz[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
-    const int ff[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
-    const unsigned cc[4] = {c8.x, c8.y, c8.z, c8.w};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int64_t r = r0 + k;
-      if (r >= start && r < end) {
-        const int c = (int)((cc[k >> 1] >> (16 * (k & 1))) & (kTileCells - 1));
-        atomicAdd(&acc_c[c], 1);
-        atomicMax(&acc_z[c], zz[k]);
-        atomicMin(&acc_f[c], ff[k]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = c0 + wave; c < c1; c += 4) {
+    const int* h = H + (int64_t)c * (T + 1);
+    const int a = h[t], b = h[t + 1];
+    const uint64_t* run = R + (int64_t)c * kChunk;
+    const int base = c * (int)kChunk;
+    for (int i = a + lane; i < b; i += 128) {
+      const bool two = i + 64 < b;
+      const uint64_t r0 = run[i];
+      const uint64_t r1 = two ? run[i + 64] : 0;
+      int cc = (int)((r0 >> 32) & (kTileCells - 1));
+      atomicAdd(&acc_c[cc], 1);
+      atomicMax(&acc_z[cc], (unsigned)r0);
+      atomicMin(&acc_f[cc], base + (int)(r0 >> 44));
+      if (two) {
+        cc = (int)((r1 >> 32) & (kTileCells - 1));
+        atomicAdd(&acc_c[cc], 1);
+        atomicMax(&acc_z[cc], (unsigned)r1);
+        atomicMin(&acc_f[cc], base + (int)(r1 >> 44));
       }
     }
   }
   __syncthreads();
-  const int64_t o = (int64_t)s * kTileCells;
-  for (int c = threadIdx.x; c < kTileCells; c += 256) {
-    pc[o + c] = acc_c[c];
-    pz[o + c] = acc_z[c];
-    pf[o + c] = acc_f[c];
+  const int64_t o = (int64_t)blockIdx.x * kTileCells;
+  for (int i = threadIdx.x; i < kTileCells; i += 256) {
+    pc[o + i] = acc_c[i];
+    pz[o + i] = acc_z[i];
+    pf[o + i] = acc_f[i];
   }
 }
 
-// 5. per cell: combine the partial tiles of its tile
-__global__ __launch_bounds__(256) void voxel_merge(const int* __restrict__ tcount,
-                                                   const int* __restrict__ pc,
+// 3. per cell: combine the partial tiles of its tile (the groups' partials
+//    of tile t are partial tiles t * groups .. t * groups + groups - 1)
+__global__ __launch_bounds__(256) void voxel_merge(const int* __restrict__ pc,
                                                    const unsigned* __restrict__ pz,
                                                    const int* __restrict__ pf,
                                                    int* __restrict__ count, float* __restrict__ zmax,
-                                                   int* __restrict__ first, int64_t G, int T) {
-  __shared__ int segb[kMaxTiles + 1];
-  __shared__ int wsum[4];
-  block_scan_tiles(T, [&](int i) { return (int)((tcount[i] + kSeg - 1) / kSeg); }, segb, wsum);
+                                                   int* __restrict__ first, int64_t G, int groups) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (v >= G) return;
   const int t = (int)(v >> kTileBits);
   const int l = (int)(v & (kTileCells - 1));
   int c = 0, f = INT_MAX;
   unsigned z = kKeyNegInf;
-  for (int s = segb[t]; s < segb[t + 1]; ++s) {
+  for (int s = t * groups; s < (t + 1) * groups; ++s) {
     const int64_t o = (int64_t)s * kTileCells + l;
     c += pc[o];
     z = max(z, pz[o]);
@@ -378,10 +295,11 @@ unsigned grid_for(int64_t work, int64_t cap) {
   return (unsigned)g;
 }
 
-// Workspace of the binned path, in 256-byte aligned pieces.
+// Workspace of the binned path, in 256-byte aligned pieces: the chunks' run
+// offsets, their records (kChunk slots per chunk), the partial tiles.
 struct Binned {
-  int T = 0, nb = 0, smax = 0;
-  size_t H = 0, tcount = 0, rz = 0, ri = 0, rc = 0, pc = 0, pz = 0, pf = 0, total = 0;
+  int T = 0, nb = 0, groups = 0, cpg = 0;
+  size_t H = 0, R = 0, pc = 0, pz = 0, pf = 0, total = 0;
 };
 
 bool use_binned(int64_t N, int64_t G) {
@@ -392,23 +310,21 @@ Binned binned_layout(int64_t N, int64_t G) {
   Binned b;
   b.T = (int)((G + kTileCells - 1) / kTileCells);
   b.nb = (int)((N + kChunk - 1) / kChunk);
-  b.smax = b.T + (int)((N + kSeg - 1) / kSeg);
+  // at least ~512 reduce workgroups: groups of chunks per tile
+  b.groups = (int)std::min<int64_t>(b.nb, std::max<int64_t>(1, (512 + b.T - 1) / b.T));
+  b.cpg = (b.nb + b.groups - 1) / b.groups;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
     off += (bytes + 255) / 256 * 256;
     return at;
   };
-  b.H = take(sizeof(int) * (size_t)b.T * b.nb);
-  b.tcount = take(sizeof(int) * (size_t)b.T);
-  // record arrays padded to a multiple of 8 records (vector loads of eight)
-  const size_t n8 = (size_t)(N + 7) / 8 * 8;
-  b.rz = take(sizeof(unsigned) * n8);
-  b.ri = take(sizeof(int) * n8);
-  b.rc = take(sizeof(unsigned short) * n8);
-  b.pc = take(sizeof(int) * (size_t)b.smax * kTileCells);
-  b.pz = take(sizeof(unsigned) * (size_t)b.smax * kTileCells);
-  b.pf = take(sizeof(int) * (size_t)b.smax * kTileCells);
+  b.H = take(sizeof(int) * (size_t)b.nb * (b.T + 1));
+  b.R = take(sizeof(uint64_t) * (size_t)b.nb * kChunk);
+  const size_t parts = (size_t)b.T * b.groups * kTileCells;
+  b.pc = take(sizeof(int) * parts);
+  b.pz = take(sizeof(unsigned) * parts);
+  b.pf = take(sizeof(int) * parts);
   b.total = off;
   return b;
 }
@@ -447,21 +363,16 @@ hipError_t voxel_f32_launch(const float* pts, int* vidx, int* count, float* zmax
       return hipErrorInvalidValue;
     char* w = static_cast<char*>(ws);
     int* H = reinterpret_cast<int*>(w + b.H);
-    int* tc = reinterpret_cast<int*>(w + b.tcount);
-    unsigned* rz = reinterpret_cast<unsigned*>(w + b.rz);
-    int* ri = reinterpret_cast<int*>(w + b.ri);
-    unsigned short* rc = reinterpret_cast<unsigned short*>(w + b.rc);
+    uint64_t* R = reinterpret_cast<uint64_t*>(w + b.R);
     int* pc = reinterpret_cast<int*>(w + b.pc);
     unsigned* pz = reinterpret_cast<unsigned*>(w + b.pz);
     int* pf = reinterpret_cast<int*>(w + b.pf);
-    hipLaunchKernelGGL(voxel_count, dim3(b.nb), blk, 0, s, p4, H, N, nx, ny, xmin, ymin, scale,
-                       b.T, b.nb);
-    hipLaunchKernelGGL(voxel_scan, dim3(b.T), blk, 0, s, H, tc, b.nb);
-    hipLaunchKernelGGL(voxel_place, dim3(b.nb), blk, 0, s, p4, vidx, H, tc, rz, ri, rc, N, nx, ny,
-                       xmin, ymin, scale, b.T, b.nb);
-    hipLaunchKernelGGL(voxel_reduce, dim3(b.smax), blk, 0, s, tc, rz, ri, rc, pc, pz, pf, b.T);
-    hipLaunchKernelGGL(voxel_merge, dim3(grid_for(G, INT_MAX)), blk, 0, s, tc, pc, pz, pf, count,
-                       zmax, first, G, b.T);
+    hipLaunchKernelGGL(voxel_bin, dim3(b.nb), blk, 0, s, p4, vidx, H, R, N, nx, ny, xmin, ymin,
+                       scale, b.T);
+    hipLaunchKernelGGL(voxel_tile_reduce, dim3(b.T * b.groups), blk, 0, s, H, R, pc, pz, pf, b.T,
+                       b.nb, b.groups, b.cpg);
+    hipLaunchKernelGGL(voxel_merge, dim3(grid_for(G, INT_MAX)), blk, 0, s, pc, pz, pf, count,
+                       zmax, first, G, b.groups);
     return hipGetLastError();
   }
   unsigned* zk = reinterpret_cast<unsigned*>(zmax);

@@ -524,7 +524,8 @@ ECPU_CFG1 = [17.4, 16.2, 21.0, 20.2, 21.8, 20.2, 21.8, 21.0, 21.3, 11.2, 17.8]
 
 
 def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
-            jitter_ms=15.0, chains_subset=None, custom=None, cpu=0.0, private=False, bf16=False):
+            jitter_ms=15.0, chains_subset=None, custom=None, cpu=0.0, private=False, bf16=False,
+            repeat=1):
     """Eleven chains of 2-6 tasks with 50-300 FP32 kernels per task.
 
     Per-chain GPU work per frame is proportional to the paper's E_gpu of the
@@ -549,9 +550,14 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
     the tasks like the GPU budget.
 
     ``private`` and ``bf16``: see _build_chain (configuration 2).
+
+    ``repeat`` > 1 takes the row list that many times (each copy a chain of
+    its own, drawn from its own stream) at the same total u_target: more,
+    smaller chains (the scheduling-overhead experiment, Sec. 6.5).
     """
     rng = np.random.default_rng([seed, 1])
     rows = CHAINS_CFG1 if chains_subset is None else [CHAINS_CFG1[i] for i in chains_subset]
+    rows = rows * repeat
     lam = u_target / sum(e / p for _, _, p, e in rows)
     n = len(rows)
     n_tight = int(round(f_tight * n))
@@ -574,6 +580,8 @@ def config1(seed=0, f_a=1.0, f_d=1.0, f_tight=0.4, u_target=1.6, window_s=10.0,
         deadline = int(period * (0.5 if ci in tight else 1.0) * f_d)
         ch = _build_chain(name, modality, period, deadline, task_blocks, scales,
                           private=private, bf16=bf16)
+        if ci >= len(rows) // repeat:
+            ch.name = f"{name}_r{ci // (len(rows) // repeat)}"
         if cpu > 0:
             ecpu = ECPU_CFG1[CHAINS_CFG1.index(rows[ci])]
             for j, task in enumerate(ch.tasks):

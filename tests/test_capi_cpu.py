@@ -412,3 +412,44 @@ def test_chain_tails_match_the_oracle():
         total += len(expect)
     assert total > 100
     g.close()
+
+
+def test_tile_table_set_load_and_errors(tmp_path):
+    """The tuning table (host logic): variants per op, set / remove / clear,
+    a table file with comments, a malformed file adds nothing, and the
+    variant a launch would take follows the table."""
+    conv = {"op": "conv3x3", "shape": (1, 32, 64, 64), "in": (0, 1), "out": (2,)}
+    gemm = {"op": "gemm", "shape": (256, 512, 1024), "in": (0, 1), "out": (2,)}
+    capi.tile_clear()
+    assert capi.tile_variants("gemm") == 3 and capi.tile_variants("conv3x3") == 5
+    assert capi.tile_variants("softmax") == 0
+    rule_c, rule_g = capi.tile_get(conv), capi.tile_get(gemm)
+    assert 0 <= rule_c < 5 and 0 <= rule_g < 3
+    capi.tile_set("conv3x3", conv["shape"], (rule_c + 1) % 5)
+    assert capi.tile_get(conv) == (rule_c + 1) % 5 and capi.tile_get(gemm) == rule_g
+    capi.tile_set("conv3x3", conv["shape"], -1)
+    assert capi.tile_get(conv) == rule_c
+    with pytest.raises(capi.UgError):
+        capi.tile_set("conv3x3", conv["shape"], 5)
+    with pytest.raises(capi.UgError):
+        capi.tile_set("softmax", (4, 4), 0)
+    good = tmp_path / "tiles.txt"
+    good.write_text(f"# a table\n{capi.OP_GEMM_F32} 256 512 1024 0 {(rule_g + 2) % 3}  # us 1 2 3\n"
+                    "\n3 1 32 64 64 0\n")
+    assert capi.tile_load(str(good)) == 2
+    assert capi.tile_get(gemm) == (rule_g + 2) % 3 and capi.tile_get(conv) == 0
+    capi.tile_clear()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("3 1 32 64 64 0\n1 256 512 1024\n")
+    with pytest.raises(capi.UgError):
+        capi.tile_load(str(bad))
+    assert capi.tile_get(conv) == rule_c           # nothing added
+    with pytest.raises(capi.UgError):
+        capi.tile_load(str(tmp_path / "missing.txt"))
+    # a context created with a table reads it
+    g = capi.Gate(device=-1, tile_table=str(good))
+    assert capi.tile_get(conv) == 0
+    g.close()
+    with pytest.raises(capi.UgError):
+        capi.Gate(device=-1, tile_table=str(bad))
+    capi.tile_clear()

@@ -250,8 +250,9 @@ def _cloud(seed, n, sigma=20.0):
 
 
 # Large clouds take the binned path (tiles of 4096 cells, chunks of 8192
-# points, segments of 65536 records): sizes that are ragged in all three.
-@pytest.mark.parametrize("n", [1 << 20, 1_100_003])
+# points, reduce workgroups over groups of chunks): sizes that are ragged in
+# all three (8 Mi + 5 points: 1025 chunks in 8 groups of up to 129).
+@pytest.mark.parametrize("n", [1 << 20, 1_100_003, (8 << 20) + 5])
 def test_voxel_binned_bit_exact(n):
     P = _cloud(n, n)
     assert capi.kernel_workspace({"op": "voxel", "shape": (n, 512, 512), "in": (0,),
@@ -260,7 +261,7 @@ def test_voxel_binned_bit_exact(n):
 
 
 def test_voxel_binned_hot_cell_many_segments():
-    # 1.2 M points in one cell (19 segments of one tile), signed zeros and
+    # 1.2 M points in one cell (every chunk's whole run in one tile), signed zeros and
     # -inf among its z values, a few points elsewhere and outside
     n = 1_200_000
     r = rng(11)

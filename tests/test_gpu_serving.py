@@ -265,8 +265,10 @@ def test_cfg3_frames_alone_and_in_the_mix_bit_identical():
     # every output of those frames is bit-identical
     wl = synth.config3(seed=3, window_s=0.2)
     dw = runner.DeviceWorkload(wl, n_sets=_frames_per_chain(wl))
-    lidar = [c for c in wl.meta["frame_dims"] if wl.meta["dims"][(c, 0)][0] > 0][:2]
-    cams = [c for c in wl.meta["frame_dims"] if wl.meta["dims"][(c, 0)][1] > 0][:2]
+    # chains whose frame 0 arrives in the window
+    have = [c for c in wl.meta["frame_dims"] if (c, 0) in wl.meta["dims"]]
+    lidar = [c for c in have if wl.meta["dims"][(c, 0)][0] > 0][:2]
+    cams = [c for c in have if wl.meta["dims"][(c, 0)][1] > 0][:2]
     picks = [(c, 0) for c in lidar + cams]
     assert len(picks) == 4
     est = profs = None
