@@ -210,6 +210,8 @@ def sweep_main(args, torch, capi, runner, synth):
                                          flags=v.get("flags", 0),
                                          **({"cpu_cores": cores} | v.get("cfg", {})))
                     runner.copy_estimates(prof, g, wl)
+                    if v.get("flags", 0) & GRAPH:
+                        runner.prepare_graphs(g, dw)
                     run_policy(g, dw, warm[: len(warm) // 2], torch)
                     th = 0
                     cu, m, st, wall = run_policy(g, dw, timed, torch)
@@ -226,6 +228,10 @@ def sweep_main(args, torch, capi, runner, synth):
                                      **({"cpu_cores": cores} | v.get("cfg", {})))
                 runner.copy_estimates(prof, g, wl)
                 flags = v.get("flags", FULL) | capi.F_PLACE
+                if flags & GRAPH:
+                    # every task's graph captured before the run
+                    g.set_flags(flags)
+                    runner.prepare_graphs(g, dw)
                 g.set_flags((flags & ~capi.F_DELAY) | capi.F_CALIBRATE)
                 g.set_threshold(0)
                 run_policy(g, dw, warm, torch)
@@ -745,6 +751,76 @@ def roofline_op(op, reps, torch):
             "reps": reps, "flops": flops, "bytes": nbytes, "traffic": measured_traffic(op)}
 
 
+def tail_roofline(torch, capi, reps=5):
+    """The tail executor on one large item (bias+ReLU of 16384 x 16384 with
+    the row sums; 8 B per element read and written), all 255 worker
+    workgroups, timed on the host from publication to the finished flag
+    (the executor is a persistent kernel: its own duration includes its idle
+    wait), after a 512 MiB flush write; median of reps."""
+    R = C = 16384
+    dev = "cuda:0"
+    x = torch.rand(R * C, device=dev) - 0.5
+    y = torch.empty_like(x)
+    b = torch.rand(C, device=dev) - 0.5
+    rs = torch.empty(R, device=dev)
+    flush = torch.empty(512 << 20 >> 2, device=dev)
+    torch.cuda.synchronize()
+    q = capi.TailQueue(workers=255, idle_ns=5_000_000)
+    times = []
+    for i in range(reps + 2):
+        flush.fill_(1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        slot, pub = q.publish(x.data_ptr(), y.data_ptr(), b.data_ptr(), R, C, 0, key=i,
+                              rs=rs.data_ptr())
+        q.kick()
+        while not q.finished(slot, pub):
+            pass
+        if i >= 2:
+            times.append(time.perf_counter() - t0)
+    q.close()
+    nbytes = 8 * R * C + 4 * C + 4 * R
+    med = sorted(times)[len(times) // 2]
+    achieved = nbytes / med / 1e9
+    del x, y, flush
+    torch.cuda.empty_cache()
+    return {"kernel": "tail_executor", "shape": [R, C, 0], "bound": "hbm",
+            "achieved": round(achieved, 2), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": round(achieved / (PEAK_HBM / 1e9), 4), "avg_us": round(sum(times) / len(times) * 1e6, 2),
+            "median_us": round(med * 1e6, 2), "reps": reps, "flops": 2 * R * C, "bytes": nbytes,
+            "traffic": None, "timing": "host, publication to finished flag"}
+
+
+def stream_ceiling(torch, capi, reps=10):
+    """A project-written stream kernel as the practical HBM ceiling: the
+    vector add c = a + b over 2^28 floats (3 GiB moved) by 65536 workgroups,
+    timed with HIP events on its stream after a flush write."""
+    n = 1 << 28
+    dev = "cuda:0"
+    a, b, c = (torch.rand(n, device=dev) for _ in range(3))
+    flush = torch.empty(512 << 20 >> 2, device=dev)
+    k = {"op": "vecadd", "shape": (n, 65536, 1), "in": (0, 1), "out": (2,)}
+    ptrs = [a.data_ptr(), b.data_ptr(), c.data_ptr()]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        capi.kernel_launch(k, ptrs, s.cuda_stream)
+        ev = []
+        for _ in range(reps):
+            flush.fill_(1.0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            capi.kernel_launch(k, ptrs, s.cuda_stream)
+            e1.record(s)
+            ev.append((e0, e1))
+    torch.cuda.synchronize()
+    dur = sorted(e0.elapsed_time(e1) * 1e-3 for e0, e1 in ev)
+    med = dur[len(dur) // 2]
+    del a, b, c, flush
+    torch.cuda.empty_cache()
+    return {"kernel": "vecadd (stream: c = a + b)", "bytes": 12 * n, "median_us": round(med * 1e6, 1),
+            "GB_per_s": round(12 * n / med / 1e9, 1), "frac_of_8TBs": round(12 * n / med / PEAK_HBM, 4)}
+
+
 def copy_ceiling(torch, reps=10):
     """Practical HBM ceiling: a 1 GiB device-to-device copy (2 GiB moved),
     timed like the HBM kernels (flush write before each launch)."""
@@ -1032,8 +1108,12 @@ def main():
         kernels.append(r)
         log("roofline:", json.dumps(r))
     roof = next(r for r in kernels if r["kernel"] == dominant)
+    kernels.append(tail_roofline(torch, capi))
+    log("roofline:", json.dumps(kernels[-1]))
     ceiling = copy_ceiling(torch)
     log("hbm copy ceiling:", json.dumps(ceiling))
+    stream = stream_ceiling(torch, capi)
+    log("stream kernel ceiling:", json.dumps(stream))
     # gate cost per kernel against the raw launch loop (Sec. 6.5)
     gate_overhead = {"raw_launch_loop": launch_floor(torch, capi)}
     for n in names:
@@ -1091,6 +1171,7 @@ def main():
         | {"kernel": roof["kernel"], "shape": roof["shape"], "avg_us": roof["avg_us"]},
         "kernels": kernels,
         "hbm_copy_ceiling": ceiling,
+        "hbm_stream_kernel_ceiling": stream,
         "gate_overhead": gate_overhead,
         "cpu_baseline": cpu,
     }

@@ -750,6 +750,17 @@ ug_status ug_kernel_launch_signal(const ug_kernel* k, void* const* buffers,
                                   uint32_t n_buffers, uint32_t* counter, uint32_t* waves,
                                   void* hip_stream);
 
+/* Task graphs (UG_F_GRAPH): captures and instantiates the graph of every
+ * task of a chain for one buffer set (buffers as in ug_frame_submit; dims as
+ * in ug_frame_submit_dims, or NULL) ahead of the run, so that the gate's
+ * first launch of each finds it ready instead of capturing it on the gate
+ * thread inside a frame's latency.  With UG_F_FUSE set, the fused variant
+ * (tails left out, producers counting) is captured as well.  Before
+ * ug_start (the graphs are the gate thread's while it runs); the graphs stay
+ * until ug_destroy.  Errors: UG_EINVAL, UG_ESTATE, UG_ENODEV, UG_EDEVICE. */
+ug_status ug_graph_prepare(void* ctx, uint32_t chain, void* const* buffers, uint32_t n_buffers,
+                           const int64_t* dims, uint32_t n_dims);
+
 /* The raw launch loop of the system-overhead comparison (Sec. 6.5, Tab.
  * "Basic operations"): launches kernel k n times back to back on hip_stream
  * (after 8 untimed launches), then waits.  *host_ns: mean host time per

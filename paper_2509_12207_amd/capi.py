@@ -60,7 +60,7 @@ EXPORTED = [
     "ug_tails_open", "ug_tails_publish", "ug_tails_set_key", "ug_tails_pause", "ug_tails_kick",
     "ug_tails_finished", "ug_tails_log", "ug_tails_close", "ug_kernel_launch_signal",
     "ug_chain_tails", "ug_launch_cost", "ug_tile_variants", "ug_tile_set", "ug_tile_clear",
-    "ug_tile_get", "ug_tile_load", "ug_kernel_launch_variant",
+    "ug_tile_get", "ug_tile_load", "ug_kernel_launch_variant", "ug_graph_prepare",
 ]
 
 
@@ -216,6 +216,8 @@ def lib():
                                      C.c_uint32]
         L.ug_launch_cost.argtypes = [C.POINTER(Kernel), C.POINTER(vp), C.c_uint32, C.c_uint32, vp,
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.ug_graph_prepare.argtypes = [vp, C.c_uint32, C.POINTER(vp), C.c_uint32,
+                                       C.POINTER(C.c_int64), C.c_uint32]
         L.ug_tile_variants.argtypes = [C.c_int32]
         L.ug_tile_set.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.c_int32]
         L.ug_tile_clear.argtypes = []
@@ -236,7 +238,7 @@ def lib():
                      "ug_tails_log", "ug_tails_close", "ug_kernel_launch_signal",
                      "ug_chain_tails", "ug_launch_cost", "ug_tile_variants", "ug_tile_set",
                      "ug_tile_clear", "ug_tile_get", "ug_tile_load",
-                     "ug_kernel_launch_variant"):
+                     "ug_kernel_launch_variant", "ug_graph_prepare"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -543,6 +545,13 @@ class Gate:
                                      int(n_buffers), C.byref(cid))
         self._check(st, "ug_chain_register")
         return int(cid.value)
+
+    def prepare_graphs(self, chain, ptrs, dims=None):
+        """Capture the chain's task graphs for one buffer set before start."""
+        arr = pointer_array(ptrs)
+        d = (C.c_int64 * max(1, len(dims or [])))(*(dims or []))
+        self._check(lib().ug_graph_prepare(self.h, chain, arr, len(ptrs), d, len(dims or [])),
+                    "ug_graph_prepare")
 
     def chain_tails(self, chain, cap=4096):
         """(first, end) kernel ranges of the chain's tails that UG_F_FUSE fuses."""

@@ -258,6 +258,27 @@ unsigned* counter_of(const Ctx* c, int32_t chain, int32_t g) {
   return c->counters + c->counter_base[chain] + static_cast<size_t>(g);
 }
 
+// The completion counters (one per kernel of every chain), allocated once:
+// captured task graphs keep their addresses until the context is destroyed.
+hipError_t alloc_counters(Ctx* c) {
+  if (c->counters) return hipSuccess;
+  size_t total = 0;
+  c->counter_base.clear();
+  for (const auto& ch : c->policy.chains()) {
+    c->counter_base.push_back(total);
+    total += ch.kernels.size();
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(total, 1) * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemset(p, 0, std::max<size_t>(total, 1) * sizeof(unsigned));
+  if (e != hipSuccess) {
+    if (p) (void)hipFree(p);
+    return e;
+  }
+  c->counters = static_cast<unsigned*>(p);
+  return hipSuccess;
+}
+
 // Graph of task j of a chain for a frame's buffers and sizes: captured on
 // first use (every kernel of the task in order on the capture stream, in
 // relaxed mode so other threads' HIP calls are unaffected), instantiated and
@@ -884,8 +905,8 @@ void ug_destroy(void* ctx) {
   stop_thread(c);
   if (c->has_device) {
     (void)hipSetDevice(c->cfg.device);
+    // the executor first: a stream on its hardware queue waits behind it
     c->tails.reset();
-    if (c->counters) (void)hipFree(c->counters);
     if (c->fuse_stream) {
       (void)hipStreamSynchronize(c->fuse_stream);
       (void)hipStreamDestroy(c->fuse_stream);
@@ -894,6 +915,8 @@ void ug_destroy(void* ctx) {
     for (auto& lv : c->level_streams)
       for (hipStream_t s : lv) (void)hipStreamSynchronize(s);
     for (hipStream_t s : c->fifo_streams) (void)hipStreamSynchronize(s);
+    if (c->capture_stream) (void)hipStreamSynchronize(c->capture_stream);
+    if (c->counters) (void)hipFree(c->counters);
     for (hipStream_t s : c->owned_streams) (void)hipStreamDestroy(s);
     for (hipEvent_t e : c->all_events) (void)hipEventDestroy(e);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -1215,22 +1238,18 @@ ug_status ug_start(void* ctx) {
   if (c->cfg.flags & UG_F_FUSE) {
     if (c->cfg.fuse_workers < 1 || c->cfg.fuse_workers > 1024 || c->cfg.fuse_idle_ns <= 0)
       return fail(c, UG_EINVAL, "fused tails need fuse_workers in 1..1024 and fuse_idle_ns > 0");
-    // one completion counter per kernel of every chain, zero between uses
-    size_t total = 0;
-    c->counter_base.clear();
-    for (const auto& ch : c->policy.chains()) {
-      c->counter_base.push_back(total);
-      total += ch.kernels.size();
-    }
+    // one completion counter per kernel of every chain, kept for the
+    // context's life (captured graphs hold their addresses), zeroed at
+    // every start
     hipError_t e = hipSuccess;
     if (!c->fuse_stream &&
         (e = hipStreamCreateWithFlags(&c->fuse_stream, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(c, e, "tail executor stream");
-    void* p = nullptr;
-    if ((e = hipMalloc(&p, std::max<size_t>(total, 1) * sizeof(unsigned))) != hipSuccess)
-      return hip_fail(c, e, "completion counters");
-    c->counters = static_cast<unsigned*>(p);
-    if ((e = hipMemset(p, 0, std::max<size_t>(total, 1) * sizeof(unsigned))) != hipSuccess)
+    if ((e = alloc_counters(c)) != hipSuccess) return hip_fail(c, e, "completion counters");
+    size_t total = 0;
+    for (const auto& ch : c->policy.chains()) total += ch.kernels.size();
+    if ((e = hipMemset(c->counters, 0, std::max<size_t>(total, 1) * sizeof(unsigned))) !=
+        hipSuccess)
       return hip_fail(c, e, "completion counters");
     c->tails.reset(new ug::TailQueue());
     // lease: a minute per launch, renewed by the next launch
@@ -1362,8 +1381,6 @@ ug_status ug_stop(void* ctx) {
     for (auto& lv : c->level_streams)
       for (hipStream_t s : lv) (void)hipStreamSynchronize(s);
     for (hipStream_t s : c->fifo_streams) (void)hipStreamSynchronize(s);
-    if (c->counters) (void)hipFree(c->counters);
-    c->counters = nullptr;
   }
   {
     std::lock_guard<std::mutex> lk(c->mu);
@@ -1689,6 +1706,44 @@ ug_status ug_kernel_launch_signal(const ug_kernel* k, void* const* buffers, uint
   const hipError_t e = ug::launch_kernel(*k, buffers, static_cast<hipStream_t>(hip_stream),
                                          nullptr, 0, counter);
   return e == hipSuccess ? UG_OK : UG_EDEVICE;
+}
+
+ug_status ug_graph_prepare(void* ctx, uint32_t chain, void* const* buffers, uint32_t n_buffers,
+                           const int64_t* dims, uint32_t n_dims) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return UG_EINVAL;
+  if (sticky(c)) return UG_EDEVICE;
+  if (!c->has_device) return fail(c, UG_ENODEV, "graphs need a device");
+  if (c->started) return fail(c, UG_ESTATE, "graphs are prepared before start");
+  const auto& chs = c->policy.chains();
+  if (chain >= chs.size() || !buffers || n_buffers != chs[chain].n_buffers)
+    return fail(c, UG_EINVAL, "graph_prepare: bad chain or buffer count");
+  for (uint32_t i = 0; i < n_buffers; ++i)
+    if (!buffers[i]) return fail(c, UG_EINVAL, "graph_prepare: null buffer");
+  const DimRange& dr = c->dim_range[chain];
+  if (n_dims < dr.lo.size() || (n_dims && !dims))
+    return fail(c, UG_EINVAL, "graph_prepare: the chain needs per-frame sizes");
+  for (size_t d = 0; d < dr.lo.size(); ++d)
+    if (dims[d] < dr.lo[d] || dims[d] > dr.hi[d])
+      return fail(c, UG_EINVAL, "graph_prepare: per-frame size out of the registered range");
+  (void)hipSetDevice(c->cfg.device);
+  Frame fr;
+  fr.chain = chain;
+  fr.buffers.assign(buffers, buffers + n_buffers);
+  if (n_dims) fr.dims.assign(dims, dims + n_dims);
+  if (c->cfg.flags & UG_F_FUSE) {
+    // the fused variant bakes in the counters' addresses: make them now
+    const hipError_t e = alloc_counters(c);
+    if (e != hipSuccess) return hip_fail(c, e, "completion counters");
+  }
+  for (size_t j = 0; j < chs[chain].task_first.size(); ++j) {
+    for (int fused = 0; fused < ((c->cfg.flags & UG_F_FUSE) ? 2 : 1); ++fused) {
+      hipError_t err = hipSuccess;
+      if (!task_graph(c, static_cast<int32_t>(chain), static_cast<int32_t>(j), fr, fused != 0, &err))
+        return hip_fail(c, err, "graph capture");
+    }
+  }
+  return UG_OK;
 }
 
 int32_t ug_tile_variants(int32_t op) { return ug::tile_variants(op); }

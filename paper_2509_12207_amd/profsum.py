@@ -49,7 +49,7 @@ TRAFFIC_KERNELS = {
     "bias_relu": (r"bias_relu_vec<0", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
     "rowsum": (r"rowsum_block", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
     "softmax": (r"softmax_reg<4, 4, ", 1, "paper_2509_12207_amd/csrc/kernels/pointwise.hip"),
-    "voxel": (r"voxel_(init|scatter|finalize|count|scan|place|reduce|merge)", 5,
+    "voxel": (r"voxel_(init|scatter|finalize|bin|tile_reduce|merge)", 3,
               "paper_2509_12207_amd/csrc/kernels/voxel.hip"),
     "gemm_fp8": (r"gemm_fp8_kernel|gemm_ring<0, false>", 1,
                  "paper_2509_12207_amd/csrc/kernels/gemm_lowp.hip"),

@@ -101,6 +101,15 @@ def make_gate(wl, policy="urgency", device=0, **cfg):
     return g
 
 
+def prepare_graphs(g, dw):
+    """Capture every task graph of every chain for every buffer set before
+    the run (UG_F_GRAPH), so no capture lands inside a frame's latency
+    (workloads without per-frame sizes)."""
+    for c in range(len(dw.wl.chains)):
+        for k in range(dw.n_sets):
+            g.prepare_graphs(c, dw.ptrs[c][k])
+
+
 def profile(g, dw, warmup=3, reps=10):
     for c in range(len(dw.wl.chains)):
         g.profile(c, dw.ptrs[c][0], warmup=warmup, reps=reps)

@@ -237,3 +237,25 @@ def test_cfg2_window_fused_replay_and_sampled_outputs(policy, graph):
     chains = T.oracle_chains(wl, est)
     assert des.replay(chains, oracle_cfg(policy, th=3 * MS, graph=graph), inst) is None
     assert check_cfg1_outputs(wl, dw, 0, samples=3, seed=2) >= 8
+
+
+def test_fused_task_graphs_prepared_and_run_twice():
+    # graphs captured before the run (ug_graph_prepare) hold the producers'
+    # counters; the same gate runs the window twice (stop, start): every
+    # frame completes both times and the outputs match the oracle
+    wl = synth.config2(seed=4, window_s=0.15)
+    n_sets = _frames_per_chain(wl)
+    dw = runner.DeviceWorkload(wl, n_sets=n_sets)
+    g = runner.make_gate(wl, "urgency", trace_capacity=1 << 22, th_slack_ns=3 * MS,
+                         flags=FUSED | capi.F_GRAPH)
+    runner.profile(g, dw, warmup=1, reps=2)
+    runner.prepare_graphs(g, dw)
+    for _ in range(2):
+        g.start()
+        comps, _ = runner.run(g, dw, wl.arrivals)
+        g.drain(60.0)
+        g.stop()
+        assert len(comps) == len(wl.arrivals)
+        assert g.stats()["tails_fused"] > 50
+    g.close()
+    assert check_cfg1_outputs(wl, dw, 0, samples=2, seed=5) >= 8
