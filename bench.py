@@ -353,7 +353,7 @@ def seed_run(args, torch, runner, synth, seed, W, H, names, reps=2, overload=Fal
         g.close()
     del dw
     return {"wl": wl, "util": util, "by_op": by_op, "th": th, "runs": runs, "timed": timed,
-            "n_kernels": n_kernels, "be_rate": be_rate, "be_frame_ns": be_frame_ns}
+            "n_kernels": n_kernels, "be_rate": be_rate, "be_frame_ns": be_frame_ns, "est": est}
 
 
 def pooled_seeds(seed_runs):
@@ -380,6 +380,67 @@ def pooled_seeds(seed_runs):
         return round(float(lat[max(0, -(-p * n // 100) - 1)]) / 1e6, 3) if n else None
     return {"miss_ratio_pct": round(100.0 * float(np.mean(ratios)) if ratios else 0.0, 3),
             "p50_ms": pct(50), "p99_ms": pct(99), "frames": frames, "missed": missed}
+
+
+def kernel_work(op, shape):
+    """Algorithmic (FLOP, bytes, compute peak) of one kernel."""
+    s = list(shape)
+    if op in ("gemm", "gemm_bf16", "gemm_fp8"):
+        M, N, K = s[:3]
+        ob = {"gemm": 4, "gemm_bf16": 2, "gemm_fp8": 1}[op]
+        peak = {"gemm": PEAK_FP32_MFMA, "gemm_bf16": PEAK_BF16_MFMA, "gemm_fp8": PEAK_FP8_MFMA}[op]
+        return 2 * M * N * K, ob * (M * K + K * N) + 4 * M * N, peak
+    if op in ("conv3x3", "conv3x3_bf16"):
+        n, C, H, W = s[:4]
+        ob = 4 if op == "conv3x3" else 2
+        peak = PEAK_FP32_MFMA if op == "conv3x3" else PEAK_BF16_MFMA
+        return 18 * n * C * C * H * W, ob * (n * C * H * W + 9 * C * C) + 4 * n * C * H * W, peak
+    if op == "bias_relu":
+        R, C = s[:2]
+        return 2 * R * C, 8 * R * C + 4 * (C if s[2] == 0 else R), None
+    if op == "rowsum":
+        R, C = s[:2]
+        return R * C, 4 * R * C + 4 * R, None
+    if op == "softmax":
+        R, L = s[:2]
+        return 5 * R * L, 8 * R * L, None
+    if op == "voxel":
+        return 0, 20 * s[0] + 12 * s[1] * s[2], None
+    return 0, 0, None
+
+
+def workload_kernels(wl, est, floor_us, top=8):
+    """The workload's kernels by (op, shape), ranked by their share of the
+    isolated GPU time per second of arrivals (profiled E times frames per
+    second): E, the time at the roofline (max of FLOP / compute peak and
+    bytes / 8 TB/s, the compute peak at the op's own precision), the
+    fraction of roofline E reaches, and E against the empty-kernel floor."""
+    rows = {}
+    for c, ch in enumerate(wl.chains):
+        if not ch.period_ns:
+            continue
+        g = 0
+        for t in ch.tasks:
+            for k in t["kernels"]:
+                e = est[(c, g)][0]
+                key = (k["op"], tuple(int(v) for v in k["shape"]))
+                r = rows.setdefault(key, {"e_ns": [], "per_s": 0.0})
+                r["e_ns"].append(e)
+                r["per_s"] += 1e9 / ch.period_ns
+                g += 1
+    total = sum(sum(r["e_ns"]) / len(r["e_ns"]) * r["per_s"] for r in rows.values())
+    out = []
+    for (op, shape), r in rows.items():
+        e = sum(r["e_ns"]) / len(r["e_ns"])
+        flops, nbytes, peak = kernel_work(op, shape)
+        t_roof = max(flops / peak if peak else 0.0, nbytes / PEAK_HBM) * 1e9
+        out.append({"op": op, "shape": list(shape), "calls_per_s": round(r["per_s"], 1),
+                    "share": round(e * r["per_s"] / total, 4), "e_us": round(e / 1e3, 2),
+                    "roofline_us": round(t_roof / 1e3, 3),
+                    "frac_of_roofline": round(t_roof / e, 4) if e else None,
+                    "e_over_empty_kernel": round(e / 1e3 / floor_us, 2) if floor_us else None})
+    out.sort(key=lambda x: -x["share"])
+    return out[:top]
 
 
 def launch_floor(torch, capi):
@@ -851,7 +912,7 @@ def copy_ceiling(torch, reps=10):
 
 
 # ----------------------------------------------------------------------------
-def cpu_baseline(wl, budget_s):
+def cpu_baseline(wl, budget_s, est=None):
     """The oracle (numpy, as written) executing frame 0 of every chain, in
     chain order, each for at most its deadline (or until the frame is done):
     a frame not done within its deadline is a miss."""
@@ -907,7 +968,33 @@ def cpu_baseline(wl, budget_s):
                        f"{spent:.1f} s of CPU time"),
             "kernels_per_s": round(kernels_done / max(spent, 1e-9), 2),
             "frame_ms_projected": frame_ms, "deadline_ms": deadline_ms,
-            **cpu_host(), "kernel_rates": cpu_kernel_rates()}
+            **cpu_host(), "kernel_rates": cpu_kernel_rates(),
+            "des": des_rate(wl, est) if est else None}
+
+
+def des_rate(wl, est, window_s=0.5):
+    """The oracle's discrete-event model of the gate (the urgency policy on
+    a serial device, kernel times = the profiled estimates) over the first
+    window_s seconds of arrivals: simulated seconds per wall second."""
+    from oracle import des
+    chains = []
+    for c, ch in enumerate(wl.chains):
+        tasks, g = [], 0
+        for task in ch.tasks:
+            n = len(task["kernels"])
+            tasks.append({"cpu_ns": task.get("cpu_ns", 0),
+                          "est_ns": [est[(c, g + i)][0] for i in range(n)],
+                          "util": [est[(c, g + i)][1] for i in range(n)]})
+            g += n
+        chains.append({"deadline_ns": ch.deadline_ns, "tasks": tasks})
+    arr = [a for a in wl.arrivals if a[2] < window_s * 1e9]
+    t0 = time.perf_counter()
+    r = des.simulate(chains, {"policy": "urgency", "th_slack_ns": 3_000_000}, arr,
+                     lambda c, f, g: est[(c, g)][0])
+    wall = time.perf_counter() - t0
+    sim = max((x[3] for x in r["completed"]), default=0) / 1e9
+    return {"frames": len(arr), "instants": len(r["instants"]), "simulated_s": round(sim, 3),
+            "wall_s": round(wall, 3), "simulated_s_per_wall_s": round(sim / wall, 3) if wall else None}
 
 
 def cpu_host():
@@ -1053,6 +1140,7 @@ def main():
     wl, util, by_op, th = main_run["wl"], main_run["util"], main_run["by_op"], main_run["th"]
     runs, timed, n_kernels = main_run["runs"], main_run["timed"], main_run["n_kernels"]
     be_rate, be_frame_ns = main_run["be_rate"], main_run["be_frame_ns"]
+    est_main = main_run["est"]
     dominant = max(by_op, key=by_op.get)
     summary = {n: pooled(runs[n], wl, len(timed), be_rate) for n in names}
     for n in names:
@@ -1116,6 +1204,9 @@ def main():
     log("stream kernel ceiling:", json.dumps(stream))
     # gate cost per kernel against the raw launch loop (Sec. 6.5)
     gate_overhead = {"raw_launch_loop": launch_floor(torch, capi)}
+    floor_us = gate_overhead["raw_launch_loop"]["empty"]["device_us_per_kernel"]
+    wk = workload_kernels(wl, est_main, floor_us)
+    log("workload kernels:", json.dumps(wk))
     for n in names:
         gate_overhead[n] = {k: summary[n][k] for k in ("gate_decide_us_per_instant",
                                                         "launch_us_per_launch",
@@ -1125,7 +1216,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         t = time.time()
-        cpu = cpu_baseline(wl, args.cpu_budget_s)
+        cpu = cpu_baseline(wl, args.cpu_budget_s, est_main)
         log(f"cpu baseline in {time.time() - t:.1f} s: {cpu}")
 
     value = urg_sum["miss_ratio_pct"]
@@ -1173,6 +1264,7 @@ def main():
         "hbm_copy_ceiling": ceiling,
         "hbm_stream_kernel_ceiling": stream,
         "gate_overhead": gate_overhead,
+        "workload_kernels": wk,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
