@@ -20,7 +20,11 @@ Readings (the paper has no fused form; these are the choices built):
   at most one row sum (in either order) that read the bias+ReLU output with
   the same rows and row length.  Rows are a multiple of 4 floats long, at
   most 4096 with a softmax, and no kernel of the tail or its producer takes
-  a per-frame size (these are limits of the executor built).  It is fused
+  a per-frame size (these are limits of the executor built).  Only short
+  kernels are fused: the bias+ReLU input is at most 1 MiB.  A larger tail
+  runs at full-device bandwidth as ordinary launches, where the launch cost
+  that batching saves is a small part of its time; on the executor it
+  would occupy a few workgroups for much longer.  It is fused
   only if no later kernel of the task writes a buffer the tail reads or
   writes, or reads a buffer the tail writes, so that running it outside the
   task's stream order changes no result; the task counts as finished only
@@ -41,6 +45,7 @@ from . import kernels as K
 
 CONTRACTIONS = ("gemm", "conv3x3", "gemm_bf16", "conv3x3_bf16")
 MAX_SOFTMAX_ROW = 4096     # a fused softmax holds its row in registers
+MAX_TAIL_BYTES = 1 << 20   # short kernels only: at most 1 MiB of FP32 input
 
 
 def tail_outputs(x, bias, axis, softmax, rowsum):
@@ -88,6 +93,7 @@ def tail_runs(kernels):
             seen.add(kernels[end]["op"])
             end += 1
         if C % 4 or ("softmax" in seen and C > MAX_SOFTMAX_ROW) \
+                or 4 * R * C > MAX_TAIL_BYTES \
                 or any(kk.get("frame_dim", 0) for kk in kernels[i - 1:end]):
             i = end
             continue

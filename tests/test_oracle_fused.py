@@ -98,12 +98,19 @@ def test_tail_runs_executor_limits():
     ks = [gemm(0, 1, 2), br(2, 3, 2, C=4098)]
     assert F.tail_runs(ks) == []
     # long rows without a softmax fuse; with one they do not
-    ks = [gemm(0, 1, 2), br(2, 3, 2, C=8192), rs(2, 5, C=8192)]
+    ks = [gemm(0, 1, 2), br(2, 3, 2, R=8, C=8192), rs(2, 5, R=8, C=8192)]
     assert F.tail_runs(ks) == [(1, 3)]
-    ks = [gemm(0, 1, 2), br(2, 3, 2, C=8192), sm(2, 5, C=8192)]
+    ks = [gemm(0, 1, 2), br(2, 3, 2, R=8, C=8192), sm(2, 5, R=8, C=8192)]
     assert F.tail_runs(ks) == []
     # a per-frame size anywhere in the producer or the tail
     ks = [dict(gemm(0, 1, 2), frame_dim=1), br(2, 3, 2)]
+    assert F.tail_runs(ks) == []
+    # short kernels only: 1 MiB of input fuses, a row more does not
+    ks = [gemm(0, 1, 2), br(2, 3, 2, R=512, C=512), sm(2, 4, R=512, C=512)]
+    assert F.tail_runs(ks) == [(1, 3)]
+    ks = [gemm(0, 1, 2), br(2, 3, 2, R=513, C=512), sm(2, 4, R=513, C=512)]
+    assert F.tail_runs(ks) == []
+    ks = [gemm(0, 1, 2), br(2, 3, 2, R=64, C=4100)]
     assert F.tail_runs(ks) == []
 
 
