@@ -687,11 +687,11 @@ ug_status ug_kernel_util(const ug_kernel* k, int32_t device, float* util);
  * launching amortises (Sec. 4.4.5) is, for the short pointwise and reduction
  * kernels after each contraction, most of their time.  The tail executor is
  * one long-lived kernel (one dispatcher and `workers` worker workgroups)
- * that takes such tails from a queue in device memory: the host publishes an
- * item with a key, the item becomes ready when its producer's completion
- * counter reaches its target, and the executor serves ready items' tiles
- * (groups of rows) smallest key first, so that the most urgent chain's work
- * runs first (Sec. 4.2).  A tail computes y = max(x + b, +0) (the bias+ReLU
+ * that takes such tails from a queue: the host publishes an item with a
+ * key, the item becomes ready when its producer's completion counter
+ * reaches its target, and the dispatcher hands ready items' tiles (groups of
+ * rows) to idle workers smallest key first, so that the most urgent chain's
+ * work runs first (Sec. 4.2).  A tail computes y = max(x + b, +0) (the bias+ReLU
  * of UG_OP_BIAS_RELU_F32, bit for bit), then optionally the softmax of each
  * row of y and the sum of each row of y (FP32).  The gate uses it under
  * UG_F_FUSE; the calls below drive it directly.  One thread at a time per
@@ -706,7 +706,9 @@ typedef struct {
   uint32_t* counter;       /* the producer's completion counter (device
                               memory, zero before the producer's launch), or
                               NULL: ready at once.  Reset to zero when the
-                              item becomes ready                             */
+                              item becomes ready.  One producer launch per
+                              counter at a time: a counter shared by two
+                              outstanding items can leave one never ready  */
   uint32_t counter_target; /* its value once the producer has finished (the
                               *waves of ug_kernel_launch_signal)             */
   uint32_t rows, cols;     /* cols a multiple of 4; x, y, sm and (axis 0)
@@ -722,8 +724,10 @@ typedef struct {
  * UG_EDEVICE. */
 ug_status ug_tails_open(int32_t device, uint32_t workers, int64_t idle_ns, uint32_t log_cap,
                         void** queue);
-/* Publishes an item with its key (smaller first); returns its slot and
- * publication number.  Errors: UG_EINVAL (shape, alignment, NULL), UG_EAGAIN
+/* Publishes an item with its key (smaller first; ties by slot); returns its
+ * slot and publication number.  Its rows per tile: about rows / workers,
+ * between 16 KiB and 128 KiB of input (at least one row), rounded up to a
+ * multiple of 4.  Errors: UG_EINVAL (shape, alignment, NULL), UG_EAGAIN
  * (all 512 slots hold unfinished items). */
 ug_status ug_tails_publish(void* queue, const ug_tail* t, uint64_t key, uint32_t* slot,
                            uint64_t* pub);
@@ -737,7 +741,8 @@ ug_status ug_tails_kick(void* queue);
 /* 1 if the item published as `pub` in `slot` has finished (the slot is
  * free again), 0 if not, < 0 on error. */
 int32_t ug_tails_finished(void* queue, uint32_t slot, uint64_t pub);
-/* Copies up to cap service-log entries; returns the count. */
+/* Copies up to cap service-log entries (in the order the tiles were handed
+ * to workers); returns the count. */
 int32_t ug_tails_log(void* queue, uint64_t* out, uint32_t cap);
 /* Stops the executor, waits for it, frees everything. */
 ug_status ug_tails_close(void* queue);
@@ -803,9 +808,11 @@ ug_status ug_kernel_launch_variant(const ug_kernel* k, void* const* buffers, uin
  * < 0.  A tail is a bias+ReLU right after a contraction whose output it
  * reads, with at most one row softmax and one row sum of its output after
  * it (same rows and row length); rows a multiple of 4 floats, at most 4096
- * with a softmax; no per-frame sizes; and no later kernel of the task
- * writes a buffer the tail reads or writes, or reads one it writes (so the
- * tail may run outside the task's stream order). */
+ * with a softmax; short kernels only (at most 1 MiB of bias+ReLU input: a
+ * larger tail gains little from saving launches and runs faster at
+ * full-device bandwidth); no per-frame sizes; and no later kernel of the
+ * task writes a buffer the tail reads or writes, or reads one it writes (so
+ * the tail may run outside the task's stream order). */
 int32_t ug_chain_tails(void* ctx, uint32_t chain, int32_t* first, int32_t* end, uint32_t cap);
 
 #ifdef __cplusplus

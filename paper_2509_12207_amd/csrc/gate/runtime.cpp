@@ -60,10 +60,22 @@ using EvKey = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t>;  // c, f,
 using GraphKey = std::tuple<int32_t, int32_t, std::vector<void*>, std::vector<int64_t>, bool>;
 using TaskKey = std::tuple<int32_t, int64_t, int32_t>;  // c, f, task
 
-// A tail published to the executor for an instance's task.
+// A captured task graph.  A fused graph's producers count on counters of
+// its own (one per producer, by kernel index in the task; null elsewhere),
+// so it is launched fused only while no item of an earlier launch still
+// uses them (`busy` counts those items until they are seen finished).
+struct GraphRec {
+  hipGraphExec_t ge = nullptr;
+  std::vector<unsigned*> sig;
+  uint32_t busy = 0;
+};
+
+// A tail published to the executor for an instance's task, and the graph
+// whose counter it waits on (null: a slot's own counter).
 struct TailRec {
   uint32_t slot;
   uint64_t pub;
+  GraphRec* graph;
 };
 
 struct Ctx {
@@ -92,22 +104,27 @@ struct Ctx {
   std::map<ug::Key, Frame> frames;                      // arrived, not completed
   // task graphs (UG_F_GRAPH): captured on their own stream, launched on the
   // task's bound stream; kept until the context is destroyed
-  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::map<GraphKey, GraphRec> graphs;
   hipStream_t capture_stream = nullptr;
   std::vector<Frame> pending;                           // submitted, not arrived
 
   // fused tails (UG_F_FUSE): the tails of every chain ([chain][kernel]: the
   // end of the tail the kernel starts, -1, or -2 inside a tail), the
-  // executor's queue and stream, one completion counter per kernel, the
+  // executor's queue and stream, the completion counters (one per queue
+  // slot for producers launched one by one: a slot's item is the only user
+  // of its counter; fused graphs take theirs from `counter_chunks`), the
   // items published per task instance (in order) with the prefix seen
   // finished, slots reserved by a producer's launch for its tail, the
   // kernel up to which an instance's launches are covered by a fused tail,
-  // and the items each recorded event waits for
+  // and the items each recorded event waits for.  Counters live as long as
+  // the context (captured graphs hold their addresses) and are zeroed at
+  // every start.
   std::vector<std::vector<int32_t>> tail_mark;
   std::unique_ptr<ug::TailQueue> tails;
   hipStream_t fuse_stream = nullptr;
-  unsigned* counters = nullptr;
-  std::vector<size_t> counter_base;
+  unsigned* slot_counters = nullptr;
+  std::vector<unsigned*> counter_chunks;
+  size_t chunk_used = 0;
   std::map<TaskKey, std::vector<TailRec>> inst_tails;
   std::map<TaskKey, size_t> inst_tails_done;
   std::map<std::pair<ug::Key, int32_t>, uint32_t> reserved;
@@ -254,29 +271,46 @@ bool tail_ok(const Ctx* c, int32_t chain, int32_t g, const Frame& fr, ug::FuseIt
   return ug::tail_item(c->policy.chains()[chain].kernels, g, end, fr.buffers.data(), it ? it : &tmp);
 }
 
-unsigned* counter_of(const Ctx* c, int32_t chain, int32_t g) {
-  return c->counters + c->counter_base[chain] + static_cast<size_t>(g);
-}
+constexpr size_t kCounterChunk = 4096;   // graph counters per allocation
 
-// The completion counters (one per kernel of every chain), allocated once:
-// captured task graphs keep their addresses until the context is destroyed.
+// The slots' completion counters, allocated once per context.
 hipError_t alloc_counters(Ctx* c) {
-  if (c->counters) return hipSuccess;
-  size_t total = 0;
-  c->counter_base.clear();
-  for (const auto& ch : c->policy.chains()) {
-    c->counter_base.push_back(total);
-    total += ch.kernels.size();
-  }
+  if (c->slot_counters) return hipSuccess;
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, std::max<size_t>(total, 1) * sizeof(unsigned));
-  if (e == hipSuccess) e = hipMemset(p, 0, std::max<size_t>(total, 1) * sizeof(unsigned));
+  hipError_t e = hipMalloc(&p, ug::kFuseSlots * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemset(p, 0, ug::kFuseSlots * sizeof(unsigned));
   if (e != hipSuccess) {
     if (p) (void)hipFree(p);
     return e;
   }
-  c->counters = static_cast<unsigned*>(p);
+  c->slot_counters = static_cast<unsigned*>(p);
   return hipSuccess;
+}
+
+// A zeroed counter of a fused graph's own (null on failure, *err set).
+unsigned* graph_counter(Ctx* c, hipError_t* err) {
+  if (c->counter_chunks.empty() || c->chunk_used == kCounterChunk) {
+    void* p = nullptr;
+    *err = hipMalloc(&p, kCounterChunk * sizeof(unsigned));
+    if (*err == hipSuccess) *err = hipMemset(p, 0, kCounterChunk * sizeof(unsigned));
+    if (*err != hipSuccess) {
+      if (p) (void)hipFree(p);
+      return nullptr;
+    }
+    c->counter_chunks.push_back(static_cast<unsigned*>(p));
+    c->chunk_used = 0;
+  }
+  return c->counter_chunks.back() + c->chunk_used++;
+}
+
+// Zeroes every counter (at start: an earlier run may have left counts).
+hipError_t zero_counters(Ctx* c) {
+  hipError_t e = alloc_counters(c);
+  if (e == hipSuccess) e = hipMemset(c->slot_counters, 0, ug::kFuseSlots * sizeof(unsigned));
+  for (unsigned* p : c->counter_chunks)
+    if (e == hipSuccess) e = hipMemset(p, 0, kCounterChunk * sizeof(unsigned));
+  for (auto& kv : c->graphs) kv.second.busy = 0;
+  return e;
 }
 
 // Graph of task j of a chain for a frame's buffers and sizes: captured on
@@ -284,16 +318,25 @@ hipError_t alloc_counters(Ctx* c) {
 // relaxed mode so other threads' HIP calls are unaffected), instantiated and
 // cached.  With `fused`, the task's fused tails are left out and their
 // producers count their wavefronts.  On failure returns null with *err set.
-hipGraphExec_t task_graph(Ctx* c, int32_t chain, int32_t j, const Frame& fr, bool fused,
-                          hipError_t* err) {
+GraphRec* task_graph(Ctx* c, int32_t chain, int32_t j, const Frame& fr, bool fused,
+                     hipError_t* err) {
   GraphKey gk{chain, j, fr.buffers, fr.dims, fused};
   auto it = c->graphs.find(gk);
-  if (it != c->graphs.end()) return it->second;
+  if (it != c->graphs.end()) return &it->second;
   if (!c->capture_stream) {
     *err = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
     if (*err != hipSuccess) return nullptr;
   }
   const ug::ChainSpec& ch = c->policy.chains()[chain];
+  GraphRec rec;
+  rec.sig.assign(static_cast<size_t>(ch.task_end[j] - ch.task_first[j]), nullptr);
+  if (fused) {
+    // the graph's own counters, made before the capture
+    for (int32_t g = ch.task_first[j]; g + 1 < ch.task_end[j]; ++g)
+      if (tail_ok(c, chain, g + 1, fr, nullptr) &&
+          !(rec.sig[g - ch.task_first[j]] = graph_counter(c, err)))
+        return nullptr;
+  }
   *err = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed);
   if (*err != hipSuccess) return nullptr;
   hipError_t launch_err = hipSuccess;
@@ -304,11 +347,8 @@ hipGraphExec_t task_graph(Ctx* c, int32_t chain, int32_t j, const Frame& fr, boo
     }
     ug_kernel k = ch.kernels[g];
     if (k.frame_dim > 0) k = ug::frame_kernel(k, fr.dims[k.frame_dim - 1]);
-    unsigned* sig = nullptr;
-    if (fused && g + 1 < ch.task_end[j] && tail_ok(c, chain, g + 1, fr, nullptr))
-      sig = counter_of(c, chain, g);
     launch_err = ug::launch_kernel(k, fr.buffers.data(), c->capture_stream, c->ws[chain][g],
-                                   c->ws_bytes[chain][g], sig);
+                                   c->ws_bytes[chain][g], rec.sig[g - ch.task_first[j]]);
   }
   hipGraph_t graph = nullptr;
   *err = hipStreamEndCapture(c->capture_stream, &graph);
@@ -317,12 +357,10 @@ hipGraphExec_t task_graph(Ctx* c, int32_t chain, int32_t j, const Frame& fr, boo
     if (graph) (void)hipGraphDestroy(graph);
     return nullptr;
   }
-  hipGraphExec_t ge = nullptr;
-  *err = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+  *err = hipGraphInstantiate(&rec.ge, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (*err != hipSuccess) return nullptr;
-  c->graphs.emplace(std::move(gk), ge);
-  return ge;
+  return &c->graphs.emplace(std::move(gk), std::move(rec)).first->second;
 }
 
 // Key of an item of instance `key`: the instance's rank in the gate's last
@@ -340,16 +378,19 @@ uint64_t tail_key(const Ctx* c, const ug::Key& key, uint64_t pub) {
   return (rank << 32) | (pub & 0xffffffffull);
 }
 
-// Publishes the tail [g, end) of an instance's task into a reserved slot.
+// Publishes the tail [g, end) of an instance's task into a reserved slot;
+// its producer counts on `sig` (a counter of `graph`'s, or the slot's own
+// when `graph` is null).
 void publish_tail(Ctx* c, const ug::Key& key, int32_t task, int32_t g, uint32_t slot,
-                  const Frame& fr) {
+                  const Frame& fr, unsigned* sig, GraphRec* graph) {
   const ug::ChainSpec& ch = c->policy.chains()[key.first];
   ug::FuseItem it;
   (void)tail_item(ch.kernels, g, c->tail_mark[key.first][g], fr.buffers.data(), &it);
-  it.sig = reinterpret_cast<uint64_t>(counter_of(c, key.first, g - 1));
+  it.sig = reinterpret_cast<uint64_t>(sig);
   it.sig_expected = ug::signal_waves(ch.kernels[g - 1]);
   const uint64_t pub = c->tails->publish(slot, it, tail_key(c, key, c->tails->next_pub()));
-  c->inst_tails[TaskKey{key.first, key.second, task}].push_back({slot, pub});
+  if (graph) graph->busy++;
+  c->inst_tails[TaskKey{key.first, key.second, task}].push_back({slot, pub, graph});
   c->covered_to[key] = c->tail_mark[key.first][g];
   c->st_tails++;
 }
@@ -491,13 +532,14 @@ bool execute(Ctx* c, const std::vector<ug_record>& dec) {
           // the task's first kernel launches the task's graph; its other
           // kernels are inside it.  With fused tails, every tail of the task
           // that qualifies takes a slot and is published once the graph is
-          // launched (without enough free slots the unfused graph runs).
+          // launched; the unfused graph runs instead when slots are short or
+          // the fused graph's counters still serve an earlier launch's items.
           err = hipSuccess;
           if (d.kernel == ch.task_first[d.task]) {
             std::vector<std::pair<int32_t, uint32_t>> pubs;
-            bool fused = false;
+            GraphRec* rec = nullptr;
             if (mark) {
-              fused = true;
+              bool fused = true;
               for (int32_t g = ch.task_first[d.task]; g < ch.task_end[d.task]; ++g) {
                 if (!tail_ok(c, d.chain, g, fr, nullptr)) continue;
                 uint32_t slot = 0;
@@ -507,16 +549,25 @@ bool execute(Ctx* c, const std::vector<ug_record>& dec) {
                 }
                 pubs.push_back({g, slot});
               }
-              if (!fused) {
+              if (fused && !pubs.empty()) {
+                rec = task_graph(c, d.chain, d.task, fr, true, &err);
+                if (rec && rec->busy) {
+                  rec = nullptr;
+                  fused = false;
+                }
+              }
+              if (!fused || !rec) {
                 for (auto& p : pubs) c->tails->unreserve(p.second);
-                c->st_tails_unfused += pubs.size();
+                if (err == hipSuccess) c->st_tails_unfused += pubs.size();
                 pubs.clear();
               }
             }
-            hipGraphExec_t ge = task_graph(c, d.chain, d.task, fr, fused && !pubs.empty(), &err);
-            if (ge) err = hipGraphLaunch(ge, c->bound.at(key));
+            if (!rec && err == hipSuccess) rec = task_graph(c, d.chain, d.task, fr, false, &err);
+            if (rec) err = hipGraphLaunch(rec->ge, c->bound.at(key));
             if (err == hipSuccess)
-              for (auto& p : pubs) publish_tail(c, key, d.task, p.first, p.second, fr);
+              for (auto& p : pubs)
+                publish_tail(c, key, d.task, p.first, p.second, fr,
+                             rec->sig[p.first - 1 - ch.task_first[d.task]], rec);
           }
         } else if (mark && (*mark)[d.kernel] == -2 && d.kernel < c->covered_to[key]) {
           // inside a fused tail: the executor runs it
@@ -526,7 +577,8 @@ bool execute(Ctx* c, const std::vector<ug_record>& dec) {
           // a slot, else launched as usual
           auto r = c->reserved.find({key, d.kernel});
           if (r != c->reserved.end()) {
-            publish_tail(c, key, d.task, d.kernel, r->second, fr);
+            publish_tail(c, key, d.task, d.kernel, r->second, fr, c->slot_counters + r->second,
+                         nullptr);
             c->reserved.erase(r);
             err = hipSuccess;
           } else {
@@ -534,13 +586,13 @@ bool execute(Ctx* c, const std::vector<ug_record>& dec) {
           }
         } else if (mark && d.kernel + 1 < ch.task_end[d.task] &&
                    tail_ok(c, d.chain, d.kernel + 1, fr, nullptr)) {
-          // the producer of a tail: counts its wavefronts when a slot is
-          // free for the tail
+          // the producer of a tail: counts its wavefronts on the slot's
+          // counter when a slot is free for the tail
           uint32_t slot = 0;
           unsigned* sig = nullptr;
           if (c->tails->reserve(&slot)) {
             c->reserved[{key, d.kernel + 1}] = slot;
-            sig = counter_of(c, d.chain, d.kernel);
+            sig = c->slot_counters + slot;
           } else {
             c->st_tails_unfused++;
           }
@@ -659,8 +711,10 @@ void gate_main(Ctx* c) {
             const TaskKey tk{in.c, in.f, in.task};
             const std::vector<TailRec>& recs = c->inst_tails[tk];
             size_t& seen = c->inst_tails_done[tk];
-            while (seen < need->second && c->tails->finished(recs[seen].slot, recs[seen].pub))
+            while (seen < need->second && c->tails->finished(recs[seen].slot, recs[seen].pub)) {
+              if (recs[seen].graph) recs[seen].graph->busy--;
               ++seen;
+            }
             if (seen < need->second) break;
           }
         }
@@ -916,10 +970,11 @@ void ug_destroy(void* ctx) {
       for (hipStream_t s : lv) (void)hipStreamSynchronize(s);
     for (hipStream_t s : c->fifo_streams) (void)hipStreamSynchronize(s);
     if (c->capture_stream) (void)hipStreamSynchronize(c->capture_stream);
-    if (c->counters) (void)hipFree(c->counters);
+    if (c->slot_counters) (void)hipFree(c->slot_counters);
+    for (unsigned* p : c->counter_chunks) (void)hipFree(p);
     for (hipStream_t s : c->owned_streams) (void)hipStreamDestroy(s);
     for (hipEvent_t e : c->all_events) (void)hipEventDestroy(e);
-    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second.ge);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto& v : c->ws)
       for (void* p : v)
@@ -1238,19 +1293,12 @@ ug_status ug_start(void* ctx) {
   if (c->cfg.flags & UG_F_FUSE) {
     if (c->cfg.fuse_workers < 1 || c->cfg.fuse_workers > 1024 || c->cfg.fuse_idle_ns <= 0)
       return fail(c, UG_EINVAL, "fused tails need fuse_workers in 1..1024 and fuse_idle_ns > 0");
-    // one completion counter per kernel of every chain, kept for the
-    // context's life (captured graphs hold their addresses), zeroed at
-    // every start
+    // the completion counters, zeroed at every start
     hipError_t e = hipSuccess;
     if (!c->fuse_stream &&
         (e = hipStreamCreateWithFlags(&c->fuse_stream, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(c, e, "tail executor stream");
-    if ((e = alloc_counters(c)) != hipSuccess) return hip_fail(c, e, "completion counters");
-    size_t total = 0;
-    for (const auto& ch : c->policy.chains()) total += ch.kernels.size();
-    if ((e = hipMemset(c->counters, 0, std::max<size_t>(total, 1) * sizeof(unsigned))) !=
-        hipSuccess)
-      return hip_fail(c, e, "completion counters");
+    if ((e = zero_counters(c)) != hipSuccess) return hip_fail(c, e, "completion counters");
     c->tails.reset(new ug::TailQueue());
     // lease: a minute per launch, renewed by the next launch
     if ((e = c->tails->open(c->cfg.device, c->cfg.fuse_workers, c->cfg.fuse_idle_ns,
@@ -1643,8 +1691,6 @@ ug_status ug_tails_publish(void* queue, const ug_tail* t, uint64_t key, uint32_t
   it.C = t->cols;
   it.axis = t->axis;
   it.flags = (t->sm ? ug::kFuseSoftmax : 0u) | (t->rs ? ug::kFuseRowsum : 0u);
-  it.rows_per_tile = ug::fuse_rows_per_tile(it.C);
-  it.tiles = (it.R + it.rows_per_tile - 1) / it.rows_per_tile;
   if (!q->reserve(slot)) return UG_EAGAIN;
   *pub = q->publish(*slot, it, key);
   return UG_OK;
@@ -1731,11 +1777,6 @@ ug_status ug_graph_prepare(void* ctx, uint32_t chain, void* const* buffers, uint
   fr.chain = chain;
   fr.buffers.assign(buffers, buffers + n_buffers);
   if (n_dims) fr.dims.assign(dims, dims + n_dims);
-  if (c->cfg.flags & UG_F_FUSE) {
-    // the fused variant bakes in the counters' addresses: make them now
-    const hipError_t e = alloc_counters(c);
-    if (e != hipSuccess) return hip_fail(c, e, "completion counters");
-  }
   for (size_t j = 0; j < chs[chain].task_first.size(); ++j) {
     for (int fused = 0; fused < ((c->cfg.flags & UG_F_FUSE) ? 2 : 1); ++fused) {
       hipError_t err = hipSuccess;

@@ -33,7 +33,7 @@ TailQueue::~TailQueue() {
 hipError_t TailQueue::open(int device, uint32_t workers, int64_t idle_ns, int64_t lease_ns,
                            uint32_t log_cap, hipStream_t stream) {
   if (h_) return hipErrorInvalidValue;
-  if (workers < 1 || workers > 1024 || idle_ns <= 0 || lease_ns <= 0 || log_cap > kFuseLogCap)
+  if (workers < 1 || workers > kFuseMaxWorkers || idle_ns <= 0 || lease_ns <= 0 || log_cap > kFuseLogCap)
     return hipErrorInvalidValue;
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) return e;
@@ -78,9 +78,12 @@ void TailQueue::unreserve(uint32_t slot) { free_.push_back(slot); }
 uint64_t TailQueue::publish(uint32_t slot, const FuseItem& it, uint64_t key) {
   const uint64_t pub = ++next_pub_;
   h_->item[slot] = it;
+  h_->item[slot].rows_per_tile = fuse_rows_per_tile(it.R, it.C, workers_);
+  h_->item[slot].tiles = (it.R + h_->item[slot].rows_per_tile - 1) / h_->item[slot].rows_per_tile;
   store_release(&h_->key[slot], key);
   store_release(&h_->pub[slot], pub);
-  store_release(&h_->npub, pub);
+  store_release(&h_->ring[(pub - 1) % kFuseSlots], slot);
+  store_release(&h_->ctl[kCtlNpub], pub);
   busy_[slot] = 1;
   ++outstanding_;
   return pub;
@@ -95,7 +98,7 @@ void TailQueue::set_key(uint32_t slot, uint64_t key) {
 void TailQueue::commit_keys() {
   if (!keys_dirty_) return;
   keys_dirty_ = false;
-  store_release(&h_->kepoch, load_acquire(&h_->kepoch) + 1);
+  store_release(&h_->ctl[kCtlKepoch], load_acquire(&h_->ctl[kCtlKepoch]) + 1);
 }
 
 bool TailQueue::finished(uint32_t slot, uint64_t pub) {
@@ -107,7 +110,7 @@ bool TailQueue::finished(uint32_t slot, uint64_t pub) {
   return true;
 }
 
-void TailQueue::set_pause(bool on) { store_release(&h_->pause, uint64_t(on ? 1 : 0)); }
+void TailQueue::set_pause(bool on) { store_release(&h_->ctl[kCtlPause], uint64_t(on ? 1 : 0)); }
 
 hipError_t TailQueue::kick() {
   if (outstanding_ == 0) return hipSuccess;
@@ -116,7 +119,11 @@ hipError_t TailQueue::kick() {
     if (q == hipErrorNotReady) return hipSuccess;   // still running
     if (q != hipSuccess) return q;
   }
-  hipError_t e = fuse_executor_launch(h_, d_, workers_, idle_ns_, lease_ns_, log_cap_, s_);
+  // launches are numbered from 1, modulo 2^32 but never 0 (a worker tells
+  // this launch's commands from the previous one's)
+  uint32_t launch = static_cast<uint32_t>(launches_ + 1);
+  if (launch == 0) launch = 1;
+  hipError_t e = fuse_executor_launch(h_, d_, workers_, launch, idle_ns_, lease_ns_, log_cap_, s_);
   if (e != hipSuccess) return e;
   if ((e = hipEventRecord(ev_, s_)) != hipSuccess) return e;
   launched_ = true;
@@ -127,12 +134,9 @@ hipError_t TailQueue::kick() {
 
 hipError_t TailQueue::halt() {
   if (!h_) return hipSuccess;
-  store_release(&h_->stop, uint64_t(1));
+  store_release(&h_->ctl[kCtlStop], uint64_t(1));
   hipError_t e = hipStreamSynchronize(s_);
-  store_release(&h_->stop, uint64_t(0));
-  // workers of a later launch must not see the old stop in the mirror
-  if (e == hipSuccess) e = hipMemsetAsync(&d_->ctl, 0, sizeof(d_->ctl), s_);
-  if (e == hipSuccess) e = hipStreamSynchronize(s_);
+  store_release(&h_->ctl[kCtlStop], uint64_t(0));
   launched_ = false;
   return e;
 }
@@ -166,8 +170,6 @@ bool tail_item(const std::vector<ug_kernel>& ks, int32_t first, int32_t end,
       it->flags |= kFuseRowsum;
     }
   }
-  it->rows_per_tile = fuse_rows_per_tile(it->C);
-  it->tiles = (it->R + it->rows_per_tile - 1) / it->rows_per_tile;
   uint64_t align = it->x | it->y | it->sm;
   if (it->axis == 0) align |= it->bias;
   return (align & 15) == 0;
@@ -208,7 +210,7 @@ void tail_runs(const std::vector<ug_kernel>& ks, int32_t lo, int32_t hi,
       ++end;
     }
     bool ok = C % 4 == 0 && !(has_sm && C > kFuseMaxSoftmaxRow) && R < (int64_t(1) << 31) &&
-              C < (int64_t(1) << 31);
+              C < (int64_t(1) << 31) && 4 * R * C <= kFuseMaxTailBytes;
     for (int32_t g = i - 1; g < end && ok; ++g) ok = ks[g].frame_dim == 0;
     if (ok) {
       std::set<int32_t> reads, writes;

@@ -13,6 +13,10 @@
 
 namespace ug {
 
+// The gate fuses short kernels only: a tail's bias+ReLU input is at most
+// this many bytes (larger tails launch as usual, at full-device bandwidth).
+constexpr int64_t kFuseMaxTailBytes = int64_t(1) << 20;
+
 class TailQueue {
  public:
   TailQueue() = default;
@@ -33,8 +37,9 @@ class TailQueue {
   void unreserve(uint32_t slot);
   // Publication number the next publish will give.
   uint64_t next_pub() const { return next_pub_ + 1; }
-  // Publishes an item into a reserved slot with its first key; returns its
-  // publication number.
+  // Publishes an item into a reserved slot with its first key (the item's
+  // rows per tile and tile count are set here, for this queue's workers);
+  // returns its publication number.
   uint64_t publish(uint32_t slot, const FuseItem& it, uint64_t key);
   // Rewrites a published item's key (takes effect at the next commit_keys).
   void set_key(uint32_t slot, uint64_t key);
@@ -80,9 +85,10 @@ bool tail_item(const std::vector<ug_kernel>& ks, int32_t first, int32_t end,
 // first) gets -2.  The rule: a bias+ReLU right after a contraction (FP32 or
 // BF16 GEMM or 3x3 convolution) whose output it reads, with at most one
 // row softmax and one row sum of its output after it (same rows and row
-// length), row length a multiple of 4 (at most 4096 with a softmax), no
-// per-frame sizes, and no later kernel of the task writing a buffer the
-// tail reads or writes or reading one it writes.
+// length), row length a multiple of 4 (at most 4096 with a softmax), at
+// most kFuseMaxTailBytes of input, no per-frame sizes, and no later kernel
+// of the task writing a buffer the tail reads or writes or reading one it
+// writes.
 void tail_runs(const std::vector<ug_kernel>& ks, int32_t lo, int32_t hi,
                std::vector<int32_t>* mark);
 

@@ -1,32 +1,41 @@
 // Tail executor: a long-lived kernel that runs fused tails (bias+ReLU of a
 // contraction's output, then optionally the row softmax and the row sum of
-// that result) taken from a queue in device memory, most urgent first.
+// that result) taken from a queue, most urgent first.
 //
 // Memory shared by the host gate and the executor:
 //   FuseHost  pinned, coherent host memory.  The gate writes an item's
-//             descriptor and key, then its publication number (pub) and
-//             the publication count (npub, last); it rewrites keys whenever
-//             its urgency order changes, then bumps kepoch.  The executor
-//             polls only npub and kepoch while nothing changes.  The
-//             executor writes `done` (the publication number of the slot's
-//             finished item) and the service log.
-//   FuseDev   device memory (zeroed before the first launch, then kept
-//             across launches).  Workgroup 0 of the executor (the
-//             dispatcher) copies new descriptors from the host, watches the
-//             producers' completion counters and mirrors keys and control
-//             words; the other workgroups (workers) claim tiles of ready
-//             items with device-scope atomics and never read host memory
-//             but to report completion.
+//             descriptor and key into a free slot, the slot's number into
+//             the publication ring, then the publication count (npub,
+//             last); it rewrites keys whenever its urgency order changes,
+//             then bumps kepoch.  While nothing changes the executor reads
+//             only the four control words.  The executor writes `done` (the
+//             publication number of the slot's finished item) and the
+//             service log.
+//   FuseDev   device memory, zeroed once and kept across launches.
+//
+// Workgroup 0, wave 0 of the executor is the dispatcher; it alone owns the
+// slots' state (FuseSlot, held in its LDS while it runs).  It takes in new publications, marks an item
+// ready once its producer's counter is complete, and hands tiles of ready
+// items, smallest key first, to idle workers through one mailbox each.
+// A worker (workgroups 1..) waits on its mailbox, runs the tile with its
+// four waves and acknowledges it; the dispatcher counts finished tiles and
+// reports a finished item to the host.  Polling loops use relaxed loads
+// only: one acquire per command taken and one release per tile finished
+// (and per batch of commands or reports), so that the caches the other
+// kernels share are not flushed on every poll.
 //
 // A producer (a contraction launched with a completion counter) adds one to
 // the counter per wavefront once that wavefront's results are stored; the
 // item is ready when the counter reaches the producer's wavefront count, and
 // the dispatcher then resets it to zero for the producer's next launch.
 //
-// Every wait of the executor is bounded: it leaves when the host sets
-// `stop`, when nothing has progressed for `idle` nanoseconds, or at the end
-// of its lease; claimed tiles are always finished first.  The host launches
-// it again while items are pending and it is not running.
+// Every wait of the executor is bounded: the dispatcher leaves when the host
+// sets `stop`, when nothing has progressed for `idle` nanoseconds, or at the
+// end of its lease, after the tiles it handed out are finished (at most
+// kFuseDrainNs more); it then sends every worker a command to leave, and a
+// worker that hears nothing leaves after the lease and twice the drain
+// bound.  The host launches the executor again while items are pending and
+// it is not running.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,9 +44,11 @@
 
 namespace ug {
 
-constexpr uint32_t kFuseSlots = 512;      // items queued at once (8 per lane of a wave)
+constexpr uint32_t kFuseSlots = 512;      // items queued at once (8 per dispatcher lane)
+constexpr uint32_t kFuseMaxWorkers = 1024;
 constexpr uint32_t kFuseLogCap = 8192;    // service-log entries (tests)
-constexpr uint32_t kFuseMaxSoftmaxRow = 4096;   // softmax rows held in registers
+constexpr uint32_t kFuseMaxSoftmaxRow = 4096;   // longest row with a fused softmax
+constexpr int64_t kFuseDrainNs = 2000000000;    // tiles handed out finish within this
 
 // Stages of an item (FuseItem::flags).
 constexpr uint32_t kFuseSoftmax = 1u;
@@ -57,41 +68,64 @@ struct FuseItem {
 };
 static_assert(sizeof(FuseItem) == 80, "descriptor layout");
 
+// FuseHost::ctl words.
+constexpr int kCtlStop = 0, kCtlPause = 1, kCtlNpub = 2, kCtlKepoch = 3;
+
 struct FuseHost {
-  uint64_t stop;
-  uint64_t pause;
-  uint64_t npub;                   // host: publications so far (after each pub)
-  uint64_t kepoch;                 // host: key rewrites so far (after the keys)
-  uint64_t pub[kFuseSlots];
-  uint64_t key[kFuseSlots];
-  uint64_t done[kFuseSlots];
-  FuseItem item[kFuseSlots];
+  uint64_t ctl[4];                 // host: stop, pause, npub (after each publication),
+                                   // kepoch (after each batch of key rewrites)
+  uint64_t pub[kFuseSlots];        // host: publication number of the slot's item
+  uint64_t key[kFuseSlots];        // host: the slot's key (smaller is served first)
+  uint64_t done[kFuseSlots];       // device: publication number of the slot's finished item
+  uint32_t ring[kFuseSlots];       // host: slot of publication p at ring[(p - 1) % kFuseSlots]
+  FuseItem item[kFuseSlots];       // host: the slot's descriptor
   uint64_t launches;               // host: executor launches so far
-  uint64_t log[kFuseLogCap];       // device: (pub << 24) | tile, per served tile
+  uint64_t log[kFuseLogCap];       // device: (pub << 24) | tile, per tile handed out
 };
 
+// The dispatcher's record of a slot.
+struct FuseSlot {
+  uint64_t key, pub, sig;
+  uint32_t state;                  // 0 free or finished, 1 waiting for the producer, 2 ready
+  uint32_t next;                   // next tile to hand out
+  uint32_t tiles, fin;             // tiles in all, tiles finished
+  uint32_t sig_expected, pad;
+};
+static_assert(sizeof(FuseSlot) == 48, "slot layout");
+
+// A command from the dispatcher to one worker.
+struct FuseMail {
+  FuseItem it;
+  uint64_t cmd;                    // (launch << 32) | sequence number
+  uint32_t slot, tile;
+  uint32_t op;                     // 0 run the tile, 1 leave
+  uint32_t pad[7];
+};
+static_assert(sizeof(FuseMail) == 128, "mailbox layout");
+
 struct FuseDev {
-  uint64_t seen[kFuseSlots];       // publication number copied
-  uint64_t key[kFuseSlots];
-  uint64_t next[kFuseSlots];       // (generation << 32) | next tile to claim
-  uint32_t state[kFuseSlots];      // 0 idle/finished, 1 waiting for producer, 2 ready
-  uint32_t fin[kFuseSlots];        // tiles finished
-  uint32_t gen[kFuseSlots];
-  uint32_t ctl;                    // bit 0 stop, bit 1 pause (mirrored by the dispatcher)
+  FuseSlot slot[kFuseSlots];
+  FuseItem item[kFuseSlots];       // descriptors taken in from the host
+  uint64_t ack[kFuseMaxWorkers];   // worker: last command finished, (launch << 32) | seq
+  uint64_t wstate[kFuseMaxWorkers];// dispatcher: (last sequence number sent << 32) |
+                                   // slot of the tile in progress (or ~0u)
+  FuseMail mail[kFuseMaxWorkers];
+  uint64_t npub_seen;              // publications taken in
   uint32_t log_n;                  // service-log entries written
-  uint64_t progress;               // device clock of the last progress
-  uint64_t tiles_run;              // tiles served since the memory was zeroed
-  FuseItem item[kFuseSlots];
+  uint32_t pad;
 };
 
 // Launches the executor: one dispatcher workgroup and `workers` worker
-// workgroups of 256 threads.  idle_ns and lease_ns bound its life (device
-// clock, 100 MHz); log_cap > 0 records the first log_cap served tiles.
-hipError_t fuse_executor_launch(FuseHost* h, FuseDev* d, uint32_t workers, int64_t idle_ns,
-                                int64_t lease_ns, uint32_t log_cap, hipStream_t s);
+// workgroups of 256 threads.  `launch` numbers the launch (from 1, distinct
+// from the previous launch's); idle_ns and lease_ns bound its life (device
+// clock, 100 MHz); log_cap > 0 records the first log_cap tiles handed out.
+hipError_t fuse_executor_launch(FuseHost* h, FuseDev* d, uint32_t workers, uint32_t launch,
+                                int64_t idle_ns, int64_t lease_ns, uint32_t log_cap,
+                                hipStream_t s);
 
-// Rows per tile of an item with rows of C floats (a multiple of 4, about
-// 128 KiB of input per tile, at least 4 rows).
-uint32_t fuse_rows_per_tile(uint32_t C);
+// Rows per tile of an item of R rows of C floats served by `workers`
+// workers: about R / workers, kept between 16 KiB and 128 KiB of input
+// (at least one row), rounded up to a multiple of 4 (one row per wave).
+uint32_t fuse_rows_per_tile(uint32_t R, uint32_t C, uint32_t workers);
 
 }  // namespace ug

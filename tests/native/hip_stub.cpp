@@ -164,7 +164,7 @@ hipError_t stream_queue_classes(const std::vector<hipStream_t>& s, std::vector<i
   for (size_t i = 0; i < s.size(); ++i) (*cls)[i] = static_cast<int>(i % 4);
   return hipSuccess;
 }
-uint32_t fuse_rows_per_tile(uint32_t) { return 4; }
-hipError_t fuse_executor_launch(FuseHost*, FuseDev*, uint32_t, int64_t, int64_t, uint32_t,
-                                hipStream_t) { return hipSuccess; }
+uint32_t fuse_rows_per_tile(uint32_t, uint32_t, uint32_t) { return 4; }
+hipError_t fuse_executor_launch(FuseHost*, FuseDev*, uint32_t, uint32_t, int64_t, int64_t,
+                                uint32_t, hipStream_t) { return hipSuccess; }
 }  // namespace ug

@@ -365,7 +365,7 @@ def _random_task(rng):
     for _ in range(int(rng.integers(1, 6))):
         out = int(rng.integers(0, nslot))
         a, b = (int(v) for v in rng.integers(0, nslot, 2))
-        R = int(rng.choice([8, 32]))
+        R = int(rng.choice([8, 32, 40]))   # 40 x 8192 floats: over the size limit
         C = int(rng.choice([32, 64, 6, 4100, 8192]))
         kind = rng.choice(["gemm", "conv3x3", "gemm_bf16", "conv3x3_bf16", "softmax"])
         if kind == "gemm":
