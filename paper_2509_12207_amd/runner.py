@@ -7,6 +7,7 @@ inputs come in ``n_sets`` copies and frame f of a chain uses copy
 f % n_sets; device-resident chain state is one buffer per chain.
 """
 
+import os
 import time
 
 import numpy as np
@@ -94,7 +95,19 @@ class DeviceWorkload:
         return tot
 
 
+# the tile-variant table the autotuner measured for the FP32 GEMM and
+# convolution shapes of configuration 1 (three seeds) on gfx950
+TILE_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiles_gfx950.txt")
+
+
 def make_gate(wl, policy="urgency", device=0, **cfg):
+    """A gate with ``wl``'s chains registered; the package's tile table
+    unless ``tile_table`` is given (None: the launchers' rules)."""
+    if "tile_table" not in cfg and os.path.exists(TILE_TABLE):
+        cfg["tile_table"] = TILE_TABLE
+    if cfg.get("tile_table") is None:
+        cfg.pop("tile_table", None)
+        capi.tile_clear()   # the table is process-wide
     g = capi.Gate(policy=policy, device=device, **cfg)
     for ch in wl.chains:
         g.register_chain(ch.period_ns, ch.deadline_ns, ch.tasks, len(ch.buffers))
