@@ -511,7 +511,7 @@ def run_policy(g, dw, arrivals, torch, be=None):
     t1 = time.perf_counter()
     g.stop()
     m = g.metrics()
-    st = g.stats()
+    st = dict(g.stats(), fuse=g.fuse_stats())
     return comps, m, st, t1 - t0
 
 
@@ -682,7 +682,22 @@ def summarise(m, st, wall, n_frames):
         "executor_launches": int(st.get("executor_launches", 0)),
         "collisions": int(st.get("collisions", 0)),
         "collision_hist_1_to_8plus": list(st.get("collision_hist", [])),
-    }
+    } | executor_summary(st.get("fuse"))
+
+
+def executor_summary(fs):
+    """The tail executor's phases over the run (ug_fuse_stats): dispatcher
+    rounds and their mean duration, items finished with their mean time
+    waiting for the producer, queued while ready, and being served, and the
+    tiles handed out; empty without fused tails.  Device clock: 10 ns."""
+    if not fs or not fs.get("items"):
+        return {}
+    n, r = fs["items"], max(1, fs["rounds"])
+    return {"executor": {"rounds": fs["rounds"], "round_us": round(fs["round_ticks"] / r / 100, 3),
+                         "items": n, "wait_producer_us": round(fs["wait_ticks"] / n / 100, 2),
+                         "queued_us": round(fs["queue_ticks"] / n / 100, 2),
+                         "served_us": round(fs["serve_ticks"] / n / 100, 2),
+                         "tiles": fs["tiles"]}}
 
 
 # ----------------------------------------------------------------------------

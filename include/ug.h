@@ -744,6 +744,17 @@ int32_t ug_tails_finished(void* queue, uint32_t slot, uint64_t pub);
 /* Copies up to cap service-log entries (in the order the tiles were handed
  * to workers); returns the count. */
 int32_t ug_tails_log(void* queue, uint64_t* out, uint32_t cap);
+/* The executor's statistics as of its last exit (a running executor's
+ * current launch is not counted yet), first n of: dispatcher rounds, their
+ * total duration, items finished, and over those items the summed time from
+ * being taken in to ready (waiting for the producer), from ready to the
+ * first tile handed out, and from then to finished, tiles handed out (times
+ * in device clock ticks of 10 ns).  Errors: UG_EINVAL, UG_EDEVICE. */
+ug_status ug_tails_stats(void* queue, uint64_t* out, uint32_t n);
+/* The same statistics for a gate's executor over its last run (from
+ * ug_start to ug_stop; read at ug_stop).  Not in ug_stats, whose layout is
+ * part of the ABI.  Errors: UG_EINVAL. */
+ug_status ug_fuse_stats(void* ctx, uint64_t* out, uint32_t n);
 /* Stops the executor, waits for it, frees everything. */
 ug_status ug_tails_close(void* queue);
 

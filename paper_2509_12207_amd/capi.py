@@ -61,7 +61,12 @@ EXPORTED = [
     "ug_tails_finished", "ug_tails_log", "ug_tails_close", "ug_kernel_launch_signal",
     "ug_chain_tails", "ug_launch_cost", "ug_tile_variants", "ug_tile_set", "ug_tile_clear",
     "ug_tile_get", "ug_tile_load", "ug_kernel_launch_variant", "ug_graph_prepare",
+    "ug_tails_stats", "ug_fuse_stats",
 ]
+
+# the executor's statistics (ug_tails_stats / ug_fuse_stats), in order
+FUSE_STATS = ("rounds", "round_ticks", "items", "wait_ticks", "queue_ticks", "serve_ticks",
+              "tiles")
 
 
 class Kernel(C.Structure):
@@ -209,6 +214,8 @@ def lib():
         L.ug_tails_kick.argtypes = [vp]
         L.ug_tails_finished.argtypes = [vp, C.c_uint32, C.c_uint64]
         L.ug_tails_log.argtypes = [vp, C.POINTER(C.c_uint64), C.c_uint32]
+        L.ug_tails_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.c_uint32]
+        L.ug_fuse_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.c_uint32]
         L.ug_tails_close.argtypes = [vp]
         L.ug_kernel_launch_signal.argtypes = [C.POINTER(Kernel), C.POINTER(vp), C.c_uint32, vp,
                                               C.POINTER(C.c_uint32), vp]
@@ -238,7 +245,8 @@ def lib():
                      "ug_tails_log", "ug_tails_close", "ug_kernel_launch_signal",
                      "ug_chain_tails", "ug_launch_cost", "ug_tile_variants", "ug_tile_set",
                      "ug_tile_clear", "ug_tile_get", "ug_tile_load",
-                     "ug_kernel_launch_variant", "ug_graph_prepare"):
+                     "ug_kernel_launch_variant", "ug_graph_prepare", "ug_tails_stats",
+                     "ug_fuse_stats"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -449,6 +457,13 @@ class TailQueue:
             raise UgError(n, "ug_tails_log")
         return [int(out[i]) for i in range(n)]
 
+    def stats(self):
+        out = (C.c_uint64 * len(FUSE_STATS))()
+        st = lib().ug_tails_stats(self.h, out, len(FUSE_STATS))
+        if st != OK:
+            raise UgError(st, "ug_tails_stats")
+        return dict(zip(FUSE_STATS, (int(v) for v in out)))
+
     def close(self):
         if self.h:
             st = lib().ug_tails_close(self.h)
@@ -656,6 +671,11 @@ class Gate:
 
     def drain(self, timeout_s=60.0):
         self._check(lib().ug_drain(self.h, int(timeout_s * 1e9)), "ug_drain")
+
+    def fuse_stats(self):
+        out = (C.c_uint64 * len(FUSE_STATS))()
+        self._check(lib().ug_fuse_stats(self.h, out, len(FUSE_STATS)), "ug_fuse_stats")
+        return dict(zip(FUSE_STATS, (int(v) for v in out)))
 
     def stats(self):
         s = Stats()

@@ -133,6 +133,7 @@ struct Ctx {
   std::vector<ug::Key> last_order;   // the ranking the queue's keys follow
   std::atomic<uint64_t> st_tails{0}, st_tails_unfused{0};
   uint64_t executor_launches = 0;    // of the last run (counted at ug_stop)
+  uint64_t fuse_stats[ug::kStatCount] = {};   // the executor's, of the last run
 
   std::mutex mu;  // inbox, outbox, counters, next_frame
   std::condition_variable cv_done;
@@ -1288,6 +1289,8 @@ ug_status ug_start(void* ctx) {
   c->inst_tails_done.clear();
   c->reserved.clear();
   c->covered_to.clear();
+  c->executor_launches = 0;
+  for (uint64_t& v : c->fuse_stats) v = 0;
   c->ev_tails.clear();
   c->last_order.clear();
   if (c->cfg.flags & UG_F_FUSE) {
@@ -1424,7 +1427,12 @@ ug_status ug_stop(void* ctx) {
   if (c->has_device) {
     (void)hipSetDevice(c->cfg.device);
     // the executor first: a stream on its hardware queue waits behind it
-    if (c->tails) c->executor_launches += c->tails->launches();
+    if (c->tails) {
+      c->executor_launches += c->tails->launches();
+      uint64_t st[ug::kStatCount] = {};
+      if (c->tails->halt() == hipSuccess && c->tails->stats(st) == hipSuccess)
+        for (int k = 0; k < ug::kStatCount; ++k) c->fuse_stats[k] += st[k];
+    }
     c->tails.reset();
     for (auto& lv : c->level_streams)
       for (hipStream_t s : lv) (void)hipStreamSynchronize(s);
@@ -1721,6 +1729,23 @@ int32_t ug_tails_finished(void* queue, uint32_t slot, uint64_t pub) {
   auto* q = static_cast<ug::TailQueue*>(queue);
   if (!q || slot >= ug::kFuseSlots) return UG_EINVAL;
   return q->finished(slot, pub) ? 1 : 0;
+}
+
+ug_status ug_tails_stats(void* queue, uint64_t* out, uint32_t n) {
+  auto* q = static_cast<ug::TailQueue*>(queue);
+  if (!q || (!out && n)) return UG_EINVAL;
+  uint64_t st[ug::kStatCount] = {};
+  if (q->stats(st) != hipSuccess) return UG_EDEVICE;
+  for (uint32_t k = 0; k < n && k < static_cast<uint32_t>(ug::kStatCount); ++k) out[k] = st[k];
+  return UG_OK;
+}
+
+ug_status ug_fuse_stats(void* ctx, uint64_t* out, uint32_t n) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c || (!out && n)) return UG_EINVAL;
+  for (uint32_t k = 0; k < n && k < static_cast<uint32_t>(ug::kStatCount); ++k)
+    out[k] = c->fuse_stats[k];
+  return UG_OK;
 }
 
 int32_t ug_tails_log(void* queue, uint64_t* out, uint32_t cap) {

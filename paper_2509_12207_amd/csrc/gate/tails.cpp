@@ -151,6 +151,11 @@ uint32_t TailQueue::read_log(uint64_t* out, uint32_t cap) const {
   return n;
 }
 
+hipError_t TailQueue::stats(uint64_t* out) const {
+  if (!d_) return hipErrorInvalidValue;
+  return hipMemcpy(out, d_->stats, sizeof(d_->stats), hipMemcpyDeviceToHost);
+}
+
 bool tail_item(const std::vector<ug_kernel>& ks, int32_t first, int32_t end,
                void* const* buffers, FuseItem* it) {
   const ug_kernel& k = ks[first];

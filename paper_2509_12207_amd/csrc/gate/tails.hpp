@@ -56,6 +56,8 @@ class TailQueue {
   uint64_t launches() const { return launches_; }
   // Service log entries (pub << 24 | tile) written so far, up to cap.
   uint32_t read_log(uint64_t* out, uint32_t cap) const;
+  // The executor's statistics (FuseStat), as of its last exit.
+  hipError_t stats(uint64_t* out) const;
 
  private:
   FuseHost* h_ = nullptr;

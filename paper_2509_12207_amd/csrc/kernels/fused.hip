@@ -26,7 +26,7 @@ constexpr uint32_t kNoSlot = ~0u;
 constexpr int kMailWords = 13;               // FuseItem, cmd, (slot, tile), op
 constexpr uint64_t kTicksPerNs10 = 10;       // device clock: 100 MHz
 constexpr uint32_t kBiasLds = 1024;          // float4 of per-column bias staged in LDS
-constexpr uint32_t kLdsBytes = 24576;        // the executor's LDS (24 KiB)
+constexpr uint32_t kLdsBytes = 24576;        // the executor's LDS (24 KiB: six workgroups a CU)
 
 // Global-memory pointers (address space 1): the items' pointers arrive as
 // integers, and without this the compiler would use flat accesses.
@@ -129,76 +129,49 @@ __device__ void dispatcher(FuseHost* __restrict__ H, FuseDev* __restrict__ D, ui
     L.fin[s] = ld(&sl->fin);
     L.expected[s] = ld(&sl->sig_expected);
   }
+  // statistics of this launch (wave-uniform): rounds, their ticks, tiles;
+  // finished items add their phases to FuseDev::stats when reported
+  uint64_t st_rounds = 0, st_round_ticks = 0, st_tiles = 0;
   uint64_t npub_seen = ld(&D->npub_seen);
   uint32_t log_n = ld(&D->log_n);
   uint64_t kepoch_seen = ~0ull;   // keys are read again at the start
   uint64_t last = t0, t_leave = 0;
   bool leaving = false;
+  // slots finished but not yet reported (an item of no tiles, or a launch
+  // that left before reporting) are looked for in the next round
+  bool report = true;
   settle();
+  // control words of the first round; later rounds' are loaded at the end of
+  // the round before, so that the PCIe read overlaps the round's work
+  uint64_t cw = lane < 4 ? ld_sys(&H->ctl[lane]) : 0ull;
   for (;;) {
     const uint64_t now = now_ticks();
-    const uint64_t cw = lane < 4 ? ld_sys(&H->ctl[lane]) : 0ull;
-    const uint64_t stop = __shfl(cw, kCtlStop, 64), pause = __shfl(cw, kCtlPause, 64);
-    const uint64_t npub = __shfl(cw, kCtlNpub, 64), kepoch = __shfl(cw, kCtlKepoch, 64);
-    bool act = false, fin_any = false;
-    if (!leaving && (stop || now - t0 > lease)) {
-      leaving = true;
-      t_leave = now;
-    }
+    bool act = false;
 
-    // 1. new publications, in order, one per lane
-    if (npub != npub_seen) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // the host's stores before npub
-      for (uint64_t base = npub_seen; base < npub; base += 64) {
-        const uint64_t p = base + 1 + lane;
-        if (p <= npub) {
-          const uint32_t s = ld_sys(&H->ring[(p - 1) % kFuseSlots]) % kFuseSlots;
-          const uint64_t* src = reinterpret_cast<const uint64_t*>(&H->item[s]);
-          uint64_t* dst = reinterpret_cast<uint64_t*>(&D->item[s]);
-          uint64_t wv[sizeof(FuseItem) / 8];
-#pragma unroll
-          for (int i = 0; i < int(sizeof(FuseItem) / 8); ++i) wv[i] = ld_sys(src + i);
-          const uint64_t key = ld_sys(&H->key[s]);
-#pragma unroll
-          for (int i = 0; i < int(sizeof(FuseItem) / 8); ++i) st(dst + i, wv[i]);
-          const uint32_t tiles = uint32_t(wv[9]);
-          L.key[s] = key;
-          L.pub[s] = p;
-          L.sig[s] = wv[5];
-          L.expected[s] = uint32_t(wv[6]);
-          L.next[s] = 0u;
-          L.fin[s] = 0u;
-          L.tiles[s] = tiles;
-          L.state[s] = tiles == 0u ? 3u : (wv[5] ? 1u : 2u);
-          fin_any |= tiles == 0u;
-        }
-      }
-      npub_seen = npub;
-      act = true;
-      settle();
+    // 3. items waiting for their producer (every counter loaded at once),
+    // beside the first 64 workers' acknowledgements
+    uint64_t ws0 = 0, a0 = 0;
+    if (lane < workers) {
+      ws0 = ld(&D->wstate[lane]);   // (sequence << 32) | slot in progress
+      a0 = ld(&D->ack[lane]);
     }
-
-    // 2. keys rewritten by the host
-    if (kepoch != kepoch_seen) {
-      kepoch_seen = kepoch;
-#pragma unroll 2
+    {
+      unsigned cnt[kPer];
+#pragma unroll
       for (uint32_t i = 0; i < kPer; ++i) {
         const uint32_t s = lane + 64 * i;
-        if (L.state[s] != 0u) L.key[s] = ld_sys(&H->key[s]);
+        cnt[i] = L.state[s] == 1u ? ld(reinterpret_cast<UG_GLOBAL unsigned*>(L.sig[s])) : 0u;
       }
-    }
-
-    // 3. items waiting for their producer
-    {
       bool ready_any = false;
 #pragma unroll
       for (uint32_t i = 0; i < kPer; ++i) {
         const uint32_t s = lane + 64 * i;
-        if (L.state[s] != 1u) continue;
-        UG_GLOBAL unsigned* sig = reinterpret_cast<UG_GLOBAL unsigned*>(L.sig[s]);
-        if (ld(sig) >= L.expected[s]) {
-          __hip_atomic_store(sig, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // ready for the next launch
+        if (L.state[s] == 1u && cnt[i] >= L.expected[s]) {
+          // ready for the producer's next launch
+          __hip_atomic_store(reinterpret_cast<UG_GLOBAL unsigned*>(L.sig[s]), 0u,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           L.state[s] = 2u;
+          st(&D->slot[s].t_ready, uint32_t(now));
           ready_any = true;
         }
       }
@@ -207,13 +180,14 @@ __device__ void dispatcher(FuseHost* __restrict__ H, FuseDev* __restrict__ D, ui
 
     // 4. acknowledgements: finished tiles, idle workers
     uint32_t avail = 0;   // bit g: worker lane + 64 g is alive and idle
-    bool busy = false;
+    bool busy = false, fin_any = report;
+    report = false;
 #pragma unroll 2
     for (uint32_t g = 0; g < groups; ++g) {
       const uint32_t w = lane + 64 * g;
       if (w >= workers) break;
-      const uint64_t ws = ld(&D->wstate[w]);   // (sequence << 32) | slot in progress
-      const uint64_t a = ld(&D->ack[w]);
+      const uint64_t ws = g == 0 ? ws0 : ld(&D->wstate[w]);
+      const uint64_t a = g == 0 ? a0 : ld(&D->ack[w]);
       const uint32_t q = uint32_t(ws >> 32), sl = uint32_t(ws);
       if (a != (tag | q)) {
         busy |= sl != kNoSlot;
@@ -221,13 +195,14 @@ __device__ void dispatcher(FuseHost* __restrict__ H, FuseDev* __restrict__ D, ui
       }
       avail |= 1u << g;
       if (sl == kNoSlot) continue;
+      // the same lane reads wstate[w] next: program order keeps this store
+      // ahead of that load
       st(&D->wstate[w], (uint64_t(q) << 32) | kNoSlot);
       if (atomicAdd(&L.fin[sl], 1u) + 1u == L.tiles[sl]) {
         L.state[sl] = 3u;   // finished, to be reported
         fin_any = true;
       }
     }
-    settle();
     if (__ballot(fin_any)) {
       act = true;
       // the workers' results (released before their acknowledgements) ahead
@@ -239,7 +214,77 @@ __device__ void dispatcher(FuseHost* __restrict__ H, FuseDev* __restrict__ D, ui
         if (L.state[s] == 3u) {
           L.state[s] = 0u;
           st_sys(&H->done[s], L.pub[s]);
+          const uint32_t ts = ld(&D->slot[s].t_seen), tr = ld(&D->slot[s].t_ready),
+                         tf = ld(&D->slot[s].t_first);
+          const uint64_t ph[4] = {1, uint32_t(tr - ts), uint32_t(tf - tr),
+                                  uint32_t(uint32_t(now) - tf)};
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            __hip_atomic_fetch_add(&D->stats[kStatItems + k], ph[k], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
+      }
+    }
+
+    // the control words (read during the previous round)
+    const uint64_t stop = __shfl(cw, kCtlStop, 64), pause = __shfl(cw, kCtlPause, 64);
+    const uint64_t npub = __shfl(cw, kCtlNpub, 64), kepoch = __shfl(cw, kCtlKepoch, 64);
+    if (!leaving && (stop || now - t0 > lease)) {
+      leaving = true;
+      t_leave = now;
+    }
+
+    // 1. new publications, in order, one per lane
+    if (npub != npub_seen) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // the host's stores before npub
+      bool empty = false;
+      for (uint64_t base = npub_seen; base < npub; base += 64) {
+        const uint64_t p = base + 1 + lane;
+        if (p <= npub) {
+          const uint32_t s = ld_sys(&H->ring[(p - 1) % kFuseSlots]) % kFuseSlots;
+          const uint64_t* src = reinterpret_cast<const uint64_t*>(&H->item[s]);
+          uint64_t* dst = reinterpret_cast<uint64_t*>(&D->item[s]);
+          // the descriptor in two halves of five words (fewer registers)
+          uint64_t wv[5];
+#pragma unroll
+          for (int i = 0; i < 5; ++i) wv[i] = ld_sys(src + i);
+#pragma unroll
+          for (int i = 0; i < 5; ++i) st(dst + i, wv[i]);
+#pragma unroll
+          for (int i = 0; i < 5; ++i) wv[i] = ld_sys(src + 5 + i);
+          const uint64_t key = ld_sys(&H->key[s]);
+#pragma unroll
+          for (int i = 0; i < 5; ++i) st(dst + 5 + i, wv[i]);
+          const uint32_t tiles = uint32_t(wv[4]);   // words 5..9: sig, (expected, R), .., tiles
+          L.key[s] = key;
+          L.pub[s] = p;
+          L.sig[s] = wv[0];
+          L.expected[s] = uint32_t(wv[1]);
+          L.next[s] = 0u;
+          L.fin[s] = 0u;
+          L.tiles[s] = tiles;
+          L.state[s] = tiles == 0u ? 3u : (wv[0] ? 1u : 2u);
+          // the item's phase clock stays in device memory (read rarely)
+          st(&D->slot[s].t_seen, uint32_t(now));
+          st(&D->slot[s].t_ready, uint32_t(now));
+          st(&D->slot[s].t_first, uint32_t(now));
+          empty |= tiles == 0u;
+        }
+      }
+      report = __ballot(empty) != 0ull;
+      npub_seen = npub;
+      act = true;
+      // other lanes copy these descriptors into mailboxes below
+      settle();
+    }
+
+    // 2. keys rewritten by the host
+    if (kepoch != kepoch_seen) {
+      kepoch_seen = kepoch;
+#pragma unroll 2
+      for (uint32_t i = 0; i < kPer; ++i) {
+        const uint32_t s = lane + 64 * i;
+        if (L.state[s] != 0u) L.key[s] = ld_sys(&H->key[s]);
       }
     }
 
@@ -304,10 +349,12 @@ __device__ void dispatcher(FuseHost* __restrict__ H, FuseDev* __restrict__ D, ui
             __hip_atomic_store(&mb->cmd, tag | q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
           }
           if (lane == bs % 64) {
+            if (base == 0u) st(&D->slot[bs].t_first, uint32_t(now));
             L.next[bs] = base + take;
             mine_best = best();
           }
           log_n += take;
+          st_tiles += take;
           // the lowest `take` idle lanes are served
           for (uint32_t t = 0; t < take; ++t) mask &= mask - 1ull;
           if (mine) avail &= ~(1u << g);
@@ -315,8 +362,10 @@ __device__ void dispatcher(FuseHost* __restrict__ H, FuseDev* __restrict__ D, ui
           act = true;
         }
       }
-      settle();
     }
+
+    // the next round's control words, in flight while this round ends
+    cw = lane < 4 ? ld_sys(&H->ctl[lane]) : 0ull;
 
     // 6. progress, leaving
     const bool busy_any = __ballot(busy) != 0ull;
@@ -325,6 +374,8 @@ __device__ void dispatcher(FuseHost* __restrict__ H, FuseDev* __restrict__ D, ui
       leaving = true;
       t_leave = now;
     }
+    st_rounds++;
+    st_round_ticks += now_ticks() - now;
     if (leaving && (!busy_any || now - t_leave > drain)) break;
     if (__ballot(act) == 0ull) __builtin_amdgcn_s_sleep(4);
   }
@@ -347,6 +398,14 @@ __device__ void dispatcher(FuseHost* __restrict__ H, FuseDev* __restrict__ D, ui
     st(&sl->state, L.state[s]);
     st(&sl->fin, L.fin[s]);
     st(&sl->sig_expected, L.expected[s]);
+  }
+  if (lane == 0) {
+    __hip_atomic_fetch_add(&D->stats[kStatRounds], st_rounds, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&D->stats[kStatRoundTicks], st_round_ticks, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&D->stats[kStatTiles], st_tiles, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
   }
   if (lane == 0) {
     st(&D->npub_seen, npub_seen);
@@ -602,7 +661,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void t
     uint64_t idle, uint64_t lease, uint32_t log_cap) {
   // the dispatcher's slot staging, or a worker's bias
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
-  static_assert(kLdsBytes >= 44 * kFuseSlots && kLdsBytes >= 16 * kBiasLds, "LDS use fits");
+  static_assert(kLdsBytes >= sizeof(SlotsLds) && kLdsBytes >= 16 * kBiasLds, "LDS use fits");
   const uint64_t t0 = now_ticks();
   if (blockIdx.x == 0) {
     if (threadIdx.x < 64) dispatcher(H, D, workers, launch, t0, idle, lease, log_cap, lds);

@@ -89,9 +89,25 @@ struct FuseSlot {
   uint32_t state;                  // 0 free or finished, 1 waiting for the producer, 2 ready
   uint32_t next;                   // next tile to hand out
   uint32_t tiles, fin;             // tiles in all, tiles finished
-  uint32_t sig_expected, pad;
+  uint32_t sig_expected;
+  uint32_t t_seen, t_ready, t_first;   // device clock (low 32 bits): taken in, ready,
+                                       // first tile handed out
+  uint32_t pad[2];
 };
-static_assert(sizeof(FuseSlot) == 48, "slot layout");
+static_assert(sizeof(FuseSlot) == 64, "slot layout");
+
+// FuseDev::stats, accumulated over the executor's launches (device clock
+// ticks of 10 ns).
+enum FuseStat {
+  kStatRounds = 0,     // dispatcher rounds
+  kStatRoundTicks,     // their total duration
+  kStatItems,          // items finished
+  kStatWaitTicks,      // taken in -> ready (waiting for the producer), summed
+  kStatQueueTicks,     // ready -> first tile handed out, summed
+  kStatServeTicks,     // first tile handed out -> finished, summed
+  kStatTiles,          // tiles handed out
+  kStatCount = 8
+};
 
 // A command from the dispatcher to one worker.
 struct FuseMail {
@@ -113,6 +129,7 @@ struct FuseDev {
   uint64_t npub_seen;              // publications taken in
   uint32_t log_n;                  // service-log entries written
   uint32_t pad;
+  uint64_t stats[kStatCount];
 };
 
 // Launches the executor: one dispatcher workgroup and `workers` worker

@@ -18,6 +18,15 @@ kernel of the roofline leg, FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of
 its timed launches, each scaled to bytes by what the same counter reads for
 the leg's 1 GiB device-to-device copy, next to the kernel's algorithmic bytes
 and the hash of its source file (a changed source invalidates the entry).
+
+    python -m paper_2509_12207_amd.profsum --sq <pass dir> [<pass dir> ...] > table.md
+
+tabulates SQ / GRBM counters of the roofline leg's kernels (mean per
+dispatch over each kernel's last 5 dispatches, from every pass directory)
+with two derived columns: MFMA busy, SQ_VALU_MFMA_BUSY_CYCLES over the
+SIMD-cycles of the dispatch (1024 SIMDs; GRBM_GUI_ACTIVE summed over the
+eight XCDs, so / 8 gives the dispatch's cycles), and the waves' waiting
+share, SQ_WAIT_ANY / SQ_WAVE_CYCLES.
 """
 
 import argparse
@@ -106,9 +115,51 @@ def traffic(fetch_dir, write_dir, roof_json, root):
     return out
 
 
+SQ_KERNELS = [("voxel bin", r"voxel_bin"), ("voxel tile_reduce", r"voxel_tile_reduce"),
+              ("FP32 GEMM 4096^3", r"gemm_f32_kernel<2, 2, 2, 2, 1, true>"),
+              ("FP32 conv C256 256^2", r"conv3x3_f32_kernel<2, 2, 2, 2, 1, 8, 16>"),
+              ("BF16 GEMM 4096^3", r"gemm_ring<1, false>"),
+              ("BF16 conv C256 256^2", r"gemm_ring<1, true>"),
+              ("FP8 GEMM 8192^3", r"gemm_ring<0, false>"),
+              ("bias+ReLU 16384^2", r"bias_relu_vec<0")]
+
+
+def sq_table(dirs, last=5):
+    by = {}
+    for d in dirs:
+        rows = _rows(d, "*counter_collection.csv")
+        for label, rx in SQ_KERNELS:
+            pat = re.compile(rx)
+            disp = {}
+            for r in rows:
+                if pat.search(r.get("Kernel_Name", "")):
+                    disp.setdefault(int(r["Dispatch_Id"]), {}).setdefault(r["Counter_Name"], 0.0)
+                    disp[int(r["Dispatch_Id"])][r["Counter_Name"]] += float(r["Counter_Value"])
+            tail = [disp[k] for k in sorted(disp)][-last:]
+            for d_ in tail:
+                for n, v in d_.items():
+                    by.setdefault(label, {}).setdefault(n, []).append(v)
+    names = sorted({n for v in by.values() for n in v})
+    out = ["| kernel | MFMA busy | waves waiting | " + " | ".join(names) + " |",
+           "|---|---|---|" + "---|" * len(names)]
+    for label, _ in SQ_KERNELS:
+        if label not in by:
+            continue
+        m = {n: sum(v) / len(v) for n, v in by[label].items()}
+        cyc = m.get("GRBM_GUI_ACTIVE", 0) / 8
+        busy = m.get("SQ_VALU_MFMA_BUSY_CYCLES", 0) / (1024 * cyc) if cyc else float("nan")
+        wait = m.get("SQ_WAIT_ANY", 0) / m["SQ_WAVE_CYCLES"] if m.get("SQ_WAVE_CYCLES") else float("nan")
+        out.append(f"| {label} | {busy:.2f} | {wait:.2f} | " +
+                   " | ".join(f"{m[n]:.4g}" if n in m else "" for n in names) + " |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     if argv is None:
         argv = sys.argv[1:]
+    if argv and argv[0] == "--sq":
+        print(sq_table(argv[1:]))
+        return 0
     if argv and argv[0] == "--traffic":
         import json
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))

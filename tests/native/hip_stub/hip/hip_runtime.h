@@ -32,7 +32,7 @@ enum { hipEventDisableTiming = 2 };
 enum { hipHostMallocMapped = 2, hipHostMallocCoherent = 0x40000000 };
 enum hipStreamCaptureMode { hipStreamCaptureModeRelaxed = 2 };
 enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount = 1 };
-enum hipMemcpyKind { hipMemcpyHostToDevice = 1 };
+enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 };
 
 hipError_t hipSetDevice(int);
 hipError_t hipGetDeviceCount(int*);
@@ -49,6 +49,7 @@ hipError_t hipHostFree(void*);
 hipError_t hipMemset(void*, int, size_t);
 hipError_t hipMemsetAsync(void*, int, size_t, hipStream_t);
 hipError_t hipMemcpyAsync(void*, const void*, size_t, hipMemcpyKind, hipStream_t);
+hipError_t hipMemcpy(void*, const void*, size_t, hipMemcpyKind);
 hipError_t hipStreamCreateWithFlags(hipStream_t*, unsigned);
 hipError_t hipStreamDestroy(hipStream_t);
 hipError_t hipStreamSynchronize(hipStream_t);
