@@ -107,6 +107,12 @@ def test_tail_executor_many_items_and_slot_reuse():
         wait_finished(q, items)
         for x, b, dy, drs, _, _ in xs:
             check_tail(x, b, 0, dy.cpu().numpy(), None, drs.cpu().numpy())
+    # the executor leaves 0.5 ms after its last item: its statistics count
+    # every item once, and at least a tile each
+    time.sleep(0.2)
+    st = q.stats()
+    assert st["items"] == 600 and st["tiles"] >= 600 and st["rounds"] > 0
+    assert st["serve_ticks"] > 0 and st["round_ticks"] > 0
     q.close()
 
 
