@@ -214,17 +214,33 @@ __global__ __launch_bounds__(256) void voxel_bin(const float4* __restrict__ pts,
 
 // 2. one workgroup per (tile, group of chunks): the tile's runs of those
 //    chunks reduced into LDS accumulators, written out as a partial tile.
-//    Each wavefront takes every fourth chunk's run.
+//    The runs' bounds of the group's chunks (up to kStage at a time) are
+//    staged in LDS first, all loaded at once; then each wavefront takes
+//    eight chunks at a time (every fourth block of eight) and reduces their
+//    runs in rounds of 128 records of every run, loaded together (sixteen
+//    loads a lane in flight) before their atomics.
+constexpr int kRunsAtOnce = 8;
+constexpr int kStage = 1024;   // chunks whose run bounds sit in LDS at once
+
+__device__ __forceinline__ void reduce_record(uint64_t r, int base, int* acc_c, unsigned* acc_z,
+                                              int* acc_f) {
+  const int cc = (int)((r >> 32) & (kTileCells - 1));
+  atomicAdd(&acc_c[cc], 1);
+  atomicMax(&acc_z[cc], (unsigned)r);
+  atomicMin(&acc_f[cc], base + (int)(r >> 44));
+}
+
 __global__ __launch_bounds__(256) void voxel_tile_reduce(const int* __restrict__ H,
                                                          const uint64_t* __restrict__ R,
                                                          int* __restrict__ pc,
                                                          unsigned* __restrict__ pz,
                                                          int* __restrict__ pf, int T, int nb,
                                                          int groups, int cpg) {
-  // 48 KiB of LDS: three workgroups fit a CU
+  // 48 KiB of accumulators and 8 KiB of run bounds: two workgroups a CU
   __shared__ int acc_c[kTileCells];
   __shared__ unsigned acc_z[kTileCells];
   __shared__ int acc_f[kTileCells];
+  __shared__ int2 bnd[kStage];
   const int t = blockIdx.x / groups, g = blockIdx.x % groups;
   const int c0 = g * cpg, c1 = c0 + cpg < nb ? c0 + cpg : nb;
   for (int i = threadIdx.x; i < kTileCells; i += 256) {
@@ -232,26 +248,43 @@ __global__ __launch_bounds__(256) void voxel_tile_reduce(const int* __restrict__
     acc_z[i] = kKeyNegInf;
     acc_f[i] = INT_MAX;
   }
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = c0 + wave; c < c1; c += 4) {
-    const int* h = H + (int64_t)c * (T + 1);
-    const int a = h[t], b = h[t + 1];
-    const uint64_t* run = R + (int64_t)c * kChunk;
-    const int base = c * (int)kChunk;
-    for (int i = a + lane; i < b; i += 128) {
-      const bool two = i + 64 < b;
-      const uint64_t r0 = run[i];
-      const uint64_t r1 = two ? run[i + 64] : 0;
-      int cc = (int)((r0 >> 32) & (kTileCells - 1));
-      atomicAdd(&acc_c[cc], 1);
-      atomicMax(&acc_z[cc], (unsigned)r0);
-      atomicMin(&acc_f[cc], base + (int)(r0 >> 44));
-      if (two) {
-        cc = (int)((r1 >> 32) & (kTileCells - 1));
-        atomicAdd(&acc_c[cc], 1);
-        atomicMax(&acc_z[cc], (unsigned)r1);
-        atomicMin(&acc_f[cc], base + (int)(r1 >> 44));
+  for (int s0 = c0; s0 < c1; s0 += kStage) {
+    const int s1 = s0 + kStage < c1 ? s0 + kStage : c1;
+    __syncthreads();   // the previous stage's bounds are no longer read
+    for (int c = s0 + threadIdx.x; c < s1; c += 256) {
+      const int* h = H + (int64_t)c * (T + 1) + t;
+      bnd[c - s0] = make_int2(h[0], h[1]);
+    }
+    __syncthreads();
+    for (int cb = s0 + wave * kRunsAtOnce; cb < s1; cb += 4 * kRunsAtOnce) {
+      int ra[kRunsAtOnce], rb[kRunsAtOnce];
+      int longest = 0;   // the same in every lane
+#pragma unroll
+      for (int k = 0; k < kRunsAtOnce; ++k) {
+        const int c = cb + k;
+        const int2 ab = c < s1 ? bnd[c - s0] : make_int2(0, 0);
+        ra[k] = ab.x;
+        rb[k] = ab.y;
+        longest = max(longest, ab.y - ab.x);
+      }
+      // rounds of 128 records of every run: sixteen loads a lane in flight
+      for (int off = 0; off < longest; off += 128) {
+        uint64_t r0[kRunsAtOnce], r1[kRunsAtOnce];
+#pragma unroll
+        for (int k = 0; k < kRunsAtOnce; ++k) {
+          const uint64_t* run = R + (int64_t)(cb + k) * kChunk;
+          const int i = ra[k] + off + lane;
+          r0[k] = i < rb[k] ? run[i] : 0;
+          r1[k] = i + 64 < rb[k] ? run[i + 64] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kRunsAtOnce; ++k) {
+          const int base = (cb + k) * (int)kChunk;
+          const int i = ra[k] + off + lane;
+          if (i < rb[k]) reduce_record(r0[k], base, acc_c, acc_z, acc_f);
+          if (i + 64 < rb[k]) reduce_record(r1[k], base, acc_c, acc_z, acc_f);
+        }
       }
     }
   }
@@ -310,8 +343,10 @@ Binned binned_layout(int64_t N, int64_t G) {
   Binned b;
   b.T = (int)((G + kTileCells - 1) / kTileCells);
   b.nb = (int)((N + kChunk - 1) / kChunk);
-  // at least ~512 reduce workgroups: groups of chunks per tile
-  b.groups = (int)std::min<int64_t>(b.nb, std::max<int64_t>(1, (512 + b.T - 1) / b.T));
+  // about 2048 reduce workgroups (groups of chunks per tile), four times
+  // the resident ones: the tiles of a clustered cloud hold very different
+  // record counts, and the workgroup dispatcher evens them out
+  b.groups = (int)std::min<int64_t>(b.nb, std::max<int64_t>(1, (2048 + b.T - 1) / b.T));
   b.cpg = (b.nb + b.groups - 1) / b.groups;
   size_t off = 0;
   auto take = [&](size_t bytes) {
