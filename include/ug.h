@@ -726,7 +726,7 @@ ug_status ug_tails_open(int32_t device, uint32_t workers, int64_t idle_ns, uint3
                         void** queue);
 /* Publishes an item with its key (smaller first; ties by slot); returns its
  * slot and publication number.  Its rows per tile: about rows / workers,
- * between 16 KiB and 128 KiB of input (at least one row), rounded up to a
+ * between 16 KiB and 512 KiB of input (at least one row), rounded up to a
  * multiple of 4.  Errors: UG_EINVAL (shape, alignment, NULL), UG_EAGAIN
  * (all 512 slots hold unfinished items). */
 ug_status ug_tails_publish(void* queue, const ug_tail* t, uint64_t key, uint32_t* slot,

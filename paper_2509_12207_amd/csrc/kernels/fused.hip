@@ -501,8 +501,7 @@ __device__ void rows_short(const Rows& t, uint32_t r, uint32_t r1, uint32_t lane
   }
 }
 
-// Long rows, one per wave at a time, U float4 per lane in flight (eight, or
-// four when a per-column bias comes from global memory as well), loads
+// Long rows, one per wave at a time, U float4 per lane in flight, loads
 // clamped as above.  With SM
 // the row's maximum and sum of exponentials are kept as a running pair,
 // rescaled when a chunk raises the maximum; the softmax is then written
@@ -558,6 +557,53 @@ __device__ void rows_long(const Rows& t, uint32_t r, uint32_t r1, uint32_t lane)
   }
 }
 
+// Long rows without a softmax whose per-column bias is too long for LDS:
+// two rows a pass (this wave's rows r and r + 4), so that each chunk of the
+// bias, read from global memory, serves both, and eight loads of x are in
+// flight beside four of the bias.
+__device__ void rows_long_pair(const Rows& t, uint32_t r, uint32_t r1, uint32_t lane) {
+  constexpr int U = 4;
+  const uint32_t jmax = t.c4 - 1;
+  const gfloat4* b4 = reinterpret_cast<const gfloat4*>(t.b);
+  for (; r < r1; r += 8) {
+    const bool two = r + 4 < r1;   // the same in every lane
+    const uint32_t r2 = two ? r + 4 : r;
+    const gfloat4* xa = t.x + size_t(r) * t.c4;
+    const gfloat4* xb = t.x + size_t(r2) * t.c4;
+    gfloat4* ya = t.y + size_t(r) * t.c4;
+    gfloat4* yb = t.y + size_t(r2) * t.c4;
+    float sa = 0.0f, sb = 0.0f;
+    for (uint32_t j0 = lane; j0 < t.c4; j0 += 64 * U) {
+      f4 bb[U], va[U], vb[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t jj = min(j0 + 64 * u, jmax);
+        bb[u] = ld4(b4, jj);
+        va[u] = ld4(xa, jj);
+        vb[u] = ld4(xb, jj);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t j = j0 + 64 * u;
+        const bool in = j < t.c4;
+        va[u] = relu_add4(va[u], bb[u]);
+        vb[u] = relu_add4(vb[u], bb[u]);
+        if (in) st4(ya, j, va[u]);
+        if (in && two) st4(yb, j, vb[u]);
+        sa += in ? sum4(va[u]) : 0.0f;
+        sb += in ? sum4(vb[u]) : 0.0f;
+      }
+    }
+    if (t.do_rs) {
+      const float ra = wave_sum(sa), rb = wave_sum(sb);
+      if (lane == 0) {
+        t.rs[r] = ra;
+        if (two) t.rs[r2] = rb;
+      }
+    }
+  }
+}
+
 __device__ void run_tile(const FuseItem& it, uint32_t tile, uint32_t wave, uint32_t lane,
                          const f4* lb) {
   Rows t;
@@ -583,7 +629,7 @@ __device__ void run_tile(const FuseItem& it, uint32_t tile, uint32_t wave, uint3
     else if (nb <= 2) rows_short<2, false>(t, r0, r1, lane);
     else if (nb <= 4) rows_short<4, false>(t, r0, r1, lane);
     else if (!t.per_col || nb <= kBiasLds / 64) rows_long<false, true, 8>(t, r0, r1, lane);
-    else rows_long<false, false, 4>(t, r0, r1, lane);
+    else rows_long_pair(t, r0, r1, lane);
   }
 }
 
@@ -674,7 +720,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void t
 
 uint32_t fuse_rows_per_tile(uint32_t R, uint32_t C, uint32_t workers) {
   const uint64_t row = 4ull * (C ? C : 1);
-  const uint64_t hi = row >= 131072 ? 1 : 131072 / row;
+  const uint64_t hi = row >= 524288 ? 1 : 524288 / row;
   uint64_t lo = (16384 + row - 1) / row;
   if (lo > hi) lo = hi;
   const uint64_t w = workers ? workers : 1;

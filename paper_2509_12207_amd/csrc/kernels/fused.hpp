@@ -141,8 +141,10 @@ hipError_t fuse_executor_launch(FuseHost* h, FuseDev* d, uint32_t workers, uint3
                                 hipStream_t s);
 
 // Rows per tile of an item of R rows of C floats served by `workers`
-// workers: about R / workers, kept between 16 KiB and 128 KiB of input
-// (at least one row), rounded up to a multiple of 4 (one row per wave).
+// workers: about R / workers, kept between 16 KiB and 512 KiB of input (at
+// least one row), rounded up to a multiple of 4 (one row per wave).  A
+// tile costs one dispatcher round trip of a few microseconds, which a
+// 512 KiB tile (tens of microseconds on one workgroup) makes small.
 uint32_t fuse_rows_per_tile(uint32_t R, uint32_t C, uint32_t workers);
 
 }  // namespace ug

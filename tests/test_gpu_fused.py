@@ -62,6 +62,7 @@ SHAPES = [  # rows, cols, axis, softmax, rowsum, in place
     (300, 256, 0, True, True, True),        # several tiles, ragged last
     (64, 4096, 0, True, True, False),       # the longest fused softmax row
     (5, 65536, 1, False, True, True),       # conv planes of 256 x 256
+    (130, 8192, 0, False, True, False),     # long rows, bias from global memory, row pairs
     (513, 1024, 1, False, True, False),
     (2049, 64, 1, False, False, True),
 ]
@@ -117,8 +118,9 @@ def test_tail_executor_many_items_and_slot_reuse():
 
 
 def _order_items(q, specs):
-    """Publish items (key, rows) of 8192-float rows (4 rows per tile);
-    returns publications and tensors."""
+    """Publish items (key, rows) of 8192-float rows (one worker: 16 rows per
+    tile, the most a 512 KiB tile of 32 KiB rows takes); returns
+    publications and tensors."""
     out = []
     for key, rows in specs:
         x = torch.rand(rows, 8192, device="cuda")
@@ -134,7 +136,7 @@ def test_tail_executor_serves_smallest_key_first():
     # ready before the worker starts (paused while they are taken in)
     q = capi.TailQueue(workers=1, idle_ns=2_000_000_000, log_cap=4096)
     q.pause(True)
-    specs = [(5 << 32 | 1, 9), (2 << 32 | 2, 4), (9 << 32 | 3, 13), (2 << 32 | 4, 5), (7, 8)]
+    specs = [(5 << 32 | 1, 40), (2 << 32 | 2, 20), (9 << 32 | 3, 60), (2 << 32 | 4, 25), (7, 36)]
     items = _order_items(q, specs)
     q.kick()
     time.sleep(0.2)
@@ -145,7 +147,7 @@ def test_tail_executor_serves_smallest_key_first():
     wait_finished(q, [(s, p) for s, p, _, _ in items])
     log = q.log()
     q.close()
-    rpt = 4                                # rows per tile at 8192 floats
+    rpt = 16                               # rows per tile at 8192 floats
     keys = [k for k, _ in specs]
     keys[3] = 1 << 32 | 4
     oracle_items = [{"key": k, "tiles": -(-rows // rpt), "ready": 0}
