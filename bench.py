@@ -168,6 +168,11 @@ SWEEPS = {
              {"name": "paper+graph+fuse", "wl": "cfg2", "flags": PAPER | GRAPH | FUSE},
              {"name": "full+fuse", "wl": "cfg2", "flags": FULL | FUSE},
              {"name": "fifo+fuse", "wl": "cfg2", "policy": "fifo", "flags": FUSE}],
+    # configuration 2's rows taken 2 and 4 times (22, 44 chains) at the same
+    # total load: more, shorter kernels, until launches limit the gate thread
+    "fuse_load": [{"name": f"{n}ch_{v}", "wl": "cfg2", "repeat": r, "flags": f}
+                  for n, r in ((22, 2), (44, 4))
+                  for v, f in (("paper", PAPER), ("paper+fuse", PAPER | FUSE))],
     # FIFO launch with the gate's probe-based queue placement beside plain FIFO
     "fifo_placed": [{"name": "fifo_placed", "policy": "fifo", "flags": 256},
                     {"name": "full", "flags": FULL}],
@@ -181,11 +186,12 @@ def sweep_main(args, torch, capi, runner, synth):
         cu = v.get("custom")
         groups.setdefault((v.get("f_a", args.f_a), v.get("f_d", args.f_d),
                            json.dumps(cu, sort_keys=True) if cu else None, v.get("cpu", 0.0),
-                           v.get("cores", 0), v.get("wl", "cfg1")), []).append(v)
+                           v.get("cores", 0), v.get("wl", "cfg1"), v.get("repeat", 1)),
+                          []).append(v)
     for seed in range(args.seed, args.seed + args.seeds):
-        for (fa, fd, cu, cpu, cores, wname), variants in groups.items():
+        for (fa, fd, cu, cpu, cores, wname, rep_), variants in groups.items():
             if wname == "cfg2":
-                wl = synth.config2(seed=seed, f_a=fa, f_d=fd, window_s=float(W + K))
+                wl = synth.config2(seed=seed, f_a=fa, f_d=fd, window_s=float(W + K), repeat=rep_)
             else:
                 wl = synth.config1(seed=seed, f_a=fa, f_d=fd, window_s=float(W + K),
                                    custom=json.loads(cu) if cu else None, cpu=cpu)
@@ -194,7 +200,8 @@ def sweep_main(args, torch, capi, runner, synth):
             dw = runner.DeviceWorkload(wl, n_sets=4)
             prof = runner.make_gate(wl, "urgency", trace_capacity=0, queue_capacity=1 << 16)
             runner.profile(prof, dw, warmup=2, reps=5)
-            point = {"seed": seed, "workload": wname, "f_a": fa, "f_d": fd, "frames": len(timed),
+            point = {"seed": seed, "workload": wname, "chains": len(wl.chains), "f_a": fa, "f_d": fd,
+                     "frames": len(timed),
                      "window_s": K, "custom": json.loads(cu) if cu else None, "cpu": cpu,
                      "cpu_cores": cores}
             fifo = runner.make_gate(wl, "fifo", trace_capacity=0, queue_capacity=1 << 16,

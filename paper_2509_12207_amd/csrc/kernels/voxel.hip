@@ -43,6 +43,7 @@ constexpr int kMaxTiles = 1024;                   // binned grids: <= 4 Mi cells
 constexpr int64_t kChunk = 8192;                  // points per bin workgroup
 static_assert(kChunk <= 8192, "a record keeps the index in its chunk in 13 bits");
 constexpr int64_t kBinnedMinPoints = int64_t(1) << 20;
+constexpr int64_t kMinChunksPerGroup = 64;        // tile reduce: chunks per workgroup, at least
 constexpr unsigned kKeyNegInf = 0x007fffffu;      // key of -inf
 
 __device__ __forceinline__ unsigned zkey(float z) {
@@ -345,8 +346,11 @@ Binned binned_layout(int64_t N, int64_t G) {
   b.nb = (int)((N + kChunk - 1) / kChunk);
   // about 2048 reduce workgroups (groups of chunks per tile), four times
   // the resident ones: the tiles of a clustered cloud hold very different
-  // record counts, and the workgroup dispatcher evens them out
-  b.groups = (int)std::min<int64_t>(b.nb, std::max<int64_t>(1, (2048 + b.T - 1) / b.T));
+  // record counts, and the workgroup dispatcher evens them out.  A group
+  // takes at least kMinChunksPerGroup chunks, so that a smaller cloud does
+  // not pay for (and hold) more partial tiles than records.
+  b.groups = (int)std::max<int64_t>(
+      1, std::min<int64_t>(b.nb / kMinChunksPerGroup, (2048 + b.T - 1) / b.T));
   b.cpg = (b.nb + b.groups - 1) / b.groups;
   size_t off = 0;
   auto take = [&](size_t bytes) {
