@@ -168,10 +168,9 @@ SWEEPS = {
              {"name": "paper+graph+fuse", "wl": "cfg2", "flags": PAPER | GRAPH | FUSE},
              {"name": "full+fuse", "wl": "cfg2", "flags": FULL | FUSE},
              {"name": "fifo+fuse", "wl": "cfg2", "policy": "fifo", "flags": FUSE}],
-    # configuration 2's rows taken 2 and 4 times (22, 44 chains) at the same
-    # total load: more, shorter kernels, until launches limit the gate thread
-    "fuse_load": [{"name": f"{n}ch_{v}", "wl": "cfg2", "repeat": r, "flags": f}
-                  for n, r in ((22, 2), (44, 4))
+    # configuration 2's rows taken twice (22 chains) at the same total load:
+    # more, shorter kernels
+    "fuse_load": [{"name": f"22ch_{v}", "wl": "cfg2", "repeat": 2, "flags": f}
                   for v, f in (("paper", PAPER), ("paper+fuse", PAPER | FUSE))],
     # FIFO launch with the gate's probe-based queue placement beside plain FIFO
     "fifo_placed": [{"name": "fifo_placed", "policy": "fifo", "flags": 256},

@@ -726,7 +726,7 @@ ug_status ug_tails_open(int32_t device, uint32_t workers, int64_t idle_ns, uint3
                         void** queue);
 /* Publishes an item with its key (smaller first; ties by slot); returns its
  * slot and publication number.  Its rows per tile: about rows / workers,
- * between 16 KiB and 512 KiB of input (at least one row), rounded up to a
+ * between 64 KiB and 512 KiB of input (at least one row), rounded up to a
  * multiple of 4.  Errors: UG_EINVAL (shape, alignment, NULL), UG_EAGAIN
  * (all 512 slots hold unfinished items). */
 ug_status ug_tails_publish(void* queue, const ug_tail* t, uint64_t key, uint32_t* slot,
@@ -758,9 +758,10 @@ ug_status ug_fuse_stats(void* ctx, uint64_t* out, uint32_t n);
 /* Stops the executor, waits for it, frees everything. */
 ug_status ug_tails_close(void* queue);
 
-/* ug_kernel_launch with a completion counter: every wavefront of the
- * kernel adds one to *counter (device memory) once its results are stored;
- * *waves receives the total.  Only UG_OP_GEMM_F32, UG_OP_CONV3X3_F32,
+/* ug_kernel_launch with a completion counter: every workgroup of the
+ * kernel adds its wavefront count to *counter (device memory, 4-byte
+ * aligned) once all its results are stored, with one agent-scope release;
+ * *waves receives the total (workgroups x wavefronts per workgroup).  Only UG_OP_GEMM_F32, UG_OP_CONV3X3_F32,
  * UG_OP_GEMM_BF16 and UG_OP_CONV3X3_BF16 take a counter (else UG_EINVAL). */
 ug_status ug_kernel_launch_signal(const ug_kernel* k, void* const* buffers,
                                   uint32_t n_buffers, uint32_t* counter, uint32_t* waves,

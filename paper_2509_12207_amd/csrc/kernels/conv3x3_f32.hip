@@ -198,8 +198,8 @@ __global__ __launch_bounds__(256) void conv3x3_f32_kernel(const float* __restric
           for (int q = 0; q < 16; ++q) red[((i * TN + j) * 16 + q) * 64 + lane] = acc[i][j][q];
     }
     __syncthreads();
-    if (ks > 0) {
-      wave_done(sig);
+    if (ks > 0) {   // handed over: meet slice 0 at the counter's barrier, then leave
+      group_done(sig);
       return;
     }
 #pragma unroll
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void conv3x3_f32_kernel(const float* __restric
         if (o < C) Yn[(size_t)o * plane + (size_t)yy * W + xx] = acc[i][j][q];
       }
   }
-  wave_done(sig);
+  group_done(sig);
 }
 
 // Tile shapes, largest first: {BM, TH, TW}.

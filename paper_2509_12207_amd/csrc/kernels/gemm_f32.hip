@@ -181,8 +181,8 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
           for (int r = 0; r < 16; ++r) red[((i * TN + j) * 16 + r) * 64 + lane] = acc[i][j][r];
     }
     __syncthreads();
-    if (ks > 0) {
-      wave_done(sig);
+    if (ks > 0) {   // handed over: meet slice 0 at the counter's barrier, then leave
+      group_done(sig);
       return;
     }
 #pragma unroll
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
         if (m < M) C[(size_t)m * N + n] = acc[i][j][r];
       }
     }
-  wave_done(sig);
+  group_done(sig);
 }
 
 enum Shape { kBig = 0, kMid = 1, kSmall = 2 };

@@ -380,7 +380,7 @@ __global__ __launch_bounds__(64 * RWAVES, 1) void gemm_ring(const unsigned char*
         if (row < M && col < N) C[(int64_t)row * N + col] = acc[i][j][r];
       }
     }
-  wave_done(sig);
+  group_done(sig);
 }
 
 }  // namespace

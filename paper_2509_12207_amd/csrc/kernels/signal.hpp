@@ -1,18 +1,29 @@
 // Completion counter of a contraction for the tail executor (fused.hpp):
-// every wavefront adds one once all its stores are out, so the counter
-// reaches (workgroups x wavefronts per workgroup) when the kernel's output is
-// complete.  A null counter costs one comparison.
+// every workgroup adds its wavefront count once all its stores are out, so
+// the counter reaches (workgroups x wavefronts per workgroup) when the
+// kernel's output is complete.  A null counter costs one comparison.
+//
+// One agent-scope release per workgroup: it writes the L2's dirty lines back
+// before the add.  An agent-scope fence per wavefront would also invalidate
+// the L2 every time, under the other workgroups still running on that XCD
+// (measured: a BF16 3x3 convolution at C = 256, 256^2 took 181 us with it
+// against 106 us without a counter).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace ug {
 
-__device__ __forceinline__ void wave_done(unsigned* sig) {
-  if (sig == nullptr) return;
-  __threadfence();   // this wavefront's stores, before its count
-  if ((threadIdx.x & 63) == 0)
-    __hip_atomic_fetch_add(sig, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Called by every thread of the workgroup (a barrier inside), after its last
+// store.
+__device__ __forceinline__ void group_done(unsigned* sig) {
+  if (sig == nullptr) return;   // the same in every workgroup
+  // this wavefront's stores are written to the L2 (vmcnt 0, other counters
+  // left alone), then the workgroup meets
+  __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8) | (0 << 14));
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(sig, blockDim.x / 64u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace ug

@@ -221,6 +221,65 @@ def test_tail_behind_a_counted_bf16_convolution():
                   <= TOL * np.abs(Yc).astype(np.float64).sum(1))
 
 
+def _signal_buffers(op, shape, r):
+    if op == "gemm":
+        M, N, K = shape
+        return [r.uniform(-1, 1, M * K).astype(np.float32),
+                r.uniform(-1, 1, K * N).astype(np.float32), np.zeros(M * N, np.float32)]
+    if op == "conv3x3":
+        n, Cc, H, W = shape
+        return [r.uniform(-1, 1, n * Cc * H * W).astype(np.float32),
+                r.uniform(-1, 1, Cc * Cc * 9).astype(np.float32),
+                np.zeros(n * Cc * H * W, np.float32)]
+    bf = lambda n: (r.uniform(-1, 1, n).astype(np.float32).view(np.uint32) >> 16).astype(
+        np.uint16).view(np.int16)
+    if op == "gemm_bf16":
+        M, N, K = shape
+        return [bf(M * K), bf(N * K), np.zeros(M * N, np.float32)]
+    _, Cc, H, W = shape
+    return [bf(H * W * Cc), bf(Cc * 9 * Cc), np.zeros(Cc * H * W, np.float32)]
+
+
+@pytest.mark.parametrize("op,shape,variant", [
+    ("gemm", (1024, 1024, 1024), -1),
+    ("gemm", (96, 160, 2048), 2),          # K split in four: slices 1-3 leave early
+    ("gemm", (200, 136, 264), 1),
+    ("conv3x3", (1, 64, 24, 40), 3),       # K split in four
+    ("conv3x3", (1, 32, 20, 16), 4),       # K split in four
+    ("conv3x3", (1, 64, 32, 32), 0),
+    ("gemm_bf16", (512, 384, 256), -1),
+    ("conv3x3_bf16", (1, 64, 24, 40), -1),
+])
+def test_launch_signal_counts_every_wavefront(op, shape, variant):
+    """The completion counter ends at exactly the wavefront count the launch
+    reports, and a counted launch stores what an uncounted one does."""
+    r = np.random.default_rng(hash((op, shape)) % (1 << 32))
+    host = _signal_buffers(op, shape, r)
+    dev = [torch.from_numpy(h).cuda() for h in host]
+    out2 = torch.zeros_like(dev[2])
+    cnt = torch.zeros(2, dtype=torch.int32, device="cuda")
+    k = {"op": op, "shape": shape, "in": (0, 1), "out": (2,)}
+    s = torch.cuda.Stream()
+    if variant >= 0:
+        capi.tile_set(op, shape, variant)
+        assert capi.tile_get(k) == variant
+    try:
+        torch.cuda.synchronize()
+        capi.kernel_launch(k, [dev[0].data_ptr(), dev[1].data_ptr(), out2.data_ptr()],
+                           s.cuda_stream)
+        for rep in range(2):
+            waves = capi.kernel_launch_signal(k, [d.data_ptr() for d in dev],
+                                              cnt[1:].data_ptr(), s.cuda_stream)
+            s.synchronize()
+            assert waves > 0 and int(cnt[1].item()) == (rep + 1) * waves
+        assert int(cnt[0].item()) == 0      # the word before the counter is untouched
+    finally:
+        if variant >= 0:
+            capi.tile_set(op, shape, -1)
+    a, b = dev[2].cpu().numpy(), out2.cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
 def test_launch_signal_refuses_other_ops():
     with pytest.raises(capi.UgError):
         x = torch.zeros(16, device="cuda")
