@@ -721,7 +721,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void t
 uint32_t fuse_rows_per_tile(uint32_t R, uint32_t C, uint32_t workers) {
   const uint64_t row = 4ull * (C ? C : 1);
   const uint64_t hi = row >= 524288 ? 1 : 524288 / row;
-  uint64_t lo = (16384 + row - 1) / row;
+  uint64_t lo = (65536 + row - 1) / row;
   if (lo > hi) lo = hi;
   const uint64_t w = workers ? workers : 1;
   uint64_t r = (uint64_t(R) + w - 1) / w;

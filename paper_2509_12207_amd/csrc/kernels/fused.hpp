@@ -24,10 +24,11 @@
 // (and per batch of commands or reports), so that the caches the other
 // kernels share are not flushed on every poll.
 //
-// A producer (a contraction launched with a completion counter) adds one to
-// the counter per wavefront once that wavefront's results are stored; the
-// item is ready when the counter reaches the producer's wavefront count, and
-// the dispatcher then resets it to zero for the producer's next launch.
+// A producer (a contraction launched with a completion counter) adds each
+// workgroup's wavefront count to the counter once the workgroup's results
+// are stored (signal.hpp); the item is ready when the counter reaches the
+// producer's wavefront count, and the dispatcher then resets it to zero for
+// the producer's next launch.
 //
 // Every wait of the executor is bounded: the dispatcher leaves when the host
 // sets `stop`, when nothing has progressed for `idle` nanoseconds, or at the
@@ -141,10 +142,13 @@ hipError_t fuse_executor_launch(FuseHost* h, FuseDev* d, uint32_t workers, uint3
                                 hipStream_t s);
 
 // Rows per tile of an item of R rows of C floats served by `workers`
-// workers: about R / workers, kept between 16 KiB and 512 KiB of input (at
+// workers: about R / workers, kept between 64 KiB and 512 KiB of input (at
 // least one row), rounded up to a multiple of 4 (one row per wave).  A
 // tile costs one dispatcher round trip of a few microseconds, which a
-// 512 KiB tile (tens of microseconds on one workgroup) makes small.
+// 512 KiB tile (tens of microseconds on one workgroup) makes small, and the
+// worker's L2 invalidate and write-back (its acquire and release), which
+// the other kernels on that XCD feel: the floor keeps a short tail to a
+// few tiles.
 uint32_t fuse_rows_per_tile(uint32_t R, uint32_t C, uint32_t workers);
 
 }  // namespace ug
