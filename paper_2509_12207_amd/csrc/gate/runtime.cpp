@@ -513,8 +513,10 @@ bool execute(Ctx* c, const std::vector<ug_record>& dec) {
           return false;
         }
         c->live_events[EvKey{d.chain, d.frame, d.task, d.a, d.b}] = e;
-        if (c->tails) {
-          // the event stands for every tail published before it as well
+        if (c->tails && d.a == 1) {
+          // a task-end event stands for every tail of the task as well; a
+          // batch-start event does not wait for the earlier batches' tails
+          // (no later kernel reads what a tail writes)
           auto t = c->inst_tails.find(TaskKey{d.chain, d.frame, d.task});
           c->ev_tails[EvKey{d.chain, d.frame, d.task, d.a, d.b}] =
               t == c->inst_tails.end() ? 0 : t->second.size();
