@@ -242,7 +242,11 @@ __global__ __launch_bounds__(256) void voxel_tile_reduce(const int* __restrict__
   __shared__ unsigned acc_z[kTileCells];
   __shared__ int acc_f[kTileCells];
   __shared__ int2 bnd[kStage];
-  const int t = blockIdx.x / groups, g = blockIdx.x % groups;
+  // chunk-group major: the workgroups resident together are the tiles of
+  // a few chunk groups, which read neighbouring pieces of the same chunk
+  // blocks (fewer distinct pages in flight than one tile's groups, which
+  // span the whole record array)
+  const int g = blockIdx.x / T, t = blockIdx.x % T;
   const int c0 = g * cpg, c1 = c0 + cpg < nb ? c0 + cpg : nb;
   for (int i = threadIdx.x; i < kTileCells; i += 256) {
     acc_c[i] = 0;
@@ -290,7 +294,7 @@ __global__ __launch_bounds__(256) void voxel_tile_reduce(const int* __restrict__
     }
   }
   __syncthreads();
-  const int64_t o = (int64_t)blockIdx.x * kTileCells;
+  const int64_t o = ((int64_t)t * groups + g) * kTileCells;
   for (int i = threadIdx.x; i < kTileCells; i += 256) {
     pc[o + i] = acc_c[i];
     pz[o + i] = acc_z[i];
