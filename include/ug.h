@@ -307,7 +307,9 @@ typedef struct {
                               has waited this long since its first hold
                               (delayed launching or admission), it is not
                               held again; a timer re-decides it when the
-                              bound is reached.  0 = no bound (the paper) */
+                              bound is reached.  Best-effort tasks
+                              (deadline 0) are not bounded.  0 = no bound
+                              (the paper)                                   */
   int32_t own_streams;     /* 0: the caller provides the stream pool with
                               ug_attach_streams before ug_start (streams made
                               by torch); 1: the library creates its own

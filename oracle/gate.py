@@ -172,7 +172,8 @@ DEFAULT_CFG = {
     "est_noise_permille": 0,    # estimate noise n: per task instance, E * (1000 + k) / 1000
     "noise_seed": 0,            #   with k uniform in [-n, n] (Sec. 6.6)
     "max_hold_ns": 0,           # hold-age bound: a task first held at t0 is not held
-                                #   again from t0 + max_hold_ns on; 0 = no bound
+                                #   again from t0 + max_hold_ns on; 0 = no bound;
+                                #   best-effort tasks are not bounded
     "cpu_cores": 0,             # CPU cores the CPU segments share; 0 = one each
     "cpu_prio": False,          # urgency-centric CPU scheduling (Sec. 4.3)
 }
@@ -531,7 +532,8 @@ class GateModel:
             g = inst.g_next
             # hold-age bound: once the task has waited max_hold since its
             # first hold, neither delayed launching nor admission holds it
-            aged = (max_hold > 0 and inst.held_since is not None
+            # (best-effort tasks have no deadline to protect: never aged)
+            aged = (max_hold > 0 and not ch.best_effort and inst.held_since is not None
                     and t >= inst.held_since + max_hold)
             # task graphs: the task is one launch, gated at its first kernel
             # with the largest utilisation of its kernels, never inside
@@ -597,7 +599,7 @@ class GateModel:
         """A hold of the task at t: its first hold starts the hold age, and
         while it waits a timer fires when the age reaches its bound."""
         max_hold = self.cfg["max_hold_ns"]
-        if max_hold <= 0:
+        if max_hold <= 0 or inst.chain.best_effort:
             return
         if inst.held_since is None:
             inst.held_since = t

@@ -575,9 +575,10 @@ void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& acti
   const bool graph = gated && cfg_.graph;
   const bool batching = gated && cfg_.batch && !graph;
   // a hold of the task at t: the first one starts the hold age; while the
-  // task waits, a timer fires when the age reaches the bound
+  // task waits, a timer fires when the age reaches the bound (best-effort
+  // tasks have no deadline to protect and no bound)
   auto held = [&]() {
-    if (cfg_.max_hold_ns <= 0) return;
+    if (cfg_.max_hold_ns <= 0 || ch.best_effort) return;
     if (!me.has_held) {
       me.has_held = true;
       me.held_since = t;
@@ -589,7 +590,8 @@ void Policy::release(Instance& me, int64_t t, const std::vector<Instance*>& acti
     const int32_t g = me.g_next;
     // hold-age bound: once the task has waited max_hold_ns since its first
     // hold, neither delayed launching nor admission holds it again
-    const bool aged = cfg_.max_hold_ns > 0 && me.has_held && t >= me.held_since + cfg_.max_hold_ns;
+    const bool aged = cfg_.max_hold_ns > 0 && !ch.best_effort && me.has_held &&
+                      t >= me.held_since + cfg_.max_hold_ns;
     // with task graphs the task is one launch: it is gated at its first
     // kernel, with the largest utilisation of its kernels
     const bool gate_here = !graph || g == ch.task_first[me.task];

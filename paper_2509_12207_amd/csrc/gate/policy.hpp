@@ -47,7 +47,7 @@ struct PolicyConfig {
   float util_exempt = 0.1f;
   int64_t th_slack_ns = 0;
   int64_t calib_period_ns = 1000000;   // at most one calibration sample per period
-  int64_t max_hold_ns = 0;             // hold-age bound per task; 0 = none
+  int64_t max_hold_ns = 0;             // hold-age bound per deadline task; 0 = none
   int32_t cpu_cores = 0;               // cores of the CPU segments; 0 = one each
   bool cpu_prio = false;               // urgency-centric CPU scheduling (Sec. 4.3)
   bool keep_order = false;             // keep each instant's full ranking (order())

@@ -790,6 +790,25 @@ def test_hold_age_exemption_lasts_for_the_rest_of_the_task():
     assert rel[0] == int(2.5 * MS) and rel[1] < int(4.5 * MS)
 
 
+@pytest.mark.parametrize("poll", [1 * MS, 0])
+def test_hold_age_bound_leaves_best_effort_tasks_held(poll):
+    # the case above with B best-effort (no deadline): the 2.5 ms bound does
+    # not release it, so it waits for A exactly as without a bound (5 ms
+    # wake of the sleep loop, or A's end observed at 4.5 ms), and no timer
+    # instant is made for it
+    ch = [chain(10 * MS, [(0, [(int(4.5 * MS), 1.0)])]), chain(0, [(0, [(1 * MS, 1.0)])])]
+    arr = [(0, 0, 0), (1, 0, 0)]
+    free = {"policy": "urgency", "th_slack_ns": 6 * MS, "delay_poll_ns": poll}
+    bounded = dict(free, max_hold_ns=int(2.5 * MS))
+    r0 = des.simulate(ch, free, arr, by_est(ch))
+    r1 = des.simulate(ch, bounded, arr, by_est(ch))
+    assert _first_launch(r1)[1] == _first_launch(r0)[1] == (5 * MS if poll else int(4.5 * MS))
+    assert [i[0] for i in r1["instants"]] == [i[0] for i in r0["instants"]]
+    assert int(2.5 * MS) not in [i[0] for i in r1["instants"]]
+    des.check_log(ch, bounded, r1["instants"])
+    assert des.replay(ch, bounded, r1["instants"]) is None
+
+
 def test_hold_age_bounds_admission():
     # one place; A runs 10 ms; B arrives at 0.5 ms and waits for the place.
     # With a 3 ms bound it starts at 3.5 ms, beside A; unbounded at 10 ms
