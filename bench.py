@@ -29,6 +29,10 @@ PEAK_BF16_MFMA = 2.5e15
 # threshold sweep (3 seeds) it lowers misses but raises p99 latency over FIFO,
 # while the 99th lowers both on every seed.
 TH_PCT = 99
+# Hold-age bound of the benchmarked gate (ug_config.max_hold_ns): in the
+# hold sweep (2 seeds, TH percentiles 85-99) a 5 ms bound lowered p99 latency
+# at every percentile, and at the 99th kept misses about where they were.
+HOLD_MS = 5
 PEAK_HBM = 8.0e12
 METRIC = "deadline-miss ratio & p99 chain latency vs FIFO launch; kernel % of roofline"
 
@@ -260,14 +264,16 @@ def sweep_main(args, torch, capi, runner, synth):
 
 # Policies of the benchmark line, each on the same arrivals:
 #   urgency      the gate as benchmarked: the paper's three mechanisms plus
-#                task admission, TH_urgent at the TH_PCT-th percentile
+#                task admission, TH_urgent at the TH_PCT-th percentile, a
+#                HOLD_MS hold-age bound
 #   paper        the paper's three mechanisms only (binding, delayed and
 #                batched launching) at its 95th percentile (Sec. 4.4.3)
 #   fifo         plain FIFO launch, HIP's own stream-to-queue mapping
 #   fifo_placed  FIFO launch on streams placed over the hardware queues by the
 #                same probe as the gate's lanes (UG_F_PLACE)
 POLICIES = {
-    "urgency": {"policy": "urgency", "flags": FULL, "pct": TH_PCT},
+    "urgency": {"policy": "urgency", "flags": FULL, "pct": TH_PCT,
+                "cfg": {"max_hold_ns": HOLD_MS * MS}},
     "paper": {"policy": "urgency", "flags": PAPER, "pct": 95},
     "fifo": {"policy": "fifo", "flags": 0},
     "fifo_placed": {"policy": "fifo", "flags": 256},
@@ -331,7 +337,8 @@ def seed_run(args, torch, runner, synth, seed, W, H, names, reps=2, overload=Fal
     for n in names:
         p = POLICIES[n]
         g = runner.make_gate(wl, p["policy"], trace_capacity=0, queue_capacity=1 << 16,
-                             flags=p["flags"] | (capi.F_PLACE if p["policy"] == "urgency" else 0))
+                             flags=p["flags"] | (capi.F_PLACE if p["policy"] == "urgency" else 0),
+                             **p.get("cfg", {}))
         for (c, k), (e, u) in est.items():
             g.set_estimate(c, k, e, u)
         if p["policy"] == "urgency":
@@ -1279,7 +1286,7 @@ def main():
                    "frames": len(timed), "kernels_per_round": n_kernels,
                    "isolated_utilisation": round(util, 3),
                    "th_urgent_slack_ms": round(th["urgency"] / 1e6, 3),
-                   "th_urgent_pct": TH_PCT},
+                   "th_urgent_pct": TH_PCT, "max_hold_ms": HOLD_MS},
         "urgency": urg_sum,
         "fifo": fifo_sum,
         "paper": summary.get("paper"),
