@@ -258,13 +258,13 @@ int chosen_variant(const ug_kernel& k) {
       const int v = tune_get(UG_OP_GEMM_F32, gkey);
       if (v >= 0) return v;
       // the plan's function tells the rule's choice apart
-      for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < tile_variants(UG_OP_GEMM_F32); ++i)
         if (gemm_f32_plan(s[0], s[1], s[2], true, i).func == gemm_f32_plan(s[0], s[1], s[2], true).func)
           return i;
       return -1;
     }
     case UG_OP_CONV3X3_F32: {
-      for (int i = 0; i < 5; ++i)
+      for (int i = 0; i < tile_variants(UG_OP_CONV3X3_F32); ++i)
         if (conv3x3_f32_plan(s[0], s[1], s[2], s[3], i).func ==
             conv3x3_f32_plan(s[0], s[1], s[2], s[3]).func)
           return i;
