@@ -111,7 +111,9 @@ SWEEPS = {
     "fa": [{"name": f"fa_{f}", "f_a": f} for f in (0.7, 0.9, 1.0, 1.1, 1.3)],
     "fd": [{"name": f"fd_{f}", "f_d": f} for f in (0.7, 1.0, 1.5)],
     # run-to-run and seed spread at the default point
-    "seeds": [{"name": "default"}],
+    "seeds": [{"name": "default"},
+              {"name": "default_hold", "cfg": {"max_hold_ns": HOLD_MS * MS}},
+              {"name": "paper", "flags": PAPER, "pct": 95}],
     # TH_urgent percentile with admission, with and without early chain exit
     "threshold_exit": [{"name": f"th_p{p}", "pct": p} for p in (95, 97, 99)]
     + [{"name": f"th_p{p}_exit", "pct": p, "flags": FULL | 32} for p in (95, 99)],
