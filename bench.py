@@ -108,8 +108,11 @@ SWEEPS = {
     + [{"name": f"th_p{p}_every_instant", "pct": p, "cfg": {"calib_period_ns": 0}}
        for p in (95, 99)],
     # arrival-rate and deadline factors (Sec. 6.2): FIFO and the full gate
-    "fa": [{"name": f"fa_{f}", "f_a": f} for f in (0.7, 0.9, 1.0, 1.1, 1.3)],
-    "fd": [{"name": f"fd_{f}", "f_d": f} for f in (0.7, 1.0, 1.5)],
+    # arrival-rate and deadline factors (Sec. 6.2), the benchmarked gate
+    "fa": [{"name": f"fa_{f}", "f_a": f, "cfg": {"max_hold_ns": HOLD_MS * MS}}
+           for f in (0.7, 0.9, 1.0, 1.1, 1.3)],
+    "fd": [{"name": f"fd_{f}", "f_d": f, "cfg": {"max_hold_ns": HOLD_MS * MS}}
+           for f in (0.7, 1.0, 1.5)],
     # run-to-run and seed spread at the default point
     "seeds": [{"name": "default"},
               {"name": "default_hold", "cfg": {"max_hold_ns": HOLD_MS * MS}},
